@@ -1,0 +1,258 @@
+"""Python access to the FP64 CPU oracle (``oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: the oracle is the plain, slow reference the GPU
+library is checked against.  Only the tests, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package; the GPU product
+path never does, and the two share no code.
+
+``build()`` compiles ``liboracle.so`` with g++ -O2 -ffp-contract=off.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = [os.path.join(HERE, "oracle.cpp")]
+
+DEFAULT_CONFIG = dict(
+    chi2_max=15.0, branches_per_surface=3, max_live_per_seed=10, max_holes=3, min_meas=6,
+    max_steps=48, max_rk_steps=100, step_tol=1e-3, step_max=200.0, land_tol=1e-4,
+    path_max=4000.0, nav_margin=1.0, mass=0.1056583755, material_on=1, tracks_per_seed=1)
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB):
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-pthread", "-Wall", "-o", LIB + ".tmp"] + SRC
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Geometry(C.Structure):
+    _fields_ = [("n_surfaces", C.c_int32), ("center", C.c_void_p), ("rot", C.c_void_p),
+                ("half", C.c_void_p), ("thick", C.c_void_p), ("layer", C.c_void_p),
+                ("n_layers", C.c_int32), ("layer_type", C.c_void_p), ("layer_pos", C.c_void_p),
+                ("layer_lo", C.c_void_p), ("layer_hi", C.c_void_p)]
+
+
+class _Field(C.Structure):
+    _fields_ = [("b", C.c_double * 3)]
+
+
+class _Meas(C.Structure):
+    _fields_ = [("n_events", C.c_int32), ("n_surfaces", C.c_int32), ("offsets", C.c_void_p),
+                ("loc", C.c_void_p), ("var", C.c_void_p)]
+
+
+class _Seeds(C.Structure):
+    _fields_ = [("n_seeds", C.c_int32), ("event", C.c_void_p), ("surface", C.c_void_p),
+                ("params", C.c_void_p), ("cov", C.c_void_p)]
+
+
+class _Config(C.Structure):
+    _fields_ = [("chi2_max", C.c_double), ("branches_per_surface", C.c_int32),
+                ("max_live_per_seed", C.c_int32), ("max_holes", C.c_int32), ("min_meas", C.c_int32),
+                ("max_steps", C.c_int32), ("max_rk_steps", C.c_int32), ("step_tol", C.c_double),
+                ("step_max", C.c_double), ("land_tol", C.c_double), ("path_max", C.c_double),
+                ("nav_margin", C.c_double), ("mass", C.c_double), ("material_on", C.c_int32),
+                ("tracks_per_seed", C.c_int32)]
+
+
+class _Tracks(C.Structure):
+    _fields_ = [("cap_tracks", C.c_int32), ("cap_meas", C.c_int32), ("n_tracks", C.c_int32),
+                ("n_meas_total", C.c_int32), ("offsets", C.c_void_p), ("meas", C.c_void_p),
+                ("params", C.c_void_p), ("cov", C.c_void_p), ("chi2", C.c_void_p), ("ndf", C.c_void_p),
+                ("holes", C.c_void_p), ("seed", C.c_void_p), ("event", C.c_void_p),
+                ("last_surface", C.c_void_p)]
+
+
+_STAT_NAMES = ("steps", "navigations", "nav_modules", "legs", "legs_failed", "rk_trials", "rk_rejects",
+               "chi2_evals", "kf_updates", "ms_updates", "crossed", "holes", "pruned", "finished")
+
+
+class _Stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in _STAT_NAMES]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = C.CDLL(LIB)
+        _lib.orc_ckf_find.restype = C.c_int
+        _lib.orc_propagate.restype = C.c_int
+        _lib.orc_propagate_free.restype = C.c_int
+        _lib.orc_kf_update.restype = C.c_int
+        _lib.orc_trace.restype = C.c_int
+        _lib.orc_navigate.restype = C.c_int
+        _lib.orc_navigate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                      C.c_uint64, C.c_double, C.c_void_p, C.c_void_p]
+        _lib.orc_scatter.restype = C.c_int
+    return _lib
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+class Inputs:
+    """Keeps contiguous copies alive while the ctypes structs point at them."""
+
+    def __init__(self, geom: dict, bfield=(0.0, 0.0, 2.0), event=None):
+        self.keep = []
+        g = {k: np.ascontiguousarray(v) for k, v in geom.items()}
+        self.keep.append(g)
+        self.geom = _Geometry(g["center"].shape[0], _p(g["center"]), _p(g["rot"]), _p(g["half"]),
+                              _p(g["thick"]), _p(g["layer"]), g["layer_type"].shape[0],
+                              _p(g["layer_type"]), _p(g["layer_pos"]), _p(g["layer_lo"]), _p(g["layer_hi"]))
+        self.field = _Field((C.c_double * 3)(*bfield))
+        if event is not None:
+            self.set_event(event)
+
+    def set_event(self, ev, seeds=None):
+        off = np.ascontiguousarray(ev.offsets, np.int32)
+        loc = np.ascontiguousarray(ev.loc, np.float32)
+        var = np.ascontiguousarray(ev.var, np.float32)
+        se = np.ascontiguousarray(ev.seed_event, np.int32)
+        ss = np.ascontiguousarray(ev.seed_surface, np.int32)
+        sp = np.ascontiguousarray(ev.seed_params, np.float64)
+        sc = np.ascontiguousarray(ev.seed_cov, np.float64)
+        if seeds is not None:
+            se, ss, sp, sc = (np.ascontiguousarray(a[seeds]) for a in (se, ss, sp, sc))
+        self.keep.append((off, loc, var, se, ss, sp, sc))
+        self.meas = _Meas(ev.n_events, ev.n_surfaces, _p(off), _p(loc), _p(var))
+        self.seeds = _Seeds(sp.shape[0], _p(se), _p(ss), _p(sp), _p(sc))
+        self.n_seeds = sp.shape[0]
+
+
+def make_config(**over):
+    d = dict(DEFAULT_CONFIG)
+    d.update(over)
+    return _Config(**d), d
+
+
+def ckf_find(inp: Inputs, n_threads=0, cap_tracks=None, cap_meas=None, **cfg):
+    """Run the oracle; returns a dict of numpy arrays (tracks in seed order)."""
+    conf, _ = make_config(**cfg)
+    n = inp.n_seeds
+    mult = 1 if conf.tracks_per_seed == 1 else 64
+    cap_t = cap_tracks or max(1, n * mult)
+    cap_m = cap_meas or max(1, cap_t * 64)
+    out = dict(offsets=np.zeros(cap_t + 1, np.int32), meas=np.zeros(cap_m, np.int32),
+               params=np.zeros((cap_t, 5)), cov=np.zeros((cap_t, 15)), chi2=np.zeros(cap_t),
+               ndf=np.zeros(cap_t, np.int32), holes=np.zeros(cap_t, np.int32),
+               seed=np.zeros(cap_t, np.int32), event=np.zeros(cap_t, np.int32),
+               last_surface=np.zeros(cap_t, np.int32))
+    tr = _Tracks(cap_t, cap_m, 0, 0, *(_p(out[k]) for k in
+                                        ("offsets", "meas", "params", "cov", "chi2", "ndf", "holes",
+                                         "seed", "event", "last_surface")))
+    st = _Stats()
+    rc = lib().orc_ckf_find(C.byref(inp.geom), C.byref(inp.field), C.byref(inp.meas), C.byref(inp.seeds),
+                            C.byref(conf), int(n_threads), C.byref(tr), C.byref(st))
+    if rc != 0:
+        raise RuntimeError(f"orc_ckf_find failed with status {rc} (tracks {tr.n_tracks}, meas {tr.n_meas_total})")
+    nt, nm = tr.n_tracks, tr.n_meas_total
+    res = {k: v[:nt] for k, v in out.items() if k not in ("offsets", "meas")}
+    res["offsets"] = out["offsets"][:nt + 1]
+    res["meas"] = out["meas"][:nm]
+    res["n_tracks"] = nt
+    res["stats"] = {k: int(getattr(st, k)) for k in _STAT_NAMES}
+    return res
+
+
+def propagate(inp: Inputs, src, params, cov, dst, **cfg):
+    conf, _ = make_config(**cfg)
+    p = np.ascontiguousarray(params, np.float64)
+    c = np.ascontiguousarray(cov, np.float64)
+    po, co, jac, path = np.zeros(5), np.zeros(15), np.zeros(25), C.c_double(0)
+    rc = lib().orc_propagate(C.byref(inp.geom), C.byref(inp.field), C.byref(conf), int(src), _p(p), _p(c),
+                             int(dst), _p(po), _p(co), _p(jac), C.byref(path))
+    if rc != 0:
+        return None
+    return po, co, jac.reshape(5, 5), path.value
+
+
+def propagate_free(bfield, free, center, normal, **cfg):
+    conf, _ = make_config(**cfg)
+    f = _Field((C.c_double * 3)(*bfield))
+    fi = np.ascontiguousarray(free, np.float64)
+    cc = np.ascontiguousarray(center, np.float64)
+    nn = np.ascontiguousarray(normal, np.float64)
+    fo, path = np.zeros(7), C.c_double(0)
+    rc = lib().orc_propagate_free(C.byref(f), C.byref(conf), _p(fi), _p(cc), _p(nn), _p(fo), C.byref(path))
+    if rc != 0:
+        return None
+    return fo, path.value
+
+
+def kf_update(params, cov, meas, var):
+    p = np.ascontiguousarray(params, np.float64)
+    c = np.ascontiguousarray(cov, np.float64)
+    m = np.ascontiguousarray(meas, np.float64)
+    v = np.ascontiguousarray(var, np.float64)
+    po, co, x2 = np.zeros(5), np.zeros(15), C.c_double(0)
+    rc = lib().orc_kf_update(_p(p), _p(c), _p(m), _p(v), _p(po), _p(co), C.byref(x2))
+    assert rc == 0
+    return po, co, x2.value
+
+
+def trace(inp: Inputs, surface, params, cap=64, **cfg):
+    conf, _ = make_config(**cfg)
+    p = np.ascontiguousarray(params, np.float64)
+    vis, cr, po = np.zeros(cap, np.int32), np.zeros(cap, np.int32), np.zeros((cap, 5))
+    n = lib().orc_trace(C.byref(inp.geom), C.byref(inp.field), C.byref(conf), int(surface), _p(p), int(cap),
+                        _p(vis), _p(cr), _p(po))
+    return vis[:n], cr[:n], po[:n]
+
+
+def navigate(inp: Inputs, surface, params, mask, path=0.0, **cfg):
+    """(next layer or -1, listed modules) from bound parameters on surface."""
+    conf, _ = make_config(**cfg)
+    p = np.ascontiguousarray(params, np.float64)
+    lst, n = np.zeros(8, np.int32), C.c_int32(0)
+    L = lib().orc_navigate(C.addressof(inp.geom), C.addressof(inp.field), C.addressof(conf), int(surface),
+                           p.ctypes.data, C.c_uint64(int(mask)), float(path), lst.ctypes.data, C.addressof(n))
+    return L, lst[:n.value].tolist()
+
+
+def seed_list(inp: Inputs, surface, params, **cfg):
+    conf, _ = make_config(**cfg)
+    p = np.ascontiguousarray(params, np.float64)
+    lst = np.zeros(8, np.int32)
+    n = lib().orc_seed_list(C.byref(inp.geom), C.byref(inp.field), C.byref(conf), int(surface), _p(p), _p(lst))
+    return lst[:n].tolist()
+
+
+def scatter(inp: Inputs, surface, params, cov, **cfg):
+    conf, _ = make_config(**cfg)
+    p = np.ascontiguousarray(params, np.float64)
+    c = np.array(cov, np.float64)
+    assert lib().orc_scatter(C.byref(inp.geom), C.byref(conf), int(surface), _p(p), _p(c)) == 0
+    return c
+
+
+PACKED = [(i, j) for i in range(5) for j in range(i, 5)]
+
+
+def unpack_cov(c15):
+    c15 = np.asarray(c15)
+    M = np.zeros(c15.shape[:-1] + (5, 5))
+    for k, (i, j) in enumerate(PACKED):
+        M[..., i, j] = c15[..., k]
+        M[..., j, i] = c15[..., k]
+    return M
+
+
+def pack_cov(M):
+    M = np.asarray(M)
+    return np.stack([M[..., i, j] for (i, j) in PACKED], -1)

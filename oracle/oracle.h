@@ -1,0 +1,172 @@
+/* FP64 CPU oracle of combinatorial-Kalman-filter track finding.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against a plain, slow, obviously correct implementation of the same
+ * method.  Only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it; the GPU product path never does.  It shares no
+ * code, header or constant with the GPU library.
+ *
+ * Method (paper, section 2): seeds are propagated with the fourth-order
+ * Runge-Kutta-Nystrom method together with their covariance; on every
+ * intersected module a chi2 from the covariance and the residual decides
+ * whether a measurement is attached, each attached measurement making a new
+ * branch; the filtered parameters at the last measurement are the most
+ * accurate.  Material effects assume muons (section 3).  Every point the
+ * paper leaves open is fixed by a documented reading; see oracle.cpp.
+ *
+ * Conventions: mm, GeV, tesla, unit charge.  Bound parameters on a module
+ * are (loc0, loc1, phi, theta, q/p); free parameters (x, y, z, Tx, Ty, Tz,
+ * q/p).  Covariances cross the interface as the packed upper triangle of the
+ * 5x5 matrix, row-major: (00,01,02,03,04,11,12,13,14,22,23,24,33,34,44).
+ * All arrays are host memory owned by the caller.
+ */
+#ifndef CKF_ORACLE_H
+#define CKF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_geometry {
+  int32_t n_surfaces;
+  const float* center;      /* [n][3] */
+  const float* rot;         /* [n][9] rows u (loc0 axis), v (loc1 axis), n (normal) */
+  const float* half;        /* [n][2] half lengths along u, v */
+  const float* thick;       /* [n] thickness in radiation lengths */
+  const int32_t* layer;     /* [n] navigation layer of the module */
+  int32_t n_layers;
+  const int32_t* layer_type; /* [L] 0 barrel cylinder, 1 disk */
+  const float* layer_pos;    /* [L] envelope radius (barrel) or signed z (disk) */
+  const float* layer_lo;     /* [L] envelope extent: z_min (barrel), r_min (disk) */
+  const float* layer_hi;     /* [L] z_max (barrel), r_max (disk) */
+} orc_geometry;
+
+typedef struct orc_field {
+  double b[3];              /* uniform field, tesla */
+} orc_field;
+
+typedef struct orc_measurements {
+  int32_t n_events;
+  int32_t n_surfaces;
+  const int32_t* offsets;   /* [n_events*n_surfaces+1] rows of (event, surface) */
+  const float* loc;         /* [n][2] local position */
+  const float* var;         /* [n][2] variance of loc0, loc1 */
+} orc_measurements;
+
+typedef struct orc_seeds {
+  int32_t n_seeds;
+  const int32_t* event;     /* [k] */
+  const int32_t* surface;   /* [k] module the parameters are bound to */
+  const double* params;     /* [k][5] */
+  const double* cov;        /* [k][15] packed upper triangle */
+} orc_seeds;
+
+typedef struct orc_config {
+  double chi2_max;          /* gate: accept chi2 < chi2_max */
+  int32_t branches_per_surface;  /* keep at most this many measurements per module; <=0: all */
+  int32_t max_live_per_seed;     /* prune to this many live candidates per seed; <=0: no pruning */
+  int32_t max_holes;        /* terminate when holes exceed this */
+  int32_t min_meas;         /* finished candidates need this many measurements */
+  int32_t max_steps;        /* step budget per seed */
+  int32_t max_rk_steps;     /* RKN4 trials per leg before the leg fails */
+  double step_tol;          /* mm, RKN4 error-estimate tolerance */
+  double step_max;          /* mm, largest RKN4 step */
+  double land_tol;          /* mm, distance to the target plane that counts as landed */
+  double path_max;          /* mm, total path budget */
+  double nav_margin;        /* mm, margin of the module-listing test */
+  double mass;              /* GeV, particle hypothesis for scattering */
+  int32_t material_on;      /* apply multiple scattering */
+  int32_t tracks_per_seed;  /* 1: best finished candidate per seed; 0: all finished */
+} orc_config;
+
+typedef struct orc_tracks {
+  int32_t cap_tracks;       /* in: capacity of the per-track arrays */
+  int32_t cap_meas;         /* in: capacity of meas */
+  int32_t n_tracks;         /* out */
+  int32_t n_meas_total;     /* out (also set when capacity is short) */
+  int32_t* offsets;         /* [cap_tracks+1] */
+  int32_t* meas;            /* [cap_meas] measurement ids in visiting order */
+  double* params;           /* [cap_tracks][5] filtered at the last measurement */
+  double* cov;              /* [cap_tracks][15] */
+  double* chi2;             /* [cap_tracks] */
+  int32_t* ndf;
+  int32_t* holes;
+  int32_t* seed;
+  int32_t* event;
+  int32_t* last_surface;
+} orc_tracks;
+
+typedef struct orc_stats {
+  int64_t steps;            /* candidate steps */
+  int64_t navigations;      /* next-layer searches */
+  int64_t nav_modules;      /* modules put through the listing test */
+  int64_t legs;             /* propagations to a module */
+  int64_t legs_failed;
+  int64_t rk_trials;        /* RKN4 steps attempted (accepted + rejected) */
+  int64_t rk_rejects;
+  int64_t chi2_evals;
+  int64_t kf_updates;
+  int64_t ms_updates;
+  int64_t crossed;          /* visits that crossed their module */
+  int64_t holes;
+  int64_t pruned;
+  int64_t finished;
+} orc_stats;
+
+/* Status codes. */
+#define ORC_OK 0
+#define ORC_ERR_ARG 1
+#define ORC_ERR_CAPACITY 3
+#define ORC_ERR_FAILED 7
+
+/* Track finding for every seed; n_threads <= 0 uses all hardware threads.
+ * Output is ordered by seed index.  stats may be NULL. */
+int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc_measurements* m,
+                 const orc_seeds* s, const orc_config* cfg, int n_threads,
+                 orc_tracks* out, orc_stats* stats);
+
+/* Propagate bound parameters and covariance from module src to the plane of
+ * module dst (no material, no bounds test).  jac (5x5 row-major, may be
+ * NULL) is d(out)/d(in).  h_trial: in/out step-size hint (<=0: step_max).
+ * Returns ORC_OK or ORC_ERR_FAILED. */
+int orc_propagate(const orc_geometry* g, const orc_field* f, const orc_config* cfg,
+                  int32_t src, const double* p_in, const double* cov_in, int32_t dst,
+                  double* p_out, double* cov_out, double* jac, double* path);
+
+/* Propagate a free state (x,y,z,Tx,Ty,Tz,q/p) onto the plane through c with
+ * normal n; returns the landed free state and the path length. */
+int orc_propagate_free(const orc_field* f, const orc_config* cfg, const double* free_in,
+                       const double* c, const double* n, double* free_out, double* path);
+
+/* One Kalman update (gain form, Joseph covariance) with a 2D measurement. */
+int orc_kf_update(const double* p_in, const double* cov_in, const double* meas,
+                  const double* var, double* p_out, double* cov_out, double* chi2);
+
+/* Follow one track through the navigator without measurements or material:
+ * visited modules in order, whether each was crossed, and the bound
+ * parameters there.  Returns the number of visits written (<= cap). */
+int orc_trace(const orc_geometry* g, const orc_field* f, const orc_config* cfg,
+              int32_t surface, const double* params, int32_t cap,
+              int32_t* visited, int32_t* crossed, double* params_out);
+
+/* The navigator alone: from bound parameters on `surface` with visited-layer
+ * mask and path so far, the next layer (returned, -1 if none) and its listed
+ * modules in visiting order (at most 4, written to list, count to n_list). */
+int orc_navigate(const orc_geometry* g, const orc_field* f, const orc_config* cfg, int32_t surface,
+                 const double* params, uint64_t mask, double path, int32_t* list, int32_t* n_list);
+
+/* The modules of the seed's own layer that a seed on `surface` visits after
+ * its own (overlaps), in visiting order (at most 4); returns the count. */
+int orc_seed_list(const orc_geometry* g, const orc_field* f, const orc_config* cfg, int32_t surface,
+                  const double* params, int32_t* list);
+
+/* Multiple-scattering covariance increment for bound parameters on a module
+ * (adds to cov in place, packed upper triangle). */
+int orc_scatter(const orc_geometry* g, const orc_config* cfg, int32_t surface, const double* params,
+                double* cov);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
