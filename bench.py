@@ -1,0 +1,154 @@
+"""Throughput of CKF track finding on one MI355X.
+
+Workload: a batch of 64 synthetic mu = 200 events (about 10k seeds and 80k
+measurements each) in the barrel + endcap detector with 1 % X0 per module
+and a uniform 2 T field, found in one persistent launch.  A step is one
+ckf_find over the whole batch with inputs already resident in HBM.
+
+Prints one JSON line: tracks/s (output tracks / device time), the roofline
+object of the dominant kernel (k_ckf: algorithmic FP32 + FP64 work from the
+kernel's own work-unit counters, over its average duration measured with
+HIP events on its stream), and the oracle timed on the host's cores on a
+bounded sample of the same events.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per unit counted by the kernel (FP32 flop, FP64 flop);
+# the derivation is in the design doc.
+UNIT_FLOPS = {
+    "rk_trials": (505, 0),      # RKN4 stage algebra + 3 tangent columns + landing prediction
+    "legs": (300, 400),         # bound->free, free->bound Jacobian (FP32); J C J^T (FP64)
+    "navigations": (300, 0),    # helix set-up and envelope crossings
+    "nav_modules": (60, 0),     # listing test of one candidate module
+    "chi2_evals": (0, 15),      # 2x2 innovation chi2
+    "kf_updates": (0, 450),     # gain + Joseph update
+    "ms_updates": (40, 4),      # Highland width (FP32), covariance increment (FP64)
+}
+PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
+PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
+
+
+def _gen(args):
+    from synth import barrel_endcap, make_event
+    seed, mu = args
+    return make_event(barrel_endcap(), seed, mu=mu)
+
+
+def make_workload(n_events, mu, workers):
+    from synth import concat_events
+    jobs = [(6000 + i, mu) for i in range(n_events)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            evs = pool.map(_gen, jobs)
+    else:
+        evs = [_gen(j) for j in jobs]
+    return evs, concat_events(evs)
+
+
+def cpu_baseline(evs, batch, n_events):
+    import oracle
+    from synth import barrel_endcap
+    oracle.build(force=not os.path.exists(oracle.LIB))
+    det = barrel_endcap()
+    inp = oracle.Inputs(det.as_arrays(), (0, 0, 2.0))
+    sel = np.nonzero(batch.seed_event < n_events)[0]
+    inp.set_event(batch, seeds=sel)
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    r = oracle.ckf_find(inp, n_threads=cores)
+    dt = time.perf_counter() - t0
+    return dict(value=r["n_tracks"] / dt, unit="tracks/s", cores=cores, kind="oracle",
+                sample=f"first {n_events} of the {batch.n_events} events ({len(sel)} seeds, "
+                       f"{r['n_tracks']} tracks) in {dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--events", type=int, default=64)
+    ap.add_argument("--mu", type=float, default=200.0)
+    ap.add_argument("--cpu-events", type=int, default=8)
+    ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--seeds-per-group", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this track finder has no multi-GPU path "
+              "(events would be sharded across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    t0 = time.time()
+    evs, batch = make_workload(args.events, args.mu, args.workers)
+    print(f"# generated {batch.n_events} events, {batch.n_seeds} seeds, {batch.n_meas} measurements "
+          f"in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    import torch
+    import paper_2505_22822_amd as ckf
+    from synth import barrel_endcap
+    det = barrel_endcap()
+    geo = ckf.Geometry(det.as_arrays())
+    fld = ckf.UniformField(0.0, 0.0, 2.0)
+    b = ckf.Batch.from_event(batch)
+    timer = ckf.KernelTimer()
+    finder = ckf.Finder(geo, fld, b, ckf.config(),
+                        ckf.launch(args.grid, args.seeds_per_group, 0, timer))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        finder.enqueue(stream)
+    torch.cuda.synchronize()
+    r = finder.result()  # checks the status flags of the warm-up
+    n_tracks = r["n_tracks"]
+    counters = r["counters"]
+    print(f"# warm-up done: {n_tracks} tracks", file=sys.stderr, flush=True)
+
+    kernel_ms = []
+    t_start, t_stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        finder.enqueue(stream)
+        kernel_ms.append(timer.elapsed_ms())  # waits for this step's kernel
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_stop)
+    st = finder.status()
+    assert st[0] == 0, f"device status {st}"
+    ms_per_step = total_ms / args.steps
+    value = n_tracks / (ms_per_step * 1e-3)
+
+    f32 = sum(counters[k] * UNIT_FLOPS[k][0] for k in UNIT_FLOPS)
+    f64 = sum(counters[k] * UNIT_FLOPS[k][1] for k in UNIT_FLOPS)
+    k_ms = float(np.mean(kernel_ms))
+    t = k_ms * 1e-3
+    frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64) / t
+    roofline = dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3), peak=PEAK_FP32 / 1e12,
+                    unit="TFLOP/s", frac=round(frac, 5), traffic=None,
+                    kernel="k_ckf", kernel_ms=round(k_ms, 4), fp32_flop=f32, fp64_flop=f64,
+                    note="achieved = FP32-equivalent rate (F32 + 2*F64)/t against the FP32 vector peak")
+    cpu = None
+    if args.cpu_events > 0:
+        cpu = cpu_baseline(evs, batch, min(args.cpu_events, batch.n_events))
+    line = dict(metric="CKF tracks/s at mu=200 on 1 GPU", value=round(value, 1), unit="tracks/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
+                config=dict(workload=f"{batch.n_events} x mu={args.mu:g} events, barrel+endcap, 1% X0, 2 T, "
+                                     f"plain CKF", events=batch.n_events, seeds=batch.n_seeds,
+                            measurements=batch.n_meas, tracks=n_tracks),
+                roofline=roofline, cpu_baseline=cpu, counters=counters)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

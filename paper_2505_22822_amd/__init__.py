@@ -1,0 +1,259 @@
+"""MI355X-native combinatorial Kalman filter (CKF) track finding.
+
+Thin Python binding over libckf.so (include/ckf.h): every step of the track
+finder runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch provides device memory and streams.  There is no CPU
+fallback: importing works without a GPU, but every call needs libckf.so and
+a visible GPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+from ._abi import COUNTER_NAMES
+
+__all__ = ["Geometry", "UniformField", "config", "find", "propagate_batch", "kf_update_batch", "CkfError"]
+
+
+class CkfError(RuntimeError):
+    def __init__(self, status, where):
+        lib = _abi.load()
+        msg = lib.ckf_last_error().decode()
+        super().__init__(f"{where}: {_abi.STATUS_NAMES.get(status, status)} ({msg})")
+        self.status = status
+
+
+def _check(rc, where):
+    if rc != _abi.CKF_OK:
+        raise CkfError(rc, where)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def config(**over) -> _abi.Config:
+    """Library defaults (ckf_config_default) with overrides."""
+    c = _abi.Config()
+    _abi.load().ckf_config_default(C.byref(c))
+    for k, v in over.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+class Geometry:
+    """Detector description uploaded once (ckf_geometry_create)."""
+
+    def __init__(self, arrays: dict):
+        lib = _abi.load()
+        a = {k: np.ascontiguousarray(v) for k, v in arrays.items()}
+        self._keep = a
+        d = _abi.GeometryDesc(
+            a["center"].shape[0], a["center"].ctypes.data, a["rot"].ctypes.data, a["half"].ctypes.data,
+            a["thick"].ctypes.data, a["layer"].ctypes.data, a["layer_type"].shape[0], a["layer_type"].ctypes.data,
+            a["layer_pos"].ctypes.data, a["layer_lo"].ctypes.data, a["layer_hi"].ctypes.data)
+        for k, dt in (("center", np.float32), ("rot", np.float32), ("half", np.float32), ("thick", np.float32),
+                      ("layer", np.int32), ("layer_type", np.int32), ("layer_pos", np.float32),
+                      ("layer_lo", np.float32), ("layer_hi", np.float32)):
+            if a[k].dtype != dt:
+                raise TypeError(f"geometry array {k} must be {np.dtype(dt).name}")
+        h = C.c_void_p()
+        _check(lib.ckf_geometry_create(C.byref(d), C.byref(h)), "ckf_geometry_create")
+        self.handle = h
+        self.n_surfaces = int(a["center"].shape[0])
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _abi.load().ckf_geometry_destroy(h)
+            self.handle = None
+
+
+class UniformField:
+    def __init__(self, bx=0.0, by=0.0, bz=2.0):
+        h = C.c_void_p()
+        _check(_abi.load().ckf_field_create_uniform(bx, by, bz, C.byref(h)), "ckf_field_create_uniform")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _abi.load().ckf_field_destroy(h)
+            self.handle = None
+
+
+@dataclass
+class Batch:
+    """Device-resident inputs of one ckf_find call (torch tensors)."""
+    n_events: int
+    n_surfaces: int
+    offsets: "object"   # int32 [E*S+1]
+    loc: "object"       # float32 [n, 2]
+    var: "object"       # float32 [n, 2]
+    seed_event: "object"    # int32 [k]
+    seed_surface: "object"  # int32 [k]
+    seed_params: "object"   # float64 [k, 5]
+    seed_cov: "object"      # float64 [k, 15]
+
+    @staticmethod
+    def from_event(ev, device="cuda"):
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+        return Batch(ev.n_events, ev.n_surfaces, t(ev.offsets, torch.int32), t(ev.loc, torch.float32),
+                     t(ev.var, torch.float32), t(ev.seed_event, torch.int32), t(ev.seed_surface, torch.int32),
+                     t(ev.seed_params, torch.float64), t(ev.seed_cov, torch.float64))
+
+    @property
+    def n_seeds(self):
+        return int(self.seed_params.shape[0])
+
+    @property
+    def n_meas(self):
+        return int(self.loc.shape[0])
+
+
+def launch(grid=0, seeds_per_group=0, nodes_per_seed=0, timer=None) -> _abi.Launch:
+    return _abi.Launch(grid, seeds_per_group, nodes_per_seed, timer.handle if timer is not None else None)
+
+
+class KernelTimer:
+    """HIP events ckf_find records around its persistent kernel."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(_abi.load().ckf_timer_create(C.byref(h)), "ckf_timer_create")
+        self.handle = h
+
+    def elapsed_ms(self) -> float:
+        ms = C.c_float(0)
+        _check(_abi.load().ckf_timer_elapsed_ms(self.handle, C.byref(ms)), "ckf_timer_elapsed_ms")
+        return float(ms.value)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _abi.load().ckf_timer_destroy(h)
+            self.handle = None
+
+
+class Finder:
+    """Holds the workspace and output buffers of repeated ckf_find calls on
+    one batch shape, so the timed call allocates nothing."""
+
+    def __init__(self, geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, counters=True):
+        import torch
+        self.geometry, self.field, self.batch = geometry, field, batch
+        self.cfg = cfg if cfg is not None else config()
+        self.launch = launch_cfg if launch_cfg is not None else launch()
+        dev = batch.loc.device
+        lib = _abi.load()
+        nb = C.c_size_t(0)
+        _check(lib.ckf_workspace_size(geometry.handle, C.byref(self.cfg), C.byref(self.launch), batch.n_events,
+                                      batch.n_seeds, batch.n_meas, C.byref(nb)), "ckf_workspace_size")
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+        n = max(1, batch.n_seeds)
+        cap_m = n * int(self.cfg.max_steps)
+        z = lambda shape, dt: torch.zeros(shape, dtype=dt, device=dev)
+        self.out = dict(n_tracks=z(1, torch.int32), offsets=z(n + 1, torch.int32), meas=z(cap_m, torch.int32),
+                        params=z((n, 5), torch.float64), cov=z((n, 15), torch.float64), chi2=z(n, torch.float64),
+                        ndf=z(n, torch.int32), holes=z(n, torch.int32), seed=z(n, torch.int32),
+                        event=z(n, torch.int32), last_surface=z(n, torch.int32), status=z(8, torch.int32),
+                        counters=z(16, torch.int64) if counters else None)
+        o = self.out
+        self._tracks = _abi.Tracks(n, cap_m, *(_ptr(o[k]) for k in
+                                              ("n_tracks", "offsets", "meas", "params", "cov", "chi2", "ndf",
+                                               "holes", "seed", "event", "last_surface", "status", "counters")))
+        b = batch
+        self._meas = _abi.Measurements(b.n_events, b.n_surfaces, b.n_meas, _ptr(b.offsets), _ptr(b.loc),
+                                       _ptr(b.var))
+        self._seeds = _abi.Seeds(b.n_seeds, _ptr(b.seed_event), _ptr(b.seed_surface), _ptr(b.seed_params),
+                                 _ptr(b.seed_cov))
+
+    def enqueue(self, stream=None):
+        """One ckf_find on the stream (asynchronous, allocation-free)."""
+        lib = _abi.load()
+        _check(lib.ckf_find(self.geometry.handle, self.field.handle, C.byref(self._meas), C.byref(self._seeds),
+                            C.byref(self.cfg), C.byref(self.launch), _ptr(self.workspace),
+                            self.workspace.numel(), C.byref(self._tracks), _stream_handle(stream)), "ckf_find")
+
+    def status(self):
+        return self.out["status"].cpu().numpy()
+
+    def result(self, check=True):
+        """Synchronise and return the found tracks as numpy arrays."""
+        import torch
+        torch.cuda.synchronize()
+        st = self.status()
+        if check and st[_abi.ST_FLAGS] != 0:
+            raise CkfError(3 if st[_abi.ST_FLAGS] & 3 else 2, f"device status flags {st[_abi.ST_FLAGS]}")
+        o = {k: v.cpu().numpy() for k, v in self.out.items() if v is not None}
+        nt = int(o["n_tracks"][0])
+        res = {k: o[k][:nt] for k in ("params", "cov", "chi2", "ndf", "holes", "seed", "event", "last_surface")}
+        res["offsets"] = o["offsets"][:nt + 1]
+        res["meas"] = o["meas"][:int(o["offsets"][nt]) if nt > 0 else 0]
+        res["n_tracks"] = nt
+        res["status"] = st
+        if "counters" in o:
+            res["counters"] = {n: int(o["counters"][i]) for i, n in enumerate(COUNTER_NAMES)}
+        return res
+
+
+def find(geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, stream=None, retries=3):
+    """Run the track finder on one batch and return the tracks (numpy).
+    Retries with a larger history capacity if the device reports it short."""
+    lc = launch_cfg if launch_cfg is not None else launch()
+    for _ in range(retries + 1):
+        f = Finder(geometry, field, batch, cfg, lc)
+        f.enqueue(stream)
+        r = f.result(check=False)
+        flags = int(r["status"][_abi.ST_FLAGS])
+        if flags & _abi.FLAG_BAD_OFFSETS:
+            raise CkfError(2, "measurement offsets are not non-decreasing")
+        if flags & _abi.FLAG_NODE_CAPACITY:
+            lc = _abi.Launch(lc.grid, lc.seeds_per_group, 2 * (lc.nodes_per_seed or 32), lc.timer)
+            continue
+        if flags:
+            raise CkfError(3, f"device status flags {flags}")
+        return r
+    raise CkfError(3, "history capacity still short after retries")
+
+
+def propagate_batch(geometry, field, src, params, cov, dst, cfg=None, stream=None):
+    """Component call: propagate bound states src -> dst (torch device tensors)."""
+    import torch
+    cfg = cfg if cfg is not None else config()
+    n = int(params.shape[0])
+    dev = params.device
+    p_out = torch.zeros((n, 5), dtype=torch.float64, device=dev)
+    c_out = torch.zeros((n, 15), dtype=torch.float64, device=dev)
+    jac = torch.zeros((n, 25), dtype=torch.float64, device=dev)
+    path = torch.zeros(n, dtype=torch.float64, device=dev)
+    ok = torch.zeros(n, dtype=torch.int32, device=dev)
+    _check(_abi.load().ckf_propagate_batch(geometry.handle, field.handle, C.byref(cfg), n, _ptr(src), _ptr(params),
+                                           _ptr(cov), _ptr(dst), _ptr(p_out), _ptr(c_out), _ptr(jac), _ptr(path),
+                                           _ptr(ok), _stream_handle(stream)), "ckf_propagate_batch")
+    return p_out, c_out, jac.view(n, 5, 5), path, ok
+
+
+def kf_update_batch(params, cov, meas, var, stream=None):
+    import torch
+    n = int(params.shape[0])
+    dev = params.device
+    p_out = torch.zeros((n, 5), dtype=torch.float64, device=dev)
+    c_out = torch.zeros((n, 15), dtype=torch.float64, device=dev)
+    chi2 = torch.zeros(n, dtype=torch.float64, device=dev)
+    _check(_abi.load().ckf_kf_update_batch(n, _ptr(params), _ptr(cov), _ptr(meas), _ptr(var), _ptr(p_out),
+                                           _ptr(c_out), _ptr(chi2), _stream_handle(stream)), "ckf_kf_update_batch")
+    return p_out, c_out, chi2

@@ -1,0 +1,86 @@
+"""ctypes mirror of include/ckf.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libckf.so")
+
+VP = C.c_void_p
+I32, I64, F32, F64 = C.c_int32, C.c_int64, C.c_float, C.c_double
+
+CKF_OK = 0
+STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsorted input", 3: "capacity", 4: "device",
+                5: "not supported", 6: "no model"}
+FLAG_NODE_CAPACITY, FLAG_OUT_CAPACITY, FLAG_BAD_OFFSETS = 1, 2, 4
+ST_FLAGS, ST_NODES, ST_TRACKS, ST_MEAS, ST_BAD_SEEDS, ST_FAILED_LEGS, ST_NAV_OVF = range(7)
+COUNTER_NAMES = ("steps", "navigations", "nav_modules", "legs", "rk_trials", "chi2_evals", "kf_updates",
+                 "ms_updates", "crossed", "holes", "pruned", "finished", "rk_rejects")
+
+
+class GeometryDesc(C.Structure):
+    _fields_ = [("n_surfaces", I32), ("center", VP), ("rot", VP), ("half", VP), ("thick", VP), ("layer", VP),
+                ("n_layers", I32), ("layer_type", VP), ("layer_pos", VP), ("layer_lo", VP), ("layer_hi", VP)]
+
+
+class Config(C.Structure):
+    _fields_ = [("chi2_max", F64), ("branches_per_surface", I32), ("max_live_per_seed", I32),
+                ("max_holes", I32), ("min_meas", I32), ("max_steps", I32), ("max_rk_steps", I32),
+                ("step_tol", F64), ("step_max", F64), ("land_tol", F64), ("path_max", F64),
+                ("nav_margin", F64), ("mass", F64), ("material_on", I32), ("tracks_per_seed", I32)]
+
+
+class Measurements(C.Structure):
+    _fields_ = [("n_events", I32), ("n_surfaces", I32), ("n_meas", I64), ("offsets", VP), ("loc", VP),
+                ("var", VP)]
+
+
+class Seeds(C.Structure):
+    _fields_ = [("n_seeds", I32), ("event", VP), ("surface", VP), ("params", VP), ("cov", VP)]
+
+
+class Tracks(C.Structure):
+    _fields_ = [("cap_tracks", I32), ("cap_meas", I64), ("n_tracks", VP), ("offsets", VP), ("meas", VP),
+                ("params", VP), ("cov", VP), ("chi2", VP), ("ndf", VP), ("holes", VP), ("seed", VP),
+                ("event", VP), ("last_surface", VP), ("status", VP), ("counters", VP)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("grid", I32), ("seeds_per_group", I32), ("nodes_per_seed", I32), ("timer", VP)]
+
+
+# every exported symbol of include/ckf.h with its ctypes signature
+SIGNATURES = {
+    "ckf_geometry_create": (I32, [C.POINTER(GeometryDesc), C.POINTER(VP)]),
+    "ckf_geometry_destroy": (None, [VP]),
+    "ckf_field_create_uniform": (I32, [F32, F32, F32, C.POINTER(VP)]),
+    "ckf_field_destroy": (None, [VP]),
+    "ckf_config_default": (None, [C.POINTER(Config)]),
+    "ckf_workspace_size": (I32, [VP, C.POINTER(Config), C.POINTER(Launch), I32, I32, I64, C.POINTER(C.c_size_t)]),
+    "ckf_find": (I32, [VP, VP, C.POINTER(Measurements), C.POINTER(Seeds), C.POINTER(Config), C.POINTER(Launch),
+                       VP, C.c_size_t, C.POINTER(Tracks), VP]),
+    "ckf_propagate_batch": (I32, [VP, VP, C.POINTER(Config), I32, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "ckf_kf_update_batch": (I32, [I32, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "ckf_timer_create": (I32, [C.POINTER(VP)]),
+    "ckf_timer_destroy": (None, [VP]),
+    "ckf_timer_elapsed_ms": (I32, [VP, C.POINTER(F32)]),
+    "ckf_status_string": (C.c_char_p, [I32]),
+    "ckf_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libckf.so; there is no fallback when it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python paper_2505_22822_amd/build.py")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib

@@ -1,0 +1,534 @@
+// Host runtime of the C ABI: validation, the navigation grid, workspace
+// carving and kernel launches.  No allocation happens in ckf_find.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ckf.h"
+#include "ckf_internal.hpp"
+#include "ckf_kernels.hpp"
+
+struct ckf_geometry {
+  ckf::GeomDev dev;
+  std::vector<void*> allocations;
+  int device;
+};
+
+struct ckf_field {
+  ckf::FieldDev dev;
+};
+
+struct ckf_timer {
+  hipEvent_t start, stop;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ckf_status fail(ckf_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+ckf_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return CKF_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr, what)                  \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+constexpr double kPi = 3.14159265358979323846;
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Boundary points of a module rectangle expanded by `pad`.
+void rect_samples(const ckf::Module& M, double pad, std::vector<double>& xs) {
+  xs.clear();
+  const double a = M.hw0 + pad, b = M.hw1 + pad;
+  const int k = 24;
+  for (int e = 0; e < 4; ++e)
+    for (int t = 0; t <= k; ++t) {
+      const double f = -1.0 + 2.0 * t / k;
+      double l0, l1;
+      if (e == 0) { l0 = f * a; l1 = -b; }
+      else if (e == 1) { l0 = a; l1 = f * b; }
+      else if (e == 2) { l0 = -f * a; l1 = b; }
+      else { l0 = -a; l1 = -f * b; }
+      for (int d = 0; d < 3; ++d) xs.push_back(M.c[d] + l0 * M.u[d] + l1 * M.v[d]);
+    }
+}
+
+struct HostGrid {
+  std::vector<ckf::LayerRec> layers;
+  std::vector<int> cell_off, cell_mod;
+  std::vector<int> barrel, disk_pos, disk_neg;
+};
+
+ckf_status build_grid(const ckf_geometry_desc* d, const std::vector<ckf::Module>& mods, HostGrid& G) {
+  const int L = d->n_layers;
+  G.layers.resize(L);
+  std::vector<std::vector<int>> members(L);
+  for (int i = 0; i < d->n_surfaces; ++i) members[d->layer[i]].push_back(i);
+  std::vector<std::vector<int>> cells;
+  std::vector<double> xs;
+  int cell_base = 0;
+  for (int l = 0; l < L; ++l) {
+    ckf::LayerRec& R = G.layers[l];
+    R.type = d->layer_type[l];
+    R.pos = d->layer_pos[l];
+    R.lo = d->layer_lo[l];
+    R.hi = d->layer_hi[l];
+    // extents of the padded modules in (phi, w) and the layer depth
+    double wlo = 1e30, whi = -1e30, depth = 0.0, rmax = 0.0;
+    struct Ext {
+      double plo, phi, wlo, whi;
+    };
+    std::vector<Ext> ext(members[l].size());
+    for (size_t q = 0; q < members[l].size(); ++q) {
+      const ckf::Module& M = mods[members[l][q]];
+      rect_samples(M, ckf::kGridPad, xs);
+      const double pc = std::atan2((double)M.c[1], (double)M.c[0]);
+      double plo = 1e30, phi = -1e30, a = 1e30, b = -1e30;
+      for (size_t k = 0; k < xs.size(); k += 3) {
+        const double x = xs[k], y = xs[k + 1], z = xs[k + 2];
+        const double r = std::sqrt(x * x + y * y);
+        double dp = std::atan2(y, x) - pc;
+        while (dp > kPi) dp -= 2 * kPi;
+        while (dp < -kPi) dp += 2 * kPi;
+        plo = std::min(plo, pc + dp);
+        phi = std::max(phi, pc + dp);
+        const double w = R.type == 0 ? z : r;
+        a = std::min(a, w);
+        b = std::max(b, w);
+        depth = std::max(depth, R.type == 0 ? r - R.pos : std::fabs(z) - std::fabs((double)R.pos));
+        rmax = std::max(rmax, r);
+      }
+      // the inner radius of a rectangle can lie inside an edge: sample densely above
+      ext[q] = {plo, phi, a, b};
+      wlo = std::min(wlo, a);
+      whi = std::max(whi, b);
+    }
+    if (members[l].empty()) {
+      wlo = R.lo;
+      whi = R.hi;
+    }
+    R.depth = (float)(depth + 1.0);
+    R.wlo = (float)wlo;
+    R.whi = (float)whi;
+    const double radius = R.type == 0 ? (double)R.pos : std::max(rmax, 1.0);
+    R.nphi = std::max(1, std::min(4096, (int)std::lround(2 * kPi * radius / 20.0)));
+    R.nw = std::max(1, std::min(4096, (int)std::lround((whi - wlo) / (R.type == 0 ? 60.0 : 30.0))));
+    R.cell_base = cell_base;
+    const int nc = R.nphi * R.nw;
+    cells.resize(cell_base + nc);
+    const double bph = 2 * kPi / R.nphi, bw = (whi - wlo) / R.nw;
+    for (size_t q = 0; q < members[l].size(); ++q) {
+      const Ext& e = ext[q];
+      const int ip0 = (int)std::floor((e.plo + kPi) / bph), ip1 = (int)std::floor((e.phi + kPi) / bph);
+      int iw0 = (int)std::floor((e.wlo - wlo) / bw), iw1 = (int)std::floor((e.whi - wlo) / bw);
+      iw0 = std::max(0, iw0);
+      iw1 = std::min(R.nw - 1, iw1);
+      const int span = std::min(ip1 - ip0, R.nphi - 1);
+      for (int ipr = ip0; ipr <= ip0 + span; ++ipr) {
+        int ip = ipr % R.nphi;
+        if (ip < 0) ip += R.nphi;
+        for (int iw = iw0; iw <= iw1; ++iw) cells[cell_base + ip * R.nw + iw].push_back(members[l][q]);
+      }
+    }
+    cell_base += nc;
+    if (R.type == 0) G.barrel.push_back(l);
+    else if (R.pos > 0) G.disk_pos.push_back(l);
+    else G.disk_neg.push_back(l);
+  }
+  G.cell_off.assign(1, 0);
+  for (auto& c : cells) {
+    std::sort(c.begin(), c.end());
+    G.cell_mod.insert(G.cell_mod.end(), c.begin(), c.end());
+    G.cell_off.push_back((int)G.cell_mod.size());
+  }
+  auto by_pos = [&](int a, int b) {
+    const float pa = std::fabs(G.layers[a].pos), pb = std::fabs(G.layers[b].pos);
+    return pa < pb || (pa == pb && a < b);
+  };
+  std::sort(G.barrel.begin(), G.barrel.end(), by_pos);
+  std::sort(G.disk_pos.begin(), G.disk_pos.end(), by_pos);
+  std::sort(G.disk_neg.begin(), G.disk_neg.end(), by_pos);
+  return CKF_OK;
+}
+
+template <class T>
+ckf_status upload(ckf_geometry* g, const std::vector<T>& v, const T** out) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+  HIP_TRY(hipMalloc(&p, bytes), "hipMalloc(geometry)");
+  g->allocations.push_back(p);
+  if (!v.empty()) HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy(geometry)");
+  *out = static_cast<const T*>(p);
+  return CKF_OK;
+}
+
+ckf_status check_config(const ckf_config* c) {
+  if (!c) return fail(CKF_ERR_INVALID_ARGUMENT, "config is NULL");
+  if (!(c->chi2_max > 0) || !(c->step_tol > 0) || !(c->step_max > 0) || !(c->land_tol > 0) || !(c->path_max > 0) ||
+      !(c->nav_margin >= 0) || !(c->mass >= 0) || c->max_holes < 0 || c->min_meas < 0 || c->max_steps < 1 ||
+      c->max_rk_steps < 1)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "config value out of range");
+  if (c->branches_per_surface < 1 || c->branches_per_surface > ckf::kMaxBranch)
+    return fail(CKF_ERR_NOT_SUPPORTED, "branches_per_surface must be 1..4 on the GPU");
+  if (c->max_live_per_seed < 1 || c->max_live_per_seed * c->branches_per_surface > 64)
+    return fail(CKF_ERR_NOT_SUPPORTED, "max_live_per_seed * branches_per_surface must be 1..64 on the GPU");
+  if (c->max_steps > ckf::kMaxSteps) return fail(CKF_ERR_NOT_SUPPORTED, "max_steps must be <= 64");
+  if (c->tracks_per_seed != 1) return fail(CKF_ERR_NOT_SUPPORTED, "tracks_per_seed must be 1 on the GPU");
+  if (c->nav_margin > ckf::kMaxNavMargin) return fail(CKF_ERR_NOT_SUPPORTED, "nav_margin must be <= 2 mm");
+  return CKF_OK;
+}
+
+ckf::CfgDev to_dev(const ckf_config* c) {
+  ckf::CfgDev d;
+  d.chi2_max = c->chi2_max;
+  d.branches = c->branches_per_surface;
+  d.max_live = c->max_live_per_seed;
+  d.max_holes = c->max_holes;
+  d.min_meas = c->min_meas;
+  d.max_steps = c->max_steps;
+  d.max_rk = c->max_rk_steps;
+  d.step_tol = (float)c->step_tol;
+  d.step_max = (float)c->step_max;
+  d.land_tol = (float)c->land_tol;
+  d.path_max = (float)c->path_max;
+  d.nav_margin = (float)c->nav_margin;
+  d.mass = c->mass;
+  d.material = c->material_on != 0;
+  return d;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  return cus;
+}
+
+constexpr int kDefaultSeedsPerGroup = 32;
+constexpr int kDefaultGroupsPerCU = 8;
+constexpr int kNodesPerSeed = 32;
+
+ckf::Launch resolve_launch(const ckf_config* c, const ckf_launch* l, int n_seeds) {
+  ckf::Launch r;
+  r.seeds_per_group = (l && l->seeds_per_group > 0) ? std::min(64, l->seeds_per_group) : kDefaultSeedsPerGroup;
+  const int want = (n_seeds + r.seeds_per_group - 1) / r.seeds_per_group;
+  const int dflt = device_cus() * kDefaultGroupsPerCU;
+  r.grid = std::max(1, std::min((l && l->grid > 0) ? l->grid : dflt, std::max(1, want)));
+  r.pool_cap = r.seeds_per_group * (c->max_live_per_seed * c->branches_per_surface + 1);
+  r.nodes_per_seed = (l && l->nodes_per_seed > 0) ? l->nodes_per_seed : kNodesPerSeed;
+  return r;
+}
+
+struct Layout {
+  size_t off_loc0, off_loc1, off_var0, off_var1, off_id, off_maxv, off_nodes, off_nodecnt, off_queue, off_res_node,
+      off_res_nm, off_res_holes, off_res_chi2, off_scan_a, off_scan_b, off_pools, total;
+  long long node_cap;
+};
+
+Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, long long n_meas) {
+  Layout o;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = at;
+    at = align_up(at + std::max<size_t>(bytes, 1));
+    return r;
+  };
+  const size_t nm = (size_t)std::max<long long>(n_meas, 1);
+  const size_t rows = (size_t)std::max(1, n_events * n_surfaces);
+  const size_t ns = (size_t)std::max(1, n_seeds);
+  o.node_cap = (long long)ns * L.nodes_per_seed + 1024;
+  o.off_loc0 = take(nm * 4);
+  o.off_loc1 = take(nm * 4);
+  o.off_var0 = take(nm * 4);
+  o.off_var1 = take(nm * 4);
+  o.off_id = take(nm * 4);
+  o.off_maxv = take(rows * 4);
+  o.off_nodes = take((size_t)o.node_cap * sizeof(ckf::Node));
+  o.off_nodecnt = take(8);
+  o.off_queue = take(8);
+  o.off_res_node = take(ns * 4);
+  o.off_res_nm = take(ns * 4);
+  o.off_res_holes = take(ns * 4);
+  o.off_res_chi2 = take(ns * 8);
+  const size_t nb = (ns + 255) / 256 + 1;
+  o.off_scan_a = take(nb * 4);
+  o.off_scan_b = take(nb * 4);
+  o.off_pools = take((size_t)L.grid * 2 * L.pool_cap * ckf::kRecBytes);
+  o.total = at;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ckf_status_string(ckf_status s) {
+  switch (s) {
+    case CKF_OK: return "ok";
+    case CKF_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case CKF_ERR_UNSORTED_INPUT: return "unsorted input";
+    case CKF_ERR_CAPACITY: return "capacity too small";
+    case CKF_ERR_DEVICE: return "device error";
+    case CKF_ERR_NOT_SUPPORTED: return "not supported";
+    case CKF_ERR_NO_MODEL: return "no model";
+  }
+  return "unknown status";
+}
+
+const char* ckf_last_error(void) { return g_last_error.c_str(); }
+
+void ckf_config_default(ckf_config* c) {
+  if (!c) return;
+  c->chi2_max = 15.0;
+  c->branches_per_surface = 3;
+  c->max_live_per_seed = 10;
+  c->max_holes = 3;
+  c->min_meas = 6;
+  c->max_steps = 48;
+  c->max_rk_steps = 100;
+  c->step_tol = 1e-3;
+  c->step_max = 200.0;
+  c->land_tol = 1e-4;
+  c->path_max = 4000.0;
+  c->nav_margin = 1.0;
+  c->mass = 0.1056583755;
+  c->material_on = 1;
+  c->tracks_per_seed = 1;
+}
+
+ckf_status ckf_geometry_create(const ckf_geometry_desc* d, ckf_geometry** out) {
+  if (!d || !out) return fail(CKF_ERR_INVALID_ARGUMENT, "geometry_create: NULL argument");
+  *out = nullptr;
+  if (d->n_surfaces <= 0 || d->n_layers <= 0) return fail(CKF_ERR_INVALID_ARGUMENT, "geometry: empty");
+  if (d->n_layers > ckf::kMaxLayers) return fail(CKF_ERR_NOT_SUPPORTED, "geometry: more than 64 layers");
+  if (!d->center || !d->rot || !d->half || !d->thick || !d->layer || !d->layer_type || !d->layer_pos ||
+      !d->layer_lo || !d->layer_hi)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "geometry: NULL array");
+  for (int l = 0; l < d->n_layers; ++l) {
+    if (d->layer_type[l] != 0 && d->layer_type[l] != 1) return fail(CKF_ERR_INVALID_ARGUMENT, "geometry: layer type");
+    if (!std::isfinite(d->layer_pos[l]) || !(d->layer_lo[l] <= d->layer_hi[l]))
+      return fail(CKF_ERR_INVALID_ARGUMENT, "geometry: layer envelope");
+    if (d->layer_type[l] == 0 && !(d->layer_pos[l] > 0)) return fail(CKF_ERR_INVALID_ARGUMENT, "geometry: barrel radius");
+  }
+  std::vector<ckf::Module> mods(d->n_surfaces);
+  for (int i = 0; i < d->n_surfaces; ++i) {
+    const float* r = d->rot + 9 * i;
+    if (!finite3(d->center + 3 * i) || !finite3(r) || !finite3(r + 3) || !finite3(r + 6) ||
+        !(d->half[2 * i] > 0) || !(d->half[2 * i + 1] > 0) || !(d->thick[i] >= 0) || d->layer[i] < 0 ||
+        d->layer[i] >= d->n_layers)
+      return fail(CKF_ERR_INVALID_ARGUMENT, "geometry: bad module " + std::to_string(i));
+    ckf::Module& M = mods[i];
+    for (int k = 0; k < 3; ++k) {
+      M.c[k] = d->center[3 * i + k];
+      M.u[k] = r[k];
+      M.v[k] = r[3 + k];
+      M.n[k] = r[6 + k];
+    }
+    M.hw0 = d->half[2 * i];
+    M.hw1 = d->half[2 * i + 1];
+    M.thick = d->thick[i];
+    M.layer = d->layer[i];
+  }
+  HostGrid G;
+  ckf_status st = build_grid(d, mods, G);
+  if (st != CKF_OK) return st;
+  ckf_geometry* g = new ckf_geometry();
+  hipGetDevice(&g->device);
+  auto cleanup = [&](ckf_status s) {
+    for (void* p : g->allocations) (void)hipFree(p);
+    delete g;
+    return s;
+  };
+  const ckf::Module* dm;
+  const ckf::LayerRec* dl;
+  const int *co, *cm, *bo, *dp, *dn;
+  if ((st = upload(g, mods, &dm)) != CKF_OK || (st = upload(g, G.layers, &dl)) != CKF_OK ||
+      (st = upload(g, G.cell_off, &co)) != CKF_OK || (st = upload(g, G.cell_mod, &cm)) != CKF_OK ||
+      (st = upload(g, G.barrel, &bo)) != CKF_OK || (st = upload(g, G.disk_pos, &dp)) != CKF_OK ||
+      (st = upload(g, G.disk_neg, &dn)) != CKF_OK)
+    return cleanup(st);
+  g->dev.n_surfaces = d->n_surfaces;
+  g->dev.n_layers = d->n_layers;
+  g->dev.mod = dm;
+  g->dev.layers = dl;
+  g->dev.cell_off = co;
+  g->dev.cell_mod = cm;
+  g->dev.barrel_order = bo;
+  g->dev.disk_pos = dp;
+  g->dev.disk_neg = dn;
+  g->dev.n_barrel = (int)G.barrel.size();
+  g->dev.n_disk_pos = (int)G.disk_pos.size();
+  g->dev.n_disk_neg = (int)G.disk_neg.size();
+  *out = g;
+  return CKF_OK;
+}
+
+void ckf_geometry_destroy(ckf_geometry* g) {
+  if (!g) return;
+  for (void* p : g->allocations) (void)hipFree(p);
+  delete g;
+}
+
+ckf_status ckf_field_create_uniform(float bx, float by, float bz, ckf_field** out) {
+  if (!out) return fail(CKF_ERR_INVALID_ARGUMENT, "field_create: NULL out");
+  if (!std::isfinite(bx) || !std::isfinite(by) || !std::isfinite(bz))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "field_create: non-finite field");
+  ckf_field* f = new ckf_field();
+  f->dev = {bx, by, bz};
+  *out = f;
+  return CKF_OK;
+}
+
+void ckf_field_destroy(ckf_field* f) { delete f; }
+
+ckf_status ckf_workspace_size(const ckf_geometry* g, const ckf_config* cfg, const ckf_launch* launch,
+                              int32_t n_events, int32_t n_seeds, int64_t n_meas, size_t* bytes) {
+  if (!g || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "workspace_size: NULL argument");
+  ckf_status st = check_config(cfg);
+  if (st != CKF_OK) return st;
+  if (n_events < 0 || n_seeds < 0 || n_meas < 0) return fail(CKF_ERR_INVALID_ARGUMENT, "workspace_size: negative size");
+  if (n_meas > INT32_MAX) return fail(CKF_ERR_NOT_SUPPORTED, "more than 2^31 measurements");
+  const ckf::Launch L = resolve_launch(cfg, launch, n_seeds);
+  *bytes = layout(L, n_events, g->dev.n_surfaces, n_seeds, n_meas).total;
+  return CKF_OK;
+}
+
+ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m, const ckf_seeds* s,
+                    const ckf_config* cfg, const ckf_launch* launch, void* workspace, size_t workspace_bytes,
+                    ckf_tracks* out, void* stream) {
+  if (!g || !f || !m || !s || !out) return fail(CKF_ERR_INVALID_ARGUMENT, "ckf_find: NULL argument");
+  ckf_status st = check_config(cfg);
+  if (st != CKF_OK) return st;
+  if (m->n_surfaces != g->dev.n_surfaces) return fail(CKF_ERR_INVALID_ARGUMENT, "measurements: n_surfaces mismatch");
+  if (m->n_events < 1 || m->n_meas < 0 || s->n_seeds < 0) return fail(CKF_ERR_INVALID_ARGUMENT, "bad batch sizes");
+  if (m->n_meas > INT32_MAX) return fail(CKF_ERR_NOT_SUPPORTED, "more than 2^31 measurements");
+  if ((long long)m->n_events * m->n_surfaces >= INT32_MAX) return fail(CKF_ERR_NOT_SUPPORTED, "too many rows");
+  if (!m->offsets || (m->n_meas > 0 && (!m->loc || !m->var)))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "measurements: NULL array");
+  if (s->n_seeds > 0 && (!s->event || !s->surface || !s->params || !s->cov))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "seeds: NULL array");
+  if (!out->n_tracks || !out->offsets || !out->status || out->cap_tracks < 0 || out->cap_meas < 0)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "tracks: NULL array or negative capacity");
+  if (out->cap_tracks > 0 && (!out->params || !out->cov || !out->chi2 || !out->ndf || !out->holes || !out->seed ||
+                              !out->event || !out->last_surface))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "tracks: NULL array");
+  if (out->cap_meas > 0 && !out->meas) return fail(CKF_ERR_INVALID_ARGUMENT, "tracks: NULL meas");
+  if (!workspace) return fail(CKF_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  const ckf::Launch L = resolve_launch(cfg, launch, s->n_seeds);
+  const Layout o = layout(L, m->n_events, m->n_surfaces, s->n_seeds, m->n_meas);
+  if (workspace_bytes < o.total)
+    return fail(CKF_ERR_CAPACITY, "workspace too small: need " + std::to_string(o.total) + " bytes");
+  char* ws = static_cast<char*>(workspace);
+  ckf::Workspace w;
+  w.m_loc0 = reinterpret_cast<float*>(ws + o.off_loc0);
+  w.m_loc1 = reinterpret_cast<float*>(ws + o.off_loc1);
+  w.m_var0 = reinterpret_cast<float*>(ws + o.off_var0);
+  w.m_var1 = reinterpret_cast<float*>(ws + o.off_var1);
+  w.m_id = reinterpret_cast<int*>(ws + o.off_id);
+  w.row_maxvar0 = reinterpret_cast<float*>(ws + o.off_maxv);
+  w.nodes = reinterpret_cast<ckf::Node*>(ws + o.off_nodes);
+  w.node_cap = o.node_cap;
+  w.node_count = reinterpret_cast<unsigned long long*>(ws + o.off_nodecnt);
+  w.queue_head = reinterpret_cast<int*>(ws + o.off_queue);
+  w.res_node = reinterpret_cast<int*>(ws + o.off_res_node);
+  w.res_nm = reinterpret_cast<int*>(ws + o.off_res_nm);
+  w.res_holes = reinterpret_cast<int*>(ws + o.off_res_holes);
+  w.res_chi2 = reinterpret_cast<double*>(ws + o.off_res_chi2);
+  w.scan_a = reinterpret_cast<int*>(ws + o.off_scan_a);
+  w.scan_b = reinterpret_cast<int*>(ws + o.off_scan_b);
+  w.pools = ws + o.off_pools;
+  w.pool_cap = L.pool_cap;
+  w.seeds_per_group = L.seeds_per_group;
+  w.grid = L.grid;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  ckf::MeasIn mi{m->n_events, m->n_surfaces, (long long)m->n_meas, m->offsets, m->loc, m->var};
+  HIP_TRY(ckf::launch_init(s->n_seeds, w, *out, hs), "launch k_init");
+  HIP_TRY(ckf::launch_meas_prepare(mi, w, out->status, hs), "launch k_meas_prepare");
+  if (s->n_seeds > 0) {
+    ckf::CkfArgs a;
+    a.g = g->dev;
+    a.f = f->dev;
+    a.cfg = to_dev(cfg);
+    a.m = mi;
+    a.s = {s->n_seeds, s->event, s->surface, s->params, s->cov};
+    a.w = w;
+    a.status = out->status;
+    a.counters = reinterpret_cast<long long*>(out->counters);
+    if (launch && launch->timer) HIP_TRY(hipEventRecord(launch->timer->start, hs), "hipEventRecord");
+    HIP_TRY(ckf::launch_ckf(a, hs), "launch k_ckf");
+    if (launch && launch->timer) HIP_TRY(hipEventRecord(launch->timer->stop, hs), "hipEventRecord");
+  }
+  HIP_TRY(ckf::launch_output(s->n_seeds, w, s->event, *out, hs), "launch output");
+  return CKF_OK;
+}
+
+ckf_status ckf_timer_create(ckf_timer** out) {
+  if (!out) return fail(CKF_ERR_INVALID_ARGUMENT, "timer_create: NULL out");
+  ckf_timer* t = new ckf_timer();
+  hipError_t e = hipEventCreate(&t->start);
+  if (e == hipSuccess) e = hipEventCreate(&t->stop);
+  if (e != hipSuccess) {
+    delete t;
+    return hip_fail(e, "hipEventCreate");
+  }
+  *out = t;
+  return CKF_OK;
+}
+
+void ckf_timer_destroy(ckf_timer* t) {
+  if (!t) return;
+  (void)hipEventDestroy(t->start);
+  (void)hipEventDestroy(t->stop);
+  delete t;
+}
+
+ckf_status ckf_timer_elapsed_ms(ckf_timer* t, float* ms) {
+  if (!t || !ms) return fail(CKF_ERR_INVALID_ARGUMENT, "timer_elapsed: NULL argument");
+  HIP_TRY(hipEventSynchronize(t->stop), "hipEventSynchronize");
+  HIP_TRY(hipEventElapsedTime(ms, t->start, t->stop), "hipEventElapsedTime");
+  return CKF_OK;
+}
+
+ckf_status ckf_propagate_batch(const ckf_geometry* g, const ckf_field* f, const ckf_config* cfg, int32_t n,
+                               const int32_t* src, const double* p_in, const double* cov_in, const int32_t* dst,
+                               double* p_out, double* cov_out, double* jac, double* path, int32_t* ok,
+                               void* stream) {
+  if (!g || !f || !cfg) return fail(CKF_ERR_INVALID_ARGUMENT, "propagate_batch: NULL argument");
+  if (n < 0) return fail(CKF_ERR_INVALID_ARGUMENT, "propagate_batch: negative n");
+  if (n > 0 && (!src || !p_in || !cov_in || !dst || !p_out || !cov_out || !ok))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "propagate_batch: NULL array");
+  ckf_status st = check_config(cfg);
+  if (st != CKF_OK) return st;
+  HIP_TRY(ckf::launch_propagate(g->dev, f->dev, to_dev(cfg), n, src, p_in, cov_in, dst, p_out, cov_out, jac, path, ok,
+                                static_cast<hipStream_t>(stream)),
+          "launch k_propagate_batch");
+  return CKF_OK;
+}
+
+ckf_status ckf_kf_update_batch(int32_t n, const double* p_in, const double* cov_in, const float* meas,
+                               const float* var, double* p_out, double* cov_out, double* chi2, void* stream) {
+  if (n < 0) return fail(CKF_ERR_INVALID_ARGUMENT, "kf_update_batch: negative n");
+  if (n > 0 && (!p_in || !cov_in || !meas || !var || !p_out || !cov_out))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "kf_update_batch: NULL array");
+  HIP_TRY(ckf::launch_kf_update(n, p_in, cov_in, meas, var, p_out, cov_out, chi2, static_cast<hipStream_t>(stream)),
+          "launch k_kf_update_batch");
+  return CKF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,513 @@
+// Device functions of the CKF hot path on gfx950.
+//
+// Precision split: propagation legs (state, tangent columns, navigation
+// geometry) run in FP32 with positions relative to the leg's start module;
+// bound parameters, covariances, chi2, the Kalman gain and the Joseph update
+// are FP64.  Every decision compares FP64 quantities or FP32 geometry with
+// the same thresholds as the documented readings.
+#pragma once
+#include <math.h>
+
+#include "ckf_internal.hpp"
+
+namespace ckf {
+
+constexpr float kKappa = 2.99792458e-4f;  // GeV / (T mm)
+
+struct V3 {
+  float x, y, z;
+};
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ float maxabs(V3 a) { return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z))); }
+__device__ __forceinline__ V3 ld3(const float* p) { return {p[0], p[1], p[2]}; }
+
+__device__ __forceinline__ V3 field_at(const FieldDev& F, V3 /*global position*/) { return {F.bx, F.by, F.bz}; }
+
+__device__ __forceinline__ void load_module(const GeomDev& g, int m, Module& M) {
+  const float4* s = reinterpret_cast<const float4*>(g.mod + m);
+  float4 a = s[0], b = s[1], c = s[2], d = s[3];
+  M.c[0] = a.x; M.c[1] = a.y; M.c[2] = a.z; M.u[0] = a.w;
+  M.u[1] = b.x; M.u[2] = b.y; M.v[0] = b.z; M.v[1] = b.w;
+  M.v[2] = c.x; M.n[0] = c.y; M.n[1] = c.z; M.n[2] = c.w;
+  M.hw0 = d.x; M.hw1 = d.y; M.thick = d.z; M.layer = __float_as_int(d.w);
+}
+
+// ---------------------------------------------------------------------------
+// Propagation leg: free state relative to `origin` (the start module centre)
+// plus the tangent columns d(state)/d(phi, theta, q/p) of the bound start
+// parameters.  In a uniform field the loc0/loc1 columns stay (u, 0, 0) and
+// (v, 0, 0) along the whole leg, so only three columns are carried.
+struct Leg {
+  V3 r, T;
+  float lam;
+  V3 dr[3], dT[3];
+};
+
+// One Nystrom RKN4 step of length h (field sampled at start, midpoint, end;
+// uniform here).  Tangent columns are differentiated through the same
+// stages.  Returns the error estimate h^2 * max|k1 - k2 - k3 + k4|.
+__device__ __forceinline__ float rkn4_step(const Leg& L, float h, V3 B, Leg& o) {
+  const float kl = kKappa * L.lam;
+  const float h2 = 0.5f * h, h6 = h * (1.0f / 6.0f), hh6 = h * h * (1.0f / 6.0f);
+  const V3 T = L.T;
+  const V3 k1 = kl * cross(T, B);
+  const V3 T2 = T + h2 * k1;
+  const V3 k2 = kl * cross(T2, B);
+  const V3 T3 = T + h2 * k2;
+  const V3 k3 = kl * cross(T3, B);
+  const V3 T4 = T + h * k3;
+  const V3 k4 = kl * cross(T4, B);
+  o.r = L.r + h * T + hh6 * (k1 + k2 + k3);
+  o.T = T + h6 * (k1 + 2.0f * (k2 + k3) + k4);
+  o.lam = L.lam;
+  // d(kappa*lambda*(T x B)) = kappa*lambda*(dT x B) + kappa*dlambda*(T x B)
+  const V3 c1 = kKappa * cross(T, B), c2 = kKappa * cross(T2, B), c3 = kKappa * cross(T3, B),
+           c4 = kKappa * cross(T4, B);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float dl = (j == 2) ? 1.0f : 0.0f;
+    const V3 dT = L.dT[j];
+    const V3 d1 = kl * cross(dT, B) + dl * c1;
+    const V3 dT2 = dT + h2 * d1;
+    const V3 d2 = kl * cross(dT2, B) + dl * c2;
+    const V3 dT3 = dT + h2 * d2;
+    const V3 d3 = kl * cross(dT3, B) + dl * c3;
+    const V3 dT4 = dT + h * d3;
+    const V3 d4 = kl * cross(dT4, B) + dl * c4;
+    o.dr[j] = L.dr[j] + h * dT + hh6 * (d1 + d2 + d3);
+    o.dT[j] = dT + h6 * (d1 + 2.0f * (d2 + d3) + d4);
+  }
+  return h * h * maxabs(k1 - k2 - k3 + k4);
+}
+
+// Signed path to the plane (c, n) from r + d T + d^2 k / 2 (root nearest the
+// straight-line one); NaN when the direction grazes the plane.
+__device__ __forceinline__ float plane_distance(V3 r, V3 T, V3 k, V3 c, V3 n) {
+  const float a = 0.5f * dot(n, k), b = dot(n, T), c0 = dot(n, r - c);
+  if (fabsf(b) < 1e-9f) return __int_as_float(0x7fc00000);
+  const float lin = -c0 / b;
+  const float disc = b * b - 4.0f * a * c0;
+  if (disc < 0.0f) return lin;
+  const float q = -0.5f * (b + copysignf(sqrtf(disc), b));
+  if (q == 0.0f) return lin;
+  return c0 / q;
+}
+
+struct LegStats {
+  int trials, rejects;
+};
+
+// Adaptive RKN4 steps onto the plane (c, n) given relative to the origin.
+__device__ bool land(Leg& L, V3 origin, V3 c, V3 n, const FieldDev& F, const CfgDev& cfg, float& h_trial,
+                     float& path, LegStats& st) {
+  for (int it = 0; it < cfg.max_rk; ++it) {
+    const V3 B = field_at(F, origin + L.r);
+    const V3 k = (kKappa * L.lam) * cross(L.T, B);
+    const float d = plane_distance(L.r, L.T, k, c, n);
+    if (!isfinite(d)) return false;
+    if (fabsf(d) < cfg.land_tol) {
+      L.r = L.r + d * L.T;
+      L.T = rsqrtf(dot(L.T, L.T)) * L.T;
+      path += fabsf(d);
+      return true;
+    }
+    const bool limited = fabsf(d) < h_trial;
+    const float h = copysignf(fminf(fabsf(d), h_trial), d);
+    Leg o;
+    const float err = rkn4_step(L, h, B, o);
+    ++st.trials;
+    if (!(err <= cfg.step_tol)) {
+      ++st.rejects;
+      h_trial = fabsf(h) * fmaxf(0.25f, 0.9f * sqrtf(sqrtf(cfg.step_tol / err)));
+      continue;
+    }
+    L = o;
+    path += fabsf(h);
+    const float grow = err > 0.0f ? fminf(4.0f, 0.9f * sqrtf(sqrtf(cfg.step_tol / err))) : 4.0f;
+    h_trial = limited ? fminf(cfg.step_max, fmaxf(h_trial, fabsf(h) * grow)) : fminf(cfg.step_max, fabsf(h) * grow);
+  }
+  return false;
+}
+
+// Bound parameters on module A -> leg start (relative to A's centre).
+__device__ __forceinline__ void leg_start(const Module& A, const double* p, Leg& L, V3& uA, V3& vA) {
+  uA = ld3(A.u);
+  vA = ld3(A.v);
+  const float l0 = (float)p[0], l1 = (float)p[1];
+  float sp, cp, st, ct;
+  sincosf((float)p[2], &sp, &cp);
+  sincosf((float)p[3], &st, &ct);
+  L.r = l0 * uA + l1 * vA;
+  L.T = {cp * st, sp * st, ct};
+  L.lam = (float)p[4];
+  L.dr[0] = L.dr[1] = L.dr[2] = {0.f, 0.f, 0.f};
+  L.dT[0] = {-sp * st, cp * st, 0.f};
+  L.dT[1] = {cp * ct, sp * ct, -st};
+  L.dT[2] = {0.f, 0.f, 0.f};
+}
+
+// Landed free state -> bound parameters on module B and the bound-to-bound
+// Jacobian with the path-length correction.  dB = B's centre relative to
+// the leg origin; qop is the start's FP64 q/p (unchanged along the leg).
+__device__ __forceinline__ void leg_end(const Leg& L, V3 uA, V3 vA, const Module& Bm, V3 dB, V3 Bf, double qop,
+                                        double* p, float J[5][5]) {
+  const V3 uB = ld3(Bm.u), vB = ld3(Bm.v), nB = ld3(Bm.n);
+  const V3 d = L.r - dB;
+  const V3 T = L.T;
+  const float st2 = T.x * T.x + T.y * T.y;
+  const float st = sqrtf(st2);
+  p[0] = (double)dot(uB, d);
+  p[1] = (double)dot(vB, d);
+  p[2] = (double)atan2f(T.y, T.x);
+  p[3] = (double)atan2f(st, T.z);
+  p[4] = qop;  // no energy loss: q/p keeps its FP64 value
+  const V3 kend = (kKappa * L.lam) * cross(T, Bf);
+  const float inT = 1.0f / dot(nB, T);
+  const float ist2 = 1.0f / st2, ist = 1.0f / st;
+  V3 dr[5], dT[5];
+  dr[0] = uA; dT[0] = {0.f, 0.f, 0.f};
+  dr[1] = vA; dT[1] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    dr[j + 2] = L.dr[j];
+    dT[j + 2] = L.dT[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const float ds = -dot(nB, dr[j]) * inT;
+    const V3 drc = dr[j] + ds * T;
+    const V3 dTc = dT[j] + ds * kend;
+    J[0][j] = dot(uB, drc);
+    J[1][j] = dot(vB, drc);
+    J[2][j] = (T.x * dTc.y - T.y * dTc.x) * ist2;
+    J[3][j] = -dTc.z * ist;
+    J[4][j] = (j == 4) ? 1.0f : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 covariance algebra on the packed upper triangle.
+
+__device__ __forceinline__ int pk(int i, int j) {
+  return i <= j ? i * 5 - (i * (i - 1)) / 2 + (j - i) : j * 5 - (j * (j - 1)) / 2 + (i - j);
+}
+
+// C <- J C J^T (J promoted to FP64), symmetric by construction.
+__device__ __forceinline__ void transport_cov(const float J[5][5], double* C) {
+  double R[15];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double row[5];  // (J C)[i][:]
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < 5; ++l) s = fma((double)J[i][l], C[pk(l, k)], s);
+      row[k] = s;
+    }
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s = fma(row[k], (double)J[j][k], s);
+      R[pk(i, j)] = s;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 15; ++q) C[q] = R[q];
+}
+
+__device__ __forceinline__ double chi2_of(const double* p, const double* C, double m0, double m1, double v0,
+                                          double v1) {
+  const double r0 = m0 - p[0], r1 = m1 - p[1];
+  const double s00 = C[0] + v0, s01 = C[1], s11 = C[5] + v1;
+  const double det = s00 * s11 - s01 * s01;
+  return (s11 * r0 * r0 - 2.0 * s01 * r0 * r1 + s00 * r1 * r1) / det;
+}
+
+__device__ __forceinline__ double wrap_phi(double phi) {
+  const double pi = 3.14159265358979323846;
+  if (phi > pi) phi -= 2.0 * pi;
+  if (phi <= -pi) phi += 2.0 * pi;
+  return phi;
+}
+
+// Gain-form Kalman update with the Joseph covariance, FP64.
+__device__ __forceinline__ void kf_update(double* p, double* C, double m0, double m1, double v0, double v1) {
+  const double s00 = C[0] + v0, s01 = C[1], s11 = C[5] + v1;
+  const double idet = 1.0 / (s00 * s11 - s01 * s01);
+  const double i00 = s11 * idet, i01 = -s01 * idet, i11 = s00 * idet;
+  const double r0 = m0 - p[0], r1 = m1 - p[1];
+  double K0[5], K1[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const double c0 = C[pk(i, 0)], c1 = C[pk(i, 1)];
+    K0[i] = c0 * i00 + c1 * i01;
+    K1[i] = c0 * i01 + c1 * i11;
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) p[i] += K0[i] * r0 + K1[i] * r1;
+  p[2] = wrap_phi(p[2]);
+  // A = I - K H; C+ = A C A^T + K V K^T.  (A C)[i][k] = C[i][k] - K0[i] C[0][k] - K1[i] C[1][k]
+  double AC[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) AC[i][k] = C[pk(i, k)] - K0[i] * C[pk(0, k)] - K1[i] * C[pk(1, k)];
+  double R[15];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      const double a = AC[i][j] - AC[i][0] * K0[j] - AC[i][1] * K1[j] + K0[i] * v0 * K0[j] + K1[i] * v1 * K1[j];
+      const double b = AC[j][i] - AC[j][0] * K0[i] - AC[j][1] * K1[i] + K0[j] * v0 * K0[i] + K1[j] * v1 * K1[i];
+      R[pk(i, j)] = 0.5 * (a + b);
+    }
+#pragma unroll
+  for (int q = 0; q < 15; ++q) C[q] = R[q];
+}
+
+// Highland multiple scattering on module M (width in FP32, added in FP64).
+__device__ __forceinline__ void apply_ms(const Module& M, double mass, const double* p, double* C) {
+  if (!(M.thick > 0.0f)) return;
+  float sp, cp, st, ct;
+  sincosf((float)p[2], &sp, &cp);
+  sincosf((float)p[3], &st, &ct);
+  const float cosa = fabsf(M.n[0] * cp * st + M.n[1] * sp * st + M.n[2] * ct);
+  const float x = M.thick / cosa;
+  const float mom = 1.0f / fabsf((float)p[4]);
+  const float m = (float)mass;
+  const float beta = mom / sqrtf(mom * mom + m * m);
+  const float th0 = 0.0136f / (beta * mom) * sqrtf(x) * (1.0f + 0.038f * logf(x / (beta * beta)));
+  const double t2 = (double)th0 * (double)th0;
+  C[pk(2, 2)] += t2 / ((double)st * (double)st);
+  C[pk(3, 3)] += t2;
+}
+
+// ---------------------------------------------------------------------------
+// Navigation: local helix about the field at the current point.
+
+struct Helix {
+  V3 p0, T0, bhat, tperp, w;
+  float tpar, om;
+};
+
+__device__ __forceinline__ Helix make_helix(V3 p, V3 T, float lam, V3 B) {
+  Helix H;
+  const float bm = sqrtf(dot(B, B));
+  H.bhat = bm > 0.f ? (1.0f / bm) * B : V3{0.f, 0.f, 1.f};
+  H.om = kKappa * lam * bm;
+  H.p0 = p;
+  H.T0 = T;
+  H.tpar = dot(T, H.bhat);
+  H.tperp = T - H.tpar * H.bhat;
+  H.w = cross(T, H.bhat);
+  return H;
+}
+
+__device__ __forceinline__ void helix_at(const Helix& H, float s, V3& p, V3& T) {
+  const float a = H.om * s;
+  float S, Cc, sa, ca;
+  sincosf(a, &sa, &ca);
+  if (fabsf(a) < 1e-3f) {
+    S = s * (1.0f - a * a * (1.0f / 6.0f));
+    Cc = s * (0.5f * a) * (1.0f - a * a * (1.0f / 12.0f));
+  } else {
+    const float hs = sinf(0.5f * a);
+    S = sa / H.om;
+    Cc = 2.0f * hs * hs / H.om;
+  }
+  p = H.p0 + (H.tpar * s) * H.bhat + S * H.tperp + Cc * H.w;
+  T = H.tpar * H.bhat + ca * H.tperp + sa * H.w;
+}
+
+__device__ bool cross_cylinder(const Helix& H, float R, float& s_out) {
+  const float a = H.T0.x * H.T0.x + H.T0.y * H.T0.y;
+  const float b = H.p0.x * H.T0.x + H.p0.y * H.T0.y;
+  const float c = H.p0.x * H.p0.x + H.p0.y * H.p0.y - R * R;
+  if (a < 1e-12f) return false;
+  const float disc = b * b - a * c;
+  if (disc < 0.f) return false;
+  float s = (-b + sqrtf(disc)) / a;
+  if (!(s > 0.f)) return false;
+  for (int it = 0; it < 20; ++it) {
+    V3 p, T;
+    helix_at(H, s, p, T);
+    const float g = p.x * p.x + p.y * p.y - R * R;
+    const float gp = 2.0f * (p.x * T.x + p.y * T.y);
+    if (!(gp > 0.f)) return false;
+    const float ds = g / gp;
+    s -= ds;
+    if (fabsf(ds) < 1e-4f) break;
+  }
+  if (!(s > 0.f)) return false;
+  V3 p, T;
+  helix_at(H, s, p, T);
+  if (fabsf(sqrtf(p.x * p.x + p.y * p.y) - R) > 1e-3f) return false;
+  s_out = s;
+  return true;
+}
+
+__device__ bool cross_zplane(const Helix& H, float Z, float& s_out) {
+  if (fabsf(H.T0.z) < 1e-12f) return false;
+  float s = (Z - H.p0.z) / H.T0.z;
+  if (!(s > 0.f)) return false;
+  for (int it = 0; it < 20; ++it) {
+    V3 p, T;
+    helix_at(H, s, p, T);
+    if (fabsf(T.z) < 1e-12f) return false;
+    const float ds = (p.z - Z) / T.z;
+    s -= ds;
+    if (fabsf(ds) < 1e-4f) break;
+  }
+  if (!(s > 0.f)) return false;
+  s_out = s;
+  return true;
+}
+
+// Candidate modules of layer `l` near the trajectory segment from P along T
+// (navigation grid lookup), then the listing test from the base point P at
+// path s_base: second-order expansion P + d T + d^2 k / 2 meets the module
+// plane within its half lengths plus the margin at positive total path.
+// Returns the number listed (<= kMaxList, sorted by path then id).
+__device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_base, int exclude, float margin,
+                          int* list, int& n_tested, int& overflow) {
+  const LayerRec Lr = g.layers[l];
+  // segment of the trajectory that can reach the layer's modules
+  float span;
+  if (Lr.type == 0) {
+    const float rp = sqrtf(P.x * P.x + P.y * P.y);
+    const float vr = rp > 0.f ? (P.x * T.x + P.y * T.y) / rp : 1.0f;
+    span = Lr.depth / fmaxf(vr, 0.05f) * 1.2f + 2.0f;
+  } else {
+    span = Lr.depth / fmaxf(fabsf(T.z), 0.05f) * 1.2f + 2.0f;
+  }
+  span = fminf(span, 400.0f);
+  const V3 Q = P + span * T;
+  const float twopi = 6.28318530718f;
+  float ph0 = atan2f(P.y, P.x), ph1 = atan2f(Q.y, Q.x);
+  float w0 = Lr.type == 0 ? P.z : sqrtf(P.x * P.x + P.y * P.y);
+  float w1 = Lr.type == 0 ? Q.z : sqrtf(Q.x * Q.x + Q.y * Q.y);
+  float dph = ph1 - ph0;
+  if (dph > 3.14159265f) dph -= twopi;
+  if (dph < -3.14159265f) dph += twopi;
+  const float phlo = fminf(ph0, ph0 + dph), phhi = fmaxf(ph0, ph0 + dph);
+  const float wlo = fminf(w0, w1), whi = fmaxf(w0, w1);
+  if (!(isfinite(phlo) && isfinite(phhi) && isfinite(wlo) && isfinite(whi))) return 0;
+  const float bph = twopi / Lr.nphi, bw = (Lr.whi - Lr.wlo) / Lr.nw;
+  int ip0 = (int)floorf((phlo + 3.14159265f) / bph) - 0;
+  int ip1 = (int)floorf((phhi + 3.14159265f) / bph);
+  int iw0 = (int)floorf((wlo - Lr.wlo) / bw), iw1 = (int)floorf((whi - Lr.wlo) / bw);
+  iw0 = max(iw0, 0);
+  iw1 = min(iw1, Lr.nw - 1);
+  if (ip1 - ip0 >= Lr.nphi) { ip0 = 0; ip1 = Lr.nphi - 1; }
+  int cand[kMaxCand];
+  int nc = 0;
+  for (int ipr = ip0; ipr <= ip1; ++ipr) {
+    int ip = ipr % Lr.nphi;
+    if (ip < 0) ip += Lr.nphi;
+    for (int iw = iw0; iw <= iw1; ++iw) {
+      const int cell = Lr.cell_base + ip * Lr.nw + iw;
+      const int a = g.cell_off[cell], b = g.cell_off[cell + 1];
+      for (int q = a; q < b; ++q) {
+        const int m = g.cell_mod[q];
+        bool dup = (m == exclude);
+        for (int t = 0; t < nc && !dup; ++t) dup = cand[t] == m;
+        if (dup) continue;
+        if (nc < kMaxCand) cand[nc++] = m;
+        else overflow = 1;
+      }
+    }
+  }
+  float ls[kMaxList];
+  int n = 0;
+  for (int t = 0; t < nc; ++t) {
+    const int m = cand[t];
+    Module M;
+    load_module(g, m, M);
+    const V3 c = ld3(M.c), nn = ld3(M.n);
+    const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
+    const V3 dc = c - P;
+    if (sqrtf(dot(dc, dc)) > hd + kReach) continue;
+    ++n_tested;
+    const float a = 0.5f * dot(nn, k), b = dot(nn, T), c0 = dot(nn, P - c);
+    if (fabsf(b) < 1e-3f) continue;
+    float d = -c0 / b;
+    const float disc = b * b - 4.0f * a * c0;
+    if (disc >= 0.f) {
+      const float q = -0.5f * (b + copysignf(sqrtf(disc), b));
+      if (q != 0.f) d = c0 / q;
+    }
+    const V3 X = P + d * T + (0.5f * d * d) * k - c;
+    const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
+    if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) continue;
+    const float s = s_base + d;
+    if (!(s > 0.f)) continue;
+    // sorted insert by (s, id), keep the first kMaxList
+    int pos = n;
+    while (pos > 0 && (ls[pos - 1] > s || (ls[pos - 1] == s && list[pos - 1] > m))) --pos;
+    if (pos >= kMaxList) continue;
+    for (int q = min(n, kMaxList - 1); q > pos; --q) {
+      ls[q] = ls[q - 1];
+      list[q] = list[q - 1];
+    }
+    ls[pos] = s;
+    list[pos] = m;
+    if (n < kMaxList) ++n;
+  }
+  return n;
+}
+
+// The next navigation layer from free state (p, T, lam) in global
+// coordinates: the unvisited layer whose envelope the local helix meets
+// first within its extent and the path budget.  Returns -1 if none.
+__device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long mask, float budget, float& s_best) {
+  const float rperp = sqrtf(H.p0.x * H.p0.x + H.p0.y * H.p0.y);
+  int best = -1;
+  s_best = INFINITY;
+  // barrels by radius: the first crossed within its extent is the nearest
+  for (int q = 0; q < g.n_barrel; ++q) {
+    const int l = g.barrel_order[q];
+    if (mask & (1ull << l)) continue;
+    const LayerRec Lr = g.layers[l];
+    if (!(Lr.pos > rperp)) continue;
+    float s;
+    if (!cross_cylinder(H, Lr.pos, s)) continue;
+    V3 p, T;
+    helix_at(H, s, p, T);
+    if (p.z < Lr.lo || p.z > Lr.hi) continue;
+    if (s > budget) break;
+    best = l;
+    s_best = s;
+    break;
+  }
+  // disks on the side the track moves to, by |z|
+  const int nd = H.T0.z > 0.f ? g.n_disk_pos : g.n_disk_neg;
+  const int* order = H.T0.z > 0.f ? g.disk_pos : g.disk_neg;
+  for (int q = 0; q < nd; ++q) {
+    const int l = order[q];
+    if (mask & (1ull << l)) continue;
+    const LayerRec Lr = g.layers[l];
+    float s;
+    if (!cross_zplane(H, Lr.pos, s)) continue;
+    if (s > s_best || s > budget) break;
+    V3 p, T;
+    helix_at(H, s, p, T);
+    const float r = sqrtf(p.x * p.x + p.y * p.y);
+    if (r < Lr.lo || r > Lr.hi) continue;
+    if (s < s_best || (s == s_best && l < best)) {
+      best = l;
+      s_best = s;
+    }
+    break;
+  }
+  return best;
+}
+
+}  // namespace ckf

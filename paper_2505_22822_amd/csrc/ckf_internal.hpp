@@ -1,0 +1,116 @@
+// Internal layouts shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ckf.h"
+
+namespace ckf {
+
+constexpr int kWave = 64;          // lanes per wavefront (one wave per workgroup)
+constexpr int kMaxList = 4;        // listed modules per navigation layer
+constexpr int kMaxBranch = 4;      // largest branches_per_surface supported
+constexpr int kMaxCand = 32;       // grid candidates per listing lookup
+constexpr int kMaxLayers = 64;     // visited-layer mask width
+constexpr int kMaxSteps = 64;      // largest max_steps (history walk buffer)
+constexpr float kReach = 30.0f;    // mm, envelope-to-module reach of the candidate pre-filter
+constexpr float kGridPad = 5.0f;   // mm, padding of module extents in the navigation grid
+constexpr float kMaxNavMargin = 2.0f;
+
+// Surface store: one 64-byte record per module (a lane reads one record per
+// access; records of neighbouring modules share cache lines).
+struct alignas(64) Module {
+  float c[3];
+  float u[3];
+  float v[3];
+  float n[3];
+  float hw0, hw1, thick;
+  int layer;
+};
+static_assert(sizeof(Module) == 64, "module record");
+
+struct LayerRec {
+  int type;        // 0 barrel, 1 disk
+  float pos;       // envelope radius or signed z
+  float lo, hi;    // envelope extent (z for barrels, r for disks)
+  float depth;     // how far modules reach beyond the envelope (+ pad)
+  int nphi, nw;    // grid bins in phi and in w (z or r)
+  float wlo, whi;  // grid range in w
+  int cell_base;   // first cell of this layer in the CSR
+  int pad0, pad1;
+};
+
+struct GeomDev {
+  int n_surfaces = 0, n_layers = 0;
+  const Module* mod = nullptr;
+  const LayerRec* layers = nullptr;
+  const int* cell_off = nullptr;   // [n_cells + 1]
+  const int* cell_mod = nullptr;
+  const int* barrel_order = nullptr;  // barrel layers by radius
+  const int* disk_pos = nullptr;      // z > 0 disks by |z|
+  const int* disk_neg = nullptr;      // z < 0 disks by |z|
+  int n_barrel = 0, n_disk_pos = 0, n_disk_neg = 0;
+};
+
+struct FieldDev {
+  float bx, by, bz;  // uniform field, tesla
+};
+
+// Scalar configuration as the kernels use it.
+struct CfgDev {
+  double chi2_max;
+  int branches, max_live, max_holes, min_meas, max_steps, max_rk;
+  float step_tol, step_max, land_tol, path_max, nav_margin;
+  double mass;
+  int material;
+};
+
+// History node: written once per Kalman update (the filtered state there).
+struct alignas(16) Node {
+  int parent;
+  int meas;
+  int surface;
+  int pad;
+  double p[5];
+  double cov[15];
+};
+static_assert(sizeof(Node) == 176, "node record");
+
+// Candidate pool record, stored structure-of-arrays per workgroup.
+enum PoolD { PD_P = 0, PD_C = 5, PD_CHI2 = 20, PD_N = 21 };
+enum PoolI { PI_SURF = 0, PI_SLOT, PI_NODE, PI_NMH, PI_MASK_LO, PI_MASK_HI, PI_LIST, PI_NLIST = PI_LIST + kMaxList, PI_N };
+enum PoolF { PF_H = 0, PF_PATH, PF_N };
+constexpr size_t kRecBytes = PD_N * 8 + PI_N * 4 + PF_N * 4;
+
+struct Workspace {
+  // carved from the caller's workspace
+  float* m_loc0;
+  float* m_loc1;
+  float* m_var0;
+  float* m_var1;
+  int* m_id;
+  float* row_maxvar0;
+  Node* nodes;
+  long long node_cap;
+  unsigned long long* node_count;
+  int* queue_head;
+  int* res_node;
+  int* res_nm;
+  int* res_holes;
+  double* res_chi2;
+  int* scan_a;      // per-block sums for the output scan
+  int* scan_b;
+  char* pools;      // per-workgroup candidate pools
+  int pool_cap;     // records per pool
+  int seeds_per_group;
+  int grid;
+};
+
+struct Launch {
+  int grid;
+  int seeds_per_group;
+  int pool_cap;
+  int nodes_per_seed;
+};
+
+}  // namespace ckf
