@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--seeds-per-group", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0, help="kernel register variant: waves per SIMD (1 or 2)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this track finder has no multi-GPU path "
@@ -103,7 +104,7 @@ def main():
     b = ckf.Batch.from_event(batch)
     timer = ckf.KernelTimer()
     finder = ckf.Finder(geo, fld, b, ckf.config(),
-                        ckf.launch(args.grid, args.seeds_per_group, 0, timer))
+                        ckf.launch(args.grid, args.seeds_per_group, 0, timer, args.waves))
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         finder.enqueue(stream)

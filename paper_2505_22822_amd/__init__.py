@@ -124,8 +124,9 @@ class Batch:
         return int(self.loc.shape[0])
 
 
-def launch(grid=0, seeds_per_group=0, nodes_per_seed=0, timer=None) -> _abi.Launch:
-    return _abi.Launch(grid, seeds_per_group, nodes_per_seed, timer.handle if timer is not None else None)
+def launch(grid=0, seeds_per_group=0, nodes_per_seed=0, timer=None, waves_per_simd=0) -> _abi.Launch:
+    return _abi.Launch(grid, seeds_per_group, nodes_per_seed, timer.handle if timer is not None else None,
+                       waves_per_simd)
 
 
 class KernelTimer:
@@ -222,7 +223,8 @@ def find(geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, str
         if flags & _abi.FLAG_BAD_OFFSETS:
             raise CkfError(2, "measurement offsets are not non-decreasing")
         if flags & _abi.FLAG_NODE_CAPACITY:
-            lc = _abi.Launch(lc.grid, lc.seeds_per_group, 2 * (lc.nodes_per_seed or 32), lc.timer)
+            lc = _abi.Launch(lc.grid, lc.seeds_per_group, 2 * (lc.nodes_per_seed or 32), lc.timer,
+                             lc.waves_per_simd)
             continue
         if flags:
             raise CkfError(3, f"device status flags {flags}")

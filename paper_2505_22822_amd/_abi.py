@@ -45,7 +45,8 @@ class Tracks(C.Structure):
 
 
 class Launch(C.Structure):
-    _fields_ = [("grid", I32), ("seeds_per_group", I32), ("nodes_per_seed", I32), ("timer", VP)]
+    _fields_ = [("grid", I32), ("seeds_per_group", I32), ("nodes_per_seed", I32), ("timer", VP),
+                ("waves_per_simd", I32)]
 
 
 # every exported symbol of include/ckf.h with its ctypes signature

@@ -232,11 +232,12 @@ ckf::Launch resolve_launch(const ckf_config* c, const ckf_launch* l, int n_seeds
   r.grid = std::max(1, std::min((l && l->grid > 0) ? l->grid : dflt, std::max(1, want)));
   r.pool_cap = r.seeds_per_group * (c->max_live_per_seed * c->branches_per_surface + 1);
   r.nodes_per_seed = (l && l->nodes_per_seed > 0) ? l->nodes_per_seed : kNodesPerSeed;
+  r.waves_per_simd = (l && l->waves_per_simd > 0) ? std::min(2, l->waves_per_simd) : 2;
   return r;
 }
 
 struct Layout {
-  size_t off_loc0, off_loc1, off_var0, off_var1, off_id, off_maxv, off_nodes, off_nodecnt, off_queue, off_res_node,
+  size_t off_loc0, off_loc1, off_var0, off_var1, off_id, off_rowof, off_maxv, off_nodes, off_nodecnt, off_queue, off_res_node,
       off_res_nm, off_res_holes, off_res_chi2, off_scan_a, off_scan_b, off_pools, total;
   long long node_cap;
 };
@@ -258,6 +259,7 @@ Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, l
   o.off_var0 = take(nm * 4);
   o.off_var1 = take(nm * 4);
   o.off_id = take(nm * 4);
+  o.off_rowof = take(nm * 4);
   o.off_maxv = take(rows * 4);
   o.off_nodes = take((size_t)o.node_cap * sizeof(ckf::Node));
   o.off_nodecnt = take(8);
@@ -441,6 +443,7 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
   w.m_var0 = reinterpret_cast<float*>(ws + o.off_var0);
   w.m_var1 = reinterpret_cast<float*>(ws + o.off_var1);
   w.m_id = reinterpret_cast<int*>(ws + o.off_id);
+  w.row_of = reinterpret_cast<int*>(ws + o.off_rowof);
   w.row_maxvar0 = reinterpret_cast<float*>(ws + o.off_maxv);
   w.nodes = reinterpret_cast<ckf::Node*>(ws + o.off_nodes);
   w.node_cap = o.node_cap;
@@ -471,7 +474,7 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
     a.status = out->status;
     a.counters = reinterpret_cast<long long*>(out->counters);
     if (launch && launch->timer) HIP_TRY(hipEventRecord(launch->timer->start, hs), "hipEventRecord");
-    HIP_TRY(ckf::launch_ckf(a, hs), "launch k_ckf");
+    HIP_TRY(ckf::launch_ckf(a, L.waves_per_simd, hs), "launch k_ckf");
     if (launch && launch->timer) HIP_TRY(hipEventRecord(launch->timer->stop, hs), "hipEventRecord");
   }
   HIP_TRY(ckf::launch_output(s->n_seeds, w, s->event, *out, hs), "launch output");

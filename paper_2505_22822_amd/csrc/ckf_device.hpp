@@ -223,6 +223,33 @@ __device__ __forceinline__ void transport_cov(const float J[5][5], double* C) {
   for (int q = 0; q < 15; ++q) C[q] = R[q];
 }
 
+// C <- J C J^T with J (FP32, row-major) read element by element from
+// per-lane LDS with stride kWave, so the Jacobian does not occupy registers
+// through the transport.
+__device__ __forceinline__ void transport_cov_lds(const float* J, double* C) {
+  double R[15];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double row[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < 5; ++l) s = fma((double)J[(5 * i + l) * kWave], C[pk(l, k)], s);
+      row[k] = s;
+    }
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s = fma(row[k], (double)J[(5 * j + k) * kWave], s);
+      R[pk(i, j)] = s;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 15; ++q) C[q] = R[q];
+}
+
 __device__ __forceinline__ double chi2_of(const double* p, const double* C, double m0, double m1, double v0,
                                           double v1) {
   const double r0 = m0 - p[0], r1 = m1 - p[1];
@@ -238,8 +265,14 @@ __device__ __forceinline__ double wrap_phi(double phi) {
   return phi;
 }
 
-// Gain-form Kalman update with the Joseph covariance, FP64.
-__device__ __forceinline__ void kf_update(double* p, double* C, double m0, double m1, double v0, double v1) {
+// Gain-form Kalman update with the Joseph covariance, FP64, out of place:
+// K = C H^T S^-1, p+ = p + K r and
+// C+ = (I - K H) C (I - K H)^T + K V K^T evaluated element by element:
+// C+_ij = C_ij - K0_i C_0j - K1_i C_1j - C_i0 K0_j - C_i1 K1_j
+//         + K0_i g0_j + K1_i g1_j + v0 K0_i K0_j + v1 K1_i K1_j
+// with g0 = C00 K0 + C01 K1 and g1 = C01 K0 + C11 K1 (symmetric as written).
+__device__ __forceinline__ void kf_update(const double* p, const double* C, double m0, double m1, double v0,
+                                          double v1, double* po, double* Co) {
   const double s00 = C[0] + v0, s01 = C[1], s11 = C[5] + v1;
   const double idet = 1.0 / (s00 * s11 - s01 * s01);
   const double i00 = s11 * idet, i01 = -s01 * idet, i11 = s00 * idet;
@@ -252,25 +285,19 @@ __device__ __forceinline__ void kf_update(double* p, double* C, double m0, doubl
     K1[i] = c0 * i01 + c1 * i11;
   }
 #pragma unroll
-  for (int i = 0; i < 5; ++i) p[i] += K0[i] * r0 + K1[i] * r1;
-  p[2] = wrap_phi(p[2]);
-  // A = I - K H; C+ = A C A^T + K V K^T.  (A C)[i][k] = C[i][k] - K0[i] C[0][k] - K1[i] C[1][k]
-  double AC[5][5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i)
-#pragma unroll
-    for (int k = 0; k < 5; ++k) AC[i][k] = C[pk(i, k)] - K0[i] * C[pk(0, k)] - K1[i] * C[pk(1, k)];
-  double R[15];
+  for (int i = 0; i < 5; ++i) po[i] = p[i] + K0[i] * r0 + K1[i] * r1;
+  po[2] = wrap_phi(po[2]);
+  const double c00 = C[0], c01 = C[1], c11 = C[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
     for (int j = i; j < 5; ++j) {
-      const double a = AC[i][j] - AC[i][0] * K0[j] - AC[i][1] * K1[j] + K0[i] * v0 * K0[j] + K1[i] * v1 * K1[j];
-      const double b = AC[j][i] - AC[j][0] * K0[i] - AC[j][1] * K1[i] + K0[j] * v0 * K0[i] + K1[j] * v1 * K1[i];
-      R[pk(i, j)] = 0.5 * (a + b);
+      const double g0 = c00 * K0[j] + c01 * K1[j], g1 = c01 * K0[j] + c11 * K1[j];
+      double x = C[pk(i, j)] - K0[i] * C[pk(0, j)] - K1[i] * C[pk(1, j)] - C[pk(i, 0)] * K0[j] -
+                 C[pk(i, 1)] * K1[j];
+      x += K0[i] * g0 + K1[i] * g1 + v0 * K0[i] * K0[j] + v1 * K1[i] * K1[j];
+      Co[pk(i, j)] = x;
     }
-#pragma unroll
-  for (int q = 0; q < 15; ++q) C[q] = R[q];
 }
 
 // Highland multiple scattering on module M (width in FP32, added in FP64).
@@ -407,8 +434,14 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
   iw0 = max(iw0, 0);
   iw1 = min(iw1, Lr.nw - 1);
   if (ip1 - ip0 >= Lr.nphi) { ip0 = 0; ip1 = Lr.nphi - 1; }
-  int cand[kMaxCand];
-  int nc = 0;
+  float ls[kMaxList];
+  int lm[kMaxList];
+#pragma unroll
+  for (int q = 0; q < kMaxList; ++q) {
+    ls[q] = INFINITY;
+    lm[q] = -1;
+  }
+  int visited = 0;
   for (int ipr = ip0; ipr <= ip1; ++ipr) {
     int ip = ipr % Lr.nphi;
     if (ip < 0) ip += Lr.nphi;
@@ -417,49 +450,55 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
       const int a = g.cell_off[cell], b = g.cell_off[cell + 1];
       for (int q = a; q < b; ++q) {
         const int m = g.cell_mod[q];
-        bool dup = (m == exclude);
-        for (int t = 0; t < nc && !dup; ++t) dup = cand[t] == m;
-        if (dup) continue;
-        if (nc < kMaxCand) cand[nc++] = m;
-        else overflow = 1;
+        if (m == exclude) continue;
+        if (++visited > kMaxCand) {
+          overflow = 1;
+          continue;
+        }
+        Module M;
+        load_module(g, m, M);
+        const V3 c = ld3(M.c), nn = ld3(M.n);
+        const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
+        const V3 dc = c - P;
+        if (sqrtf(dot(dc, dc)) > hd + kReach) continue;
+        ++n_tested;
+        const float qa = 0.5f * dot(nn, k), qb = dot(nn, T), c0 = dot(nn, P - c);
+        if (fabsf(qb) < 1e-3f) continue;
+        float d = -c0 / qb;
+        const float disc = qb * qb - 4.0f * qa * c0;
+        if (disc >= 0.f) {
+          const float qq = -0.5f * (qb + copysignf(sqrtf(disc), qb));
+          if (qq != 0.f) d = c0 / qq;
+        }
+        const V3 X = P + d * T + (0.5f * d * d) * k - c;
+        const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
+        if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) continue;
+        float cs = s_base + d;
+        if (!(cs > 0.f)) continue;
+        // a module found in two cells is listed once; keep the kMaxList
+        // smallest (path, id) in sorted order
+        if (lm[0] == m || lm[1] == m || lm[2] == m || lm[3] == m) continue;
+        int cm = m;
+#pragma unroll
+        for (int q = 0; q < kMaxList; ++q) {
+          const bool lt = cs < ls[q] || (cs == ls[q] && cm < lm[q]);
+          if (lt) {
+            const float ts = ls[q];
+            const int tm = lm[q];
+            ls[q] = cs;
+            lm[q] = cm;
+            cs = ts;
+            cm = tm;
+          }
+        }
       }
     }
   }
-  float ls[kMaxList];
   int n = 0;
-  for (int t = 0; t < nc; ++t) {
-    const int m = cand[t];
-    Module M;
-    load_module(g, m, M);
-    const V3 c = ld3(M.c), nn = ld3(M.n);
-    const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
-    const V3 dc = c - P;
-    if (sqrtf(dot(dc, dc)) > hd + kReach) continue;
-    ++n_tested;
-    const float a = 0.5f * dot(nn, k), b = dot(nn, T), c0 = dot(nn, P - c);
-    if (fabsf(b) < 1e-3f) continue;
-    float d = -c0 / b;
-    const float disc = b * b - 4.0f * a * c0;
-    if (disc >= 0.f) {
-      const float q = -0.5f * (b + copysignf(sqrtf(disc), b));
-      if (q != 0.f) d = c0 / q;
-    }
-    const V3 X = P + d * T + (0.5f * d * d) * k - c;
-    const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
-    if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) continue;
-    const float s = s_base + d;
-    if (!(s > 0.f)) continue;
-    // sorted insert by (s, id), keep the first kMaxList
-    int pos = n;
-    while (pos > 0 && (ls[pos - 1] > s || (ls[pos - 1] == s && list[pos - 1] > m))) --pos;
-    if (pos >= kMaxList) continue;
-    for (int q = min(n, kMaxList - 1); q > pos; --q) {
-      ls[q] = ls[q - 1];
-      list[q] = list[q - 1];
-    }
-    ls[pos] = s;
-    list[pos] = m;
-    if (n < kMaxList) ++n;
+#pragma unroll
+  for (int q = 0; q < kMaxList; ++q) {
+    list[q] = lm[q];
+    n += lm[q] >= 0 ? 1 : 0;
   }
   return n;
 }

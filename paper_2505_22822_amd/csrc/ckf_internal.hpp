@@ -10,7 +10,7 @@ namespace ckf {
 constexpr int kWave = 64;          // lanes per wavefront (one wave per workgroup)
 constexpr int kMaxList = 4;        // listed modules per navigation layer
 constexpr int kMaxBranch = 4;      // largest branches_per_surface supported
-constexpr int kMaxCand = 32;       // grid candidates per listing lookup
+constexpr int kMaxCand = 96;       // grid cell entries visited per listing lookup
 constexpr int kMaxLayers = 64;     // visited-layer mask width
 constexpr int kMaxSteps = 64;      // largest max_steps (history walk buffer)
 constexpr float kReach = 30.0f;    // mm, envelope-to-module reach of the candidate pre-filter
@@ -28,6 +28,7 @@ struct alignas(64) Module {
   int layer;
 };
 static_assert(sizeof(Module) == 64, "module record");
+static_assert(kMaxList == 4 && kMaxBranch == 4, "list code is unrolled for 4 entries");
 
 struct LayerRec {
   int type;        // 0 barrel, 1 disk
@@ -89,6 +90,7 @@ struct Workspace {
   float* m_var0;
   float* m_var1;
   int* m_id;
+  int* row_of;
   float* row_maxvar0;
   Node* nodes;
   long long node_cap;
@@ -111,6 +113,7 @@ struct Launch {
   int seeds_per_group;
   int pool_cap;
   int nodes_per_seed;
+  int waves_per_simd;
 };
 
 }  // namespace ckf

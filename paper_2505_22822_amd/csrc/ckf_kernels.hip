@@ -1,7 +1,7 @@
 // gfx950 kernels of CKF track finding.
 //
-//  k_meas_prepare  per (event, module) row: measurements sorted by loc0 (ids
-//                  kept) and the row's largest var0, for the exact chi2
+//  k_meas_rows,    per (event, module) row: measurements sorted by loc0 (ids
+//  k_meas_scatter  kept) and the row's largest var0, for the exact chi2
 //                  window of the search.
 //  k_ckf           persistent kernel: each 64-lane workgroup pulls seeds from
 //                  a global work queue into its slots and advances all their
@@ -19,9 +19,10 @@ namespace ckf {
 // ---------------------------------------------------------------------------
 // measurement preparation
 
-__global__ void k_meas_prepare(int n_rows, long long n_meas, const int* __restrict__ offsets,
-                               const float* __restrict__ loc, const float* __restrict__ var, float* l0, float* l1,
-                               float* v0, float* v1, int* id, float* maxv0, int* status) {
+// Pass 1, one thread per (event, module) row: validate the offsets, tag
+// every measurement with its row, largest var0 of the row.
+__global__ void k_meas_rows(int n_rows, long long n_meas, const int* __restrict__ offsets,
+                            const float* __restrict__ var, int* row_of, float* maxv0, int* status) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n_rows) return;
   const int a = offsets[row], b = offsets[row + 1];
@@ -32,24 +33,34 @@ __global__ void k_meas_prepare(int n_rows, long long n_meas, const int* __restri
   }
   float mv = 0.f;
   for (int i = a; i < b; ++i) {
-    const float x = loc[2 * i];
-    int j = i;
-    while (j > a && l0[j - 1] > x) {
-      l0[j] = l0[j - 1];
-      l1[j] = l1[j - 1];
-      v0[j] = v0[j - 1];
-      v1[j] = v1[j - 1];
-      id[j] = id[j - 1];
-      --j;
-    }
-    l0[j] = x;
-    l1[j] = loc[2 * i + 1];
-    v0[j] = var[2 * i];
-    v1[j] = var[2 * i + 1];
-    id[j] = i;
+    row_of[i] = row;
     mv = fmaxf(mv, var[2 * i]);
   }
   maxv0[row] = mv;
+}
+
+// Pass 2, one thread per measurement: its rank by (loc0, id) inside its row
+// is its sorted position (a stable segmented sort by loc0).
+__global__ void k_meas_scatter(long long n_meas, const int* __restrict__ offsets, const int* __restrict__ row_of,
+                               const float* __restrict__ loc, const float* __restrict__ var, float* l0, float* l1,
+                               float* v0, float* v1, int* id, const int* status) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_meas) return;
+  if (status[CKF_STATUS_FLAGS] & CKF_FLAG_BAD_OFFSETS) return;
+  const int row = row_of[i];
+  const int a = offsets[row], b = offsets[row + 1];
+  const float x = loc[2 * i];
+  int rank = 0;
+  for (int j = a; j < b; ++j) {
+    const float y = loc[2 * j];
+    rank += (y < x || (y == x && j < i)) ? 1 : 0;
+  }
+  const int d = a + rank;
+  l0[d] = x;
+  l1[d] = loc[2 * i + 1];
+  v0[d] = var[2 * i];
+  v1[d] = var[2 * i + 1];
+  id[d] = (int)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -73,19 +84,7 @@ __global__ void k_init(int n_seeds, int* res_node, int* res_nm, int* queue_head,
 }
 
 // ---------------------------------------------------------------------------
-// candidate pool records
-
-struct Rec {
-  double p[5];
-  double C[15];
-  double chi2;
-  int surf, slot, node, nm, holes;
-  unsigned long long mask;
-  int list[kMaxList];
-  int nlist;
-  int root;
-  float h, path;
-};
+// candidate pool: structure-of-arrays per workgroup, two buffers (in/out)
 
 struct Pool {
   double* d;
@@ -104,15 +103,22 @@ __device__ __forceinline__ Pool pool_at(char* base, int cap, int which) {
   return P;
 }
 
-__device__ __forceinline__ void load_rec(const Pool& P, int r, Rec& c) {
+// Everything of a candidate except its covariance (loaded only when needed).
+struct Light {
+  double p[5];
+  double chi2;
+  int surf, node, nm, holes, nlist, root;
+  unsigned long long mask;
+  int list[kMaxList];
+  float h, path;
+};
+
+__device__ __forceinline__ void load_light(const Pool& P, int r, Light& c) {
   const int cap = P.cap;
 #pragma unroll
   for (int k = 0; k < 5; ++k) c.p[k] = P.d[(PD_P + k) * cap + r];
-#pragma unroll
-  for (int k = 0; k < 15; ++k) c.C[k] = P.d[(PD_C + k) * cap + r];
   c.chi2 = P.d[PD_CHI2 * cap + r];
   c.surf = P.i[PI_SURF * cap + r];
-  c.slot = P.i[PI_SLOT * cap + r];
   c.node = P.i[PI_NODE * cap + r];
   const int nmh = P.i[PI_NMH * cap + r];
   c.nm = nmh & 0xffff;
@@ -128,17 +134,25 @@ __device__ __forceinline__ void load_rec(const Pool& P, int r, Rec& c) {
   c.path = P.f[PF_PATH * cap + r];
 }
 
-__device__ __forceinline__ void store_rec(const Pool& P, int r, const Rec& c) {
+__device__ __forceinline__ void load_cov(const Pool& P, int r, double* C) {
+#pragma unroll
+  for (int k = 0; k < 15; ++k) C[k] = P.d[(PD_C + k) * P.cap + r];
+}
+
+// Store a record from its light part, with parameters/covariance/chi2/node/
+// counts given separately (children differ from the parent only there).
+__device__ __forceinline__ void store_rec(const Pool& P, int r, const Light& c, int slot, const double* p,
+                                          const double* C, double chi2, int node, int nm, int holes) {
   const int cap = P.cap;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) P.d[(PD_P + k) * cap + r] = c.p[k];
+  for (int k = 0; k < 5; ++k) P.d[(PD_P + k) * cap + r] = p[k];
 #pragma unroll
-  for (int k = 0; k < 15; ++k) P.d[(PD_C + k) * cap + r] = c.C[k];
-  P.d[PD_CHI2 * cap + r] = c.chi2;
+  for (int k = 0; k < 15; ++k) P.d[(PD_C + k) * cap + r] = C[k];
+  P.d[PD_CHI2 * cap + r] = chi2;
   P.i[PI_SURF * cap + r] = c.surf;
-  P.i[PI_SLOT * cap + r] = c.slot;
-  P.i[PI_NODE * cap + r] = c.node;
-  P.i[PI_NMH * cap + r] = c.nm | (c.holes << 16);
+  P.i[PI_SLOT * cap + r] = slot;
+  P.i[PI_NODE * cap + r] = node;
+  P.i[PI_NMH * cap + r] = nm | (holes << 16);
   P.i[PI_MASK_LO * cap + r] = (int)(unsigned)(c.mask & 0xffffffffull);
   P.i[PI_MASK_HI * cap + r] = (int)(unsigned)(c.mask >> 32);
 #pragma unroll
@@ -172,37 +186,41 @@ __device__ __forceinline__ long long wave_sum64(long long v) {
 }
 
 // Rank key: more measurements, smaller chi2 sum, fewer holes, then the
-// measurement-id sequence in lexicographic order (walk of the history).
+// measurement-id sequence in lexicographic order.  For equal lengths the
+// histories are walked back together; the last difference met is the first
+// in visiting order.  A shared ancestor ends the walk.
 __device__ bool better(int nmA, double chiA, int hoA, int nodeA, int nmB, double chiB, int hoB, int nodeB,
                        const Node* nodes) {
   if (nmA != nmB) return nmA > nmB;
   if (chiA != chiB) return chiA < chiB;
   if (hoA != hoB) return hoA < hoB;
-  int ia[kMaxSteps], ib[kMaxSteps];
-  int n = min(nmA, kMaxSteps);
-  for (int k = n - 1; k >= 0; --k) {
-    ia[k] = nodeA >= 0 ? nodes[nodeA].meas : -1;
-    ib[k] = nodeB >= 0 ? nodes[nodeB].meas : -1;
-    nodeA = nodeA >= 0 ? nodes[nodeA].parent : -1;
-    nodeB = nodeB >= 0 ? nodes[nodeB].parent : -1;
+  int da = 0, db = 0;
+  bool diff = false;
+  for (int k = 0; k < nmA && nodeA >= 0 && nodeB >= 0 && nodeA != nodeB; ++k) {
+    const int ma = nodes[nodeA].meas, mb = nodes[nodeB].meas;
+    if (ma != mb) {
+      da = ma;
+      db = mb;
+      diff = true;
+    }
+    nodeA = nodes[nodeA].parent;
+    nodeB = nodes[nodeB].parent;
   }
-  for (int k = 0; k < n; ++k)
-    if (ia[k] != ib[k]) return ia[k] < ib[k];
-  return false;
+  return diff && da < db;
 }
 
-struct Cnt {
-  int v[CKF_CNT_N];
-};
 
 constexpr int kMaxSlots = 64;
 
-__global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
+template <int kMinWaves>
+__global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   __shared__ int sh_seed[kMaxSlots], sh_event[kMaxSlots], sh_live[kMaxSlots], sh_step[kMaxSlots];
   __shared__ int sh_best_node[kMaxSlots], sh_best_nm[kMaxSlots], sh_best_holes[kMaxSlots];
   __shared__ double sh_best_chi2[kMaxSlots];
   __shared__ int sh_n_out, sh_bcast;
   __shared__ unsigned long long sh_node_base;
+  __shared__ int sh_cnt[CKF_CNT_N + 3][kWave];  // per-lane work counters (kept out of registers)
+  __shared__ float sh_J[25][kWave];              // per-lane bound-to-bound Jacobian of the leg
 
   const GeomDev& g = A.g;
   const CfgDev& cfg = A.cfg;
@@ -213,15 +231,14 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
   char* base = A.w.pools + (size_t)blockIdx.x * 2 * cap * kRecBytes;
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
-  Cnt cnt;
+  int* const cntp = &sh_cnt[0][lane];  // counter k of this lane at cntp[k * kWave]
+#define CNT(k) cntp[(k) * kWave]
+  constexpr int kBad = CKF_CNT_N, kFailed = CKF_CNT_N + 1, kNavOvf = CKF_CNT_N + 2;
 #pragma unroll
-  for (int k = 0; k < CKF_CNT_N; ++k) cnt.v[k] = 0;
-  int bad_seeds = 0, failed_legs = 0, nav_ovf = 0;
+  for (int k = 0; k < CKF_CNT_N + 3; ++k) CNT(k) = 0;
 
-  if (lane < kMaxSlots) {
-    sh_seed[lane] = -1;
-    sh_live[lane] = 0;
-  }
+  sh_seed[lane] = -1;
+  sh_live[lane] = 0;
   __syncthreads();
 
   int cur = 0, n_in = 0;
@@ -253,7 +270,7 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
           if (!good) {
             A.w.res_node[seed] = -1;
             A.w.res_nm[seed] = 0;
-            ++bad_seeds;
+            ++CNT(kBad);
             ok = false;
           }
         }
@@ -268,22 +285,21 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
           sh_best_nm[lane] = -1;
           sh_best_holes[lane] = 0;
           sh_best_chi2[lane] = 0.0;
-          Rec c;
-          for (int k = 0; k < 5; ++k) c.p[k] = A.s.params[5 * seed + k];
-          for (int k = 0; k < 15; ++k) c.C[k] = A.s.cov[15 * seed + k];
-          c.chi2 = 0.0;
+          Light c;
+          double p[5], C[15];
+#pragma unroll
+          for (int k = 0; k < 5; ++k) p[k] = A.s.params[5 * seed + k];
+#pragma unroll
+          for (int k = 0; k < 15; ++k) C[k] = A.s.cov[15 * seed + k];
           c.surf = A.s.surface[seed];
-          c.slot = lane;
-          c.node = -1;
-          c.nm = 0;
-          c.holes = 0;
           c.mask = 1ull << g.mod[c.surf].layer;
+#pragma unroll
           for (int k = 0; k < kMaxList; ++k) c.list[k] = -1;
           c.nlist = 0;
           c.root = 1;
           c.h = cfg.step_max;
           c.path = 0.f;
-          store_rec(Pin, r, c);
+          store_rec(Pin, r, c, lane, p, C, 0.0, -1, 0, 0);
         }
         n_in += __popcll(om);
         __syncthreads();
@@ -295,25 +311,23 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
     }
 
     // ---- one step of every live candidate
-    if (lane < kMaxSlots) sh_live[lane] = 0;
+    sh_live[lane] = 0;
     if (lane == 0) sh_n_out = 0;
     __syncthreads();
     for (int b0 = 0; b0 < n_in; b0 += kWave) {
       const int r = b0 + lane;
-      Rec c;
-      bool act = r < n_in;
-      if (act) {
-        load_rec(Pin, r, c);
-        act = c.slot >= 0;
-      }
+      int slot = -1;
+      if (r < n_in) slot = Pin.i[PI_SLOT * cap + r];
+      const bool act = slot >= 0;
+      Light c;
       int n_out = 0, n_acc = 0;
-      bool fin = false;
-      double acc_chi2[kMaxBranch];
-      int acc_pos[kMaxBranch];
+      bool fin = false, moved = false, crossed = false;
       Module M;
+      // ---- navigation and the propagation leg (FP32)
       if (act) {
-        ++cnt.v[CKF_CNT_STEPS];
-        bool go = true, crossed = false;
+        load_light(Pin, r, c);
+        ++CNT(CKF_CNT_STEPS);
+        bool go = true;
         if (c.root) {
           c.root = 0;
           load_module(g, c.surf, M);
@@ -323,8 +337,10 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
           const V3 P = ld3(M.c) + L.r;
           const V3 k = (kKappa * L.lam) * cross(L.T, field_at(A.f, P));
           int nt = 0;
-          c.nlist = list_layer(g, M.layer, P, L.T, k, 0.f, c.surf, margin, c.list, nt, nav_ovf);
-          cnt.v[CKF_CNT_NAV_MODULES] += nt;
+          int ovf = 0;
+          c.nlist = list_layer(g, M.layer, P, L.T, k, 0.f, c.surf, margin, c.list, nt, ovf);
+          CNT(kNavOvf) += ovf;
+          CNT(CKF_CNT_NAV_MODULES) += nt;
           crossed = true;
         } else {
           if (c.nlist == 0) {
@@ -337,7 +353,7 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
             const V3 Bf = field_at(A.f, P);
             const Helix H = make_helix(P, L.T, L.lam, Bf);
             float sL;
-            ++cnt.v[CKF_CNT_NAV];
+            ++CNT(CKF_CNT_NAV);
             const int nl = next_layer(g, H, c.mask, cfg.path_max - c.path, sL);
             if (nl < 0) {
               fin = true;
@@ -348,8 +364,10 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
               helix_at(H, sL, Ps, Ts);
               const V3 ks = (kKappa * L.lam) * cross(Ts, Bf);
               int nt = 0;
-              c.nlist = list_layer(g, nl, Ps, Ts, ks, sL, -1, margin, c.list, nt, nav_ovf);
-              cnt.v[CKF_CNT_NAV_MODULES] += nt;
+              int ovf = 0;
+              c.nlist = list_layer(g, nl, Ps, Ts, ks, sL, -1, margin, c.list, nt, ovf);
+              CNT(kNavOvf) += ovf;
+              CNT(CKF_CNT_NAV_MODULES) += nt;
               if (c.nlist == 0) {
                 n_out = 1;  // the layer is crossed in a gap
                 go = false;
@@ -371,82 +389,99 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
             const V3 origin = ld3(Am.c);
             const V3 dB = ld3(M.c) - origin;
             LegStats ls{0, 0};
-            ++cnt.v[CKF_CNT_LEGS];
-            const bool ok = land(L, origin, dB, ld3(M.n), A.f, cfg, c.h, c.path, ls);
-            cnt.v[CKF_CNT_RK_TRIALS] += ls.trials;
-            cnt.v[CKF_CNT_RK_REJECTS] += ls.rejects;
-            double pn[5];
-            float J[5][5];
-            bool good = ok;
-            if (ok) {
+            ++CNT(CKF_CNT_LEGS);
+            bool good = land(L, origin, dB, ld3(M.n), A.f, cfg, c.h, c.path, ls);
+            CNT(CKF_CNT_RK_TRIALS) += ls.trials;
+            CNT(CKF_CNT_RK_REJECTS) += ls.rejects;
+            if (good) {
+              double pn[5];
+              float J[5][5];
               leg_end(L, uA, vA, M, dB, field_at(A.f, origin + L.r), c.p[4], pn, J);
 #pragma unroll
+              for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int b = 0; b < 5; ++b) sh_J[5 * a + b][lane] = J[a][b];
+#pragma unroll
               for (int k = 0; k < 5; ++k) good = good && isfinite(pn[k]);
-            }
-            if (!good) {
-              ++failed_legs;
-              go = false;  // dropped
-            } else {
-              transport_cov(J, c.C);
 #pragma unroll
               for (int k = 0; k < 5; ++k) c.p[k] = pn[k];
+            }
+            if (!good) {
+              ++CNT(kFailed);  // dropped
+            } else {
+              moved = true;
               c.surf = m;
-              crossed = fabs(pn[0]) <= (double)M.hw0 && fabs(pn[1]) <= (double)M.hw1;
-              if (!crossed) {
-                n_out = 1;  // listed but not crossed
-                go = false;
-              }
+              crossed = fabs(c.p[0]) <= (double)M.hw0 && fabs(c.p[1]) <= (double)M.hw1;
+              if (!crossed) n_out = 1;  // listed but not crossed
             }
-          }
-        }
-        if (go && crossed) {
-          ++cnt.v[CKF_CNT_CROSSED];
-          const int row = sh_event[c.slot] * g.n_surfaces + c.surf;
-          const int a = A.m.offsets[row], b = A.m.offsets[row + 1];
-          if (b > a) {
-            const double wd = sqrt(cfg.chi2_max * (c.C[0] + (double)A.w.row_maxvar0[row]));
-            const float lo = (float)(c.p[0] - wd) - 1e-3f, hi = (float)(c.p[0] + wd) + 1e-3f;
-            int l = a, u = b;
-            while (l < u) {  // first position with loc0 >= lo
-              const int mid = (l + u) >> 1;
-              if (A.w.m_loc0[mid] < lo) l = mid + 1; else u = mid;
-            }
-            for (int i = l; i < b && A.w.m_loc0[i] <= hi; ++i) {
-              ++cnt.v[CKF_CNT_CHI2];
-              const double x2 = chi2_of(c.p, c.C, (double)A.w.m_loc0[i], (double)A.w.m_loc1[i],
-                                        (double)A.w.m_var0[i], (double)A.w.m_var1[i]);
-              if (!(x2 < cfg.chi2_max)) continue;
-              const int idi = A.w.m_id[i];
-              int pos = n_acc;
-              while (pos > 0 && (acc_chi2[pos - 1] > x2 ||
-                                 (acc_chi2[pos - 1] == x2 && A.w.m_id[acc_pos[pos - 1]] > idi)))
-                --pos;
-              if (pos >= cfg.branches) continue;
-              for (int q = min(n_acc, cfg.branches - 1); q > pos; --q) {
-                acc_chi2[q] = acc_chi2[q - 1];
-                acc_pos[q] = acc_pos[q - 1];
-              }
-              acc_chi2[pos] = x2;
-              acc_pos[pos] = i;
-              if (n_acc < cfg.branches) ++n_acc;
-            }
-          }
-          if (n_acc == 0) {
-            ++cnt.v[CKF_CNT_HOLES];
-            ++c.holes;
-            if (cfg.material) {
-              apply_ms(M, cfg.mass, c.p, c.C);
-              ++cnt.v[CKF_CNT_MS];
-            }
-            if (c.holes > cfg.max_holes) fin = true;
-            else n_out = 1;
-          } else {
-            n_out = n_acc;
           }
         }
       }
+      // ---- covariance transport, search and gate (FP64)
+      double acc_x2[kMaxBranch];
+      int acc_id[kMaxBranch], acc_pos[kMaxBranch];
+#pragma unroll
+      for (int k = 0; k < kMaxBranch; ++k) {
+        acc_x2[k] = INFINITY;
+        acc_id[k] = 0x7fffffff;
+        acc_pos[k] = 0;
+      }
+      double C[15];
+      if (act) load_cov(Pin, r, C);
+      if (moved) transport_cov_lds(&sh_J[0][lane], C);
+      if (crossed) {
+        ++CNT(CKF_CNT_CROSSED);
+        const int row = sh_event[slot] * g.n_surfaces + c.surf;
+        const int a = A.m.offsets[row], b = A.m.offsets[row + 1];
+        if (b > a) {
+          const double wd = sqrt(cfg.chi2_max * (C[0] + (double)A.w.row_maxvar0[row]));
+          const float lo = (float)(c.p[0] - wd) - 1e-3f, hi = (float)(c.p[0] + wd) + 1e-3f;
+          int l = a, u = b;
+          while (l < u) {  // first position with loc0 >= lo
+            const int mid = (l + u) >> 1;
+            if (A.w.m_loc0[mid] < lo) l = mid + 1; else u = mid;
+          }
+          for (int i = l; i < b; ++i) {
+            const float x0 = A.w.m_loc0[i];
+            if (x0 > hi) break;
+            ++CNT(CKF_CNT_CHI2);
+            const double x2 = chi2_of(c.p, C, (double)x0, (double)A.w.m_loc1[i], (double)A.w.m_var0[i],
+                                      (double)A.w.m_var1[i]);
+            if (!(x2 < cfg.chi2_max)) continue;
+            double cx = x2;
+            int cid = A.w.m_id[i], cpos = i;
+#pragma unroll
+            for (int k = 0; k < kMaxBranch; ++k) {
+              const bool lt = cx < acc_x2[k] || (cx == acc_x2[k] && cid < acc_id[k]);
+              if (lt) {
+                const double tx = acc_x2[k];
+                const int ti = acc_id[k], tp = acc_pos[k];
+                acc_x2[k] = cx;
+                acc_id[k] = cid;
+                acc_pos[k] = cpos;
+                cx = tx;
+                cid = ti;
+                cpos = tp;
+              }
+            }
+            n_acc = min(n_acc + 1, cfg.branches);
+          }
+        }
+        if (n_acc == 0) {
+          ++CNT(CKF_CNT_HOLES);
+          ++c.holes;
+          if (cfg.material) {
+            apply_ms(M, cfg.mass, c.p, C);
+            ++CNT(CKF_CNT_MS);
+          }
+          if (c.holes > cfg.max_holes) fin = true;
+          else n_out = 1;
+        } else {
+          n_out = n_acc;
+        }
+      }
 
-      // ---- slots for the outputs (wave ballot/scan) and history nodes
+      // ---- slots for the outputs (wave scan) and history nodes
       int tot_out;
       const int off = wave_excl_scan(n_out, tot_out);
       const int pos0 = sh_n_out + off;
@@ -459,57 +494,58 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
       }
       __syncthreads();
       const long long node0 = (long long)sh_node_base + noff;
-      if (act && n_out > 0) {
+      if (n_out > 0) {
         if (n_acc == 0) {
-          store_rec(Pout, pos0, c);
-          atomicAdd(&sh_live[c.slot], 1);
+          store_rec(Pout, pos0, c, slot, c.p, C, c.chi2, c.node, c.nm, c.holes);
+          atomicAdd(&sh_live[slot], 1);
         } else {
           const bool room = node0 + n_acc <= A.w.node_cap;
           if (!room) atomicOr(A.status + CKF_STATUS_FLAGS, CKF_FLAG_NODE_CAPACITY);
-          for (int j = 0; j < n_acc; ++j) {
-            const int i = acc_pos[j];
-            Rec ch = c;
-            kf_update(ch.p, ch.C, (double)A.w.m_loc0[i], (double)A.w.m_loc1[i], (double)A.w.m_var0[i],
-                      (double)A.w.m_var1[i]);
-            ++cnt.v[CKF_CNT_KF];
-            ch.nm = c.nm + 1;
-            ch.chi2 = c.chi2 + acc_chi2[j];
-            ch.node = room ? (int)(node0 + j) : -1;
-            if (room) {
-              Node* nd = A.w.nodes + node0 + j;
-              nd->parent = c.node;
-              nd->meas = A.w.m_id[i];
-              nd->surface = c.surf;
-              nd->pad = 0;
 #pragma unroll
-              for (int k = 0; k < 5; ++k) nd->p[k] = ch.p[k];
+          for (int j = 0; j < kMaxBranch; ++j) {
+            if (j < n_acc) {
+              const int i = acc_pos[j];
+              double pc[5], Cc[15];
+              kf_update(c.p, C, (double)A.w.m_loc0[i], (double)A.w.m_loc1[i], (double)A.w.m_var0[i],
+                        (double)A.w.m_var1[i], pc, Cc);
+              ++CNT(CKF_CNT_KF);
+              const int nd = room ? (int)(node0 + j) : -1;
+              if (room) {
+                Node* np = A.w.nodes + node0 + j;
+                np->parent = c.node;
+                np->meas = acc_id[j];
+                np->surface = c.surf;
+                np->pad = 0;
 #pragma unroll
-              for (int k = 0; k < 15; ++k) nd->cov[k] = ch.C[k];
+                for (int k = 0; k < 5; ++k) np->p[k] = pc[k];
+#pragma unroll
+                for (int k = 0; k < 15; ++k) np->cov[k] = Cc[k];
+              }
+              if (cfg.material) {
+                apply_ms(M, cfg.mass, pc, Cc);
+                ++CNT(CKF_CNT_MS);
+              }
+              store_rec(Pout, pos0 + j, c, slot, pc, Cc, c.chi2 + acc_x2[j], nd, c.nm + 1, c.holes);
+              atomicAdd(&sh_live[slot], 1);
             }
-            if (cfg.material) {
-              apply_ms(M, cfg.mass, ch.p, ch.C);
-              ++cnt.v[CKF_CNT_MS];
-            }
-            store_rec(Pout, pos0 + j, ch);
-            atomicAdd(&sh_live[c.slot], 1);
           }
         }
       }
       // ---- finished candidates update their seed's best (one lane at a time)
-      unsigned long long fm = __ballot(act && fin);
+      unsigned long long fm = __ballot(fin);
       while (fm) {
         const int l = __ffsll((long long)fm) - 1;
         fm &= fm - 1;
         if (lane == l) {
-          ++cnt.v[CKF_CNT_FINISHED];
-          const int sl = c.slot;
+          ++CNT(CKF_CNT_FINISHED);
           if (c.nm >= cfg.min_meas &&
-              (sh_best_node[sl] < 0 || better(c.nm, c.chi2, c.holes, c.node, sh_best_nm[sl], sh_best_chi2[sl],
-                                               sh_best_holes[sl], sh_best_node[sl], A.w.nodes))) {
-            sh_best_node[sl] = c.node;
-            sh_best_nm[sl] = c.nm;
-            sh_best_chi2[sl] = c.chi2;
-            sh_best_holes[sl] = c.holes;
+              (sh_best_node[slot] < 0 || better(c.nm, c.chi2, c.holes, c.node, sh_best_nm[slot],
+                                                sh_best_chi2[slot], sh_best_holes[slot], sh_best_node[slot],
+                                                A.w.nodes))) {
+            sh_best_node[slot] = c.node;
+            sh_best_nm[slot] = c.nm;
+            sh_best_chi2[slot] = c.chi2;
+            sh_best_holes[slot] = c.holes;
           }
         }
         __syncthreads();
@@ -523,30 +559,33 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
       const bool over = lane < S && sh_seed[lane] >= 0 && sh_live[lane] > cfg.max_live;
       if (__ballot(over)) {
         if (over) {
-          int idx[kMaxSlots];
-          int n = 0;
-          for (int r = 0; r < n_out_total && n < kMaxSlots; ++r)
-            if (Pout.i[PI_SLOT * cap + r] == lane) idx[n++] = r;
-          for (int a = 0; a < n; ++a) {
-            const int ra = idx[a];
+          int kept = 0;
+          for (int ra = 0; ra < n_out_total; ++ra) {
+            if (Pout.i[PI_SLOT * cap + ra] != lane && Pout.i[PI_SLOT * cap + ra] != -2 - lane) continue;
             const int nmh_a = Pout.i[PI_NMH * cap + ra];
             const double ch_a = Pout.d[PD_CHI2 * cap + ra];
             const int nd_a = Pout.i[PI_NODE * cap + ra];
             int n_better = 0;
-            for (int b = 0; b < n; ++b) {
-              if (b == a) continue;
-              const int rb = idx[b];
+            for (int rb = 0; rb < n_out_total; ++rb) {
+              if (rb == ra) continue;
+              const int sb = Pout.i[PI_SLOT * cap + rb];
+              if (sb != lane && sb != -2 - lane) continue;
               const int nmh_b = Pout.i[PI_NMH * cap + rb];
               if (better(nmh_b & 0xffff, Pout.d[PD_CHI2 * cap + rb], nmh_b >> 16, Pout.i[PI_NODE * cap + rb],
                          nmh_a & 0xffff, ch_a, nmh_a >> 16, nd_a, A.w.nodes))
                 ++n_better;
             }
             if (n_better >= cfg.max_live) {
-              Pout.i[PI_SLOT * cap + ra] = -1;  // dead: skipped by the next step
-              ++cnt.v[CKF_CNT_PRUNED];
+              Pout.i[PI_SLOT * cap + ra] = -2 - lane;  // pruned (still ranked by the others)
+              ++CNT(CKF_CNT_PRUNED);
+            } else {
+              ++kept;
             }
           }
-          sh_live[lane] = min(n, cfg.max_live);
+          // pruned records become dead
+          for (int ra = 0; ra < n_out_total; ++ra)
+            if (Pout.i[PI_SLOT * cap + ra] == -2 - lane) Pout.i[PI_SLOT * cap + ra] = -1;
+          sh_live[lane] = kept;
         }
       }
       __syncthreads();
@@ -583,7 +622,7 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
             const int l = __ffsll((long long)fm) - 1;
             fm &= fm - 1;
             if (lane == l) {
-              ++cnt.v[CKF_CNT_FINISHED];
+              ++CNT(CKF_CNT_FINISHED);
               if (nm >= cfg.min_meas && (sh_best_node[sl] < 0 || better(nm, ch, ho, nd, sh_best_nm[sl],
                                                                           sh_best_chi2[sl], sh_best_holes[sl],
                                                                           sh_best_node[sl], A.w.nodes))) {
@@ -619,16 +658,17 @@ __global__ __launch_bounds__(kWave) void k_ckf(CkfArgs A) {
   if (A.counters) {
 #pragma unroll
     for (int k = 0; k < CKF_CNT_N; ++k) {
-      const long long t = wave_sum64((long long)cnt.v[k]);
+      const long long t = wave_sum64((long long)CNT(k));
       if (lane == 0 && t) atomicAdd((unsigned long long*)(A.counters + k), (unsigned long long)t);
     }
   }
-  const long long tb = wave_sum64(bad_seeds), tf = wave_sum64(failed_legs), tn = wave_sum64(nav_ovf);
+  const long long tb = wave_sum64(CNT(kBad)), tf = wave_sum64(CNT(kFailed)), tn = wave_sum64(CNT(kNavOvf));
   if (lane == 0) {
     if (tb) atomicAdd(A.status + CKF_STATUS_BAD_SEEDS, (int)tb);
     if (tf) atomicAdd(A.status + CKF_STATUS_FAILED_LEGS, (int)tf);
     if (tn) atomicAdd(A.status + CKF_STATUS_NAV_OVERFLOW, (int)tn);
   }
+#undef CNT
 }
 
 // ---------------------------------------------------------------------------
@@ -781,9 +821,10 @@ __global__ void k_kf_update_batch(int n, const double* p_in, const double* cov_i
   for (int k = 0; k < 15; ++k) C[k] = cov_in[15 * i + k];
   const double m0 = meas[2 * i], m1 = meas[2 * i + 1], v0 = var[2 * i], v1 = var[2 * i + 1];
   if (chi2) chi2[i] = chi2_of(p, C, m0, m1, v0, v1);
-  kf_update(p, C, m0, m1, v0, v1);
-  for (int k = 0; k < 5; ++k) p_out[5 * i + k] = p[k];
-  for (int k = 0; k < 15; ++k) cov_out[15 * i + k] = C[k];
+  double po[5], Co[15];
+  kf_update(p, C, m0, m1, v0, v1, po, Co);
+  for (int k = 0; k < 5; ++k) p_out[5 * i + k] = po[k];
+  for (int k = 0; k < 15; ++k) cov_out[15 * i + k] = Co[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -799,14 +840,20 @@ hipError_t launch_init(int n_seeds, const Workspace& w, const ckf_tracks& out, h
 hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status, hipStream_t st) {
   const int rows = m.n_events * m.n_surfaces;
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_meas_prepare, dim3((rows + 255) / 256), dim3(256), 0, st, rows, (long long)m.n_meas,
-                     m.offsets, m.loc, m.var, w.m_loc0, w.m_loc1, w.m_var0, w.m_var1, w.m_id, w.row_maxvar0,
-                     status);
+  hipLaunchKernelGGL(k_meas_rows, dim3((rows + 255) / 256), dim3(256), 0, st, rows, (long long)m.n_meas, m.offsets,
+                     m.var, w.row_of, w.row_maxvar0, status);
+  if (m.n_meas > 0)
+    hipLaunchKernelGGL(k_meas_scatter, dim3((unsigned)((m.n_meas + 255) / 256)), dim3(256), 0, st,
+                       (long long)m.n_meas, m.offsets, w.row_of, m.loc, m.var, w.m_loc0, w.m_loc1, w.m_var0,
+                       w.m_var1, w.m_id, status);
   return hipGetLastError();
 }
 
-hipError_t launch_ckf(const CkfArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_ckf, dim3(a.w.grid), dim3(kWave), 0, st, a);
+hipError_t launch_ckf(const CkfArgs& a, int waves_per_simd, hipStream_t st) {
+  if (waves_per_simd >= 2)
+    hipLaunchKernelGGL(k_ckf<2>, dim3(a.w.grid), dim3(kWave), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_ckf<1>, dim3(a.w.grid), dim3(kWave), 0, st, a);
   return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ struct CkfArgs {
 
 hipError_t launch_init(int n_seeds, const Workspace& w, const ckf_tracks& out, hipStream_t st);
 hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status, hipStream_t st);
-hipError_t launch_ckf(const CkfArgs& a, hipStream_t st);
+hipError_t launch_ckf(const CkfArgs& a, int waves_per_simd, hipStream_t st);
 hipError_t launch_output(int n_seeds, const Workspace& w, const int* seed_event, const ckf_tracks& out,
                          hipStream_t st);
 hipError_t launch_propagate(const GeomDev& g, const FieldDev& f, const CfgDev& c, int n, const int* src,
