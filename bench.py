@@ -102,16 +102,23 @@ def main():
     geo = ckf.Geometry(det.as_arrays())
     fld = ckf.UniformField(0.0, 0.0, 2.0)
     b = ckf.Batch.from_event(batch)
+    stream = torch.cuda.current_stream()
+    # one run of the instrumented kernel variant counts the work units of the
+    # batch (the search is deterministic, so every run does the same work)
+    counting = ckf.Finder(geo, fld, b, ckf.config(), ckf.launch(args.grid, args.seeds_per_group), counters=True)
+    counting.enqueue(stream)
+    rc = counting.result()
+    counters = rc["counters"]
+    del counting
     timer = ckf.KernelTimer()
     finder = ckf.Finder(geo, fld, b, ckf.config(),
-                        ckf.launch(args.grid, args.seeds_per_group, 0, timer, args.waves))
-    stream = torch.cuda.current_stream()
+                        ckf.launch(args.grid, args.seeds_per_group, 0, timer, args.waves), counters=False)
     for _ in range(args.warmup):
         finder.enqueue(stream)
     torch.cuda.synchronize()
     r = finder.result()  # checks the status flags of the warm-up
     n_tracks = r["n_tracks"]
-    counters = r["counters"]
+    assert n_tracks == rc["n_tracks"] and np.array_equal(r["meas"], rc["meas"]), "variants disagree"
     print(f"# warm-up done: {n_tracks} tracks", file=sys.stderr, flush=True)
 
     kernel_ms = []

@@ -150,7 +150,8 @@ typedef struct ckf_tracks {
   int64_t* counters;         /* [16] or NULL: work-unit counters (see ckf_counter) */
 } ckf_tracks;
 
-/* Work-unit counters accumulated into tracks->counters when it is not NULL. */
+/* Work-unit counters accumulated into tracks->counters when it is not NULL
+ * (an instrumented kernel variant runs then; results are identical). */
 enum {
   CKF_CNT_STEPS = 0,       /* candidate steps */
   CKF_CNT_NAV = 1,         /* next-layer searches */
@@ -174,7 +175,7 @@ typedef struct ckf_launch {
   int32_t seeds_per_group;   /* concurrent seeds per 64-lane workgroup (1..64); 0 = default */
   int32_t nodes_per_seed;    /* history capacity per seed in the workspace; 0 = default (32) */
   ckf_timer* timer;          /* NULL, or events recorded around the track-finding kernel */
-  int32_t waves_per_simd;    /* register budget of the kernel variant: 1 or 2 (0 = default) */
+  int32_t waves_per_simd;    /* register budget of the kernel variant: 1 or 2 waves per SIMD (0 = 2) */
 } ckf_launch;
 
 /* Geometry: validates, builds the navigation grid on the host, uploads. */

@@ -77,7 +77,10 @@ class Geometry:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            _abi.load().ckf_geometry_destroy(h)
+            try:
+                _abi.load().ckf_geometry_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self.handle = None
 
 
@@ -90,7 +93,10 @@ class UniformField:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            _abi.load().ckf_field_destroy(h)
+            try:
+                _abi.load().ckf_field_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self.handle = None
 
 
@@ -145,7 +151,10 @@ class KernelTimer:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            _abi.load().ckf_timer_destroy(h)
+            try:
+                _abi.load().ckf_timer_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self.handle = None
 
 

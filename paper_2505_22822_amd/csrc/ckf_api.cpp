@@ -237,7 +237,7 @@ ckf::Launch resolve_launch(const ckf_config* c, const ckf_launch* l, int n_seeds
 }
 
 struct Layout {
-  size_t off_loc0, off_loc1, off_var0, off_var1, off_id, off_rowof, off_maxv, off_nodes, off_nodecnt, off_queue, off_res_node,
+  size_t off_sorted, off_id, off_rowof, off_maxv, off_nodes, off_nodecnt, off_queue, off_res_node,
       off_res_nm, off_res_holes, off_res_chi2, off_scan_a, off_scan_b, off_pools, total;
   long long node_cap;
 };
@@ -254,10 +254,7 @@ Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, l
   const size_t rows = (size_t)std::max(1, n_events * n_surfaces);
   const size_t ns = (size_t)std::max(1, n_seeds);
   o.node_cap = (long long)ns * L.nodes_per_seed + 1024;
-  o.off_loc0 = take(nm * 4);
-  o.off_loc1 = take(nm * 4);
-  o.off_var0 = take(nm * 4);
-  o.off_var1 = take(nm * 4);
+  o.off_sorted = take(nm * 16);
   o.off_id = take(nm * 4);
   o.off_rowof = take(nm * 4);
   o.off_maxv = take(rows * 4);
@@ -271,7 +268,7 @@ Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, l
   const size_t nb = (ns + 255) / 256 + 1;
   o.off_scan_a = take(nb * 4);
   o.off_scan_b = take(nb * 4);
-  o.off_pools = take((size_t)L.grid * 2 * L.pool_cap * ckf::kRecBytes);
+  o.off_pools = take((size_t)L.grid * 2 * L.pool_cap * ckf::kRecStride);
   o.total = at;
   return o;
 }
@@ -438,10 +435,7 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
     return fail(CKF_ERR_CAPACITY, "workspace too small: need " + std::to_string(o.total) + " bytes");
   char* ws = static_cast<char*>(workspace);
   ckf::Workspace w;
-  w.m_loc0 = reinterpret_cast<float*>(ws + o.off_loc0);
-  w.m_loc1 = reinterpret_cast<float*>(ws + o.off_loc1);
-  w.m_var0 = reinterpret_cast<float*>(ws + o.off_var0);
-  w.m_var1 = reinterpret_cast<float*>(ws + o.off_var1);
+  w.m_sorted = reinterpret_cast<float4*>(ws + o.off_sorted);
   w.m_id = reinterpret_cast<int*>(ws + o.off_id);
   w.row_of = reinterpret_cast<int*>(ws + o.off_rowof);
   w.row_maxvar0 = reinterpret_cast<float*>(ws + o.off_maxv);

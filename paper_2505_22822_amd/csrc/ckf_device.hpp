@@ -49,41 +49,51 @@ struct Leg {
   V3 dr[3], dT[3];
 };
 
-// One Nystrom RKN4 step of length h (field sampled at start, midpoint, end;
-// uniform here).  Tangent columns are differentiated through the same
-// stages.  Returns the error estimate h^2 * max|k1 - k2 - k3 + k4|.
-__device__ __forceinline__ float rkn4_step(const Leg& L, float h, V3 B, Leg& o) {
+// One Nystrom RKN4 step of length h for r'' = kappa*lambda*(r' x B) (field
+// sampled at start, midpoint and end; uniform here).  The stages are
+// evaluated first and give the error estimate h^2 * max|k1 - k2 - k3 + k4|;
+// only an accepted step then advances the state and carries the tangent
+// columns through the same stages, in place.
+struct Stages {
+  V3 k1, k2, k3, k4, T2, T3, T4;
+};
+
+__device__ __forceinline__ float rkn4_stages(const Leg& L, float h, V3 B, Stages& S) {
+  const float kl = kKappa * L.lam;
+  const float h2 = 0.5f * h;
+  S.k1 = kl * cross(L.T, B);
+  S.T2 = L.T + h2 * S.k1;
+  S.k2 = kl * cross(S.T2, B);
+  S.T3 = L.T + h2 * S.k2;
+  S.k3 = kl * cross(S.T3, B);
+  S.T4 = L.T + h * S.k3;
+  S.k4 = kl * cross(S.T4, B);
+  return h * h * maxabs(S.k1 - S.k2 - S.k3 + S.k4);
+}
+
+__device__ __forceinline__ void rkn4_advance(Leg& L, float h, V3 B, const Stages& S) {
   const float kl = kKappa * L.lam;
   const float h2 = 0.5f * h, h6 = h * (1.0f / 6.0f), hh6 = h * h * (1.0f / 6.0f);
-  const V3 T = L.T;
-  const V3 k1 = kl * cross(T, B);
-  const V3 T2 = T + h2 * k1;
-  const V3 k2 = kl * cross(T2, B);
-  const V3 T3 = T + h2 * k2;
-  const V3 k3 = kl * cross(T3, B);
-  const V3 T4 = T + h * k3;
-  const V3 k4 = kl * cross(T4, B);
-  o.r = L.r + h * T + hh6 * (k1 + k2 + k3);
-  o.T = T + h6 * (k1 + 2.0f * (k2 + k3) + k4);
-  o.lam = L.lam;
   // d(kappa*lambda*(T x B)) = kappa*lambda*(dT x B) + kappa*dlambda*(T x B)
-  const V3 c1 = kKappa * cross(T, B), c2 = kKappa * cross(T2, B), c3 = kKappa * cross(T3, B),
-           c4 = kKappa * cross(T4, B);
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const float dl = (j == 2) ? 1.0f : 0.0f;
     const V3 dT = L.dT[j];
-    const V3 d1 = kl * cross(dT, B) + dl * c1;
+    V3 d1 = kl * cross(dT, B);
+    if (j == 2) d1 = d1 + kKappa * cross(L.T, B);
     const V3 dT2 = dT + h2 * d1;
-    const V3 d2 = kl * cross(dT2, B) + dl * c2;
+    V3 d2 = kl * cross(dT2, B);
+    if (j == 2) d2 = d2 + kKappa * cross(S.T2, B);
     const V3 dT3 = dT + h2 * d2;
-    const V3 d3 = kl * cross(dT3, B) + dl * c3;
+    V3 d3 = kl * cross(dT3, B);
+    if (j == 2) d3 = d3 + kKappa * cross(S.T3, B);
     const V3 dT4 = dT + h * d3;
-    const V3 d4 = kl * cross(dT4, B) + dl * c4;
-    o.dr[j] = L.dr[j] + h * dT + hh6 * (d1 + d2 + d3);
-    o.dT[j] = dT + h6 * (d1 + 2.0f * (d2 + d3) + d4);
+    V3 d4 = kl * cross(dT4, B);
+    if (j == 2) d4 = d4 + kKappa * cross(S.T4, B);
+    L.dr[j] = L.dr[j] + h * dT + hh6 * (d1 + d2 + d3);
+    L.dT[j] = dT + h6 * (d1 + 2.0f * (d2 + d3) + d4);
   }
-  return h * h * maxabs(k1 - k2 - k3 + k4);
+  L.r = L.r + h * L.T + hh6 * (S.k1 + S.k2 + S.k3);
+  L.T = L.T + h6 * (S.k1 + 2.0f * (S.k2 + S.k3) + S.k4);
 }
 
 // Signed path to the plane (c, n) from r + d T + d^2 k / 2 (root nearest the
@@ -119,15 +129,15 @@ __device__ bool land(Leg& L, V3 origin, V3 c, V3 n, const FieldDev& F, const Cfg
     }
     const bool limited = fabsf(d) < h_trial;
     const float h = copysignf(fminf(fabsf(d), h_trial), d);
-    Leg o;
-    const float err = rkn4_step(L, h, B, o);
+    Stages S;
+    const float err = rkn4_stages(L, h, B, S);
     ++st.trials;
     if (!(err <= cfg.step_tol)) {
       ++st.rejects;
       h_trial = fabsf(h) * fmaxf(0.25f, 0.9f * sqrtf(sqrtf(cfg.step_tol / err)));
       continue;
     }
-    L = o;
+    rkn4_advance(L, h, B, S);
     path += fabsf(h);
     const float grow = err > 0.0f ? fminf(4.0f, 0.9f * sqrtf(sqrtf(cfg.step_tol / err))) : 4.0f;
     h_trial = limited ? fminf(cfg.step_max, fmaxf(h_trial, fabsf(h) * grow)) : fminf(cfg.step_max, fabsf(h) * grow);

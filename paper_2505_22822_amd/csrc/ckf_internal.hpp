@@ -77,19 +77,17 @@ struct alignas(16) Node {
 };
 static_assert(sizeof(Node) == 176, "node record");
 
-// Candidate pool record, stored structure-of-arrays per workgroup.
+// Candidate pool record (array of structs per workgroup): doubles, ints, floats.
 enum PoolD { PD_P = 0, PD_C = 5, PD_CHI2 = 20, PD_N = 21 };
 enum PoolI { PI_SURF = 0, PI_SLOT, PI_NODE, PI_NMH, PI_MASK_LO, PI_MASK_HI, PI_LIST, PI_NLIST = PI_LIST + kMaxList, PI_N };
 enum PoolF { PF_H = 0, PF_PATH, PF_N };
 constexpr size_t kRecBytes = PD_N * 8 + PI_N * 4 + PF_N * 4;
+constexpr size_t kRecStride = (kRecBytes + 15) / 16 * 16;  // array-of-structs record stride
 
 struct Workspace {
   // carved from the caller's workspace
-  float* m_loc0;
-  float* m_loc1;
-  float* m_var0;
-  float* m_var1;
-  int* m_id;
+  float4* m_sorted;  // (loc0, loc1, var0, var1) sorted by loc0 within each row
+  int* m_id;         // caller's id of each sorted measurement
   int* row_of;
   float* row_maxvar0;
   Node* nodes;

@@ -42,8 +42,8 @@ __global__ void k_meas_rows(int n_rows, long long n_meas, const int* __restrict_
 // Pass 2, one thread per measurement: its rank by (loc0, id) inside its row
 // is its sorted position (a stable segmented sort by loc0).
 __global__ void k_meas_scatter(long long n_meas, const int* __restrict__ offsets, const int* __restrict__ row_of,
-                               const float* __restrict__ loc, const float* __restrict__ var, float* l0, float* l1,
-                               float* v0, float* v1, int* id, const int* status) {
+                               const float* __restrict__ loc, const float* __restrict__ var, float4* sorted, int* id,
+                               const int* status) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_meas) return;
   if (status[CKF_STATUS_FLAGS] & CKF_FLAG_BAD_OFFSETS) return;
@@ -56,10 +56,7 @@ __global__ void k_meas_scatter(long long n_meas, const int* __restrict__ offsets
     rank += (y < x || (y == x && j < i)) ? 1 : 0;
   }
   const int d = a + rank;
-  l0[d] = x;
-  l1[d] = loc[2 * i + 1];
-  v0[d] = var[2 * i];
-  v1[d] = var[2 * i + 1];
+  sorted[d] = make_float4(x, loc[2 * i + 1], var[2 * i], var[2 * i + 1]);
   id[d] = (int)i;
 }
 
@@ -87,20 +84,27 @@ __global__ void k_init(int n_seeds, int* res_node, int* res_nm, int* queue_head,
 // candidate pool: structure-of-arrays per workgroup, two buffers (in/out)
 
 struct Pool {
-  double* d;
-  int* i;
-  float* f;
+  char* base;  // records of kRecStride bytes: doubles, then ints, then floats
   int cap;
 };
 
 __device__ __forceinline__ Pool pool_at(char* base, int cap, int which) {
-  char* p = base + (size_t)which * cap * kRecBytes;
   Pool P;
-  P.d = reinterpret_cast<double*>(p);
-  P.i = reinterpret_cast<int*>(p + (size_t)cap * PD_N * 8);
-  P.f = reinterpret_cast<float*>(p + (size_t)cap * (PD_N * 8 + PI_N * 4));
+  P.base = base + (size_t)which * cap * kRecStride;
   P.cap = cap;
   return P;
+}
+
+// Field k of record r: one per-lane base address, the field is an immediate
+// offset from it.
+__device__ __forceinline__ double& PDr(const Pool& P, int r, int k) {
+  return reinterpret_cast<double*>(P.base + (size_t)r * kRecStride)[k];
+}
+__device__ __forceinline__ int& PIr(const Pool& P, int r, int k) {
+  return reinterpret_cast<int*>(P.base + (size_t)r * kRecStride + PD_N * 8)[k];
+}
+__device__ __forceinline__ float& PFr(const Pool& P, int r, int k) {
+  return reinterpret_cast<float*>(P.base + (size_t)r * kRecStride + PD_N * 8 + PI_N * 4)[k];
 }
 
 // Everything of a candidate except its covariance (loaded only when needed).
@@ -114,52 +118,50 @@ struct Light {
 };
 
 __device__ __forceinline__ void load_light(const Pool& P, int r, Light& c) {
-  const int cap = P.cap;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) c.p[k] = P.d[(PD_P + k) * cap + r];
-  c.chi2 = P.d[PD_CHI2 * cap + r];
-  c.surf = P.i[PI_SURF * cap + r];
-  c.node = P.i[PI_NODE * cap + r];
-  const int nmh = P.i[PI_NMH * cap + r];
+  for (int k = 0; k < 5; ++k) c.p[k] = PDr(P, r, (PD_P + k));
+  c.chi2 = PDr(P, r, PD_CHI2);
+  c.surf = PIr(P, r, PI_SURF);
+  c.node = PIr(P, r, PI_NODE);
+  const int nmh = PIr(P, r, PI_NMH);
   c.nm = nmh & 0xffff;
   c.holes = nmh >> 16;
-  c.mask = (unsigned long long)(unsigned)P.i[PI_MASK_LO * cap + r] |
-           ((unsigned long long)(unsigned)P.i[PI_MASK_HI * cap + r] << 32);
+  c.mask = (unsigned long long)(unsigned)PIr(P, r, PI_MASK_LO) |
+           ((unsigned long long)(unsigned)PIr(P, r, PI_MASK_HI) << 32);
 #pragma unroll
-  for (int k = 0; k < kMaxList; ++k) c.list[k] = P.i[(PI_LIST + k) * cap + r];
-  const int nl = P.i[PI_NLIST * cap + r];
+  for (int k = 0; k < kMaxList; ++k) c.list[k] = PIr(P, r, (PI_LIST + k));
+  const int nl = PIr(P, r, PI_NLIST);
   c.nlist = nl & 0xff;
   c.root = nl >> 8;
-  c.h = P.f[PF_H * cap + r];
-  c.path = P.f[PF_PATH * cap + r];
+  c.h = PFr(P, r, PF_H);
+  c.path = PFr(P, r, PF_PATH);
 }
 
 __device__ __forceinline__ void load_cov(const Pool& P, int r, double* C) {
 #pragma unroll
-  for (int k = 0; k < 15; ++k) C[k] = P.d[(PD_C + k) * P.cap + r];
+  for (int k = 0; k < 15; ++k) C[k] = PDr(P, r, PD_C + k);
 }
 
 // Store a record from its light part, with parameters/covariance/chi2/node/
 // counts given separately (children differ from the parent only there).
 __device__ __forceinline__ void store_rec(const Pool& P, int r, const Light& c, int slot, const double* p,
                                           const double* C, double chi2, int node, int nm, int holes) {
-  const int cap = P.cap;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) P.d[(PD_P + k) * cap + r] = p[k];
+  for (int k = 0; k < 5; ++k) PDr(P, r, (PD_P + k)) = p[k];
 #pragma unroll
-  for (int k = 0; k < 15; ++k) P.d[(PD_C + k) * cap + r] = C[k];
-  P.d[PD_CHI2 * cap + r] = chi2;
-  P.i[PI_SURF * cap + r] = c.surf;
-  P.i[PI_SLOT * cap + r] = slot;
-  P.i[PI_NODE * cap + r] = node;
-  P.i[PI_NMH * cap + r] = nm | (holes << 16);
-  P.i[PI_MASK_LO * cap + r] = (int)(unsigned)(c.mask & 0xffffffffull);
-  P.i[PI_MASK_HI * cap + r] = (int)(unsigned)(c.mask >> 32);
+  for (int k = 0; k < 15; ++k) PDr(P, r, (PD_C + k)) = C[k];
+  PDr(P, r, PD_CHI2) = chi2;
+  PIr(P, r, PI_SURF) = c.surf;
+  PIr(P, r, PI_SLOT) = slot;
+  PIr(P, r, PI_NODE) = node;
+  PIr(P, r, PI_NMH) = nm | (holes << 16);
+  PIr(P, r, PI_MASK_LO) = (int)(unsigned)(c.mask & 0xffffffffull);
+  PIr(P, r, PI_MASK_HI) = (int)(unsigned)(c.mask >> 32);
 #pragma unroll
-  for (int k = 0; k < kMaxList; ++k) P.i[(PI_LIST + k) * cap + r] = c.list[k];
-  P.i[PI_NLIST * cap + r] = c.nlist | (c.root << 8);
-  P.f[PF_H * cap + r] = c.h;
-  P.f[PF_PATH * cap + r] = c.path;
+  for (int k = 0; k < kMaxList; ++k) PIr(P, r, (PI_LIST + k)) = c.list[k];
+  PIr(P, r, PI_NLIST) = c.nlist | (c.root << 8);
+  PFr(P, r, PF_H) = c.h;
+  PFr(P, r, PF_PATH) = c.path;
 }
 
 // ---------------------------------------------------------------------------
@@ -212,15 +214,16 @@ __device__ bool better(int nmA, double chiA, int hoA, int nodeA, int nmB, double
 
 constexpr int kMaxSlots = 64;
 
-template <int kMinWaves>
+// kCount: the instrumented variant that accumulates the work-unit counters
+// (used once to measure the algorithmic work; the work is deterministic).
+template <int kMinWaves, bool kCount>
 __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   __shared__ int sh_seed[kMaxSlots], sh_event[kMaxSlots], sh_live[kMaxSlots], sh_step[kMaxSlots];
   __shared__ int sh_best_node[kMaxSlots], sh_best_nm[kMaxSlots], sh_best_holes[kMaxSlots];
   __shared__ double sh_best_chi2[kMaxSlots];
   __shared__ int sh_n_out, sh_bcast;
   __shared__ unsigned long long sh_node_base;
-  __shared__ int sh_cnt[CKF_CNT_N + 3][kWave];  // per-lane work counters (kept out of registers)
-  __shared__ float sh_J[25][kWave];              // per-lane bound-to-bound Jacobian of the leg
+  __shared__ int sh_cnt[kCount ? CKF_CNT_N + 3 : 3][kWave];  // per-lane counters (kept out of registers)
 
   const GeomDev& g = A.g;
   const CfgDev& cfg = A.cfg;
@@ -228,14 +231,22 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   const int S = A.w.seeds_per_group;
   const int cap = A.w.pool_cap;
   const float margin = cfg.nav_margin;
-  char* base = A.w.pools + (size_t)blockIdx.x * 2 * cap * kRecBytes;
+  char* base = A.w.pools + (size_t)blockIdx.x * 2 * cap * kRecStride;
   const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
-  int* const cntp = &sh_cnt[0][lane];  // counter k of this lane at cntp[k * kWave]
-#define CNT(k) cntp[(k) * kWave]
+  // Counter k of this lane.  Work counters (k < CKF_CNT_N) exist only in
+  // the instrumented variant; the three status counters always exist.
+  int* const cntp = &sh_cnt[0][lane];
   constexpr int kBad = CKF_CNT_N, kFailed = CKF_CNT_N + 1, kNavOvf = CKF_CNT_N + 2;
+  constexpr int kStatusBase = kCount ? CKF_CNT_N : 0;
+#define CNT_IDX(k) ((k) >= CKF_CNT_N ? (k) - CKF_CNT_N + kStatusBase : (k))
+#define CNT_ADD(k, v)                                          \
+  do {                                                         \
+    if (kCount || (k) >= CKF_CNT_N) cntp[CNT_IDX(k) * kWave] += (v); \
+  } while (0)
+#define CNT_GET(k) cntp[CNT_IDX(k) * kWave]
 #pragma unroll
-  for (int k = 0; k < CKF_CNT_N + 3; ++k) CNT(k) = 0;
+  for (int k = 0; k < kStatusBase + 3; ++k) cntp[k * kWave] = 0;
 
   sh_seed[lane] = -1;
   sh_live[lane] = 0;
@@ -270,7 +281,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           if (!good) {
             A.w.res_node[seed] = -1;
             A.w.res_nm[seed] = 0;
-            ++CNT(kBad);
+            CNT_ADD(kBad, 1);
             ok = false;
           }
         }
@@ -317,107 +328,125 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
     for (int b0 = 0; b0 < n_in; b0 += kWave) {
       const int r = b0 + lane;
       int slot = -1;
-      if (r < n_in) slot = Pin.i[PI_SLOT * cap + r];
+      if (r < n_in) slot = PIr(Pin, r, PI_SLOT);
       const bool act = slot >= 0;
-      Light c;
-      int n_out = 0, n_acc = 0;
-      bool fin = false, moved = false, crossed = false;
-      Module M;
-      // ---- navigation and the propagation leg (FP32)
+      // outcome of this step: 0 nothing (dropped or idle), 1 the candidate
+      // continues as it is, 2 it crossed a module (search), 3 it finished
+      int outcome = 0;
+      bool moved = false;
+      float J[5][5];
+
+      // ---- phase 1: navigation and the propagation leg (FP32); the changed
+      // navigation state is written back into the candidate's own record
       if (act) {
-        load_light(Pin, r, c);
-        ++CNT(CKF_CNT_STEPS);
-        bool go = true;
-        if (c.root) {
-          c.root = 0;
-          load_module(g, c.surf, M);
+        CNT_ADD(CKF_CNT_STEPS, 1);
+        double p[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
+        int surf = PIr(Pin, r, PI_SURF);
+        const int nlp = PIr(Pin, r, PI_NLIST);
+        int nlist = nlp & 0xff;
+        const int root = nlp >> 8;
+        unsigned long long mask = (unsigned long long)(unsigned)PIr(Pin, r, PI_MASK_LO) |
+                                  ((unsigned long long)(unsigned)PIr(Pin, r, PI_MASK_HI) << 32);
+        int list[kMaxList];
+#pragma unroll
+        for (int k = 0; k < kMaxList; ++k) list[k] = PIr(Pin, r, (PI_LIST + k));
+        float h = PFr(Pin, r, PF_H), path = PFr(Pin, r, PF_PATH);
+        if (root) {
+          Module M;
+          load_module(g, surf, M);
           Leg L;
           V3 uA, vA;
-          leg_start(M, c.p, L, uA, vA);
+          leg_start(M, p, L, uA, vA);
           const V3 P = ld3(M.c) + L.r;
           const V3 k = (kKappa * L.lam) * cross(L.T, field_at(A.f, P));
-          int nt = 0;
-          int ovf = 0;
-          c.nlist = list_layer(g, M.layer, P, L.T, k, 0.f, c.surf, margin, c.list, nt, ovf);
-          CNT(kNavOvf) += ovf;
-          CNT(CKF_CNT_NAV_MODULES) += nt;
-          crossed = true;
+          int nt = 0, ovf = 0;
+          nlist = list_layer(g, M.layer, P, L.T, k, 0.f, surf, margin, list, nt, ovf);
+          CNT_ADD(CKF_CNT_NAV_MODULES, nt);
+          CNT_ADD(kNavOvf, ovf);
+          outcome = 2;
         } else {
-          if (c.nlist == 0) {
+          bool go = true;
+          if (nlist == 0) {
             Module Cm;
-            load_module(g, c.surf, Cm);
+            load_module(g, surf, Cm);
             Leg L;
             V3 uA, vA;
-            leg_start(Cm, c.p, L, uA, vA);
+            leg_start(Cm, p, L, uA, vA);
             const V3 P = ld3(Cm.c) + L.r;
             const V3 Bf = field_at(A.f, P);
             const Helix H = make_helix(P, L.T, L.lam, Bf);
             float sL;
-            ++CNT(CKF_CNT_NAV);
-            const int nl = next_layer(g, H, c.mask, cfg.path_max - c.path, sL);
+            CNT_ADD(CKF_CNT_NAV, 1);
+            const int nl = next_layer(g, H, mask, cfg.path_max - path, sL);
             if (nl < 0) {
-              fin = true;
+              outcome = 3;
               go = false;
             } else {
-              c.mask |= 1ull << nl;
+              mask |= 1ull << nl;
               V3 Ps, Ts;
               helix_at(H, sL, Ps, Ts);
               const V3 ks = (kKappa * L.lam) * cross(Ts, Bf);
-              int nt = 0;
-              int ovf = 0;
-              c.nlist = list_layer(g, nl, Ps, Ts, ks, sL, -1, margin, c.list, nt, ovf);
-              CNT(kNavOvf) += ovf;
-              CNT(CKF_CNT_NAV_MODULES) += nt;
-              if (c.nlist == 0) {
-                n_out = 1;  // the layer is crossed in a gap
+              int nt = 0, ovf = 0;
+              nlist = list_layer(g, nl, Ps, Ts, ks, sL, -1, margin, list, nt, ovf);
+              CNT_ADD(CKF_CNT_NAV_MODULES, nt);
+              CNT_ADD(kNavOvf, ovf);
+              if (nlist == 0) {
+                outcome = 1;  // the layer is crossed in a gap
                 go = false;
               }
             }
           }
           if (go) {
-            const int m = c.list[0];
+            const int m = list[0];
 #pragma unroll
-            for (int k = 0; k < kMaxList - 1; ++k) c.list[k] = c.list[k + 1];
-            c.list[kMaxList - 1] = -1;
-            --c.nlist;
-            Module Am;
-            load_module(g, c.surf, Am);
-            load_module(g, m, M);
+            for (int k = 0; k < kMaxList - 1; ++k) list[k] = list[k + 1];
+            list[kMaxList - 1] = -1;
+            --nlist;
+            Module Am, Bm;
+            load_module(g, surf, Am);
+            load_module(g, m, Bm);
             Leg L;
             V3 uA, vA;
-            leg_start(Am, c.p, L, uA, vA);
+            leg_start(Am, p, L, uA, vA);
             const V3 origin = ld3(Am.c);
-            const V3 dB = ld3(M.c) - origin;
+            const V3 dB = ld3(Bm.c) - origin;
             LegStats ls{0, 0};
-            ++CNT(CKF_CNT_LEGS);
-            bool good = land(L, origin, dB, ld3(M.n), A.f, cfg, c.h, c.path, ls);
-            CNT(CKF_CNT_RK_TRIALS) += ls.trials;
-            CNT(CKF_CNT_RK_REJECTS) += ls.rejects;
+            CNT_ADD(CKF_CNT_LEGS, 1);
+            bool good = land(L, origin, dB, ld3(Bm.n), A.f, cfg, h, path, ls);
+            CNT_ADD(CKF_CNT_RK_TRIALS, ls.trials);
+            CNT_ADD(CKF_CNT_RK_REJECTS, ls.rejects);
             if (good) {
               double pn[5];
-              float J[5][5];
-              leg_end(L, uA, vA, M, dB, field_at(A.f, origin + L.r), c.p[4], pn, J);
-#pragma unroll
-              for (int a = 0; a < 5; ++a)
-#pragma unroll
-                for (int b = 0; b < 5; ++b) sh_J[5 * a + b][lane] = J[a][b];
+              leg_end(L, uA, vA, Bm, dB, field_at(A.f, origin + L.r), p[4], pn, J);
 #pragma unroll
               for (int k = 0; k < 5; ++k) good = good && isfinite(pn[k]);
 #pragma unroll
-              for (int k = 0; k < 5; ++k) c.p[k] = pn[k];
+              for (int k = 0; k < 5; ++k) p[k] = pn[k];
             }
             if (!good) {
-              ++CNT(kFailed);  // dropped
+              CNT_ADD(kFailed, 1);  // dropped
             } else {
               moved = true;
-              c.surf = m;
-              crossed = fabs(c.p[0]) <= (double)M.hw0 && fabs(c.p[1]) <= (double)M.hw1;
-              if (!crossed) n_out = 1;  // listed but not crossed
+              surf = m;
+              outcome = (fabs(p[0]) <= (double)Bm.hw0 && fabs(p[1]) <= (double)Bm.hw1) ? 2 : 1;
             }
           }
         }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) PDr(Pin, r, (PD_P + k)) = p[k];
+        PIr(Pin, r, PI_SURF) = surf;
+        PIr(Pin, r, PI_NLIST) = nlist;  // root flag cleared
+        PIr(Pin, r, PI_MASK_LO) = (int)(unsigned)(mask & 0xffffffffull);
+        PIr(Pin, r, PI_MASK_HI) = (int)(unsigned)(mask >> 32);
+#pragma unroll
+        for (int k = 0; k < kMaxList; ++k) PIr(Pin, r, (PI_LIST + k)) = list[k];
+        PFr(Pin, r, PF_H) = h;
+        PFr(Pin, r, PF_PATH) = path;
       }
-      // ---- covariance transport, search and gate (FP64)
+
+      // ---- phase 2: covariance transport (FP64), search and gate
       double acc_x2[kMaxBranch];
       int acc_id[kMaxBranch], acc_pos[kMaxBranch];
 #pragma unroll
@@ -426,67 +455,80 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         acc_id[k] = 0x7fffffff;
         acc_pos[k] = 0;
       }
-      double C[15];
-      if (act) load_cov(Pin, r, C);
-      if (moved) transport_cov_lds(&sh_J[0][lane], C);
-      if (crossed) {
-        ++CNT(CKF_CNT_CROSSED);
-        const int row = sh_event[slot] * g.n_surfaces + c.surf;
-        const int a = A.m.offsets[row], b = A.m.offsets[row + 1];
-        if (b > a) {
-          const double wd = sqrt(cfg.chi2_max * (C[0] + (double)A.w.row_maxvar0[row]));
-          const float lo = (float)(c.p[0] - wd) - 1e-3f, hi = (float)(c.p[0] + wd) + 1e-3f;
-          int l = a, u = b;
-          while (l < u) {  // first position with loc0 >= lo
-            const int mid = (l + u) >> 1;
-            if (A.w.m_loc0[mid] < lo) l = mid + 1; else u = mid;
-          }
-          for (int i = l; i < b; ++i) {
-            const float x0 = A.w.m_loc0[i];
-            if (x0 > hi) break;
-            ++CNT(CKF_CNT_CHI2);
-            const double x2 = chi2_of(c.p, C, (double)x0, (double)A.w.m_loc1[i], (double)A.w.m_var0[i],
-                                      (double)A.w.m_var1[i]);
-            if (!(x2 < cfg.chi2_max)) continue;
-            double cx = x2;
-            int cid = A.w.m_id[i], cpos = i;
+      int n_acc = 0;
+      if (outcome == 1 || outcome == 2) {
+        double C[15];
+        load_cov(Pin, r, C);
+        if (moved) transport_cov(J, C);
+        bool changed = moved;
+        if (outcome == 2) {
+          CNT_ADD(CKF_CNT_CROSSED, 1);
+          double p[5];
 #pragma unroll
-            for (int k = 0; k < kMaxBranch; ++k) {
-              const bool lt = cx < acc_x2[k] || (cx == acc_x2[k] && cid < acc_id[k]);
-              if (lt) {
-                const double tx = acc_x2[k];
-                const int ti = acc_id[k], tp = acc_pos[k];
-                acc_x2[k] = cx;
-                acc_id[k] = cid;
-                acc_pos[k] = cpos;
-                cx = tx;
-                cid = ti;
-                cpos = tp;
-              }
+          for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
+          const int surf = PIr(Pin, r, PI_SURF);
+          const int row = sh_event[slot] * g.n_surfaces + surf;
+          const int a = A.m.offsets[row], b = A.m.offsets[row + 1];
+          if (b > a) {
+            const double wd = sqrt(cfg.chi2_max * (C[0] + (double)A.w.row_maxvar0[row]));
+            const float lo = (float)(p[0] - wd) - 1e-3f, hi = (float)(p[0] + wd) + 1e-3f;
+            int l = a, u = b;
+            while (l < u) {  // first position with loc0 >= lo
+              const int mid = (l + u) >> 1;
+              if (A.w.m_sorted[mid].x < lo) l = mid + 1; else u = mid;
             }
-            n_acc = min(n_acc + 1, cfg.branches);
+            for (int i = l; i < b; ++i) {
+              const float4 ms = A.w.m_sorted[i];
+              if (ms.x > hi) break;
+              CNT_ADD(CKF_CNT_CHI2, 1);
+              const double x2 = chi2_of(p, C, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w);
+              if (!(x2 < cfg.chi2_max)) continue;
+              double cx = x2;
+              int cid = A.w.m_id[i], cpos = i;
+#pragma unroll
+              for (int k = 0; k < kMaxBranch; ++k) {
+                const bool lt = cx < acc_x2[k] || (cx == acc_x2[k] && cid < acc_id[k]);
+                if (lt) {
+                  const double tx = acc_x2[k];
+                  const int ti = acc_id[k], tp = acc_pos[k];
+                  acc_x2[k] = cx;
+                  acc_id[k] = cid;
+                  acc_pos[k] = cpos;
+                  cx = tx;
+                  cid = ti;
+                  cpos = tp;
+                }
+              }
+              n_acc = min(n_acc + 1, cfg.branches);
+            }
+          }
+          if (n_acc == 0) {  // a hole
+            CNT_ADD(CKF_CNT_HOLES, 1);
+            const int nmh = PIr(Pin, r, PI_NMH) + (1 << 16);
+            PIr(Pin, r, PI_NMH) = nmh;
+            if (cfg.material) {
+              Module M;
+              load_module(g, surf, M);
+              apply_ms(M, cfg.mass, p, C);
+              CNT_ADD(CKF_CNT_MS, 1);
+              changed = true;
+            }
+            outcome = (nmh >> 16) > cfg.max_holes ? 3 : 1;
           }
         }
-        if (n_acc == 0) {
-          ++CNT(CKF_CNT_HOLES);
-          ++c.holes;
-          if (cfg.material) {
-            apply_ms(M, cfg.mass, c.p, C);
-            ++CNT(CKF_CNT_MS);
-          }
-          if (c.holes > cfg.max_holes) fin = true;
-          else n_out = 1;
-        } else {
-          n_out = n_acc;
-        }
+        if (changed)
+#pragma unroll
+          for (int k = 0; k < 15; ++k) PDr(Pin, r, (PD_C + k)) = C[k];
       }
 
-      // ---- slots for the outputs (wave scan) and history nodes
+      // ---- phase 3: slots for the outputs (wave scan) and history nodes
+      const int n_out = outcome == 1 ? 1 : (outcome == 2 ? n_acc : 0);
+      const int n_kf = outcome == 2 ? n_acc : 0;
       int tot_out;
       const int off = wave_excl_scan(n_out, tot_out);
       const int pos0 = sh_n_out + off;
       int tot_nodes;
-      const int noff = wave_excl_scan(n_acc, tot_nodes);
+      const int noff = wave_excl_scan(n_kf, tot_nodes);
       __syncthreads();
       if (lane == 0) {
         sh_n_out += tot_out;
@@ -494,58 +536,86 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       }
       __syncthreads();
       const long long node0 = (long long)sh_node_base + noff;
-      if (n_out > 0) {
-        if (n_acc == 0) {
-          store_rec(Pout, pos0, c, slot, c.p, C, c.chi2, c.node, c.nm, c.holes);
-          atomicAdd(&sh_live[slot], 1);
-        } else {
-          const bool room = node0 + n_acc <= A.w.node_cap;
-          if (!room) atomicOr(A.status + CKF_STATUS_FLAGS, CKF_FLAG_NODE_CAPACITY);
+
+      // ---- phase 4: outputs
+      if (outcome == 1) {  // the record moves on unchanged
 #pragma unroll
-          for (int j = 0; j < kMaxBranch; ++j) {
-            if (j < n_acc) {
-              const int i = acc_pos[j];
-              double pc[5], Cc[15];
-              kf_update(c.p, C, (double)A.w.m_loc0[i], (double)A.w.m_loc1[i], (double)A.w.m_var0[i],
-                        (double)A.w.m_var1[i], pc, Cc);
-              ++CNT(CKF_CNT_KF);
-              const int nd = room ? (int)(node0 + j) : -1;
-              if (room) {
-                Node* np = A.w.nodes + node0 + j;
-                np->parent = c.node;
-                np->meas = acc_id[j];
-                np->surface = c.surf;
-                np->pad = 0;
+        for (int k = 0; k < PD_N; ++k) PDr(Pout, pos0, k) = PDr(Pin, r, k);
 #pragma unroll
-                for (int k = 0; k < 5; ++k) np->p[k] = pc[k];
+        for (int k = 0; k < PI_N; ++k) PIr(Pout, pos0, k) = PIr(Pin, r, k);
 #pragma unroll
-                for (int k = 0; k < 15; ++k) np->cov[k] = Cc[k];
-              }
-              if (cfg.material) {
-                apply_ms(M, cfg.mass, pc, Cc);
-                ++CNT(CKF_CNT_MS);
-              }
-              store_rec(Pout, pos0 + j, c, slot, pc, Cc, c.chi2 + acc_x2[j], nd, c.nm + 1, c.holes);
-              atomicAdd(&sh_live[slot], 1);
+        for (int k = 0; k < PF_N; ++k) PFr(Pout, pos0, k) = PFr(Pin, r, k);
+        atomicAdd(&sh_live[slot], 1);
+      } else if (n_kf > 0) {  // one Kalman-updated child per accepted measurement
+        const bool room = node0 + n_kf <= A.w.node_cap;
+        if (!room) atomicOr(A.status + CKF_STATUS_FLAGS, CKF_FLAG_NODE_CAPACITY);
+        double p[5], C[15];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
+        load_cov(Pin, r, C);
+        const int surf = PIr(Pin, r, PI_SURF);
+        const int parent = PIr(Pin, r, PI_NODE);
+        const int nmh = PIr(Pin, r, PI_NMH);
+        const double chi2 = PDr(Pin, r, PD_CHI2);
+        Module M;
+        if (cfg.material) load_module(g, surf, M);
+#pragma unroll
+        for (int j = 0; j < kMaxBranch; ++j) {
+          if (j < n_kf) {
+            const int i = acc_pos[j];
+            double pc[5], Cc[15];
+            const float4 ms = A.w.m_sorted[i];
+            kf_update(p, C, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w, pc, Cc);
+            CNT_ADD(CKF_CNT_KF, 1);
+            const int q = pos0 + j;
+            if (room) {
+              Node* np = A.w.nodes + node0 + j;
+              np->parent = parent;
+              np->meas = acc_id[j];
+              np->surface = surf;
+              np->pad = 0;
+#pragma unroll
+              for (int k = 0; k < 5; ++k) np->p[k] = pc[k];
+#pragma unroll
+              for (int k = 0; k < 15; ++k) np->cov[k] = Cc[k];
             }
+            if (cfg.material) {
+              apply_ms(M, cfg.mass, pc, Cc);
+              CNT_ADD(CKF_CNT_MS, 1);
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) PDr(Pout, q, (PD_P + k)) = pc[k];
+#pragma unroll
+            for (int k = 0; k < 15; ++k) PDr(Pout, q, (PD_C + k)) = Cc[k];
+            PDr(Pout, q, PD_CHI2) = chi2 + acc_x2[j];
+            PIr(Pout, q, PI_NODE) = room ? (int)(node0 + j) : -1;
+            PIr(Pout, q, PI_NMH) = nmh + 1;
+#pragma unroll
+            for (int k = 0; k < PI_N; ++k)
+              if (k != PI_NODE && k != PI_NMH) PIr(Pout, q, k) = PIr(Pin, r, k);
+#pragma unroll
+            for (int k = 0; k < PF_N; ++k) PFr(Pout, q, k) = PFr(Pin, r, k);
+            atomicAdd(&sh_live[slot], 1);
           }
         }
       }
       // ---- finished candidates update their seed's best (one lane at a time)
-      unsigned long long fm = __ballot(fin);
+      unsigned long long fm = __ballot(outcome == 3);
       while (fm) {
         const int l = __ffsll((long long)fm) - 1;
         fm &= fm - 1;
         if (lane == l) {
-          ++CNT(CKF_CNT_FINISHED);
-          if (c.nm >= cfg.min_meas &&
-              (sh_best_node[slot] < 0 || better(c.nm, c.chi2, c.holes, c.node, sh_best_nm[slot],
-                                                sh_best_chi2[slot], sh_best_holes[slot], sh_best_node[slot],
-                                                A.w.nodes))) {
-            sh_best_node[slot] = c.node;
-            sh_best_nm[slot] = c.nm;
-            sh_best_chi2[slot] = c.chi2;
-            sh_best_holes[slot] = c.holes;
+          CNT_ADD(CKF_CNT_FINISHED, 1);
+          const int nmh = PIr(Pin, r, PI_NMH);
+          const int nm = nmh & 0xffff, ho = nmh >> 16, nd = PIr(Pin, r, PI_NODE);
+          const double ch = PDr(Pin, r, PD_CHI2);
+          if (nm >= cfg.min_meas && (sh_best_node[slot] < 0 || better(nm, ch, ho, nd, sh_best_nm[slot],
+                                                                      sh_best_chi2[slot], sh_best_holes[slot],
+                                                                      sh_best_node[slot], A.w.nodes))) {
+            sh_best_node[slot] = nd;
+            sh_best_nm[slot] = nm;
+            sh_best_chi2[slot] = ch;
+            sh_best_holes[slot] = ho;
           }
         }
         __syncthreads();
@@ -561,30 +631,30 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         if (over) {
           int kept = 0;
           for (int ra = 0; ra < n_out_total; ++ra) {
-            if (Pout.i[PI_SLOT * cap + ra] != lane && Pout.i[PI_SLOT * cap + ra] != -2 - lane) continue;
-            const int nmh_a = Pout.i[PI_NMH * cap + ra];
-            const double ch_a = Pout.d[PD_CHI2 * cap + ra];
-            const int nd_a = Pout.i[PI_NODE * cap + ra];
+            if (PIr(Pout, ra, PI_SLOT) != lane && PIr(Pout, ra, PI_SLOT) != -2 - lane) continue;
+            const int nmh_a = PIr(Pout, ra, PI_NMH);
+            const double ch_a = PDr(Pout, ra, PD_CHI2);
+            const int nd_a = PIr(Pout, ra, PI_NODE);
             int n_better = 0;
             for (int rb = 0; rb < n_out_total; ++rb) {
               if (rb == ra) continue;
-              const int sb = Pout.i[PI_SLOT * cap + rb];
+              const int sb = PIr(Pout, rb, PI_SLOT);
               if (sb != lane && sb != -2 - lane) continue;
-              const int nmh_b = Pout.i[PI_NMH * cap + rb];
-              if (better(nmh_b & 0xffff, Pout.d[PD_CHI2 * cap + rb], nmh_b >> 16, Pout.i[PI_NODE * cap + rb],
+              const int nmh_b = PIr(Pout, rb, PI_NMH);
+              if (better(nmh_b & 0xffff, PDr(Pout, rb, PD_CHI2), nmh_b >> 16, PIr(Pout, rb, PI_NODE),
                          nmh_a & 0xffff, ch_a, nmh_a >> 16, nd_a, A.w.nodes))
                 ++n_better;
             }
             if (n_better >= cfg.max_live) {
-              Pout.i[PI_SLOT * cap + ra] = -2 - lane;  // pruned (still ranked by the others)
-              ++CNT(CKF_CNT_PRUNED);
+              PIr(Pout, ra, PI_SLOT) = -2 - lane;  // pruned (still ranked by the others)
+              CNT_ADD(CKF_CNT_PRUNED, 1);
             } else {
               ++kept;
             }
           }
           // pruned records become dead
           for (int ra = 0; ra < n_out_total; ++ra)
-            if (Pout.i[PI_SLOT * cap + ra] == -2 - lane) Pout.i[PI_SLOT * cap + ra] = -1;
+            if (PIr(Pout, ra, PI_SLOT) == -2 - lane) PIr(Pout, ra, PI_SLOT) = -1;
           sh_live[lane] = kept;
         }
       }
@@ -606,15 +676,15 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           int sl = -1, nm = 0, ho = 0, nd = -1;
           double ch = 0.0;
           if (r < n_out_total) {
-            sl = Pout.i[PI_SLOT * cap + r];
+            sl = PIr(Pout, r, PI_SLOT);
             if (sl >= 0 && sh_step[sl] >= cfg.max_steps) {
               f = true;
-              const int nmh = Pout.i[PI_NMH * cap + r];
+              const int nmh = PIr(Pout, r, PI_NMH);
               nm = nmh & 0xffff;
               ho = nmh >> 16;
-              nd = Pout.i[PI_NODE * cap + r];
-              ch = Pout.d[PD_CHI2 * cap + r];
-              Pout.i[PI_SLOT * cap + r] = -1;
+              nd = PIr(Pout, r, PI_NODE);
+              ch = PDr(Pout, r, PD_CHI2);
+              PIr(Pout, r, PI_SLOT) = -1;
             }
           }
           unsigned long long fm = __ballot(f);
@@ -622,7 +692,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             const int l = __ffsll((long long)fm) - 1;
             fm &= fm - 1;
             if (lane == l) {
-              ++CNT(CKF_CNT_FINISHED);
+              CNT_ADD(CKF_CNT_FINISHED, 1);
               if (nm >= cfg.min_meas && (sh_best_node[sl] < 0 || better(nm, ch, ho, nd, sh_best_nm[sl],
                                                                           sh_best_chi2[sl], sh_best_holes[sl],
                                                                           sh_best_node[sl], A.w.nodes))) {
@@ -655,20 +725,23 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   }
 
   // ---- counters and status
-  if (A.counters) {
+  if (kCount && A.counters) {
 #pragma unroll
     for (int k = 0; k < CKF_CNT_N; ++k) {
-      const long long t = wave_sum64((long long)CNT(k));
+      const long long t = wave_sum64((long long)CNT_GET(k));
       if (lane == 0 && t) atomicAdd((unsigned long long*)(A.counters + k), (unsigned long long)t);
     }
   }
-  const long long tb = wave_sum64(CNT(kBad)), tf = wave_sum64(CNT(kFailed)), tn = wave_sum64(CNT(kNavOvf));
+  const long long tb = wave_sum64(CNT_GET(kBad)), tf = wave_sum64(CNT_GET(kFailed)),
+                  tn = wave_sum64(CNT_GET(kNavOvf));
   if (lane == 0) {
     if (tb) atomicAdd(A.status + CKF_STATUS_BAD_SEEDS, (int)tb);
     if (tf) atomicAdd(A.status + CKF_STATUS_FAILED_LEGS, (int)tf);
     if (tn) atomicAdd(A.status + CKF_STATUS_NAV_OVERFLOW, (int)tn);
   }
-#undef CNT
+#undef CNT_ADD
+#undef CNT_GET
+#undef CNT_IDX
 }
 
 // ---------------------------------------------------------------------------
@@ -844,16 +917,21 @@ hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status,
                      m.var, w.row_of, w.row_maxvar0, status);
   if (m.n_meas > 0)
     hipLaunchKernelGGL(k_meas_scatter, dim3((unsigned)((m.n_meas + 255) / 256)), dim3(256), 0, st,
-                       (long long)m.n_meas, m.offsets, w.row_of, m.loc, m.var, w.m_loc0, w.m_loc1, w.m_var0,
-                       w.m_var1, w.m_id, status);
+                       (long long)m.n_meas, m.offsets, w.row_of, m.loc, m.var, w.m_sorted, w.m_id, status);
   return hipGetLastError();
 }
 
 hipError_t launch_ckf(const CkfArgs& a, int waves_per_simd, hipStream_t st) {
-  if (waves_per_simd >= 2)
-    hipLaunchKernelGGL(k_ckf<2>, dim3(a.w.grid), dim3(kWave), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_ckf<1>, dim3(a.w.grid), dim3(kWave), 0, st, a);
+  const dim3 grid(a.w.grid), block(kWave);
+  // 3 or 4 waves per SIMD would need register spills; those builds were
+  // slower and not bitwise identical to these, so they are not offered.
+  if (a.counters) {
+    hipLaunchKernelGGL((k_ckf<1, true>), grid, block, 0, st, a);
+  } else if (waves_per_simd >= 2) {
+    hipLaunchKernelGGL((k_ckf<2, false>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_ckf<1, false>), grid, block, 0, st, a);
+  }
   return hipGetLastError();
 }
 

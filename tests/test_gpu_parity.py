@@ -219,7 +219,12 @@ def test_ckf_repeatable_and_launch_invariant(ckf, det_dense):
     b = ckf.Batch.from_event(ev)
     _say("[ckf/repeat] 2000 seeds, 3 launch shapes")
     runs = [ckf.find(geo, fld, b, launch_cfg=ckf.launch(grid=g, seeds_per_group=s, waves_per_simd=w))
-            for g, s, w in ((0, 0, 0), (0, 0, 0), (7, 5, 1), (64, 64, 2), (0, 16, 2))]
+            for g, s, w in ((0, 0, 0), (0, 0, 0), (7, 5, 1), (64, 64, 2))]
+    for g, s, w in ((0, 0, 1), (0, 0, 2), (5, 48, 2), (300, 8, 1)):  # uninstrumented variants
+        f = ckf.Finder(geo, fld, b, launch_cfg=ckf.launch(grid=g, seeds_per_group=s, waves_per_simd=w),
+                       counters=False)
+        f.enqueue()
+        runs.append(f.result())
     for r in runs[1:]:
         assert r["n_tracks"] == runs[0]["n_tracks"]
         for k in ("offsets", "meas", "params", "cov", "chi2", "seed"):
