@@ -84,7 +84,20 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--seeds-per-group", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0, help="kernel register variant: waves per SIMD (1 or 2)")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes_read=4 * n, copy_bytes_written=4 * n, launches=3)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this track finder has no multi-GPU path "
               "(events would be sharded across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
@@ -102,40 +115,63 @@ def main():
     geo = ckf.Geometry(det.as_arrays())
     fld = ckf.UniformField(0.0, 0.0, 2.0)
     b = ckf.Batch.from_event(batch)
-    stream = torch.cuda.current_stream()
+    # launch shape: autotuned on this batch (cached per device/geometry/size/config)
+    from paper_2505_22822_amd import autotune
+    if args.grid or args.seeds_per_group or args.waves:
+        shape = dict(grid=args.grid, seeds_per_group=args.seeds_per_group, waves_per_simd=args.waves)
+    else:
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        shapes = [dict(grid=n_cu * g, seeds_per_group=s, waves_per_simd=2) for g in (8, 16) for s in (24, 32, 48)]
+        shape, table = autotune.tune(geo, fld, b, ckf.config(), shapes=shapes, reps=2, verbose=True,
+                                     use_cache=not args.retune)
+    print(f"# launch shape {shape}", file=sys.stderr, flush=True)
+    lc = lambda timer=None: ckf.launch(shape["grid"], shape["seeds_per_group"], 0, timer, shape["waves_per_simd"])
+
+    stream = torch.cuda.Stream()
     # one run of the instrumented kernel variant counts the work units of the
     # batch (the search is deterministic, so every run does the same work)
-    counting = ckf.Finder(geo, fld, b, ckf.config(), ckf.launch(args.grid, args.seeds_per_group), counters=True)
+    counting = ckf.Finder(geo, fld, b, ckf.config(), lc(), counters=True)
     counting.enqueue(stream)
     rc = counting.result()
     counters = rc["counters"]
     del counting
+    # the kernel's own duration: HIP events the library records around it
     timer = ckf.KernelTimer()
-    finder = ckf.Finder(geo, fld, b, ckf.config(),
-                        ckf.launch(args.grid, args.seeds_per_group, 0, timer, args.waves), counters=False)
-    for _ in range(args.warmup):
-        finder.enqueue(stream)
-    torch.cuda.synchronize()
-    r = finder.result()  # checks the status flags of the warm-up
+    eager = ckf.Finder(geo, fld, b, ckf.config(), lc(timer), counters=False)
+    kernel_ms = []
+    for i in range(args.warmup + args.steps):
+        eager.enqueue(stream)
+        ms = timer.elapsed_ms()
+        if i >= args.warmup:
+            kernel_ms.append(ms)
+    r = eager.result()
     n_tracks = r["n_tracks"]
     assert n_tracks == rc["n_tracks"] and np.array_equal(r["meas"], rc["meas"]), "variants disagree"
+    del eager
+    # the timed region: the hipGraph-captured ckf_find, replayed
+    finder = ckf.Finder(geo, fld, b, ckf.config(), lc(), counters=False)
+    finder.capture(stream)
+    for _ in range(args.warmup):
+        finder.launch_graph(stream)
+    stream.synchronize()
     print(f"# warm-up done: {n_tracks} tracks", file=sys.stderr, flush=True)
-
-    kernel_ms = []
     t_start, t_stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
     for _ in range(args.steps):
-        finder.enqueue(stream)
-        kernel_ms.append(timer.elapsed_ms())  # waits for this step's kernel
+        finder.launch_graph(stream)
     t_stop.record(stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_stop)
-    st = finder.status()
-    assert st[0] == 0, f"device status {st}"
+    rg = finder.result()
+    assert rg["n_tracks"] == n_tracks and np.array_equal(rg["meas"], r["meas"]), "graph replay disagrees"
     ms_per_step = total_ms / args.steps
     value = n_tracks / (ms_per_step * 1e-3)
 
+    cyc = {k: counters.pop(k) for k in ("cycles_leg", "cycles_search", "cycles_out")}
+    tot = max(1, sum(cyc.values()))
+    print("# instrumented run, share of step time per phase: " +
+          ", ".join(f"{k[7:]} {v / tot:.2f}" for k, v in cyc.items()), file=sys.stderr, flush=True)
     f32 = sum(counters[k] * UNIT_FLOPS[k][0] for k in UNIT_FLOPS)
     f64 = sum(counters[k] * UNIT_FLOPS[k][1] for k in UNIT_FLOPS)
     k_ms = float(np.mean(kernel_ms))
@@ -152,8 +188,9 @@ def main():
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
                 config=dict(workload=f"{batch.n_events} x mu={args.mu:g} events, barrel+endcap, 1% X0, 2 T, "
-                                     f"plain CKF", events=batch.n_events, seeds=batch.n_seeds,
-                            measurements=batch.n_meas, tracks=n_tracks),
+                                     f"plain CKF, one hipGraph-captured ckf_find per step",
+                            events=batch.n_events, seeds=batch.n_seeds, measurements=batch.n_meas,
+                            tracks=n_tracks, launch=shape),
                 roofline=roofline, cpu_baseline=cpu, counters=counters)
     print(json.dumps(line))
 

@@ -68,6 +68,7 @@ enum {
 typedef struct ckf_geometry ckf_geometry; /* opaque, device-resident */
 typedef struct ckf_field ckf_field;       /* opaque, device-resident */
 typedef struct ckf_timer ckf_timer;       /* opaque pair of HIP events */
+typedef struct ckf_plan ckf_plan;         /* opaque captured ckf_find (hipGraph) */
 
 /* Host description of a detector, copied by ckf_geometry_create.
  * Modules are planar rectangles: centre c, unit row vectors u (loc0 axis),
@@ -166,6 +167,9 @@ enum {
   CKF_CNT_PRUNED = 10,
   CKF_CNT_FINISHED = 11,
   CKF_CNT_RK_REJECTS = 12,
+  CKF_CNT_CYC_LEG = 13,    /* shader clocks per wave in navigation + leg (instrumented run) */
+  CKF_CNT_CYC_SEARCH = 14, /* ... in covariance transport + search */
+  CKF_CNT_CYC_OUT = 15,    /* ... in output slots, children, finishing */
   CKF_CNT_N = 16
 };
 
@@ -199,6 +203,19 @@ ckf_status ckf_workspace_size(const ckf_geometry* g, const ckf_config* cfg, cons
 ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m,
                     const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch,
                     void* workspace, size_t workspace_bytes, ckf_tracks* out, void* stream);
+
+/* Capture the whole ckf_find sequence for these arguments into a hipGraph
+ * once (capture on `stream`, instantiation: allocates host-side graph
+ * objects), so that repeated calls on the same buffers are one graph launch.
+ * Every argument and buffer must stay valid and unchanged in address while
+ * the plan is used; contents may change between launches.  The plan holds
+ * no timer events (launch->timer is ignored). */
+ckf_status ckf_plan_create(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m,
+                           const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch, void* workspace,
+                           size_t workspace_bytes, ckf_tracks* out, void* stream, ckf_plan** plan);
+/* Replay the captured sequence on `stream` (asynchronous, allocation-free). */
+ckf_status ckf_plan_launch(ckf_plan* plan, void* stream);
+void ckf_plan_destroy(ckf_plan* plan);
 
 /* Component entry points (parity tests of single steps of the method). */
 

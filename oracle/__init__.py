@@ -21,7 +21,7 @@ SRC = [os.path.join(HERE, "oracle.cpp")]
 
 DEFAULT_CONFIG = dict(
     chi2_max=15.0, branches_per_surface=3, max_live_per_seed=10, max_holes=3, min_meas=6,
-    max_steps=48, max_rk_steps=100, step_tol=1e-3, step_max=200.0, land_tol=1e-4,
+    max_steps=48, max_rk_steps=100, step_tol=1e-2, step_max=200.0, land_tol=1e-4,
     path_max=4000.0, nav_margin=1.0, mass=0.1056583755, material_on=1, tracks_per_seed=1)
 
 

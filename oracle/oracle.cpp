@@ -25,7 +25,8 @@
 //            estimate h^2 * max|k1-k2-k3+k4|; accept if <= step_tol; next
 //            trial h * clamp(0.9 (tol/err)^(1/4)) within [0.25, 4].
 //   R-land   each trial step is limited to the distance to the target plane
-//            predicted by the second-order expansion r + dT + d^2 k/2; landed
+//            along the local helix (field at the current point; three Newton
+//            steps from the second-order estimate r + dT + d^2 k/2); landed
 //            when that distance is below land_tol, then moved onto the plane
 //            along T.
 //   R-jac    Jacobian by differentiating each RKN4 stage (tangent columns),
@@ -306,13 +307,62 @@ double plane_distance(V3 r, V3 T, V3 k, V3 c, V3 n) {
   return c0 / q;
 }
 
+// Local helix of a free state about the field at its position (exact
+// trajectory in a uniform field).
+struct Helix {
+  V3 p0, T0, bhat, w;  // w = T0 x bhat
+  double tpar;         // T0 . bhat
+  V3 tperp;            // T0 - tpar bhat
+  double om;           // kappa * q/p * |B|, turning rate about bhat
+  double lam;
+  V3 B;
+  Helix(const Free& f, V3 B_) : p0(f.r), T0(f.T), lam(f.qop), B(B_) {
+    const double bm = norm(B);
+    bhat = bm > 0 ? (1.0 / bm) * B : V3{0, 0, 1};
+    om = kKappa * f.qop * bm;
+    tpar = dot(T0, bhat);
+    tperp = T0 - tpar * bhat;
+    w = cross(T0, bhat);
+  }
+  void at(double s, V3& p, V3& T) const {
+    const double a = om * s;
+    double S, Cc;  // sin(a)/om and (1-cos a)/om, stable for small a
+    if (std::fabs(a) < 1e-4) {
+      S = s * (1.0 - a * a / 6.0);
+      Cc = s * (0.5 * a) * (1.0 - a * a / 12.0);
+    } else {
+      S = std::sin(a) / om;
+      const double hs = std::sin(0.5 * a);
+      Cc = 2.0 * hs * hs / om;
+    }
+    p = p0 + (tpar * s) * bhat + S * tperp + Cc * w;
+    T = tpar * bhat + std::cos(a) * tperp + std::sin(a) * w;
+  }
+};
+
+// Signed path to the plane (c, n) along the local helix: three Newton steps
+// from the second-order estimate.  NaN when the direction grazes the plane.
+double helix_distance(const Field& F, const Free& f, V3 c, V3 n) {
+  const V3 k = (kKappa * f.qop) * cross(f.T, F.at(f.r));
+  double s = plane_distance(f.r, f.T, k, c, n);
+  if (!std::isfinite(s)) return s;
+  const Helix H(f, F.at(f.r));
+  for (int it = 0; it < 3; ++it) {
+    V3 p, T;
+    H.at(s, p, T);
+    const double fp = dot(n, T);
+    if (std::fabs(fp) < 1e-9) return NAN;
+    s -= dot(n, p - c) / fp;
+  }
+  return s;
+}
+
 // Step onto the plane (c, n): RKN4 trials limited by the predicted distance,
 // adaptive step size, landed below land_tol.  h_trial and path are updated.
 bool land(const Field& F, const Cfg& cfg, V3 c, V3 n, Free& f, Tangents& J, double& h_trial,
           double& path, Stats& st) {
   for (int it = 0; it < cfg.max_rk; ++it) {
-    const V3 k = (kKappa * f.qop) * cross(f.T, F.at(f.r));
-    const double d = plane_distance(f.r, f.T, k, c, n);
+    const double d = helix_distance(F, f, c, n);
     if (!std::isfinite(d)) return false;
     if (std::fabs(d) < cfg.land_tol) {
       f.r = f.r + d * f.T;
@@ -448,36 +498,6 @@ void apply_ms(const Surface& S, double mass, const double* p, M5& C) {
 // ---------------------------------------------------------------------------
 // Navigation: local helix, layer envelopes, module listing.
 
-struct Helix {
-  V3 p0, T0, bhat, w;  // w = T0 x bhat
-  double tpar;         // T0 . bhat
-  V3 tperp;            // T0 - tpar bhat
-  double om;           // kappa * q/p * |B|, turning rate about bhat
-  double lam;
-  V3 B;
-  Helix(const Free& f, V3 B_) : p0(f.r), T0(f.T), lam(f.qop), B(B_) {
-    const double bm = norm(B);
-    bhat = bm > 0 ? (1.0 / bm) * B : V3{0, 0, 1};
-    om = kKappa * f.qop * bm;
-    tpar = dot(T0, bhat);
-    tperp = T0 - tpar * bhat;
-    w = cross(T0, bhat);
-  }
-  void at(double s, V3& p, V3& T) const {
-    const double a = om * s;
-    double S, Cc;  // sin(a)/om and (1-cos a)/om, stable for small a
-    if (std::fabs(a) < 1e-4) {
-      S = s * (1.0 - a * a / 6.0);
-      Cc = s * (0.5 * a) * (1.0 - a * a / 12.0);
-    } else {
-      S = std::sin(a) / om;
-      const double hs = std::sin(0.5 * a);
-      Cc = 2.0 * hs * hs / om;
-    }
-    p = p0 + (tpar * s) * bhat + S * tperp + Cc * w;
-    T = tpar * bhat + std::cos(a) * tperp + std::sin(a) * w;
-  }
-};
 
 // Smallest positive path to the cylinder r = R: straight-line root, then
 // Newton on |p_perp(s)|^2 - R^2.  Returns false when there is none.

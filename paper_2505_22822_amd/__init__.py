@@ -198,6 +198,29 @@ class Finder:
                             C.byref(self.cfg), C.byref(self.launch), _ptr(self.workspace),
                             self.workspace.numel(), C.byref(self._tracks), _stream_handle(stream)), "ckf_find")
 
+    def capture(self, stream):
+        """Capture this call into a hipGraph (ckf_plan_create); later
+        launch_graph() replays it.  stream must be a non-default stream."""
+        lib = _abi.load()
+        h = C.c_void_p()
+        _check(lib.ckf_plan_create(self.geometry.handle, self.field.handle, C.byref(self._meas),
+                                   C.byref(self._seeds), C.byref(self.cfg), C.byref(self.launch),
+                                   _ptr(self.workspace), self.workspace.numel(), C.byref(self._tracks),
+                                   _stream_handle(stream), C.byref(h)), "ckf_plan_create")
+        self.plan = h
+
+    def launch_graph(self, stream=None):
+        _check(_abi.load().ckf_plan_launch(self.plan, _stream_handle(stream)), "ckf_plan_launch")
+
+    def __del__(self):
+        h = getattr(self, "plan", None)
+        if h is not None and h.value:
+            try:
+                _abi.load().ckf_plan_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self.plan = None
+
     def status(self):
         return self.out["status"].cpu().numpy()
 

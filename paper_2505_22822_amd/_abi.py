@@ -14,7 +14,8 @@ STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsorted input", 3: "capacit
 FLAG_NODE_CAPACITY, FLAG_OUT_CAPACITY, FLAG_BAD_OFFSETS = 1, 2, 4
 ST_FLAGS, ST_NODES, ST_TRACKS, ST_MEAS, ST_BAD_SEEDS, ST_FAILED_LEGS, ST_NAV_OVF = range(7)
 COUNTER_NAMES = ("steps", "navigations", "nav_modules", "legs", "rk_trials", "chi2_evals", "kf_updates",
-                 "ms_updates", "crossed", "holes", "pruned", "finished", "rk_rejects")
+                 "ms_updates", "crossed", "holes", "pruned", "finished", "rk_rejects", "cycles_leg",
+                 "cycles_search", "cycles_out")
 
 
 class GeometryDesc(C.Structure):
@@ -61,6 +62,10 @@ SIGNATURES = {
                        VP, C.c_size_t, C.POINTER(Tracks), VP]),
     "ckf_propagate_batch": (I32, [VP, VP, C.POINTER(Config), I32, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
     "ckf_kf_update_batch": (I32, [I32, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "ckf_plan_create": (I32, [VP, VP, C.POINTER(Measurements), C.POINTER(Seeds), C.POINTER(Config),
+                              C.POINTER(Launch), VP, C.c_size_t, C.POINTER(Tracks), VP, C.POINTER(VP)]),
+    "ckf_plan_launch": (I32, [VP, VP]),
+    "ckf_plan_destroy": (None, [VP]),
     "ckf_timer_create": (I32, [C.POINTER(VP)]),
     "ckf_timer_destroy": (None, [VP]),
     "ckf_timer_elapsed_ms": (I32, [VP, C.POINTER(F32)]),

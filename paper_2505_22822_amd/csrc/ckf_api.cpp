@@ -26,6 +26,11 @@ struct ckf_timer {
   hipEvent_t start, stop;
 };
 
+struct ckf_plan {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -301,7 +306,7 @@ void ckf_config_default(ckf_config* c) {
   c->min_meas = 6;
   c->max_steps = 48;
   c->max_rk_steps = 100;
-  c->step_tol = 1e-3;
+  c->step_tol = 1e-2;
   c->step_max = 200.0;
   c->land_tol = 1e-4;
   c->path_max = 4000.0;
@@ -473,6 +478,50 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
   }
   HIP_TRY(ckf::launch_output(s->n_seeds, w, s->event, *out, hs), "launch output");
   return CKF_OK;
+}
+
+ckf_status ckf_plan_create(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m,
+                           const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch, void* workspace,
+                           size_t workspace_bytes, ckf_tracks* out, void* stream, ckf_plan** plan) {
+  if (!plan) return fail(CKF_ERR_INVALID_ARGUMENT, "plan_create: NULL plan");
+  *plan = nullptr;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (!hs) return fail(CKF_ERR_INVALID_ARGUMENT, "plan_create: capture needs a non-default stream");
+  ckf_launch l{};
+  if (launch) l = *launch;
+  l.timer = nullptr;
+  HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  const ckf_status st = ckf_find(g, f, m, s, cfg, &l, workspace, workspace_bytes, out, stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(hs, &graph);
+  if (st != CKF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+  ckf_plan* p = new ckf_plan();
+  p->graph = graph;
+  const hipError_t ei = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    delete p;
+    return hip_fail(ei, "hipGraphInstantiate");
+  }
+  *plan = p;
+  return CKF_OK;
+}
+
+ckf_status ckf_plan_launch(ckf_plan* plan, void* stream) {
+  if (!plan || !plan->exec) return fail(CKF_ERR_INVALID_ARGUMENT, "plan_launch: NULL plan");
+  HIP_TRY(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+  return CKF_OK;
+}
+
+void ckf_plan_destroy(ckf_plan* plan) {
+  if (!plan) return;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  delete plan;
 }
 
 ckf_status ckf_timer_create(ckf_timer** out) {

@@ -109,6 +109,62 @@ __device__ __forceinline__ float plane_distance(V3 r, V3 T, V3 k, V3 c, V3 n) {
   return c0 / q;
 }
 
+// ---------------------------------------------------------------------------
+// Navigation: local helix about the field at the current point.
+
+struct Helix {
+  V3 p0, T0, bhat, tperp, w;
+  float tpar, om;
+};
+
+__device__ __forceinline__ Helix make_helix(V3 p, V3 T, float lam, V3 B) {
+  Helix H;
+  const float bm = sqrtf(dot(B, B));
+  H.bhat = bm > 0.f ? (1.0f / bm) * B : V3{0.f, 0.f, 1.f};
+  H.om = kKappa * lam * bm;
+  H.p0 = p;
+  H.T0 = T;
+  H.tpar = dot(T, H.bhat);
+  H.tperp = T - H.tpar * H.bhat;
+  H.w = cross(T, H.bhat);
+  return H;
+}
+
+__device__ __forceinline__ void helix_at(const Helix& H, float s, V3& p, V3& T) {
+  const float a = H.om * s;
+  float S, Cc, sa, ca;
+  sincosf(a, &sa, &ca);
+  if (fabsf(a) < 1e-3f) {
+    S = s * (1.0f - a * a * (1.0f / 6.0f));
+    Cc = s * (0.5f * a) * (1.0f - a * a * (1.0f / 12.0f));
+  } else {
+    const float hs = sinf(0.5f * a);
+    S = sa / H.om;
+    Cc = 2.0f * hs * hs / H.om;
+  }
+  p = H.p0 + (H.tpar * s) * H.bhat + S * H.tperp + Cc * H.w;
+  T = H.tpar * H.bhat + ca * H.tperp + sa * H.w;
+}
+
+// Signed path to the plane (c, n) along the local helix of (r, T, lam) in
+// field B: three Newton steps from the second-order estimate; NaN when the
+// direction grazes the plane.
+__device__ __forceinline__ float helix_distance(V3 r, V3 T, float lam, V3 B, V3 c, V3 n) {
+  const V3 k = (kKappa * lam) * cross(T, B);
+  float s = plane_distance(r, T, k, c, n);
+  if (!isfinite(s)) return s;
+  const Helix H = make_helix(r, T, lam, B);
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    V3 p, Ts;
+    helix_at(H, s, p, Ts);
+    const float fp = dot(n, Ts);
+    if (fabsf(fp) < 1e-9f) return __int_as_float(0x7fc00000);
+    s -= dot(n, p - c) / fp;
+  }
+  return s;
+}
+
 struct LegStats {
   int trials, rejects;
 };
@@ -118,8 +174,7 @@ __device__ bool land(Leg& L, V3 origin, V3 c, V3 n, const FieldDev& F, const Cfg
                      float& path, LegStats& st) {
   for (int it = 0; it < cfg.max_rk; ++it) {
     const V3 B = field_at(F, origin + L.r);
-    const V3 k = (kKappa * L.lam) * cross(L.T, B);
-    const float d = plane_distance(L.r, L.T, k, c, n);
+    const float d = helix_distance(L.r, L.T, L.lam, B, c, n);
     if (!isfinite(d)) return false;
     if (fabsf(d) < cfg.land_tol) {
       L.r = L.r + d * L.T;
@@ -325,43 +380,6 @@ __device__ __forceinline__ void apply_ms(const Module& M, double mass, const dou
   const double t2 = (double)th0 * (double)th0;
   C[pk(2, 2)] += t2 / ((double)st * (double)st);
   C[pk(3, 3)] += t2;
-}
-
-// ---------------------------------------------------------------------------
-// Navigation: local helix about the field at the current point.
-
-struct Helix {
-  V3 p0, T0, bhat, tperp, w;
-  float tpar, om;
-};
-
-__device__ __forceinline__ Helix make_helix(V3 p, V3 T, float lam, V3 B) {
-  Helix H;
-  const float bm = sqrtf(dot(B, B));
-  H.bhat = bm > 0.f ? (1.0f / bm) * B : V3{0.f, 0.f, 1.f};
-  H.om = kKappa * lam * bm;
-  H.p0 = p;
-  H.T0 = T;
-  H.tpar = dot(T, H.bhat);
-  H.tperp = T - H.tpar * H.bhat;
-  H.w = cross(T, H.bhat);
-  return H;
-}
-
-__device__ __forceinline__ void helix_at(const Helix& H, float s, V3& p, V3& T) {
-  const float a = H.om * s;
-  float S, Cc, sa, ca;
-  sincosf(a, &sa, &ca);
-  if (fabsf(a) < 1e-3f) {
-    S = s * (1.0f - a * a * (1.0f / 6.0f));
-    Cc = s * (0.5f * a) * (1.0f - a * a * (1.0f / 12.0f));
-  } else {
-    const float hs = sinf(0.5f * a);
-    S = sa / H.om;
-    Cc = 2.0f * hs * hs / H.om;
-  }
-  p = H.p0 + (H.tpar * s) * H.bhat + S * H.tperp + Cc * H.w;
-  T = H.tpar * H.bhat + ca * H.tperp + sa * H.w;
 }
 
 __device__ bool cross_cylinder(const Helix& H, float R, float& s_out) {

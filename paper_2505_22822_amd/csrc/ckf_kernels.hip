@@ -335,6 +335,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       int outcome = 0;
       bool moved = false;
       float J[5][5];
+      long long t_phase = kCount ? clock64() : 0;
 
       // ---- phase 1: navigation and the propagation leg (FP32); the changed
       // navigation state is written back into the candidate's own record
@@ -446,6 +447,11 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         PFr(Pin, r, PF_PATH) = path;
       }
 
+      if (kCount && lane == 0) {
+        const long long t = clock64();
+        CNT_ADD(CKF_CNT_CYC_LEG, (int)(t - t_phase));
+        t_phase = t;
+      }
       // ---- phase 2: covariance transport (FP64), search and gate
       double acc_x2[kMaxBranch];
       int acc_id[kMaxBranch], acc_pos[kMaxBranch];
@@ -521,6 +527,11 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           for (int k = 0; k < 15; ++k) PDr(Pin, r, (PD_C + k)) = C[k];
       }
 
+      if (kCount && lane == 0) {
+        const long long t = clock64();
+        CNT_ADD(CKF_CNT_CYC_SEARCH, (int)(t - t_phase));
+        t_phase = t;
+      }
       // ---- phase 3: slots for the outputs (wave scan) and history nodes
       const int n_out = outcome == 1 ? 1 : (outcome == 2 ? n_acc : 0);
       const int n_kf = outcome == 2 ? n_acc : 0;
@@ -620,6 +631,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         }
         __syncthreads();
       }
+      if (kCount && lane == 0) CNT_ADD(CKF_CNT_CYC_OUT, (int)(clock64() - t_phase));
     }
     __syncthreads();
     const int n_out_total = sh_n_out;

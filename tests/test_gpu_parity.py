@@ -262,3 +262,32 @@ def test_ckf_edge_cases(ckf, det_dense):
                        b.seed_cov)
     with pytest.raises(ckf.CkfError):
         ckf.find(geo, fld, badoff)
+
+
+def test_graph_replay_equals_eager(ckf, det_dense):
+    """The hipGraph-captured ckf_find, replayed several times with eager
+    calls and synchronisations in between, reproduces the eager result
+    exactly on every replay."""
+    import torch
+    ev = concat_events([make_event(det_dense, 60 + i, mu=m) for i, m in enumerate((30, 80))])
+    geo = ckf.Geometry(det_dense.as_arrays())
+    fld = ckf.UniformField(0, 0, 2.0)
+    b = ckf.Batch.from_event(ev)
+    _say(f"[ckf/graph] {ev.n_seeds} seeds, 3 replays")
+    eager = ckf.Finder(geo, fld, b, counters=False)
+    eager.enqueue()
+    ref = eager.result()
+    g = ckf.Finder(geo, fld, b, counters=False)
+    s = torch.cuda.Stream()
+    g.capture(s)
+    for rep in range(3):
+        for k in ("meas", "params", "n_tracks"):
+            g.out[k].zero_()
+        g.launch_graph(s)
+        s.synchronize()
+        got = g.result()
+        assert got["n_tracks"] == ref["n_tracks"], rep
+        for k in ("offsets", "meas", "params", "cov", "chi2", "seed", "event", "holes"):
+            assert np.array_equal(got[k], ref[k]), (rep, k)
+        eager.enqueue()  # eager work between replays
+        torch.cuda.synchronize()

@@ -80,8 +80,8 @@ def test_helix_closed_form_tight(oracle_lib, B):
 
 
 def test_helix_production_tolerance(oracle_lib):
-    """Default controller (step_tol 1e-3 mm): position error below 1e-3 mm
-    per metre for 0.5-10 GeV tracks."""
+    """Default controller (step_tol 1e-2 mm on the error estimate): true
+    position error below 1e-3 mm per metre for 0.5-10 GeV tracks."""
     rng = np.random.default_rng(11)
     worst = 0.0
     for _ in range(40):
