@@ -168,10 +168,12 @@ def main():
     ms_per_step = total_ms / args.steps
     value = n_tracks / (ms_per_step * 1e-3)
 
-    cyc = {k: counters.pop(k) for k in ("cycles_leg", "cycles_search", "cycles_out")}
-    tot = max(1, sum(cyc.values()))
-    print("# instrumented run, share of step time per phase: " +
-          ", ".join(f"{k[7:]} {v / tot:.2f}" for k, v in cyc.items()), file=sys.stderr, flush=True)
+    cyc = {k: counters.pop(k) for k in ("cycles_leg", "cycles_search", "cycles_out", "cycles_nav", "cycles_step")}
+    tot = max(1, cyc["cycles_step"])
+    print("# instrumented run, share of step time: phase1 (nav+leg) {:.2f}, search {:.2f}, out {:.2f}; "
+          "lane-average navigation time / phase1 {:.2f}".format(
+              cyc["cycles_leg"] / tot, cyc["cycles_search"] / tot, cyc["cycles_out"] / tot,
+              cyc["cycles_nav"] / 64.0 / max(1, cyc["cycles_leg"])), file=sys.stderr, flush=True)
     f32 = sum(counters[k] * UNIT_FLOPS[k][0] for k in UNIT_FLOPS)
     f64 = sum(counters[k] * UNIT_FLOPS[k][1] for k in UNIT_FLOPS)
     k_ms = float(np.mean(kernel_ms))

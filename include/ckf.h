@@ -148,7 +148,7 @@ typedef struct ckf_tracks {
   int32_t* event;            /* [cap_tracks] */
   int32_t* last_surface;     /* [cap_tracks] module of the last measurement */
   int32_t* status;           /* [8] CKF_STATUS_* words */
-  int64_t* counters;         /* [16] or NULL: work-unit counters (see ckf_counter) */
+  int64_t* counters;         /* [24] or NULL: work-unit counters (CKF_CNT_*) */
 } ckf_tracks;
 
 /* Work-unit counters accumulated into tracks->counters when it is not NULL
@@ -167,10 +167,12 @@ enum {
   CKF_CNT_PRUNED = 10,
   CKF_CNT_FINISHED = 11,
   CKF_CNT_RK_REJECTS = 12,
-  CKF_CNT_CYC_LEG = 13,    /* shader clocks per wave in navigation + leg (instrumented run) */
+  CKF_CNT_CYC_LEG = 13,    /* shader clocks per wave in the propagation leg (instrumented run) */
   CKF_CNT_CYC_SEARCH = 14, /* ... in covariance transport + search */
   CKF_CNT_CYC_OUT = 15,    /* ... in output slots, children, finishing */
-  CKF_CNT_N = 16
+  CKF_CNT_CYC_NAV = 16,    /* ... in navigation (next layer, module listing) */
+  CKF_CNT_CYC_STEP = 17,   /* ... per whole step including admission, pruning, publishing */
+  CKF_CNT_N = 24
 };
 
 /* Launch shape of ckf_find (chosen by the autotuner or the caller). */

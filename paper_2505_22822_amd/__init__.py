@@ -180,7 +180,7 @@ class Finder:
                         params=z((n, 5), torch.float64), cov=z((n, 15), torch.float64), chi2=z(n, torch.float64),
                         ndf=z(n, torch.int32), holes=z(n, torch.int32), seed=z(n, torch.int32),
                         event=z(n, torch.int32), last_surface=z(n, torch.int32), status=z(8, torch.int32),
-                        counters=z(16, torch.int64) if counters else None)
+                        counters=z(24, torch.int64) if counters else None)
         o = self.out
         self._tracks = _abi.Tracks(n, cap_m, *(_ptr(o[k]) for k in
                                               ("n_tracks", "offsets", "meas", "params", "cov", "chi2", "ndf",

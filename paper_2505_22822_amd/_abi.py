@@ -15,7 +15,7 @@ FLAG_NODE_CAPACITY, FLAG_OUT_CAPACITY, FLAG_BAD_OFFSETS = 1, 2, 4
 ST_FLAGS, ST_NODES, ST_TRACKS, ST_MEAS, ST_BAD_SEEDS, ST_FAILED_LEGS, ST_NAV_OVF = range(7)
 COUNTER_NAMES = ("steps", "navigations", "nav_modules", "legs", "rk_trials", "chi2_evals", "kf_updates",
                  "ms_updates", "crossed", "holes", "pruned", "finished", "rk_rejects", "cycles_leg",
-                 "cycles_search", "cycles_out")
+                 "cycles_search", "cycles_out", "cycles_nav", "cycles_step")
 
 
 class GeometryDesc(C.Structure):

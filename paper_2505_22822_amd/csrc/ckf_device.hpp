@@ -469,6 +469,42 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
     ls[q] = INFINITY;
     lm[q] = -1;
   }
+  // listing test of one candidate module; keeps the kMaxList smallest (path,
+  // id) in sorted order, each module once (it may sit in two cells)
+  auto consider = [&](int m, const Module& M) {
+    const V3 c = ld3(M.c), nn = ld3(M.n);
+    const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
+    const V3 dc = c - P;
+    if (sqrtf(dot(dc, dc)) > hd + kReach) return;
+    ++n_tested;
+    const float qa = 0.5f * dot(nn, k), qb = dot(nn, T), c0 = dot(nn, P - c);
+    if (fabsf(qb) < 1e-3f) return;
+    float d = -c0 / qb;
+    const float disc = qb * qb - 4.0f * qa * c0;
+    if (disc >= 0.f) {
+      const float qq = -0.5f * (qb + copysignf(sqrtf(disc), qb));
+      if (qq != 0.f) d = c0 / qq;
+    }
+    const V3 X = P + d * T + (0.5f * d * d) * k - c;
+    const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
+    if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) return;
+    float cs = s_base + d;
+    if (!(cs > 0.f)) return;
+    if (lm[0] == m || lm[1] == m || lm[2] == m || lm[3] == m) return;
+    int cm = m;
+#pragma unroll
+    for (int q = 0; q < kMaxList; ++q) {
+      const bool lt = cs < ls[q] || (cs == ls[q] && cm < lm[q]);
+      if (lt) {
+        const float ts = ls[q];
+        const int tm = lm[q];
+        ls[q] = cs;
+        lm[q] = cm;
+        cs = ts;
+        cm = tm;
+      }
+    }
+  };
   int visited = 0;
   for (int ipr = ip0; ipr <= ip1; ++ipr) {
     int ip = ipr % Lr.nphi;
@@ -476,49 +512,20 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
     for (int iw = iw0; iw <= iw1; ++iw) {
       const int cell = Lr.cell_base + ip * Lr.nw + iw;
       const int a = g.cell_off[cell], b = g.cell_off[cell + 1];
-      for (int q = a; q < b; ++q) {
-        const int m = g.cell_mod[q];
-        if (m == exclude) continue;
-        if (++visited > kMaxCand) {
+      // two candidates per round: their id and record loads are in flight together
+      for (int q = a; q < b; q += 2) {
+        if (visited >= kMaxCand) {
           overflow = 1;
-          continue;
+          break;
         }
-        Module M;
-        load_module(g, m, M);
-        const V3 c = ld3(M.c), nn = ld3(M.n);
-        const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
-        const V3 dc = c - P;
-        if (sqrtf(dot(dc, dc)) > hd + kReach) continue;
-        ++n_tested;
-        const float qa = 0.5f * dot(nn, k), qb = dot(nn, T), c0 = dot(nn, P - c);
-        if (fabsf(qb) < 1e-3f) continue;
-        float d = -c0 / qb;
-        const float disc = qb * qb - 4.0f * qa * c0;
-        if (disc >= 0.f) {
-          const float qq = -0.5f * (qb + copysignf(sqrtf(disc), qb));
-          if (qq != 0.f) d = c0 / qq;
-        }
-        const V3 X = P + d * T + (0.5f * d * d) * k - c;
-        const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
-        if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) continue;
-        float cs = s_base + d;
-        if (!(cs > 0.f)) continue;
-        // a module found in two cells is listed once; keep the kMaxList
-        // smallest (path, id) in sorted order
-        if (lm[0] == m || lm[1] == m || lm[2] == m || lm[3] == m) continue;
-        int cm = m;
-#pragma unroll
-        for (int q = 0; q < kMaxList; ++q) {
-          const bool lt = cs < ls[q] || (cs == ls[q] && cm < lm[q]);
-          if (lt) {
-            const float ts = ls[q];
-            const int tm = lm[q];
-            ls[q] = cs;
-            lm[q] = cm;
-            cs = ts;
-            cm = tm;
-          }
-        }
+        visited += 2;
+        const int m0 = g.cell_mod[q];
+        const int m1 = q + 1 < b ? g.cell_mod[q + 1] : -1;
+        Module M0, M1;
+        load_module(g, m0, M0);
+        if (m1 >= 0) load_module(g, m1, M1);
+        if (m0 != exclude) consider(m0, M0);
+        if (m1 >= 0 && m1 != exclude) consider(m1, M1);
       }
     }
   }

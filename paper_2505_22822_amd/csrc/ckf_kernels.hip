@@ -225,9 +225,21 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   __shared__ unsigned long long sh_node_base;
   __shared__ int sh_cnt[kCount ? CKF_CNT_N + 3 : 3][kWave];  // per-lane counters (kept out of registers)
 
-  const GeomDev& g = A.g;
+  __shared__ LayerRec sh_layers[kMaxLayers];
+  __shared__ int sh_order[3][kMaxLayers];
+
   const CfgDev& cfg = A.cfg;
   const int lane = lane_id();
+  // the per-layer navigation tables are small: keep them in LDS
+  GeomDev g = A.g;
+  if (lane < g.n_layers) sh_layers[lane] = A.g.layers[lane];
+  if (lane < g.n_barrel) sh_order[0][lane] = A.g.barrel_order[lane];
+  if (lane < g.n_disk_pos) sh_order[1][lane] = A.g.disk_pos[lane];
+  if (lane < g.n_disk_neg) sh_order[2][lane] = A.g.disk_neg[lane];
+  g.layers = sh_layers;
+  g.barrel_order = sh_order[0];
+  g.disk_pos = sh_order[1];
+  g.disk_neg = sh_order[2];
   const int S = A.w.seeds_per_group;
   const int cap = A.w.pool_cap;
   const float margin = cfg.nav_margin;
@@ -322,6 +334,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
     }
 
     // ---- one step of every live candidate
+    const long long t_step = kCount ? clock64() : 0;
     sh_live[lane] = 0;
     if (lane == 0) sh_n_out = 0;
     __syncthreads();
@@ -354,6 +367,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
 #pragma unroll
         for (int k = 0; k < kMaxList; ++k) list[k] = PIr(Pin, r, (PI_LIST + k));
         float h = PFr(Pin, r, PF_H), path = PFr(Pin, r, PF_PATH);
+        long long t_nav = kCount ? clock64() : 0;
         if (root) {
           Module M;
           load_module(g, surf, M);
@@ -398,6 +412,11 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
                 go = false;
               }
             }
+          }
+          if (kCount) {  // navigation time of this lane (summed over lanes, divided later)
+            const long long t = clock64();
+            CNT_ADD(CKF_CNT_CYC_NAV, (int)(t - t_nav));
+            t_nav = t;
           }
           if (go) {
             const int m = list[0];
@@ -452,6 +471,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         CNT_ADD(CKF_CNT_CYC_LEG, (int)(t - t_phase));
         t_phase = t;
       }
+      if (kCount) __syncthreads();
       // ---- phase 2: covariance transport (FP64), search and gate
       double acc_x2[kMaxBranch];
       int acc_id[kMaxBranch], acc_pos[kMaxBranch];
@@ -732,6 +752,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       sh_seed[lane] = -1;
     }
     __syncthreads();
+    if (kCount && lane == 0) CNT_ADD(CKF_CNT_CYC_STEP, (int)(clock64() - t_step));
     cur = 1 - cur;
     n_in = n_out_total;
   }
