@@ -69,7 +69,7 @@ class _Tracks(C.Structure):
                 ("n_meas_total", C.c_int32), ("offsets", C.c_void_p), ("meas", C.c_void_p),
                 ("params", C.c_void_p), ("cov", C.c_void_p), ("chi2", C.c_void_p), ("ndf", C.c_void_p),
                 ("holes", C.c_void_p), ("seed", C.c_void_p), ("event", C.c_void_p),
-                ("last_surface", C.c_void_p)]
+                ("last_surface", C.c_void_p), ("meas_surface", C.c_void_p), ("meas_params", C.c_void_p)]
 
 
 _STAT_NAMES = ("steps", "navigations", "nav_modules", "legs", "legs_failed", "rk_trials", "rk_rejects",
@@ -152,19 +152,22 @@ def ckf_find(inp: Inputs, n_threads=0, cap_tracks=None, cap_meas=None, **cfg):
                params=np.zeros((cap_t, 5)), cov=np.zeros((cap_t, 15)), chi2=np.zeros(cap_t),
                ndf=np.zeros(cap_t, np.int32), holes=np.zeros(cap_t, np.int32),
                seed=np.zeros(cap_t, np.int32), event=np.zeros(cap_t, np.int32),
-               last_surface=np.zeros(cap_t, np.int32))
+               last_surface=np.zeros(cap_t, np.int32), meas_surface=np.zeros(cap_m, np.int32),
+               meas_params=np.zeros((cap_m, 5)))
     tr = _Tracks(cap_t, cap_m, 0, 0, *(_p(out[k]) for k in
                                         ("offsets", "meas", "params", "cov", "chi2", "ndf", "holes",
-                                         "seed", "event", "last_surface")))
+                                         "seed", "event", "last_surface", "meas_surface", "meas_params")))
     st = _Stats()
     rc = lib().orc_ckf_find(C.byref(inp.geom), C.byref(inp.field), C.byref(inp.meas), C.byref(inp.seeds),
                             C.byref(conf), int(n_threads), C.byref(tr), C.byref(st))
     if rc != 0:
         raise RuntimeError(f"orc_ckf_find failed with status {rc} (tracks {tr.n_tracks}, meas {tr.n_meas_total})")
     nt, nm = tr.n_tracks, tr.n_meas_total
-    res = {k: v[:nt] for k, v in out.items() if k not in ("offsets", "meas")}
+    per_meas = ("meas", "meas_surface", "meas_params")
+    res = {k: v[:nt] for k, v in out.items() if k != "offsets" and k not in per_meas}
     res["offsets"] = out["offsets"][:nt + 1]
-    res["meas"] = out["meas"][:nm]
+    for k in per_meas:
+        res[k] = out[k][:nm]
     res["n_tracks"] = nt
     res["stats"] = {k: int(getattr(st, k)) for k in _STAT_NAMES}
     return res

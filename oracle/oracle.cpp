@@ -634,6 +634,8 @@ struct Cand {
   int n_meas = 0, holes = 0;
   double chi2 = 0;
   std::vector<int> ids;
+  std::vector<int> id_surface;              // module of each measurement
+  std::vector<std::array<double, 5>> id_p;  // filtered parameters after each measurement
   int snap_surface = -1;
   double snap_p[5] = {0, 0, 0, 0, 0};
   M5 snap_C{};
@@ -736,6 +738,8 @@ void step_candidate(const Geometry& G, const Field& F, const Cfg& cfg, const orc
     ch.n_meas += 1;
     ch.chi2 += a.chi2;
     ch.ids.push_back(i);
+    ch.id_surface.push_back(ch.surface);
+    ch.id_p.push_back({po[0], po[1], po[2], po[3], po[4]});
     ch.snap_surface = ch.surface;
     std::memcpy(ch.snap_p, ch.p, sizeof ch.p);
     ch.snap_C = ch.C;
@@ -841,7 +845,11 @@ extern "C" int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc
   out->offsets[0] = 0;
   for (int k = 0; k < n; ++k)
     for (const Cand& t : res[k].tracks) {
-      for (int id : t.ids) out->meas[im++] = id;
+      for (size_t q = 0; q < t.ids.size(); ++q) {
+        if (out->meas_surface) out->meas_surface[im] = t.id_surface[q];
+        if (out->meas_params) std::memcpy(out->meas_params + 5 * im, t.id_p[q].data(), 5 * sizeof(double));
+        out->meas[im++] = t.ids[q];
+      }
       out->offsets[it + 1] = im;
       std::memcpy(out->params + 5 * it, t.snap_p, 5 * sizeof(double));
       pack(t.snap_C, out->cov + 15 * it);

@@ -95,6 +95,8 @@ typedef struct orc_tracks {
   int32_t* seed;
   int32_t* event;
   int32_t* last_surface;
+  int32_t* meas_surface;    /* [cap_meas] or NULL: module of each measurement */
+  double* meas_params;      /* [cap_meas][5] or NULL: filtered parameters after each measurement */
 } orc_tracks;
 
 typedef struct orc_stats {

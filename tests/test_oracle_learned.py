@@ -1,0 +1,234 @@
+"""Pins of the oracle's learned-proposal pieces (no GPU): the network's
+gradient against central finite differences and closed forms, Adam against
+its closed form for a constant gradient, bf16 rounding against exact
+values, the network wiring against a hand-built network, and the neighbour
+table against truth trajectories and geometric invariants."""
+import numpy as np
+import pytest
+
+from oracle import learned as OL
+
+
+def _rand_problem(n=24, seed=3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = OL.init_params(seed).astype(np.float64)
+    params[OL.N_PARAMS - 32:] = rng.normal(0, 0.1, 32)  # non-zero output biases
+    P = OL.unpack_params(params)
+    P["b1"][:] = rng.normal(0, 0.1, 64)
+    P["b2"][:] = rng.normal(0, 0.1, 64)
+    params = OL.pack_params(P)
+    x = rng.normal(0, 1, (n, 7))
+    labels = rng.integers(0, 32, n).astype(np.int32)
+    return params, x, labels
+
+
+def test_gradient_matches_central_differences():
+    params, x, labels = _rand_problem()
+    loss, g = OL.loss_and_grad(params, x, labels)
+    rng = np.random.Generator(np.random.PCG64(7))
+    idx = np.concatenate([rng.choice(OL.N_PARAMS, 300, replace=False), np.arange(OL.N_PARAMS - 32, OL.N_PARAMS)])
+    h = 1e-6
+    for i in idx:
+        pp, pm = params.copy(), params.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (OL.loss_and_grad(pp, x, labels)[0] - OL.loss_and_grad(pm, x, labels)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(abs(g[i]), 1e-3), (i, fd, g[i])
+    assert np.isfinite(loss) and loss > 0
+
+
+def test_output_layer_closed_form():
+    """With W3 = 0 every row's logits are b3: the loss is logsumexp(b3) minus
+    the mean of b3 at the labels, the b3 gradient is softmax(b3) minus the
+    label frequencies, and nothing below the output layer gets a gradient."""
+    params, x, labels = _rand_problem(n=40)
+    P = OL.unpack_params(params)
+    P["W3"][:] = 0.0
+    beta = np.linspace(-1.0, 2.0, 32)
+    P["b3"][:] = beta
+    params = OL.pack_params(P)
+    loss, g = OL.loss_and_grad(params, x, labels)
+    e = np.exp(beta - beta.max())
+    soft = e / e.sum()
+    lse = beta.max() + np.log(e.sum())
+    assert abs(loss - (lse - beta[labels].mean())) < 1e-12
+    freq = np.bincount(labels, minlength=32) / len(labels)
+    G = OL.unpack_params(g)
+    np.testing.assert_allclose(G["b3"], soft - freq, atol=1e-14)
+    for k in ("W1", "b1", "W2", "b2"):
+        assert np.all(G[k] == 0.0), k
+
+
+def test_adam_constant_gradient_closed_form():
+    """For a constant gradient the bias-corrected moments are exactly g and
+    g^2, so every step moves each parameter by lr * g / (|g| + eps)."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    p0 = rng.normal(0, 1, 50)
+    g = rng.normal(0, 1e-2, 50)
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for k in range(1, 6):
+        p, m, v = OL.adam_step(p, m, v, g, k, lr=1e-3)
+    np.testing.assert_allclose(p, p0 - 5 * 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-13)
+
+
+def test_bf16_rounding_exact_values():
+    one = 1.0
+    u = 2.0 ** -7  # bf16 spacing at 1
+    vals = np.array([one, one + u / 2, one + 3 * u / 2, one + u / 4, -2.0 - u, 3.0e38, 1.5e-39], np.float64)
+    got = OL.bf16_round(vals)
+    assert got[0] == 1.0
+    assert got[1] == 1.0             # halfway, ties to the even mantissa
+    assert got[2] == one + 2 * u     # halfway, ties up to even
+    assert got[3] == 1.0
+    assert got[4] == -2.0            # spacing at 2 is 2u: -2 - u is halfway, even is -2
+    assert np.isfinite(got[5]) and abs(got[5] / 3.0e38 - 1) < 2 ** -8
+    assert abs(got[6] - 1.5e-39) <= 2.0 ** -133  # subnormal keeps 16 bits
+
+
+def test_forward_wiring_hand_built_network():
+    """W1 and W3 pick the first seven inputs and W2 is the identity, so the
+    first seven logits are relu(x) + b3 and the rest are b3."""
+    P = OL.unpack_params(np.zeros(OL.N_PARAMS))
+    P["W1"][:7, :7] = np.eye(7)
+    P["W2"][:] = np.eye(64)
+    P["W3"][:7, :7] = np.eye(7)
+    P["b3"][:] = np.arange(32) * 0.5
+    params = OL.pack_params(P)
+    x = np.array([[0.5, -1.0, 2.0, -0.25, 3.0, 0.0, 1.25], [-2.0, 1.0, -1.0, 4.0, -3.0, 0.75, -0.5]])
+    z = OL.forward(params, x)
+    want = np.tile(np.arange(32) * 0.5, (2, 1))
+    want[:, :7] += np.maximum(x, 0.0)
+    np.testing.assert_array_equal(z, want)
+    np.testing.assert_array_equal(OL.forward(params, x, bf16=True), want)  # all values exact in bf16
+
+
+def test_top3_order_and_mass():
+    z = np.array([[0.0, 3.0, 1.0, 3.0, -1.0] + [-50.0] * 27])
+    idx, mass = OL.top3(z)
+    assert list(idx[0]) == [1, 3, 2]  # tie 1 vs 3 by index
+    e = np.exp(z[0] - 3.0)
+    assert abs(mass[0] - (e[1] + e[3] + e[2]) / e.sum()) < 1e-15
+
+
+@pytest.fixture(scope="module")
+def tiny_truth():
+    from synth import barrel10, make_event
+    det = barrel10()
+    ev = make_event(det, 1, kind="tiny")
+    return det, ev
+
+
+def test_neighbour_table_covers_truth_transitions(tiny_truth):
+    """Particles from the origin (tiny event, pT 1-10 GeV): every layer change
+    of the truth trajectory goes to a layer listed as next for the module it
+    leaves, and to one of that layer's 32 listed modules."""
+    det, ev = tiny_truth
+    g = det.as_arrays()
+    tr = ev.truth
+    layer = g["layer"]
+    mods = np.unique(tr.surface)
+    nxt, nbr, anchors = OL.neighbour_table(g, modules=mods)
+    row = {int(m): i for i, m in enumerate(mods)}
+    n = ok = 0
+    for k in range(len(tr.particle) - 1):
+        if tr.particle[k] != tr.particle[k + 1]:
+            continue
+        m, m2 = int(tr.surface[k]), int(tr.surface[k + 1])
+        if layer[m] == layer[m2]:
+            continue
+        n += 1
+        i = row[m]
+        s = np.nonzero(nxt[i] == layer[m2])[0]
+        ok += len(s) > 0 and m2 in nbr[i, s[0]]
+    assert n > 500 and ok / n >= 0.995, (ok, n)
+
+
+def test_neighbour_table_invariants():
+    from synth import barrel_endcap
+    det = barrel_endcap()
+    g = det.as_arrays()
+    rng = np.random.Generator(np.random.PCG64(5))
+    mods = rng.choice(g["center"].shape[0], 400, replace=False)
+    nxt, nbr, anchors = OL.neighbour_table(g, modules=mods)
+    layer = g["layer"]
+    c = g["center"].astype(np.float64)
+    for i, m in enumerate(mods):
+        for s in range(OL.MAX_NEXT):
+            L = nxt[i, s]
+            if L < 0:
+                assert np.all(nbr[i, s] == -1)
+                continue
+            assert L != layer[m]
+            X = anchors[i, s]
+            if g["layer_type"][L] == 0:
+                assert abs(np.hypot(X[0], X[1]) - g["layer_pos"][L]) < 1e-9
+            else:
+                assert abs(X[2] - g["layer_pos"][L]) < 1e-9
+            # anchor further out along its ray than the module
+            assert np.linalg.norm(X) > np.linalg.norm(c[m]) - np.hypot(*g["half"][m])
+            ids = nbr[i, s][nbr[i, s] >= 0]
+            assert len(ids) == min(32, int((layer == L).sum()))
+            assert np.all(layer[ids] == L)
+            d = np.linalg.norm(c[ids] - X, axis=1)
+            assert np.all(np.diff(d) >= -1e-9)
+            rest = np.setdiff1d(np.nonzero(layer == L)[0], ids)
+            if len(rest):
+                assert np.linalg.norm(c[rest] - X, axis=1).min() >= d.max() - 1e-9
+
+
+def test_features_definition():
+    from synth import barrel_endcap
+    det = barrel_endcap()
+    g = det.as_arrays()
+    rng = np.random.Generator(np.random.PCG64(9))
+    surf = rng.integers(0, g["center"].shape[0], 50)
+    p = np.column_stack([rng.uniform(-10, 10, 50), rng.uniform(-30, 30, 50), rng.uniform(-3, 3, 50),
+                         rng.uniform(0.2, 2.9, 50), rng.uniform(-2, 2, 50)])
+    x = OL.features(g, surf, p, np.full(50, 5))
+    np.testing.assert_allclose(x[:, 0], p[:, 0] / 10)
+    np.testing.assert_allclose(x[:, 1], p[:, 1] / 30)
+    np.testing.assert_allclose(np.linalg.norm(x[:, 2:5], axis=1), 1.0, atol=1e-12)
+    np.testing.assert_allclose(x[:, 5], p[:, 4])
+    np.testing.assert_allclose(x[:, 6], 5 / g["layer_type"].shape[0])
+    # a module frame equal to the global axes gives the global direction
+    g2 = dict(g)
+    rot = g["rot"].copy()
+    rot[surf[0]] = np.eye(3, dtype=np.float32).reshape(-1)
+    g2["rot"] = rot
+    x0 = OL.features(g2, surf[:1], p[:1], [5])[0]
+    ph, th = p[0, 2], p[0, 3]
+    np.testing.assert_allclose(x0[2:5], [np.cos(ph) * np.sin(th), np.sin(ph) * np.sin(th), np.cos(th)], atol=1e-15)
+
+
+def test_pairs_from_oracle_tracks(tiny_truth):
+    """Pairs taken from the oracle's own tracks on the tiny event: the label
+    points at the module of the next measurement, the state is that of the
+    measurement the pair starts from, and the per-measurement states end in
+    the track's output state."""
+    import oracle
+    det, ev = tiny_truth
+    g = det.as_arrays()
+    inp = oracle.Inputs(g, (0, 0, 2.0), ev)
+    r = oracle.ckf_find(inp, material_on=0)
+    off, ms, mp = r["offsets"], r["meas_surface"], r["meas_params"]
+    assert r["n_tracks"] > 90
+    np.testing.assert_array_equal(mp[off[1:] - 1], r["params"])
+    np.testing.assert_array_equal(ms[off[1:] - 1], r["last_surface"])
+    mods = np.unique(ms)
+    sub_nxt, sub_nbr, _ = OL.neighbour_table(g, modules=mods)
+    n_mod = g["center"].shape[0]
+    nxt = np.full((n_mod, OL.MAX_NEXT), -1, np.int32)
+    nbr = np.full((n_mod, OL.MAX_NEXT, OL.K_NEIGH), -1, np.int32)
+    nxt[mods], nbr[mods] = sub_nxt, sub_nbr
+    x, lab, trk, pos, dropped = OL.capture_pairs(g, nxt, nbr, off, ms, mp)
+    layer = g["layer"]
+    changes = sum(int(layer[ms[i]] != layer[ms[i + 1]]) for t in range(len(off) - 1)
+                  for i in range(off[t], off[t + 1] - 1))
+    # drops: the next measurement lies beyond a hole, on a layer that is not next
+    assert len(lab) + dropped == changes and dropped <= 0.03 * changes
+    for k in range(len(lab)):
+        m, m2 = ms[pos[k]], ms[pos[k] + 1]
+        s = list(nxt[m]).index(layer[m2])
+        assert nbr[m, s, lab[k]] == m2
+        assert off[trk[k]] <= pos[k] < off[trk[k] + 1] - 1
+    np.testing.assert_array_equal(x, OL.features(g, ms[pos], mp[pos], layer[ms[pos + 1]]))
