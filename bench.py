@@ -1,15 +1,23 @@
-"""Throughput of CKF track finding on one MI355X.
+"""Throughput of CKF track finding on one MI355X: learned proposal vs plain.
 
 Workload: a batch of 64 synthetic mu = 200 events (about 10k seeds and 80k
 measurements each) in the barrel + endcap detector with 1 % X0 per module
 and a uniform 2 T field, found in one persistent launch.  A step is one
-ckf_find over the whole batch with inputs already resident in HBM.
+ckf_find over the whole batch with inputs already resident in HBM, replayed
+from a hipGraph.
 
-Prints one JSON line: tracks/s (output tracks / device time), the roofline
-object of the dominant kernel (k_ckf: algorithmic FP32 + FP64 work from the
-kernel's own work-unit counters, over its average duration measured with
-HIP events on its stream), and the oracle timed on the host's cores on a
-bounded sample of the same events.
+Both forms of the search run on the same batch: the plain geometric
+navigation, and the learned form, whose next-module network is trained on
+the GPU at start-up (pairs captured from the plain search on separate
+training events, seeds 5000 + i; Adam, 20 epochs, batch 4096).  `value` is
+the learned form's tracks/s; the plain form's figures and both finding
+efficiencies (double matching, paper section 3.1) are in the same line.
+
+Prints one JSON line: tracks/s, the roofline object of the dominant kernel
+(k_ckf of the form `value` measures: algorithmic FP32 + FP64 (+ bf16 MFMA)
+work from the kernel's own work-unit counters over its average duration
+measured with HIP events on its stream), and the oracle timed on the host's
+cores on a bounded sample of the same events.
 """
 import argparse
 import json
@@ -22,8 +30,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per unit counted by the kernel (FP32 flop, FP64 flop);
-# the derivation is in the design doc.
+# Algorithmic work per unit counted by the kernel (FP32 flop, FP64 flop),
+# counted from the arithmetic each unit performs.
 UNIT_FLOPS = {
     "rk_trials": (505, 0),      # RKN4 stage algebra + 3 tangent columns + landing prediction
     "legs": (300, 400),         # bound->free, free->bound Jacobian (FP32); J C J^T (FP64)
@@ -32,9 +40,12 @@ UNIT_FLOPS = {
     "chi2_evals": (0, 15),      # 2x2 innovation chi2
     "kf_updates": (0, 450),     # gain + Joseph update
     "ms_updates": (40, 4),      # Highland width (FP32), covariance increment (FP64)
+    "mlp_rows": (90, 0),        # network input (30) and softmax/top-3 of one row (60)
 }
+MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 16x16x16 MFMAs
 PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
 PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
+PEAK_BF16 = 2.5e15    # MI355X dense bf16 MFMA, FLOP/s
 
 
 def _gen(args):
@@ -43,9 +54,9 @@ def _gen(args):
     return make_event(barrel_endcap(), seed, mu=mu)
 
 
-def make_workload(n_events, mu, workers):
+def make_events(seeds, mu, workers):
     from synth import concat_events
-    jobs = [(6000 + i, mu) for i in range(n_events)]
+    jobs = [(s, mu) for s in seeds]
     if workers > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:
@@ -55,7 +66,41 @@ def make_workload(n_events, mu, workers):
     return evs, concat_events(evs)
 
 
-def cpu_baseline(evs, batch, n_events):
+def efficiency(ev, r):
+    """Paper section 3.1: a track is double-matched to the particle that
+    contributes N of its Nt measurements (of Np it has) if N > Nt/2 and
+    N > Np/2 and the seed came from that particle.  Efficiency: fraction of
+    reconstructible seeded particles (pT > 0.5 GeV, vertex |z| < 500 mm and
+    r < 200 mm) with a double-matched track."""
+    nt = int(r["n_tracks"])
+    off = r["offsets"]
+    meas = r["meas"]
+    if nt == 0:
+        return 0.0
+    tid = np.repeat(np.arange(nt), np.diff(off))
+    part = ev.meas_particle[meas]
+    ok = part >= 0
+    P = int(ev.particle_pt.shape[0]) + 1
+    uk, cnt = np.unique(tid[ok].astype(np.int64) * P + part[ok], return_counts=True)
+    t_of, p_of = uk // P, uk % P
+    order = np.lexsort((-cnt, t_of))
+    first = order[np.r_[True, t_of[order][1:] != t_of[order][:-1]]]
+    tr, maj, N = t_of[first], p_of[first], cnt[first]
+    Nt = np.diff(off)[tr]
+    Np = ev.particle_nhits[maj]
+    sp = ev.seed_particle[r["seed"][tr]]
+    matched = (N > Nt / 2) & (N > Np / 2) & (maj == sp)
+    vtx = ev.particle_vtx
+    recon = (ev.particle_pt > 0.5) & (np.abs(vtx[:, 2]) < 500) & (np.hypot(vtx[:, 0], vtx[:, 1]) < 200)
+    seeded = np.zeros(P - 1, bool)
+    seeded[ev.seed_particle] = True
+    den = recon & seeded
+    found = np.zeros(P - 1, bool)
+    found[maj[matched]] = True
+    return float((found & den).sum() / max(1, den.sum()))
+
+
+def cpu_baseline(batch, n_events):
     import oracle
     from synth import barrel_endcap
     oracle.build(force=not os.path.exists(oracle.LIB))
@@ -72,6 +117,72 @@ def cpu_baseline(evs, batch, n_events):
                        f"{r['n_tracks']} tracks) in {dt:.2f} s")
 
 
+def measure(ckf, geo, fld, b, shape, steps, warmup, stream, model=None, audit=False):
+    """Counting run (work units), eager runs timed by the library's kernel
+    timer, then the hipGraph-captured call replayed `steps` times."""
+    import torch
+    lc = lambda timer=None: ckf.launch(shape["grid"], shape["seeds_per_group"], 0, timer, shape["waves_per_simd"])
+    counting = ckf.Finder(geo, fld, b, ckf.config(), lc(), counters=True, model=model, seed_flags=audit)
+    counting.enqueue(stream)
+    rc = counting.result()
+    del counting
+    timer = ckf.KernelTimer()
+    eager = ckf.Finder(geo, fld, b, ckf.config(), lc(timer), counters=False, model=model)
+    kernel_ms = []
+    for i in range(warmup + steps):
+        eager.enqueue(stream)
+        ms = timer.elapsed_ms()
+        if i >= warmup:
+            kernel_ms.append(ms)
+    r = eager.result()
+    assert r["n_tracks"] == rc["n_tracks"] and np.array_equal(r["meas"], rc["meas"]), "variants disagree"
+    del eager
+    finder = ckf.Finder(geo, fld, b, ckf.config(), lc(), counters=False, model=model)
+    finder.capture(stream)
+    for _ in range(warmup):
+        finder.launch_graph(stream)
+    stream.synchronize()
+    t_start, t_stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(steps):
+        finder.launch_graph(stream)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_stop)
+    rg = finder.result()
+    assert rg["n_tracks"] == r["n_tracks"] and np.array_equal(rg["meas"], r["meas"]), "graph replay disagrees"
+    ms_per_step = total_ms / steps
+    return dict(result=r, counters=rc["counters"], seed_flags=rc.get("seed_flags"), kernel_ms=float(np.mean(kernel_ms)),
+                ms_per_step=ms_per_step, tracks_per_s=r["n_tracks"] / (ms_per_step * 1e-3))
+
+
+def roofline_of(m):
+    c = dict(m["counters"])
+    f32 = sum(c.get(k, 0) * UNIT_FLOPS[k][0] for k in UNIT_FLOPS)
+    f64 = sum(c.get(k, 0) * UNIT_FLOPS[k][1] for k in UNIT_FLOPS)
+    mf = c.get("mlp_blocks", 0) * MFMA_FLOP_PER_BLOCK
+    t = m["kernel_ms"] * 1e-3
+    frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64 + mf / PEAK_BF16) / t
+    return dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                frac=round(frac, 5), traffic=None, kernel="k_ckf", kernel_ms=round(m["kernel_ms"], 4), fp32_flop=f32,
+                fp64_flop=f64, bf16_mfma_flop=mf,
+                note="achieved = FP32-equivalent rate (F32 + 2*F64 + F_bf16/15.9)/t against the FP32 vector peak")
+
+
+def phase_line(c, label):
+    tot = max(1, c["cycles_step"])
+    return ("# {} instrumented run, share of step time: phase1 (nav+leg) {:.2f}, search {:.2f}, out {:.2f}; "
+            "lane-average navigation / phase1 {:.2f}, next-layer search / navigation {:.2f}; "
+            "lane occupancy {:.2f}; clocks per 64-lane pass {:.0f}").format(
+        label, c["cycles_leg"] / tot, c["cycles_search"] / tot, c["cycles_out"] / tot,
+        c["cycles_nav"] / 64.0 / max(1, c["cycles_leg"]), c["cycles_next"] / max(1, c["cycles_nav"]),
+        c["steps"] / 64.0 / max(1, c["chunks"]), tot / max(1, c["chunks"]))
+
+
+CYCLE_KEYS = ("cycles_leg", "cycles_search", "cycles_out", "cycles_nav", "cycles_step", "cycles_next", "chunks")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +196,9 @@ def main():
     ap.add_argument("--seeds-per-group", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0, help="kernel register variant: waves per SIMD (1 or 2)")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--no-learned", action="store_true", help="plain form only")
+    ap.add_argument("--train-events", type=int, default=26)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -100,100 +214,107 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this track finder has no multi-GPU path "
-              "(events would be sharded across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(events would be sharded across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
+    say = lambda msg: print(msg, file=sys.stderr, flush=True)
 
     t0 = time.time()
-    evs, batch = make_workload(args.events, args.mu, args.workers)
-    print(f"# generated {batch.n_events} events, {batch.n_seeds} seeds, {batch.n_meas} measurements "
-          f"in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    evs, batch = make_events([6000 + i for i in range(args.events)], args.mu, args.workers)
+    say(f"# generated {batch.n_events} events, {batch.n_seeds} seeds, {batch.n_meas} measurements "
+        f"in {time.time() - t0:.1f} s")
 
     import torch
     import paper_2505_22822_amd as ckf
+    from paper_2505_22822_amd import autotune
     from synth import barrel_endcap
     det = barrel_endcap()
     geo = ckf.Geometry(det.as_arrays())
     fld = ckf.UniformField(0.0, 0.0, 2.0)
     b = ckf.Batch.from_event(batch)
-    # launch shape: autotuned on this batch (cached per device/geometry/size/config)
-    from paper_2505_22822_amd import autotune
-    if args.grid or args.seeds_per_group or args.waves:
-        shape = dict(grid=args.grid, seeds_per_group=args.seeds_per_group, waves_per_simd=args.waves)
-    else:
-        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-        shapes = [dict(grid=n_cu * g, seeds_per_group=s, waves_per_simd=2) for g in (8, 16) for s in (24, 32, 48)]
-        shape, table = autotune.tune(geo, fld, b, ckf.config(), shapes=shapes, reps=2, verbose=True,
-                                     use_cache=not args.retune)
-    print(f"# launch shape {shape}", file=sys.stderr, flush=True)
-    lc = lambda timer=None: ckf.launch(shape["grid"], shape["seeds_per_group"], 0, timer, shape["waves_per_simd"])
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    fixed = bool(args.grid or args.seeds_per_group or args.waves)
+
+    def pick(model=None):
+        if fixed:
+            return dict(grid=args.grid, seeds_per_group=args.seeds_per_group, waves_per_simd=args.waves)
+        waves = (2,) if model is None else (2, 1)
+        shapes = [dict(grid=n_cu * g, seeds_per_group=s, waves_per_simd=w)
+                  for w in waves for g in (8, 16) for s in (24, 32, 48)]
+        shape, _ = autotune.tune(geo, fld, b, ckf.config(), shapes=shapes, reps=2, verbose=True,
+                                 use_cache=not args.retune and model is None, model=model)
+        return shape
 
     stream = torch.cuda.Stream()
-    # one run of the instrumented kernel variant counts the work units of the
-    # batch (the search is deterministic, so every run does the same work)
-    counting = ckf.Finder(geo, fld, b, ckf.config(), lc(), counters=True)
-    counting.enqueue(stream)
-    rc = counting.result()
-    counters = rc["counters"]
-    del counting
-    # the kernel's own duration: HIP events the library records around it
-    timer = ckf.KernelTimer()
-    eager = ckf.Finder(geo, fld, b, ckf.config(), lc(timer), counters=False)
-    kernel_ms = []
-    for i in range(args.warmup + args.steps):
-        eager.enqueue(stream)
-        ms = timer.elapsed_ms()
-        if i >= args.warmup:
-            kernel_ms.append(ms)
-    r = eager.result()
-    n_tracks = r["n_tracks"]
-    assert n_tracks == rc["n_tracks"] and np.array_equal(r["meas"], rc["meas"]), "variants disagree"
-    del eager
-    # the timed region: the hipGraph-captured ckf_find, replayed
-    finder = ckf.Finder(geo, fld, b, ckf.config(), lc(), counters=False)
-    finder.capture(stream)
-    for _ in range(args.warmup):
-        finder.launch_graph(stream)
-    stream.synchronize()
-    print(f"# warm-up done: {n_tracks} tracks", file=sys.stderr, flush=True)
-    t_start, t_stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for _ in range(args.steps):
-        finder.launch_graph(stream)
-    t_stop.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_stop)
-    rg = finder.result()
-    assert rg["n_tracks"] == n_tracks and np.array_equal(rg["meas"], r["meas"]), "graph replay disagrees"
-    ms_per_step = total_ms / args.steps
-    value = n_tracks / (ms_per_step * 1e-3)
+    shape_plain = pick()
+    say(f"# plain launch shape {shape_plain}")
+    plain = measure(ckf, geo, fld, b, shape_plain, args.steps, args.warmup, stream)
+    eff_plain = efficiency(batch, plain["result"])
+    say(f"# plain: {plain['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel {plain['kernel_ms']:.3f} ms, "
+        f"efficiency {eff_plain:.4f}")
+    cyc_plain = {k: plain["counters"].pop(k) for k in CYCLE_KEYS}
+    say(phase_line({**plain["counters"], **cyc_plain}, "plain"))
 
-    cyc = {k: counters.pop(k) for k in ("cycles_leg", "cycles_search", "cycles_out", "cycles_nav", "cycles_step")}
-    tot = max(1, cyc["cycles_step"])
-    print("# instrumented run, share of step time: phase1 (nav+leg) {:.2f}, search {:.2f}, out {:.2f}; "
-          "lane-average navigation time / phase1 {:.2f}".format(
-              cyc["cycles_leg"] / tot, cyc["cycles_search"] / tot, cyc["cycles_out"] / tot,
-              cyc["cycles_nav"] / 64.0 / max(1, cyc["cycles_leg"])), file=sys.stderr, flush=True)
-    f32 = sum(counters[k] * UNIT_FLOPS[k][0] for k in UNIT_FLOPS)
-    f64 = sum(counters[k] * UNIT_FLOPS[k][1] for k in UNIT_FLOPS)
-    k_ms = float(np.mean(kernel_ms))
-    t = k_ms * 1e-3
-    frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64) / t
-    roofline = dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3), peak=PEAK_FP32 / 1e12,
-                    unit="TFLOP/s", frac=round(frac, 5), traffic=None,
-                    kernel="k_ckf", kernel_ms=round(k_ms, 4), fp32_flop=f32, fp64_flop=f64,
-                    note="achieved = FP32-equivalent rate (F32 + 2*F64)/t against the FP32 vector peak")
+    learned_info = None
+    head = plain
+    if not args.no_learned:
+        from paper_2505_22822_amd import learned
+        t0 = time.time()
+        tevs, tbatch = make_events([5000 + i for i in range(args.train_events)], args.mu, args.workers)
+        tb = ckf.Batch.from_event(tbatch)
+        del tevs
+        t1 = time.time()
+        params, log, info = learned.train_from_batches(geo, fld, [tb], epochs=args.epochs, batch=4096, lr=1e-3,
+                                                       seed=0, stream=stream)
+        torch.cuda.synchronize()
+        t2 = time.time()
+        say(f"# training: {info['pairs']} pairs ({info['dropped']} dropped) from {tbatch.n_events} events "
+            f"(generated in {t1 - t0:.1f} s); {log.steps} Adam steps in {t2 - t1:.1f} s; loss {log.loss[0]:.3f} -> "
+            f"{log.loss[-1]:.3f}; validation top-1 {log.val_top1:.3f}, top-3 {log.val_top3:.3f}, "
+            f"confident {log.val_confident:.3f} (of which right {log.val_confident_right:.4f})")
+        del tb, tbatch
+        model = ckf.Model(params)
+        shape_learned = pick(model)
+        say(f"# learned launch shape {shape_learned}")
+        lm = measure(ckf, geo, fld, b, shape_learned, args.steps, args.warmup, stream, model=model, audit=True)
+        eff_learned = efficiency(batch, lm["result"])
+        c = lm["counters"]
+        say(f"# learned: {lm['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel {lm['kernel_ms']:.3f} ms, "
+            f"efficiency {eff_learned:.4f}; network rows {c['mlp_rows']} of {c['navigations']} navigations, "
+            f"proposals used {c['proposals']}, listings differing from the geometric one {c['proposal_misses']}, "
+            f"seeds affected {int(lm['seed_flags'].sum())}")
+        cyc_learned = {k: lm["counters"].pop(k) for k in CYCLE_KEYS}
+        say(phase_line({**lm["counters"], **cyc_learned}, "learned"))
+        learned_info = dict(tracks_per_s=round(lm["tracks_per_s"], 1), ms_per_step=round(lm["ms_per_step"], 4),
+                            efficiency=round(eff_learned, 5), launch=shape_learned,
+                            proposals=c["proposals"], network_rows=c["mlp_rows"], navigations=c["navigations"],
+                            listing_misses=c["proposal_misses"], seeds_affected=int(lm["seed_flags"].sum()),
+                            training=dict(events=args.train_events, pairs=info["pairs"], dropped=info["dropped"],
+                                          epochs=log.epochs, adam_steps=log.steps, seconds=round(t2 - t1, 2),
+                                          loss_first=round(log.loss[0], 4), loss_last=round(log.loss[-1], 4),
+                                          val_top1=round(log.val_top1, 4), val_top3=round(log.val_top3, 4),
+                                          val_confident=round(log.val_confident, 4)),
+                            counters=c)
+        head = lm
+
     cpu = None
     if args.cpu_events > 0:
-        cpu = cpu_baseline(evs, batch, min(args.cpu_events, batch.n_events))
-    line = dict(metric="CKF tracks/s at mu=200 on 1 GPU", value=round(value, 1), unit="tracks/s", n_gpus=1,
-                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
-                scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
+        cpu = cpu_baseline(batch, min(args.cpu_events, batch.n_events))
+    form = "learned proposal" if learned_info else "plain"
+    line = dict(metric="CKF tracks/s at mu=200 on 1 GPU; learned-proposal vs plain at equal efficiency",
+                value=round(head["tracks_per_s"], 1), unit="tracks/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=round(head["ms_per_step"], 4), higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f32+f64" + ("+bf16" if learned_info else ""),
+                data="synthetic",
                 config=dict(workload=f"{batch.n_events} x mu={args.mu:g} events, barrel+endcap, 1% X0, 2 T, "
-                                     f"plain CKF, one hipGraph-captured ckf_find per step",
+                                     f"{form} CKF, one hipGraph-captured ckf_find per step",
                             events=batch.n_events, seeds=batch.n_seeds, measurements=batch.n_meas,
-                            tracks=n_tracks, launch=shape),
-                roofline=roofline, cpu_baseline=cpu, counters=counters)
+                            tracks=head["result"]["n_tracks"],
+                            launch=learned_info["launch"] if learned_info else shape_plain),
+                plain=dict(tracks_per_s=round(plain["tracks_per_s"], 1), ms_per_step=round(plain["ms_per_step"], 4),
+                           efficiency=round(eff_plain, 5), launch=shape_plain),
+                learned=learned_info,
+                equal_efficiency=(learned_info["efficiency"] >= eff_plain - 0.005) if learned_info else None,
+                roofline=roofline_of(head), cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
     print(json.dumps(line))
 
 

@@ -10,8 +10,8 @@
  * is the pattern of measurements with its filtered parameters at the last
  * measurement.  Material effects assume muons (section 3).  The paper leaves
  * the step controller, navigation, gate, pruning and output rules open;
- * this library implements the documented readings listed in the design doc of
- * the source distribution (the same ones the test oracle implements).
+ * this library fixes them as stated at ckf_config and at each entry point
+ * below (the test oracle implements the same readings independently).
  *
  * Units: mm, GeV, tesla, unit charge.  Bound parameters on a module are
  * (loc0, loc1, phi, theta, q/p).  A 5x5 covariance crosses the interface as
@@ -69,6 +69,30 @@ typedef struct ckf_geometry ckf_geometry; /* opaque, device-resident */
 typedef struct ckf_field ckf_field;       /* opaque, device-resident */
 typedef struct ckf_timer ckf_timer;       /* opaque pair of HIP events */
 typedef struct ckf_plan ckf_plan;         /* opaque captured ckf_find (hipGraph) */
+typedef struct ckf_model ckf_model;       /* opaque next-module network packed for bf16 MFMA */
+
+/* The learned next-module proposal (not in the paper: it replaces the
+ * geometric module lookup of the navigation, section 2, by a small network
+ * and keeps that lookup as its fallback).  For every module m the geometry
+ * holds a neighbour table: the next layers a straight ray from the origin
+ * through m's centre or corners meets (at most CKF_MAX_NEXT_LAYERS, in ray
+ * order: centre, then corners (-,-), (+,-), (-,+), (+,+) in (loc0, loc1)),
+ * and for each such layer the CKF_NEIGHBOURS modules whose centres are
+ * nearest to the anchor - where the first of those rays that reaches the
+ * layer meets its envelope - ordered by distance, ties by id.  The network
+ * maps the state on m to a softmax over those CKF_NEIGHBOURS entries:
+ *   inputs (CKF_MLP_INPUTS): loc0/10, loc1/30, the unit direction in m's
+ *   (u, v, n) frame, q/p in 1/GeV, target layer / number of layers;
+ *   7 -> 64 -> 64 -> 32 with ReLU, bf16 weights and activations, FP32 sums.
+ * Parameters cross the interface as one FP32 vector of CKF_MLP_PARAMS in
+ * the order W1 [64][7], b1 [64], W2 [64][64], b2 [64], W3 [32][64], b3 [32]
+ * (row-major, W[out][in]). */
+#define CKF_MAX_NEXT_LAYERS 3
+#define CKF_NEIGHBOURS 32
+#define CKF_MLP_INPUTS 7
+#define CKF_MLP_HIDDEN 64
+#define CKF_MLP_OUTPUTS 32
+#define CKF_MLP_PARAMS 6752
 
 /* Host description of a detector, copied by ckf_geometry_create.
  * Modules are planar rectangles: centre c, unit row vectors u (loc0 axis),
@@ -108,6 +132,8 @@ typedef struct ckf_config {
   double mass;                  /* GeV, particle hypothesis for scattering */
   int32_t material_on;          /* apply multiple scattering */
   int32_t tracks_per_seed;      /* must be 1: the best finished candidate per seed */
+  double learned_min_prob;      /* learned proposal: used when its top-k probabilities sum to at least this */
+  int32_t learned_topk;         /* learned proposal: modules tested (1..3) */
 } ckf_config;
 
 /* Measurements of one or more events, grouped by (event, surface): those of
@@ -149,6 +175,12 @@ typedef struct ckf_tracks {
   int32_t* last_surface;     /* [cap_tracks] module of the last measurement */
   int32_t* status;           /* [8] CKF_STATUS_* words */
   int64_t* counters;         /* [24] or NULL: work-unit counters (CKF_CNT_*) */
+  int32_t* meas_surface;     /* [cap_meas] or NULL: module of each measurement */
+  double* meas_params;       /* [cap_meas][5] or NULL: filtered parameters after each measurement */
+  int32_t* seed_flags;       /* [n_seeds] or NULL: with counters and a model, 1 for a seed one of whose
+                                candidates used a proposal whose listing differs from the geometric one
+                                (those seeds may differ from the plain search; all others are identical);
+                                cleared by ckf_find */
 } ckf_tracks;
 
 /* Work-unit counters accumulated into tracks->counters when it is not NULL
@@ -172,6 +204,12 @@ enum {
   CKF_CNT_CYC_OUT = 15,    /* ... in output slots, children, finishing */
   CKF_CNT_CYC_NAV = 16,    /* ... in navigation (next layer, module listing) */
   CKF_CNT_CYC_STEP = 17,   /* ... per whole step including admission, pruning, publishing */
+  CKF_CNT_CHUNKS = 18,     /* 64-lane passes over the candidate pools (instrumented run) */
+  CKF_CNT_CYC_NEXT = 19,   /* shader clocks summed over lanes in the next-layer search */
+  CKF_CNT_MLP_ROWS = 20,   /* navigations that evaluated the network */
+  CKF_CNT_PROPOSALS = 21,  /* ... whose proposal was used (confident, non-empty listing) */
+  CKF_CNT_PROPOSAL_MISS = 22, /* used proposals whose listing differs from the geometric one (audit) */
+  CKF_CNT_MLP_BLOCKS = 23, /* 16-row network evaluations on the matrix cores */
   CKF_CNT_N = 24
 };
 
@@ -192,8 +230,12 @@ void ckf_geometry_destroy(ckf_geometry* g);
 ckf_status ckf_field_create_uniform(float bx, float by, float bz, ckf_field** out);
 void ckf_field_destroy(ckf_field* f);
 
-/* The defaults of every configuration field (the readings documented in
- * the design doc). */
+/* The defaults of every configuration field: chi2_max 15, 3 branches per
+ * module, 10 live candidates per seed, 3 holes, 6 measurements, 48 steps,
+ * 100 RKN4 trials per leg, step tolerance 1e-2 mm, largest step 200 mm,
+ * landing tolerance 1e-4 mm, path budget 4000 mm, listing margin 1 mm,
+ * muon mass, scattering on, one track per seed, learned proposal used at a
+ * summed top-3 probability of 0.95. */
 void ckf_config_default(ckf_config* cfg);
 
 /* Workspace bytes ckf_find needs for this batch shape and launch. */
@@ -201,9 +243,15 @@ ckf_status ckf_workspace_size(const ckf_geometry* g, const ckf_config* cfg, cons
                               int32_t n_events, int32_t n_seeds, int64_t n_meas, size_t* bytes);
 
 /* Track finding for all seeds of a batch in one persistent launch.  stream
- * is a hipStream_t (NULL: the default stream).  launch may be NULL. */
+ * is a hipStream_t (NULL: the default stream).  launch may be NULL.  model
+ * NULL runs the plain geometric navigation; a model adds the learned
+ * proposal: a navigation that finds a next layer listed for the current
+ * module evaluates the network (one 16-row bf16 MFMA pass per 16 lanes) and,
+ * when its top learned_topk probabilities sum to at least learned_min_prob,
+ * lists among those modules only (same listing test); otherwise, or when
+ * none of them passes, the geometric lookup runs. */
 ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m,
-                    const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch,
+                    const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch, const ckf_model* model,
                     void* workspace, size_t workspace_bytes, ckf_tracks* out, void* stream);
 
 /* Capture the whole ckf_find sequence for these arguments into a hipGraph
@@ -213,8 +261,9 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
  * the plan is used; contents may change between launches.  The plan holds
  * no timer events (launch->timer is ignored). */
 ckf_status ckf_plan_create(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m,
-                           const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch, void* workspace,
-                           size_t workspace_bytes, ckf_tracks* out, void* stream, ckf_plan** plan);
+                           const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch,
+                           const ckf_model* model, void* workspace, size_t workspace_bytes, ckf_tracks* out,
+                           void* stream, ckf_plan** plan);
 /* Replay the captured sequence on `stream` (asynchronous, allocation-free). */
 ckf_status ckf_plan_launch(ckf_plan* plan, void* stream);
 void ckf_plan_destroy(ckf_plan* plan);
@@ -234,6 +283,57 @@ ckf_status ckf_propagate_batch(const ckf_geometry* g, const ckf_field* f, const 
  * 2D measurements (device arrays). */
 ckf_status ckf_kf_update_batch(int32_t n, const double* p_in, const double* cov_in, const float* meas,
                                const float* var, double* p_out, double* cov_out, double* chi2, void* stream);
+
+/* ---- Learned proposal: neighbour table, network, training ---- */
+
+/* Copy the geometry's neighbour table to host memory: next_layers
+ * [n_surfaces][CKF_MAX_NEXT_LAYERS] and neighbours
+ * [n_surfaces][CKF_MAX_NEXT_LAYERS][CKF_NEIGHBOURS], -1 padded.
+ * Synchronous. */
+ckf_status ckf_geometry_neighbours(const ckf_geometry* g, int32_t* next_layers, int32_t* neighbours);
+
+/* Pack CKF_MLP_PARAMS FP32 parameters (device memory, 16-byte aligned)
+ * into a model for ckf_find (allocates ~15 KB of device memory; the packing
+ * runs on `stream`).  ckf_model_update repacks new parameters into the same
+ * model (allocation-free, asynchronous). */
+ckf_status ckf_model_create(const float* params, void* stream, ckf_model** out);
+ckf_status ckf_model_update(ckf_model* model, const float* params, void* stream);
+void ckf_model_destroy(ckf_model* model);
+
+/* Network logits [n][32] for inputs x [n][7] (device memory), evaluated
+ * exactly as inside ckf_find (bf16 MFMA, FP32 sums). */
+ckf_status ckf_mlp_forward(const ckf_model* model, const float* x, int64_t n, float* logits, void* stream);
+
+/* Workspace bytes of ckf_mlp_grad for a batch of n rows. */
+ckf_status ckf_mlp_workspace_size(int64_t n, size_t* bytes);
+
+/* Mean softmax cross-entropy of a batch and its gradient with respect to
+ * the FP32 parameters (forward and backward on bf16 MFMA with FP32 sums;
+ * per-64-row partial gradients summed in a fixed order, so the result is
+ * deterministic).  Row i of the batch is x[rows[i]], labels[rows[i]]
+ * (rows NULL: row i).  grad [CKF_MLP_PARAMS] and loss [1] are written. */
+ckf_status ckf_mlp_grad(const float* params, const float* x, const int32_t* labels, const int32_t* rows,
+                        int64_t n, void* workspace, size_t workspace_bytes, float* grad, float* loss,
+                        void* stream);
+
+/* One Adam step (bias-corrected; step counts from 1) on FP32 parameters
+ * with FP32 moments m, v (all CKF_MLP_PARAMS, device memory). */
+ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr,
+                        float beta1, float beta2, float eps, void* stream);
+
+/* Training pairs from found tracks (device memory): at every change of
+ * layer between consecutive measurements of a track, the network input of
+ * the state at the last measurement of the layer (target layer: that of
+ * the next measurement) and the position of the next measurement's module
+ * in the neighbour table.  Pairs whose target layer or module is not in the
+ * table are dropped.  Pairs are written in track order, then measurement
+ * order, up to cap_pairs: x [cap][7], label [cap], track [cap] (may be
+ * NULL).  counts [2] receives the number of pairs (also beyond cap) and of
+ * dropped pairs.  n_tracks is a device int32 (as ckf_find writes it). */
+ckf_status ckf_capture_pairs(const ckf_geometry* g, const int32_t* n_tracks, int32_t cap_tracks,
+                             const int32_t* offsets, const int32_t* meas_surface, const double* meas_params,
+                             int64_t cap_pairs, float* x, int32_t* label, int32_t* track, int64_t* counts,
+                             void* stream);
 
 /* A pair of HIP events that ckf_find records, on its stream, immediately
  * before and after the persistent track-finding kernel when the launch

@@ -233,28 +233,35 @@ def softmax(z):
     return e / e.sum(axis=-1, keepdims=True)
 
 
-def loss_and_grad(params, x, labels):
+def loss_and_grad(params, x, labels, bf16=False):
     """Mean softmax cross-entropy over the rows and its gradient (flat, FP64)
-    by reverse-mode differentiation of the three layers."""
+    by reverse-mode differentiation of the three layers.  bf16=True rounds
+    to bfloat16 where a bf16 matrix-core evaluation does: the weights, the
+    input, both hidden activations and the three backpropagated
+    pre-activation gradients where they enter products (bias gradients use
+    the unrounded ones); the ReLU derivative is then taken from the rounded
+    activation."""
     P = unpack_params(params)
-    x = np.asarray(x, np.float64)
+    r = bf16_round if bf16 else (lambda a: np.asarray(a, np.float64))
+    x = r(x)
+    W1, W2, W3 = r(P["W1"]), r(P["W2"]), r(P["W3"])
     n = x.shape[0]
-    z1 = x @ P["W1"].T + P["b1"]
-    h1 = np.maximum(z1, 0.0)
-    z2 = h1 @ P["W2"].T + P["b2"]
-    h2 = np.maximum(z2, 0.0)
-    z3 = h2 @ P["W3"].T + P["b3"]
+    z1 = x @ W1.T + P["b1"]
+    h1 = r(np.maximum(z1, 0.0))
+    z2 = h1 @ W2.T + P["b2"]
+    h2 = r(np.maximum(z2, 0.0))
+    z3 = h2 @ W3.T + P["b3"]
     p = softmax(z3)
     rows = np.arange(n)
     loss = -np.mean(np.log(p[rows, labels]))
     dz3 = p.copy()
     dz3[rows, labels] -= 1.0
     dz3 /= n
-    g = {"W3": dz3.T @ h2, "b3": dz3.sum(0)}
-    dz2 = (dz3 @ P["W3"]) * (z2 > 0)
-    g["W2"], g["b2"] = dz2.T @ h1, dz2.sum(0)
-    dz1 = (dz2 @ P["W2"]) * (z1 > 0)
-    g["W1"], g["b1"] = dz1.T @ x, dz1.sum(0)
+    g = {"W3": r(dz3).T @ h2, "b3": dz3.sum(0)}
+    dz2 = (r(dz3) @ W3) * ((h2 > 0) if bf16 else (z2 > 0))
+    g["W2"], g["b2"] = r(dz2).T @ h1, dz2.sum(0)
+    dz1 = (r(dz2) @ W2) * ((h1 > 0) if bf16 else (z1 > 0))
+    g["W1"], g["b1"] = r(dz1).T @ x, dz1.sum(0)
     return loss, pack_params(g)
 
 

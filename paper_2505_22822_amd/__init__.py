@@ -16,7 +16,8 @@ import numpy as np
 from . import _abi
 from ._abi import COUNTER_NAMES
 
-__all__ = ["Geometry", "UniformField", "config", "find", "propagate_batch", "kf_update_batch", "CkfError"]
+__all__ = ["Geometry", "UniformField", "Model", "config", "find", "propagate_batch", "kf_update_batch",
+           "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "CkfError"]
 
 
 class CkfError(RuntimeError):
@@ -82,6 +83,109 @@ class Geometry:
             except Exception:  # interpreter shutdown
                 pass
             self.handle = None
+
+
+def neighbours(geometry: Geometry):
+    """The geometry's neighbour table (ckf_geometry_neighbours): next layers
+    [n, 3] and neighbour modules [n, 3, 32], -1 padded (numpy)."""
+    n = geometry.n_surfaces
+    nxt = np.zeros((n, _abi.MAX_NEXT_LAYERS), np.int32)
+    nbr = np.zeros((n, _abi.MAX_NEXT_LAYERS, _abi.NEIGHBOURS), np.int32)
+    _check(_abi.load().ckf_geometry_neighbours(geometry.handle, nxt.ctypes.data, nbr.ctypes.data),
+           "ckf_geometry_neighbours")
+    return nxt, nbr
+
+
+class Model:
+    """The next-module network packed for the matrix cores (ckf_model_create)
+    from FP32 parameters on the device (torch float32 [6752])."""
+
+    def __init__(self, params, stream=None):
+        self._check_params(params)
+        h = C.c_void_p()
+        _check(_abi.load().ckf_model_create(_ptr(params), _stream_handle(stream), C.byref(h)), "ckf_model_create")
+        self.handle = h
+
+    @staticmethod
+    def _check_params(params):
+        import torch
+        if params.dtype != torch.float32 or params.numel() != _abi.MLP_PARAMS or not params.is_cuda \
+                or not params.is_contiguous():
+            raise TypeError("model parameters must be a contiguous float32 device tensor of 6752")
+
+    def update(self, params, stream=None):
+        self._check_params(params)
+        _check(_abi.load().ckf_model_update(self.handle, _ptr(params), _stream_handle(stream)), "ckf_model_update")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                _abi.load().ckf_model_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self.handle = None
+
+
+def mlp_forward(model: Model, x, stream=None):
+    """Logits [n, 32] (torch, device) of inputs x [n, 7] (float32 device)."""
+    import torch
+    n = int(x.shape[0])
+    out = torch.empty((n, _abi.MLP_OUTPUTS), dtype=torch.float32, device=x.device)
+    _check(_abi.load().ckf_mlp_forward(model.handle, _ptr(x.contiguous()), n, _ptr(out), _stream_handle(stream)),
+           "ckf_mlp_forward")
+    return out
+
+
+class MlpWorkspace:
+    def __init__(self, n, device="cuda"):
+        import torch
+        nb = C.c_size_t(0)
+        _check(_abi.load().ckf_mlp_workspace_size(int(n), C.byref(nb)), "ckf_mlp_workspace_size")
+        self.buf = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        self.n = int(n)
+
+
+def mlp_grad(params, x, labels, rows=None, n=None, workspace=None, grad=None, loss=None, stream=None):
+    """Mean cross-entropy and its gradient (ckf_mlp_grad).  rows: int32
+    device tensor (or a raw device address with n) selecting the batch."""
+    import torch
+    if n is None:
+        n = int(rows.shape[0]) if rows is not None and not isinstance(rows, int) else int(x.shape[0])
+    ws = workspace if workspace is not None else MlpWorkspace(n, x.device)
+    g = grad if grad is not None else torch.empty(_abi.MLP_PARAMS, dtype=torch.float32, device=x.device)
+    l = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=x.device)
+    rp = C.c_void_p(rows) if isinstance(rows, int) else _ptr(rows)
+    _check(_abi.load().ckf_mlp_grad(_ptr(params), _ptr(x), _ptr(labels), rp, int(n), _ptr(ws.buf), ws.buf.numel(),
+                                    _ptr(g), _ptr(l), _stream_handle(stream)), "ckf_mlp_grad")
+    return g, l
+
+
+def mlp_adam(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_abi.load().ckf_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step), float(lr), float(beta1),
+                                    float(beta2), float(eps), _stream_handle(stream)), "ckf_mlp_adam")
+
+
+def capture_pairs(geometry: Geometry, out: dict, cap_pairs: int, stream=None):
+    """Training pairs from a Finder's device outputs (made with
+    meas_states=True): returns (x [k, 7], label [k], track [k], n_pairs,
+    n_dropped) with x/label/track torch device tensors of the captured
+    pairs (k = min(n_pairs, cap_pairs))."""
+    import torch
+    dev = out["offsets"].device
+    cap = max(1, int(cap_pairs))
+    x = torch.empty((cap, _abi.MLP_INPUTS), dtype=torch.float32, device=dev)
+    lab = torch.empty(cap, dtype=torch.int32, device=dev)
+    trk = torch.empty(cap, dtype=torch.int32, device=dev)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    cap_tracks = int(out["offsets"].numel()) - 1
+    _check(_abi.load().ckf_capture_pairs(geometry.handle, _ptr(out["n_tracks"]), cap_tracks, _ptr(out["offsets"]),
+                                         _ptr(out["meas_surface"]), _ptr(out["meas_params"]), cap, _ptr(x),
+                                         _ptr(lab), _ptr(trk), _ptr(counts), _stream_handle(stream)),
+           "ckf_capture_pairs")
+    c = counts.cpu().numpy()
+    k = int(min(c[0], cap))
+    return x[:k], lab[:k], trk[:k], int(c[0]), int(c[1])
 
 
 class UniformField:
@@ -162,9 +266,10 @@ class Finder:
     """Holds the workspace and output buffers of repeated ckf_find calls on
     one batch shape, so the timed call allocates nothing."""
 
-    def __init__(self, geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, counters=True):
+    def __init__(self, geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, counters=True,
+                 model: "Model" = None, meas_states=False, seed_flags=False):
         import torch
-        self.geometry, self.field, self.batch = geometry, field, batch
+        self.geometry, self.field, self.batch, self.model = geometry, field, batch, model
         self.cfg = cfg if cfg is not None else config()
         self.launch = launch_cfg if launch_cfg is not None else launch()
         dev = batch.loc.device
@@ -180,11 +285,15 @@ class Finder:
                         params=z((n, 5), torch.float64), cov=z((n, 15), torch.float64), chi2=z(n, torch.float64),
                         ndf=z(n, torch.int32), holes=z(n, torch.int32), seed=z(n, torch.int32),
                         event=z(n, torch.int32), last_surface=z(n, torch.int32), status=z(8, torch.int32),
-                        counters=z(24, torch.int64) if counters else None)
+                        counters=z(24, torch.int64) if counters else None,
+                        meas_surface=z(cap_m, torch.int32) if meas_states else None,
+                        meas_params=z((cap_m, 5), torch.float64) if meas_states else None,
+                        seed_flags=z(n, torch.int32) if seed_flags else None)
         o = self.out
         self._tracks = _abi.Tracks(n, cap_m, *(_ptr(o[k]) for k in
                                               ("n_tracks", "offsets", "meas", "params", "cov", "chi2", "ndf",
-                                               "holes", "seed", "event", "last_surface", "status", "counters")))
+                                               "holes", "seed", "event", "last_surface", "status", "counters",
+                                               "meas_surface", "meas_params", "seed_flags")))
         b = batch
         self._meas = _abi.Measurements(b.n_events, b.n_surfaces, b.n_meas, _ptr(b.offsets), _ptr(b.loc),
                                        _ptr(b.var))
@@ -195,8 +304,11 @@ class Finder:
         """One ckf_find on the stream (asynchronous, allocation-free)."""
         lib = _abi.load()
         _check(lib.ckf_find(self.geometry.handle, self.field.handle, C.byref(self._meas), C.byref(self._seeds),
-                            C.byref(self.cfg), C.byref(self.launch), _ptr(self.workspace),
+                            C.byref(self.cfg), C.byref(self.launch), self._model_handle(), _ptr(self.workspace),
                             self.workspace.numel(), C.byref(self._tracks), _stream_handle(stream)), "ckf_find")
+
+    def _model_handle(self):
+        return self.model.handle if self.model is not None else None
 
     def capture(self, stream):
         """Capture this call into a hipGraph (ckf_plan_create); later
@@ -205,7 +317,8 @@ class Finder:
         h = C.c_void_p()
         _check(lib.ckf_plan_create(self.geometry.handle, self.field.handle, C.byref(self._meas),
                                    C.byref(self._seeds), C.byref(self.cfg), C.byref(self.launch),
-                                   _ptr(self.workspace), self.workspace.numel(), C.byref(self._tracks),
+                                   self._model_handle(), _ptr(self.workspace), self.workspace.numel(),
+                                   C.byref(self._tracks),
                                    _stream_handle(stream), C.byref(h)), "ckf_plan_create")
         self.plan = h
 
@@ -235,7 +348,13 @@ class Finder:
         nt = int(o["n_tracks"][0])
         res = {k: o[k][:nt] for k in ("params", "cov", "chi2", "ndf", "holes", "seed", "event", "last_surface")}
         res["offsets"] = o["offsets"][:nt + 1]
-        res["meas"] = o["meas"][:int(o["offsets"][nt]) if nt > 0 else 0]
+        nm = int(o["offsets"][nt]) if nt > 0 else 0
+        res["meas"] = o["meas"][:nm]
+        if "meas_surface" in o:
+            res["meas_surface"] = o["meas_surface"][:nm]
+            res["meas_params"] = o["meas_params"][:nm]
+        if "seed_flags" in o:
+            res["seed_flags"] = o["seed_flags"][:self.batch.n_seeds]
         res["n_tracks"] = nt
         res["status"] = st
         if "counters" in o:
@@ -243,12 +362,13 @@ class Finder:
         return res
 
 
-def find(geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, stream=None, retries=3):
+def find(geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, stream=None, retries=3, model=None,
+         meas_states=False, seed_flags=False):
     """Run the track finder on one batch and return the tracks (numpy).
     Retries with a larger history capacity if the device reports it short."""
     lc = launch_cfg if launch_cfg is not None else launch()
     for _ in range(retries + 1):
-        f = Finder(geometry, field, batch, cfg, lc)
+        f = Finder(geometry, field, batch, cfg, lc, model=model, meas_states=meas_states, seed_flags=seed_flags)
         f.enqueue(stream)
         r = f.result(check=False)
         flags = int(r["status"][_abi.ST_FLAGS])

@@ -15,7 +15,9 @@ FLAG_NODE_CAPACITY, FLAG_OUT_CAPACITY, FLAG_BAD_OFFSETS = 1, 2, 4
 ST_FLAGS, ST_NODES, ST_TRACKS, ST_MEAS, ST_BAD_SEEDS, ST_FAILED_LEGS, ST_NAV_OVF = range(7)
 COUNTER_NAMES = ("steps", "navigations", "nav_modules", "legs", "rk_trials", "chi2_evals", "kf_updates",
                  "ms_updates", "crossed", "holes", "pruned", "finished", "rk_rejects", "cycles_leg",
-                 "cycles_search", "cycles_out", "cycles_nav", "cycles_step")
+                 "cycles_search", "cycles_out", "cycles_nav", "cycles_step", "chunks", "cycles_next",
+                 "mlp_rows", "proposals", "proposal_misses", "mlp_blocks")
+MAX_NEXT_LAYERS, NEIGHBOURS, MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS = 3, 32, 7, 32, 6752
 
 
 class GeometryDesc(C.Structure):
@@ -27,7 +29,8 @@ class Config(C.Structure):
     _fields_ = [("chi2_max", F64), ("branches_per_surface", I32), ("max_live_per_seed", I32),
                 ("max_holes", I32), ("min_meas", I32), ("max_steps", I32), ("max_rk_steps", I32),
                 ("step_tol", F64), ("step_max", F64), ("land_tol", F64), ("path_max", F64),
-                ("nav_margin", F64), ("mass", F64), ("material_on", I32), ("tracks_per_seed", I32)]
+                ("nav_margin", F64), ("mass", F64), ("material_on", I32), ("tracks_per_seed", I32),
+                ("learned_min_prob", F64), ("learned_topk", I32)]
 
 
 class Measurements(C.Structure):
@@ -42,7 +45,8 @@ class Seeds(C.Structure):
 class Tracks(C.Structure):
     _fields_ = [("cap_tracks", I32), ("cap_meas", I64), ("n_tracks", VP), ("offsets", VP), ("meas", VP),
                 ("params", VP), ("cov", VP), ("chi2", VP), ("ndf", VP), ("holes", VP), ("seed", VP),
-                ("event", VP), ("last_surface", VP), ("status", VP), ("counters", VP)]
+                ("event", VP), ("last_surface", VP), ("status", VP), ("counters", VP), ("meas_surface", VP),
+                ("meas_params", VP), ("seed_flags", VP)]
 
 
 class Launch(C.Structure):
@@ -59,16 +63,25 @@ SIGNATURES = {
     "ckf_config_default": (None, [C.POINTER(Config)]),
     "ckf_workspace_size": (I32, [VP, C.POINTER(Config), C.POINTER(Launch), I32, I32, I64, C.POINTER(C.c_size_t)]),
     "ckf_find": (I32, [VP, VP, C.POINTER(Measurements), C.POINTER(Seeds), C.POINTER(Config), C.POINTER(Launch),
-                       VP, C.c_size_t, C.POINTER(Tracks), VP]),
+                       VP, VP, C.c_size_t, C.POINTER(Tracks), VP]),
     "ckf_propagate_batch": (I32, [VP, VP, C.POINTER(Config), I32, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
     "ckf_kf_update_batch": (I32, [I32, VP, VP, VP, VP, VP, VP, VP, VP]),
     "ckf_plan_create": (I32, [VP, VP, C.POINTER(Measurements), C.POINTER(Seeds), C.POINTER(Config),
-                              C.POINTER(Launch), VP, C.c_size_t, C.POINTER(Tracks), VP, C.POINTER(VP)]),
+                              C.POINTER(Launch), VP, VP, C.c_size_t, C.POINTER(Tracks), VP, C.POINTER(VP)]),
     "ckf_plan_launch": (I32, [VP, VP]),
     "ckf_plan_destroy": (None, [VP]),
     "ckf_timer_create": (I32, [C.POINTER(VP)]),
     "ckf_timer_destroy": (None, [VP]),
     "ckf_timer_elapsed_ms": (I32, [VP, C.POINTER(F32)]),
+    "ckf_geometry_neighbours": (I32, [VP, VP, VP]),
+    "ckf_model_create": (I32, [VP, VP, C.POINTER(VP)]),
+    "ckf_model_update": (I32, [VP, VP, VP]),
+    "ckf_model_destroy": (None, [VP]),
+    "ckf_mlp_forward": (I32, [VP, VP, I64, VP, VP]),
+    "ckf_mlp_workspace_size": (I32, [I64, C.POINTER(C.c_size_t)]),
+    "ckf_mlp_grad": (I32, [VP, VP, VP, VP, I64, VP, C.c_size_t, VP, VP, VP]),
+    "ckf_mlp_adam": (I32, [VP, VP, VP, VP, I32, F32, F32, F32, F32, VP]),
+    "ckf_capture_pairs": (I32, [VP, VP, I32, VP, VP, VP, I64, VP, VP, VP, VP, VP]),
     "ckf_status_string": (C.c_char_p, [I32]),
     "ckf_last_error": (C.c_char_p, []),
 }

@@ -21,11 +21,12 @@ from . import Finder, KernelTimer, _abi, launch
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ckf_mi355x", "autotune.json")
 
 
-def _key(batch, cfg, device_name):
+def _key(batch, cfg, device_name, learned):
     c = {name: getattr(cfg, name) for name, _ in _abi.Config._fields_}
     h = hashlib.sha1(json.dumps(c, sort_keys=True).encode()).hexdigest()[:12]
     seeds_class = int(2 ** round(np.log2(max(1, batch.n_seeds))))
-    return f"{device_name}|surf={batch.n_surfaces}|seeds~{seeds_class}|cfg={h}"
+    form = "learned" if learned else "plain"
+    return f"{device_name}|surf={batch.n_surfaces}|seeds~{seeds_class}|cfg={h}|{form}"
 
 
 def candidates(n_cus: int):
@@ -36,11 +37,13 @@ def candidates(n_cus: int):
 
 
 def tune(geometry, field, batch, cfg=None, shapes=None, reps=3, cache_path=DEFAULT_CACHE, use_cache=True,
-         verbose=False):
-    """Return (best launch dict, table of (shape, median kernel ms))."""
+         verbose=False, model=None):
+    """Return (best launch dict, table of (shape, median kernel ms)).  With a
+    model the learned form is tuned (its timing depends on the model, so a
+    cached entry is only a starting point: pass use_cache=False to retune)."""
     import torch
     props = torch.cuda.get_device_properties(batch.loc.device)
-    key = _key(batch, cfg if cfg is not None else _default_cfg(), props.name)
+    key = _key(batch, cfg if cfg is not None else _default_cfg(), props.name, model is not None)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         try:
@@ -54,7 +57,8 @@ def tune(geometry, field, batch, cfg=None, shapes=None, reps=3, cache_path=DEFAU
     table, ref = [], None
     for sh in shapes:
         f = Finder(geometry, field, batch, cfg,
-                   launch(sh["grid"], sh["seeds_per_group"], 0, timer, sh["waves_per_simd"]), counters=False)
+                   launch(sh["grid"], sh["seeds_per_group"], 0, timer, sh["waves_per_simd"]), counters=False,
+                   model=model)
         f.enqueue()  # warm-up
         torch.cuda.synchronize()
         ms = []

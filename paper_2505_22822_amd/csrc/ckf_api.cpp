@@ -31,6 +31,11 @@ struct ckf_plan {
   hipGraphExec_t exec = nullptr;
 };
 
+struct ckf_model {
+  void* buf = nullptr;  // packed fragments and biases (kModelBytes)
+  int device = 0;
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -183,6 +188,83 @@ ckf_status upload(ckf_geometry* g, const std::vector<T>& v, const T** out) {
   return CKF_OK;
 }
 
+// Neighbour table of the learned proposal, in FP64 from the FP32 geometry.
+// For module m: rays from the origin through its centre and corners
+// (-,-), (+,-), (-,+), (+,+) in (loc0, loc1); each ray's next layer is the
+// layer other than m's whose envelope it meets first, beyond the ray's
+// point on m and within the envelope's extent.  The distinct next layers in
+// ray order (at most kMaxNext) are kept, each with the anchor where its
+// first ray meets the envelope, and the kNeighbours modules of that layer
+// with centres nearest to the anchor (squared distance, ties by id).
+void build_neighbours(const ckf_geometry_desc* d, std::vector<int>& nb_next, std::vector<int>& nb_mod) {
+  const int n = d->n_surfaces, nl = d->n_layers;
+  nb_next.assign((size_t)n * ckf::kMaxNext, -1);
+  nb_mod.assign((size_t)n * ckf::kMaxNext * ckf::kNeighbours, -1);
+  std::vector<std::vector<int>> members(nl);
+  for (int i = 0; i < n; ++i) members[d->layer[i]].push_back(i);
+  std::vector<std::pair<double, int>> cand;
+  for (int m = 0; m < n; ++m) {
+    const float* c = d->center + 3 * m;
+    const float* r = d->rot + 9 * m;
+    const double h0 = d->half[2 * m], h1 = d->half[2 * m + 1];
+    const double sgn[5][2] = {{0, 0}, {-1, -1}, {1, -1}, {-1, 1}, {1, 1}};
+    int n_next = 0;
+    double anchors[ckf::kMaxNext][3];
+    for (int ray = 0; ray < 5 && n_next < ckf::kMaxNext; ++ray) {
+      double q[3];
+      for (int k = 0; k < 3; ++k)
+        q[k] = ((double)c[k] + sgn[ray][0] * h0 * (double)r[k]) + sgn[ray][1] * h1 * (double)r[3 + k];
+      const double tm = std::sqrt((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]);
+      if (!(tm > 0)) continue;
+      const double dv[3] = {q[0] / tm, q[1] / tm, q[2] / tm};
+      const double dperp = std::hypot(dv[0], dv[1]);
+      int best = -1;
+      double tbest = INFINITY;
+      for (int L = 0; L < nl; ++L) {
+        if (L == d->layer[m]) continue;
+        const double pos = d->layer_pos[L], lo = d->layer_lo[L], hi = d->layer_hi[L];
+        double t;
+        if (d->layer_type[L] == 0) {
+          if (!(dperp > 0)) continue;
+          t = pos / dperp;
+          const double z = t * dv[2];
+          if (!(z >= lo && z <= hi)) continue;
+        } else {
+          if (dv[2] == 0) continue;
+          t = pos / dv[2];
+          const double rr = t * dperp;
+          if (!(t > 0 && rr >= lo && rr <= hi)) continue;
+        }
+        if (!(t > tm)) continue;
+        if (t < tbest) {
+          tbest = t;
+          best = L;
+        }
+      }
+      if (best < 0) continue;
+      bool seen = false;
+      for (int k = 0; k < n_next; ++k) seen = seen || nb_next[(size_t)m * ckf::kMaxNext + k] == best;
+      if (seen) continue;
+      nb_next[(size_t)m * ckf::kMaxNext + n_next] = best;
+      for (int k = 0; k < 3; ++k) anchors[n_next][k] = tbest * dv[k];
+      ++n_next;
+    }
+    for (int k = 0; k < n_next; ++k) {
+      const std::vector<int>& mem = members[nb_next[(size_t)m * ckf::kMaxNext + k]];
+      cand.clear();
+      for (int j : mem) {
+        const double dx = (double)d->center[3 * j] - anchors[k][0], dy = (double)d->center[3 * j + 1] - anchors[k][1],
+                     dz = (double)d->center[3 * j + 2] - anchors[k][2];
+        cand.emplace_back((dx * dx + dy * dy) + dz * dz, j);
+      }
+      const size_t kk = std::min<size_t>(cand.size(), ckf::kNeighbours);
+      std::partial_sort(cand.begin(), cand.begin() + kk, cand.end());
+      for (size_t q = 0; q < kk; ++q)
+        nb_mod[((size_t)m * ckf::kMaxNext + k) * ckf::kNeighbours + q] = cand[q].second;
+    }
+  }
+}
+
 ckf_status check_config(const ckf_config* c) {
   if (!c) return fail(CKF_ERR_INVALID_ARGUMENT, "config is NULL");
   if (!(c->chi2_max > 0) || !(c->step_tol > 0) || !(c->step_max > 0) || !(c->land_tol > 0) || !(c->path_max > 0) ||
@@ -196,6 +278,8 @@ ckf_status check_config(const ckf_config* c) {
   if (c->max_steps > ckf::kMaxSteps) return fail(CKF_ERR_NOT_SUPPORTED, "max_steps must be <= 64");
   if (c->tracks_per_seed != 1) return fail(CKF_ERR_NOT_SUPPORTED, "tracks_per_seed must be 1 on the GPU");
   if (c->nav_margin > ckf::kMaxNavMargin) return fail(CKF_ERR_NOT_SUPPORTED, "nav_margin must be <= 2 mm");
+  if (!(c->learned_min_prob >= 0) || c->learned_topk < 1 || c->learned_topk > 3)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "learned_min_prob must be >= 0 and learned_topk 1..3");
   return CKF_OK;
 }
 
@@ -215,6 +299,8 @@ ckf::CfgDev to_dev(const ckf_config* c) {
   d.nav_margin = (float)c->nav_margin;
   d.mass = c->mass;
   d.material = c->material_on != 0;
+  d.min_prob = (float)c->learned_min_prob;
+  d.topk = c->learned_topk;
   return d;
 }
 
@@ -314,6 +400,8 @@ void ckf_config_default(ckf_config* c) {
   c->mass = 0.1056583755;
   c->material_on = 1;
   c->tracks_per_seed = 1;
+  c->learned_min_prob = 0.95;
+  c->learned_topk = 3;
 }
 
 ckf_status ckf_geometry_create(const ckf_geometry_desc* d, ckf_geometry** out) {
@@ -352,6 +440,8 @@ ckf_status ckf_geometry_create(const ckf_geometry_desc* d, ckf_geometry** out) {
   HostGrid G;
   ckf_status st = build_grid(d, mods, G);
   if (st != CKF_OK) return st;
+  std::vector<int> nb_next, nb_mod;
+  build_neighbours(d, nb_next, nb_mod);
   ckf_geometry* g = new ckf_geometry();
   hipGetDevice(&g->device);
   auto cleanup = [&](ckf_status s) {
@@ -361,12 +451,15 @@ ckf_status ckf_geometry_create(const ckf_geometry_desc* d, ckf_geometry** out) {
   };
   const ckf::Module* dm;
   const ckf::LayerRec* dl;
-  const int *co, *cm, *bo, *dp, *dn;
+  const int *co, *cm, *bo, *dp, *dn, *nn, *nm;
   if ((st = upload(g, mods, &dm)) != CKF_OK || (st = upload(g, G.layers, &dl)) != CKF_OK ||
       (st = upload(g, G.cell_off, &co)) != CKF_OK || (st = upload(g, G.cell_mod, &cm)) != CKF_OK ||
       (st = upload(g, G.barrel, &bo)) != CKF_OK || (st = upload(g, G.disk_pos, &dp)) != CKF_OK ||
-      (st = upload(g, G.disk_neg, &dn)) != CKF_OK)
+      (st = upload(g, G.disk_neg, &dn)) != CKF_OK || (st = upload(g, nb_next, &nn)) != CKF_OK ||
+      (st = upload(g, nb_mod, &nm)) != CKF_OK)
     return cleanup(st);
+  g->dev.nb_next = nn;
+  g->dev.nb_mod = nm;
   g->dev.n_surfaces = d->n_surfaces;
   g->dev.n_layers = d->n_layers;
   g->dev.mod = dm;
@@ -414,8 +507,8 @@ ckf_status ckf_workspace_size(const ckf_geometry* g, const ckf_config* cfg, cons
 }
 
 ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m, const ckf_seeds* s,
-                    const ckf_config* cfg, const ckf_launch* launch, void* workspace, size_t workspace_bytes,
-                    ckf_tracks* out, void* stream) {
+                    const ckf_config* cfg, const ckf_launch* launch, const ckf_model* model, void* workspace,
+                    size_t workspace_bytes, ckf_tracks* out, void* stream) {
   if (!g || !f || !m || !s || !out) return fail(CKF_ERR_INVALID_ARGUMENT, "ckf_find: NULL argument");
   ckf_status st = check_config(cfg);
   if (st != CKF_OK) return st;
@@ -472,6 +565,9 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
     a.w = w;
     a.status = out->status;
     a.counters = reinterpret_cast<long long*>(out->counters);
+    a.learned = model != nullptr;
+    a.model = model ? ckf::model_view(model->buf) : ckf::ModelDev{};
+    a.seed_flags = out->seed_flags;
     if (launch && launch->timer) HIP_TRY(hipEventRecord(launch->timer->start, hs), "hipEventRecord");
     HIP_TRY(ckf::launch_ckf(a, L.waves_per_simd, hs), "launch k_ckf");
     if (launch && launch->timer) HIP_TRY(hipEventRecord(launch->timer->stop, hs), "hipEventRecord");
@@ -481,8 +577,9 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
 }
 
 ckf_status ckf_plan_create(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m,
-                           const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch, void* workspace,
-                           size_t workspace_bytes, ckf_tracks* out, void* stream, ckf_plan** plan) {
+                           const ckf_seeds* s, const ckf_config* cfg, const ckf_launch* launch,
+                           const ckf_model* model, void* workspace, size_t workspace_bytes, ckf_tracks* out,
+                           void* stream, ckf_plan** plan) {
   if (!plan) return fail(CKF_ERR_INVALID_ARGUMENT, "plan_create: NULL plan");
   *plan = nullptr;
   hipStream_t hs = static_cast<hipStream_t>(stream);
@@ -491,7 +588,7 @@ ckf_status ckf_plan_create(const ckf_geometry* g, const ckf_field* f, const ckf_
   if (launch) l = *launch;
   l.timer = nullptr;
   HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  const ckf_status st = ckf_find(g, f, m, s, cfg, &l, workspace, workspace_bytes, out, stream);
+  const ckf_status st = ckf_find(g, f, m, s, cfg, &l, model, workspace, workspace_bytes, out, stream);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(hs, &graph);
   if (st != CKF_OK) {
@@ -574,6 +671,103 @@ ckf_status ckf_kf_update_batch(int32_t n, const double* p_in, const double* cov_
     return fail(CKF_ERR_INVALID_ARGUMENT, "kf_update_batch: NULL array");
   HIP_TRY(ckf::launch_kf_update(n, p_in, cov_in, meas, var, p_out, cov_out, chi2, static_cast<hipStream_t>(stream)),
           "launch k_kf_update_batch");
+  return CKF_OK;
+}
+
+ckf_status ckf_geometry_neighbours(const ckf_geometry* g, int32_t* next_layers, int32_t* neighbours) {
+  if (!g || !next_layers || !neighbours) return fail(CKF_ERR_INVALID_ARGUMENT, "geometry_neighbours: NULL argument");
+  const size_t n = (size_t)g->dev.n_surfaces * ckf::kMaxNext;
+  HIP_TRY(hipMemcpy(next_layers, g->dev.nb_next, n * sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(neighbours)");
+  HIP_TRY(hipMemcpy(neighbours, g->dev.nb_mod, n * ckf::kNeighbours * sizeof(int), hipMemcpyDeviceToHost),
+          "hipMemcpy(neighbours)");
+  return CKF_OK;
+}
+
+ckf_status ckf_model_create(const float* params, void* stream, ckf_model** out) {
+  if (!params || !out) return fail(CKF_ERR_INVALID_ARGUMENT, "model_create: NULL argument");
+  *out = nullptr;
+  if (reinterpret_cast<uintptr_t>(params) % 16 != 0)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "model_create: params must be 16-byte aligned");
+  ckf_model* md = new ckf_model();
+  hipGetDevice(&md->device);
+  const hipError_t e = hipMalloc(&md->buf, ckf::kModelBytes);
+  if (e != hipSuccess) {
+    delete md;
+    return hip_fail(e, "hipMalloc(model)");
+  }
+  const hipError_t e2 = ckf::launch_model_pack(params, md->buf, static_cast<hipStream_t>(stream));
+  if (e2 != hipSuccess) {
+    (void)hipFree(md->buf);
+    delete md;
+    return hip_fail(e2, "launch k_model_pack");
+  }
+  *out = md;
+  return CKF_OK;
+}
+
+ckf_status ckf_model_update(ckf_model* model, const float* params, void* stream) {
+  if (!model || !params) return fail(CKF_ERR_INVALID_ARGUMENT, "model_update: NULL argument");
+  if (reinterpret_cast<uintptr_t>(params) % 16 != 0)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "model_update: params must be 16-byte aligned");
+  HIP_TRY(ckf::launch_model_pack(params, model->buf, static_cast<hipStream_t>(stream)), "launch k_model_pack");
+  return CKF_OK;
+}
+
+void ckf_model_destroy(ckf_model* model) {
+  if (!model) return;
+  (void)hipFree(model->buf);
+  delete model;
+}
+
+ckf_status ckf_mlp_forward(const ckf_model* model, const float* x, int64_t n, float* logits, void* stream) {
+  if (!model || n < 0 || (n > 0 && (!x || !logits))) return fail(CKF_ERR_INVALID_ARGUMENT, "mlp_forward: bad argument");
+  if (reinterpret_cast<uintptr_t>(logits) % 16 != 0)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "mlp_forward: logits must be 16-byte aligned");
+  HIP_TRY(ckf::launch_mlp_forward(ckf::model_view(model->buf), x, n, logits, static_cast<hipStream_t>(stream)),
+          "launch k_mlp_forward");
+  return CKF_OK;
+}
+
+ckf_status ckf_mlp_workspace_size(int64_t n, size_t* bytes) {
+  if (n < 1 || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "mlp_workspace_size: bad argument");
+  *bytes = ckf::mlp_workspace_bytes(n);
+  return CKF_OK;
+}
+
+ckf_status ckf_mlp_grad(const float* params, const float* x, const int32_t* labels, const int32_t* rows, int64_t n,
+                        void* workspace, size_t workspace_bytes, float* grad, float* loss, void* stream) {
+  if (!params || !x || !labels || !workspace || !grad || !loss || n < 1)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "mlp_grad: bad argument");
+  if (reinterpret_cast<uintptr_t>(params) % 16 != 0)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "mlp_grad: params must be 16-byte aligned");
+  if (n > (int64_t)INT32_MAX * 64) return fail(CKF_ERR_NOT_SUPPORTED, "mlp_grad: batch too large");
+  if (workspace_bytes < ckf::mlp_workspace_bytes(n)) return fail(CKF_ERR_CAPACITY, "mlp_grad: workspace too small");
+  HIP_TRY(ckf::launch_mlp_grad(params, x, labels, rows, n, workspace, grad, loss, static_cast<hipStream_t>(stream)),
+          "launch k_mlp_grad");
+  return CKF_OK;
+}
+
+ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
+                        float beta2, float eps, void* stream) {
+  if (!params || !m || !v || !grad || step < 1 || !(lr >= 0) || !(beta1 >= 0 && beta1 < 1) ||
+      !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "mlp_adam: bad argument");
+  HIP_TRY(ckf::launch_mlp_adam(params, m, v, grad, step, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream)),
+          "launch k_mlp_adam");
+  return CKF_OK;
+}
+
+ckf_status ckf_capture_pairs(const ckf_geometry* g, const int32_t* n_tracks, int32_t cap_tracks,
+                             const int32_t* offsets, const int32_t* meas_surface, const double* meas_params,
+                             int64_t cap_pairs, float* x, int32_t* label, int32_t* track, int64_t* counts,
+                             void* stream) {
+  if (!g || !n_tracks || !offsets || !meas_surface || !meas_params || !counts || cap_tracks < 0 || cap_pairs < 0 ||
+      (cap_pairs > 0 && (!x || !label)))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "capture_pairs: bad argument");
+  HIP_TRY(ckf::launch_capture_pairs(g->dev, n_tracks, cap_tracks, offsets, meas_surface, meas_params, cap_pairs, x,
+                                    label, track, reinterpret_cast<long long*>(counts),
+                                    static_cast<hipStream_t>(stream)),
+          "launch k_capture_pairs");
   return CKF_OK;
 }
 

@@ -426,11 +426,72 @@ __device__ bool cross_zplane(const Helix& H, float Z, float& s_out) {
   return true;
 }
 
+// Listing test: the second-order expansion P + d T + d^2 k / 2 (from the
+// base point P at path s_base) meets the module plane within its half
+// lengths plus the margin at positive total path.  The accumulator keeps the
+// kMaxList smallest (path, id) in sorted order, each module once.
+struct ListAcc {
+  float ls[kMaxList];
+  int lm[kMaxList];
+};
+
+__device__ __forceinline__ void list_init(ListAcc& a) {
+#pragma unroll
+  for (int q = 0; q < kMaxList; ++q) {
+    a.ls[q] = INFINITY;
+    a.lm[q] = -1;
+  }
+}
+
+__device__ __forceinline__ void list_test(ListAcc& a, int m, const Module& M, V3 P, V3 T, V3 k, float s_base,
+                                          float margin, int& n_tested) {
+  const V3 c = ld3(M.c), nn = ld3(M.n);
+  const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
+  const V3 dc = c - P;
+  if (sqrtf(dot(dc, dc)) > hd + kReach) return;
+  ++n_tested;
+  const float qa = 0.5f * dot(nn, k), qb = dot(nn, T), c0 = dot(nn, P - c);
+  if (fabsf(qb) < 1e-3f) return;
+  float d = -c0 / qb;
+  const float disc = qb * qb - 4.0f * qa * c0;
+  if (disc >= 0.f) {
+    const float qq = -0.5f * (qb + copysignf(sqrtf(disc), qb));
+    if (qq != 0.f) d = c0 / qq;
+  }
+  const V3 X = P + d * T + (0.5f * d * d) * k - c;
+  const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
+  if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) return;
+  float cs = s_base + d;
+  if (!(cs > 0.f)) return;
+  if (a.lm[0] == m || a.lm[1] == m || a.lm[2] == m || a.lm[3] == m) return;
+  int cm = m;
+#pragma unroll
+  for (int q = 0; q < kMaxList; ++q) {
+    const bool lt = cs < a.ls[q] || (cs == a.ls[q] && cm < a.lm[q]);
+    if (lt) {
+      const float ts = a.ls[q];
+      const int tm = a.lm[q];
+      a.ls[q] = cs;
+      a.lm[q] = cm;
+      cs = ts;
+      cm = tm;
+    }
+  }
+}
+
+__device__ __forceinline__ int list_out(const ListAcc& a, int* list) {
+  int n = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxList; ++q) {
+    list[q] = a.lm[q];
+    n += a.lm[q] >= 0 ? 1 : 0;
+  }
+  return n;
+}
+
 // Candidate modules of layer `l` near the trajectory segment from P along T
-// (navigation grid lookup), then the listing test from the base point P at
-// path s_base: second-order expansion P + d T + d^2 k / 2 meets the module
-// plane within its half lengths plus the margin at positive total path.
-// Returns the number listed (<= kMaxList, sorted by path then id).
+// (navigation grid lookup), each put through the listing test.  Returns the
+// number listed (<= kMaxList, sorted by path then id).
 __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_base, int exclude, float margin,
                           int* list, int& n_tested, int& overflow) {
   const LayerRec Lr = g.layers[l];
@@ -462,49 +523,8 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
   iw0 = max(iw0, 0);
   iw1 = min(iw1, Lr.nw - 1);
   if (ip1 - ip0 >= Lr.nphi) { ip0 = 0; ip1 = Lr.nphi - 1; }
-  float ls[kMaxList];
-  int lm[kMaxList];
-#pragma unroll
-  for (int q = 0; q < kMaxList; ++q) {
-    ls[q] = INFINITY;
-    lm[q] = -1;
-  }
-  // listing test of one candidate module; keeps the kMaxList smallest (path,
-  // id) in sorted order, each module once (it may sit in two cells)
-  auto consider = [&](int m, const Module& M) {
-    const V3 c = ld3(M.c), nn = ld3(M.n);
-    const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
-    const V3 dc = c - P;
-    if (sqrtf(dot(dc, dc)) > hd + kReach) return;
-    ++n_tested;
-    const float qa = 0.5f * dot(nn, k), qb = dot(nn, T), c0 = dot(nn, P - c);
-    if (fabsf(qb) < 1e-3f) return;
-    float d = -c0 / qb;
-    const float disc = qb * qb - 4.0f * qa * c0;
-    if (disc >= 0.f) {
-      const float qq = -0.5f * (qb + copysignf(sqrtf(disc), qb));
-      if (qq != 0.f) d = c0 / qq;
-    }
-    const V3 X = P + d * T + (0.5f * d * d) * k - c;
-    const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
-    if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) return;
-    float cs = s_base + d;
-    if (!(cs > 0.f)) return;
-    if (lm[0] == m || lm[1] == m || lm[2] == m || lm[3] == m) return;
-    int cm = m;
-#pragma unroll
-    for (int q = 0; q < kMaxList; ++q) {
-      const bool lt = cs < ls[q] || (cs == ls[q] && cm < lm[q]);
-      if (lt) {
-        const float ts = ls[q];
-        const int tm = lm[q];
-        ls[q] = cs;
-        lm[q] = cm;
-        cs = ts;
-        cm = tm;
-      }
-    }
-  };
+  ListAcc acc;
+  list_init(acc);
   int visited = 0;
   for (int ipr = ip0; ipr <= ip1; ++ipr) {
     int ip = ipr % Lr.nphi;
@@ -524,18 +544,12 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
         Module M0, M1;
         load_module(g, m0, M0);
         if (m1 >= 0) load_module(g, m1, M1);
-        if (m0 != exclude) consider(m0, M0);
-        if (m1 >= 0 && m1 != exclude) consider(m1, M1);
+        if (m0 != exclude) list_test(acc, m0, M0, P, T, k, s_base, margin, n_tested);
+        if (m1 >= 0 && m1 != exclude) list_test(acc, m1, M1, P, T, k, s_base, margin, n_tested);
       }
     }
   }
-  int n = 0;
-#pragma unroll
-  for (int q = 0; q < kMaxList; ++q) {
-    list[q] = lm[q];
-    n += lm[q] >= 0 ? 1 : 0;
-  }
-  return n;
+  return list_out(acc, list);
 }
 
 // The next navigation layer from free state (p, T, lam) in global

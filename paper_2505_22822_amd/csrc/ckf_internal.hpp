@@ -16,6 +16,8 @@ constexpr int kMaxSteps = 64;      // largest max_steps (history walk buffer)
 constexpr float kReach = 30.0f;    // mm, envelope-to-module reach of the candidate pre-filter
 constexpr float kGridPad = 5.0f;   // mm, padding of module extents in the navigation grid
 constexpr float kMaxNavMargin = 2.0f;
+constexpr int kMaxNext = CKF_MAX_NEXT_LAYERS;  // next layers per module in the neighbour table
+constexpr int kNeighbours = CKF_NEIGHBOURS;    // modules per (module, next layer)
 
 // Surface store: one 64-byte record per module (a lane reads one record per
 // access; records of neighbouring modules share cache lines).
@@ -51,6 +53,10 @@ struct GeomDev {
   const int* disk_pos = nullptr;      // z > 0 disks by |z|
   const int* disk_neg = nullptr;      // z < 0 disks by |z|
   int n_barrel = 0, n_disk_pos = 0, n_disk_neg = 0;
+  // neighbour table of the learned proposal: per module the next layers
+  // [n][kMaxNext] (-1 pads) and per (module, slot) kNeighbours module ids
+  const int* nb_next = nullptr;
+  const int* nb_mod = nullptr;
 };
 
 struct FieldDev {
@@ -64,7 +70,23 @@ struct CfgDev {
   float step_tol, step_max, land_tol, path_max, nav_margin;
   double mass;
   int material;
+  float min_prob;  // learned proposal: smallest summed probability of the top-k to use it
+  int topk;        // learned proposal: modules tested per proposal
 };
+
+// The next-module network packed for the bf16 matrix cores: weight tiles in
+// the A-operand order of v_mfma_f32_16x16x16_bf16 (per 16x16 tile, lane l
+// holds W[16*ob + l%16][16*kb + 4*(l/16) + j], j = 0..3), FP32 biases.
+struct ModelDev {
+  const uint2* w1 = nullptr;  // [4 ob][64 lanes]      (inputs padded 7 -> 16)
+  const uint2* w2 = nullptr;  // [4 ob][4 kb][64 lanes]
+  const uint2* w3 = nullptr;  // [2 ob][4 kb][64 lanes]
+  const float* b1 = nullptr;  // [64]
+  const float* b2 = nullptr;  // [64]
+  const float* b3 = nullptr;  // [32]
+};
+constexpr int kModelW1 = 4 * 64, kModelW2 = 16 * 64, kModelW3 = 8 * 64;  // uint2 fragments
+constexpr size_t kModelBytes = (size_t)(kModelW1 + kModelW2 + kModelW3) * 8 + 160 * 4;
 
 // History node: written once per Kalman update (the filtered state there).
 struct alignas(16) Node {

@@ -13,6 +13,7 @@
 //  k_propagate_batch, k_kf_update_batch: single-step component kernels.
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
+#include "ckf_mlp.hpp"
 
 namespace ckf {
 
@@ -64,11 +65,12 @@ __global__ void k_meas_scatter(long long n_meas, const int* __restrict__ offsets
 // per-call initialisation (a fill kernel, so the sequence can be captured)
 
 __global__ void k_init(int n_seeds, int* res_node, int* res_nm, int* queue_head, unsigned long long* node_count,
-                       int* status, long long* counters, int* n_tracks, int* offsets) {
+                       int* status, long long* counters, int* n_tracks, int* offsets, int* seed_flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_seeds) {
     res_node[i] = -1;
     res_nm[i] = 0;
+    if (seed_flags) seed_flags[i] = 0;
   }
   if (i == 0) {
     *queue_head = 0;
@@ -216,7 +218,8 @@ constexpr int kMaxSlots = 64;
 
 // kCount: the instrumented variant that accumulates the work-unit counters
 // (used once to measure the algorithmic work; the work is deterministic).
-template <int kMinWaves, bool kCount>
+// kLearned: the learned-proposal form (network inference in the navigation).
+template <int kMinWaves, bool kCount, bool kLearned>
 __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   __shared__ int sh_seed[kMaxSlots], sh_event[kMaxSlots], sh_live[kMaxSlots], sh_step[kMaxSlots];
   __shared__ int sh_best_node[kMaxSlots], sh_best_nm[kMaxSlots], sh_best_holes[kMaxSlots];
@@ -227,6 +230,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
 
   __shared__ LayerRec sh_layers[kMaxLayers];
   __shared__ int sh_order[3][kMaxLayers];
+  __shared__ unsigned short sh_x[kLearned ? kWave * 8 : 1];  // network inputs (bf16), one row per lane
 
   const CfgDev& cfg = A.cfg;
   const int lane = lane_id();
@@ -349,70 +353,184 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       bool moved = false;
       float J[5][5];
       long long t_phase = kCount ? clock64() : 0;
+      if (kCount && lane == 0) CNT_ADD(CKF_CNT_CHUNKS, 1);
 
       // ---- phase 1: navigation and the propagation leg (FP32); the changed
-      // navigation state is written back into the candidate's own record
-      if (act) {
+      // navigation state is written back into the candidate's own record.
+      // Stage A: the next layer; then (learned form) the network for all
+      // lanes together; stage B: module listing and the leg.
+      double p[5];
+      int surf = -1, nlist = 0, root = 0;
+      unsigned long long mask = 0;
+      int list[kMaxList];
+      float h = 0.f, path = 0.f;
+      Module Am;
+      Leg L;
+      V3 uA, vA, origin, Pl, Tl;
+      bool go = false, need_list = false;
+      int lay = 0, excl = -1, nb_slot = -1;
+      float sb = 0.f;
+      long long t_nav = 0;
+      int prop[3] = {-1, -1, -1};
+      bool confident = false;
+      auto stage_a = [&]() {
         CNT_ADD(CKF_CNT_STEPS, 1);
-        double p[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
-        int surf = PIr(Pin, r, PI_SURF);
+        surf = PIr(Pin, r, PI_SURF);
         const int nlp = PIr(Pin, r, PI_NLIST);
-        int nlist = nlp & 0xff;
-        const int root = nlp >> 8;
-        unsigned long long mask = (unsigned long long)(unsigned)PIr(Pin, r, PI_MASK_LO) |
-                                  ((unsigned long long)(unsigned)PIr(Pin, r, PI_MASK_HI) << 32);
-        int list[kMaxList];
+        nlist = nlp & 0xff;
+        root = nlp >> 8;
+        mask = (unsigned long long)(unsigned)PIr(Pin, r, PI_MASK_LO) |
+               ((unsigned long long)(unsigned)PIr(Pin, r, PI_MASK_HI) << 32);
 #pragma unroll
         for (int k = 0; k < kMaxList; ++k) list[k] = PIr(Pin, r, (PI_LIST + k));
-        float h = PFr(Pin, r, PF_H), path = PFr(Pin, r, PF_PATH);
-        long long t_nav = kCount ? clock64() : 0;
+        h = PFr(Pin, r, PF_H);
+        path = PFr(Pin, r, PF_PATH);
+        if (kCount) t_nav = clock64();
+        // the start module and the leg's initial free state are the same for
+        // the seed's listing, the next-layer search and the leg itself
+        load_module(g, surf, Am);
+        leg_start(Am, p, L, uA, vA);
+        origin = ld3(Am.c);
+        go = !root;
+        // one listing call for both the seed's own layer and a newly found
+        // layer, so that a wave holding both kinds of lanes lists once
+        need_list = root;
+        lay = Am.layer;
+        excl = surf;
+        Pl = origin + L.r;
+        Tl = L.T;
         if (root) {
-          Module M;
-          load_module(g, surf, M);
-          Leg L;
-          V3 uA, vA;
-          leg_start(M, p, L, uA, vA);
-          const V3 P = ld3(M.c) + L.r;
-          const V3 k = (kKappa * L.lam) * cross(L.T, field_at(A.f, P));
-          int nt = 0, ovf = 0;
-          nlist = list_layer(g, M.layer, P, L.T, k, 0.f, surf, margin, list, nt, ovf);
-          CNT_ADD(CKF_CNT_NAV_MODULES, nt);
-          CNT_ADD(kNavOvf, ovf);
           outcome = 2;
-        } else {
-          bool go = true;
-          if (nlist == 0) {
-            Module Cm;
-            load_module(g, surf, Cm);
-            Leg L;
-            V3 uA, vA;
-            leg_start(Cm, p, L, uA, vA);
-            const V3 P = ld3(Cm.c) + L.r;
-            const V3 Bf = field_at(A.f, P);
-            const Helix H = make_helix(P, L.T, L.lam, Bf);
-            float sL;
-            CNT_ADD(CKF_CNT_NAV, 1);
-            const int nl = next_layer(g, H, mask, cfg.path_max - path, sL);
-            if (nl < 0) {
-              outcome = 3;
-              go = false;
-            } else {
-              mask |= 1ull << nl;
-              V3 Ps, Ts;
-              helix_at(H, sL, Ps, Ts);
-              const V3 ks = (kKappa * L.lam) * cross(Ts, Bf);
-              int nt = 0, ovf = 0;
-              nlist = list_layer(g, nl, Ps, Ts, ks, sL, -1, margin, list, nt, ovf);
-              CNT_ADD(CKF_CNT_NAV_MODULES, nt);
-              CNT_ADD(kNavOvf, ovf);
-              if (nlist == 0) {
-                outcome = 1;  // the layer is crossed in a gap
-                go = false;
+        } else if (nlist == 0) {
+          const V3 Bf = field_at(A.f, Pl);
+          const Helix H = make_helix(Pl, L.T, L.lam, Bf);
+          float sL;
+          CNT_ADD(CKF_CNT_NAV, 1);
+          const long long t_next = kCount ? clock64() : 0;
+          const int nl = next_layer(g, H, mask, cfg.path_max - path, sL);
+          if (kCount) CNT_ADD(CKF_CNT_CYC_NEXT, (int)(clock64() - t_next));
+          if (nl < 0) {
+            outcome = 3;
+            go = false;
+          } else {
+            mask |= 1ull << nl;
+            helix_at(H, sL, Pl, Tl);
+            need_list = true;
+            lay = nl;
+            excl = -1;
+            sb = sL;
+            if (kLearned) {
+#pragma unroll
+              for (int q = 0; q < kMaxNext; ++q)
+                if (nb_slot < 0 && g.nb_next[surf * kMaxNext + q] == nl) nb_slot = q;
+              if (nb_slot >= 0) {  // the network input goes to LDS now
+                float f[7];
+                mlp_features(Am, p, lay, g.n_layers, f);
+#pragma unroll
+                for (int c = 0; c < 7; ++c) sh_x[lane * 8 + c] = bf16_bits(f[c]);
+                sh_x[lane * 8 + 7] = 0;
               }
             }
           }
+        }
+      };
+      // learned proposal: the network for every lane that found a next layer
+      // listed in its module's neighbour table, 16 rows per MFMA pass
+      auto proposal = [&]() {
+        const unsigned long long wm = __ballot(nb_slot >= 0);
+        if (wm) {
+          if (nb_slot < 0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) sh_x[lane * 8 + c] = 0;
+          }
+          __syncthreads();
+          const int q4 = 4 * (lane >> 4);
+          Top3 mine;
+          float conf = 0.f;
+#pragma unroll 1
+          for (int rb = 0; rb < 4; ++rb) {
+            if (((wm >> (16 * rb)) & 0xffffull) == 0) continue;
+            bf16x4 xb;
+            const int src = (16 * rb + (lane & 15)) * 8 + q4;
+            xb.x = q4 < 8 ? (short)sh_x[src + 0] : (short)0;
+            xb.y = q4 < 8 ? (short)sh_x[src + 1] : (short)0;
+            xb.z = q4 < 8 ? (short)sh_x[src + 2] : (short)0;
+            xb.w = q4 < 8 ? (short)sh_x[src + 3] : (short)0;
+            f32x4 out[2];
+            mlp_block(A.model, xb, lane, out);
+            Top3 t;
+            float c;
+            mlp_top3(out, lane, cfg.topk, t, c);
+            if ((lane >> 4) == rb) {
+              mine = t;
+              conf = c;
+            }
+            if (kCount && lane == 0) CNT_ADD(CKF_CNT_MLP_BLOCKS, 1);
+          }
+          __syncthreads();
+          if (nb_slot >= 0) {
+            CNT_ADD(CKF_CNT_MLP_ROWS, 1);
+            confident = conf >= cfg.min_prob;
+            const int* nb = g.nb_mod + ((long long)surf * kMaxNext + nb_slot) * kNeighbours;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)  // (a class outside 0..31 only if the logits were not finite)
+              if (k < cfg.topk && mine.c[k] >= 0 && mine.c[k] < kNeighbours) prop[k] = nb[mine.c[k]];
+            confident = confident && prop[0] >= 0;
+          }
+        }
+      };
+      auto stage_b = [&]() {
+        if (kLearned) {
+          // recomputed rather than kept in registers across the network
+          load_module(g, surf, Am);
+          leg_start(Am, p, L, uA, vA);
+          origin = ld3(Am.c);
+        }
+        if (need_list) {
+          const V3 kl = (kKappa * L.lam) * cross(Tl, field_at(A.f, Pl));
+          int nt = 0, ovf = 0;
+          bool listed = false;
+          if (kLearned && confident) {
+            // the proposed modules through the same listing test
+            ListAcc acc;
+            list_init(acc);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              if (prop[k] < 0) continue;
+              Module Mp;
+              load_module(g, prop[k], Mp);
+              list_test(acc, prop[k], Mp, Pl, Tl, kl, sb, margin, nt);
+            }
+            const int np = list_out(acc, list);
+            if (np > 0) {
+              listed = true;
+              nlist = np;
+              CNT_ADD(CKF_CNT_PROPOSALS, 1);
+              if (kCount) {  // audit against the geometric listing
+                int full[kMaxList];
+                int nt2 = 0, ovf2 = 0;
+                const int nf = list_layer(g, lay, Pl, Tl, kl, sb, excl, margin, full, nt2, ovf2);
+                bool same = nf == np;
+#pragma unroll
+                for (int k = 0; k < kMaxList; ++k) same = same && full[k] == list[k];
+                if (!same) {
+                  CNT_ADD(CKF_CNT_PROPOSAL_MISS, 1);
+                  if (A.seed_flags) A.seed_flags[sh_seed[slot]] = 1;
+                }
+              }
+            }
+          }
+          if (!listed) nlist = list_layer(g, lay, Pl, Tl, kl, sb, excl, margin, list, nt, ovf);
+          CNT_ADD(CKF_CNT_NAV_MODULES, nt);
+          CNT_ADD(kNavOvf, ovf);
+          if (!root && nlist == 0) {
+            outcome = 1;  // the layer is crossed in a gap
+            go = false;
+          }
+        }
+        if (!root) {
           if (kCount) {  // navigation time of this lane (summed over lanes, divided later)
             const long long t = clock64();
             CNT_ADD(CKF_CNT_CYC_NAV, (int)(t - t_nav));
@@ -424,13 +542,8 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             for (int k = 0; k < kMaxList - 1; ++k) list[k] = list[k + 1];
             list[kMaxList - 1] = -1;
             --nlist;
-            Module Am, Bm;
-            load_module(g, surf, Am);
+            Module Bm;
             load_module(g, m, Bm);
-            Leg L;
-            V3 uA, vA;
-            leg_start(Am, p, L, uA, vA);
-            const V3 origin = ld3(Am.c);
             const V3 dB = ld3(Bm.c) - origin;
             LegStats ls{0, 0};
             CNT_ADD(CKF_CNT_LEGS, 1);
@@ -464,6 +577,15 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         for (int k = 0; k < kMaxList; ++k) PIr(Pin, r, (PI_LIST + k)) = list[k];
         PFr(Pin, r, PF_H) = h;
         PFr(Pin, r, PF_PATH) = path;
+      };
+      if (kLearned) {
+        // the network runs with all lanes together between the two stages
+        if (act) stage_a();
+        proposal();
+        if (act) stage_b();
+      } else if (act) {
+        stage_a();
+        stage_b();
       }
 
       if (kCount && lane == 0) {
@@ -867,8 +989,12 @@ __global__ __launch_bounds__(kScanBlock) void k_out_write(int n, const int* res_
   for (int k = 0; k < 15; ++k) out.cov[15 * t + k] = last.cov[k];
   out.last_surface[t] = last.surface;
   for (int k = nm - 1; k >= 0 && nd >= 0 && nd < node_cap; --k) {
-    out.meas[mo + k] = nodes[nd].meas;
-    nd = nodes[nd].parent;
+    const Node& q = nodes[nd];
+    out.meas[mo + k] = q.meas;
+    if (out.meas_surface) out.meas_surface[mo + k] = q.surface;
+    if (out.meas_params)
+      for (int c = 0; c < 5; ++c) out.meas_params[5 * (mo + k) + c] = q.p[c];
+    nd = q.parent;
   }
   out.chi2[t] = res_chi2[s];
   out.ndf[t] = 2 * nm - 5;
@@ -939,7 +1065,8 @@ __global__ void k_kf_update_batch(int n, const double* p_in, const double* cov_i
 hipError_t launch_init(int n_seeds, const Workspace& w, const ckf_tracks& out, hipStream_t st) {
   const int n = n_seeds > 64 ? n_seeds : 64;
   hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, st, n_seeds, w.res_node, w.res_nm, w.queue_head,
-                     w.node_count, out.status, reinterpret_cast<long long*>(out.counters), out.n_tracks, out.offsets);
+                     w.node_count, out.status, reinterpret_cast<long long*>(out.counters), out.n_tracks, out.offsets,
+                     out.seed_flags);
   return hipGetLastError();
 }
 
@@ -958,12 +1085,20 @@ hipError_t launch_ckf(const CkfArgs& a, int waves_per_simd, hipStream_t st) {
   const dim3 grid(a.w.grid), block(kWave);
   // 3 or 4 waves per SIMD would need register spills; those builds were
   // slower and not bitwise identical to these, so they are not offered.
-  if (a.counters) {
-    hipLaunchKernelGGL((k_ckf<1, true>), grid, block, 0, st, a);
-  } else if (waves_per_simd >= 2) {
-    hipLaunchKernelGGL((k_ckf<2, false>), grid, block, 0, st, a);
+  if (a.learned) {
+    if (a.counters)
+      hipLaunchKernelGGL((k_ckf<1, true, true>), grid, block, 0, st, a);
+    else if (waves_per_simd >= 2)
+      hipLaunchKernelGGL((k_ckf<2, false, true>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_ckf<1, false, true>), grid, block, 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_ckf<1, false>), grid, block, 0, st, a);
+    if (a.counters)
+      hipLaunchKernelGGL((k_ckf<1, true, false>), grid, block, 0, st, a);
+    else if (waves_per_simd >= 2)
+      hipLaunchKernelGGL((k_ckf<2, false, false>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_ckf<1, false, false>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }

@@ -29,6 +29,9 @@ struct CkfArgs {
   Workspace w;
   int* status;
   long long* counters;
+  bool learned;       // the learned-proposal form (model valid)
+  ModelDev model;
+  int* seed_flags;    // audit output of the instrumented learned form, or null
 };
 
 hipError_t launch_init(int n_seeds, const Workspace& w, const ckf_tracks& out, hipStream_t st);
@@ -39,6 +42,17 @@ hipError_t launch_output(int n_seeds, const Workspace& w, const int* seed_event,
 hipError_t launch_propagate(const GeomDev& g, const FieldDev& f, const CfgDev& c, int n, const int* src,
                             const double* p_in, const double* cov_in, const int* dst, double* p_out,
                             double* cov_out, double* jac, double* path, int* ok, hipStream_t st);
+hipError_t launch_model_pack(const float* params, void* out, hipStream_t st);
+ModelDev model_view(const void* buf);
+hipError_t launch_mlp_forward(const ModelDev& M, const float* x, long long n, float* logits, hipStream_t st);
+size_t mlp_workspace_bytes(long long n);
+hipError_t launch_mlp_grad(const float* params, const float* x, const int* labels, const int* rows, long long n,
+                           void* ws, float* grad, float* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, int step, float lr, float b1,
+                           float b2, float eps, hipStream_t st);
+hipError_t launch_capture_pairs(const GeomDev& g, const int* n_tracks, int cap_tracks, const int* off,
+                                const int* msurf, const double* mpar, long long cap_pairs, float* x, int* label,
+                                int* track, long long* counts, hipStream_t st);
 hipError_t launch_kf_update(int n, const double* p_in, const double* cov_in, const float* meas, const float* var,
                             double* p_out, double* cov_out, double* chi2, hipStream_t st);
 

@@ -1,0 +1,190 @@
+// The next-module network on the gfx950 matrix cores (device code shared by
+// the track-finding kernel and the training kernels).
+//
+// The network runs transposed, features x rows: Z^T = W . X^T + b, so that
+// one 16x16x16 bf16 MFMA (v_mfma_f32_16x16x16_bf16) takes a weight tile as
+// its A operand and 16 rows' activations as its B operand.  With that
+// operand order the 16x16 result tile of one layer (lane l: features
+// 4*(l/16)+j of row l%16) is exactly the B operand of the next layer, so a
+// 16-row block goes through all three layers in registers.
+#pragma once
+#include "ckf_device.hpp"
+
+namespace ckf {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16, round to nearest, ties to even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ __forceinline__ bf16x4 pack_bf16(f32x4 v) {
+  bf16x4 r;
+  r.x = (short)bf16_bits(v.x);
+  r.y = (short)bf16_bits(v.y);
+  r.z = (short)bf16_bits(v.z);
+  r.w = (short)bf16_bits(v.w);
+  return r;
+}
+
+__device__ __forceinline__ bf16x4 relu_bf16(f32x4 v) {
+  v.x = fmaxf(v.x, 0.f);
+  v.y = fmaxf(v.y, 0.f);
+  v.z = fmaxf(v.z, 0.f);
+  v.w = fmaxf(v.w, 0.f);
+  return pack_bf16(v);
+}
+
+__device__ __forceinline__ bf16x4 as_bf16x4(uint2 u) {
+  bf16x4 r;
+  r.x = (short)(u.x & 0xffffu);
+  r.y = (short)(u.x >> 16);
+  r.z = (short)(u.y & 0xffffu);
+  r.w = (short)(u.y >> 16);
+  return r;
+}
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 ld_f4(const float* p) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  f32x4 r;
+  r.x = v.x;
+  r.y = v.y;
+  r.z = v.z;
+  r.w = v.w;
+  return r;
+}
+
+// Logits of one 16-row block.  xb: this lane's B operand of the input
+// (features 4*(l/16)..+3 of row l%16, zero beyond the 7 inputs).  Must be
+// called by all 64 lanes together.  out[ob] holds classes 16*ob + 4*(l/16)
+// + j of row l%16.
+__device__ __forceinline__ void mlp_block(const ModelDev& M, bf16x4 xb, int lane, f32x4 out[2]) {
+  const int q4 = 4 * (lane >> 4);
+  bf16x4 h1[4], h2[4];
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    f32x4 acc = ld_f4(M.b1 + 16 * ob + q4);
+    acc = mfma16(as_bf16x4(M.w1[ob * 64 + lane]), xb, acc);
+    h1[ob] = relu_bf16(acc);
+  }
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    f32x4 acc = ld_f4(M.b2 + 16 * ob + q4);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc = mfma16(as_bf16x4(M.w2[(ob * 4 + kb) * 64 + lane]), h1[kb], acc);
+    h2[ob] = relu_bf16(acc);
+  }
+#pragma unroll
+  for (int ob = 0; ob < 2; ++ob) {
+    f32x4 acc = ld_f4(M.b3 + 16 * ob + q4);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc = mfma16(as_bf16x4(M.w3[(ob * 4 + kb) * 64 + lane]), h2[kb], acc);
+    out[ob] = acc;
+  }
+}
+
+// Network input for the state on module M with bound parameters p, asking
+// for layer `target`: loc0/10, loc1/30, the unit direction in the module's
+// (u, v, n) frame, q/p in 1/GeV, target / n_layers.
+__device__ __forceinline__ void mlp_features(const Module& M, const double* p, int target, int n_layers,
+                                             float x[7]) {
+  float sp, cp, st, ct;
+  sincosf((float)p[2], &sp, &cp);
+  sincosf((float)p[3], &st, &ct);
+  const V3 T = {cp * st, sp * st, ct};
+  x[0] = (float)p[0] * 0.1f;
+  x[1] = (float)p[1] * (1.0f / 30.0f);
+  x[2] = dot(ld3(M.u), T);
+  x[3] = dot(ld3(M.v), T);
+  x[4] = dot(ld3(M.n), T);
+  x[5] = (float)p[4];
+  x[6] = (float)target / (float)n_layers;
+}
+
+// Sorted top-3 (value descending, class ascending) of (v, c) pairs.
+struct Top3 {
+  float v[3];
+  int c[3];
+};
+
+__device__ __forceinline__ bool top_before(float va, int ca, float vb, int cb) {
+  return va > vb || (va == vb && ca < cb);
+}
+
+__device__ __forceinline__ void top_insert(Top3& t, float v, int c) {
+  if (!top_before(v, c, t.v[2], t.c[2])) return;
+  if (top_before(v, c, t.v[1], t.c[1])) {
+    t.v[2] = t.v[1];
+    t.c[2] = t.c[1];
+    if (top_before(v, c, t.v[0], t.c[0])) {
+      t.v[1] = t.v[0];
+      t.c[1] = t.c[0];
+      t.v[0] = v;
+      t.c[0] = c;
+    } else {
+      t.v[1] = v;
+      t.c[1] = c;
+    }
+  } else {
+    t.v[2] = v;
+    t.c[2] = c;
+  }
+}
+
+// Softmax statistics and the top-3 classes of each row of a block: the four
+// lanes holding one row (l, l^16, l^32, l^48) all end with the same result.
+// conf = summed probability of the first k (1..3) of the top three.
+__device__ __forceinline__ void mlp_top3(const f32x4 out[2], int lane, int k, Top3& t, float& conf) {
+  const int q4 = 4 * (lane >> 4);
+  float vals[8];
+#pragma unroll
+  for (int ob = 0; ob < 2; ++ob) {
+    vals[4 * ob + 0] = out[ob].x;
+    vals[4 * ob + 1] = out[ob].y;
+    vals[4 * ob + 2] = out[ob].z;
+    vals[4 * ob + 3] = out[ob].w;
+  }
+  float mx = vals[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) mx = fmaxf(mx, vals[i]);
+  mx = fmaxf(mx, __shfl_xor(mx, 16));
+  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s += __expf(vals[i] - mx);
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  t.v[0] = t.v[1] = t.v[2] = -INFINITY;
+  t.c[0] = t.c[1] = t.c[2] = 1 << 20;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) top_insert(t, vals[i], 16 * (i >> 2) + q4 + (i & 3));
+#pragma unroll
+  for (int x = 16; x <= 32; x <<= 1) {
+    float ov[3];
+    int oc[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      ov[j] = __shfl_xor(t.v[j], x);
+      oc[j] = __shfl_xor(t.c[j], x);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) top_insert(t, ov[j], oc[j]);
+  }
+  float num = 0.f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (j < k) num += __expf(t.v[j] - mx);
+  conf = num / s;
+}
+
+}  // namespace ckf

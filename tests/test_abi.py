@@ -74,8 +74,12 @@ def test_host_side_validation(lib):
     cfg = _abi.Config()
     lib.ckf_config_default(C.byref(cfg))
     assert cfg.chi2_max == 15.0 and cfg.branches_per_surface == 3 and cfg.tracks_per_seed == 1
+    assert cfg.learned_min_prob == 0.95 and cfg.learned_topk == 3
     nb = C.c_size_t(0)
     assert lib.ckf_workspace_size(None, C.byref(cfg), None, 1, 1, 1, C.byref(nb)) == 1
-    assert lib.ckf_find(None, None, None, None, C.byref(cfg), None, None, 0, None, None) == 1
+    assert lib.ckf_find(None, None, None, None, C.byref(cfg), None, None, None, 0, None, None) == 1
+    assert lib.ckf_mlp_workspace_size(0, C.byref(nb)) == 1
+    assert lib.ckf_model_create(None, None, C.byref(h)) == 1
+    assert lib.ckf_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == 1
     assert lib.ckf_kf_update_batch(-1, None, None, None, None, None, None, None, None) == 1
     assert lib.ckf_status_string(5) == b"not supported"

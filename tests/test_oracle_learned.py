@@ -232,3 +232,24 @@ def test_pairs_from_oracle_tracks(tiny_truth):
         assert nbr[m, s, lab[k]] == m2
         assert off[trk[k]] <= pos[k] < off[trk[k] + 1] - 1
     np.testing.assert_array_equal(x, OL.features(g, ms[pos], mp[pos], layer[ms[pos + 1]]))
+
+
+def test_bf16_gradient_mode_stays_close():
+    """The bf16-rounding mode of the gradient (the precision of the matrix-core
+    kernels) stays close to the FP64 gradient, and equals it when every
+    rounded quantity is already a bf16 value (zero hidden layers' input)."""
+    params, x, labels = _rand_problem(n=50, seed=8)
+    _, g = OL.loss_and_grad(params, x, labels)
+    _, gb = OL.loss_and_grad(params, x, labels, bf16=True)
+    assert g @ gb / (np.linalg.norm(g) * np.linalg.norm(gb)) > 0.999
+    P = OL.unpack_params(params)
+    for k in ("W1", "W2", "W3"):
+        P[k][:] = OL.bf16_round(P[k])
+    P["W3"][:] = 0.0  # backpropagated gradients vanish below the output layer
+    p2 = OL.pack_params(P)
+    x2 = OL.bf16_round(np.zeros_like(x))
+    l1, g1 = OL.loss_and_grad(p2, x2, labels)
+    l2, g2 = OL.loss_and_grad(p2, x2, labels, bf16=True)
+    G1, G2 = OL.unpack_params(g1), OL.unpack_params(g2)
+    np.testing.assert_array_equal(G1["b3"], G2["b3"])
+    assert l1 == l2
