@@ -42,7 +42,19 @@ class _Geometry(C.Structure):
 
 
 class _Field(C.Structure):
-    _fields_ = [("b", C.c_double * 3)]
+    _fields_ = [("b", C.c_double * 3), ("map", C.c_void_p), ("nr", C.c_int32), ("nz", C.c_int32),
+                ("r0", C.c_double), ("z0", C.c_double), ("dr", C.c_double), ("dz", C.c_double)]
+
+
+def make_field(bfield):
+    """A uniform field (3-tuple, tesla) or a map dict (synth.field); returns
+    (struct, keep-alive)."""
+    if isinstance(bfield, dict):
+        m = np.ascontiguousarray(bfield["map"], np.float32)
+        f = _Field((C.c_double * 3)(0, 0, 0), m.ctypes.data, int(bfield["nr"]), int(bfield["nz"]),
+                   float(bfield["r0"]), float(bfield["z0"]), float(bfield["dr"]), float(bfield["dz"]))
+        return f, m
+    return _Field((C.c_double * 3)(*bfield), None, 0, 0, 0.0, 0.0, 1.0, 1.0), None
 
 
 class _Meas(C.Structure):
@@ -115,7 +127,8 @@ class Inputs:
         self.geom = _Geometry(g["center"].shape[0], _p(g["center"]), _p(g["rot"]), _p(g["half"]),
                               _p(g["thick"]), _p(g["layer"]), g["layer_type"].shape[0],
                               _p(g["layer_type"]), _p(g["layer_pos"]), _p(g["layer_lo"]), _p(g["layer_hi"]))
-        self.field = _Field((C.c_double * 3)(*bfield))
+        self.field, fkeep = make_field(bfield)
+        self.keep.append(fkeep)
         if event is not None:
             self.set_event(event)
 
@@ -187,7 +200,7 @@ def propagate(inp: Inputs, src, params, cov, dst, **cfg):
 
 def propagate_free(bfield, free, center, normal, **cfg):
     conf, _ = make_config(**cfg)
-    f = _Field((C.c_double * 3)(*bfield))
+    f, _keep = make_field(bfield)
     fi = np.ascontiguousarray(free, np.float64)
     cc = np.ascontiguousarray(center, np.float64)
     nn = np.ascontiguousarray(normal, np.float64)
@@ -259,3 +272,16 @@ def unpack_cov(c15):
 def pack_cov(M):
     M = np.asarray(M)
     return np.stack([M[..., i, j] for (i, j) in PACKED], -1)
+
+
+def field_eval(bfield, points, grad=False):
+    """The oracle's field (and gradient of the interpolant) at points [n, 3]."""
+    f, keep = make_field(bfield)
+    p = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+    B = np.zeros_like(p)
+    G = np.zeros((p.shape[0], 3, 3)) if grad else None
+    rc = lib().orc_field_eval(C.byref(f), p.shape[0], _p(p), _p(B), _p(G))
+    del keep
+    if rc != 0:
+        raise RuntimeError("orc_field_eval failed")
+    return (B, G) if grad else B

@@ -121,10 +121,92 @@ Geometry load_geometry(const orc_geometry* g) {
   return G;
 }
 
+// Field: uniform, or bilinear interpolation of an (r, z) map of (B_r, B_z)
+// with coordinates clamped to the grid (the grid is the field's definition).
 struct Field {
-  V3 b;
-  V3 at(V3) const { return b; }  // uniform field
+  V3 b{0, 0, 0};
+  const float* map = nullptr;
+  int nr = 0, nz = 0;
+  double r0 = 0, z0 = 0, dr = 1, dz = 1;
+
+  // cell, fractions and whether the coordinate was clamped
+  void cell(double u, int n, int& i, double& f, bool& clamped) const {
+    clamped = false;
+    if (u <= 0) {
+      u = 0;
+      clamped = true;
+    } else if (u >= n - 1) {
+      u = n - 1;
+      clamped = true;
+    }
+    i = std::min((int)std::floor(u), n - 2);
+    f = u - i;
+  }
+  double node(int ir, int iz, int c) const { return map[((size_t)iz * nr + ir) * 2 + c]; }
+
+  V3 at(V3 p) const {
+    V3 B;
+    double G[3][3];
+    eval(p, B, G, false);
+    return B;
+  }
+  // B at p and, if want_grad, G[i][j] = dB_i/dx_j (of the interpolant)
+  void eval(V3 p, V3& B, double G[3][3], bool want_grad) const {
+    if (!map) {
+      B = b;
+      if (want_grad)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) G[i][j] = 0;
+      return;
+    }
+    const double r = std::hypot(p.x, p.y);
+    int ir, iz;
+    double fr, fz;
+    bool cr, cz;
+    cell((r - r0) / dr, nr, ir, fr, cr);
+    cell((p.z - z0) / dz, nz, iz, fz, cz);
+    double v[2], vr[2], vz[2];
+    for (int c = 0; c < 2; ++c) {
+      const double a = node(ir, iz, c), bb = node(ir + 1, iz, c), cc = node(ir, iz + 1, c),
+                   d = node(ir + 1, iz + 1, c);
+      v[c] = (1 - fr) * (1 - fz) * a + fr * (1 - fz) * bb + (1 - fr) * fz * cc + fr * fz * d;
+      vr[c] = cr ? 0.0 : ((1 - fz) * (bb - a) + fz * (d - cc)) / dr;
+      vz[c] = cz ? 0.0 : ((1 - fr) * (cc - a) + fr * (d - bb)) / dz;
+    }
+    const double cx = r > 0 ? p.x / r : 0.0, sy = r > 0 ? p.y / r : 0.0;
+    B = {v[0] * cx, v[0] * sy, v[1]};
+    if (!want_grad) return;
+    // chain rule through r = hypot(x, y): d(cx)/dx = sy^2/r, d(cx)/dy = -cx sy/r, ...
+    const double ir_ = r > 0 ? 1.0 / r : 0.0;
+    G[0][0] = vr[0] * cx * cx + v[0] * sy * sy * ir_;
+    G[0][1] = vr[0] * cx * sy - v[0] * cx * sy * ir_;
+    G[0][2] = vz[0] * cx;
+    G[1][0] = vr[0] * cx * sy - v[0] * cx * sy * ir_;
+    G[1][1] = vr[0] * sy * sy + v[0] * cx * cx * ir_;
+    G[1][2] = vz[0] * sy;
+    G[2][0] = vr[1] * cx;
+    G[2][1] = vr[1] * sy;
+    G[2][2] = vz[1];
+  }
 };
+
+V3 mat_vec(const double G[3][3], V3 d) {
+  return {G[0][0] * d.x + G[0][1] * d.y + G[0][2] * d.z, G[1][0] * d.x + G[1][1] * d.y + G[1][2] * d.z,
+          G[2][0] * d.x + G[2][1] * d.y + G[2][2] * d.z};
+}
+
+Field load_field(const orc_field* f) {
+  Field F;
+  F.b = {f->b[0], f->b[1], f->b[2]};
+  F.map = f->map;
+  F.nr = f->nr;
+  F.nz = f->nz;
+  F.r0 = f->r0;
+  F.z0 = f->z0;
+  F.dr = f->dr;
+  F.dz = f->dz;
+  return F;
+}
 
 struct Cfg {
   double chi2_max, step_tol, step_max, land_tol, path_max, nav_margin, mass;
@@ -261,33 +343,42 @@ Tangents bound_to_free_jacobian(const Surface& S, const double* p) {
 double rkn4_step(const Field& F, const Free& f, const Tangents& J, double h, Free& fo, Tangents& Jo) {
   const double lam = f.qop;
   const V3 r = f.r, T = f.T;
-  const V3 B1 = F.at(r);
+  V3 B1, B2, B4;
+  double G1[3][3], G2[3][3], G4[3][3];
+  const bool grad = F.map != nullptr;  // a uniform field has no position derivative
+  F.eval(r, B1, G1, grad);
   const V3 k1 = (kKappa * lam) * cross(T, B1);
   const V3 rm = r + (0.5 * h) * T + (h * h / 8.0) * k1;
-  const V3 B2 = F.at(rm);
+  F.eval(rm, B2, G2, grad);
   const V3 T2 = T + (0.5 * h) * k1;
   const V3 k2 = (kKappa * lam) * cross(T2, B2);
   const V3 T3 = T + (0.5 * h) * k2;
   const V3 k3 = (kKappa * lam) * cross(T3, B2);
   const V3 re = r + h * T + (0.5 * h * h) * k3;
-  const V3 B4 = F.at(re);
+  F.eval(re, B4, G4, grad);
   const V3 T4 = T + h * k3;
   const V3 k4 = (kKappa * lam) * cross(T4, B4);
   fo.r = r + h * T + (h * h / 6.0) * (k1 + k2 + k3);
   fo.T = T + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
   fo.qop = lam;
   for (int j = 0; j < 5; ++j) {
-    // Uniform field: B does not depend on r, so only dT and dlambda enter.
-    const V3 dT = J[j].dT;
+    // d k = kappa (dl T x B + lam dT x B + lam T x (dB/dr . d(stage point)))
+    const V3 dr = J[j].dr, dT = J[j].dT;
     const double dl = J[j].dl;
-    const V3 dk1 = kKappa * (dl * cross(T, B1) + lam * cross(dT, B1));
+    V3 dk1 = kKappa * (dl * cross(T, B1) + lam * cross(dT, B1));
+    if (grad) dk1 = dk1 + (kKappa * lam) * cross(T, mat_vec(G1, dr));
+    const V3 drm = dr + (0.5 * h) * dT + (h * h / 8.0) * dk1;
     const V3 dT2 = dT + (0.5 * h) * dk1;
-    const V3 dk2 = kKappa * (dl * cross(T2, B2) + lam * cross(dT2, B2));
+    V3 dk2 = kKappa * (dl * cross(T2, B2) + lam * cross(dT2, B2));
+    if (grad) dk2 = dk2 + (kKappa * lam) * cross(T2, mat_vec(G2, drm));
     const V3 dT3 = dT + (0.5 * h) * dk2;
-    const V3 dk3 = kKappa * (dl * cross(T3, B2) + lam * cross(dT3, B2));
+    V3 dk3 = kKappa * (dl * cross(T3, B2) + lam * cross(dT3, B2));
+    if (grad) dk3 = dk3 + (kKappa * lam) * cross(T3, mat_vec(G2, drm));
+    const V3 dre = dr + h * dT + (0.5 * h * h) * dk3;
     const V3 dT4 = dT + h * dk3;
-    const V3 dk4 = kKappa * (dl * cross(T4, B4) + lam * cross(dT4, B4));
-    Jo[j].dr = J[j].dr + h * dT + (h * h / 6.0) * (dk1 + dk2 + dk3);
+    V3 dk4 = kKappa * (dl * cross(T4, B4) + lam * cross(dT4, B4));
+    if (grad) dk4 = dk4 + (kKappa * lam) * cross(T4, mat_vec(G4, dre));
+    Jo[j].dr = dr + h * dT + (h * h / 6.0) * (dk1 + dk2 + dk3);
     Jo[j].dT = dT + (h / 6.0) * (dk1 + 2.0 * dk2 + 2.0 * dk3 + dk4);
     Jo[j].dl = dl;
   }
@@ -803,13 +894,30 @@ void to_stats(const Stats& s, orc_stats* o) {
 
 }  // namespace
 
+extern "C" int orc_field_eval(const orc_field* f, int32_t n, const double* p, double* B, double* G) {
+  if (!f || !p || !B || n < 0) return ORC_ERR_ARG;
+  const Field F = load_field(f);
+  for (int i = 0; i < n; ++i) {
+    V3 b;
+    double g[3][3];
+    F.eval({p[3 * i], p[3 * i + 1], p[3 * i + 2]}, b, g, G != nullptr);
+    B[3 * i] = b.x;
+    B[3 * i + 1] = b.y;
+    B[3 * i + 2] = b.z;
+    if (G)
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) G[9 * i + 3 * a + c] = g[a][c];
+  }
+  return ORC_OK;
+}
+
 extern "C" int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc_measurements* m,
                             const orc_seeds* s, const orc_config* c, int n_threads, orc_tracks* out,
                             orc_stats* stats) {
   if (!g || !f || !m || !s || !c || !out) return ORC_ERR_ARG;
   if (g->n_layers > 64 || m->n_surfaces != g->n_surfaces) return ORC_ERR_ARG;
   const Geometry G = load_geometry(g);
-  const Field F{{f->b[0], f->b[1], f->b[2]}};
+  const Field F = load_field(f);
   const Cfg cfg = load_cfg(c);
   const int n = s->n_seeds;
   std::vector<SeedResult> res(n);
@@ -870,7 +978,7 @@ extern "C" int orc_propagate(const orc_geometry* g, const orc_field* f, const or
   if (!g || !f || !c || !p_in || !cov_in || !p_out || !cov_out) return ORC_ERR_ARG;
   if (src < 0 || dst < 0 || src >= g->n_surfaces || dst >= g->n_surfaces) return ORC_ERR_ARG;
   const Geometry G = load_geometry(g);
-  const Field F{{f->b[0], f->b[1], f->b[2]}};
+  const Field F = load_field(f);
   const Cfg cfg = load_cfg(c);
   Stats st;
   M5 Co, J;
@@ -885,7 +993,7 @@ extern "C" int orc_propagate(const orc_geometry* g, const orc_field* f, const or
 extern "C" int orc_propagate_free(const orc_field* f, const orc_config* c, const double* fin,
                                   const double* cc, const double* nn, double* fout, double* path) {
   if (!f || !c || !fin || !cc || !nn || !fout) return ORC_ERR_ARG;
-  const Field F{{f->b[0], f->b[1], f->b[2]}};
+  const Field F = load_field(f);
   const Cfg cfg = load_cfg(c);
   Stats st;
   Free fr{{fin[0], fin[1], fin[2]}, {fin[3], fin[4], fin[5]}, fin[6]};
@@ -913,7 +1021,7 @@ extern "C" int orc_trace(const orc_geometry* g, const orc_field* f, const orc_co
                          double* params_out) {
   if (!g || !f || !c || !params || !visited || !crossed) return -1;
   const Geometry G = load_geometry(g);
-  const Field F{{f->b[0], f->b[1], f->b[2]}};
+  const Field F = load_field(f);
   const Cfg cfg = load_cfg(c);
   Stats st;
   int cur = surface;
@@ -957,7 +1065,7 @@ extern "C" int orc_navigate(const orc_geometry* g, const orc_field* f, const orc
                             const double* params, uint64_t mask, double path, int32_t* list, int32_t* n_list) {
   if (!g || !f || !c || !params || !list || !n_list) return -2;
   const Geometry G = load_geometry(g);
-  const Field F{{f->b[0], f->b[1], f->b[2]}};
+  const Field F = load_field(f);
   const Cfg cfg = load_cfg(c);
   Stats st;
   std::vector<int> l;
@@ -981,7 +1089,7 @@ extern "C" int orc_seed_list(const orc_geometry* g, const orc_field* f, const or
                              const double* params, int32_t* list) {
   if (!g || !f || !c || !params || !list) return -1;
   const Geometry G = load_geometry(g);
-  const Field F{{f->b[0], f->b[1], f->b[2]}};
+  const Field F = load_field(f);
   const Cfg cfg = load_cfg(c);
   Stats st;
   const Free f0 = bound_to_free(G.s[surface], params);

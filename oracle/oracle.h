@@ -42,8 +42,15 @@ typedef struct orc_geometry {
   const float* layer_hi;     /* [L] z_max (barrel), r_max (disk) */
 } orc_geometry;
 
+/* Magnetic field, tesla: uniform b, or (map != NULL) a solenoidal map of
+ * (B_r, B_z) on a regular (r, z) grid - node (ir, iz) at r0 + ir*dr,
+ * z0 + iz*dz, values map[(iz*nr + ir)*2 + {0: B_r, 1: B_z}] - interpolated
+ * bilinearly, coordinates clamped to the grid; B_x,y = B_r x,y / r. */
 typedef struct orc_field {
-  double b[3];              /* uniform field, tesla */
+  double b[3];
+  const float* map;
+  int32_t nr, nz;
+  double r0, z0, dr, dz;
 } orc_field;
 
 typedef struct orc_measurements {
@@ -121,6 +128,10 @@ typedef struct orc_stats {
 #define ORC_ERR_ARG 1
 #define ORC_ERR_CAPACITY 3
 #define ORC_ERR_FAILED 7
+
+/* The field (tesla) at n points p [n][3] (mm), and if G is not NULL its
+ * gradient G [n][3][3] = dB_i/dx_j of the interpolant. */
+int orc_field_eval(const orc_field* f, int32_t n, const double* p, double* B, double* G);
 
 /* Track finding for every seed; n_threads <= 0 uses all hardware threads.
  * Output is ordered by seed index.  stats may be NULL. */

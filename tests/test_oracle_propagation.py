@@ -132,10 +132,14 @@ def test_zero_length_transport_is_identity(oracle_lib):
         assert abs(path) < 1e-12
 
 
-@pytest.mark.parametrize("B", [(0, 0, 2.0), (0.2, 0.1, 2.0), (0, 0, 0)])
+@pytest.mark.parametrize("B", [(0, 0, 2.0), (0.2, 0.1, 2.0), (0, 0, 0), "solenoid map"])
 def test_jacobian_matches_finite_differences(oracle_lib, B):
     """The transported bound-to-bound Jacobian equals central finite
-    differences of the propagate-to-plane map (tight controller)."""
+    differences of the propagate-to-plane map (tight controller); in the
+    field map the position columns carry the field-gradient terms."""
+    if B == "solenoid map":
+        from synth.field import solenoid_map
+        B = solenoid_map()
     geo = _plane_geometry(2, positions=[50.0, 450.0], tilt=0.2)
     inp = oracle_lib.Inputs(geo, B)
     tight = dict(step_tol=1e-11, land_tol=1e-12, step_max=20.0, max_rk_steps=100000)
