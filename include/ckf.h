@@ -228,6 +228,16 @@ void ckf_geometry_destroy(ckf_geometry* g);
 
 /* Uniform magnetic field (tesla). */
 ckf_status ckf_field_create_uniform(float bx, float by, float bz, ckf_field** out);
+
+/* A solenoidal field map (tesla) on a regular (r, z) grid: node (ir, iz) at
+ * (r0 + ir*dr, z0 + iz*dz) holds values[(iz*nr + ir)*2 + {0: B_r, 1: B_z}]
+ * (host memory, copied to the device once; nr, nz >= 2, dr, dz > 0).  The
+ * field at a point is the bilinear interpolant in (r, z), coordinates
+ * clamped to the grid, with B_x,y = B_r x,y / r; the transport Jacobian
+ * includes the interpolant's gradient.  Not combined with the learned
+ * proposal (ckf_find returns CKF_ERR_NOT_SUPPORTED). */
+ckf_status ckf_field_create_rz(const float* values, int32_t nr, int32_t nz, float r0, float z0, float dr, float dz,
+                               ckf_field** out);
 void ckf_field_destroy(ckf_field* f);
 
 /* The defaults of every configuration field: chi2_max 15, 3 branches per

@@ -16,7 +16,7 @@ import numpy as np
 from . import _abi
 from ._abi import COUNTER_NAMES
 
-__all__ = ["Geometry", "UniformField", "Model", "config", "find", "propagate_batch", "kf_update_batch",
+__all__ = ["Geometry", "UniformField", "FieldMap", "Model", "config", "find", "propagate_batch", "kf_update_batch",
            "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "CkfError"]
 
 
@@ -186,6 +186,30 @@ def capture_pairs(geometry: Geometry, out: dict, cap_pairs: int, stream=None):
     c = counts.cpu().numpy()
     k = int(min(c[0], cap))
     return x[:k], lab[:k], trk[:k], int(c[0]), int(c[1])
+
+
+class FieldMap:
+    """A solenoidal (r, z) field map (ckf_field_create_rz) from a dict with
+    map [nz, nr, 2] float32 (B_r, B_z), nr, nz, r0, z0, dr, dz."""
+
+    def __init__(self, m: dict):
+        v = np.ascontiguousarray(m["map"], np.float32)
+        if v.shape != (int(m["nz"]), int(m["nr"]), 2):
+            raise ValueError("field map must be [nz, nr, 2]")
+        h = C.c_void_p()
+        _check(_abi.load().ckf_field_create_rz(v.ctypes.data, int(m["nr"]), int(m["nz"]), float(m["r0"]),
+                                               float(m["z0"]), float(m["dr"]), float(m["dz"]), C.byref(h)),
+               "ckf_field_create_rz")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                _abi.load().ckf_field_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self.handle = None
 
 
 class UniformField:

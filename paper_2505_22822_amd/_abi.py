@@ -59,6 +59,7 @@ SIGNATURES = {
     "ckf_geometry_create": (I32, [C.POINTER(GeometryDesc), C.POINTER(VP)]),
     "ckf_geometry_destroy": (None, [VP]),
     "ckf_field_create_uniform": (I32, [F32, F32, F32, C.POINTER(VP)]),
+    "ckf_field_create_rz": (I32, [VP, I32, I32, F32, F32, F32, F32, C.POINTER(VP)]),
     "ckf_field_destroy": (None, [VP]),
     "ckf_config_default": (None, [C.POINTER(Config)]),
     "ckf_workspace_size": (I32, [VP, C.POINTER(Config), C.POINTER(Launch), I32, I32, I64, C.POINTER(C.c_size_t)]),

@@ -20,6 +20,7 @@ struct ckf_geometry {
 
 struct ckf_field {
   ckf::FieldDev dev;
+  void* map = nullptr;  // device copy of a field map
 };
 
 struct ckf_timer {
@@ -492,7 +493,51 @@ ckf_status ckf_field_create_uniform(float bx, float by, float bz, ckf_field** ou
   return CKF_OK;
 }
 
-void ckf_field_destroy(ckf_field* f) { delete f; }
+ckf_status ckf_field_create_rz(const float* values, int32_t nr, int32_t nz, float r0, float z0, float dr, float dz,
+                               ckf_field** out) {
+  if (!values || !out) return fail(CKF_ERR_INVALID_ARGUMENT, "field_create_rz: NULL argument");
+  *out = nullptr;
+  if (nr < 2 || nz < 2 || !(dr > 0) || !(dz > 0) || !std::isfinite(r0) || !std::isfinite(z0) ||
+      (long long)nr * nz > (1ll << 28))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "field_create_rz: bad grid");
+  // per (iz, ir): (B_r, B_z) at ir and at ir+1, so a cell row is one 16-byte load
+  std::vector<float4> dev((size_t)nr * nz);
+  for (int iz = 0; iz < nz; ++iz)
+    for (int ir = 0; ir < nr; ++ir) {
+      const int i1 = std::min(ir + 1, nr - 1);
+      const float* a = values + ((size_t)iz * nr + ir) * 2;
+      const float* b = values + ((size_t)iz * nr + i1) * 2;
+      if (!std::isfinite(a[0]) || !std::isfinite(a[1])) return fail(CKF_ERR_INVALID_ARGUMENT, "field map: non-finite");
+      dev[(size_t)iz * nr + ir] = make_float4(a[0], a[1], b[0], b[1]);
+    }
+  ckf_field* f = new ckf_field();
+  const hipError_t e = hipMalloc(&f->map, dev.size() * sizeof(float4));
+  if (e != hipSuccess) {
+    delete f;
+    return hip_fail(e, "hipMalloc(field map)");
+  }
+  const hipError_t e2 = hipMemcpy(f->map, dev.data(), dev.size() * sizeof(float4), hipMemcpyHostToDevice);
+  if (e2 != hipSuccess) {
+    (void)hipFree(f->map);
+    delete f;
+    return hip_fail(e2, "hipMemcpy(field map)");
+  }
+  f->dev.map = static_cast<const float4*>(f->map);
+  f->dev.nr = nr;
+  f->dev.nz = nz;
+  f->dev.r0 = r0;
+  f->dev.z0 = z0;
+  f->dev.inv_dr = 1.0f / dr;
+  f->dev.inv_dz = 1.0f / dz;
+  *out = f;
+  return CKF_OK;
+}
+
+void ckf_field_destroy(ckf_field* f) {
+  if (!f) return;
+  if (f->map) (void)hipFree(f->map);
+  delete f;
+}
 
 ckf_status ckf_workspace_size(const ckf_geometry* g, const ckf_config* cfg, const ckf_launch* launch,
                               int32_t n_events, int32_t n_seeds, int64_t n_meas, size_t* bytes) {
@@ -527,6 +572,7 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
     return fail(CKF_ERR_INVALID_ARGUMENT, "tracks: NULL array");
   if (out->cap_meas > 0 && !out->meas) return fail(CKF_ERR_INVALID_ARGUMENT, "tracks: NULL meas");
   if (!workspace) return fail(CKF_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  if (model && f->dev.map) return fail(CKF_ERR_NOT_SUPPORTED, "the learned proposal runs in a uniform field");
   const ckf::Launch L = resolve_launch(cfg, launch, s->n_seeds);
   const Layout o = layout(L, m->n_events, m->n_surfaces, s->n_seeds, m->n_meas);
   if (workspace_bytes < o.total)

@@ -27,7 +27,81 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 __device__ __forceinline__ float maxabs(V3 a) { return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z))); }
 __device__ __forceinline__ V3 ld3(const float* p) { return {p[0], p[1], p[2]}; }
 
-__device__ __forceinline__ V3 field_at(const FieldDev& F, V3 /*global position*/) { return {F.bx, F.by, F.bz}; }
+// Bilinear cell of the (r, z) map at p: the two rows and the fractions;
+// cr / cz tell that the coordinate was clamped (no gradient along it).
+struct MapCell {
+  float4 lo, hi;  // rows iz and iz+1: (B_r, B_z) at ir and ir+1
+  float fr, fz, r;
+  bool cr, cz;
+};
+
+__device__ __forceinline__ void map_cell(const FieldDev& F, V3 p, MapCell& c) {
+  c.r = sqrtf(p.x * p.x + p.y * p.y);
+  float u = (c.r - F.r0) * F.inv_dr, w = (p.z - F.z0) * F.inv_dz;
+  c.cr = c.cz = false;
+  if (!(u > 0.f)) {  // also NaN
+    u = 0.f;
+    c.cr = true;
+  } else if (u >= (float)(F.nr - 1)) {
+    u = (float)(F.nr - 1);
+    c.cr = true;
+  }
+  if (!(w > 0.f)) {
+    w = 0.f;
+    c.cz = true;
+  } else if (w >= (float)(F.nz - 1)) {
+    w = (float)(F.nz - 1);
+    c.cz = true;
+  }
+  const int ir = min((int)u, F.nr - 2), iz = min((int)w, F.nz - 2);
+  c.fr = u - (float)ir;
+  c.fz = w - (float)iz;
+  c.lo = F.map[iz * F.nr + ir];
+  c.hi = F.map[(iz + 1) * F.nr + ir];
+}
+
+template <bool kMap>
+__device__ __forceinline__ V3 field_at(const FieldDev& F, V3 p) {
+  if (!kMap) return {F.bx, F.by, F.bz};
+  MapCell c;
+  map_cell(F, p, c);
+  const float a = (1.f - c.fr) * (1.f - c.fz), b = c.fr * (1.f - c.fz), d = (1.f - c.fr) * c.fz, e = c.fr * c.fz;
+  const float br = a * c.lo.x + b * c.lo.z + d * c.hi.x + e * c.hi.z;
+  const float bz = a * c.lo.y + b * c.lo.w + d * c.hi.y + e * c.hi.w;
+  const float ir = c.r > 0.f ? 1.0f / c.r : 0.f;
+  return {br * p.x * ir, br * p.y * ir, bz};
+}
+
+// The map field and its gradient G[i][j] = dB_i/dx_j (of the interpolant).
+__device__ __forceinline__ V3 field_grad(const FieldDev& F, V3 p, float G[3][3]) {
+  MapCell c;
+  map_cell(F, p, c);
+  const float a = (1.f - c.fr) * (1.f - c.fz), b = c.fr * (1.f - c.fz), d = (1.f - c.fr) * c.fz, e = c.fr * c.fz;
+  const float br = a * c.lo.x + b * c.lo.z + d * c.hi.x + e * c.hi.z;
+  const float bz = a * c.lo.y + b * c.lo.w + d * c.hi.y + e * c.hi.w;
+  const float inv_dr = F.inv_dr, inv_dz = F.inv_dz;
+  const float brr = c.cr ? 0.f : ((1.f - c.fz) * (c.lo.z - c.lo.x) + c.fz * (c.hi.z - c.hi.x)) * inv_dr;
+  const float bzr = c.cr ? 0.f : ((1.f - c.fz) * (c.lo.w - c.lo.y) + c.fz * (c.hi.w - c.hi.y)) * inv_dr;
+  const float brz = c.cz ? 0.f : ((1.f - c.fr) * (c.hi.x - c.lo.x) + c.fr * (c.hi.z - c.lo.z)) * inv_dz;
+  const float bzz = c.cz ? 0.f : ((1.f - c.fr) * (c.hi.y - c.lo.y) + c.fr * (c.hi.w - c.lo.w)) * inv_dz;
+  const float ir = c.r > 0.f ? 1.0f / c.r : 0.f;
+  const float cx = p.x * ir, sy = p.y * ir;
+  G[0][0] = brr * cx * cx + br * sy * sy * ir;
+  G[0][1] = brr * cx * sy - br * cx * sy * ir;
+  G[0][2] = brz * cx;
+  G[1][0] = G[0][1];
+  G[1][1] = brr * sy * sy + br * cx * cx * ir;
+  G[1][2] = brz * sy;
+  G[2][0] = bzr * cx;
+  G[2][1] = bzr * sy;
+  G[2][2] = bzz;
+  return {br * cx, br * sy, bz};
+}
+
+__device__ __forceinline__ V3 mat_vec(const float G[3][3], V3 d) {
+  return {G[0][0] * d.x + G[0][1] * d.y + G[0][2] * d.z, G[1][0] * d.x + G[1][1] * d.y + G[1][2] * d.z,
+          G[2][0] * d.x + G[2][1] * d.y + G[2][2] * d.z};
+}
 
 __device__ __forceinline__ void load_module(const GeomDev& g, int m, Module& M) {
   const float4* s = reinterpret_cast<const float4*>(g.mod + m);
@@ -40,57 +114,94 @@ __device__ __forceinline__ void load_module(const GeomDev& g, int m, Module& M) 
 
 // ---------------------------------------------------------------------------
 // Propagation leg: free state relative to `origin` (the start module centre)
-// plus the tangent columns d(state)/d(phi, theta, q/p) of the bound start
-// parameters.  In a uniform field the loc0/loc1 columns stay (u, 0, 0) and
-// (v, 0, 0) along the whole leg, so only three columns are carried.
-struct Leg {
+// plus tangent columns d(state)/d(bound start parameters).  In a uniform
+// field the loc0/loc1 columns stay (u, 0, 0) and (v, 0, 0) along the whole
+// leg, so NC = 3 columns (phi, theta, q/p) are carried; in a field map the
+// force depends on position and all NC = 5 are.
+template <int NC>
+struct LegT {
   V3 r, T;
   float lam;
-  V3 dr[3], dT[3];
+  V3 dr[NC], dT[NC];
 };
+using Leg = LegT<3>;
 
-// One Nystrom RKN4 step of length h for r'' = kappa*lambda*(r' x B) (field
-// sampled at start, midpoint and end; uniform here).  The stages are
-// evaluated first and give the error estimate h^2 * max|k1 - k2 - k3 + k4|;
-// only an accepted step then advances the state and carries the tangent
-// columns through the same stages, in place.
+// One Nystrom RKN4 step of length h for r'' = kappa*lambda*(r' x B(r))
+// (field sampled at start, midpoint and end).  The stages are evaluated
+// first and give the error estimate h^2 * max|k1 - k2 - k3 + k4|; only an
+// accepted step then advances the state and carries the tangent columns
+// through the same stages, in place.
 struct Stages {
   V3 k1, k2, k3, k4, T2, T3, T4;
+  V3 B2, B4;  // field at the midpoint and the end (a map)
 };
 
-__device__ __forceinline__ float rkn4_stages(const Leg& L, float h, V3 B, Stages& S) {
+template <bool kMap, int NC>
+__device__ __forceinline__ float rkn4_stages(const LegT<NC>& L, float h, V3 origin, const FieldDev& F, V3 B,
+                                             Stages& S) {
   const float kl = kKappa * L.lam;
   const float h2 = 0.5f * h;
   S.k1 = kl * cross(L.T, B);
+  S.B2 = kMap ? field_at<true>(F, origin + L.r + h2 * L.T + (0.125f * h * h) * S.k1) : B;
   S.T2 = L.T + h2 * S.k1;
-  S.k2 = kl * cross(S.T2, B);
+  S.k2 = kl * cross(S.T2, S.B2);
   S.T3 = L.T + h2 * S.k2;
-  S.k3 = kl * cross(S.T3, B);
+  S.k3 = kl * cross(S.T3, S.B2);
+  S.B4 = kMap ? field_at<true>(F, origin + L.r + h * L.T + (0.5f * h * h) * S.k3) : B;
   S.T4 = L.T + h * S.k3;
-  S.k4 = kl * cross(S.T4, B);
+  S.k4 = kl * cross(S.T4, S.B4);
   return h * h * maxabs(S.k1 - S.k2 - S.k3 + S.k4);
 }
 
-__device__ __forceinline__ void rkn4_advance(Leg& L, float h, V3 B, const Stages& S) {
+template <bool kMap, int NC>
+__device__ __forceinline__ void rkn4_advance(LegT<NC>& L, float h, V3 origin, const FieldDev& F, V3 B,
+                                             const Stages& S) {
   const float kl = kKappa * L.lam;
   const float h2 = 0.5f * h, h6 = h * (1.0f / 6.0f), hh6 = h * h * (1.0f / 6.0f);
-  // d(kappa*lambda*(T x B)) = kappa*lambda*(dT x B) + kappa*dlambda*(T x B)
+  if (!kMap) {
+    // d(kappa*lambda*(T x B)) = kappa*lambda*(dT x B) + kappa*dlambda*(T x B)
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const V3 dT = L.dT[j];
-    V3 d1 = kl * cross(dT, B);
-    if (j == 2) d1 = d1 + kKappa * cross(L.T, B);
-    const V3 dT2 = dT + h2 * d1;
-    V3 d2 = kl * cross(dT2, B);
-    if (j == 2) d2 = d2 + kKappa * cross(S.T2, B);
-    const V3 dT3 = dT + h2 * d2;
-    V3 d3 = kl * cross(dT3, B);
-    if (j == 2) d3 = d3 + kKappa * cross(S.T3, B);
-    const V3 dT4 = dT + h * d3;
-    V3 d4 = kl * cross(dT4, B);
-    if (j == 2) d4 = d4 + kKappa * cross(S.T4, B);
-    L.dr[j] = L.dr[j] + h * dT + hh6 * (d1 + d2 + d3);
-    L.dT[j] = dT + h6 * (d1 + 2.0f * (d2 + d3) + d4);
+    for (int j = 0; j < NC; ++j) {
+      const V3 dT = L.dT[j];
+      V3 d1 = kl * cross(dT, B);
+      if (j == NC - 1) d1 = d1 + kKappa * cross(L.T, B);
+      const V3 dT2 = dT + h2 * d1;
+      V3 d2 = kl * cross(dT2, B);
+      if (j == NC - 1) d2 = d2 + kKappa * cross(S.T2, B);
+      const V3 dT3 = dT + h2 * d2;
+      V3 d3 = kl * cross(dT3, B);
+      if (j == NC - 1) d3 = d3 + kKappa * cross(S.T3, B);
+      const V3 dT4 = dT + h * d3;
+      V3 d4 = kl * cross(dT4, B);
+      if (j == NC - 1) d4 = d4 + kKappa * cross(S.T4, B);
+      L.dr[j] = L.dr[j] + h * dT + hh6 * (d1 + d2 + d3);
+      L.dT[j] = dT + h6 * (d1 + 2.0f * (d2 + d3) + d4);
+    }
+  } else {
+    // plus kappa*lambda*(T x (dB/dr . d(stage point))) at each stage
+    float G1[3][3], G2[3][3], G4[3][3];
+    (void)field_grad(F, origin + L.r, G1);
+    (void)field_grad(F, origin + L.r + h2 * L.T + (0.125f * h * h) * S.k1, G2);
+    (void)field_grad(F, origin + L.r + h * L.T + (0.5f * h * h) * S.k3, G4);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const V3 dr = L.dr[j], dT = L.dT[j];
+      V3 d1 = kl * (cross(dT, B) + cross(L.T, mat_vec(G1, dr)));
+      if (j == NC - 1) d1 = d1 + kKappa * cross(L.T, B);
+      const V3 drm = dr + h2 * dT + (0.125f * h * h) * d1;
+      const V3 dT2 = dT + h2 * d1;
+      V3 d2 = kl * (cross(dT2, S.B2) + cross(S.T2, mat_vec(G2, drm)));
+      if (j == NC - 1) d2 = d2 + kKappa * cross(S.T2, S.B2);
+      const V3 dT3 = dT + h2 * d2;
+      V3 d3 = kl * (cross(dT3, S.B2) + cross(S.T3, mat_vec(G2, drm)));
+      if (j == NC - 1) d3 = d3 + kKappa * cross(S.T3, S.B2);
+      const V3 dre = dr + h * dT + (0.5f * h * h) * d3;
+      const V3 dT4 = dT + h * d3;
+      V3 d4 = kl * (cross(dT4, S.B4) + cross(S.T4, mat_vec(G4, dre)));
+      if (j == NC - 1) d4 = d4 + kKappa * cross(S.T4, S.B4);
+      L.dr[j] = dr + h * dT + hh6 * (d1 + d2 + d3);
+      L.dT[j] = dT + h6 * (d1 + 2.0f * (d2 + d3) + d4);
+    }
   }
   L.r = L.r + h * L.T + hh6 * (S.k1 + S.k2 + S.k3);
   L.T = L.T + h6 * (S.k1 + 2.0f * (S.k2 + S.k3) + S.k4);
@@ -170,10 +281,11 @@ struct LegStats {
 };
 
 // Adaptive RKN4 steps onto the plane (c, n) given relative to the origin.
-__device__ bool land(Leg& L, V3 origin, V3 c, V3 n, const FieldDev& F, const CfgDev& cfg, float& h_trial,
+template <bool kMap, int NC>
+__device__ bool land(LegT<NC>& L, V3 origin, V3 c, V3 n, const FieldDev& F, const CfgDev& cfg, float& h_trial,
                      float& path, LegStats& st) {
   for (int it = 0; it < cfg.max_rk; ++it) {
-    const V3 B = field_at(F, origin + L.r);
+    const V3 B = field_at<kMap>(F, origin + L.r);
     const float d = helix_distance(L.r, L.T, L.lam, B, c, n);
     if (!isfinite(d)) return false;
     if (fabsf(d) < cfg.land_tol) {
@@ -185,14 +297,14 @@ __device__ bool land(Leg& L, V3 origin, V3 c, V3 n, const FieldDev& F, const Cfg
     const bool limited = fabsf(d) < h_trial;
     const float h = copysignf(fminf(fabsf(d), h_trial), d);
     Stages S;
-    const float err = rkn4_stages(L, h, B, S);
+    const float err = rkn4_stages<kMap>(L, h, origin, F, B, S);
     ++st.trials;
     if (!(err <= cfg.step_tol)) {
       ++st.rejects;
       h_trial = fabsf(h) * fmaxf(0.25f, 0.9f * sqrtf(sqrtf(cfg.step_tol / err)));
       continue;
     }
-    rkn4_advance(L, h, B, S);
+    rkn4_advance<kMap>(L, h, origin, F, B, S);
     path += fabsf(h);
     const float grow = err > 0.0f ? fminf(4.0f, 0.9f * sqrtf(sqrtf(cfg.step_tol / err))) : 4.0f;
     h_trial = limited ? fminf(cfg.step_max, fmaxf(h_trial, fabsf(h) * grow)) : fminf(cfg.step_max, fabsf(h) * grow);
@@ -201,7 +313,8 @@ __device__ bool land(Leg& L, V3 origin, V3 c, V3 n, const FieldDev& F, const Cfg
 }
 
 // Bound parameters on module A -> leg start (relative to A's centre).
-__device__ __forceinline__ void leg_start(const Module& A, const double* p, Leg& L, V3& uA, V3& vA) {
+template <int NC>
+__device__ __forceinline__ void leg_start(const Module& A, const double* p, LegT<NC>& L, V3& uA, V3& vA) {
   uA = ld3(A.u);
   vA = ld3(A.v);
   const float l0 = (float)p[0], l1 = (float)p[1];
@@ -211,16 +324,21 @@ __device__ __forceinline__ void leg_start(const Module& A, const double* p, Leg&
   L.r = l0 * uA + l1 * vA;
   L.T = {cp * st, sp * st, ct};
   L.lam = (float)p[4];
-  L.dr[0] = L.dr[1] = L.dr[2] = {0.f, 0.f, 0.f};
-  L.dT[0] = {-sp * st, cp * st, 0.f};
-  L.dT[1] = {cp * ct, sp * ct, -st};
-  L.dT[2] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < NC; ++j) L.dr[j] = L.dT[j] = {0.f, 0.f, 0.f};
+  if (NC == 5) {
+    L.dr[0] = uA;
+    L.dr[1] = vA;
+  }
+  L.dT[NC - 3] = {-sp * st, cp * st, 0.f};
+  L.dT[NC - 2] = {cp * ct, sp * ct, -st};
 }
 
 // Landed free state -> bound parameters on module B and the bound-to-bound
 // Jacobian with the path-length correction.  dB = B's centre relative to
 // the leg origin; qop is the start's FP64 q/p (unchanged along the leg).
-__device__ __forceinline__ void leg_end(const Leg& L, V3 uA, V3 vA, const Module& Bm, V3 dB, V3 Bf, double qop,
+template <int NC>
+__device__ __forceinline__ void leg_end(const LegT<NC>& L, V3 uA, V3 vA, const Module& Bm, V3 dB, V3 Bf, double qop,
                                         double* p, float J[5][5]) {
   const V3 uB = ld3(Bm.u), vB = ld3(Bm.v), nB = ld3(Bm.n);
   const V3 d = L.r - dB;
@@ -236,12 +354,16 @@ __device__ __forceinline__ void leg_end(const Leg& L, V3 uA, V3 vA, const Module
   const float inT = 1.0f / dot(nB, T);
   const float ist2 = 1.0f / st2, ist = 1.0f / st;
   V3 dr[5], dT[5];
-  dr[0] = uA; dT[0] = {0.f, 0.f, 0.f};
-  dr[1] = vA; dT[1] = {0.f, 0.f, 0.f};
+  if (NC == 3) {
+    dr[0] = uA;
+    dT[0] = {0.f, 0.f, 0.f};
+    dr[1] = vA;
+    dT[1] = {0.f, 0.f, 0.f};
+  }
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    dr[j + 2] = L.dr[j];
-    dT[j + 2] = L.dT[j];
+  for (int j = 0; j < NC; ++j) {
+    dr[j + 5 - NC] = L.dr[j];
+    dT[j + 5 - NC] = L.dT[j];
   }
 #pragma unroll
   for (int j = 0; j < 5; ++j) {

@@ -59,8 +59,15 @@ struct GeomDev {
   const int* nb_mod = nullptr;
 };
 
+// Field: uniform (map == nullptr) or a solenoidal (r, z) map interpolated
+// bilinearly with clamped coordinates.  map[iz*nr + ir] holds
+// (B_r, B_z) at (ir, iz) and at (ir+1, iz), so one z row of a cell is one
+// 16-byte load.
 struct FieldDev {
-  float bx, by, bz;  // uniform field, tesla
+  float bx = 0.f, by = 0.f, bz = 0.f;  // uniform field, tesla
+  const float4* map = nullptr;
+  int nr = 0, nz = 0;
+  float r0 = 0.f, z0 = 0.f, inv_dr = 1.f, inv_dz = 1.f;
 };
 
 // Scalar configuration as the kernels use it.

@@ -219,7 +219,8 @@ constexpr int kMaxSlots = 64;
 // kCount: the instrumented variant that accumulates the work-unit counters
 // (used once to measure the algorithmic work; the work is deterministic).
 // kLearned: the learned-proposal form (network inference in the navigation).
-template <int kMinWaves, bool kCount, bool kLearned>
+// kMap: a field map (five tangent columns with field-gradient terms).
+template <int kMinWaves, bool kCount, bool kLearned, bool kMap>
 __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   __shared__ int sh_seed[kMaxSlots], sh_event[kMaxSlots], sh_live[kMaxSlots], sh_step[kMaxSlots];
   __shared__ int sh_best_node[kMaxSlots], sh_best_nm[kMaxSlots], sh_best_holes[kMaxSlots];
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       int list[kMaxList];
       float h = 0.f, path = 0.f;
       Module Am;
-      Leg L;
+      LegT<kMap ? 5 : 3> L;
       V3 uA, vA, origin, Pl, Tl;
       bool go = false, need_list = false;
       int lay = 0, excl = -1, nb_slot = -1;
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         if (root) {
           outcome = 2;
         } else if (nlist == 0) {
-          const V3 Bf = field_at(A.f, Pl);
+          const V3 Bf = field_at<kMap>(A.f, Pl);
           const Helix H = make_helix(Pl, L.T, L.lam, Bf);
           float sL;
           CNT_ADD(CKF_CNT_NAV, 1);
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           origin = ld3(Am.c);
         }
         if (need_list) {
-          const V3 kl = (kKappa * L.lam) * cross(Tl, field_at(A.f, Pl));
+          const V3 kl = (kKappa * L.lam) * cross(Tl, field_at<kMap>(A.f, Pl));
           int nt = 0, ovf = 0;
           bool listed = false;
           if (kLearned && confident) {
@@ -547,12 +548,12 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             const V3 dB = ld3(Bm.c) - origin;
             LegStats ls{0, 0};
             CNT_ADD(CKF_CNT_LEGS, 1);
-            bool good = land(L, origin, dB, ld3(Bm.n), A.f, cfg, h, path, ls);
+            bool good = land<kMap>(L, origin, dB, ld3(Bm.n), A.f, cfg, h, path, ls);
             CNT_ADD(CKF_CNT_RK_TRIALS, ls.trials);
             CNT_ADD(CKF_CNT_RK_REJECTS, ls.rejects);
             if (good) {
               double pn[5];
-              leg_end(L, uA, vA, Bm, dB, field_at(A.f, origin + L.r), p[4], pn, J);
+              leg_end(L, uA, vA, Bm, dB, field_at<kMap>(A.f, origin + L.r), p[4], pn, J);
 #pragma unroll
               for (int k = 0; k < 5; ++k) good = good && isfinite(pn[k]);
 #pragma unroll
@@ -1006,7 +1007,8 @@ __global__ __launch_bounds__(kScanBlock) void k_out_write(int n, const int* res_
 // ---------------------------------------------------------------------------
 // component kernels
 
-__global__ void k_propagate_batch(GeomDev g, FieldDev F, CfgDev cfg, int n, const int* src, const double* p_in,
+template <bool kMap>
+__global__ void __launch_bounds__(64) k_propagate_batch(GeomDev g, FieldDev F, CfgDev cfg, int n, const int* src, const double* p_in,
                                   const double* cov_in, const int* dst, double* p_out, double* cov_out, double* jac,
                                   double* path_out, int* ok_out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1022,19 +1024,19 @@ __global__ void k_propagate_batch(GeomDev g, FieldDev F, CfgDev cfg, int n, cons
   double p[5], C[15];
   for (int k = 0; k < 5; ++k) p[k] = p_in[5 * i + k];
   for (int k = 0; k < 15; ++k) C[k] = cov_in[15 * i + k];
-  Leg L;
+  LegT<kMap ? 5 : 3> L;
   V3 uA, vA;
   leg_start(Am, p, L, uA, vA);
   const V3 origin = ld3(Am.c);
   const V3 dB = ld3(Bm.c) - origin;
   float h = cfg.step_max, path = 0.f;
   LegStats st{0, 0};
-  const bool ok = land(L, origin, dB, ld3(Bm.n), F, cfg, h, path, st);
+  const bool ok = land<kMap>(L, origin, dB, ld3(Bm.n), F, cfg, h, path, st);
   ok_out[i] = ok ? 1 : 0;
   if (!ok) return;
   double pn[5];
   float J[5][5];
-  leg_end(L, uA, vA, Bm, dB, field_at(F, origin + L.r), p[4], pn, J);
+  leg_end(L, uA, vA, Bm, dB, field_at<kMap>(F, origin + L.r), p[4], pn, J);
   transport_cov(J, C);
   for (int k = 0; k < 5; ++k) p_out[5 * i + k] = pn[k];
   for (int k = 0; k < 15; ++k) cov_out[15 * i + k] = C[k];
@@ -1085,20 +1087,29 @@ hipError_t launch_ckf(const CkfArgs& a, int waves_per_simd, hipStream_t st) {
   const dim3 grid(a.w.grid), block(kWave);
   // 3 or 4 waves per SIMD would need register spills; those builds were
   // slower and not bitwise identical to these, so they are not offered.
-  if (a.learned) {
+  // The learned form runs in a uniform field (the host rejects a map).
+  const bool two = waves_per_simd >= 2;
+  if (a.f.map) {
     if (a.counters)
-      hipLaunchKernelGGL((k_ckf<1, true, true>), grid, block, 0, st, a);
-    else if (waves_per_simd >= 2)
-      hipLaunchKernelGGL((k_ckf<2, false, true>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_ckf<1, true, false, true>), grid, block, 0, st, a);
+    else if (two)
+      hipLaunchKernelGGL((k_ckf<2, false, false, true>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_ckf<1, false, true>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_ckf<1, false, false, true>), grid, block, 0, st, a);
+  } else if (a.learned) {
+    if (a.counters)
+      hipLaunchKernelGGL((k_ckf<1, true, true, false>), grid, block, 0, st, a);
+    else if (two)
+      hipLaunchKernelGGL((k_ckf<2, false, true, false>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_ckf<1, false, true, false>), grid, block, 0, st, a);
   } else {
     if (a.counters)
-      hipLaunchKernelGGL((k_ckf<1, true, false>), grid, block, 0, st, a);
-    else if (waves_per_simd >= 2)
-      hipLaunchKernelGGL((k_ckf<2, false, false>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_ckf<1, true, false, false>), grid, block, 0, st, a);
+    else if (two)
+      hipLaunchKernelGGL((k_ckf<2, false, false, false>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_ckf<1, false, false>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_ckf<1, false, false, false>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -1120,8 +1131,12 @@ hipError_t launch_propagate(const GeomDev& g, const FieldDev& f, const CfgDev& c
                             const double* p_in, const double* cov_in, const int* dst, double* p_out,
                             double* cov_out, double* jac, double* path, int* ok, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_propagate_batch, dim3((n + 63) / 64), dim3(64), 0, st, g, f, c, n, src, p_in, cov_in, dst,
-                     p_out, cov_out, jac, path, ok);
+  if (f.map)
+    hipLaunchKernelGGL(k_propagate_batch<true>, dim3((n + 63) / 64), dim3(64), 0, st, g, f, c, n, src, p_in, cov_in,
+                       dst, p_out, cov_out, jac, path, ok);
+  else
+    hipLaunchKernelGGL(k_propagate_batch<false>, dim3((n + 63) / 64), dim3(64), 0, st, g, f, c, n, src, p_in, cov_in,
+                       dst, p_out, cov_out, jac, path, ok);
   return hipGetLastError();
 }
 
