@@ -43,6 +43,12 @@ UNIT_FLOPS = {
     "mlp_rows": (90, 0),        # network input (30) and softmax/top-3 of one row (60)
 }
 MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 16x16x16 MFMAs
+# HBM bytes per launch of the track-finding kernel from the FETCH_SIZE and
+# WRITE_SIZE counters (scaled by a plain copy's factors 2.0 and 1.0), keyed
+# by (form, grid, seeds per group, waves per SIMD): the pools make the
+# traffic depend on the launch shape.  Source: profiles/k_ckf_mu200x64_hbm_traffic.md;
+# an entry is dropped when its kernel changes.
+MEASURED_TRAFFIC = {("plain", 2048, 48, 2): 21.57e9}
 PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
 PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
 PEAK_BF16 = 2.5e15    # MI355X dense bf16 MFMA, FLOP/s
@@ -157,15 +163,16 @@ def measure(ckf, geo, fld, b, shape, steps, warmup, stream, model=None, audit=Fa
                 ms_per_step=ms_per_step, tracks_per_s=r["n_tracks"] / (ms_per_step * 1e-3))
 
 
-def roofline_of(m):
+def roofline_of(m, form, shape):
     c = dict(m["counters"])
     f32 = sum(c.get(k, 0) * UNIT_FLOPS[k][0] for k in UNIT_FLOPS)
     f64 = sum(c.get(k, 0) * UNIT_FLOPS[k][1] for k in UNIT_FLOPS)
     mf = c.get("mlp_blocks", 0) * MFMA_FLOP_PER_BLOCK
     t = m["kernel_ms"] * 1e-3
     frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64 + mf / PEAK_BF16) / t
+    traffic = MEASURED_TRAFFIC.get((form, shape["grid"], shape["seeds_per_group"], shape["waves_per_simd"]))
     return dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                frac=round(frac, 5), traffic=None, kernel="k_ckf", kernel_ms=round(m["kernel_ms"], 4), fp32_flop=f32,
+                frac=round(frac, 5), traffic=traffic, kernel="k_ckf", kernel_ms=round(m["kernel_ms"], 4), fp32_flop=f32,
                 fp64_flop=f64, bf16_mfma_flop=mf,
                 note="achieved = FP32-equivalent rate (F32 + 2*F64 + F_bf16/15.9)/t against the FP32 vector peak")
 
@@ -314,7 +321,10 @@ def main():
                            efficiency=round(eff_plain, 5), launch=shape_plain),
                 learned=learned_info,
                 equal_efficiency=(learned_info["efficiency"] >= eff_plain - 0.005) if learned_info else None,
-                roofline=roofline_of(head), cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
+                roofline=roofline_of(head, "learned" if learned_info else "plain",
+                                     learned_info["launch"] if learned_info else shape_plain),
+                plain_roofline=roofline_of(plain, "plain", shape_plain),
+                cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
     print(json.dumps(line))
 
 

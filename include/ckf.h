@@ -77,18 +77,28 @@ typedef struct ckf_model ckf_model;       /* opaque next-module network packed f
  * holds a neighbour table: the next layers a straight ray from the origin
  * through m's centre or corners meets (at most CKF_MAX_NEXT_LAYERS, in ray
  * order: centre, then corners (-,-), (+,-), (-,+), (+,+) in (loc0, loc1)),
- * and for each such layer the CKF_NEIGHBOURS modules whose centres are
- * nearest to the anchor - where the first of those rays that reaches the
- * layer meets its envelope - ordered by distance, ties by id.  The network
- * maps the state on m to a softmax over those CKF_NEIGHBOURS entries:
- *   inputs (CKF_MLP_INPUTS): loc0/10, loc1/30, the unit direction in m's
- *   (u, v, n) frame, q/p in 1/GeV, target layer / number of layers;
- *   7 -> 64 -> 64 -> 32 with ReLU, bf16 weights and activations, FP32 sums.
+ * and for each such layer L' the anchor A (where the first of those rays
+ * that reaches L' meets its envelope), the module pitches (pu, pv) of L'
+ * there, and a region of CKF_REGION_U x CKF_REGION_V cells around A in the
+ * layer's curvilinear coordinates - (R dphi, dz) on a barrel of radius R,
+ * (r dphi, dr) on a disk with r the point's own radius - each holding the
+ * module of L' whose centre offset rounds to that cell (the nearest to the
+ * cell centre when several do, ties by id).  A navigation that finds L'
+ * centres a window of 8 x 4 cells (CKF_NEIGHBOURS) on the cell of its
+ * local helix's crossing of L''s envelope; the network maps
+ *   inputs (CKF_MLP_INPUTS): the crossing's fractional position in its cell
+ *   (u, v), the direction there in the layer frame (phi-hat, then z-hat and
+ *   r-hat on barrels, r-hat and z-hat on disks), q/p in 1/GeV, L' / number
+ *   of layers;
+ *   7 -> 64 -> 64 -> 32 with ReLU, bf16 weights and activations, FP32 sums,
+ * to a softmax over the window's cells, in order (iv, iu) from (-2, -4).
  * Parameters cross the interface as one FP32 vector of CKF_MLP_PARAMS in
  * the order W1 [64][7], b1 [64], W2 [64][64], b2 [64], W3 [32][64], b3 [32]
  * (row-major, W[out][in]). */
 #define CKF_MAX_NEXT_LAYERS 3
 #define CKF_NEIGHBOURS 32
+#define CKF_REGION_U 24
+#define CKF_REGION_V 8
 #define CKF_MLP_INPUTS 7
 #define CKF_MLP_HIDDEN 64
 #define CKF_MLP_OUTPUTS 32
@@ -297,10 +307,13 @@ ckf_status ckf_kf_update_batch(int32_t n, const double* p_in, const double* cov_
 /* ---- Learned proposal: neighbour table, network, training ---- */
 
 /* Copy the geometry's neighbour table to host memory: next_layers
- * [n_surfaces][CKF_MAX_NEXT_LAYERS] and neighbours
- * [n_surfaces][CKF_MAX_NEXT_LAYERS][CKF_NEIGHBOURS], -1 padded.
- * Synchronous. */
-ckf_status ckf_geometry_neighbours(const ckf_geometry* g, int32_t* next_layers, int32_t* neighbours);
+ * [n_surfaces][CKF_MAX_NEXT_LAYERS] (-1 pads), anchors
+ * [n_surfaces][CKF_MAX_NEXT_LAYERS][4] = (phi_A, w_A, pu, pv) with w_A = z
+ * on a barrel and r on a disk, and regions
+ * [n_surfaces][CKF_MAX_NEXT_LAYERS][CKF_REGION_V * CKF_REGION_U] of module
+ * ids, cell (iu, iv) for iu in [-12, 11], iv in [-4, 3] at
+ * (iv + 4) * 24 + iu + 12 (-1 empty).  Synchronous. */
+ckf_status ckf_geometry_neighbours(const ckf_geometry* g, int32_t* next_layers, float* anchors, int32_t* regions);
 
 /* Pack CKF_MLP_PARAMS FP32 parameters (device memory, 16-byte aligned)
  * into a model for ckf_find (allocates ~15 KB of device memory; the packing
@@ -333,17 +346,21 @@ ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, in
 
 /* Training pairs from found tracks (device memory): at every change of
  * layer between consecutive measurements of a track, the network input of
- * the state at the last measurement of the layer (target layer: that of
- * the next measurement) and the position of the next measurement's module
- * in the neighbour table.  Pairs whose target layer or module is not in the
- * table are dropped.  Pairs are written in track order, then measurement
- * order, up to cap_pairs: x [cap][7], label [cap], track [cap] (may be
- * NULL).  counts [2] receives the number of pairs (also beyond cap) and of
- * dropped pairs.  n_tracks is a device int32 (as ckf_find writes it). */
-ckf_status ckf_capture_pairs(const ckf_geometry* g, const int32_t* n_tracks, int32_t cap_tracks,
-                             const int32_t* offsets, const int32_t* meas_surface, const double* meas_params,
-                             int64_t cap_pairs, float* x, int32_t* label, int32_t* track, int64_t* counts,
-                             void* stream);
+ * the state at the last measurement of the layer - through its local
+ * helix's crossing of the next measurement's layer, in `field` - and the
+ * position of the next measurement's module in the window around that
+ * crossing.  A pair is dropped when that layer is not listed for the
+ * module, the helix misses the envelope, or the module is outside the
+ * window (or a module id is out of range).  Pairs are written in track
+ * order, then measurement order, up to cap_pairs: x [cap][7], label [cap],
+ * track [cap] (may be NULL).  counts [2] receives the number of pairs (also
+ * beyond cap) and of dropped pairs.  n_tracks is a device int32 (as
+ * ckf_find writes it); offsets, meas_surface and meas_params are a
+ * ckf_find output (offsets within meas capacity).  Uniform field only. */
+ckf_status ckf_capture_pairs(const ckf_geometry* g, const ckf_field* field, const int32_t* n_tracks,
+                             int32_t cap_tracks, const int32_t* offsets, const int32_t* meas_surface,
+                             const double* meas_params, int64_t cap_pairs, float* x, int32_t* label,
+                             int32_t* track, int64_t* counts, void* stream);
 
 /* A pair of HIP events that ckf_find records, on its stream, immediately
  * before and after the persistent track-finding kernel when the launch

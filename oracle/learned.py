@@ -7,11 +7,14 @@ What is defined here:
 
 * the neighbour table of a detector: for every module m the (at most three)
   layers a straight ray from the origin through m meets next, and for each
-  such layer L' the 32 modules of L' whose centres are nearest to where the
-  ray through m's centre (or, if that ray meets another layer first, the
-  first corner ray that meets L') crosses L''s envelope, ties by id;
-* the 7-number state that the network sees on module m when it asks for
-  layer L';
+  such layer L' the anchor (where the first ray meeting L' crosses its
+  envelope), the layer's module pitches there, and a 24 x 8 region of
+  cells in the layer's curvilinear coordinates around the anchor, each cell
+  holding the L' module whose centre falls in it;
+* the proposal window: the 8 x 4 cells around the cell where the local
+  helix from the state on m crosses L''s envelope; the 7-number input of
+  the network is that crossing's fractional position in its cell, the
+  direction there in the layer's local frame, q/p and L';
 * the (state, label) pairs taken from found tracks: at every change of layer
   between consecutive measurements, the state at the last measurement of the
   layer and the position of the next measurement's module in the table;
@@ -102,26 +105,87 @@ def _ray_points(geom):
     return np.stack(pts, axis=1)  # (n, 5, 3)
 
 
+WIN_U, WIN_V = 8, 4            # the 32 network outputs: cells iu in [-4, 3] x iv in [-2, 1] around the crossing
+WU0, WV0 = -4, -2
+REG_U, REG_V = 24, 8           # the stored region: cells iu in [-12, 11] x iv in [-4, 3] around the anchor
+RU0, RV0 = -12, -4
+
+
+def _rnd(x):
+    return np.floor(x + 0.5)
+
+
+def _wrap(a):
+    return (a + np.pi) % (2.0 * np.pi) - np.pi
+
+
+def layer_coords(geom, L, X, A):
+    """Curvilinear offsets of points X [..., 3] from the anchor A on layer L:
+    barrels (R dphi, dz) with R the layer radius, disks (r dphi, dr) with r
+    the point's own radius."""
+    X = np.asarray(X, np.float64)
+    dphi = _wrap(np.arctan2(X[..., 1], X[..., 0]) - np.arctan2(A[1], A[0]))
+    rX = np.hypot(X[..., 0], X[..., 1])
+    if int(geom["layer_type"][L]) == 0:
+        return dphi * float(geom["layer_pos"][L]), X[..., 2] - A[2]
+    return dphi * rX, rX - np.hypot(A[0], A[1])
+
+
+def _cells(geom, L, A):
+    """Pitches and the stored region of layer L around anchor A: the pitch
+    along u is the smallest positive u-offset between the module nearest to
+    A (ties by id) and another module of its row (|dv| < its half length v),
+    the pitch along v the smallest positive v-offset to a module of its
+    column (|du| < half the u pitch), else the module's full lengths; a
+    module sits in cell (round(du/pu), round(dv/pv)) of its centre's offset
+    from A, and each cell of the 24 x 8 region keeps the module nearest to
+    the cell's centre (ties by id)."""
+    layer = np.asarray(geom["layer"])
+    c = np.asarray(geom["center"], np.float64)
+    half = np.asarray(geom["half"], np.float64)
+    mem = np.nonzero(layer == L)[0]
+    du, dv = layer_coords(geom, L, c[mem], A)
+    d2 = du * du + dv * dv
+    a = int(np.lexsort((mem, d2))[0])
+    ou, ov = du - du[a], dv - dv[a]
+    row = (np.abs(ov) < half[mem[a], 1]) & (ou > 1e-3)
+    pu = float(ou[row].min()) if row.any() else 2.0 * half[mem[a], 0]
+    col = (np.abs(ou) < 0.5 * pu) & (ov > 1e-3)
+    pv = float(ov[col].min()) if col.any() else 2.0 * half[mem[a], 1]
+    iu, iv = _rnd(du / pu), _rnd(dv / pv)
+    region = np.full(REG_U * REG_V, -1, np.int32)
+    best = np.full(REG_U * REG_V, np.inf)
+    ok = (iu >= RU0) & (iu < RU0 + REG_U) & (iv >= RV0) & (iv < RV0 + REG_V)
+    for j in np.nonzero(ok)[0]:
+        k = int((iv[j] - RV0) * REG_U + (iu[j] - RU0))
+        eu, ev = du[j] - iu[j] * pu, dv[j] - iv[j] * pv
+        dist = eu * eu + ev * ev
+        m = int(mem[j])
+        if dist < best[k] or (dist == best[k] and m < region[k]):
+            best[k], region[k] = dist, m
+    return pu, pv, region
+
+
 def neighbour_table(geom, modules=None):
-    """(next_layers [n, 3], neighbours [n, 3, 32]) for the given modules
-    (all by default); -1 pads."""
+    """For the given modules (all by default): next layers [n, 3], the stored
+    cell regions [n, 3, 192] and the anchors with pitches [n, 3, 5] =
+    (anchor x, y, z, pitch u, pitch v) of each (module, next layer); -1 pads
+    the regions (and the layers)."""
     n_mod = np.asarray(geom["center"]).shape[0]
     mods = np.arange(n_mod) if modules is None else np.asarray(modules)
     layer = np.asarray(geom["layer"])
-    centers = np.asarray(geom["center"], np.float64)
     pts = _ray_points(geom)[mods]
     tm = np.linalg.norm(pts, axis=-1)
     dirs = pts / tm[..., None]
     t = _ray_crossings(geom, dirs)  # (k, 5, L)
     own = layer[mods]
-    n_layers = t.shape[-1]
     t[np.arange(len(mods))[:, None], :, own[:, None]] = np.inf
     t = np.where(t > tm[..., None], t, np.inf)
     first = np.argmin(t, axis=-1)  # (k, 5)
     hit = np.isfinite(np.take_along_axis(t, first[..., None], -1)[..., 0])
     nxt = np.full((len(mods), MAX_NEXT), -1, np.int32)
-    nbr = np.full((len(mods), MAX_NEXT, K_NEIGH), -1, np.int32)
-    anchors = np.zeros((len(mods), MAX_NEXT, 3))
+    reg = np.full((len(mods), MAX_NEXT, REG_U * REG_V), -1, np.int32)
+    anc = np.zeros((len(mods), MAX_NEXT, 5))
     for i in range(len(mods)):
         k = 0
         for r in range(5):
@@ -131,51 +195,161 @@ def neighbour_table(geom, modules=None):
             if L in nxt[i, :k] or k == MAX_NEXT:
                 continue
             nxt[i, k] = L
-            anchors[i, k] = t[i, r, L] * dirs[i, r]
+            A = t[i, r, L] * dirs[i, r]
+            pu, pv, region = _cells(geom, L, A)
+            anc[i, k] = (A[0], A[1], A[2], pu, pv)
+            reg[i, k] = region
             k += 1
-    by_layer = [np.nonzero(layer == L)[0] for L in range(n_layers)]
-    for L in range(n_layers):
-        sel = np.nonzero(nxt == L)
-        if len(sel[0]) == 0:
-            continue
-        cand = by_layer[L]
-        X = anchors[sel]  # (q, 3)
-        d = centers[cand][None, :, :] - X[:, None, :]
-        d2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
-        order = np.lexsort((np.broadcast_to(cand, d2.shape), d2), axis=-1)[:, :K_NEIGH]
-        nbr[sel[0], sel[1], :order.shape[1]] = cand[order]
-    return nxt, nbr, anchors
+    return nxt, reg, anc
 
 
 # ---------------------------------------------------------------------------
 # Network input
 
 
-def features(geom, surface, params, target_layer):
-    """State on module `surface` with bound params (loc0, loc1, phi, theta, q/p)
-    asking for layer `target_layer`: loc0/10, loc1/30, the unit direction in
-    the module frame (u, v, n), q/p in 1/GeV, target layer / number of layers."""
-    surface = np.asarray(surface)
-    p = np.asarray(params, np.float64).reshape(-1, 5)
-    rot = np.asarray(geom["rot"], np.float64).reshape(-1, 3, 3)[surface]
+def _helix_layer_crossing(P, T, qop, B, ltype, pos):
+    """First positive-path crossing of the local helix (field B at P) with a
+    barrel layer's cylinder r = pos or a disk layer's plane z = pos: Newton
+    from the straight-line estimate (the navigation's own definition).
+    Returns (s, point, direction) or None."""
+    kappa = 2.99792458e-4
+    bm = np.linalg.norm(B)
+    bhat = B / bm if bm > 0 else np.array([0.0, 0.0, 1.0])
+    om = kappa * qop * bm
+    tpar = T @ bhat
+    tperp = T - tpar * bhat
+    w = np.cross(T, bhat)
+
+    def at(s):
+        a = om * s
+        if abs(a) < 1e-4:
+            S = s * (1 - a * a / 6.0)
+            Cc = s * (0.5 * a) * (1 - a * a / 12.0)
+        else:
+            S = np.sin(a) / om
+            Cc = 2.0 * np.sin(0.5 * a) ** 2 / om
+        return P + tpar * s * bhat + S * tperp + Cc * w, tpar * bhat + np.cos(a) * tperp + np.sin(a) * w
+
+    if ltype == 0:
+        a = T[0] ** 2 + T[1] ** 2
+        b = P[0] * T[0] + P[1] * T[1]
+        c = P[0] ** 2 + P[1] ** 2 - pos * pos
+        if a < 1e-12 or b * b - a * c < 0:
+            return None
+        s = (-b + np.sqrt(b * b - a * c)) / a
+        if not s > 0:
+            return None
+        for _ in range(20):
+            p, t = at(s)
+            g = p[0] ** 2 + p[1] ** 2 - pos * pos
+            gp = 2.0 * (p[0] * t[0] + p[1] * t[1])
+            if not gp > 0:
+                return None
+            ds = g / gp
+            s -= ds
+            if abs(ds) < 1e-4:
+                break
+        if not s > 0:
+            return None
+        p, t = at(s)
+        if abs(np.hypot(p[0], p[1]) - pos) > 1e-3:
+            return None
+        return s, p, t
+    if abs(T[2]) < 1e-12:
+        return None
+    s = (pos - P[2]) / T[2]
+    if not s > 0:
+        return None
+    for _ in range(20):
+        p, t = at(s)
+        if abs(t[2]) < 1e-12:
+            return None
+        ds = (p[2] - pos) / t[2]
+        s -= ds
+        if abs(ds) < 1e-4:
+            break
+    if not s > 0:
+        return None
+    p, t = at(s)
+    return s, p, t
+
+
+def crossing_window(geom, L, X, anc):
+    """Centre cell (iu, iv) of the proposal window for a crossing X of layer
+    L and the fractional position of X in it (each in [-1/2, 1/2))."""
+    du, dv = layer_coords(geom, L, X, anc[:3])
+    qu, qv = du / anc[3], dv / anc[4]
+    iu, iv = _rnd(qu), _rnd(qv)
+    return int(iu), int(iv), qu - iu, qv - iv
+
+
+def features_at(geom, L, X, Tx, qop, anc):
+    """Network input for a trajectory crossing layer L's envelope at X with
+    direction Tx: its fractional position in the centre cell, the direction
+    in the layer's local frame (phi-hat, then z-hat and r-hat for barrels,
+    r-hat and z-hat for disks), q/p in 1/GeV, L / number of layers."""
     n_layers = np.asarray(geom["layer_type"]).shape[0]
-    ph, th = p[:, 2], p[:, 3]
-    T = np.stack([np.cos(ph) * np.sin(th), np.sin(ph) * np.sin(th), np.cos(th)], axis=-1)
-    loc_dir = np.einsum("kij,kj->ki", rot, T)
-    x = np.empty((p.shape[0], N_IN))
-    x[:, 0] = p[:, 0] / 10.0
-    x[:, 1] = p[:, 1] / 30.0
-    x[:, 2:5] = loc_dir
-    x[:, 5] = p[:, 4]
-    x[:, 6] = np.asarray(target_layer, np.float64) / n_layers
-    return x
+    _, _, fu, fv = crossing_window(geom, L, X, anc)
+    r = np.hypot(X[0], X[1])
+    ph = np.array([-X[1] / r, X[0] / r, 0.0])
+    rh = np.array([X[0] / r, X[1] / r, 0.0])
+    zh = np.array([0.0, 0.0, 1.0])
+    if int(geom["layer_type"][L]) == 0:
+        tv, tn = Tx @ zh, Tx @ rh
+    else:
+        tv, tn = Tx @ rh, Tx @ zh
+    return np.array([fu, fv, Tx @ ph, tv, tn, qop, L / n_layers])
 
 
-def capture_pairs(geom, nxt, nbr, offsets, meas_surface, meas_params):
+def window_label(geom, L, X, anc, region, module):
+    """Position (0..31) of `module` in the proposal window centred on the
+    crossing X, or -1 when it is not in the stored region or the window."""
+    iu, iv, _, _ = crossing_window(geom, L, X, anc)
+    hits = np.nonzero(region == module)[0]
+    if len(hits) == 0:
+        return -1
+    ku, kv = hits[0] % REG_U + RU0, hits[0] // REG_U + RV0
+    wu, wv = ku - iu - WU0, kv - iv - WV0
+    if not (0 <= wu < WIN_U and 0 <= wv < WIN_V):
+        return -1
+    return int(wv * WIN_U + wu)
+
+
+def window_modules(geom, L, X, anc, region):
+    """The 32 window entries (module ids, -1 outside the region or empty)
+    around the crossing X, in output order."""
+    iu, iv, _, _ = crossing_window(geom, L, X, anc)
+    out = np.full(WIN_U * WIN_V, -1, np.int32)
+    for k in range(WIN_U * WIN_V):
+        cu, cv = iu + WU0 + k % WIN_U, iv + WV0 + k // WIN_U
+        if RU0 <= cu < RU0 + REG_U and RV0 <= cv < RV0 + REG_V:
+            out[k] = region[(cv - RV0) * REG_U + (cu - RU0)]
+    return out
+
+
+def state_crossing(geom, surface, params, L, bfield=(0.0, 0.0, 2.0)):
+    """Where the local helix of the bound state on `surface` crosses layer
+    L's envelope (point, direction), or None."""
+    c = np.asarray(geom["center"], np.float64)
+    rot = np.asarray(geom["rot"], np.float64).reshape(-1, 3, 3)
+    p = np.asarray(params, np.float64)
+    P = c[surface] + p[0] * rot[surface, 0] + p[1] * rot[surface, 1]
+    T = np.array([np.cos(p[2]) * np.sin(p[3]), np.sin(p[2]) * np.sin(p[3]), np.cos(p[3])])
+    hx = _helix_layer_crossing(P, T, p[4], np.asarray(bfield, np.float64), int(geom["layer_type"][L]),
+                               float(geom["layer_pos"][L]))
+    return None if hx is None else (hx[1], hx[2])
+
+
+def capture_pairs(geom, nxt, reg, anc, offsets, meas_surface, meas_params, bfield=(0.0, 0.0, 2.0)):
     """Training pairs from found tracks (CSR `offsets` over the measurements,
     each with its module and filtered parameters).  Returns (x [k, 7],
     label [k], track [k], position [k], n_dropped); pairs in track order, then
-    measurement order."""
+    measurement order.  At each change of layer, the state at the last
+    measurement of the layer gives the input (through its helix crossing of
+    the next measurement's layer) and the label is that measurement's
+    module's place in the window; the pair is dropped when the layer is not
+    listed for the module, the helix misses the envelope, or the module is
+    outside the window."""
     layer = np.asarray(geom["layer"])
     xs, labels, trk, posn, dropped = [], [], [], [], 0
     for t in range(len(offsets) - 1):
@@ -185,15 +359,17 @@ def capture_pairs(geom, nxt, nbr, offsets, meas_surface, meas_params):
                 continue
             L2 = int(layer[m2])
             slots = np.nonzero(nxt[m] == L2)[0]
-            if len(slots) == 0:
+            cr = state_crossing(geom, m, meas_params[i], L2, bfield) if len(slots) else None
+            if cr is None:
                 dropped += 1
                 continue
-            pos = np.nonzero(nbr[m, slots[0]] == m2)[0]
-            if len(pos) == 0:
+            s = slots[0]
+            lab = window_label(geom, L2, cr[0], anc[m, s], reg[m, s], m2)
+            if lab < 0:
                 dropped += 1
                 continue
-            xs.append(features(geom, [m], meas_params[i], [L2])[0])
-            labels.append(int(pos[0]))
+            xs.append(features_at(geom, L2, cr[0], cr[1], float(meas_params[i][4]), anc[m, s]))
+            labels.append(lab)
             trk.append(t)
             posn.append(i)
     x = np.array(xs).reshape(-1, N_IN)

@@ -87,13 +87,15 @@ class Geometry:
 
 def neighbours(geometry: Geometry):
     """The geometry's neighbour table (ckf_geometry_neighbours): next layers
-    [n, 3] and neighbour modules [n, 3, 32], -1 padded (numpy)."""
+    [n, 3], anchors [n, 3, 4] = (phi_A, w_A, pitch u, pitch v) and stored
+    cell regions [n, 3, 8 * 24] of module ids, -1 padded (numpy)."""
     n = geometry.n_surfaces
     nxt = np.zeros((n, _abi.MAX_NEXT_LAYERS), np.int32)
-    nbr = np.zeros((n, _abi.MAX_NEXT_LAYERS, _abi.NEIGHBOURS), np.int32)
-    _check(_abi.load().ckf_geometry_neighbours(geometry.handle, nxt.ctypes.data, nbr.ctypes.data),
+    anc = np.zeros((n, _abi.MAX_NEXT_LAYERS, 4), np.float32)
+    reg = np.zeros((n, _abi.MAX_NEXT_LAYERS, _abi.REGION_U * _abi.REGION_V), np.int32)
+    _check(_abi.load().ckf_geometry_neighbours(geometry.handle, nxt.ctypes.data, anc.ctypes.data, reg.ctypes.data),
            "ckf_geometry_neighbours")
-    return nxt, nbr
+    return nxt, anc, reg
 
 
 class Model:
@@ -166,7 +168,7 @@ def mlp_adam(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
                                     float(beta2), float(eps), _stream_handle(stream)), "ckf_mlp_adam")
 
 
-def capture_pairs(geometry: Geometry, out: dict, cap_pairs: int, stream=None):
+def capture_pairs(geometry: Geometry, field, out: dict, cap_pairs: int, stream=None):
     """Training pairs from a Finder's device outputs (made with
     meas_states=True): returns (x [k, 7], label [k], track [k], n_pairs,
     n_dropped) with x/label/track torch device tensors of the captured
@@ -174,16 +176,18 @@ def capture_pairs(geometry: Geometry, out: dict, cap_pairs: int, stream=None):
     import torch
     dev = out["offsets"].device
     cap = max(1, int(cap_pairs))
-    x = torch.empty((cap, _abi.MLP_INPUTS), dtype=torch.float32, device=dev)
-    lab = torch.empty(cap, dtype=torch.int32, device=dev)
-    trk = torch.empty(cap, dtype=torch.int32, device=dev)
-    counts = torch.zeros(2, dtype=torch.int64, device=dev)
-    cap_tracks = int(out["offsets"].numel()) - 1
-    _check(_abi.load().ckf_capture_pairs(geometry.handle, _ptr(out["n_tracks"]), cap_tracks, _ptr(out["offsets"]),
-                                         _ptr(out["meas_surface"]), _ptr(out["meas_params"]), cap, _ptr(x),
-                                         _ptr(lab), _ptr(trk), _ptr(counts), _stream_handle(stream)),
-           "ckf_capture_pairs")
-    c = counts.cpu().numpy()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):  # buffers, the capture and the read-back on one stream
+        x = torch.empty((cap, _abi.MLP_INPUTS), dtype=torch.float32, device=dev)
+        lab = torch.empty(cap, dtype=torch.int32, device=dev)
+        trk = torch.empty(cap, dtype=torch.int32, device=dev)
+        counts = torch.zeros(2, dtype=torch.int64, device=dev)
+        cap_tracks = int(out["offsets"].numel()) - 1
+        _check(_abi.load().ckf_capture_pairs(geometry.handle, field.handle, _ptr(out["n_tracks"]), cap_tracks,
+                                             _ptr(out["offsets"]), _ptr(out["meas_surface"]),
+                                             _ptr(out["meas_params"]), cap, _ptr(x), _ptr(lab), _ptr(trk),
+                                             _ptr(counts), _stream_handle(s)), "ckf_capture_pairs")
+        c = counts.cpu().numpy()
     k = int(min(c[0], cap))
     return x[:k], lab[:k], trk[:k], int(c[0]), int(c[1])
 

@@ -18,6 +18,7 @@ COUNTER_NAMES = ("steps", "navigations", "nav_modules", "legs", "rk_trials", "ch
                  "cycles_search", "cycles_out", "cycles_nav", "cycles_step", "chunks", "cycles_next",
                  "mlp_rows", "proposals", "proposal_misses", "mlp_blocks")
 MAX_NEXT_LAYERS, NEIGHBOURS, MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS = 3, 32, 7, 32, 6752
+REGION_U, REGION_V = 24, 8
 
 
 class GeometryDesc(C.Structure):
@@ -74,7 +75,7 @@ SIGNATURES = {
     "ckf_timer_create": (I32, [C.POINTER(VP)]),
     "ckf_timer_destroy": (None, [VP]),
     "ckf_timer_elapsed_ms": (I32, [VP, C.POINTER(F32)]),
-    "ckf_geometry_neighbours": (I32, [VP, VP, VP]),
+    "ckf_geometry_neighbours": (I32, [VP, VP, VP, VP]),
     "ckf_model_create": (I32, [VP, VP, C.POINTER(VP)]),
     "ckf_model_update": (I32, [VP, VP, VP]),
     "ckf_model_destroy": (None, [VP]),
@@ -82,7 +83,7 @@ SIGNATURES = {
     "ckf_mlp_workspace_size": (I32, [I64, C.POINTER(C.c_size_t)]),
     "ckf_mlp_grad": (I32, [VP, VP, VP, VP, I64, VP, C.c_size_t, VP, VP, VP]),
     "ckf_mlp_adam": (I32, [VP, VP, VP, VP, I32, F32, F32, F32, F32, VP]),
-    "ckf_capture_pairs": (I32, [VP, VP, I32, VP, VP, VP, I64, VP, VP, VP, VP, VP]),
+    "ckf_capture_pairs": (I32, [VP, VP, VP, I32, VP, VP, VP, I64, VP, VP, VP, VP, VP]),
     "ckf_status_string": (C.c_char_p, [I32]),
     "ckf_last_error": (C.c_char_p, []),
 }

@@ -16,6 +16,7 @@ struct ckf_geometry {
   ckf::GeomDev dev;
   std::vector<void*> allocations;
   int device;
+  int nb_rows = 0;  // rows of the neighbour table
 };
 
 struct ckf_field {
@@ -194,31 +195,57 @@ ckf_status upload(ckf_geometry* g, const std::vector<T>& v, const T** out) {
 // (-,-), (+,-), (-,+), (+,+) in (loc0, loc1); each ray's next layer is the
 // layer other than m's whose envelope it meets first, beyond the ray's
 // point on m and within the envelope's extent.  The distinct next layers in
-// ray order (at most kMaxNext) are kept, each with the anchor where its
-// first ray meets the envelope, and the kNeighbours modules of that layer
-// with centres nearest to the anchor (squared distance, ties by id).
-void build_neighbours(const ckf_geometry_desc* d, std::vector<int>& nb_next, std::vector<int>& nb_mod) {
+// ray order (at most kMaxNext) are kept, each with the anchor A where its
+// first ray meets the envelope, the layer's module pitches there and the
+// region of cells around A in the layer's curvilinear coordinates.
+struct NbTable {
+  std::vector<int> next, row, reg;
+  std::vector<float4> anc;
+};
+
+double wrap_pi(double a) {
+  a = std::fmod(a + kPi, 2.0 * kPi);
+  if (a < 0) a += 2.0 * kPi;
+  return a - kPi;
+}
+
+// curvilinear offset of point (x, y, z) from the anchor on layer L:
+// barrels (R dphi, dz), disks (r dphi, dr) with r the point's radius
+void layer_coords(const ckf_geometry_desc* d, int L, const double* X, const double* A, double& du, double& dv) {
+  const double dphi = wrap_pi(std::atan2(X[1], X[0]) - std::atan2(A[1], A[0]));
+  const double rX = std::hypot(X[0], X[1]);
+  if (d->layer_type[L] == 0) {
+    du = dphi * (double)d->layer_pos[L];
+    dv = X[2] - A[2];
+  } else {
+    du = dphi * rX;
+    dv = rX - std::hypot(A[0], A[1]);
+  }
+}
+
+void build_neighbours(const ckf_geometry_desc* d, NbTable& T) {
   const int n = d->n_surfaces, nl = d->n_layers;
-  nb_next.assign((size_t)n * ckf::kMaxNext, -1);
-  nb_mod.assign((size_t)n * ckf::kMaxNext * ckf::kNeighbours, -1);
+  T.next.assign((size_t)n * ckf::kMaxNext, -1);
+  T.row.assign((size_t)n * ckf::kMaxNext, -1);
+  T.reg.clear();
+  T.anc.clear();
   std::vector<std::vector<int>> members(nl);
   for (int i = 0; i < n; ++i) members[d->layer[i]].push_back(i);
-  std::vector<std::pair<double, int>> cand;
+  std::vector<double> du, dv;
   for (int m = 0; m < n; ++m) {
     const float* c = d->center + 3 * m;
     const float* r = d->rot + 9 * m;
     const double h0 = d->half[2 * m], h1 = d->half[2 * m + 1];
     const double sgn[5][2] = {{0, 0}, {-1, -1}, {1, -1}, {-1, 1}, {1, 1}};
     int n_next = 0;
-    double anchors[ckf::kMaxNext][3];
     for (int ray = 0; ray < 5 && n_next < ckf::kMaxNext; ++ray) {
       double q[3];
       for (int k = 0; k < 3; ++k)
         q[k] = ((double)c[k] + sgn[ray][0] * h0 * (double)r[k]) + sgn[ray][1] * h1 * (double)r[3 + k];
       const double tm = std::sqrt((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]);
       if (!(tm > 0)) continue;
-      const double dv[3] = {q[0] / tm, q[1] / tm, q[2] / tm};
-      const double dperp = std::hypot(dv[0], dv[1]);
+      const double dvv[3] = {q[0] / tm, q[1] / tm, q[2] / tm};
+      const double dperp = std::hypot(dvv[0], dvv[1]);
       int best = -1;
       double tbest = INFINITY;
       for (int L = 0; L < nl; ++L) {
@@ -228,11 +255,11 @@ void build_neighbours(const ckf_geometry_desc* d, std::vector<int>& nb_next, std
         if (d->layer_type[L] == 0) {
           if (!(dperp > 0)) continue;
           t = pos / dperp;
-          const double z = t * dv[2];
+          const double z = t * dvv[2];
           if (!(z >= lo && z <= hi)) continue;
         } else {
-          if (dv[2] == 0) continue;
-          t = pos / dv[2];
+          if (dvv[2] == 0) continue;
+          t = pos / dvv[2];
           const double rr = t * dperp;
           if (!(t > 0 && rr >= lo && rr <= hi)) continue;
         }
@@ -244,24 +271,57 @@ void build_neighbours(const ckf_geometry_desc* d, std::vector<int>& nb_next, std
       }
       if (best < 0) continue;
       bool seen = false;
-      for (int k = 0; k < n_next; ++k) seen = seen || nb_next[(size_t)m * ckf::kMaxNext + k] == best;
+      for (int k = 0; k < n_next; ++k) seen = seen || T.next[(size_t)m * ckf::kMaxNext + k] == best;
       if (seen) continue;
-      nb_next[(size_t)m * ckf::kMaxNext + n_next] = best;
-      for (int k = 0; k < 3; ++k) anchors[n_next][k] = tbest * dv[k];
-      ++n_next;
-    }
-    for (int k = 0; k < n_next; ++k) {
-      const std::vector<int>& mem = members[nb_next[(size_t)m * ckf::kMaxNext + k]];
-      cand.clear();
-      for (int j : mem) {
-        const double dx = (double)d->center[3 * j] - anchors[k][0], dy = (double)d->center[3 * j + 1] - anchors[k][1],
-                     dz = (double)d->center[3 * j + 2] - anchors[k][2];
-        cand.emplace_back((dx * dx + dy * dy) + dz * dz, j);
+      const double A[3] = {tbest * dvv[0], tbest * dvv[1], tbest * dvv[2]};
+      // pitches from the module nearest to the anchor, then the cells
+      const std::vector<int>& mem = members[best];
+      du.resize(mem.size());
+      dv.resize(mem.size());
+      size_t a = 0;
+      double d2best = INFINITY;
+      for (size_t j = 0; j < mem.size(); ++j) {
+        const double X[3] = {d->center[3 * mem[j]], d->center[3 * mem[j] + 1], d->center[3 * mem[j] + 2]};
+        layer_coords(d, best, X, A, du[j], dv[j]);
+        const double d2 = du[j] * du[j] + dv[j] * dv[j];
+        if (d2 < d2best || (d2 == d2best && mem[j] < mem[a])) {
+          d2best = d2;
+          a = j;
+        }
       }
-      const size_t kk = std::min<size_t>(cand.size(), ckf::kNeighbours);
-      std::partial_sort(cand.begin(), cand.begin() + kk, cand.end());
-      for (size_t q = 0; q < kk; ++q)
-        nb_mod[((size_t)m * ckf::kMaxNext + k) * ckf::kNeighbours + q] = cand[q].second;
+      const int am = mem[a];
+      double pu = INFINITY, pv = INFINITY;
+      for (size_t j = 0; j < mem.size(); ++j) {
+        const double ou = du[j] - du[a], ov = dv[j] - dv[a];
+        if (std::fabs(ov) < d->half[2 * am + 1] && ou > 1e-3) pu = std::min(pu, ou);
+      }
+      if (!std::isfinite(pu)) pu = 2.0 * d->half[2 * am];
+      for (size_t j = 0; j < mem.size(); ++j) {
+        const double ou = du[j] - du[a], ov = dv[j] - dv[a];
+        if (std::fabs(ou) < 0.5 * pu && ov > 1e-3) pv = std::min(pv, ov);
+      }
+      if (!std::isfinite(pv)) pv = 2.0 * d->half[2 * am + 1];
+      const int row = (int)T.anc.size();
+      std::vector<double> bestd(ckf::kRegCells, INFINITY);
+      T.reg.resize((size_t)(row + 1) * ckf::kRegCells, -1);
+      int* cells = T.reg.data() + (size_t)row * ckf::kRegCells;
+      for (size_t j = 0; j < mem.size(); ++j) {
+        const double iu = std::floor(du[j] / pu + 0.5), iv = std::floor(dv[j] / pv + 0.5);
+        if (iu < ckf::kRegU0 || iu >= ckf::kRegU0 + ckf::kRegU || iv < ckf::kRegV0 || iv >= ckf::kRegV0 + ckf::kRegV)
+          continue;
+        const int k = (int)(iv - ckf::kRegV0) * ckf::kRegU + (int)(iu - ckf::kRegU0);
+        const double eu = du[j] - iu * pu, ev = dv[j] - iv * pv;
+        const double dist = eu * eu + ev * ev;
+        if (dist < bestd[k] || (dist == bestd[k] && mem[j] < cells[k])) {
+          bestd[k] = dist;
+          cells[k] = mem[j];
+        }
+      }
+      const double wA = d->layer_type[best] == 0 ? A[2] : std::hypot(A[0], A[1]);
+      T.anc.push_back(make_float4((float)std::atan2(A[1], A[0]), (float)wA, (float)pu, (float)pv));
+      T.next[(size_t)m * ckf::kMaxNext + n_next] = best;
+      T.row[(size_t)m * ckf::kMaxNext + n_next] = row;
+      ++n_next;
     }
   }
 }
@@ -441,8 +501,8 @@ ckf_status ckf_geometry_create(const ckf_geometry_desc* d, ckf_geometry** out) {
   HostGrid G;
   ckf_status st = build_grid(d, mods, G);
   if (st != CKF_OK) return st;
-  std::vector<int> nb_next, nb_mod;
-  build_neighbours(d, nb_next, nb_mod);
+  NbTable nb;
+  build_neighbours(d, nb);
   ckf_geometry* g = new ckf_geometry();
   hipGetDevice(&g->device);
   auto cleanup = [&](ckf_status s) {
@@ -452,15 +512,20 @@ ckf_status ckf_geometry_create(const ckf_geometry_desc* d, ckf_geometry** out) {
   };
   const ckf::Module* dm;
   const ckf::LayerRec* dl;
-  const int *co, *cm, *bo, *dp, *dn, *nn, *nm;
+  const int *co, *cm, *bo, *dp, *dn, *nn, *nr, *ng;
+  const float4* na;
   if ((st = upload(g, mods, &dm)) != CKF_OK || (st = upload(g, G.layers, &dl)) != CKF_OK ||
       (st = upload(g, G.cell_off, &co)) != CKF_OK || (st = upload(g, G.cell_mod, &cm)) != CKF_OK ||
       (st = upload(g, G.barrel, &bo)) != CKF_OK || (st = upload(g, G.disk_pos, &dp)) != CKF_OK ||
-      (st = upload(g, G.disk_neg, &dn)) != CKF_OK || (st = upload(g, nb_next, &nn)) != CKF_OK ||
-      (st = upload(g, nb_mod, &nm)) != CKF_OK)
+      (st = upload(g, G.disk_neg, &dn)) != CKF_OK || (st = upload(g, nb.next, &nn)) != CKF_OK ||
+      (st = upload(g, nb.row, &nr)) != CKF_OK || (st = upload(g, nb.anc, &na)) != CKF_OK ||
+      (st = upload(g, nb.reg, &ng)) != CKF_OK)
     return cleanup(st);
   g->dev.nb_next = nn;
-  g->dev.nb_mod = nm;
+  g->dev.nb_row = nr;
+  g->dev.nb_anc = na;
+  g->dev.nb_reg = ng;
+  g->nb_rows = (int)nb.anc.size();
   g->dev.n_surfaces = d->n_surfaces;
   g->dev.n_layers = d->n_layers;
   g->dev.mod = dm;
@@ -720,12 +785,37 @@ ckf_status ckf_kf_update_batch(int32_t n, const double* p_in, const double* cov_
   return CKF_OK;
 }
 
-ckf_status ckf_geometry_neighbours(const ckf_geometry* g, int32_t* next_layers, int32_t* neighbours) {
-  if (!g || !next_layers || !neighbours) return fail(CKF_ERR_INVALID_ARGUMENT, "geometry_neighbours: NULL argument");
+ckf_status ckf_geometry_neighbours(const ckf_geometry* g, int32_t* next_layers, float* anchors, int32_t* regions) {
+  if (!g || !next_layers || !anchors || !regions)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "geometry_neighbours: NULL argument");
   const size_t n = (size_t)g->dev.n_surfaces * ckf::kMaxNext;
+  std::vector<int> row(n);
+  std::vector<float4> anc(std::max(1, g->nb_rows));
+  std::vector<int> reg((size_t)std::max(1, g->nb_rows) * ckf::kRegCells);
   HIP_TRY(hipMemcpy(next_layers, g->dev.nb_next, n * sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(neighbours)");
-  HIP_TRY(hipMemcpy(neighbours, g->dev.nb_mod, n * ckf::kNeighbours * sizeof(int), hipMemcpyDeviceToHost),
-          "hipMemcpy(neighbours)");
+  HIP_TRY(hipMemcpy(row.data(), g->dev.nb_row, n * sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(neighbours)");
+  if (g->nb_rows > 0) {
+    HIP_TRY(hipMemcpy(anc.data(), g->dev.nb_anc, (size_t)g->nb_rows * sizeof(float4), hipMemcpyDeviceToHost),
+            "hipMemcpy(neighbours)");
+    HIP_TRY(hipMemcpy(reg.data(), g->dev.nb_reg, (size_t)g->nb_rows * ckf::kRegCells * sizeof(int),
+                      hipMemcpyDeviceToHost),
+            "hipMemcpy(neighbours)");
+  }
+  for (size_t i = 0; i < n; ++i) {
+    float* a = anchors + 4 * i;
+    int32_t* r = regions + i * ckf::kRegCells;
+    if (row[i] < 0) {
+      a[0] = a[1] = a[2] = a[3] = 0.f;
+      for (int k = 0; k < ckf::kRegCells; ++k) r[k] = -1;
+      continue;
+    }
+    const float4 v = anc[row[i]];
+    a[0] = v.x;
+    a[1] = v.y;
+    a[2] = v.z;
+    a[3] = v.w;
+    std::memcpy(r, reg.data() + (size_t)row[i] * ckf::kRegCells, ckf::kRegCells * sizeof(int));
+  }
   return CKF_OK;
 }
 
@@ -803,15 +893,16 @@ ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, in
   return CKF_OK;
 }
 
-ckf_status ckf_capture_pairs(const ckf_geometry* g, const int32_t* n_tracks, int32_t cap_tracks,
-                             const int32_t* offsets, const int32_t* meas_surface, const double* meas_params,
-                             int64_t cap_pairs, float* x, int32_t* label, int32_t* track, int64_t* counts,
-                             void* stream) {
-  if (!g || !n_tracks || !offsets || !meas_surface || !meas_params || !counts || cap_tracks < 0 || cap_pairs < 0 ||
-      (cap_pairs > 0 && (!x || !label)))
+ckf_status ckf_capture_pairs(const ckf_geometry* g, const ckf_field* field, const int32_t* n_tracks,
+                             int32_t cap_tracks, const int32_t* offsets, const int32_t* meas_surface,
+                             const double* meas_params, int64_t cap_pairs, float* x, int32_t* label,
+                             int32_t* track, int64_t* counts, void* stream) {
+  if (!g || !field || !n_tracks || !offsets || !meas_surface || !meas_params || !counts || cap_tracks < 0 ||
+      cap_pairs < 0 || (cap_pairs > 0 && (!x || !label)))
     return fail(CKF_ERR_INVALID_ARGUMENT, "capture_pairs: bad argument");
-  HIP_TRY(ckf::launch_capture_pairs(g->dev, n_tracks, cap_tracks, offsets, meas_surface, meas_params, cap_pairs, x,
-                                    label, track, reinterpret_cast<long long*>(counts),
+  if (field->dev.map) return fail(CKF_ERR_NOT_SUPPORTED, "capture_pairs: uniform field only");
+  HIP_TRY(ckf::launch_capture_pairs(g->dev, field->dev, n_tracks, cap_tracks, offsets, meas_surface, meas_params,
+                                    cap_pairs, x, label, track, reinterpret_cast<long long*>(counts),
                                     static_cast<hipStream_t>(stream)),
           "launch k_capture_pairs");
   return CKF_OK;

@@ -17,7 +17,11 @@ constexpr float kReach = 30.0f;    // mm, envelope-to-module reach of the candid
 constexpr float kGridPad = 5.0f;   // mm, padding of module extents in the navigation grid
 constexpr float kMaxNavMargin = 2.0f;
 constexpr int kMaxNext = CKF_MAX_NEXT_LAYERS;  // next layers per module in the neighbour table
-constexpr int kNeighbours = CKF_NEIGHBOURS;    // modules per (module, next layer)
+constexpr int kNeighbours = CKF_NEIGHBOURS;    // network outputs: the proposal window's cells
+constexpr int kWinU = 8, kWinV = 4, kWinU0 = -4, kWinV0 = -2;          // window cells around the crossing
+constexpr int kRegU = CKF_REGION_U, kRegV = CKF_REGION_V, kRegU0 = -12, kRegV0 = -4;  // stored region
+constexpr int kRegCells = kRegU * kRegV;
+static_assert(kWinU * kWinV == kNeighbours, "window size");
 
 // Surface store: one 64-byte record per module (a lane reads one record per
 // access; records of neighbouring modules share cache lines).
@@ -53,10 +57,14 @@ struct GeomDev {
   const int* disk_pos = nullptr;      // z > 0 disks by |z|
   const int* disk_neg = nullptr;      // z < 0 disks by |z|
   int n_barrel = 0, n_disk_pos = 0, n_disk_neg = 0;
-  // neighbour table of the learned proposal: per module the next layers
-  // [n][kMaxNext] (-1 pads) and per (module, slot) kNeighbours module ids
+  // neighbour table of the learned proposal: per module the next layers and
+  // their rows [n][kMaxNext] (-1 pads); per row the anchor and pitches
+  // (phi_A, w_A, pitch u, pitch v) and the stored region of kRegCells
+  // module ids (-1 empty), cell (iu, iv) at (iv - kRegV0) * kRegU + iu - kRegU0
   const int* nb_next = nullptr;
-  const int* nb_mod = nullptr;
+  const int* nb_row = nullptr;
+  const float4* nb_anc = nullptr;
+  const int* nb_reg = nullptr;
 };
 
 // Field: uniform (map == nullptr) or a solenoidal (r, z) map interpolated

@@ -369,7 +369,8 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       LegT<kMap ? 5 : 3> L;
       V3 uA, vA, origin, Pl, Tl;
       bool go = false, need_list = false;
-      int lay = 0, excl = -1, nb_slot = -1;
+      int lay = 0, excl = -1, nb_slot = -1, nb_row = -1;
+      Window win{0, 0, 0.f, 0.f};
       float sb = 0.f;
       long long t_nav = 0;
       int prop[3] = {-1, -1, -1};
@@ -426,9 +427,13 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
 #pragma unroll
               for (int q = 0; q < kMaxNext; ++q)
                 if (nb_slot < 0 && g.nb_next[surf * kMaxNext + q] == nl) nb_slot = q;
+              if (nb_slot >= 0) {
+                nb_row = g.nb_row[surf * kMaxNext + nb_slot];
+                if (!crossing_window(g.layers[nl], g.nb_anc[nb_row], Pl, win)) nb_slot = -1;
+              }
               if (nb_slot >= 0) {  // the network input goes to LDS now
                 float f[7];
-                mlp_features(Am, p, lay, g.n_layers, f);
+                mlp_features(g.layers[nl], nl, g.n_layers, win, Pl, Tl, L.lam, f);
 #pragma unroll
                 for (int c = 0; c < 7; ++c) sh_x[lane * 8 + c] = bf16_bits(f[c]);
                 sh_x[lane * 8 + 7] = 0;
@@ -448,37 +453,39 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           }
           __syncthreads();
           const int q4 = 4 * (lane >> 4);
+          // all four 16-row blocks together: each weight tile is read once
+          bf16x4 xb[4];
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb) {
+            const int src = (16 * rb + (lane & 15)) * 8 + q4;
+            xb[rb].x = q4 < 8 ? (short)sh_x[src + 0] : (short)0;
+            xb[rb].y = q4 < 8 ? (short)sh_x[src + 1] : (short)0;
+            xb[rb].z = q4 < 8 ? (short)sh_x[src + 2] : (short)0;
+            xb[rb].w = q4 < 8 ? (short)sh_x[src + 3] : (short)0;
+          }
+          f32x4 out[4][2];
+          mlp_wave(A.model, xb, lane, out);
+          if (kCount && lane == 0) CNT_ADD(CKF_CNT_MLP_BLOCKS, 4);
           Top3 mine;
           float conf = 0.f;
-#pragma unroll 1
+#pragma unroll
           for (int rb = 0; rb < 4; ++rb) {
-            if (((wm >> (16 * rb)) & 0xffffull) == 0) continue;
-            bf16x4 xb;
-            const int src = (16 * rb + (lane & 15)) * 8 + q4;
-            xb.x = q4 < 8 ? (short)sh_x[src + 0] : (short)0;
-            xb.y = q4 < 8 ? (short)sh_x[src + 1] : (short)0;
-            xb.z = q4 < 8 ? (short)sh_x[src + 2] : (short)0;
-            xb.w = q4 < 8 ? (short)sh_x[src + 3] : (short)0;
-            f32x4 out[2];
-            mlp_block(A.model, xb, lane, out);
             Top3 t;
             float c;
-            mlp_top3(out, lane, cfg.topk, t, c);
+            mlp_top3(out[rb], lane, cfg.topk, t, c);
             if ((lane >> 4) == rb) {
               mine = t;
               conf = c;
             }
-            if (kCount && lane == 0) CNT_ADD(CKF_CNT_MLP_BLOCKS, 1);
           }
           __syncthreads();
           if (nb_slot >= 0) {
             CNT_ADD(CKF_CNT_MLP_ROWS, 1);
             confident = conf >= cfg.min_prob;
-            const int* nb = g.nb_mod + ((long long)surf * kMaxNext + nb_slot) * kNeighbours;
 #pragma unroll
             for (int k = 0; k < 3; ++k)  // (a class outside 0..31 only if the logits were not finite)
-              if (k < cfg.topk && mine.c[k] >= 0 && mine.c[k] < kNeighbours) prop[k] = nb[mine.c[k]];
-            confident = confident && prop[0] >= 0;
+              if (k < cfg.topk && mine.c[k] >= 0 && mine.c[k] < kNeighbours)
+                prop[k] = window_module(g, nb_row, win, mine.c[k]);
           }
         }
       };

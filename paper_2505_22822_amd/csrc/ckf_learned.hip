@@ -310,7 +310,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh_w, int& total) {
   return base + x - v;
 }
 
-__global__ void __launch_bounds__(kCapThreads) k_capture_pairs(GeomDev g, const int* __restrict__ n_tracks_p,
+__global__ void __launch_bounds__(kCapThreads) k_capture_pairs(GeomDev g, FieldDev F, const int* __restrict__ n_tracks_p,
                                                                int cap_tracks, const int* __restrict__ off,
                                                                const int* __restrict__ msurf,
                                                                const double* __restrict__ mpar, long long cap_pairs,
@@ -339,18 +339,36 @@ __global__ void __launch_bounds__(kCapThreads) k_capture_pairs(GeomDev g, const 
           if (L == L2) continue;
           int slot = -1;
           for (int s = 0; s < kMaxNext; ++s)
-            if (g.nb_next[m * kMaxNext + s] == L2) {
-              slot = s;
-              break;
-            }
+            if (slot < 0 && g.nb_next[m * kMaxNext + s] == L2) slot = s;
+          // the local helix from the state on m to L2's envelope, as the navigation finds it
           int lab = -1;
-          if (slot >= 0) {
-            const int* nb = g.nb_mod + ((long long)m * kMaxNext + slot) * kNeighbours;
-            for (int q = 0; q < kNeighbours; ++q)
-              if (nb[q] == m2) {
-                lab = q;
-                break;
+          V3 X = {0.f, 0.f, 0.f}, Tx = {0.f, 0.f, 0.f};
+          Window w{0, 0, 0.f, 0.f};
+          const LayerRec Lr = g.layers[L2];
+          const int row = slot >= 0 ? g.nb_row[m * kMaxNext + slot] : -1;
+          if (row >= 0) {
+            Module M;
+            load_module(g, m, M);
+            const double* p = mpar + 5ll * i;
+            float sp, cp, st, ct;
+            sincosf((float)p[2], &sp, &cp);
+            sincosf((float)p[3], &st, &ct);
+            const V3 P = ld3(M.c) + (float)p[0] * ld3(M.u) + (float)p[1] * ld3(M.v);
+            const V3 T = {cp * st, sp * st, ct};
+            const Helix H = make_helix(P, T, (float)p[4], field_at<false>(F, P));
+            float sc;
+            const bool hit = Lr.type == 0 ? cross_cylinder(H, Lr.pos, sc) : cross_zplane(H, Lr.pos, sc);
+            if (hit) {
+              helix_at(H, sc, X, Tx);
+              if (crossing_window(Lr, g.nb_anc[row], X, w)) {
+                const int* reg = g.nb_reg + (long long)row * kRegCells;
+                for (int q = 0; q < kRegCells; ++q)
+                  if (lab < 0 && reg[q] == m2) {
+                    const int wu = (q % kRegU + kRegU0) - w.iu - kWinU0, wv = (q / kRegU + kRegV0) - w.iv - kWinV0;
+                    lab = (wu >= 0 && wu < kWinU && wv >= 0 && wv < kWinV) ? wv * kWinU + wu : -2;
+                  }
               }
+            }
           }
           if (lab < 0) {
             if (pass == 0) ++drop;
@@ -363,10 +381,8 @@ __global__ void __launch_bounds__(kCapThreads) k_capture_pairs(GeomDev g, const 
           const long long o = base + pos + k;
           ++k;
           if (o >= cap_pairs) continue;
-          Module M;
-          load_module(g, m, M);
           float f[7];
-          mlp_features(M, mpar + 5ll * i, L2, g.n_layers, f);
+          mlp_features(Lr, L2, g.n_layers, w, X, Tx, (float)mpar[5ll * i + 4], f);
           for (int c = 0; c < 7; ++c) x[o * 7 + c] = f[c];
           label[o] = lab;
           if (track) track[o] = t;
@@ -431,11 +447,11 @@ hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad,
   return hipGetLastError();
 }
 
-hipError_t launch_capture_pairs(const GeomDev& g, const int* n_tracks, int cap_tracks, const int* off,
-                                const int* msurf, const double* mpar, long long cap_pairs, float* x, int* label,
-                                int* track, long long* counts, hipStream_t st) {
-  hipLaunchKernelGGL(k_capture_pairs, dim3(1), dim3(kCapThreads), 0, st, g, n_tracks, cap_tracks, off, msurf, mpar,
-                     cap_pairs, x, label, track, counts);
+hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* n_tracks, int cap_tracks,
+                                const int* off, const int* msurf, const double* mpar, long long cap_pairs, float* x,
+                                int* label, int* track, long long* counts, hipStream_t st) {
+  hipLaunchKernelGGL(k_capture_pairs, dim3(1), dim3(kCapThreads), 0, st, g, f, n_tracks, cap_tracks, off, msurf,
+                     mpar, cap_pairs, x, label, track, counts);
   return hipGetLastError();
 }
 

@@ -93,22 +93,100 @@ __device__ __forceinline__ void mlp_block(const ModelDev& M, bf16x4 xb, int lane
   }
 }
 
-// Network input for the state on module M with bound parameters p, asking
-// for layer `target`: loc0/10, loc1/30, the unit direction in the module's
-// (u, v, n) frame, q/p in 1/GeV, target / n_layers.
-__device__ __forceinline__ void mlp_features(const Module& M, const double* p, int target, int n_layers,
-                                             float x[7]) {
-  float sp, cp, st, ct;
-  sincosf((float)p[2], &sp, &cp);
-  sincosf((float)p[3], &st, &ct);
-  const V3 T = {cp * st, sp * st, ct};
-  x[0] = (float)p[0] * 0.1f;
-  x[1] = (float)p[1] * (1.0f / 30.0f);
-  x[2] = dot(ld3(M.u), T);
-  x[3] = dot(ld3(M.v), T);
-  x[4] = dot(ld3(M.n), T);
-  x[5] = (float)p[4];
-  x[6] = (float)target / (float)n_layers;
+// Logits of all four 16-row blocks of a wave at once: every weight tile is
+// fetched once and applied to the four blocks, which gives four independent
+// MFMA chains.  xb[rb]: this lane's B operand of the input of rows
+// 16*rb + l%16.  Must be called by all 64 lanes together.
+__device__ __forceinline__ void mlp_wave(const ModelDev& M, const bf16x4 xb[4], int lane, f32x4 out[4][2]) {
+  const int q4 = 4 * (lane >> 4);
+  bf16x4 h1[4][4], h2[4][4];
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    const f32x4 b = ld_f4(M.b1 + 16 * ob + q4);
+    const bf16x4 w = as_bf16x4(M.w1[ob * 64 + lane]);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) h1[rb][ob] = relu_bf16(mfma16(w, xb[rb], b));
+  }
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    f32x4 acc[4];
+    const f32x4 b = ld_f4(M.b2 + 16 * ob + q4);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = b;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const bf16x4 w = as_bf16x4(M.w2[(ob * 4 + kb) * 64 + lane]);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma16(w, h1[rb][kb], acc[rb]);
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) h2[rb][ob] = relu_bf16(acc[rb]);
+  }
+#pragma unroll
+  for (int ob = 0; ob < 2; ++ob) {
+    const f32x4 b = ld_f4(M.b3 + 16 * ob + q4);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) out[rb][ob] = b;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const bf16x4 w = as_bf16x4(M.w3[(ob * 4 + kb) * 64 + lane]);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) out[rb][ob] = mfma16(w, h2[rb][kb], out[rb][ob]);
+    }
+  }
+}
+
+// Proposal window of a crossing X of layer Lr's envelope, for a neighbour
+// table row with anchor (phi_A, w_A, pitch u, pitch v): the centre cell
+// (iu, iv) in the layer's curvilinear coordinates - (R dphi, dz) on a
+// barrel, (r dphi, dr) on a disk - and X's fractional position in it.
+// Returns false for a non-finite or far-away crossing.
+struct Window {
+  int iu, iv;
+  float fu, fv;
+};
+
+__device__ __forceinline__ bool crossing_window(const LayerRec& Lr, float4 anc, V3 X, Window& w) {
+  const float r = sqrtf(X.x * X.x + X.y * X.y);
+  float dphi = atan2f(X.y, X.x) - anc.x;
+  if (dphi >= 3.14159265f) dphi -= 6.28318531f;
+  if (dphi < -3.14159265f) dphi += 6.28318531f;
+  const float du = Lr.type == 0 ? dphi * Lr.pos : dphi * r;
+  const float dv = Lr.type == 0 ? X.z - anc.y : r - anc.y;
+  const float qu = du / anc.z, qv = dv / anc.w;
+  if (!(fabsf(qu) < 1000.f && fabsf(qv) < 1000.f)) return false;
+  const float cu = floorf(qu + 0.5f), cv = floorf(qv + 0.5f);
+  w.iu = (int)cu;
+  w.iv = (int)cv;
+  w.fu = qu - cu;
+  w.fv = qv - cv;
+  return true;
+}
+
+// Network input at a crossing X (direction T) of layer `L`: the fractional
+// cell position, the direction in the layer frame (phi-hat, then z-hat and
+// r-hat on barrels, r-hat and z-hat on disks), q/p, L / n_layers.
+__device__ __forceinline__ void mlp_features(const LayerRec& Lr, int L, int n_layers, const Window& w, V3 X, V3 T,
+                                             float qop, float x[7]) {
+  const float r = sqrtf(X.x * X.x + X.y * X.y);
+  const float ir = r > 0.f ? 1.0f / r : 0.f;
+  const float tphi = (-X.y * T.x + X.x * T.y) * ir;
+  const float tr = (X.x * T.x + X.y * T.y) * ir;
+  x[0] = w.fu;
+  x[1] = w.fv;
+  x[2] = tphi;
+  x[3] = Lr.type == 0 ? T.z : tr;
+  x[4] = Lr.type == 0 ? tr : T.z;
+  x[5] = qop;
+  x[6] = (float)L / (float)n_layers;
+}
+
+// Module id of output k (0..31) of the window, or -1 (empty cell or outside
+// the stored region).
+__device__ __forceinline__ int window_module(const GeomDev& g, int row, const Window& w, int k) {
+  const int cu = w.iu + kWinU0 + (k % kWinU), cv = w.iv + kWinV0 + k / kWinU;
+  if (cu < kRegU0 || cu >= kRegU0 + kRegU || cv < kRegV0 || cv >= kRegV0 + kRegV) return -1;
+  return g.nb_reg[(long long)row * kRegCells + (cv - kRegV0) * kRegU + (cu - kRegU0)];
 }
 
 // Sorted top-3 (value descending, class ascending) of (v, c) pairs.

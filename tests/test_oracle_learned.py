@@ -118,17 +118,26 @@ def tiny_truth():
     return det, ev
 
 
-def test_neighbour_table_covers_truth_transitions(tiny_truth):
-    """Particles from the origin (tiny event, pT 1-10 GeV): every layer change
-    of the truth trajectory goes to a layer listed as next for the module it
-    leaves, and to one of that layer's 32 listed modules."""
+def _full_table(g, mods):
+    n_mod = g["center"].shape[0]
+    sn, sr, sa = OL.neighbour_table(g, modules=mods)
+    nxt = np.full((n_mod, OL.MAX_NEXT), -1, np.int32)
+    reg = np.full((n_mod, OL.MAX_NEXT, OL.REG_U * OL.REG_V), -1, np.int32)
+    anc = np.zeros((n_mod, OL.MAX_NEXT, 5))
+    nxt[mods], reg[mods], anc[mods] = sn, sr, sa
+    return nxt, reg, anc
+
+
+def test_window_covers_truth_transitions(tiny_truth):
+    """Particles from the origin (tiny event, pT 1-10 GeV): at every layer
+    change of the truth trajectory the next layer is listed for the module
+    left, and the module crossed there lies in the 32-cell window around
+    the local helix's crossing of that layer's envelope."""
     det, ev = tiny_truth
     g = det.as_arrays()
     tr = ev.truth
     layer = g["layer"]
-    mods = np.unique(tr.surface)
-    nxt, nbr, anchors = OL.neighbour_table(g, modules=mods)
-    row = {int(m): i for i, m in enumerate(mods)}
+    nxt, reg, anc = _full_table(g, np.unique(tr.surface))
     n = ok = 0
     for k in range(len(tr.particle) - 1):
         if tr.particle[k] != tr.particle[k + 1]:
@@ -137,74 +146,105 @@ def test_neighbour_table_covers_truth_transitions(tiny_truth):
         if layer[m] == layer[m2]:
             continue
         n += 1
-        i = row[m]
-        s = np.nonzero(nxt[i] == layer[m2])[0]
-        ok += len(s) > 0 and m2 in nbr[i, s[0]]
+        s = np.nonzero(nxt[m] == layer[m2])[0]
+        if len(s) == 0:
+            continue
+        d = tr.dir[k]
+        p = [tr.loc[k, 0], tr.loc[k, 1], np.arctan2(d[1], d[0]), np.arccos(d[2]), tr.qop[k]]
+        cr = OL.state_crossing(g, m, p, int(layer[m2]))
+        if cr is None:
+            continue
+        ok += OL.window_label(g, int(layer[m2]), cr[0], anc[m, s[0]], reg[m, s[0]], m2) >= 0
     assert n > 500 and ok / n >= 0.995, (ok, n)
 
 
-def test_neighbour_table_invariants():
+def test_region_invariants():
+    """Anchors lie on the layer's envelope, beyond the module; every stored
+    module belongs to the layer and sits in the cell its centre offset
+    rounds to; a module appears at most once; and the module nearest to the
+    anchor is the region's centre cell."""
     from synth import barrel_endcap
     det = barrel_endcap()
     g = det.as_arrays()
     rng = np.random.Generator(np.random.PCG64(5))
-    mods = rng.choice(g["center"].shape[0], 400, replace=False)
-    nxt, nbr, anchors = OL.neighbour_table(g, modules=mods)
+    mods = rng.choice(g["center"].shape[0], 300, replace=False)
+    nxt, reg, anc = OL.neighbour_table(g, modules=mods)
     layer = g["layer"]
     c = g["center"].astype(np.float64)
     for i, m in enumerate(mods):
         for s in range(OL.MAX_NEXT):
             L = nxt[i, s]
             if L < 0:
-                assert np.all(nbr[i, s] == -1)
+                assert np.all(reg[i, s] == -1)
                 continue
             assert L != layer[m]
-            X = anchors[i, s]
+            A = anc[i, s, :3]
             if g["layer_type"][L] == 0:
-                assert abs(np.hypot(X[0], X[1]) - g["layer_pos"][L]) < 1e-9
+                assert abs(np.hypot(A[0], A[1]) - g["layer_pos"][L]) < 1e-9
             else:
-                assert abs(X[2] - g["layer_pos"][L]) < 1e-9
-            # anchor further out along its ray than the module
-            assert np.linalg.norm(X) > np.linalg.norm(c[m]) - np.hypot(*g["half"][m])
-            ids = nbr[i, s][nbr[i, s] >= 0]
-            assert len(ids) == min(32, int((layer == L).sum()))
-            assert np.all(layer[ids] == L)
-            d = np.linalg.norm(c[ids] - X, axis=1)
-            assert np.all(np.diff(d) >= -1e-9)
-            rest = np.setdiff1d(np.nonzero(layer == L)[0], ids)
-            if len(rest):
-                assert np.linalg.norm(c[rest] - X, axis=1).min() >= d.max() - 1e-9
+                assert abs(A[2] - g["layer_pos"][L]) < 1e-9
+            assert np.linalg.norm(A) > np.linalg.norm(c[m]) - np.hypot(*g["half"][m])
+            pu, pv = anc[i, s, 3], anc[i, s, 4]
+            assert 5.0 < pu < 25.0 and 20.0 < pv < 70.0
+            ids = reg[i, s]
+            k = np.nonzero(ids >= 0)[0]
+            assert len(k) > 0 and len(set(ids[k])) == len(k)
+            assert np.all(layer[ids[k]] == L)
+            du, dv = OL.layer_coords(g, L, c[ids[k]], A)
+            np.testing.assert_array_equal(OL._rnd(du / pu), k % OL.REG_U + OL.RU0)
+            np.testing.assert_array_equal(OL._rnd(dv / pv), k // OL.REG_U + OL.RV0)
+            mem = np.nonzero(layer == L)[0]
+            du_all, dv_all = OL.layer_coords(g, L, c[mem], A)
+            near = mem[np.argmin(du_all * du_all + dv_all * dv_all)]
+            centre = (0 - OL.RV0) * OL.REG_U + (0 - OL.RU0)
+            assert ids[centre] == near
 
 
 def test_features_definition():
+    """Straight line (no field) from a barrel module: the crossing of the
+    next barrel's cylinder is the closed-form line/cylinder solution, the
+    input's position is its fractional cell offset and the direction is the
+    line's direction in the layer frame."""
     from synth import barrel_endcap
     det = barrel_endcap()
     g = det.as_arrays()
-    rng = np.random.Generator(np.random.PCG64(9))
-    surf = rng.integers(0, g["center"].shape[0], 50)
-    p = np.column_stack([rng.uniform(-10, 10, 50), rng.uniform(-30, 30, 50), rng.uniform(-3, 3, 50),
-                         rng.uniform(0.2, 2.9, 50), rng.uniform(-2, 2, 50)])
-    x = OL.features(g, surf, p, np.full(50, 5))
-    np.testing.assert_allclose(x[:, 0], p[:, 0] / 10)
-    np.testing.assert_allclose(x[:, 1], p[:, 1] / 30)
-    np.testing.assert_allclose(np.linalg.norm(x[:, 2:5], axis=1), 1.0, atol=1e-12)
-    np.testing.assert_allclose(x[:, 5], p[:, 4])
-    np.testing.assert_allclose(x[:, 6], 5 / g["layer_type"].shape[0])
-    # a module frame equal to the global axes gives the global direction
-    g2 = dict(g)
-    rot = g["rot"].copy()
-    rot[surf[0]] = np.eye(3, dtype=np.float32).reshape(-1)
-    g2["rot"] = rot
-    x0 = OL.features(g2, surf[:1], p[:1], [5])[0]
-    ph, th = p[0, 2], p[0, 3]
-    np.testing.assert_allclose(x0[2:5], [np.cos(ph) * np.sin(th), np.sin(ph) * np.sin(th), np.cos(th)], atol=1e-15)
+    l1 = np.nonzero(g["layer"] == 1)[0]
+    m = int(l1[np.argmin(np.abs(g["center"][l1, 2]))])  # a central module: the next layer is a barrel
+    nxt, reg, anc = OL.neighbour_table(g, modules=[m])
+    L = int(nxt[0, 0])
+    assert g["layer_type"][L] == 0
+    p = np.array([2.0, -7.0, 0.3, 1.4, 0.8])
+    X, Tx = OL.state_crossing(g, m, p, L, bfield=(0.0, 0.0, 0.0))
+    rot = g["rot"].reshape(-1, 3, 3).astype(np.float64)
+    P = g["center"][m].astype(np.float64) + p[0] * rot[m, 0] + p[1] * rot[m, 1]
+    T = np.array([np.cos(p[2]) * np.sin(p[3]), np.sin(p[2]) * np.sin(p[3]), np.cos(p[3])])
+    R = float(g["layer_pos"][L])
+    a, b, cc = T[0] ** 2 + T[1] ** 2, P[0] * T[0] + P[1] * T[1], P[0] ** 2 + P[1] ** 2 - R * R
+    s = (-b + np.sqrt(b * b - a * cc)) / a
+    np.testing.assert_allclose(X, P + s * T, atol=1e-9)
+    np.testing.assert_allclose(Tx, T, atol=1e-12)
+    x = OL.features_at(g, L, X, Tx, p[4], anc[0, 0])
+    A = anc[0, 0, :3]
+    du = ((np.arctan2(X[1], X[0]) - np.arctan2(A[1], A[0]) + np.pi) % (2 * np.pi) - np.pi) * R
+    qu = du / anc[0, 0, 3]
+    assert abs(x[0] - (qu - np.floor(qu + 0.5))) < 1e-12 and -0.5 <= x[0] < 0.5
+    qv = (X[2] - A[2]) / anc[0, 0, 4]
+    assert abs(x[1] - (qv - np.floor(qv + 0.5))) < 1e-12
+    r = np.hypot(X[0], X[1])
+    np.testing.assert_allclose(x[2:5], [(-X[1] * T[0] + X[0] * T[1]) / r, T[2], (X[0] * T[0] + X[1] * T[1]) / r],
+                               atol=1e-12)
+    assert x[5] == p[4] and x[6] == L / g["layer_type"].shape[0]
+    # the window's module ids are the region's cells around the crossing
+    win = OL.window_modules(g, L, X, anc[0, 0], reg[0, 0])
+    lab = OL.window_label(g, L, X, anc[0, 0], reg[0, 0], win[20])
+    assert win[20] < 0 or lab == 20
 
 
 def test_pairs_from_oracle_tracks(tiny_truth):
     """Pairs taken from the oracle's own tracks on the tiny event: the label
-    points at the module of the next measurement, the state is that of the
-    measurement the pair starts from, and the per-measurement states end in
-    the track's output state."""
+    points at the module of the next measurement in the window, the input is
+    that of the measurement the pair starts from, and the per-measurement
+    states end in the track's output state."""
     import oracle
     det, ev = tiny_truth
     g = det.as_arrays()
@@ -214,13 +254,8 @@ def test_pairs_from_oracle_tracks(tiny_truth):
     assert r["n_tracks"] > 90
     np.testing.assert_array_equal(mp[off[1:] - 1], r["params"])
     np.testing.assert_array_equal(ms[off[1:] - 1], r["last_surface"])
-    mods = np.unique(ms)
-    sub_nxt, sub_nbr, _ = OL.neighbour_table(g, modules=mods)
-    n_mod = g["center"].shape[0]
-    nxt = np.full((n_mod, OL.MAX_NEXT), -1, np.int32)
-    nbr = np.full((n_mod, OL.MAX_NEXT, OL.K_NEIGH), -1, np.int32)
-    nxt[mods], nbr[mods] = sub_nxt, sub_nbr
-    x, lab, trk, pos, dropped = OL.capture_pairs(g, nxt, nbr, off, ms, mp)
+    nxt, reg, anc = _full_table(g, np.unique(ms))
+    x, lab, trk, pos, dropped = OL.capture_pairs(g, nxt, reg, anc, off, ms, mp)
     layer = g["layer"]
     changes = sum(int(layer[ms[i]] != layer[ms[i + 1]]) for t in range(len(off) - 1)
                   for i in range(off[t], off[t + 1] - 1))
@@ -229,9 +264,10 @@ def test_pairs_from_oracle_tracks(tiny_truth):
     for k in range(len(lab)):
         m, m2 = ms[pos[k]], ms[pos[k] + 1]
         s = list(nxt[m]).index(layer[m2])
-        assert nbr[m, s, lab[k]] == m2
+        X, Tx = OL.state_crossing(g, m, mp[pos[k]], int(layer[m2]))
+        assert OL.window_modules(g, int(layer[m2]), X, anc[m, s], reg[m, s])[lab[k]] == m2
+        np.testing.assert_array_equal(x[k], OL.features_at(g, int(layer[m2]), X, Tx, mp[pos[k]][4], anc[m, s]))
         assert off[trk[k]] <= pos[k] < off[trk[k] + 1] - 1
-    np.testing.assert_array_equal(x, OL.features(g, ms[pos], mp[pos], layer[ms[pos + 1]]))
 
 
 def test_bf16_gradient_mode_stays_close():
