@@ -347,11 +347,12 @@ ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, in
 /* Training pairs from found tracks (device memory): at every change of
  * layer between consecutive measurements of a track, the network input of
  * the state at the last measurement of the layer - through its local
- * helix's crossing of the next measurement's layer, in `field` - and the
- * position of the next measurement's module in the window around that
- * crossing.  A pair is dropped when that layer is not listed for the
- * module, the helix misses the envelope, or the module is outside the
- * window (or a module id is out of range).  Pairs are written in track
+ * helix's crossing of the next measurement's layer, in `field` - paired
+ * with the position in the window around that crossing of the module of
+ * each measurement the track has on that layer (overlapping modules give
+ * several pairs with the same input).  A pair is dropped when that layer
+ * is not listed for the module, the helix misses the envelope, or the
+ * module is outside the window (or a module id is out of range).  Pairs are written in track
  * order, then measurement order, up to cap_pairs: x [cap][7], label [cap],
  * track [cap] (may be NULL).  counts [2] receives the number of pairs (also
  * beyond cap) and of dropped pairs.  n_tracks is a device int32 (as

@@ -346,32 +346,37 @@ def capture_pairs(geom, nxt, reg, anc, offsets, meas_surface, meas_params, bfiel
     label [k], track [k], position [k], n_dropped); pairs in track order, then
     measurement order.  At each change of layer, the state at the last
     measurement of the layer gives the input (through its helix crossing of
-    the next measurement's layer) and the label is that measurement's
-    module's place in the window; the pair is dropped when the layer is not
-    listed for the module, the helix misses the envelope, or the module is
-    outside the window."""
+    the next measurement's layer), and every measurement of the track on
+    that layer (overlapping modules give several) gives one pair with its
+    module's place in the window as the label; such a pair is dropped when
+    the layer is not listed for the module, the helix misses the envelope,
+    or the module is outside the window."""
     layer = np.asarray(geom["layer"])
     xs, labels, trk, posn, dropped = [], [], [], [], 0
     for t in range(len(offsets) - 1):
         for i in range(offsets[t], offsets[t + 1] - 1):
-            m, m2 = int(meas_surface[i]), int(meas_surface[i + 1])
-            if layer[m2] == layer[m]:
+            m = int(meas_surface[i])
+            L2 = int(layer[meas_surface[i + 1]])
+            if L2 == layer[m]:
                 continue
-            L2 = int(layer[m2])
+            j_end = i + 1
+            while j_end < offsets[t + 1] and layer[meas_surface[j_end]] == L2:
+                j_end += 1
             slots = np.nonzero(nxt[m] == L2)[0]
             cr = state_crossing(geom, m, meas_params[i], L2, bfield) if len(slots) else None
-            if cr is None:
-                dropped += 1
-                continue
-            s = slots[0]
-            lab = window_label(geom, L2, cr[0], anc[m, s], reg[m, s], m2)
-            if lab < 0:
-                dropped += 1
-                continue
-            xs.append(features_at(geom, L2, cr[0], cr[1], float(meas_params[i][4]), anc[m, s]))
-            labels.append(lab)
-            trk.append(t)
-            posn.append(i)
+            for j in range(i + 1, j_end):
+                m2 = int(meas_surface[j])
+                lab = -1
+                if cr is not None:
+                    s = slots[0]
+                    lab = window_label(geom, L2, cr[0], anc[m, s], reg[m, s], m2)
+                if lab < 0:
+                    dropped += 1
+                    continue
+                xs.append(features_at(geom, L2, cr[0], cr[1], float(meas_params[i][4]), anc[m, s]))
+                labels.append(lab)
+                trk.append(t)
+                posn.append(i)
     x = np.array(xs).reshape(-1, N_IN)
     return x, np.array(labels, np.int32), np.array(trk, np.int32), np.array(posn, np.int64), dropped
 

@@ -418,7 +418,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             go = false;
           } else {
             mask |= 1ull << nl;
-            helix_at(H, sL, Pl, Tl);
+            helix_at_nav(H, sL, Pl, Tl);
             need_list = true;
             lay = nl;
             excl = -1;
@@ -453,29 +453,33 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           }
           __syncthreads();
           const int q4 = 4 * (lane >> 4);
-          // all four 16-row blocks together: each weight tile is read once
-          bf16x4 xb[4];
-#pragma unroll
-          for (int rb = 0; rb < 4; ++rb) {
-            const int src = (16 * rb + (lane & 15)) * 8 + q4;
-            xb[rb].x = q4 < 8 ? (short)sh_x[src + 0] : (short)0;
-            xb[rb].y = q4 < 8 ? (short)sh_x[src + 1] : (short)0;
-            xb[rb].z = q4 < 8 ? (short)sh_x[src + 2] : (short)0;
-            xb[rb].w = q4 < 8 ? (short)sh_x[src + 3] : (short)0;
-          }
-          f32x4 out[4][2];
-          mlp_wave(A.model, xb, lane, out);
-          if (kCount && lane == 0) CNT_ADD(CKF_CNT_MLP_BLOCKS, 4);
+          // two 16-row blocks at a time: each weight tile is read once per pair
           Top3 mine;
           float conf = 0.f;
+#pragma unroll 1
+          for (int rb0 = 0; rb0 < 4; rb0 += 2) {
+            if (((wm >> (16 * rb0)) & 0xffffffffull) == 0) continue;
+            bf16x4 xb[2];
 #pragma unroll
-          for (int rb = 0; rb < 4; ++rb) {
-            Top3 t;
-            float c;
-            mlp_top3(out[rb], lane, cfg.topk, t, c);
-            if ((lane >> 4) == rb) {
-              mine = t;
-              conf = c;
+            for (int h = 0; h < 2; ++h) {
+              const int src = (16 * (rb0 + h) + (lane & 15)) * 8 + q4;
+              xb[h].x = q4 < 8 ? (short)sh_x[src + 0] : (short)0;
+              xb[h].y = q4 < 8 ? (short)sh_x[src + 1] : (short)0;
+              xb[h].z = q4 < 8 ? (short)sh_x[src + 2] : (short)0;
+              xb[h].w = q4 < 8 ? (short)sh_x[src + 3] : (short)0;
+            }
+            f32x4 out[2][2];
+            mlp_blocks<2>(A.model, xb, lane, out);
+            if (kCount && lane == 0) CNT_ADD(CKF_CNT_MLP_BLOCKS, 2);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              Top3 t;
+              float c;
+              mlp_top3(out[h], lane, cfg.topk, t, c);
+              if ((lane >> 4) == rb0 + h) {
+                mine = t;
+                conf = c;
+              }
             }
           }
           __syncthreads();

@@ -72,13 +72,14 @@ __global__ void __launch_bounds__(64) k_mlp_forward(ModelDev M, const float* __r
 #pragma unroll 1
   for (int rb = 0; rb < 4; ++rb) {
     const long long row = r0 + 16 * rb + i;
-    f32x4 out[2];
-    mlp_block(M, input_frag(x, row, n, lane), lane, out);
+    f32x4 out[1][2];
+    const bf16x4 xb[1] = {input_frag(x, row, n, lane)};
+    mlp_blocks<1>(M, xb, lane, out);
     if (row < n) {
 #pragma unroll
       for (int ob = 0; ob < 2; ++ob)
         *reinterpret_cast<float4*>(logits + row * 32 + 16 * ob + q4) =
-            make_float4(out[ob].x, out[ob].y, out[ob].z, out[ob].w);
+            make_float4(out[0][ob].x, out[0][ob].y, out[0][ob].z, out[0][ob].w);
     }
   }
 }
@@ -330,18 +331,18 @@ __global__ void __launch_bounds__(kCapThreads) k_capture_pairs(GeomDev g, FieldD
       int k = 0;
       if (t < n_t) {
         for (int i = off[t]; i < off[t + 1] - 1; ++i) {
-          const int m = msurf[i], m2 = msurf[i + 1];
-          if (m < 0 || m >= g.n_surfaces || m2 < 0 || m2 >= g.n_surfaces) {
+          const int m = msurf[i], m1 = msurf[i + 1];
+          if (m < 0 || m >= g.n_surfaces || m1 < 0 || m1 >= g.n_surfaces) {
             if (pass == 0) ++drop;
             continue;
           }
-          const int L = g.mod[m].layer, L2 = g.mod[m2].layer;
+          const int L = g.mod[m].layer, L2 = g.mod[m1].layer;
           if (L == L2) continue;
           int slot = -1;
           for (int s = 0; s < kMaxNext; ++s)
             if (slot < 0 && g.nb_next[m * kMaxNext + s] == L2) slot = s;
           // the local helix from the state on m to L2's envelope, as the navigation finds it
-          int lab = -1;
+          bool have = false;
           V3 X = {0.f, 0.f, 0.f}, Tx = {0.f, 0.f, 0.f};
           Window w{0, 0, 0.f, 0.f};
           const LayerRec Lr = g.layers[L2];
@@ -359,33 +360,40 @@ __global__ void __launch_bounds__(kCapThreads) k_capture_pairs(GeomDev g, FieldD
             float sc;
             const bool hit = Lr.type == 0 ? cross_cylinder(H, Lr.pos, sc) : cross_zplane(H, Lr.pos, sc);
             if (hit) {
-              helix_at(H, sc, X, Tx);
-              if (crossing_window(Lr, g.nb_anc[row], X, w)) {
-                const int* reg = g.nb_reg + (long long)row * kRegCells;
-                for (int q = 0; q < kRegCells; ++q)
-                  if (lab < 0 && reg[q] == m2) {
-                    const int wu = (q % kRegU + kRegU0) - w.iu - kWinU0, wv = (q / kRegU + kRegV0) - w.iv - kWinV0;
-                    lab = (wu >= 0 && wu < kWinU && wv >= 0 && wv < kWinV) ? wv * kWinU + wu : -2;
-                  }
-              }
+              helix_at_nav(H, sc, X, Tx);
+              have = crossing_window(Lr, g.nb_anc[row], X, w);
             }
           }
-          if (lab < 0) {
-            if (pass == 0) ++drop;
-            continue;
+          // one pair per measurement of the track on L2 (overlaps give several)
+          for (int j = i + 1; j < off[t + 1]; ++j) {
+            const int m2 = msurf[j];
+            if (m2 < 0 || m2 >= g.n_surfaces || g.mod[m2].layer != L2) break;
+            int lab = -1;
+            if (have) {
+              const int* reg = g.nb_reg + (long long)row * kRegCells;
+              for (int q = 0; q < kRegCells; ++q)
+                if (lab < 0 && reg[q] == m2) {
+                  const int wu = (q % kRegU + kRegU0) - w.iu - kWinU0, wv = (q / kRegU + kRegV0) - w.iv - kWinV0;
+                  lab = (wu >= 0 && wu < kWinU && wv >= 0 && wv < kWinV) ? wv * kWinU + wu : -2;
+                }
+            }
+            if (lab < 0) {
+              if (pass == 0) ++drop;
+              continue;
+            }
+            if (pass == 0) {
+              ++cnt;
+              continue;
+            }
+            const long long o = base + pos + k;
+            ++k;
+            if (o >= cap_pairs) continue;
+            float f[7];
+            mlp_features(Lr, L2, g.n_layers, w, X, Tx, (float)mpar[5ll * i + 4], f);
+            for (int c = 0; c < 7; ++c) x[o * 7 + c] = f[c];
+            label[o] = lab;
+            if (track) track[o] = t;
           }
-          if (pass == 0) {
-            ++cnt;
-            continue;
-          }
-          const long long o = base + pos + k;
-          ++k;
-          if (o >= cap_pairs) continue;
-          float f[7];
-          mlp_features(Lr, L2, g.n_layers, w, X, Tx, (float)mpar[5ll * i + 4], f);
-          for (int c = 0; c < 7; ++c) x[o * 7 + c] = f[c];
-          label[o] = lab;
-          if (track) track[o] = t;
         }
       }
       if (pass == 1) base += total;

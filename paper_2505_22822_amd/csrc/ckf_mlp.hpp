@@ -64,74 +64,46 @@ __device__ __forceinline__ f32x4 ld_f4(const float* p) {
   return r;
 }
 
-// Logits of one 16-row block.  xb: this lane's B operand of the input
-// (features 4*(l/16)..+3 of row l%16, zero beyond the 7 inputs).  Must be
-// called by all 64 lanes together.  out[ob] holds classes 16*ob + 4*(l/16)
-// + j of row l%16.
-__device__ __forceinline__ void mlp_block(const ModelDev& M, bf16x4 xb, int lane, f32x4 out[2]) {
+// Logits of NB 16-row blocks at once: every weight tile is fetched once and
+// applied to the NB blocks, which gives NB independent MFMA chains.
+// xb[rb]: this lane's B operand of the input of rows 16*rb + l%16 of those
+// blocks.  Must be called by all 64 lanes together.
+template <int NB>
+__device__ __forceinline__ void mlp_blocks(const ModelDev& M, const bf16x4 xb[NB], int lane, f32x4 out[NB][2]) {
   const int q4 = 4 * (lane >> 4);
-  bf16x4 h1[4], h2[4];
-#pragma unroll
-  for (int ob = 0; ob < 4; ++ob) {
-    f32x4 acc = ld_f4(M.b1 + 16 * ob + q4);
-    acc = mfma16(as_bf16x4(M.w1[ob * 64 + lane]), xb, acc);
-    h1[ob] = relu_bf16(acc);
-  }
-#pragma unroll
-  for (int ob = 0; ob < 4; ++ob) {
-    f32x4 acc = ld_f4(M.b2 + 16 * ob + q4);
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) acc = mfma16(as_bf16x4(M.w2[(ob * 4 + kb) * 64 + lane]), h1[kb], acc);
-    h2[ob] = relu_bf16(acc);
-  }
-#pragma unroll
-  for (int ob = 0; ob < 2; ++ob) {
-    f32x4 acc = ld_f4(M.b3 + 16 * ob + q4);
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) acc = mfma16(as_bf16x4(M.w3[(ob * 4 + kb) * 64 + lane]), h2[kb], acc);
-    out[ob] = acc;
-  }
-}
-
-// Logits of all four 16-row blocks of a wave at once: every weight tile is
-// fetched once and applied to the four blocks, which gives four independent
-// MFMA chains.  xb[rb]: this lane's B operand of the input of rows
-// 16*rb + l%16.  Must be called by all 64 lanes together.
-__device__ __forceinline__ void mlp_wave(const ModelDev& M, const bf16x4 xb[4], int lane, f32x4 out[4][2]) {
-  const int q4 = 4 * (lane >> 4);
-  bf16x4 h1[4][4], h2[4][4];
+  bf16x4 h1[NB][4], h2[NB][4];
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
     const f32x4 b = ld_f4(M.b1 + 16 * ob + q4);
     const bf16x4 w = as_bf16x4(M.w1[ob * 64 + lane]);
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) h1[rb][ob] = relu_bf16(mfma16(w, xb[rb], b));
+    for (int rb = 0; rb < NB; ++rb) h1[rb][ob] = relu_bf16(mfma16(w, xb[rb], b));
   }
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
-    f32x4 acc[4];
+    f32x4 acc[NB];
     const f32x4 b = ld_f4(M.b2 + 16 * ob + q4);
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) acc[rb] = b;
+    for (int rb = 0; rb < NB; ++rb) acc[rb] = b;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
       const bf16x4 w = as_bf16x4(M.w2[(ob * 4 + kb) * 64 + lane]);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma16(w, h1[rb][kb], acc[rb]);
+      for (int rb = 0; rb < NB; ++rb) acc[rb] = mfma16(w, h1[rb][kb], acc[rb]);
     }
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) h2[rb][ob] = relu_bf16(acc[rb]);
+    for (int rb = 0; rb < NB; ++rb) h2[rb][ob] = relu_bf16(acc[rb]);
   }
 #pragma unroll
   for (int ob = 0; ob < 2; ++ob) {
     const f32x4 b = ld_f4(M.b3 + 16 * ob + q4);
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) out[rb][ob] = b;
+    for (int rb = 0; rb < NB; ++rb) out[rb][ob] = b;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
       const bf16x4 w = as_bf16x4(M.w3[(ob * 4 + kb) * 64 + lane]);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) out[rb][ob] = mfma16(w, h2[rb][kb], out[rb][ob]);
+      for (int rb = 0; rb < NB; ++rb) out[rb][ob] = mfma16(w, h2[rb][kb], out[rb][ob]);
     }
   }
 }
