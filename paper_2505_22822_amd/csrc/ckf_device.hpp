@@ -27,6 +27,32 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 __device__ __forceinline__ float maxabs(V3 a) { return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z))); }
 __device__ __forceinline__ V3 ld3(const float* p) { return {p[0], p[1], p[2]}; }
 
+// a / b through the hardware reciprocal (about 1 ulp, instead of the
+// correctly rounded division sequence) for FP32 geometry and step control
+__device__ __forceinline__ float fdiv_fast(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// atan2 from the arctangent polynomial of Abramowitz and Stegun 4.4.49
+// (|error| <= 2e-8 rad on [-1, 1]) after reducing to |x| <= 1 by octant;
+// about 20 instructions against several times that for the library call.
+__device__ __forceinline__ float atan2_as(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float t = mx > 0.f ? fdiv_fast(mn, mx) : 0.f;
+  const float t2 = t * t;
+  float p = 0.0028662257f;
+  p = fmaf(p, t2, -0.0161657367f);
+  p = fmaf(p, t2, 0.0429096138f);
+  p = fmaf(p, t2, -0.0752896400f);
+  p = fmaf(p, t2, 0.1065626393f);
+  p = fmaf(p, t2, -0.1420889944f);
+  p = fmaf(p, t2, 0.1999355085f);
+  p = fmaf(p, t2, -0.3333314528f);
+  float a = fmaf(p * t2, t, t);
+  if (ay > ax) a = 1.57079632679f - a;
+  if (x < 0.f) a = 3.14159265359f - a;
+  return copysignf(a, y);
+}
+
 // Bilinear cell of the (r, z) map at p: the two rows and the fractions;
 // cr / cz tell that the coordinate was clamped (no gradient along it).
 struct MapCell {
@@ -212,12 +238,12 @@ __device__ __forceinline__ void rkn4_advance(LegT<NC>& L, float h, V3 origin, co
 __device__ __forceinline__ float plane_distance(V3 r, V3 T, V3 k, V3 c, V3 n) {
   const float a = 0.5f * dot(n, k), b = dot(n, T), c0 = dot(n, r - c);
   if (fabsf(b) < 1e-9f) return __int_as_float(0x7fc00000);
-  const float lin = -c0 / b;
+  const float lin = fdiv_fast(-c0, b);
   const float disc = b * b - 4.0f * a * c0;
   if (disc < 0.0f) return lin;
   const float q = -0.5f * (b + copysignf(sqrtf(disc), b));
   if (q == 0.0f) return lin;
-  return c0 / q;
+  return fdiv_fast(c0, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,7 +259,7 @@ __device__ __forceinline__ Helix make_helix(V3 p, V3 T, float lam, V3 B) {
   const float bm = sqrtf(dot(B, B));
   H.bhat = bm > 0.f ? (1.0f / bm) * B : V3{0.f, 0.f, 1.f};
   H.om = kKappa * lam * bm;
-  H.inv_om = H.om != 0.f ? 1.0f / H.om : 0.f;
+  H.inv_om = H.om != 0.f ? __builtin_amdgcn_rcpf(H.om) : 0.f;
   H.p0 = p;
   H.T0 = T;
   H.tpar = dot(T, H.bhat);
@@ -292,7 +318,7 @@ __device__ __forceinline__ float helix_distance(V3 r, V3 T, float lam, V3 B, V3 
     helix_at(H, s, p, Ts);
     const float fp = dot(n, Ts);
     if (fabsf(fp) < 1e-9f) return __int_as_float(0x7fc00000);
-    s -= dot(n, p - c) / fp;
+    s -= fdiv_fast(dot(n, p - c), fp);
   }
   return s;
 }
@@ -322,12 +348,12 @@ __device__ bool land(LegT<NC>& L, V3 origin, V3 c, V3 n, const FieldDev& F, cons
     ++st.trials;
     if (!(err <= cfg.step_tol)) {
       ++st.rejects;
-      h_trial = fabsf(h) * fmaxf(0.25f, 0.9f * sqrtf(sqrtf(cfg.step_tol / err)));
+      h_trial = fabsf(h) * fmaxf(0.25f, 0.9f * sqrtf(sqrtf(fdiv_fast(cfg.step_tol, err))));
       continue;
     }
     rkn4_advance<kMap>(L, h, origin, F, B, S);
     path += fabsf(h);
-    const float grow = err > 0.0f ? fminf(4.0f, 0.9f * sqrtf(sqrtf(cfg.step_tol / err))) : 4.0f;
+    const float grow = err > 0.0f ? fminf(4.0f, 0.9f * sqrtf(sqrtf(fdiv_fast(cfg.step_tol, err)))) : 4.0f;
     h_trial = limited ? fminf(cfg.step_max, fmaxf(h_trial, fabsf(h) * grow)) : fminf(cfg.step_max, fabsf(h) * grow);
   }
   return false;
@@ -368,12 +394,12 @@ __device__ __forceinline__ void leg_end(const LegT<NC>& L, V3 uA, V3 vA, const M
   const float st = sqrtf(st2);
   p[0] = (double)dot(uB, d);
   p[1] = (double)dot(vB, d);
-  p[2] = (double)atan2f(T.y, T.x);
-  p[3] = (double)atan2f(st, T.z);
+  p[2] = (double)atan2_as(T.y, T.x);
+  p[3] = (double)atan2_as(st, T.z);
   p[4] = qop;  // no energy loss: q/p keeps its FP64 value
   const V3 kend = (kKappa * L.lam) * cross(T, Bf);
-  const float inT = 1.0f / dot(nB, T);
-  const float ist2 = 1.0f / st2, ist = 1.0f / st;
+  const float inT = fdiv_fast(1.0f, dot(nB, T));
+  const float ist2 = fdiv_fast(1.0f, st2), ist = fdiv_fast(1.0f, st);
   V3 dr[5], dT[5];
   if (NC == 3) {
     dr[0] = uA;
@@ -515,11 +541,11 @@ __device__ __forceinline__ void apply_ms(const Module& M, double mass, const dou
   sincosf((float)p[2], &sp, &cp);
   sincosf((float)p[3], &st, &ct);
   const float cosa = fabsf(M.n[0] * cp * st + M.n[1] * sp * st + M.n[2] * ct);
-  const float x = M.thick / cosa;
-  const float mom = 1.0f / fabsf((float)p[4]);
+  const float x = fdiv_fast(M.thick, cosa);
+  const float mom = __builtin_amdgcn_rcpf(fabsf((float)p[4]));
   const float m = (float)mass;
-  const float beta = mom / sqrtf(mom * mom + m * m);
-  const float th0 = 0.0136f / (beta * mom) * sqrtf(x) * (1.0f + 0.038f * logf(x / (beta * beta)));
+  const float beta = mom * __builtin_amdgcn_rsqf(mom * mom + m * m);
+  const float th0 = fdiv_fast(0.0136f, beta * mom) * sqrtf(x) * (1.0f + 0.038f * logf(fdiv_fast(x, beta * beta)));
   const double t2 = (double)th0 * (double)th0;
   C[pk(2, 2)] += t2 / ((double)st * (double)st);
   C[pk(3, 3)] += t2;
@@ -532,7 +558,7 @@ __device__ bool cross_cylinder(const Helix& H, float R, float& s_out) {
   if (a < 1e-12f) return false;
   const float disc = b * b - a * c;
   if (disc < 0.f) return false;
-  float s = (-b + sqrtf(disc)) / a;
+  float s = fdiv_fast(-b + sqrtf(disc), a);
   if (!(s > 0.f)) return false;
   for (int it = 0; it < 20; ++it) {
     V3 p, T;
@@ -540,7 +566,7 @@ __device__ bool cross_cylinder(const Helix& H, float R, float& s_out) {
     const float g = p.x * p.x + p.y * p.y - R * R;
     const float gp = 2.0f * (p.x * T.x + p.y * T.y);
     if (!(gp > 0.f)) return false;
-    const float ds = __fdividef(g, gp);
+    const float ds = fdiv_fast(g, gp);
     s -= ds;
     if (fabsf(ds) < 1e-4f) break;
   }
@@ -554,13 +580,13 @@ __device__ bool cross_cylinder(const Helix& H, float R, float& s_out) {
 
 __device__ bool cross_zplane(const Helix& H, float Z, float& s_out) {
   if (fabsf(H.T0.z) < 1e-12f) return false;
-  float s = (Z - H.p0.z) / H.T0.z;
+  float s = fdiv_fast(Z - H.p0.z, H.T0.z);
   if (!(s > 0.f)) return false;
   for (int it = 0; it < 20; ++it) {
     V3 p, T;
     helix_at_nav(H, s, p, T);
     if (fabsf(T.z) < 1e-12f) return false;
-    const float ds = __fdividef(p.z - Z, T.z);
+    const float ds = fdiv_fast(p.z - Z, T.z);
     s -= ds;
     if (fabsf(ds) < 1e-4f) break;
   }
@@ -591,15 +617,16 @@ __device__ __forceinline__ void list_test(ListAcc& a, int m, const Module& M, V3
   const V3 c = ld3(M.c), nn = ld3(M.n);
   const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
   const V3 dc = c - P;
-  if (sqrtf(dot(dc, dc)) > hd + kReach) return;
+  const float reach = hd + kReach;
+  if (dot(dc, dc) > reach * reach) return;
   ++n_tested;
   const float qa = 0.5f * dot(nn, k), qb = dot(nn, T), c0 = dot(nn, P - c);
   if (fabsf(qb) < 1e-3f) return;
-  float d = -c0 / qb;
+  float d = fdiv_fast(-c0, qb);
   const float disc = qb * qb - 4.0f * qa * c0;
   if (disc >= 0.f) {
     const float qq = -0.5f * (qb + copysignf(sqrtf(disc), qb));
-    if (qq != 0.f) d = c0 / qq;
+    if (qq != 0.f) d = fdiv_fast(c0, qq);
   }
   const V3 X = P + d * T + (0.5f * d * d) * k - c;
   const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
@@ -642,15 +669,15 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
   float span;
   if (Lr.type == 0) {
     const float rp = sqrtf(P.x * P.x + P.y * P.y);
-    const float vr = rp > 0.f ? (P.x * T.x + P.y * T.y) / rp : 1.0f;
-    span = Lr.depth / fmaxf(vr, 0.05f) * 1.2f + 2.0f;
+    const float vr = rp > 0.f ? fdiv_fast(P.x * T.x + P.y * T.y, rp) : 1.0f;
+    span = fdiv_fast(Lr.depth, fmaxf(vr, 0.05f)) * 1.2f + 2.0f;
   } else {
-    span = Lr.depth / fmaxf(fabsf(T.z), 0.05f) * 1.2f + 2.0f;
+    span = fdiv_fast(Lr.depth, fmaxf(fabsf(T.z), 0.05f)) * 1.2f + 2.0f;
   }
   span = fminf(span, 400.0f);
   const V3 Q = P + span * T;
   const float twopi = 6.28318530718f;
-  float ph0 = atan2f(P.y, P.x), ph1 = atan2f(Q.y, Q.x);
+  float ph0 = atan2_as(P.y, P.x), ph1 = atan2_as(Q.y, Q.x);
   float w0 = Lr.type == 0 ? P.z : sqrtf(P.x * P.x + P.y * P.y);
   float w1 = Lr.type == 0 ? Q.z : sqrtf(Q.x * Q.x + Q.y * Q.y);
   float dph = ph1 - ph0;
@@ -659,10 +686,12 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
   const float phlo = fminf(ph0, ph0 + dph), phhi = fmaxf(ph0, ph0 + dph);
   const float wlo = fminf(w0, w1), whi = fmaxf(w0, w1);
   if (!(isfinite(phlo) && isfinite(phhi) && isfinite(wlo) && isfinite(whi))) return 0;
-  const float bph = twopi / Lr.nphi, bw = (Lr.whi - Lr.wlo) / Lr.nw;
-  int ip0 = (int)floorf((phlo + 3.14159265f) / bph) - 0;
-  int ip1 = (int)floorf((phhi + 3.14159265f) / bph);
-  int iw0 = (int)floorf((wlo - Lr.wlo) / bw), iw1 = (int)floorf((whi - Lr.wlo) / bw);
+  // bins per radian and per unit of w (the grid extents are padded, so
+  // rounding of the bin edges cannot lose a module)
+  const float iph = (float)Lr.nphi * (1.0f / twopi), iw = fdiv_fast((float)Lr.nw, Lr.whi - Lr.wlo);
+  int ip0 = (int)floorf((phlo + 3.14159265f) * iph);
+  int ip1 = (int)floorf((phhi + 3.14159265f) * iph);
+  int iw0 = (int)floorf((wlo - Lr.wlo) * iw), iw1 = (int)floorf((whi - Lr.wlo) * iw);
   iw0 = max(iw0, 0);
   iw1 = min(iw1, Lr.nw - 1);
   if (ip1 - ip0 >= Lr.nphi) { ip0 = 0; ip1 = Lr.nphi - 1; }

@@ -120,12 +120,12 @@ struct Window {
 
 __device__ __forceinline__ bool crossing_window(const LayerRec& Lr, float4 anc, V3 X, Window& w) {
   const float r = sqrtf(X.x * X.x + X.y * X.y);
-  float dphi = atan2f(X.y, X.x) - anc.x;
+  float dphi = atan2_as(X.y, X.x) - anc.x;
   if (dphi >= 3.14159265f) dphi -= 6.28318531f;
   if (dphi < -3.14159265f) dphi += 6.28318531f;
   const float du = Lr.type == 0 ? dphi * Lr.pos : dphi * r;
   const float dv = Lr.type == 0 ? X.z - anc.y : r - anc.y;
-  const float qu = du / anc.z, qv = dv / anc.w;
+  const float qu = fdiv_fast(du, anc.z), qv = fdiv_fast(dv, anc.w);
   if (!(fabsf(qu) < 1000.f && fabsf(qv) < 1000.f)) return false;
   const float cu = floorf(qu + 0.5f), cv = floorf(qv + 0.5f);
   w.iu = (int)cu;
