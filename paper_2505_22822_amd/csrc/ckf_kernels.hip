@@ -232,6 +232,12 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   __shared__ LayerRec sh_layers[kMaxLayers];
   __shared__ int sh_order[3][kMaxLayers];
   __shared__ unsigned short sh_x[kLearned ? kWave * 8 : 1];  // network inputs (bf16), one row per lane
+  // phase 4 work list: per output slot of a pass its parent lane and branch;
+  // per parent lane its child count, node offset and accepted measurements
+  __shared__ int sh_item[kWave * kMaxBranch];
+  __shared__ int sh_kind[kWave], sh_noff[kWave];
+  __shared__ int sh_acc_pos[kMaxBranch][kWave], sh_acc_id[kMaxBranch][kWave];
+  __shared__ double sh_acc_x2[kMaxBranch][kWave];
 
   const CfgDev& cfg = A.cfg;
   const int lane = lane_id();
@@ -700,69 +706,79 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         sh_node_base = tot_nodes > 0 ? atomicAdd(A.w.node_count, (unsigned long long)tot_nodes) : 0ull;
       }
       __syncthreads();
-      const long long node0 = (long long)sh_node_base + noff;
 
-      // ---- phase 4: outputs
-      if (outcome == 1) {  // the record moves on unchanged
+      // ---- phase 4: outputs, one output record per lane and round: the
+      // parents' accepted measurements go through LDS, so a parent with
+      // three children costs three lanes instead of three rounds of the wave
+      sh_kind[lane] = act ? n_kf : 0;
+      sh_noff[lane] = noff;
 #pragma unroll
-        for (int k = 0; k < PD_N; ++k) PDr(Pout, pos0, k) = PDr(Pin, r, k);
+      for (int j = 0; j < kMaxBranch; ++j) {
+        sh_acc_pos[j][lane] = acc_pos[j];
+        sh_acc_id[j][lane] = acc_id[j];
+        sh_acc_x2[j][lane] = acc_x2[j];
+      }
+      for (int j = 0; j < n_out; ++j) sh_item[off + j] = lane | (j << 8);
+      __syncthreads();
+      const int out_base = pos0 - off;  // this pass's first output slot (uniform)
+      for (int c = lane; c < tot_out; c += kWave) {
+        const int it = sh_item[c];
+        const int src = it & 0xff, j = it >> 8;
+        const int rs = b0 + src, q = out_base + c;
+        const int nkf = sh_kind[src];
+        const int pslot = PIr(Pin, rs, PI_SLOT);
+        if (nkf == 0) {  // the record moves on unchanged
 #pragma unroll
-        for (int k = 0; k < PI_N; ++k) PIr(Pout, pos0, k) = PIr(Pin, r, k);
+          for (int k = 0; k < PD_N; ++k) PDr(Pout, q, k) = PDr(Pin, rs, k);
 #pragma unroll
-        for (int k = 0; k < PF_N; ++k) PFr(Pout, pos0, k) = PFr(Pin, r, k);
-        atomicAdd(&sh_live[slot], 1);
-      } else if (n_kf > 0) {  // one Kalman-updated child per accepted measurement
-        const bool room = node0 + n_kf <= A.w.node_cap;
-        if (!room) atomicOr(A.status + CKF_STATUS_FLAGS, CKF_FLAG_NODE_CAPACITY);
-        double p[5], C[15];
+          for (int k = 0; k < PI_N; ++k) PIr(Pout, q, k) = PIr(Pin, rs, k);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
-        load_cov(Pin, r, C);
-        const int surf = PIr(Pin, r, PI_SURF);
-        const int parent = PIr(Pin, r, PI_NODE);
-        const int nmh = PIr(Pin, r, PI_NMH);
-        const double chi2 = PDr(Pin, r, PD_CHI2);
-        Module M;
-        if (cfg.material) load_module(g, surf, M);
+          for (int k = 0; k < PF_N; ++k) PFr(Pout, q, k) = PFr(Pin, rs, k);
+        } else {  // the Kalman-updated child for the parent's j-th accepted measurement
+          const long long nd = (long long)sh_node_base + sh_noff[src];
+          const bool room = nd + nkf <= A.w.node_cap;
+          if (!room && j == 0) atomicOr(A.status + CKF_STATUS_FLAGS, CKF_FLAG_NODE_CAPACITY);
+          double p[5], C[15];
 #pragma unroll
-        for (int j = 0; j < kMaxBranch; ++j) {
-          if (j < n_kf) {
-            const int i = acc_pos[j];
-            double pc[5], Cc[15];
-            const float4 ms = A.w.m_sorted[i];
-            kf_update(p, C, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w, pc, Cc);
-            CNT_ADD(CKF_CNT_KF, 1);
-            const int q = pos0 + j;
-            if (room) {
-              Node* np = A.w.nodes + node0 + j;
-              np->parent = parent;
-              np->meas = acc_id[j];
-              np->surface = surf;
-              np->pad = 0;
+          for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, rs, (PD_P + k));
+          load_cov(Pin, rs, C);
+          const int surf = PIr(Pin, rs, PI_SURF);
+          const int i = sh_acc_pos[j][src];
+          double pc[5], Cc[15];
+          const float4 ms = A.w.m_sorted[i];
+          kf_update(p, C, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w, pc, Cc);
+          CNT_ADD(CKF_CNT_KF, 1);
+          if (room) {
+            Node* np = A.w.nodes + nd + j;
+            np->parent = PIr(Pin, rs, PI_NODE);
+            np->meas = sh_acc_id[j][src];
+            np->surface = surf;
+            np->pad = 0;
 #pragma unroll
-              for (int k = 0; k < 5; ++k) np->p[k] = pc[k];
+            for (int k = 0; k < 5; ++k) np->p[k] = pc[k];
 #pragma unroll
-              for (int k = 0; k < 15; ++k) np->cov[k] = Cc[k];
-            }
-            if (cfg.material) {
-              apply_ms(M, cfg.mass, pc, Cc);
-              CNT_ADD(CKF_CNT_MS, 1);
-            }
-#pragma unroll
-            for (int k = 0; k < 5; ++k) PDr(Pout, q, (PD_P + k)) = pc[k];
-#pragma unroll
-            for (int k = 0; k < 15; ++k) PDr(Pout, q, (PD_C + k)) = Cc[k];
-            PDr(Pout, q, PD_CHI2) = chi2 + acc_x2[j];
-            PIr(Pout, q, PI_NODE) = room ? (int)(node0 + j) : -1;
-            PIr(Pout, q, PI_NMH) = nmh + 1;
-#pragma unroll
-            for (int k = 0; k < PI_N; ++k)
-              if (k != PI_NODE && k != PI_NMH) PIr(Pout, q, k) = PIr(Pin, r, k);
-#pragma unroll
-            for (int k = 0; k < PF_N; ++k) PFr(Pout, q, k) = PFr(Pin, r, k);
-            atomicAdd(&sh_live[slot], 1);
+            for (int k = 0; k < 15; ++k) np->cov[k] = Cc[k];
           }
+          if (cfg.material) {
+            Module M;
+            load_module(g, surf, M);
+            apply_ms(M, cfg.mass, pc, Cc);
+            CNT_ADD(CKF_CNT_MS, 1);
+          }
+#pragma unroll
+          for (int k = 0; k < 5; ++k) PDr(Pout, q, (PD_P + k)) = pc[k];
+#pragma unroll
+          for (int k = 0; k < 15; ++k) PDr(Pout, q, (PD_C + k)) = Cc[k];
+          PDr(Pout, q, PD_CHI2) = PDr(Pin, rs, PD_CHI2) + sh_acc_x2[j][src];
+          PIr(Pout, q, PI_NODE) = room ? (int)(nd + j) : -1;
+          PIr(Pout, q, PI_NMH) = PIr(Pin, rs, PI_NMH) + 1;
+#pragma unroll
+          for (int k = 0; k < PI_N; ++k)
+            if (k != PI_NODE && k != PI_NMH) PIr(Pout, q, k) = PIr(Pin, rs, k);
+#pragma unroll
+          for (int k = 0; k < PF_N; ++k) PFr(Pout, q, k) = PFr(Pin, rs, k);
         }
+        atomicAdd(&sh_live[pslot], 1);
       }
       // ---- finished candidates update their seed's best (one lane at a time)
       unsigned long long fm = __ballot(outcome == 3);
