@@ -244,9 +244,9 @@ def main():
     def pick(model=None):
         if fixed:
             return dict(grid=args.grid, seeds_per_group=args.seeds_per_group, waves_per_simd=args.waves)
-        waves = (2,) if model is None else (2, 1)
-        shapes = [dict(grid=n_cu * g, seeds_per_group=s, waves_per_simd=w)
-                  for w in waves for g in (8, 16) for s in (24, 32, 48)]
+        waves = (3, 2) if model is None else (3, 2, 1)
+        shapes = [dict(grid=n_cu * 4 * w * g, seeds_per_group=s, waves_per_simd=w)
+                  for w in waves for g in (1, 2) for s in (32, 48)]
         shape, _ = autotune.tune(geo, fld, b, ckf.config(), shapes=shapes, reps=2, verbose=True,
                                  use_cache=not args.retune and model is None, model=model)
         return shape

@@ -229,7 +229,8 @@ typedef struct ckf_launch {
   int32_t seeds_per_group;   /* concurrent seeds per 64-lane workgroup (1..64); 0 = default */
   int32_t nodes_per_seed;    /* history capacity per seed in the workspace; 0 = default (32) */
   ckf_timer* timer;          /* NULL, or events recorded around the track-finding kernel */
-  int32_t waves_per_simd;    /* register budget of the kernel variant: 1 or 2 waves per SIMD (0 = 2) */
+  int32_t waves_per_simd;    /* register budget of the kernel variant: 1, 2 or 3 waves per SIMD (0 = 3;
+                                a field map uses at most 2) */
 } ckf_launch;
 
 /* Geometry: validates, builds the navigation grid on the host, uploads. */

@@ -30,9 +30,9 @@ def _key(batch, cfg, device_name, learned):
 
 
 def candidates(n_cus: int):
-    for waves in (2, 1):
+    for waves in (3, 2, 1):
         for spg in (16, 24, 32, 48, 64):
-            for per_cu in (4, 8, 16):
+            for per_cu in (4 * waves, 8 * waves):
                 yield dict(grid=n_cus * per_cu, seeds_per_group=spg, waves_per_simd=waves)
 
 

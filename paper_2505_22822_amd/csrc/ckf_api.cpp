@@ -372,19 +372,19 @@ int device_cus() {
   return cus;
 }
 
-constexpr int kDefaultSeedsPerGroup = 32;
-constexpr int kDefaultGroupsPerCU = 8;
+constexpr int kDefaultSeedsPerGroup = 48;
 constexpr int kNodesPerSeed = 32;
 
 ckf::Launch resolve_launch(const ckf_config* c, const ckf_launch* l, int n_seeds) {
   ckf::Launch r;
+  r.waves_per_simd = (l && l->waves_per_simd > 0) ? std::min(3, l->waves_per_simd) : 3;
   r.seeds_per_group = (l && l->seeds_per_group > 0) ? std::min(64, l->seeds_per_group) : kDefaultSeedsPerGroup;
   const int want = (n_seeds + r.seeds_per_group - 1) / r.seeds_per_group;
-  const int dflt = device_cus() * kDefaultGroupsPerCU;
+  // one workgroup per wave slot: 4 SIMDs per CU times the waves per SIMD
+  const int dflt = device_cus() * 4 * r.waves_per_simd;
   r.grid = std::max(1, std::min((l && l->grid > 0) ? l->grid : dflt, std::max(1, want)));
   r.pool_cap = r.seeds_per_group * (c->max_live_per_seed * c->branches_per_surface + 1);
   r.nodes_per_seed = (l && l->nodes_per_seed > 0) ? l->nodes_per_seed : kNodesPerSeed;
-  r.waves_per_simd = (l && l->waves_per_simd > 0) ? std::min(2, l->waves_per_simd) : 2;
   return r;
 }
 

@@ -1112,28 +1112,32 @@ hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status,
 
 hipError_t launch_ckf(const CkfArgs& a, int waves_per_simd, hipStream_t st) {
   const dim3 grid(a.w.grid), block(kWave);
-  // 3 or 4 waves per SIMD would need register spills; those builds were
-  // slower and not bitwise identical to these, so they are not offered.
-  // The learned form runs in a uniform field (the host rejects a map).
-  const bool two = waves_per_simd >= 2;
+  // Register budgets of 1, 2 and 3 waves per SIMD (the 3-wave build spills a
+  // little and is still the fastest on the dense batch; 4 would spill much
+  // more).  The learned form runs in a uniform field (the host rejects a map).
+  const int w = waves_per_simd;
   if (a.f.map) {
     if (a.counters)
       hipLaunchKernelGGL((k_ckf<1, true, false, true>), grid, block, 0, st, a);
-    else if (two)
+    else if (w >= 2)
       hipLaunchKernelGGL((k_ckf<2, false, false, true>), grid, block, 0, st, a);
     else
       hipLaunchKernelGGL((k_ckf<1, false, false, true>), grid, block, 0, st, a);
   } else if (a.learned) {
     if (a.counters)
       hipLaunchKernelGGL((k_ckf<1, true, true, false>), grid, block, 0, st, a);
-    else if (two)
+    else if (w >= 3)
+      hipLaunchKernelGGL((k_ckf<3, false, true, false>), grid, block, 0, st, a);
+    else if (w == 2)
       hipLaunchKernelGGL((k_ckf<2, false, true, false>), grid, block, 0, st, a);
     else
       hipLaunchKernelGGL((k_ckf<1, false, true, false>), grid, block, 0, st, a);
   } else {
     if (a.counters)
       hipLaunchKernelGGL((k_ckf<1, true, false, false>), grid, block, 0, st, a);
-    else if (two)
+    else if (w >= 3)
+      hipLaunchKernelGGL((k_ckf<3, false, false, false>), grid, block, 0, st, a);
+    else if (w == 2)
       hipLaunchKernelGGL((k_ckf<2, false, false, false>), grid, block, 0, st, a);
     else
       hipLaunchKernelGGL((k_ckf<1, false, false, false>), grid, block, 0, st, a);

@@ -235,7 +235,7 @@ def test_learned_search_equals_plain_where_listing_agrees(ckf, det_dense, traine
     for k in ("offsets", "meas", "params", "cov"):
         assert np.array_equal(never[k], plain[k]), k
     # the uninstrumented learned kernels find the same tracks as the instrumented one
-    for waves in (1, 2):
+    for waves in (1, 2, 3):
         f = ckf.Finder(geo, fld, b, ckf.config(), ckf.launch(0, 0, 64, None, waves), counters=False, model=model)
         f.enqueue()
         r = f.result()

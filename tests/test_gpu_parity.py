@@ -217,10 +217,10 @@ def test_ckf_repeatable_and_launch_invariant(ckf, det_dense):
     geo = ckf.Geometry(det_dense.as_arrays())
     fld = ckf.UniformField(0, 0, 2.0)
     b = ckf.Batch.from_event(ev)
-    _say("[ckf/repeat] 2000 seeds, 3 launch shapes")
+    _say("[ckf/repeat] 2000 seeds, launch shapes of every register variant")
     runs = [ckf.find(geo, fld, b, launch_cfg=ckf.launch(grid=g, seeds_per_group=s, waves_per_simd=w))
             for g, s, w in ((0, 0, 0), (0, 0, 0), (7, 5, 1), (64, 64, 2))]
-    for g, s, w in ((0, 0, 1), (0, 0, 2), (5, 48, 2), (300, 8, 1)):  # uninstrumented variants
+    for g, s, w in ((0, 0, 1), (0, 0, 2), (0, 0, 3), (5, 48, 2), (300, 8, 1), (40, 32, 3)):  # uninstrumented
         f = ckf.Finder(geo, fld, b, launch_cfg=ckf.launch(grid=g, seeds_per_group=s, waves_per_simd=w),
                        counters=False)
         f.enqueue()
