@@ -48,7 +48,7 @@ MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 
 # by (form, grid, seeds per group, waves per SIMD): the pools make the
 # traffic depend on the launch shape.  Source: profiles/k_ckf_mu200x64_hbm_traffic.md;
 # an entry is dropped when its kernel changes.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.56e9}
 PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
 PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
 PEAK_BF16 = 2.5e15    # MI355X dense bf16 MFMA, FLOP/s

@@ -345,6 +345,9 @@ ckf_status ckf_mlp_grad(const float* params, const float* x, const int32_t* labe
 ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr,
                         float beta1, float beta2, float eps, void* stream);
 
+/* Device workspace of ckf_capture_pairs for cap_tracks tracks: bytes it needs. */
+ckf_status ckf_capture_workspace_size(int32_t cap_tracks, size_t* bytes);
+
 /* Training pairs from found tracks (device memory): at every change of
  * layer between consecutive measurements of a track, the network input of
  * the state at the last measurement of the layer - through its local
@@ -358,11 +361,16 @@ ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, in
  * track [cap] (may be NULL).  counts [2] receives the number of pairs (also
  * beyond cap) and of dropped pairs.  n_tracks is a device int32 (as
  * ckf_find writes it); offsets, meas_surface and meas_params are a
- * ckf_find output (offsets within meas capacity).  Uniform field only. */
+ * ckf_find output (offsets within meas capacity).  workspace: device
+ * memory of at least ckf_capture_workspace_size(cap_tracks) bytes
+ * (CKF_ERR_CAPACITY if smaller), owned by the caller, free again when the
+ * stream has passed the call.  Uniform field only (CKF_ERR_NOT_SUPPORTED
+ * for a map). */
 ckf_status ckf_capture_pairs(const ckf_geometry* g, const ckf_field* field, const int32_t* n_tracks,
                              int32_t cap_tracks, const int32_t* offsets, const int32_t* meas_surface,
                              const double* meas_params, int64_t cap_pairs, float* x, int32_t* label,
-                             int32_t* track, int64_t* counts, void* stream);
+                             int32_t* track, int64_t* counts, void* workspace, size_t workspace_bytes,
+                             void* stream);
 
 /* A pair of HIP events that ckf_find records, on its stream, immediately
  * before and after the persistent track-finding kernel when the launch

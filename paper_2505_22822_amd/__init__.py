@@ -183,10 +183,14 @@ def capture_pairs(geometry: Geometry, field, out: dict, cap_pairs: int, stream=N
         trk = torch.empty(cap, dtype=torch.int32, device=dev)
         counts = torch.zeros(2, dtype=torch.int64, device=dev)
         cap_tracks = int(out["offsets"].numel()) - 1
-        _check(_abi.load().ckf_capture_pairs(geometry.handle, field.handle, _ptr(out["n_tracks"]), cap_tracks,
-                                             _ptr(out["offsets"]), _ptr(out["meas_surface"]),
-                                             _ptr(out["meas_params"]), cap, _ptr(x), _ptr(lab), _ptr(trk),
-                                             _ptr(counts), _stream_handle(s)), "ckf_capture_pairs")
+        lib = _abi.load()
+        nb = C.c_size_t(0)
+        _check(lib.ckf_capture_workspace_size(cap_tracks, C.byref(nb)), "ckf_capture_workspace_size")
+        ws = torch.empty(max(1, int(nb.value)), dtype=torch.uint8, device=dev)
+        _check(lib.ckf_capture_pairs(geometry.handle, field.handle, _ptr(out["n_tracks"]), cap_tracks,
+                                     _ptr(out["offsets"]), _ptr(out["meas_surface"]), _ptr(out["meas_params"]), cap,
+                                     _ptr(x), _ptr(lab), _ptr(trk), _ptr(counts), _ptr(ws), int(nb.value),
+                                     _stream_handle(s)), "ckf_capture_pairs")
         c = counts.cpu().numpy()
     k = int(min(c[0], cap))
     return x[:k], lab[:k], trk[:k], int(c[0]), int(c[1])

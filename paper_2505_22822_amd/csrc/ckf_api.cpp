@@ -893,18 +893,27 @@ ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, in
   return CKF_OK;
 }
 
+ckf_status ckf_capture_workspace_size(int32_t cap_tracks, size_t* bytes) {
+  if (cap_tracks < 0 || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "capture_workspace_size: bad argument");
+  *bytes = ckf::capture_workspace_bytes(cap_tracks);
+  return CKF_OK;
+}
+
 ckf_status ckf_capture_pairs(const ckf_geometry* g, const ckf_field* field, const int32_t* n_tracks,
                              int32_t cap_tracks, const int32_t* offsets, const int32_t* meas_surface,
                              const double* meas_params, int64_t cap_pairs, float* x, int32_t* label,
-                             int32_t* track, int64_t* counts, void* stream) {
+                             int32_t* track, int64_t* counts, void* workspace, size_t workspace_bytes,
+                             void* stream) {
   if (!g || !field || !n_tracks || !offsets || !meas_surface || !meas_params || !counts || cap_tracks < 0 ||
-      cap_pairs < 0 || (cap_pairs > 0 && (!x || !label)))
+      cap_pairs < 0 || (cap_pairs > 0 && (!x || !label)) || !workspace)
     return fail(CKF_ERR_INVALID_ARGUMENT, "capture_pairs: bad argument");
+  if (workspace_bytes < ckf::capture_workspace_bytes(cap_tracks))
+    return fail(CKF_ERR_CAPACITY, "capture_pairs: workspace too small");
   if (field->dev.map) return fail(CKF_ERR_NOT_SUPPORTED, "capture_pairs: uniform field only");
   HIP_TRY(ckf::launch_capture_pairs(g->dev, field->dev, n_tracks, cap_tracks, offsets, meas_surface, meas_params,
-                                    cap_pairs, x, label, track, reinterpret_cast<long long*>(counts),
+                                    cap_pairs, x, label, track, reinterpret_cast<long long*>(counts), workspace,
                                     static_cast<hipStream_t>(stream)),
-          "launch k_capture_pairs");
+          "launch the pair capture");
   return CKF_OK;
 }
 

@@ -91,11 +91,13 @@ struct CfgDev {
 
 // The next-module network packed for the bf16 matrix cores: weight tiles in
 // the A-operand order of v_mfma_f32_16x16x16_bf16 (per 16x16 tile, lane l
-// holds W[16*ob + l%16][16*kb + 4*(l/16) + j], j = 0..3), FP32 biases.
+// holds W[16*ob + l%16][16*kb + 4*(l/16) + j], j = 0..3), FP32 biases.  The
+// four fragments a lane needs for one output tile are adjacent (32 bytes),
+// so a tile's operands arrive with two 16-byte loads.
 struct ModelDev {
-  const uint2* w1 = nullptr;  // [4 ob][64 lanes]      (inputs padded 7 -> 16)
-  const uint2* w2 = nullptr;  // [4 ob][4 kb][64 lanes]
-  const uint2* w3 = nullptr;  // [2 ob][4 kb][64 lanes]
+  const uint2* w1 = nullptr;  // [64 lanes][4 ob]      (inputs padded 7 -> 16)
+  const uint2* w2 = nullptr;  // [4 ob][64 lanes][4 kb]
+  const uint2* w3 = nullptr;  // [2 ob][64 lanes][4 kb]
   const float* b1 = nullptr;  // [64]
   const float* b2 = nullptr;  // [64]
   const float* b3 = nullptr;  // [32]

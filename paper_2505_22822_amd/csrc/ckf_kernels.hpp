@@ -50,9 +50,10 @@ hipError_t launch_mlp_grad(const float* params, const float* x, const int* label
                            void* ws, float* grad, float* loss, hipStream_t st);
 hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, int step, float lr, float b1,
                            float b2, float eps, hipStream_t st);
+size_t capture_workspace_bytes(int cap_tracks);
 hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* n_tracks, int cap_tracks, const int* off,
                                 const int* msurf, const double* mpar, long long cap_pairs, float* x, int* label,
-                                int* track, long long* counts, hipStream_t st);
+                                int* track, long long* counts, void* ws, hipStream_t st);
 hipError_t launch_kf_update(int n, const double* p_in, const double* cov_in, const float* meas, const float* var,
                             double* p_out, double* cov_out, double* chi2, hipStream_t st);
 

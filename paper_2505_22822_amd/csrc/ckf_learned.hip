@@ -32,15 +32,15 @@ __global__ void k_model_pack(const float* __restrict__ P, uint2* __restrict__ ou
         const int col = q4 + j;
         v[j] = col < 7 ? P[kW1 + (16 * f + i) * 7 + col] : 0.f;
       }
-      w1[f * 64 + lane] = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+      w1[lane * 4 + f] = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
     } else if (f < 4 + 16) {
       const int g = f - 4, ob = g >> 2, kb = g & 3;
       for (int j = 0; j < 4; ++j) v[j] = P[kW2 + (16 * ob + i) * 64 + 16 * kb + q4 + j];
-      w2[g * 64 + lane] = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+      w2[(ob * 64 + lane) * 4 + kb] = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
     } else {
       const int g = f - 20, ob = g >> 2, kb = g & 3;
       for (int j = 0; j < 4; ++j) v[j] = P[kW3 + (16 * ob + i) * 64 + 16 * kb + q4 + j];
-      w3[g * 64 + lane] = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+      w3[(ob * 64 + lane) * 4 + kb] = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
     }
   }
   for (int t = threadIdx.x; t < 160; t += blockDim.x)
@@ -289,8 +289,9 @@ __global__ void k_mlp_adam(float* __restrict__ P, float* __restrict__ m, float* 
 // the tracks in chunks; a block scan places each chunk's pairs in track
 // order)
 
-constexpr int kCapThreads = 1024;
+constexpr int kCapBlock = 256;  // threads (tracks) per capture block
 
+// Exclusive prefix sum of v over the kCapBlock threads of a block.
 __device__ __forceinline__ int block_excl_scan(int v, int* sh_w, int& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int x = v;
@@ -302,7 +303,8 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh_w, int& total) {
   if (lane == 63) sh_w[w] = x;
   __syncthreads();
   int base = 0, tot = 0;
-  for (int k = 0; k < kCapThreads / 64; ++k) {
+#pragma unroll
+  for (int k = 0; k < kCapBlock / 64; ++k) {
     if (k < w) base += sh_w[k];
     tot += sh_w[k];
   }
@@ -311,100 +313,148 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh_w, int& total) {
   return base + x - v;
 }
 
-__global__ void __launch_bounds__(kCapThreads) k_capture_pairs(GeomDev g, FieldDev F, const int* __restrict__ n_tracks_p,
-                                                               int cap_tracks, const int* __restrict__ off,
-                                                               const int* __restrict__ msurf,
-                                                               const double* __restrict__ mpar, long long cap_pairs,
-                                                               float* __restrict__ x, int* __restrict__ label,
-                                                               int* __restrict__ track,
-                                                               long long* __restrict__ counts) {
-  __shared__ int sh_w[kCapThreads / 64];
-  const int n_t = min(*n_tracks_p, cap_tracks);
-  long long base = 0, dropped = 0;
-  for (int t0 = 0; t0 < n_t; t0 += kCapThreads) {
-    const int t = t0 + threadIdx.x;
-    int cnt = 0, drop = 0;
-    // pass 1: count; pass 2: write at the scanned position
-    for (int pass = 0; pass < 2; ++pass) {
-      int pos = 0, total = 0;
-      if (pass == 1) pos = block_excl_scan(cnt, sh_w, total);
-      int k = 0;
-      if (t < n_t) {
-        for (int i = off[t]; i < off[t + 1] - 1; ++i) {
-          const int m = msurf[i], m1 = msurf[i + 1];
-          if (m < 0 || m >= g.n_surfaces || m1 < 0 || m1 >= g.n_surfaces) {
-            if (pass == 0) ++drop;
-            continue;
-          }
-          const int L = g.mod[m].layer, L2 = g.mod[m1].layer;
-          if (L == L2) continue;
-          int slot = -1;
-          for (int s = 0; s < kMaxNext; ++s)
-            if (slot < 0 && g.nb_next[m * kMaxNext + s] == L2) slot = s;
-          // the local helix from the state on m to L2's envelope, as the navigation finds it
-          bool have = false;
-          V3 X = {0.f, 0.f, 0.f}, Tx = {0.f, 0.f, 0.f};
-          Window w{0, 0, 0.f, 0.f};
-          const LayerRec Lr = g.layers[L2];
-          const int row = slot >= 0 ? g.nb_row[m * kMaxNext + slot] : -1;
-          if (row >= 0) {
-            Module M;
-            load_module(g, m, M);
-            const double* p = mpar + 5ll * i;
-            float sp, cp, st, ct;
-            sincosf((float)p[2], &sp, &cp);
-            sincosf((float)p[3], &st, &ct);
-            const V3 P = ld3(M.c) + (float)p[0] * ld3(M.u) + (float)p[1] * ld3(M.v);
-            const V3 T = {cp * st, sp * st, ct};
-            const Helix H = make_helix(P, T, (float)p[4], field_at<false>(F, P));
-            float sc;
-            const bool hit = Lr.type == 0 ? cross_cylinder(H, Lr.pos, sc) : cross_zplane(H, Lr.pos, sc);
-            if (hit) {
-              helix_at_nav(H, sc, X, Tx);
-              have = crossing_window(Lr, g.nb_anc[row], X, w);
-            }
-          }
-          // one pair per measurement of the track on L2 (overlaps give several)
-          for (int j = i + 1; j < off[t + 1]; ++j) {
-            const int m2 = msurf[j];
-            if (m2 < 0 || m2 >= g.n_surfaces || g.mod[m2].layer != L2) break;
-            int lab = -1;
-            if (have) {
-              const int* reg = g.nb_reg + (long long)row * kRegCells;
-              for (int q = 0; q < kRegCells; ++q)
-                if (lab < 0 && reg[q] == m2) {
-                  const int wu = (q % kRegU + kRegU0) - w.iu - kWinU0, wv = (q / kRegU + kRegV0) - w.iv - kWinV0;
-                  lab = (wu >= 0 && wu < kWinU && wv >= 0 && wv < kWinV) ? wv * kWinU + wu : -2;
-                }
-            }
-            if (lab < 0) {
-              if (pass == 0) ++drop;
-              continue;
-            }
-            if (pass == 0) {
-              ++cnt;
-              continue;
-            }
-            const long long o = base + pos + k;
-            ++k;
-            if (o >= cap_pairs) continue;
-            float f[7];
-            mlp_features(Lr, L2, g.n_layers, w, X, Tx, (float)mpar[5ll * i + 4], f);
-            for (int c = 0; c < 7; ++c) x[o * 7 + c] = f[c];
-            label[o] = lab;
-            if (track) track[o] = t;
-          }
-        }
-      }
-      if (pass == 1) base += total;
+// The pairs of found track t: counted (write false: cnt pairs, drop
+// dropped) or written from position o0 on (write true).
+__device__ void capture_track(const GeomDev& g, const FieldDev& F, int t, const int* __restrict__ off,
+                              const int* __restrict__ msurf, const double* __restrict__ mpar, bool write, long long o0,
+                              long long cap_pairs, float* __restrict__ x, int* __restrict__ label,
+                              int* __restrict__ track, int& cnt, int& drop) {
+  int k = 0;
+  for (int i = off[t]; i < off[t + 1] - 1; ++i) {
+    const int m = msurf[i], m1 = msurf[i + 1];
+    if (m < 0 || m >= g.n_surfaces || m1 < 0 || m1 >= g.n_surfaces) {
+      ++drop;
+      continue;
     }
-    int dtot = 0;
-    (void)block_excl_scan(drop, sh_w, dtot);
-    dropped += dtot;
+    const int L = g.mod[m].layer, L2 = g.mod[m1].layer;
+    if (L == L2) continue;
+    int slot = -1;
+    for (int s = 0; s < kMaxNext; ++s)
+      if (slot < 0 && g.nb_next[m * kMaxNext + s] == L2) slot = s;
+    // the local helix from the state on m to L2's envelope, as the navigation finds it
+    bool have = false;
+    V3 X = {0.f, 0.f, 0.f}, Tx = {0.f, 0.f, 0.f};
+    Window w{0, 0, 0.f, 0.f};
+    const LayerRec Lr = g.layers[L2];
+    const int row = slot >= 0 ? g.nb_row[m * kMaxNext + slot] : -1;
+    if (row >= 0) {
+      Module M;
+      load_module(g, m, M);
+      const double* p = mpar + 5ll * i;
+      float sp, cp, st, ct;
+      sincosf((float)p[2], &sp, &cp);
+      sincosf((float)p[3], &st, &ct);
+      const V3 P = ld3(M.c) + (float)p[0] * ld3(M.u) + (float)p[1] * ld3(M.v);
+      const V3 T = {cp * st, sp * st, ct};
+      const Helix H = make_helix(P, T, (float)p[4], field_at<false>(F, P));
+      float sc;
+      const bool hit = Lr.type == 0 ? cross_cylinder(H, Lr.pos, sc) : cross_zplane(H, Lr.pos, sc);
+      if (hit) {
+        helix_at_nav(H, sc, X, Tx);
+        have = crossing_window(Lr, g.nb_anc[row], X, w);
+      }
+    }
+    // one pair per measurement of the track on L2 (overlaps give several)
+    for (int j = i + 1; j < off[t + 1]; ++j) {
+      const int m2 = msurf[j];
+      if (m2 < 0 || m2 >= g.n_surfaces || g.mod[m2].layer != L2) break;
+      int lab = -1;
+      if (have) {
+        const int* reg = g.nb_reg + (long long)row * kRegCells;
+        for (int q = 0; q < kRegCells; ++q)
+          if (lab < 0 && reg[q] == m2) {
+            const int wu = (q % kRegU + kRegU0) - w.iu - kWinU0, wv = (q / kRegU + kRegV0) - w.iv - kWinV0;
+            lab = (wu >= 0 && wu < kWinU && wv >= 0 && wv < kWinV) ? wv * kWinU + wu : -2;
+          }
+      }
+      if (lab < 0) {
+        ++drop;
+        continue;
+      }
+      ++cnt;
+      if (!write) continue;
+      const long long o = o0 + k;
+      ++k;
+      if (o >= cap_pairs) continue;
+      float f[7];
+      mlp_features(Lr, L2, g.n_layers, w, X, Tx, (float)mpar[5ll * i + 4], f);
+      for (int c = 0; c < 7; ++c) x[o * 7 + c] = f[c];
+      label[o] = lab;
+      if (track) track[o] = t;
+    }
+  }
+}
+
+// Pass 1: pairs of each track (kept for pass 3) and per-block sums of
+// pairs and drops.
+__global__ void __launch_bounds__(kCapBlock) k_capture_count(GeomDev g, FieldDev F, const int* __restrict__ n_tracks_p,
+                                                             int cap_tracks, const int* __restrict__ off,
+                                                             const int* __restrict__ msurf,
+                                                             const double* __restrict__ mpar,
+                                                             int* __restrict__ ws_cnt,
+                                                             long long* __restrict__ ws_bsum) {
+  __shared__ int sh_w[kCapBlock / 64];
+  const int n_t = min(*n_tracks_p, cap_tracks);
+  const int t = blockIdx.x * kCapBlock + threadIdx.x;
+  int cnt = 0, drop = 0;
+  if (t < n_t) capture_track(g, F, t, off, msurf, mpar, false, 0, 0, nullptr, nullptr, nullptr, cnt, drop);
+  if (t < cap_tracks) ws_cnt[t] = cnt;
+  int tc = 0, td = 0;
+  (void)block_excl_scan(cnt, sh_w, tc);
+  (void)block_excl_scan(drop, sh_w, td);
+  if (threadIdx.x == 0) {
+    ws_bsum[2 * blockIdx.x] = tc;
+    ws_bsum[2 * blockIdx.x + 1] = td;
+  }
+}
+
+// Pass 2 (one block): block offsets in track order and the totals.
+__global__ void __launch_bounds__(kCapBlock) k_capture_offsets(int nb, const long long* __restrict__ ws_bsum,
+                                                               long long* __restrict__ ws_boff,
+                                                               long long* __restrict__ counts) {
+  __shared__ long long sh_c[kCapBlock], sh_d[kCapBlock];
+  long long base = 0, dropped = 0;
+  for (int b0 = 0; b0 < nb; b0 += kCapBlock) {
+    const int b = b0 + threadIdx.x;
+    sh_c[threadIdx.x] = b < nb ? ws_bsum[2 * b] : 0;
+    sh_d[threadIdx.x] = b < nb ? ws_bsum[2 * b + 1] : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // serial over one chunk: a few thousand blocks at most
+      for (int k = 0; k < kCapBlock && b0 + k < nb; ++k) {
+        const long long c = sh_c[k];
+        ws_boff[b0 + k] = base;
+        base += c;
+        dropped += sh_d[k];
+      }
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
     counts[0] = base;
     counts[1] = dropped;
+  }
+}
+
+// Pass 3: each track's pairs written at its block offset plus its position
+// in the block.
+__global__ void __launch_bounds__(kCapBlock) k_capture_write(GeomDev g, FieldDev F, const int* __restrict__ n_tracks_p,
+                                                             int cap_tracks, const int* __restrict__ off,
+                                                             const int* __restrict__ msurf,
+                                                             const double* __restrict__ mpar,
+                                                             const int* __restrict__ ws_cnt,
+                                                             const long long* __restrict__ ws_boff, long long cap_pairs,
+                                                             float* __restrict__ x, int* __restrict__ label,
+                                                             int* __restrict__ track) {
+  __shared__ int sh_w[kCapBlock / 64];
+  const int n_t = min(*n_tracks_p, cap_tracks);
+  const int t = blockIdx.x * kCapBlock + threadIdx.x;
+  const int cnt = t < n_t ? ws_cnt[t] : 0;
+  int tot = 0;
+  const int pos = block_excl_scan(cnt, sh_w, tot);
+  const long long o0 = ws_boff[blockIdx.x] + pos;
+  if (t < n_t && cnt > 0 && o0 < cap_pairs) {
+    int c = 0, d = 0;
+    capture_track(g, F, t, off, msurf, mpar, true, o0, cap_pairs, x, label, track, c, d);
   }
 }
 
@@ -455,11 +505,36 @@ hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad,
   return hipGetLastError();
 }
 
+namespace {
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t capture_workspace_bytes(int cap_tracks) {
+  const size_t nb = (size_t)(cap_tracks + kCapBlock - 1) / kCapBlock;
+  return align256((size_t)cap_tracks * sizeof(int)) + align256(nb * 2 * sizeof(long long)) +
+         align256(nb * sizeof(long long));
+}
+
 hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* n_tracks, int cap_tracks,
                                 const int* off, const int* msurf, const double* mpar, long long cap_pairs, float* x,
-                                int* label, int* track, long long* counts, hipStream_t st) {
-  hipLaunchKernelGGL(k_capture_pairs, dim3(1), dim3(kCapThreads), 0, st, g, f, n_tracks, cap_tracks, off, msurf,
-                     mpar, cap_pairs, x, label, track, counts);
+                                int* label, int* track, long long* counts, void* ws, hipStream_t st) {
+  const int nb = (cap_tracks + kCapBlock - 1) / kCapBlock;
+  char* w = static_cast<char*>(ws);
+  int* ws_cnt = reinterpret_cast<int*>(w);
+  long long* ws_bsum = reinterpret_cast<long long*>(w + align256((size_t)cap_tracks * sizeof(int)));
+  long long* ws_boff = reinterpret_cast<long long*>(reinterpret_cast<char*>(ws_bsum) +
+                                                    align256((size_t)nb * 2 * sizeof(long long)));
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_capture_count, dim3(nb), dim3(kCapBlock), 0, st, g, f, n_tracks, cap_tracks, off, msurf, mpar,
+                       ws_cnt, ws_bsum);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_capture_offsets, dim3(1), dim3(kCapBlock), 0, st, nb, ws_bsum, ws_boff, counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nb == 0) return e;
+  hipLaunchKernelGGL(k_capture_write, dim3(nb), dim3(kCapBlock), 0, st, g, f, n_tracks, cap_tracks, off, msurf, mpar,
+                     ws_cnt, ws_boff, cap_pairs, x, label, track);
   return hipGetLastError();
 }
 

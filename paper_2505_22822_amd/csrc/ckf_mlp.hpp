@@ -65,29 +65,59 @@ __device__ __forceinline__ f32x4 ld_f4(const float* p) {
 }
 
 // Logits of NB 16-row blocks at once: every weight tile is fetched once and
-// applied to the NB blocks, which gives NB independent MFMA chains.
+// applied to the NB blocks, which gives NB independent MFMA chains.  The
+// operands of the next output tile (two 16-byte weight loads and the bias)
+// are requested before the current tile's products, so each tile waits for
+// at most one memory round trip, overlapped with the previous tile's work.
 // xb[rb]: this lane's B operand of the input of rows 16*rb + l%16 of those
 // blocks.  Must be called by all 64 lanes together.
+struct TileOps {
+  uint4 w01, w23;  // fragments kb = 0, 1 and 2, 3
+  f32x4 b;
+};
+
+__device__ __forceinline__ TileOps tile_ops(const uint2* w, const float* b, int ob, int lane) {
+  const uint4* p = reinterpret_cast<const uint4*>(w + (ob * 64 + lane) * 4);
+  TileOps t;
+  t.w01 = p[0];
+  t.w23 = p[1];
+  t.b = ld_f4(b + 16 * ob + 4 * (lane >> 4));
+  return t;
+}
+
+__device__ __forceinline__ bf16x4 frag(const TileOps& t, int kb) {
+  const uint4& u = kb < 2 ? t.w01 : t.w23;
+  return as_bf16x4((kb & 1) ? make_uint2(u.z, u.w) : make_uint2(u.x, u.y));
+}
+
 template <int NB>
 __device__ __forceinline__ void mlp_blocks(const ModelDev& M, const bf16x4 xb[NB], int lane, f32x4 out[NB][2]) {
   const int q4 = 4 * (lane >> 4);
   bf16x4 h1[NB][4], h2[NB][4];
+  // layer 1: the lane's four W1 fragments (one per output tile) and biases
+  const uint4* p1 = reinterpret_cast<const uint4*>(M.w1 + lane * 4);
+  const uint4 w1a = p1[0], w1b = p1[1];
+  f32x4 b1[4];
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) b1[ob] = ld_f4(M.b1 + 16 * ob + q4);
+  TileOps nxt = tile_ops(M.w2, M.b2, 0, lane);
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
-    const f32x4 b = ld_f4(M.b1 + 16 * ob + q4);
-    const bf16x4 w = as_bf16x4(M.w1[ob * 64 + lane]);
+    const uint4& u = ob < 2 ? w1a : w1b;
+    const bf16x4 w = as_bf16x4((ob & 1) ? make_uint2(u.z, u.w) : make_uint2(u.x, u.y));
 #pragma unroll
-    for (int rb = 0; rb < NB; ++rb) h1[rb][ob] = relu_bf16(mfma16(w, xb[rb], b));
+    for (int rb = 0; rb < NB; ++rb) h1[rb][ob] = relu_bf16(mfma16(w, xb[rb], b1[ob]));
   }
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
+    const TileOps cur = nxt;
+    nxt = ob < 3 ? tile_ops(M.w2, M.b2, ob + 1, lane) : tile_ops(M.w3, M.b3, 0, lane);
     f32x4 acc[NB];
-    const f32x4 b = ld_f4(M.b2 + 16 * ob + q4);
 #pragma unroll
-    for (int rb = 0; rb < NB; ++rb) acc[rb] = b;
+    for (int rb = 0; rb < NB; ++rb) acc[rb] = cur.b;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
-      const bf16x4 w = as_bf16x4(M.w2[(ob * 4 + kb) * 64 + lane]);
+      const bf16x4 w = frag(cur, kb);
 #pragma unroll
       for (int rb = 0; rb < NB; ++rb) acc[rb] = mfma16(w, h1[rb][kb], acc[rb]);
     }
@@ -96,12 +126,13 @@ __device__ __forceinline__ void mlp_blocks(const ModelDev& M, const bf16x4 xb[NB
   }
 #pragma unroll
   for (int ob = 0; ob < 2; ++ob) {
-    const f32x4 b = ld_f4(M.b3 + 16 * ob + q4);
+    const TileOps cur = nxt;
+    if (ob == 0) nxt = tile_ops(M.w3, M.b3, 1, lane);
 #pragma unroll
-    for (int rb = 0; rb < NB; ++rb) out[rb][ob] = b;
+    for (int rb = 0; rb < NB; ++rb) out[rb][ob] = cur.b;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
-      const bf16x4 w = as_bf16x4(M.w3[(ob * 4 + kb) * 64 + lane]);
+      const bf16x4 w = frag(cur, kb);
 #pragma unroll
       for (int rb = 0; rb < NB; ++rb) out[rb][ob] = mfma16(w, h2[rb][kb], out[rb][ob]);
     }

@@ -79,6 +79,12 @@ def test_host_side_validation(lib):
     assert lib.ckf_workspace_size(None, C.byref(cfg), None, 1, 1, 1, C.byref(nb)) == 1
     assert lib.ckf_find(None, None, None, None, C.byref(cfg), None, None, None, 0, None, None) == 1
     assert lib.ckf_mlp_workspace_size(0, C.byref(nb)) == 1
+    assert lib.ckf_capture_workspace_size(-1, C.byref(nb)) == 1
+    assert lib.ckf_capture_workspace_size(0, C.byref(nb)) == 0
+    small = nb.value
+    assert lib.ckf_capture_workspace_size(600000, C.byref(nb)) == 0 and nb.value >= 600000 * 4 > small
+    assert lib.ckf_capture_pairs(None, None, None, 0, None, None, None, 0, None, None, None, None, None, 0,
+                                 None) == 1
     assert lib.ckf_model_create(None, None, C.byref(h)) == 1
     assert lib.ckf_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == 1
     assert lib.ckf_kf_update_batch(-1, None, None, None, None, None, None, None, None) == 1

@@ -168,6 +168,56 @@ def test_capture_pairs_matches_oracle(ckf, det_barrel):
     assert n2 == n_pairs and np.array_equal(lab2.cpu().numpy(), lab[:17])
 
 
+def test_capture_pairs_many_tracks_matches_oracle(ckf, det_dense):
+    """600 truth trajectories of a dense event, given as found tracks (the
+    seeded generator's crossings: surface, local position, direction, q/p),
+    span three capture blocks: the GPU capture gives the oracle's pairs in
+    the same track and measurement order, and a capacity cut inside the
+    second block keeps exactly the first pairs."""
+    import torch
+    from oracle import learned as OL
+    _say("# pair capture, 600 truth tracks")
+    g = det_dense.as_arrays()
+    ev = make_event(det_dense, 11, mu=12)
+    tr = ev.truth
+    _, first = np.unique(tr.particle, return_index=True)
+    offsets = np.append(first, len(tr.particle)).astype(np.int32)
+    d = tr.dir
+    mp = np.stack([tr.loc[:, 0], tr.loc[:, 1], np.arctan2(d[:, 1], d[:, 0]), np.arccos(np.clip(d[:, 2], -1, 1)),
+                   tr.qop], -1)
+    ms = tr.surface.astype(np.int32)
+    n_t = len(first)
+    assert n_t > 512
+    mods = np.unique(ms)
+    n_mod = g["center"].shape[0]
+    sn, sr, sa = OL.neighbour_table(g, modules=mods)
+    onxt = np.full((n_mod, 3), -1, np.int32)
+    oreg = np.full((n_mod, 3, 192), -1, np.int32)
+    oanc = np.zeros((n_mod, 3, 5))
+    onxt[mods], oreg[mods], oanc[mods] = sn, sr, sa
+    x_o, lab_o, trk_o, _, drop_o = OL.capture_pairs(g, onxt, oreg, oanc, offsets, ms, mp)
+    geo = ckf.Geometry(g)
+    fld = ckf.UniformField(0, 0, 2.0)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    out = dict(n_tracks=dev(np.array([n_t], np.int32)), offsets=dev(offsets), meas_surface=dev(ms),
+               meas_params=dev(mp))
+    x, lab, trk, n_pairs, dropped = ckf.capture_pairs(geo, fld, out, len(lab_o) + 10)
+    _say(f"#   pairs {n_pairs} (oracle {len(lab_o)}), dropped {dropped} (oracle {drop_o})")
+    assert n_pairs == len(lab_o) and dropped == drop_o
+    x, lab, trk = x.cpu().numpy(), lab.cpu().numpy(), trk.cpu().numpy()
+    np.testing.assert_array_equal(trk, trk_o)
+    assert trk.max() >= 2 * 256  # pairs from the third block
+    edge = (np.abs(np.abs(x_o[:, 0]) - 0.5) < 1e-4) | (np.abs(np.abs(x_o[:, 1]) - 0.5) < 1e-4)
+    same = lab == lab_o
+    assert np.all(same | edge) and same.mean() > 0.99
+    np.testing.assert_allclose(x[same & ~edge], x_o[same & ~edge], rtol=0, atol=2e-5)
+    cut = int(np.searchsorted(trk_o, 300)) + 3  # inside the second block's pairs
+    x2, lab2, trk2, n2, _ = ckf.capture_pairs(geo, fld, out, cut)
+    assert n2 == n_pairs and len(lab2) == cut
+    np.testing.assert_array_equal(lab2.cpu().numpy(), lab[:cut])
+    np.testing.assert_array_equal(trk2.cpu().numpy(), trk[:cut])
+
+
 @pytest.fixture(scope="module")
 def trained(ckf, det_dense):
     """A network trained on the GPU on pairs from the plain GPU search of
