@@ -345,6 +345,40 @@ ckf_status ckf_mlp_grad(const float* params, const float* x, const int32_t* labe
 ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step, float lr,
                         float beta1, float beta2, float eps, void* stream);
 
+/* Kalman-filter fit of found tracks with a smoother (paper section 2: the
+ * fit that follows track finding, with the Rauch-Tung-Striebel smoother;
+ * section 4: the optimal two-filter smoother).  The forward filter starts
+ * from each track's seed and visits the modules of its measurements in
+ * order (the search's FP32 stepper and Jacobian, FP64 transport, gain-form
+ * update with the Joseph covariance, then the module's scattering added at
+ * the updated state).  The smoother gives every measurement the state
+ * estimated from all of the track's measurements:
+ *   CKF_SMOOTHER_RTS:        Rauch-Tung-Striebel gains over the forward pass;
+ *   CKF_SMOOTHER_TWO_FILTER: a backward filter over reversed legs, started
+ *                            at the last measurement from the forward state
+ *                            with 100 times its covariance, combined with
+ *                            the forward filtered state by weight.
+ * Tracks (device memory, the layout ckf_find writes): n_tracks (device
+ * int32, at most cap_tracks used), offsets [cap_tracks+1] into meas,
+ * meas_surface [cap_meas] and seed [cap_tracks]; measurement ids index the
+ * measurement arrays of m, seed ids the seeds of s.  Outputs (device,
+ * caller-owned): params [cap_meas][5] and cov [cap_meas][15] smoothed at
+ * each measurement (NaN for a track that failed), chi2 [cap_tracks] (sum of
+ * the forward filter's chi2), ok [cap_tracks]: 1 fitted, 0 a leg failed or
+ * a covariance lost positive definiteness, -1 ids out of range (offsets
+ * outside [0, cap_meas] leave the track's outputs untouched).  workspace:
+ * at least ckf_fit_workspace_size(cap_meas) bytes of device memory
+ * (CKF_ERR_CAPACITY if smaller).  Asynchronous on `stream`; allocates
+ * nothing. */
+#define CKF_SMOOTHER_RTS 0
+#define CKF_SMOOTHER_TWO_FILTER 1
+ckf_status ckf_fit_workspace_size(int64_t cap_meas, size_t* bytes);
+ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m, const ckf_seeds* s,
+                   const ckf_config* cfg, const int32_t* n_tracks, int32_t cap_tracks, int64_t cap_meas,
+                   const int32_t* offsets, const int32_t* meas, const int32_t* meas_surface, const int32_t* seed,
+                   int32_t smoother, void* workspace, size_t workspace_bytes, double* params, double* cov,
+                   double* chi2, int32_t* ok, void* stream);
+
 /* Device workspace of ckf_capture_pairs for cap_tracks tracks: bytes it needs. */
 ckf_status ckf_capture_workspace_size(int32_t cap_tracks, size_t* bytes);
 

@@ -17,7 +17,7 @@ from . import _abi
 from ._abi import COUNTER_NAMES
 
 __all__ = ["Geometry", "UniformField", "FieldMap", "Model", "config", "find", "propagate_batch", "kf_update_batch",
-           "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "CkfError"]
+           "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "Fitter", "CkfError"]
 
 
 class CkfError(RuntimeError):
@@ -392,6 +392,67 @@ class Finder:
         if "counters" in o:
             res["counters"] = {n: int(o["counters"][i]) for i, n in enumerate(COUNTER_NAMES)}
         return res
+
+
+SMOOTHERS = {"rts": 0, "two_filter": 1}
+
+
+class Fitter:
+    """Workspace and outputs of repeated ckf_fit calls: the Kalman-filter fit
+    of found tracks with the RTS or the two-filter smoother.  `tracks`
+    holds device tensors in ckf_find's layout: n_tracks [1], offsets,
+    meas, meas_surface, seed (a Finder made with meas_states=True has them
+    in .out; see from_finder)."""
+
+    def __init__(self, geometry: Geometry, field, batch: Batch, tracks: dict, cfg=None, smoother="rts"):
+        import torch
+        if tracks.get("meas_surface") is None:
+            raise ValueError("tracks need meas_surface (a Finder made with meas_states=True)")
+        self.geometry, self.field, self.batch, self.tracks = geometry, field, batch, tracks
+        self.cfg = cfg if cfg is not None else config()
+        self.smoother = SMOOTHERS[smoother]
+        dev = tracks["offsets"].device
+        self.cap_tracks = int(tracks["offsets"].numel()) - 1
+        self.cap_meas = int(tracks["meas"].numel())
+        nb = C.c_size_t(0)
+        _check(_abi.load().ckf_fit_workspace_size(self.cap_meas, C.byref(nb)), "ckf_fit_workspace_size")
+        self.workspace = torch.empty(max(1, int(nb.value)), dtype=torch.uint8, device=dev)
+        self.params = torch.zeros((self.cap_meas, 5), dtype=torch.float64, device=dev)
+        self.cov = torch.zeros((self.cap_meas, 15), dtype=torch.float64, device=dev)
+        self.chi2 = torch.zeros(self.cap_tracks, dtype=torch.float64, device=dev)
+        self.ok = torch.zeros(self.cap_tracks, dtype=torch.int32, device=dev)
+        b = batch
+        self._meas = _abi.Measurements(b.n_events, b.n_surfaces, b.n_meas, _ptr(b.offsets), _ptr(b.loc),
+                                       _ptr(b.var))
+        self._seeds = _abi.Seeds(b.n_seeds, _ptr(b.seed_event), _ptr(b.seed_surface), _ptr(b.seed_params),
+                                 _ptr(b.seed_cov))
+
+    @staticmethod
+    def from_finder(finder: "Finder", smoother="rts"):
+        return Fitter(finder.geometry, finder.field, finder.batch, finder.out, finder.cfg, smoother)
+
+    def enqueue(self, stream=None):
+        """One ckf_fit on the stream (asynchronous, allocation-free)."""
+        t = self.tracks
+        _check(_abi.load().ckf_fit(self.geometry.handle, self.field.handle, C.byref(self._meas),
+                                   C.byref(self._seeds), C.byref(self.cfg), _ptr(t["n_tracks"]), self.cap_tracks,
+                                   self.cap_meas, _ptr(t["offsets"]), _ptr(t["meas"]), _ptr(t["meas_surface"]),
+                                   _ptr(t["seed"]), self.smoother, _ptr(self.workspace), self.workspace.numel(),
+                                   _ptr(self.params), _ptr(self.cov), _ptr(self.chi2), _ptr(self.ok),
+                                   _stream_handle(stream)), "ckf_fit")
+
+    def result(self):
+        """Synchronise and return the smoothed states per measurement
+        (aligned with the tracks' meas), chi2 and ok per track (numpy)."""
+        import torch
+        torch.cuda.synchronize()
+        t = self.tracks
+        nt = min(int(t["n_tracks"].cpu()[0]), self.cap_tracks)
+        off = t["offsets"][:nt + 1].cpu().numpy()
+        nm = int(off[-1]) if nt > 0 else 0
+        return dict(n_tracks=nt, offsets=off, params=self.params[:nm].cpu().numpy(),
+                    cov=self.cov[:nm].cpu().numpy(), chi2=self.chi2[:nt].cpu().numpy(),
+                    ok=self.ok[:nt].cpu().numpy())
 
 
 def find(geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, stream=None, retries=3, model=None,

@@ -893,6 +893,41 @@ ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, in
   return CKF_OK;
 }
 
+ckf_status ckf_fit_workspace_size(int64_t cap_meas, size_t* bytes) {
+  if (cap_meas < 0 || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "fit_workspace_size: bad argument");
+  *bytes = ckf::fit_workspace_bytes(cap_meas);
+  return CKF_OK;
+}
+
+ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m, const ckf_seeds* s,
+                   const ckf_config* cfg, const int32_t* n_tracks, int32_t cap_tracks, int64_t cap_meas,
+                   const int32_t* offsets, const int32_t* meas, const int32_t* meas_surface, const int32_t* seed,
+                   int32_t smoother, void* workspace, size_t workspace_bytes, double* params, double* cov,
+                   double* chi2, int32_t* ok, void* stream) {
+  if (!g || !f || !m || !s || !cfg) return fail(CKF_ERR_INVALID_ARGUMENT, "fit: NULL argument");
+  if (cap_tracks < 0 || cap_meas < 0) return fail(CKF_ERR_INVALID_ARGUMENT, "fit: negative capacity");
+  if (smoother != CKF_SMOOTHER_RTS && smoother != CKF_SMOOTHER_TWO_FILTER)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "fit: unknown smoother");
+  if (m->n_surfaces != g->dev.n_surfaces) return fail(CKF_ERR_INVALID_ARGUMENT, "fit: n_surfaces differs from geometry");
+  if (cap_tracks > 0 && (!n_tracks || !offsets || !seed || !chi2 || !ok))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "fit: NULL track array");
+  if (cap_meas > 0 && (!meas || !meas_surface || !params || !cov))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "fit: NULL measurement array");
+  if (cap_tracks > 0 && (!s->surface || !s->params || !s->cov || (m->n_meas > 0 && (!m->loc || !m->var))))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "fit: NULL seed or measurement input");
+  ckf_status st = check_config(cfg);
+  if (st != CKF_OK) return st;
+  if (workspace_bytes < ckf::fit_workspace_bytes(cap_meas) || (cap_meas > 0 && !workspace))
+    return fail(CKF_ERR_CAPACITY, "fit: workspace too small");
+  const ckf::MeasIn mi{m->n_events, m->n_surfaces, (long long)m->n_meas, m->offsets, m->loc, m->var};
+  const ckf::SeedsIn si{s->n_seeds, s->event, s->surface, s->params, s->cov};
+  HIP_TRY(ckf::launch_fit(g->dev, f->dev, to_dev(cfg), mi, si, n_tracks, cap_tracks, cap_meas, offsets, meas,
+                          meas_surface, seed, smoother == CKF_SMOOTHER_TWO_FILTER, workspace, params, cov, chi2, ok,
+                          static_cast<hipStream_t>(stream)),
+          "launch the fit");
+  return CKF_OK;
+}
+
 ckf_status ckf_capture_workspace_size(int32_t cap_tracks, size_t* bytes) {
   if (cap_tracks < 0 || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "capture_workspace_size: bad argument");
   *bytes = ckf::capture_workspace_bytes(cap_tracks);

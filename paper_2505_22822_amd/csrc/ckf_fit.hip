@@ -1,0 +1,411 @@
+// Kalman-filter fit of found tracks with a smoother (paper section 2: after
+// track finding a Kalman-filter fit with the Rauch-Tung-Striebel smoother
+// gives every measurement the information of the whole track; section 4:
+// the optimal two-filter smoother as the stable alternative).
+//
+// One lane per track.  The forward filter starts from the track's seed and
+// visits the surfaces of its measurements in order: an FP32 RKN4 leg with
+// its tangent-column Jacobian (the search's stepper), FP64 covariance
+// transport, FP64 gain-form update with the Joseph covariance, then the
+// module's Highland scattering added at the updated state.  Predicted and
+// filtered states and the leg Jacobians go to the workspace (one 432-byte
+// record per measurement); the smoother then runs backwards over them:
+//   RTS:        A_k = C_k|k F^T C_k+1|k^-1 (a Cholesky solve, no inverse),
+//               x_k|n = x_k|k + A_k (x_k+1|n - x_k+1|k),
+//               C_k|n = C_k|k + A_k (C_k+1|n - C_k+1|k) A_k^T;
+//   two-filter: a backward filter from the last measurement (its start is
+//               the forward state there with the forward covariance times
+//               kBackwardInflation) runs reversed legs (the same curve with
+//               opposite direction and charge), adds the scattering of each
+//               surface to its prediction there, and is combined with the
+//               forward filtered state as x = x_f + C_f (C_f + C_b)^-1
+//               (x_b - x_f), C = C_f - C_f (C_f + C_b)^-1 C_f.
+#include "ckf_device.hpp"
+#include "ckf_kernels.hpp"
+
+namespace ckf {
+
+constexpr double kBackwardInflation = 100.0;
+constexpr double kPi = 3.14159265358979323846;
+
+struct alignas(16) FitRec {
+  double pp[5], pC[15];  // predicted at the measurement
+  double fp[5], fC[15];  // filtered
+  float F[25];           // the leg into the measurement (row-major)
+  float pad[3];
+};
+static_assert(sizeof(FitRec) == 432, "fit record layout");
+
+size_t fit_workspace_bytes(long long cap_meas) { return (size_t)cap_meas * sizeof(FitRec); }
+
+namespace {
+
+__device__ __forceinline__ void unpack5(const double* c, double M[5][5]) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) M[i][j] = M[j][i] = c[pk(i, j)];
+}
+
+// Cholesky factor of a 5x5 SPD matrix (lower, in place of its lower part);
+// false if not positive definite.
+__device__ __forceinline__ bool chol5(double M[5][5]) {
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    double d = M[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= M[j][k] * M[j][k];
+    if (!(d > 0.0)) return false;
+    const double l = sqrt(d), il = 1.0 / l;
+    M[j][j] = l;
+#pragma unroll
+    for (int i = j + 1; i < 5; ++i) {
+      double s = M[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= M[i][k] * M[j][k];
+      M[i][j] = s * il;
+    }
+  }
+  return true;
+}
+
+// X = (L L^T)^-1 B for the factor in L's lower part (B overwritten by X).
+__device__ __forceinline__ void chol5_solve(const double L[5][5], double B[5][5]) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      double s = B[i][c];
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= L[i][k] * B[k][c];
+      B[i][c] = s / L[i][i];
+    }
+#pragma unroll
+    for (int i = 4; i >= 0; --i) {
+      double s = B[i][c];
+#pragma unroll
+      for (int k = i + 1; k < 5; ++k) s -= L[k][i] * B[k][c];
+      B[i][c] = s / L[i][i];
+    }
+  }
+}
+
+// Reverse the direction of travel on the same surface: (l0, l1, phi + pi,
+// pi - theta, -q/p); the covariance picks up the signs (1, 1, 1, -1, -1).
+__device__ __forceinline__ void flip(double* p, double* C) {
+  p[2] = wrap_phi(p[2] + kPi);
+  p[3] = kPi - p[3];
+  p[4] = -p[4];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j)
+      if ((i >= 3) != (j >= 3)) C[pk(i, j)] = -C[pk(i, j)];
+}
+
+// One leg from module src to module dst: state and covariance replaced by
+// the transported ones, J the bound-to-bound Jacobian.  False if it fails.
+template <bool kMap>
+__device__ bool fit_leg(const GeomDev& g, const FieldDev& F, const CfgDev& cfg, int src, int dst, double* p,
+                        double* C, float J[5][5]) {
+  Module Am, Bm;
+  load_module(g, src, Am);
+  load_module(g, dst, Bm);
+  LegT<kMap ? 5 : 3> L;
+  V3 uA, vA;
+  leg_start(Am, p, L, uA, vA);
+  const V3 origin = ld3(Am.c);
+  const V3 dB = ld3(Bm.c) - origin;
+  float h = cfg.step_max, path = 0.f;
+  LegStats st{0, 0};
+  if (!land<kMap>(L, origin, dB, ld3(Bm.n), F, cfg, h, path, st)) return false;
+  double pn[5];
+  leg_end(L, uA, vA, Bm, dB, field_at<kMap>(F, origin + L.r), p[4], pn, J);
+  bool good = true;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) good = good && isfinite(pn[k]);
+  if (!good) return false;
+  transport_cov(J, C);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) p[k] = pn[k];
+  return true;
+}
+
+__device__ __forceinline__ void fail_track(long long a, long long b, double* out_p, double* out_C, int* ok, int t,
+                                           int code) {
+  for (long long k = a; k < b; ++k) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) out_p[5 * k + i] = NAN;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) out_C[15 * k + i] = NAN;
+  }
+  ok[t] = code;
+}
+
+template <bool kMap, bool kTwo>
+__global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, MeasIn m, SeedsIn s,
+                                            const int* __restrict__ n_tracks_p, int cap_tracks, long long cap_meas,
+                                            const int* __restrict__ off, const int* __restrict__ meas,
+                                            const int* __restrict__ msurf, const int* __restrict__ seed,
+                                            FitRec* __restrict__ ws, double* __restrict__ out_p,
+                                            double* __restrict__ out_C, double* __restrict__ chi2_out,
+                                            int* __restrict__ ok) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_t = min(*n_tracks_p, cap_tracks);
+  if (t >= n_t) return;
+  const long long a = off[t], b = off[t + 1];
+  if (a < 0 || b > cap_meas || b < a) {  // the CSR itself cannot be trusted: touch nothing of it
+    ok[t] = -1;
+    chi2_out[t] = 0.0;
+    return;
+  }
+  const int si = seed[t];
+  bool valid = si >= 0 && si < s.n && s.surface[si] >= 0 && s.surface[si] < g.n_surfaces;
+  for (long long k = a; k < b && valid; ++k)
+    valid = meas[k] >= 0 && meas[k] < m.n_meas && msurf[k] >= 0 && msurf[k] < g.n_surfaces;
+  chi2_out[t] = 0.0;
+  if (!valid) {
+    fail_track(a, b, out_p, out_C, ok, t, -1);
+    return;
+  }
+  if (b == a) {
+    ok[t] = 1;
+    return;
+  }
+  // ---- forward filter
+  double p[5], C[15];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) p[i] = s.params[5ll * si + i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) C[i] = s.cov[15ll * si + i];
+  int cur = s.surface[si];
+  double chi2 = 0.0;
+  for (long long k = a; k < b; ++k) {
+    FitRec& R = ws[k];
+    const int dst = msurf[k];
+    float J[5][5];
+    if (dst != cur) {
+      if (!fit_leg<kMap>(g, F, cfg, cur, dst, p, C, J)) {
+        fail_track(a, b, out_p, out_C, ok, t, 0);
+        return;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) J[i][j] = i == j ? 1.f : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) R.pp[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) R.pC[i] = C[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) R.F[5 * i + j] = J[i][j];
+    const int id = meas[k];
+    const double m0 = m.loc[2ll * id], m1 = m.loc[2ll * id + 1], v0 = m.var[2ll * id], v1 = m.var[2ll * id + 1];
+    chi2 += chi2_of(p, C, m0, m1, v0, v1);
+    double po[5], Co[15];
+    kf_update(p, C, m0, m1, v0, v1, po, Co);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) R.fp[i] = p[i] = po[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) R.fC[i] = C[i] = Co[i];
+    if (cfg.material) {
+      Module M;
+      load_module(g, dst, M);
+      apply_ms(M, cfg.mass, p, C);
+    }
+    cur = dst;
+  }
+  chi2_out[t] = chi2;
+  // ---- the last measurement: smoothed = filtered
+  double xs[5], Cs[15];
+  {
+    const FitRec& R = ws[b - 1];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) xs[i] = out_p[5 * (b - 1) + i] = R.fp[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) Cs[i] = out_C[15 * (b - 1) + i] = R.fC[i];
+  }
+  if (!kTwo) {
+    // ---- RTS
+    for (long long k = b - 2; k >= a; --k) {
+      const FitRec& Rk = ws[k];
+      const FitRec& Rn = ws[k + 1];
+      double fC[5][5], G[5][5], L[5][5];
+      unpack5(Rk.fC, fC);
+      // G = F fC  (so A^T = pC^-1 G)
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int l = 0; l < 5; ++l) acc = fma((double)Rn.F[5 * i + l], fC[l][j], acc);
+          G[i][j] = acc;
+        }
+      unpack5(Rn.pC, L);
+      if (!chol5(L)) {
+        fail_track(a, b, out_p, out_C, ok, t, 0);
+        return;
+      }
+      chol5_solve(L, G);  // G now holds X = A^T
+      double d[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) d[i] = xs[i] - Rn.pp[i];
+      d[2] = wrap_phi(d[2]);
+      double xn[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        double acc = Rk.fp[i];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) acc = fma(G[j][i], d[j], acc);
+        xn[i] = acc;
+      }
+      xn[2] = wrap_phi(xn[2]);
+      // C_k|n = fC + X^T (Cs - pC) X
+      double D[5][5], E[5][5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = i; j < 5; ++j) D[i][j] = D[j][i] = Cs[pk(i, j)] - Rn.pC[pk(i, j)];
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int l = 0; l < 5; ++l) acc = fma(D[i][l], G[l][j], acc);
+          E[i][j] = acc;
+        }
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = i; j < 5; ++j) {
+          double acc = fC[i][j];
+#pragma unroll
+          for (int l = 0; l < 5; ++l) acc = fma(G[l][i], E[l][j], acc);
+          Cs[pk(i, j)] = acc;
+        }
+#pragma unroll
+      for (int i = 0; i < 5; ++i) xs[i] = xn[i];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) out_p[5 * k + i] = xs[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) out_C[15 * k + i] = Cs[i];
+    }
+  } else {
+    // ---- two-filter: backward filter, combined with the forward one
+    double bp[5], bC[15];
+    {
+      const FitRec& R = ws[b - 1];
+      double q[5], Q[15];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) q[i] = R.fp[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) Q[i] = R.fC[i] * kBackwardInflation;
+      const int id = meas[b - 1];
+      kf_update(q, Q, m.loc[2ll * id], m.loc[2ll * id + 1], m.var[2ll * id], m.var[2ll * id + 1], bp, bC);
+    }
+    for (long long k = b - 2; k >= a; --k) {
+      const FitRec& Rk = ws[k];
+      flip(bp, bC);
+      if (msurf[k + 1] != msurf[k]) {
+        float J[5][5];
+        if (!fit_leg<kMap>(g, F, cfg, msurf[k + 1], msurf[k], bp, bC, J)) {
+          fail_track(a, b, out_p, out_C, ok, t, 0);
+          return;
+        }
+      }
+      flip(bp, bC);
+      if (cfg.material) {
+        Module M;
+        load_module(g, msurf[k], M);
+        apply_ms(M, cfg.mass, bp, bC);
+      }
+      // K^T = (fC + bC)^-1 fC
+      double S[5][5], Z[5][5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = i; j < 5; ++j) {
+          S[i][j] = S[j][i] = Rk.fC[pk(i, j)] + bC[pk(i, j)];
+          Z[i][j] = Z[j][i] = Rk.fC[pk(i, j)];
+        }
+      if (!chol5(S)) {
+        fail_track(a, b, out_p, out_C, ok, t, 0);
+        return;
+      }
+      chol5_solve(S, Z);
+      double d[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) d[i] = bp[i] - Rk.fp[i];
+      d[2] = wrap_phi(d[2]);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        double acc = Rk.fp[i];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) acc = fma(Z[j][i], d[j], acc);
+        xs[i] = acc;
+      }
+      xs[2] = wrap_phi(xs[2]);
+      // C = fC - K fC, symmetrised
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = i; j < 5; ++j) {
+          double kij = 0.0, kji = 0.0;
+#pragma unroll
+          for (int l = 0; l < 5; ++l) {
+            kij = fma(Z[l][i], Rk.fC[pk(l, j)], kij);
+            kji = fma(Z[l][j], Rk.fC[pk(l, i)], kji);
+          }
+          Cs[pk(i, j)] = Rk.fC[pk(i, j)] - 0.5 * (kij + kji);
+        }
+#pragma unroll
+      for (int i = 0; i < 5; ++i) out_p[5 * k + i] = xs[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) out_C[15 * k + i] = Cs[i];
+      // the backward filter takes measurement k
+      const int id = meas[k];
+      double q[5], Q[15];
+      kf_update(bp, bC, m.loc[2ll * id], m.loc[2ll * id + 1], m.var[2ll * id], m.var[2ll * id + 1], q, Q);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) bp[i] = q[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) bC[i] = Q[i];
+    }
+  }
+  ok[t] = 1;
+}
+
+}  // namespace
+
+hipError_t launch_fit(const GeomDev& g, const FieldDev& f, const CfgDev& cfg, const MeasIn& m, const SeedsIn& s,
+                      const int* n_tracks, int cap_tracks, long long cap_meas, const int* off, const int* meas,
+                      const int* msurf, const int* seed, bool two_filter, void* ws, double* out_p, double* out_C,
+                      double* chi2, int* ok, hipStream_t st) {
+  if (cap_tracks <= 0) return hipSuccess;
+  const dim3 grid((cap_tracks + 63) / 64), block(64);
+  FitRec* w = static_cast<FitRec*>(ws);
+  if (f.map) {
+    if (two_filter)
+      hipLaunchKernelGGL((k_fit<true, true>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks, cap_meas,
+                         off, meas, msurf, seed, w, out_p, out_C, chi2, ok);
+    else
+      hipLaunchKernelGGL((k_fit<true, false>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks, cap_meas,
+                         off, meas, msurf, seed, w, out_p, out_C, chi2, ok);
+  } else {
+    if (two_filter)
+      hipLaunchKernelGGL((k_fit<false, true>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks, cap_meas,
+                         off, meas, msurf, seed, w, out_p, out_C, chi2, ok);
+    else
+      hipLaunchKernelGGL((k_fit<false, false>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks,
+                         cap_meas, off, meas, msurf, seed, w, out_p, out_C, chi2, ok);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ckf

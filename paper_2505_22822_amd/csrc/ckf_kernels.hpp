@@ -54,6 +54,11 @@ size_t capture_workspace_bytes(int cap_tracks);
 hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* n_tracks, int cap_tracks, const int* off,
                                 const int* msurf, const double* mpar, long long cap_pairs, float* x, int* label,
                                 int* track, long long* counts, void* ws, hipStream_t st);
+size_t fit_workspace_bytes(long long cap_meas);
+hipError_t launch_fit(const GeomDev& g, const FieldDev& f, const CfgDev& cfg, const MeasIn& m, const SeedsIn& s,
+                      const int* n_tracks, int cap_tracks, long long cap_meas, const int* off, const int* meas,
+                      const int* msurf, const int* seed, bool two_filter, void* ws, double* out_p, double* out_C,
+                      double* chi2, int* ok, hipStream_t st);
 hipError_t launch_kf_update(int n, const double* p_in, const double* cov_in, const float* meas, const float* var,
                             double* p_out, double* cov_out, double* chi2, hipStream_t st);
 
