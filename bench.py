@@ -163,6 +163,57 @@ def measure(ckf, geo, fld, b, shape, steps, warmup, stream, model=None, audit=Fa
                 ms_per_step=ms_per_step, tracks_per_s=r["n_tracks"] / (ms_per_step * 1e-3))
 
 
+# Kalman-filter fit, per measurement (FP32 flop, FP64 flop): the forward
+# filter's leg (bound->free, free->bound Jacobian; J C J^T), chi2, update and
+# scattering; the RTS step (F C_k|k, Cholesky of C_k+1|k and its solve for
+# A^T, the state and the A (C' - C) A^T products); the two-filter step (the
+# backward leg, its update and scattering, the Cholesky solve of the
+# combination and its products).  The legs' RKN4 trials are priced at the
+# search's measured trials per leg.
+FIT_FORWARD = (300 + 40, 400 + 15 + 450 + 4)
+FIT_RTS = (0, 1100)
+FIT_TWO = (300 + 40, 400 + 450 + 4 + 780)
+
+
+def measure_fit(ckf, geo, fld, b, shape, stream, reps, trials_per_leg):
+    """Both smoothers on the plain search's tracks of the batch: device time
+    of one ckf_fit launch (HIP events on the launch stream, mean of reps),
+    fitted fraction and the algorithmic rate."""
+    import torch
+    finder = ckf.Finder(geo, fld, b, ckf.config(), ckf.launch(**shape), counters=False, meas_states=True)
+    with torch.cuda.stream(stream):
+        finder.enqueue(stream)
+    r = finder.result()
+    n_t, n_m = r["n_tracks"], len(r["meas"])
+    out = dict(tracks=n_t, measurements=n_m)
+    for name in ("rts", "two_filter"):
+        f = ckf.Fitter.from_finder(finder, name)
+        f.enqueue(stream)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            f.enqueue(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        g = f.result()
+        rk = 505 * trials_per_leg
+        if name == "rts":
+            f32 = n_m * (FIT_FORWARD[0] + rk)
+            f64 = n_m * (FIT_FORWARD[1] + FIT_RTS[1])
+        else:
+            f32 = n_m * (FIT_FORWARD[0] + FIT_TWO[0] + 2 * rk)
+            f64 = n_m * (FIT_FORWARD[1] + FIT_TWO[1])
+        frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64) / (ms * 1e-3)
+        out[name] = dict(tracks_per_s=round(n_t / (ms * 1e-3), 1), kernel_ms=round(ms, 4),
+                         fitted=round(float(np.mean(g["ok"] == 1)), 6),
+                         roofline=dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3),
+                                       peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=round(frac, 5), traffic=None,
+                                       kernel="k_fit", fp32_flop=int(f32), fp64_flop=int(f64)))
+    return out
+
+
 def roofline_of(m, form, shape):
     c = dict(m["counters"])
     f32 = sum(c.get(k, 0) * UNIT_FLOPS[k][0] for k in UNIT_FLOPS)
@@ -261,6 +312,13 @@ def main():
     cyc_plain = {k: plain["counters"].pop(k) for k in CYCLE_KEYS}
     say(phase_line({**plain["counters"], **cyc_plain}, "plain"))
 
+    c0 = plain["counters"]
+    fit = measure_fit(ckf, geo, fld, b, shape_plain, stream, max(3, args.steps // 4),
+                      c0["rk_trials"] / max(1, c0["legs"]))
+    say(f"# fit of the plain search's {fit['tracks']} tracks ({fit['measurements']} measurements): "
+        + "; ".join(f"{k} {fit[k]['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel {fit[k]['kernel_ms']:.3f} ms, "
+                    f"fitted {fit[k]['fitted']:.5f}" for k in ("rts", "two_filter")))
+
     learned_info = None
     head = plain
     if not args.no_learned:
@@ -324,7 +382,7 @@ def main():
                 roofline=roofline_of(head, "learned" if learned_info else "plain",
                                      learned_info["launch"] if learned_info else shape_plain),
                 plain_roofline=roofline_of(plain, "plain", shape_plain),
-                cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
+                fit=fit, cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
     print(json.dumps(line))
 
 
