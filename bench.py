@@ -48,7 +48,12 @@ MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 
 # by (form, grid, seeds per group, waves per SIMD): the pools make the
 # traffic depend on the launch shape.  Source: profiles/k_ckf_mu200x64_hbm_traffic.md;
 # an entry is dropped when its kernel changes.
-MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.56e9}
+MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.56e9, ("plain", 3072, 48, 3): 29.56e9,
+                    ("learned", 2048, 48, 2): 24.57e9, ("learned", 4096, 48, 2): 24.57e9}
+# HBM bytes per k_fit launch on the 64 x mu=200 batch's plain-search tracks
+# (560,806 tracks, 4,620,871 measurements), same counters and factors.
+# Source: profiles/k_fit_mu200x64.md.
+FIT_TRAFFIC = {(560806, 4620871): {"rts": 7.571e9, "two_filter": 7.019e9}}
 PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
 PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
 PEAK_BF16 = 2.5e15    # MI355X dense bf16 MFMA, FLOP/s
@@ -206,11 +211,13 @@ def measure_fit(ckf, geo, fld, b, shape, stream, reps, trials_per_leg):
             f32 = n_m * (FIT_FORWARD[0] + FIT_TWO[0] + 2 * rk)
             f64 = n_m * (FIT_FORWARD[1] + FIT_TWO[1])
         frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64) / (ms * 1e-3)
+        traffic = FIT_TRAFFIC.get((n_t, n_m), {}).get(name)
         out[name] = dict(tracks_per_s=round(n_t / (ms * 1e-3), 1), kernel_ms=round(ms, 4),
                          fitted=round(float(np.mean(g["ok"] == 1)), 6),
                          roofline=dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3),
-                                       peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=round(frac, 5), traffic=None,
-                                       kernel="k_fit", fp32_flop=int(f32), fp64_flop=int(f64)))
+                                       peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=round(frac, 5), traffic=traffic,
+                                       kernel="k_fit", fp32_flop=int(f32), fp64_flop=int(f64),
+                                       hbm_tb_per_s=round(traffic / (ms * 1e-3) / 1e12, 3) if traffic else None))
     return out
 
 

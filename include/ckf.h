@@ -379,6 +379,32 @@ ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurem
                    int32_t smoother, void* workspace, size_t workspace_bytes, double* params, double* cov,
                    double* chi2, int32_t* ok, void* stream);
 
+/* Greedy ambiguity resolution of found tracks by shared measurements (paper
+ * section 4: the stage after track finding that removes duplicate and fake
+ * tracks).  A measurement is shared when more than one surviving track holds
+ * it; a surviving track is bad when more than max_shared of its
+ * measurements are shared.  While a bad track exists, the bad track with the
+ * largest shared fraction s/n is removed (ties: the larger chi2/ndf taken in
+ * FP32, then the larger track index), and the shares are recounted.  The
+ * result equals that sequential definition; the library reaches it in
+ * parallel rounds that each remove every bad track whose key beats all bad
+ * tracks it shares a measurement with.
+ * Tracks (device memory, ckf_find's layout): n_tracks (device int32, at
+ * most cap_tracks used), offsets [cap_tracks+1] into meas [cap_meas],
+ * chi2 and ndf [cap_tracks]; measurement ids must lie in [0, n_meas).
+ * keep [cap_tracks] (device) receives 1 kept, 0 removed, -1 for a track
+ * whose offsets or ids are out of range (it takes no part).  rounds (host,
+ * may be NULL) receives the number of parallel rounds.  workspace: at least
+ * ckf_resolve_workspace_size(cap_tracks, n_meas) bytes (CKF_ERR_CAPACITY if
+ * smaller).  SYNCHRONOUS: the call waits on `stream` once per round (it
+ * reads the number of bad tracks); it allocates nothing.  n_meas above
+ * 2^31 - 1 gives CKF_ERR_NOT_SUPPORTED. */
+ckf_status ckf_resolve_workspace_size(int32_t cap_tracks, int64_t n_meas, size_t* bytes);
+ckf_status ckf_resolve(const int32_t* n_tracks, int32_t cap_tracks, int64_t cap_meas, const int32_t* offsets,
+                       const int32_t* meas, int64_t n_meas, const double* chi2, const int32_t* ndf,
+                       int32_t max_shared, void* workspace, size_t workspace_bytes, int32_t* keep, int32_t* rounds,
+                       void* stream);
+
 /* Device workspace of ckf_capture_pairs for cap_tracks tracks: bytes it needs. */
 ckf_status ckf_capture_workspace_size(int32_t cap_tracks, size_t* bytes);
 

@@ -17,7 +17,7 @@ from . import _abi
 from ._abi import COUNTER_NAMES
 
 __all__ = ["Geometry", "UniformField", "FieldMap", "Model", "config", "find", "propagate_batch", "kf_update_batch",
-           "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "Fitter", "CkfError"]
+           "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "Fitter", "resolve", "CkfError"]
 
 
 class CkfError(RuntimeError):
@@ -453,6 +453,29 @@ class Fitter:
         return dict(n_tracks=nt, offsets=off, params=self.params[:nm].cpu().numpy(),
                     cov=self.cov[:nm].cpu().numpy(), chi2=self.chi2[:nt].cpu().numpy(),
                     ok=self.ok[:nt].cpu().numpy())
+
+
+def resolve(tracks: dict, n_meas: int, max_shared=1, stream=None, workspace=None):
+    """Greedy ambiguity resolution (ckf_resolve) of found tracks held as
+    device tensors in ckf_find's layout (n_tracks, offsets, meas, chi2, ndf;
+    a Finder's .out).  Returns (keep device tensor [cap_tracks] int32:
+    1 kept, 0 removed, -1 invalid; number of parallel rounds).  Synchronous."""
+    import torch
+    lib = _abi.load()
+    dev = tracks["offsets"].device
+    cap_tracks = int(tracks["offsets"].numel()) - 1
+    cap_meas = int(tracks["meas"].numel())
+    if workspace is None:
+        nb = C.c_size_t(0)
+        _check(lib.ckf_resolve_workspace_size(cap_tracks, int(n_meas), C.byref(nb)), "ckf_resolve_workspace_size")
+        workspace = torch.empty(max(1, int(nb.value)), dtype=torch.uint8, device=dev)
+    keep = torch.zeros(max(1, cap_tracks), dtype=torch.int32, device=dev)
+    rounds = C.c_int32(0)
+    _check(lib.ckf_resolve(_ptr(tracks["n_tracks"]), cap_tracks, cap_meas, _ptr(tracks["offsets"]),
+                           _ptr(tracks["meas"]), int(n_meas), _ptr(tracks["chi2"]), _ptr(tracks["ndf"]),
+                           int(max_shared), _ptr(workspace), workspace.numel(), _ptr(keep), C.byref(rounds),
+                           _stream_handle(stream)), "ckf_resolve")
+    return keep[:cap_tracks], int(rounds.value)
 
 
 def find(geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, stream=None, retries=3, model=None,

@@ -928,6 +928,33 @@ ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurem
   return CKF_OK;
 }
 
+ckf_status ckf_resolve_workspace_size(int32_t cap_tracks, int64_t n_meas, size_t* bytes) {
+  if (cap_tracks < 0 || n_meas < 0 || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "resolve_workspace_size: bad argument");
+  *bytes = ckf::resolve_workspace_bytes(cap_tracks, n_meas);
+  return CKF_OK;
+}
+
+ckf_status ckf_resolve(const int32_t* n_tracks, int32_t cap_tracks, int64_t cap_meas, const int32_t* offsets,
+                       const int32_t* meas, int64_t n_meas, const double* chi2, const int32_t* ndf,
+                       int32_t max_shared, void* workspace, size_t workspace_bytes, int32_t* keep, int32_t* rounds,
+                       void* stream) {
+  if (cap_tracks < 0 || cap_meas < 0 || n_meas < 0 || max_shared < 0)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "resolve: negative size or max_shared");
+  if (n_meas > INT32_MAX) return fail(CKF_ERR_NOT_SUPPORTED, "resolve: more than 2^31 - 1 measurements");
+  if (cap_tracks > 0 && (!n_tracks || !offsets || !chi2 || !ndf || !keep || (cap_meas > 0 && !meas)))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "resolve: NULL array");
+  if (!workspace || workspace_bytes < ckf::resolve_workspace_bytes(cap_tracks, n_meas))
+    return fail(CKF_ERR_CAPACITY, "resolve: workspace too small");
+  int r = 0;
+  bool conv = true;
+  HIP_TRY(ckf::run_resolve(n_tracks, cap_tracks, cap_meas, offsets, meas, n_meas, chi2, ndf, max_shared, workspace,
+                           keep, 100000, &r, &conv, static_cast<hipStream_t>(stream)),
+          "ambiguity resolution");
+  if (rounds) *rounds = r;
+  if (!conv) return fail(CKF_ERR_CAPACITY, "resolve: round limit reached");
+  return CKF_OK;
+}
+
 ckf_status ckf_capture_workspace_size(int32_t cap_tracks, size_t* bytes) {
   if (cap_tracks < 0 || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "capture_workspace_size: bad argument");
   *bytes = ckf::capture_workspace_bytes(cap_tracks);

@@ -55,6 +55,10 @@ hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* 
                                 const int* msurf, const double* mpar, long long cap_pairs, float* x, int* label,
                                 int* track, long long* counts, void* ws, hipStream_t st);
 size_t fit_workspace_bytes(long long cap_meas);
+size_t resolve_workspace_bytes(int cap_tracks, long long n_meas);
+hipError_t run_resolve(const int* n_tracks, int cap_tracks, long long cap_meas, const int* off, const int* meas,
+                       long long n_meas, const double* chi2, const int* ndf, int max_shared, void* ws, int* keep,
+                       int max_rounds, int* rounds, bool* converged, hipStream_t st);
 hipError_t launch_fit(const GeomDev& g, const FieldDev& f, const CfgDev& cfg, const MeasIn& m, const SeedsIn& s,
                       const int* n_tracks, int cap_tracks, long long cap_meas, const int* off, const int* meas,
                       const int* msurf, const int* seed, bool two_filter, void* ws, double* out_p, double* out_C,
