@@ -20,6 +20,7 @@ measured with HIP events on its stream), and the oracle timed on the host's
 cores on a bounded sample of the same events.
 """
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -218,7 +219,75 @@ def measure_fit(ckf, geo, fld, b, shape, stream, reps, trials_per_leg):
                                        peak=PEAK_FP32 / 1e12, unit="TFLOP/s", frac=round(frac, 5), traffic=traffic,
                                        kernel="k_fit", fp32_flop=int(f32), fp64_flop=int(f64),
                                        hbm_tb_per_s=round(traffic / (ms * 1e-3) / 1e12, 3) if traffic else None))
+    out["_finder"] = finder
     return out
+
+
+def _majority(ev, r):
+    """Per track with a particle hit: (track, majority particle, N, Nt, Np)."""
+    nt, off, meas = int(r["n_tracks"]), r["offsets"], r["meas"]
+    tid = np.repeat(np.arange(nt), np.diff(off))
+    part = ev.meas_particle[meas]
+    ok = part >= 0
+    P = int(ev.particle_pt.shape[0]) + 1
+    uk, cnt = np.unique(tid[ok].astype(np.int64) * P + part[ok], return_counts=True)
+    t_of, p_of = uk // P, uk % P
+    order = np.lexsort((-cnt, t_of))
+    first = order[np.r_[True, t_of[order][1:] != t_of[order][:-1]]] if len(order) else order
+    tr, maj, N = t_of[first], p_of[first], cnt[first]
+    return tr, maj, N, np.diff(off)[tr], ev.particle_nhits[maj]
+
+
+def track_rates(ev, r, keep=None):
+    """Paper section 4: fake tracks (no particle double-matched) and
+    duplicate tracks (double-matched to a particle that another kept track
+    already matches), as fractions of the kept tracks."""
+    nt = int(r["n_tracks"])
+    kept = np.ones(nt, bool) if keep is None else (keep[:nt] == 1)
+    tr, maj, N, Nt, Np = _majority(ev, r)
+    good = (N > Nt / 2) & (N > Np / 2) & kept[tr]
+    n = int(kept.sum())
+    matched = int(good.sum())
+    distinct = int(np.unique(maj[good]).size)
+    return dict(tracks=n, fake_rate=round((n - matched) / max(1, n), 6),
+                duplicate_rate=round((matched - distinct) / max(1, n), 6))
+
+
+def kept_tracks(r, keep):
+    """The result dict restricted to the kept tracks (for the efficiency)."""
+    nt = int(r["n_tracks"])
+    k = np.nonzero(keep[:nt] == 1)[0]
+    n = np.diff(r["offsets"])[k]
+    off = np.zeros(len(k) + 1, np.int64)
+    off[1:] = np.cumsum(n)
+    idx = np.concatenate([np.arange(r["offsets"][t], r["offsets"][t + 1]) for t in k]) if len(k) else np.zeros(0, int)
+    return dict(n_tracks=len(k), offsets=off, meas=r["meas"][idx], seed=r["seed"][k])
+
+
+def measure_resolve(ckf, finder, ev, stream, reps=3):
+    """Ambiguity resolution of a finder's tracks: wall time of the
+    (synchronous) call, rounds, removed tracks, fake and duplicate rates and
+    efficiency before and after."""
+    import torch
+    r = finder.result()
+    nb = C.c_size_t(0)
+    from paper_2505_22822_amd import _abi
+    cap = int(finder.out["offsets"].numel()) - 1
+    assert _abi.load().ckf_resolve_workspace_size(cap, ev.n_meas, C.byref(nb)) == 0
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=finder.out["offsets"].device)
+    times = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep, rounds = ckf.resolve(finder.out, ev.n_meas, stream=stream, workspace=ws)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    keep = keep.cpu().numpy()
+    before, after = track_rates(ev, r), track_rates(ev, r, keep)
+    return dict(ms=round(float(np.mean(times[1:])), 4), rounds=rounds, tracks_in=int(r["n_tracks"]),
+                removed=int(np.sum(keep[:r["n_tracks"]] == 0)), before=before, after=after,
+                efficiency_before=round(efficiency(ev, r), 5), efficiency_after=round(efficiency(ev, kept_tracks(r, keep)), 5),
+                note="wall time of the synchronous call (one stream synchronisation per round)")
 
 
 def roofline_of(m, form, shape):
@@ -325,6 +394,12 @@ def main():
     say(f"# fit of the plain search's {fit['tracks']} tracks ({fit['measurements']} measurements): "
         + "; ".join(f"{k} {fit[k]['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel {fit[k]['kernel_ms']:.3f} ms, "
                     f"fitted {fit[k]['fitted']:.5f}" for k in ("rts", "two_filter")))
+    amb = measure_resolve(ckf, fit.pop("_finder"), batch, stream)
+    say(f"# ambiguity resolution of the plain search's tracks: {amb['ms']:.2f} ms, {amb['rounds']} rounds, "
+        f"{amb['removed']} of {amb['tracks_in']} removed; fake rate {amb['before']['fake_rate']:.5f} -> "
+        f"{amb['after']['fake_rate']:.5f}, duplicate rate {amb['before']['duplicate_rate']:.5f} -> "
+        f"{amb['after']['duplicate_rate']:.5f}, efficiency {amb['efficiency_before']:.4f} -> "
+        f"{amb['efficiency_after']:.4f}")
 
     learned_info = None
     head = plain
@@ -389,7 +464,7 @@ def main():
                 roofline=roofline_of(head, "learned" if learned_info else "plain",
                                      learned_info["launch"] if learned_info else shape_plain),
                 plain_roofline=roofline_of(plain, "plain", shape_plain),
-                fit=fit, cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
+                fit=fit, ambiguity=amb, cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
     print(json.dumps(line))
 
 
