@@ -129,17 +129,18 @@ def cpu_baseline(batch, n_events):
                        f"{r['n_tracks']} tracks) in {dt:.2f} s")
 
 
-def measure(ckf, geo, fld, b, shape, steps, warmup, stream, model=None, audit=False):
+def measure(ckf, geo, fld, b, shape, steps, warmup, stream, model=None, audit=False, cfg=None):
     """Counting run (work units), eager runs timed by the library's kernel
     timer, then the hipGraph-captured call replayed `steps` times."""
     import torch
     lc = lambda timer=None: ckf.launch(shape["grid"], shape["seeds_per_group"], 0, timer, shape["waves_per_simd"])
-    counting = ckf.Finder(geo, fld, b, ckf.config(), lc(), counters=True, model=model, seed_flags=audit)
+    cfg = cfg if cfg is not None else ckf.config()
+    counting = ckf.Finder(geo, fld, b, cfg, lc(), counters=True, model=model, seed_flags=audit)
     counting.enqueue(stream)
     rc = counting.result()
     del counting
     timer = ckf.KernelTimer()
-    eager = ckf.Finder(geo, fld, b, ckf.config(), lc(timer), counters=False, model=model)
+    eager = ckf.Finder(geo, fld, b, cfg, lc(timer), counters=False, model=model)
     kernel_ms = []
     for i in range(warmup + steps):
         eager.enqueue(stream)
@@ -149,7 +150,7 @@ def measure(ckf, geo, fld, b, shape, steps, warmup, stream, model=None, audit=Fa
     r = eager.result()
     assert r["n_tracks"] == rc["n_tracks"] and np.array_equal(r["meas"], rc["meas"]), "variants disagree"
     del eager
-    finder = ckf.Finder(geo, fld, b, ckf.config(), lc(), counters=False, model=model)
+    finder = ckf.Finder(geo, fld, b, cfg, lc(), counters=False, model=model)
     finder.capture(stream)
     for _ in range(warmup):
         finder.launch_graph(stream)
@@ -333,6 +334,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="plain form only")
     ap.add_argument("--train-events", type=int, default=26)
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--min-prob", type=float, default=0.98,
+                    help="learned form: summed top-3 probability above which the proposal is used (0.98: the "
+                         "threshold at which its efficiency stays within 0.5 %% of the plain form's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -422,7 +426,8 @@ def main():
         model = ckf.Model(params)
         shape_learned = pick(model)
         say(f"# learned launch shape {shape_learned}")
-        lm = measure(ckf, geo, fld, b, shape_learned, args.steps, args.warmup, stream, model=model, audit=True)
+        lm = measure(ckf, geo, fld, b, shape_learned, args.steps, args.warmup, stream, model=model, audit=True,
+                     cfg=ckf.config(learned_min_prob=args.min_prob))
         eff_learned = efficiency(batch, lm["result"])
         c = lm["counters"]
         say(f"# learned: {lm['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel {lm['kernel_ms']:.3f} ms, "
@@ -432,6 +437,7 @@ def main():
         cyc_learned = {k: lm["counters"].pop(k) for k in CYCLE_KEYS}
         say(phase_line({**lm["counters"], **cyc_learned}, "learned"))
         learned_info = dict(tracks_per_s=round(lm["tracks_per_s"], 1), ms_per_step=round(lm["ms_per_step"], 4),
+                            min_prob=args.min_prob,
                             efficiency=round(eff_learned, 5), launch=shape_learned,
                             proposals=c["proposals"], network_rows=c["mlp_rows"], navigations=c["navigations"],
                             listing_misses=c["proposal_misses"], seeds_affected=int(lm["seed_flags"].sum()),
