@@ -379,6 +379,43 @@ ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurem
                    int32_t smoother, void* workspace, size_t workspace_bytes, double* params, double* cov,
                    double* chi2, int32_t* ok, void* stream);
 
+/* Activated detector cells (device memory) in readout order: grouped by
+ * (event, module) row like the measurements, then by row c1 and column c0
+ * inside a module (strictly increasing (c1, c0) within a module). */
+typedef struct ckf_cells {
+  int32_t n_events;
+  int32_t n_surfaces;        /* must equal the geometry's */
+  int64_t n_cells;
+  const int32_t* offsets;    /* [n_events*n_surfaces+1] */
+  const int32_t* c0;         /* [n_cells] column */
+  const int32_t* c1;         /* [n_cells] row */
+  const float* q;            /* [n_cells] charge (> 0) */
+} ckf_cells;
+
+#define CKF_CLUSTER_BAD_OFFSETS 1 /* a row's offsets out of order or beyond n_cells (row skipped) */
+#define CKF_CLUSTER_UNSORTED 2    /* cells of a module not in readout order (its clusters are not defined) */
+
+/* Cell clustering and measurement formation (paper section 2: connected
+ * component analysis of the activated cells, weighted centroids as
+ * measurements, spacepoints in global coordinates).  Two cells of a module
+ * are connected when |dc0| <= 1 and |dc1| <= 1; a cluster is a connected
+ * component, named by its first cell in readout order, and a module's
+ * clusters come out in that order.  Measurement: the charge-weighted mean of
+ * the cell centres ((c + 1/2) pitch - half length, FP64 sums in readout
+ * order, stored FP32), variances pitch^2 / 12.  pitch [n_surfaces][2]
+ * (device) gives each module's cell size in mm.  Outputs (device,
+ * caller-owned, sized for n_cells clusters at most): meas_offsets
+ * [n_events*n_surfaces+1] (the layout of ckf_measurements), loc and var
+ * [n_cells][2], spacepoints [n_cells][3] or NULL (centre + loc0 u + loc1 v),
+ * cell_cluster [n_cells] or NULL (the measurement index of every cell),
+ * status [1] (device, cleared by the call): CKF_CLUSTER_* bits.
+ * workspace: at least ckf_cluster_workspace_size bytes (CKF_ERR_CAPACITY).
+ * Asynchronous on `stream`; allocates nothing. */
+ckf_status ckf_cluster_workspace_size(const ckf_cells* cells, size_t* bytes);
+ckf_status ckf_cluster(const ckf_geometry* g, const ckf_cells* cells, const float* pitch, void* workspace,
+                       size_t workspace_bytes, int32_t* meas_offsets, float* loc, float* var, float* spacepoints,
+                       int32_t* cell_cluster, int32_t* status, void* stream);
+
 /* Greedy ambiguity resolution of found tracks by shared measurements (paper
  * section 4: the stage after track finding that removes duplicate and fake
  * tracks).  A measurement is shared when more than one surviving track holds

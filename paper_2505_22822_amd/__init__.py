@@ -17,7 +17,8 @@ from . import _abi
 from ._abi import COUNTER_NAMES
 
 __all__ = ["Geometry", "UniformField", "FieldMap", "Model", "config", "find", "propagate_batch", "kf_update_batch",
-           "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "Fitter", "resolve", "CkfError"]
+           "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "Fitter", "resolve", "CellBatch", "cluster",
+           "CkfError"]
 
 
 class CkfError(RuntimeError):
@@ -453,6 +454,82 @@ class Fitter:
         return dict(n_tracks=nt, offsets=off, params=self.params[:nm].cpu().numpy(),
                     cov=self.cov[:nm].cpu().numpy(), chi2=self.chi2[:nt].cpu().numpy(),
                     ok=self.ok[:nt].cpu().numpy())
+
+
+@dataclass
+class CellBatch:
+    """Device-resident activated cells in readout order (torch tensors)."""
+    n_events: int
+    n_surfaces: int
+    offsets: "object"   # int32 [E*S+1]
+    c0: "object"        # int32 [n]
+    c1: "object"        # int32 [n]
+    q: "object"         # float32 [n]
+
+    @staticmethod
+    def from_cells(c, device="cuda"):
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+        return CellBatch(c.n_events, c.n_surfaces, t(c.offsets, torch.int32), t(c.c0, torch.int32),
+                         t(c.c1, torch.int32), t(c.q, torch.float32))
+
+    @property
+    def n_cells(self):
+        return int(self.c0.shape[0])
+
+
+class Clusterer:
+    """Workspace and outputs of repeated ckf_cluster calls on one cell-batch
+    shape; pitch is a [n_surfaces, 2] float32 device tensor."""
+
+    def __init__(self, geometry: Geometry, cells: CellBatch, pitch, spacepoints=True, cell_cluster=True):
+        import torch
+        self.geometry, self.cells, self.pitch = geometry, cells, pitch
+        dev = cells.c0.device
+        self._desc = _abi.CellsDesc(cells.n_events, cells.n_surfaces, cells.n_cells, _ptr(cells.offsets),
+                                    _ptr(cells.c0), _ptr(cells.c1), _ptr(cells.q))
+        nb = C.c_size_t(0)
+        _check(_abi.load().ckf_cluster_workspace_size(C.byref(self._desc), C.byref(nb)), "ckf_cluster_workspace_size")
+        self.workspace = torch.empty(max(1, int(nb.value)), dtype=torch.uint8, device=dev)
+        n = max(1, cells.n_cells)
+        z = lambda shape, dt: torch.zeros(shape, dtype=dt, device=dev)
+        self.offsets = z(cells.n_events * cells.n_surfaces + 1, torch.int32)
+        self.loc, self.var = z((n, 2), torch.float32), z((n, 2), torch.float32)
+        self.spacepoints = z((n, 3), torch.float32) if spacepoints else None
+        self.cell_cluster = z(n, torch.int32) if cell_cluster else None
+        self.status = z(1, torch.int32)
+
+    def enqueue(self, stream=None):
+        _check(_abi.load().ckf_cluster(self.geometry.handle, C.byref(self._desc), _ptr(self.pitch),
+                                       _ptr(self.workspace), self.workspace.numel(), _ptr(self.offsets),
+                                       _ptr(self.loc), _ptr(self.var), _ptr(self.spacepoints),
+                                       _ptr(self.cell_cluster), _ptr(self.status), _stream_handle(stream)),
+               "ckf_cluster")
+
+    def measurements(self):
+        """The clusters as a Batch-style measurement set (device tensors):
+        (offsets, loc, var) views sized to the number of clusters."""
+        m = int(self.offsets[-1].item())
+        return self.offsets, self.loc[:m], self.var[:m]
+
+    def result(self):
+        import torch
+        torch.cuda.synchronize()
+        m = int(self.offsets[-1].item())
+        out = dict(offsets=self.offsets.cpu().numpy(), loc=self.loc[:m].cpu().numpy(), var=self.var[:m].cpu().numpy(),
+                   status=int(self.status.item()), n_meas=m)
+        if self.spacepoints is not None:
+            out["spacepoints"] = self.spacepoints[:m].cpu().numpy()
+        if self.cell_cluster is not None:
+            out["cell_cluster"] = self.cell_cluster[:self.cells.n_cells].cpu().numpy()
+        return out
+
+
+def cluster(geometry: Geometry, cells: CellBatch, pitch, stream=None):
+    """One ckf_cluster call; returns its result (numpy)."""
+    c = Clusterer(geometry, cells, pitch)
+    c.enqueue(stream)
+    return c.result()
 
 
 def resolve(tracks: dict, n_meas: int, max_shared=1, stream=None, workspace=None):

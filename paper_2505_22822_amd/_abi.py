@@ -34,6 +34,11 @@ class Config(C.Structure):
                 ("learned_min_prob", F64), ("learned_topk", I32)]
 
 
+class CellsDesc(C.Structure):
+    _fields_ = [("n_events", I32), ("n_surfaces", I32), ("n_cells", I64), ("offsets", VP), ("c0", VP), ("c1", VP),
+                ("q", VP)]
+
+
 class Measurements(C.Structure):
     _fields_ = [("n_events", I32), ("n_surfaces", I32), ("n_meas", I64), ("offsets", VP), ("loc", VP),
                 ("var", VP)]
@@ -86,6 +91,8 @@ SIGNATURES = {
     "ckf_fit_workspace_size": (I32, [I64, C.POINTER(C.c_size_t)]),
     "ckf_fit": (I32, [VP, VP, C.POINTER(Measurements), C.POINTER(Seeds), C.POINTER(Config), VP, I32, I64, VP, VP,
                       VP, VP, I32, VP, C.c_size_t, VP, VP, VP, VP, VP]),
+    "ckf_cluster_workspace_size": (I32, [C.POINTER(CellsDesc), C.POINTER(C.c_size_t)]),
+    "ckf_cluster": (I32, [VP, C.POINTER(CellsDesc), VP, VP, C.c_size_t, VP, VP, VP, VP, VP, VP, VP]),
     "ckf_resolve_workspace_size": (I32, [I32, I64, C.POINTER(C.c_size_t)]),
     "ckf_resolve": (I32, [VP, I32, I64, VP, VP, I64, VP, VP, I32, VP, C.c_size_t, VP, C.POINTER(I32), VP]),
     "ckf_capture_workspace_size": (I32, [I32, C.POINTER(C.c_size_t)]),

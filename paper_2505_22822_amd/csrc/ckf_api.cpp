@@ -928,6 +928,34 @@ ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurem
   return CKF_OK;
 }
 
+ckf_status ckf_cluster_workspace_size(const ckf_cells* c, size_t* bytes) {
+  if (!c || !bytes || c->n_events < 0 || c->n_surfaces < 0 || c->n_cells < 0)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "cluster_workspace_size: bad argument");
+  *bytes = ckf::cluster_workspace_bytes((long long)c->n_events * c->n_surfaces, c->n_cells);
+  return CKF_OK;
+}
+
+ckf_status ckf_cluster(const ckf_geometry* g, const ckf_cells* c, const float* pitch, void* workspace,
+                       size_t workspace_bytes, int32_t* meas_offsets, float* loc, float* var, float* spacepoints,
+                       int32_t* cell_cluster, int32_t* status, void* stream) {
+  if (!g || !c || !pitch || !meas_offsets || !status) return fail(CKF_ERR_INVALID_ARGUMENT, "cluster: NULL argument");
+  if (c->n_events < 0 || c->n_cells < 0) return fail(CKF_ERR_INVALID_ARGUMENT, "cluster: negative size");
+  if (c->n_surfaces != g->dev.n_surfaces) return fail(CKF_ERR_INVALID_ARGUMENT, "cluster: n_surfaces differs from geometry");
+  if (c->n_cells > INT32_MAX || (long long)c->n_events * c->n_surfaces >= INT32_MAX)
+    return fail(CKF_ERR_NOT_SUPPORTED, "cluster: more than 2^31 - 1 cells or rows");
+  if (c->n_events > 0 && !c->offsets) return fail(CKF_ERR_INVALID_ARGUMENT, "cluster: NULL offsets");
+  if (c->n_cells > 0 && (!c->c0 || !c->c1 || !c->q || !loc || !var))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "cluster: NULL cell or output array");
+  if (!workspace || workspace_bytes < ckf::cluster_workspace_bytes((long long)c->n_events * c->n_surfaces, c->n_cells))
+    return fail(CKF_ERR_CAPACITY, "cluster: workspace too small");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const ckf::CellsIn ci{c->n_events, c->n_surfaces, c->n_cells, c->offsets, c->c0, c->c1, c->q};
+  HIP_TRY(ckf::launch_cluster(ci, g->dev, pitch, workspace, meas_offsets, loc, var, spacepoints, cell_cluster, status,
+                              hs),
+          "launch the clustering");
+  return CKF_OK;
+}
+
 ckf_status ckf_resolve_workspace_size(int32_t cap_tracks, int64_t n_meas, size_t* bytes) {
   if (cap_tracks < 0 || n_meas < 0 || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "resolve_workspace_size: bad argument");
   *bytes = ckf::resolve_workspace_bytes(cap_tracks, n_meas);

@@ -20,6 +20,15 @@ struct SeedsIn {
   const double* cov;
 };
 
+struct CellsIn {
+  int n_events, n_surfaces;
+  long long n_cells;
+  const int* offsets;
+  const int* c0;
+  const int* c1;
+  const float* q;
+};
+
 struct CkfArgs {
   GeomDev g;
   FieldDev f;
@@ -55,6 +64,9 @@ hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* 
                                 const int* msurf, const double* mpar, long long cap_pairs, float* x, int* label,
                                 int* track, long long* counts, void* ws, hipStream_t st);
 size_t fit_workspace_bytes(long long cap_meas);
+size_t cluster_workspace_bytes(long long rows, long long n_cells);
+hipError_t launch_cluster(const CellsIn& c, const GeomDev& g, const float* pitch, void* ws, int* moff, float* loc,
+                          float* var, float* sp, int* cell_cluster, int* status, hipStream_t st);
 size_t resolve_workspace_bytes(int cap_tracks, long long n_meas);
 hipError_t run_resolve(const int* n_tracks, int cap_tracks, long long cap_meas, const int* off, const int* meas,
                        long long n_meas, const double* chi2, const int* ndf, int max_shared, void* ws, int* keep,

@@ -44,8 +44,8 @@ def test_struct_layouts_match_header(lib):
 #include <stdio.h>
 #include "ckf.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(ckf_geometry_desc), sizeof(ckf_config), sizeof(ckf_measurements),
-         sizeof(ckf_seeds), sizeof(ckf_tracks), sizeof(ckf_launch));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(ckf_geometry_desc), sizeof(ckf_config), sizeof(ckf_measurements),
+         sizeof(ckf_seeds), sizeof(ckf_tracks), sizeof(ckf_launch), sizeof(ckf_cells));
   return 0;
 }
 '''
@@ -56,7 +56,7 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
         sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     mine = [C.sizeof(t) for t in (_abi.GeometryDesc, _abi.Config, _abi.Measurements, _abi.Seeds, _abi.Tracks,
-                                  _abi.Launch)]
+                                  _abi.Launch, _abi.CellsDesc)]
     assert sizes == mine
 
 

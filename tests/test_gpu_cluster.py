@@ -1,0 +1,139 @@
+"""Cell clustering and measurement formation on the GPU (ckf_cluster) against
+the oracle: the same clusters (every cell's measurement index) and
+measurements on a mu = 20 event, and on sampled modules of an 8 x mu = 200
+batch; the measurements fed into the track finder; edge cases."""
+import sys
+
+import numpy as np
+import pytest
+
+from synth import concat_events, make_event
+from synth.cells import cell_grid, concat_cells, make_cells
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ckf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_22822_amd as ckf
+    return ckf
+
+
+def _run(ckf, det, cells):
+    import torch
+    geo = ckf.Geometry(det.as_arrays())
+    _, pitch = cell_grid(det)
+    cl = ckf.Clusterer(geo, ckf.CellBatch.from_cells(cells), torch.as_tensor(pitch, device="cuda"))
+    cl.enqueue()
+    return cl, cl.result()
+
+
+def test_cluster_matches_oracle(ckf, det_dense):
+    """Clusters and measurements of a mu = 20 event: offsets and every cell's
+    measurement index identical; centroids within one float32 rounding of
+    the oracle's FP64 value; variances pitch^2/12; spacepoints to 1e-4 mm."""
+    from oracle import clustering as OC
+    ev = make_event(det_dense, 6000, mu=20)
+    cells = make_cells(det_dense, ev, 1)
+    _, pitch = cell_grid(det_dense)
+    ref = OC.cluster(cells, det_dense.as_arrays(), pitch)
+    _, got = _run(ckf, det_dense, cells)
+    _say(f"# clustering: {cells.n_cells} cells, {got['n_meas']} clusters (oracle {len(ref['size'])})")
+    assert got["status"] == 0
+    np.testing.assert_array_equal(got["offsets"], ref["offsets"])
+    np.testing.assert_array_equal(got["cell_cluster"], ref["label"])
+    d = np.abs(got["loc"] - ref["loc"])
+    _say(f"#   centroid worst {d.max():.2e} mm")
+    assert np.all(d <= 4e-6)
+    np.testing.assert_allclose(got["var"], ref["var"], rtol=1e-6)
+    np.testing.assert_allclose(got["spacepoints"], ref["spacepoint"], rtol=0, atol=1e-4)
+
+
+def test_cluster_batch_sampled_modules(ckf, det_dense):
+    """8 x mu = 200 events in one call: on 3,000 sampled non-empty (event,
+    module) rows the oracle, run row by row, gives the same clusters and
+    centroids; the totals add up."""
+    from oracle import clustering as OC
+    from synth.cells import Cells
+    evs = [make_event(det_dense, 7000 + i, mu=200) for i in range(8)]
+    cells = concat_cells([make_cells(det_dense, e, 100 + i) for i, e in enumerate(evs)])
+    _, pitch = cell_grid(det_dense)
+    _, got = _run(ckf, det_dense, cells)
+    _say(f"# clustering batch: {cells.n_cells} cells, {got['n_meas']} clusters")
+    assert got["status"] == 0 and got["offsets"][-1] == got["n_meas"]
+    rows = np.nonzero(np.diff(cells.offsets) > 0)[0]
+    rng = np.random.default_rng(5)
+    S = cells.n_surfaces
+    g = det_dense.as_arrays()
+    for r in rng.choice(rows, 3000, replace=False):
+        a, b = cells.offsets[r], cells.offsets[r + 1]
+        s = r % S
+        one = Cells(1, S, np.r_[np.zeros(s + 1, np.int32), np.full(S - s, b - a, np.int32)], cells.c0[a:b],
+                    cells.c1[a:b], cells.q[a:b], cells.particle[a:b])
+        ref = OC.cluster(one, g, pitch)
+        m0, m1 = got["offsets"][r], got["offsets"][r + 1]
+        assert m1 - m0 == len(ref["size"])
+        np.testing.assert_array_equal(got["cell_cluster"][a:b] - m0, ref["label"])
+        assert np.all(np.abs(got["loc"][m0:m1] - ref["loc"]) <= 4e-6)
+
+
+def test_clusters_feed_the_track_finder(ckf, det_dense):
+    """The GPU's measurements of a mu = 100 event (clusters of its cells) as
+    the track finder's input, with the event's seeds: most seeds give a
+    track, and most tracks are made of their seed particle's clusters."""
+    import torch
+    ev = make_event(det_dense, 6100, mu=100)
+    cells = make_cells(det_dense, ev, 3)
+    cl, got = _run(ckf, det_dense, cells)
+    # each cluster's particle: the particle of its largest-charge cell
+    m = got["n_meas"]
+    cc = got["cell_cluster"]
+    o = np.lexsort((-cells.q, cc))
+    first = o[np.r_[True, cc[o][1:] != cc[o][:-1]]]
+    cl_part = np.full(m, -1, np.int64)
+    cl_part[cc[first]] = cells.particle[first]
+    geo = ckf.Geometry(det_dense.as_arrays())
+    fld = ckf.UniformField(0, 0, 2.0)
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    b = ckf.Batch(1, ev.n_surfaces, t(got["offsets"], torch.int32), t(got["loc"], torch.float32),
+                  t(got["var"], torch.float32), t(ev.seed_event, torch.int32), t(ev.seed_surface, torch.int32),
+                  t(ev.seed_params, torch.float64), t(ev.seed_cov, torch.float64))
+    r = ckf.find(geo, fld, b)
+    pure = 0
+    for k in range(r["n_tracks"]):
+        ids = r["meas"][r["offsets"][k]:r["offsets"][k + 1]]
+        pure += np.mean(cl_part[ids] == ev.seed_particle[r["seed"][k]]) > 0.5
+    _say(f"# chain: {m} clusters, {r['n_tracks']} tracks of {ev.n_seeds} seeds, {pure} with a seed-particle majority")
+    assert r["n_tracks"] > 0.8 * ev.n_seeds and pure > 0.95 * r["n_tracks"]
+
+
+def test_cluster_edge_cases(ckf, det_dense):
+    """No cells; cells out of readout order flag CKF_CLUSTER_UNSORTED; a
+    row whose offsets pass n_cells flags CKF_CLUSTER_BAD_OFFSETS."""
+    from synth.cells import Cells
+    S = det_dense.n_surfaces
+    empty = Cells(1, S, np.zeros(S + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                  np.zeros(0, np.float32), np.zeros(0, np.int64))
+    _, got = _run(ckf, det_dense, empty)
+    assert got["n_meas"] == 0 and got["status"] == 0
+    off = np.zeros(S + 1, np.int32)
+    off[6:] = 3
+    bad = Cells(1, S, off, np.array([5, 4, 9], np.int32), np.array([2, 2, 2], np.int32),
+                np.ones(3, np.float32), np.zeros(3, np.int64))
+    _, got = _run(ckf, det_dense, bad)
+    assert got["status"] & 2
+    off2 = np.zeros(S + 1, np.int32)
+    off2[6] = 2
+    off2[7:] = 1   # row 6 ends past row 7's start: out of order
+    bad2 = Cells(1, S, off2, np.array([1, 2], np.int32), np.array([1, 1], np.int32), np.ones(2, np.float32),
+                 np.zeros(2, np.int64))
+    _, got = _run(ckf, det_dense, bad2)
+    assert got["status"] & 1
