@@ -62,20 +62,31 @@ PEAK_BF16 = 2.5e15    # MI355X dense bf16 MFMA, FLOP/s
 
 def _gen(args):
     from synth import barrel_endcap, make_event
-    seed, mu = args
-    return make_event(barrel_endcap(), seed, mu=mu)
+    seed, mu, cells = args
+    det = barrel_endcap()
+    ev = make_event(det, seed, mu=mu)
+    if not cells:
+        return ev
+    from synth.cells import make_cells
+    return ev, make_cells(det, ev, seed + 100000)
 
 
-def make_events(seeds, mu, workers):
+def make_events(seeds, mu, workers, cells=False):
+    """Events (and, with cells=True, their detector cells) generated in
+    parallel; returns (events, concatenated batch[, concatenated cells])."""
     from synth import concat_events
-    jobs = [(s, mu) for s in seeds]
+    jobs = [(s, mu, cells) for s in seeds]
     if workers > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(workers) as pool:
-            evs = pool.map(_gen, jobs)
+            out = pool.map(_gen, jobs)
     else:
-        evs = [_gen(j) for j in jobs]
-    return evs, concat_events(evs)
+        out = [_gen(j) for j in jobs]
+    if not cells:
+        return out, concat_events(out)
+    from synth.cells import concat_cells
+    evs = [e for e, _ in out]
+    return evs, concat_events(evs), concat_cells([c for _, c in out])
 
 
 def efficiency(ev, r):
@@ -291,6 +302,36 @@ def measure_resolve(ckf, finder, ev, stream, reps=3):
                 note="wall time of the synchronous call (one stream synchronisation per round)")
 
 
+def measure_cluster(ckf, geo, det, cells, stream, reps):
+    """Clustering of the batch's cells: device time of one ckf_cluster call
+    (HIP events on the launch stream around its kernels, mean of reps) and
+    the HBM roofline of its algorithmic bytes: the cells read once (c0, c1,
+    q: 12 B) and the row offsets (4 B), every cell's cluster index written
+    (4 B), per cluster loc, var and spacepoint (28 B), the measurement
+    offsets (4 B per row)."""
+    import torch
+    from synth.cells import cell_grid
+    _, pitch = cell_grid(det)
+    cl = ckf.Clusterer(geo, ckf.CellBatch.from_cells(cells), torch.as_tensor(pitch, device="cuda"))
+    cl.enqueue(stream)
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        cl.enqueue(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    r = cl.result()
+    rows = cells.n_events * cells.n_surfaces
+    algo = 16 * cells.n_cells + 28 * r["n_meas"] + 8 * rows
+    return dict(cells=cells.n_cells, clusters=r["n_meas"], status=r["status"], ms=round(ms, 4),
+                cells_per_s=round(cells.n_cells / (ms * 1e-3), 1),
+                roofline=dict(bound="hbm", achieved=round(algo / (ms * 1e-3) / 1e9, 1), peak=8000.0, unit="GB/s",
+                              frac=round(algo / (ms * 1e-3) / 8e12, 5), traffic=None, kernel="k_cl_*",
+                              algorithmic_bytes=int(algo)))
+
+
 def roofline_of(m, form, shape):
     c = dict(m["counters"])
     f32 = sum(c.get(k, 0) * UNIT_FLOPS[k][0] for k in UNIT_FLOPS)
@@ -357,8 +398,9 @@ def main():
     say = lambda msg: print(msg, file=sys.stderr, flush=True)
 
     t0 = time.time()
-    evs, batch = make_events([6000 + i for i in range(args.events)], args.mu, args.workers)
-    say(f"# generated {batch.n_events} events, {batch.n_seeds} seeds, {batch.n_meas} measurements "
+    evs, batch, cells = make_events([6000 + i for i in range(args.events)], args.mu, args.workers, cells=True)
+    say(f"# generated {batch.n_events} events, {batch.n_seeds} seeds, {batch.n_meas} measurements, "
+        f"{cells.n_cells} cells "
         f"in {time.time() - t0:.1f} s")
 
     import torch
@@ -399,6 +441,10 @@ def main():
         + "; ".join(f"{k} {fit[k]['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel {fit[k]['kernel_ms']:.3f} ms, "
                     f"fitted {fit[k]['fitted']:.5f}" for k in ("rts", "two_filter")))
     amb = measure_resolve(ckf, fit.pop("_finder"), batch, stream)
+    clu = measure_cluster(ckf, geo, det, cells, stream, max(3, args.steps // 4))
+    say(f"# clustering of the batch's {clu['cells']} cells: {clu['clusters']} clusters in {clu['ms']:.3f} ms "
+        f"({clu['cells_per_s'] / 1e9:.2f} G cells/s, {clu['roofline']['achieved']:.0f} GB/s algorithmic), "
+        f"status {clu['status']}")
     say(f"# ambiguity resolution of the plain search's tracks: {amb['ms']:.2f} ms, {amb['rounds']} rounds, "
         f"{amb['removed']} of {amb['tracks_in']} removed; fake rate {amb['before']['fake_rate']:.5f} -> "
         f"{amb['after']['fake_rate']:.5f}, duplicate rate {amb['before']['duplicate_rate']:.5f} -> "
@@ -470,7 +516,7 @@ def main():
                 roofline=roofline_of(head, "learned" if learned_info else "plain",
                                      learned_info["launch"] if learned_info else shape_plain),
                 plain_roofline=roofline_of(plain, "plain", shape_plain),
-                fit=fit, ambiguity=amb, cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
+                fit=fit, ambiguity=amb, clustering=clu, cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
     print(json.dumps(line))
 
 

@@ -16,8 +16,9 @@ readings:
 * a cluster is named by its first cell in readout order (row c1, then
   column c0); a module's clusters are taken in that order;
 * the measurement is the charge-weighted mean of the cluster's cell centres
-  in local coordinates, (c + 1/2) pitch - half length, summed in readout
-  order; its variances are pitch^2 / 12;
+  in local coordinates: with the sums W = sum q and X = sum q (c + 1/2) over
+  the cluster's cells (in cell units), loc = pitch X / W - half length; its
+  variances are pitch^2 / 12;
 * the spacepoint is centre + loc0 u + loc1 v of the module.
 """
 from __future__ import annotations
@@ -81,9 +82,9 @@ def cluster(cells, geom, pitch):
             for i in members:
                 q = float(cells.q[a + i])
                 w += q
-                x += q * ((cells.c0[a + i] + 0.5) * p0 - half[s, 0])
-                y += q * ((cells.c1[a + i] + 0.5) * p1 - half[s, 1])
-            l0, l1 = x / w, y / w
+                x += q * (cells.c0[a + i] + 0.5)
+                y += q * (cells.c1[a + i] + 0.5)
+            l0, l1 = p0 * (x / w) - half[s, 0], p1 * (y / w) - half[s, 1]
             loc.append((l0, l1))
             size.append(len(members))
             first.append(a + root)

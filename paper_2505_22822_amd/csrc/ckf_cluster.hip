@@ -6,18 +6,26 @@
 // Cells arrive in readout order: grouped by (event, module) row, then by
 // row c1 and column c0 inside a module.  Two cells touch when |dc0| <= 1 and
 // |dc1| <= 1, so a cell's earlier neighbours lie in the rows c1 - 1 and c1,
-// just before it in the order.  One lane takes one (event, module) row:
-//   label   - union-find over the row's cells, each cell joined to the
-//             touching cells found by scanning back while c1 >= its c1 - 1;
-//             roots are the smaller index, so a cluster is named by its
-//             first cell; clusters per row counted;
-//   scan    - exclusive prefix sum of the counts: the measurements' row
-//             offsets, the layout ckf_find reads;
-//   measure - each cluster's charge-weighted mean of the cell centres (FP64
-//             sums in readout order), pitch^2 / 12 variances, spacepoints.
-// Rows hold a few cells each on average, so one lane per row keeps the
-// union-find in private order with no atomics; the kernels stream the cells
-// once or twice and are bound by memory and latency.
+// just before it in the order.  Everything runs one thread per cell (or per
+// cluster), with no per-module serial work:
+//   heads   - each (event, module) row marks its first cell; an inclusive
+//             max-scan gives every cell its row;
+//   link    - each cell scans back over the cells of its module while
+//             c1 >= its c1 - 1 and joins the touching ones in a lock-free
+//             union-find (compare-and-swap of the larger root onto the
+//             smaller), so every cluster's root is its first cell;
+//   flatten - every cell's root (read-only walk of the final forest) and
+//             the root flags;
+//   number  - an exclusive sum-scan of the root flags numbers the clusters in
+//             readout order of their first cells: clusters come out grouped
+//             by row, in the order the measurement layout needs, and a row's
+//             measurement offset is the scan at its first cell;
+//   sums    - each cell adds q, q (c0 + 1/2), q (c1 + 1/2) to its cluster in
+//             FP64 atomics: every term has at most 35 significant bits and
+//             the sums stay far below 2^53 of their quantum, so they are exact
+//             and the result does not depend on the order of the additions;
+//   measure - per cluster: loc = pitch X / W - half length, pitch^2 / 12
+//             variances, the spacepoint.
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
 
@@ -28,174 +36,276 @@ namespace {
 constexpr int kClBlock = 256;
 constexpr int kScanBlock = 1024;
 
-__device__ __forceinline__ int cl_find(int* p, int x) {
-  while (p[x] != x) {
-    const int g = p[p[x]];
-    p[x] = g;
-    x = g;
-  }
-  return x;
-}
+struct OpSum {
+  __device__ static long long id() { return 0; }
+  __device__ static long long f(long long a, long long b) { return a + b; }
+};
+struct OpMax {
+  __device__ static long long id() { return -1; }
+  __device__ static long long f(long long a, long long b) { return a > b ? a : b; }
+};
+
+__device__ __forceinline__ int grid_i() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
 __global__ void k_cl_clear(int* status) { *status = 0; }
 
-__global__ void k_cl_label(CellsIn c, int* __restrict__ parent, int* __restrict__ counts, int* __restrict__ status) {
+__global__ void k_cl_init(long long n, int* __restrict__ head, int* __restrict__ parent) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  head[i] = -1;
+  parent[i] = (int)i;
+}
+
+// each row marks its first cell with its row number; offsets checked
+__global__ void k_cl_heads(CellsIn c, int* __restrict__ head, int* __restrict__ status) {
   const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long rows = (long long)c.n_events * c.n_surfaces;
   if (r >= rows) return;
   const int a = c.offsets[r], b = c.offsets[r + 1];
   if (a < 0 || b < a || (long long)b > c.n_cells) {
     atomicOr(status, CKF_CLUSTER_BAD_OFFSETS);
-    counts[r] = 0;
     return;
   }
-  int n_root = 0;
-  for (int i = a; i < b; ++i) {
-    parent[i] = i;
-    const int x = c.c0[i], y = c.c1[i];
-    if (i > a && (c.c1[i - 1] > y || (c.c1[i - 1] == y && c.c0[i - 1] >= x))) atomicOr(status, CKF_CLUSTER_UNSORTED);
-    for (int j = i - 1; j >= a && c.c1[j] >= y - 1; --j) {
-      if (abs(c.c0[j] - x) > 1) continue;
-      const int ri = cl_find(parent, i), rj = cl_find(parent, j);
-      if (ri != rj) parent[max(ri, rj)] = min(ri, rj);
-    }
-  }
-  for (int i = a; i < b; ++i) {
-    const int root = cl_find(parent, i);
-    parent[i] = root;
-    n_root += root == i ? 1 : 0;
-  }
-  counts[r] = n_root;
+  if (r == 0 && a != 0) atomicOr(status, CKF_CLUSTER_BAD_OFFSETS);
+  if (a < b) head[a] = (int)r;
 }
 
-// exclusive scan of n ints in blocks of kScanBlock: per-block scans and sums
+// scan of n values in blocks of kScanBlock (inclusive or exclusive): per-block
+// scans and block totals; then the totals scanned by one block; then applied
+template <class Op, bool kIncl>
 __global__ void __launch_bounds__(kScanBlock) k_scan_blocks(const int* __restrict__ in, long long n,
                                                               int* __restrict__ out, long long* __restrict__ sums) {
   __shared__ long long sh[kScanBlock];
   const long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x;
-  const long long v = i < n ? in[i] : 0;
+  const long long v = i < n ? in[i] : Op::id();
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int o = 1; o < kScanBlock; o <<= 1) {
-    const long long t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+    const long long t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : Op::id();
     __syncthreads();
-    sh[threadIdx.x] += t;
+    sh[threadIdx.x] = Op::f(sh[threadIdx.x], t);
     __syncthreads();
   }
-  if (i < n) out[i] = (int)(sh[threadIdx.x] - v);
+  if (i < n) out[i] = (int)(kIncl ? sh[threadIdx.x] : (threadIdx.x ? sh[threadIdx.x - 1] : Op::id()));
   if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = sh[threadIdx.x];
 }
 
-// one block: block sums -> block offsets (serial over chunks), and the total
+// one block: block totals -> exclusive block prefixes (serial over chunks); the grand total
+template <class Op>
 __global__ void __launch_bounds__(kScanBlock) k_scan_sums(long long nb, long long* __restrict__ sums,
                                                             int* __restrict__ total) {
   __shared__ long long sh[kScanBlock];
-  long long base = 0;
+  long long base = Op::id();
   for (long long b0 = 0; b0 < nb; b0 += kScanBlock) {
     const long long b = b0 + threadIdx.x;
-    const long long v = b < nb ? sums[b] : 0;
+    const long long v = b < nb ? sums[b] : Op::id();
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < kScanBlock; o <<= 1) {
-      const long long t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+      const long long t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : Op::id();
       __syncthreads();
-      sh[threadIdx.x] += t;
+      sh[threadIdx.x] = Op::f(sh[threadIdx.x], t);
       __syncthreads();
     }
-    if (b < nb) sums[b] = base + sh[threadIdx.x] - v;
+    const long long prev = threadIdx.x ? sh[threadIdx.x - 1] : Op::id();
+    if (b < nb) sums[b] = Op::f(base, prev);
     const long long chunk = sh[kScanBlock - 1];
     __syncthreads();
-    base += chunk;
+    base = Op::f(base, chunk);
   }
-  if (threadIdx.x == 0) *total = (int)base;
+  if (threadIdx.x == 0 && total) *total = (int)base;
 }
 
+template <class Op>
 __global__ void k_scan_apply(long long n, int* __restrict__ out, const long long* __restrict__ sums) {
   const long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x;
-  if (i < n) out[i] += (int)sums[blockIdx.x];
+  if (i < n) out[i] = (int)Op::f(sums[blockIdx.x], out[i]);
 }
 
-__global__ void k_cl_measure(CellsIn c, GeomDev g, const float* __restrict__ pitch, const int* __restrict__ parent,
-                             const int* __restrict__ moff, int* __restrict__ slot, double* __restrict__ acc,
-                             float* __restrict__ loc, float* __restrict__ var, float* __restrict__ sp,
-                             int* __restrict__ cell_cluster) {
-  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long rows = (long long)c.n_events * c.n_surfaces;
-  if (r >= rows) return;
-  const int a = c.offsets[r], b = c.offsets[r + 1];
-  if (a < 0 || b < a || (long long)b > c.n_cells || a == b) return;
-  const int s = (int)(r % c.n_surfaces);
-  const int o0 = moff[r];
-  int k = o0;
-  for (int i = a; i < b; ++i)
-    if (parent[i] == i) {
-      slot[i] = k;
-      acc[3ll * k] = acc[3ll * k + 1] = acc[3ll * k + 2] = 0.0;
-      ++k;
+__device__ __forceinline__ int cl_find(int* p, int x) {
+  int y = p[x];
+  while (y != x) {  // parents only ever move to smaller indices: halving stays valid under races
+    const int z = p[y];
+    if (z != y) p[x] = z;
+    x = y;
+    y = z;
+  }
+  return x;
+}
+
+__global__ void k_cl_link(CellsIn c, const int* __restrict__ row, int* __restrict__ parent,
+                          int* __restrict__ status) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n_cells) return;
+  const int r = row[i];
+  if (r < 0) return;  // before the first row (bad offsets)
+  const int x = c.c0[i], y = c.c1[i];
+  const long long a = c.offsets[r];
+  if (i > a && (c.c1[i - 1] > y || (c.c1[i - 1] == y && c.c0[i - 1] >= x))) atomicOr(status, CKF_CLUSTER_UNSORTED);
+  for (long long j = i - 1; j >= a && c.c1[j] >= y - 1; --j) {
+    if (abs(c.c0[j] - x) > 1) continue;
+    int ri = cl_find(parent, (int)i), rj = cl_find(parent, (int)j);
+    while (ri != rj) {  // hook the larger root under the smaller one
+      if (ri < rj) {
+        const int t = ri;
+        ri = rj;
+        rj = t;
+      }
+      const int old = atomicCAS(&parent[ri], ri, rj);
+      if (old == ri) break;
+      ri = cl_find(parent, old);
+      rj = cl_find(parent, rj);
     }
+  }
+}
+
+// every cell's root into a separate array: the forest is final, and it is
+// only read here (a shortening store into it could land after another
+// cell's and leave that cell pointing at an ancestor short of its root)
+__global__ void k_cl_flatten(long long n, const int* __restrict__ parent, int* __restrict__ root,
+                             int* __restrict__ is_root) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x = (int)i, y = parent[x];
+  while (y != x) {
+    x = y;
+    y = parent[x];
+  }
+  root[i] = x;
+  is_root[i] = x == i ? 1 : 0;
+}
+
+// roots: clear their cluster's sums and note the cluster's first cell
+__global__ void k_cl_roots(long long n, const int* __restrict__ root, const int* __restrict__ cid,
+                           int* __restrict__ first, double* __restrict__ acc) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || root[i] != i) return;
+  const int k = cid[i];
+  first[k] = (int)i;
+  acc[3ll * k] = acc[3ll * k + 1] = acc[3ll * k + 2] = 0.0;
+}
+
+__global__ void k_cl_sums(CellsIn c, const int* __restrict__ row, const int* __restrict__ root,
+                          const int* __restrict__ cid, double* __restrict__ acc, int* __restrict__ cell_cluster) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n_cells) return;
+  if (row[i] < 0) {
+    if (cell_cluster) cell_cluster[i] = -1;
+    return;
+  }
+  const int k = cid[root[i]];
+  const double q = c.q[i];
+  atomicAdd(&acc[3ll * k], q);
+  atomicAdd(&acc[3ll * k + 1], q * ((double)c.c0[i] + 0.5));
+  atomicAdd(&acc[3ll * k + 2], q * ((double)c.c1[i] + 0.5));
+  if (cell_cluster) cell_cluster[i] = k;
+}
+
+__global__ void k_cl_measure(CellsIn c, GeomDev g, const float* __restrict__ pitch, const int* __restrict__ n_cl,
+                             const int* __restrict__ first, const int* __restrict__ row,
+                             const double* __restrict__ acc, float* __restrict__ loc, float* __restrict__ var,
+                             float* __restrict__ sp) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= *n_cl) return;
+  const int rr = row[first[k]];
+  if (rr < 0) {  // a cell before the first row (bad offsets, flagged): no module
+    loc[2 * k] = loc[2 * k + 1] = var[2 * k] = var[2 * k + 1] = NAN;
+    if (sp) sp[3 * k] = sp[3 * k + 1] = sp[3 * k + 2] = NAN;
+    return;
+  }
+  const int s = rr % c.n_surfaces;
   Module M;
   load_module(g, s, M);
-  const double p0 = pitch[2 * s], p1 = pitch[2 * s + 1], h0 = M.hw0, h1 = M.hw1;
-  for (int i = a; i < b; ++i) {
-    const int kk = slot[parent[i]];
-    const double q = c.q[i];
-    acc[3ll * kk] += q;
-    acc[3ll * kk + 1] += q * ((c.c0[i] + 0.5) * p0 - h0);
-    acc[3ll * kk + 2] += q * ((c.c1[i] + 0.5) * p1 - h1);
-    if (cell_cluster) cell_cluster[i] = kk;
-  }
-  const float v0 = (float)(p0 * p0 / 12.0), v1 = (float)(p1 * p1 / 12.0);
-  for (int m = o0; m < k; ++m) {
-    const double w = acc[3ll * m];
-    const double l0 = acc[3ll * m + 1] / w, l1 = acc[3ll * m + 2] / w;
-    loc[2ll * m] = (float)l0;
-    loc[2ll * m + 1] = (float)l1;
-    var[2ll * m] = v0;
-    var[2ll * m + 1] = v1;
-    if (sp) {
-      const float f0 = (float)l0, f1 = (float)l1;
+  const double p0 = pitch[2 * s], p1 = pitch[2 * s + 1];
+  const double w = acc[3 * k];
+  const double l0 = p0 * (acc[3 * k + 1] / w) - (double)M.hw0, l1 = p1 * (acc[3 * k + 2] / w) - (double)M.hw1;
+  loc[2 * k] = (float)l0;
+  loc[2 * k + 1] = (float)l1;
+  var[2 * k] = (float)(p0 * p0 / 12.0);
+  var[2 * k + 1] = (float)(p1 * p1 / 12.0);
+  if (sp) {
+    const float f0 = (float)l0, f1 = (float)l1;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) sp[3ll * m + d] = M.c[d] + f0 * M.u[d] + f1 * M.v[d];
-    }
+    for (int d = 0; d < 3; ++d) sp[3 * k + d] = M.c[d] + f0 * M.u[d] + f1 * M.v[d];
   }
+}
+
+// a row's measurement offset: the cluster number at its first cell (the
+// total past the last cell)
+__global__ void k_cl_offsets(CellsIn c, const int* __restrict__ cid, const int* __restrict__ n_cl,
+                             int* __restrict__ moff) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long rows = (long long)c.n_events * c.n_surfaces;
+  if (r > rows) return;
+  const long long a = r < rows ? c.offsets[r] : c.n_cells;
+  moff[r] = (a >= 0 && a < c.n_cells) ? cid[a] : *n_cl;
 }
 
 size_t al256c(size_t b) { return (b + 255) & ~(size_t)255; }
 
+struct ClWs {
+  int *head, *row, *parent, *is_root, *cid, *first, *n_cl;
+  double* acc;
+  long long* sums;
+};
+
+ClWs cl_view(void* ws, long long n) {
+  char* p = static_cast<char*>(ws);
+  ClWs w;
+  int** ints[] = {&w.head, &w.row, &w.parent, &w.is_root, &w.cid, &w.first};
+  for (int** q : ints) {
+    *q = reinterpret_cast<int*>(p);
+    p += al256c((size_t)n * 4);
+  }
+  w.acc = reinterpret_cast<double*>(p);
+  p += al256c((size_t)n * 24);
+  w.n_cl = reinterpret_cast<int*>(p);
+  p += 256;
+  w.sums = reinterpret_cast<long long*>(p);
+  return w;
+}
+
+template <class Op, bool kIncl>
+void scan(const int* in, long long n, int* out, long long* sums, int* total, hipStream_t st) {
+  const long long nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb > 0)
+    hipLaunchKernelGGL((k_scan_blocks<Op, kIncl>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, out, sums);
+  hipLaunchKernelGGL((k_scan_sums<Op>), dim3(1), dim3(kScanBlock), 0, st, nb, sums, total);
+  if (nb > 0) hipLaunchKernelGGL((k_scan_apply<Op>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, n, out, sums);
+}
+
 }  // namespace
 
 size_t cluster_workspace_bytes(long long rows, long long n_cells) {
-  const long long nb = (rows + kScanBlock - 1) / kScanBlock;
-  return al256c((size_t)n_cells * 4) * 2 + al256c((size_t)n_cells * 24) + al256c((size_t)rows * 4) +
-         al256c((size_t)(nb + 1) * 8) + 256;
+  (void)rows;
+  const long long n = n_cells > 0 ? n_cells : 1;
+  const long long nb = (n + kScanBlock - 1) / kScanBlock;
+  return 6 * al256c((size_t)n * 4) + al256c((size_t)n * 24) + 256 + al256c((size_t)(nb + 1) * 8) + 256;
 }
 
 hipError_t launch_cluster(const CellsIn& c, const GeomDev& g, const float* pitch, void* ws, int* moff, float* loc,
                           float* var, float* sp, int* cell_cluster, int* status, hipStream_t st) {
   const long long rows = (long long)c.n_events * c.n_surfaces;
-  const long long nb = (rows + kScanBlock - 1) / kScanBlock;
+  const long long n = c.n_cells;
+  const ClWs w = cl_view(ws, n > 0 ? n : 1);
   hipLaunchKernelGGL(k_cl_clear, dim3(1), dim3(1), 0, st, status);  // a kernel, not a memset: capturable
-  char* p = static_cast<char*>(ws);
-  int* parent = reinterpret_cast<int*>(p);
-  p += al256c((size_t)c.n_cells * 4);
-  int* slot = reinterpret_cast<int*>(p);
-  p += al256c((size_t)c.n_cells * 4);
-  double* acc = reinterpret_cast<double*>(p);
-  p += al256c((size_t)c.n_cells * 24);
-  int* counts = reinterpret_cast<int*>(p);
-  p += al256c((size_t)rows * 4);
-  long long* sums = reinterpret_cast<long long*>(p);
-  if (rows <= 0) {  // no rows: only the total (zero) of the offsets
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, 0ll, sums, moff);
-    return hipGetLastError();
+  const auto blocks = [](long long m) { return dim3((unsigned)((m + kClBlock - 1) / kClBlock)); };
+  if (n > 0) hipLaunchKernelGGL(k_cl_init, blocks(n), dim3(kClBlock), 0, st, n, w.head, w.parent);
+  if (rows > 0) hipLaunchKernelGGL(k_cl_heads, blocks(rows), dim3(kClBlock), 0, st, c, w.head, status);
+  scan<OpMax, true>(w.head, n, w.row, w.sums, nullptr, st);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_cl_link, blocks(n), dim3(kClBlock), 0, st, c, w.row, w.parent, status);
+    // the row heads are scanned already: their array takes the roots
+    hipLaunchKernelGGL(k_cl_flatten, blocks(n), dim3(kClBlock), 0, st, n, w.parent, w.head, w.is_root);
   }
-  const dim3 grid((unsigned)((rows + kClBlock - 1) / kClBlock)), block(kClBlock);
-  hipLaunchKernelGGL(k_cl_label, grid, block, 0, st, c, parent, counts, status);
-  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kScanBlock), 0, st, counts, rows, moff, sums);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, nb, sums, moff + rows);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, st, rows, moff, sums);
-  hipLaunchKernelGGL(k_cl_measure, grid, block, 0, st, c, g, pitch, parent, moff, slot, acc, loc, var, sp,
-                     cell_cluster);
+  scan<OpSum, false>(w.is_root, n, w.cid, w.sums, w.n_cl, st);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_cl_roots, blocks(n), dim3(kClBlock), 0, st, n, w.head, w.cid, w.first, w.acc);
+    hipLaunchKernelGGL(k_cl_sums, blocks(n), dim3(kClBlock), 0, st, c, w.row, w.head, w.cid, w.acc, cell_cluster);
+    hipLaunchKernelGGL(k_cl_measure, blocks(n), dim3(kClBlock), 0, st, c, g, pitch, w.n_cl, w.first, w.row, w.acc,
+                       loc, var, sp);
+  }
+  hipLaunchKernelGGL(k_cl_offsets, blocks(rows + 1), dim3(kClBlock), 0, st, c, w.cid, w.n_cl, moff);
   return hipGetLastError();
 }
 
