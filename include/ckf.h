@@ -416,6 +416,39 @@ ckf_status ckf_cluster(const ckf_geometry* g, const ckf_cells* cells, const floa
                        size_t workspace_bytes, int32_t* meas_offsets, float* loc, float* var, float* spacepoints,
                        int32_t* cell_cluster, int32_t* status, void* stream);
 
+/* Triplet seeding and helix parameter estimation (paper section 2: triplets
+ * of spacepoints that can approximately form a helix; the track's position
+ * and momentum estimated at the first spacepoint with the helix model).
+ * Spacepoints in the measurement layout (ckf_cluster's output): rows of
+ * (event, module) given by meas_offsets [n_events*n_surfaces+1], with
+ * global positions spacepoints [n_sp][3] and local positions loc [n_sp][2]
+ * (device).  layers [n_layers] (HOST array, 3 <= n_layers <= 8): the
+ * seeding layers' geometry ids ordered outwards.  A triplet has its bottom,
+ * middle and top on three seeding layers in that order, in one event.
+ * Cuts (FP64, no fused operations): per doublet |dz/dr| <= 3, azimuth step
+ * <= 0.12 rad, the bottom doublet's line within 200 mm of z = 0 at r = 0;
+ * per triplet |cot_BM - cot_MT| <= 0.01 + 0.007 (1 + cot_BM^2), the
+ * transverse circle's radius >= the helix radius of 0.5 GeV in bz and its
+ * distance of closest approach to the beam line <= 1 mm.  Per middle
+ * spacepoint at most the 2 best by (distance, bottom, top); seeds in order
+ * of their middle spacepoint.  Seed on the bottom spacepoint's module:
+ * (loc0, loc1) = its local position, phi = the circle's tangent there
+ * towards the middle, theta from the transverse arc to the top and dz,
+ * q/p = q sin(theta) / (kappa |bz| R); covariance diagonal (0.2 mm, 0.6 mm,
+ * 10 mrad, 10 mrad, 15 % of q/p).  Outputs (device, caller-owned, cap_seeds
+ * rows; seeds beyond the capacity are counted but not written): n_seeds
+ * [1], seed_event, seed_surface, seed_params [cap][5], seed_cov [cap][15]
+ * (the layout of ckf_seeds), seed_spacepoints [cap][3] (bottom, middle,
+ * top) or NULL.  workspace: at least ckf_seed_workspace_size bytes
+ * (CKF_ERR_CAPACITY).  Asynchronous on `stream`; allocates nothing. */
+ckf_status ckf_seed_workspace_size(int32_t n_events, int32_t n_surfaces, int64_t n_sp, int32_t n_layers,
+                                   size_t* bytes);
+ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas_offsets, int64_t n_sp,
+                    const float* spacepoints, const float* loc, const int32_t* layers, int32_t n_layers, double bz,
+                    void* workspace, size_t workspace_bytes, int64_t cap_seeds, int32_t* n_seeds,
+                    int32_t* seed_event, int32_t* seed_surface, double* seed_params, double* seed_cov,
+                    int32_t* seed_spacepoints, void* stream);
+
 /* Greedy ambiguity resolution of found tracks by shared measurements (paper
  * section 4: the stage after track finding that removes duplicate and fake
  * tracks).  A measurement is shared when more than one surviving track holds

@@ -85,16 +85,17 @@ def _doublets(p, q, bottom):
     return ok, cot
 
 
-def triplets(xyz, layer_index, bz):
+def triplets(xyz, layer_index, bz, middles=None):
     """All kept triplets: list of (middle, bottom, top, d0) in output order.
     xyz [n,3] float64 (one event), layer_index [n] (-1: not a seeding
-    layer).  Every middle is tested against every other spacepoint of the
-    event (no binning)."""
+    layer); middles: only these middle spacepoints (default all).  Every
+    middle is tested against every other spacepoint of the event (no
+    binning)."""
     rmin = r_min(bz)
     n = xyz.shape[0]
     li = np.asarray(layer_index)
     out = []
-    for m in range(n):
+    for m in (range(n) if middles is None else middles):
         lm = li[m]
         if lm < 0:
             continue

@@ -18,7 +18,7 @@ from ._abi import COUNTER_NAMES
 
 __all__ = ["Geometry", "UniformField", "FieldMap", "Model", "config", "find", "propagate_batch", "kf_update_batch",
            "neighbours", "mlp_forward", "mlp_grad", "mlp_adam", "capture_pairs", "Fitter", "resolve", "CellBatch", "cluster",
-           "CkfError"]
+           "seed", "CkfError"]
 
 
 class CkfError(RuntimeError):
@@ -530,6 +530,37 @@ def cluster(geometry: Geometry, cells: CellBatch, pitch, stream=None):
     c = Clusterer(geometry, cells, pitch)
     c.enqueue(stream)
     return c.result()
+
+
+def seed(geometry: Geometry, n_events: int, meas_offsets, spacepoints, loc, layers, bz=2.0, cap_seeds=None,
+         stream=None):
+    """Triplet seeding (ckf_seed) on spacepoints in the measurement layout
+    (a Clusterer's offsets, spacepoints and loc, device tensors).  layers:
+    the seeding layers' geometry ids ordered outwards.  Returns a dict of
+    device tensors (event, surface, params, cov, spacepoints) sized to the
+    number of seeds, and that number."""
+    import torch
+    lib = _abi.load()
+    dev = meas_offsets.device
+    n_sp = int(spacepoints.shape[0])
+    lay = np.ascontiguousarray(np.asarray(layers, np.int32))
+    nl = len(lay)
+    nb = C.c_size_t(0)
+    _check(lib.ckf_seed_workspace_size(int(n_events), geometry.n_surfaces, n_sp, nl, C.byref(nb)),
+           "ckf_seed_workspace_size")
+    ws = torch.empty(max(1, int(nb.value)), dtype=torch.uint8, device=dev)
+    cap = int(cap_seeds) if cap_seeds is not None else max(1, 2 * n_sp)
+    z = lambda shape, dt: torch.zeros(shape, dtype=dt, device=dev)
+    out = dict(event=z(cap, torch.int32), surface=z(cap, torch.int32), params=z((cap, 5), torch.float64),
+               cov=z((cap, 15), torch.float64), spacepoints=z((cap, 3), torch.int32))
+    n = z(1, torch.int32)
+    _check(lib.ckf_seed(geometry.handle, int(n_events), _ptr(meas_offsets), n_sp, _ptr(spacepoints), _ptr(loc),
+                        lay.ctypes.data_as(C.c_void_p), nl, float(bz), _ptr(ws), ws.numel(), cap, _ptr(n),
+                        _ptr(out["event"]), _ptr(out["surface"]), _ptr(out["params"]), _ptr(out["cov"]),
+                        _ptr(out["spacepoints"]), _stream_handle(stream)), "ckf_seed")
+    k = int(n.cpu()[0])
+    m = min(k, cap)
+    return {key: v[:m] for key, v in out.items()}, k
 
 
 def resolve(tracks: dict, n_meas: int, max_shared=1, stream=None, workspace=None):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libckf.so")
-SOURCES = ["ckf_kernels.hip", "ckf_learned.hip", "ckf_fit.hip", "ckf_resolve.hip", "ckf_cluster.hip", "ckf_api.cpp"]
+SOURCES = ["ckf_kernels.hip", "ckf_learned.hip", "ckf_fit.hip", "ckf_resolve.hip", "ckf_cluster.hip", "ckf_seed.hip", "ckf_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

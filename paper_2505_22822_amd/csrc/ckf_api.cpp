@@ -956,6 +956,42 @@ ckf_status ckf_cluster(const ckf_geometry* g, const ckf_cells* c, const float* p
   return CKF_OK;
 }
 
+ckf_status ckf_seed_workspace_size(int32_t n_events, int32_t n_surfaces, int64_t n_sp, int32_t n_layers,
+                                   size_t* bytes) {
+  if (!bytes || n_events < 0 || n_surfaces < 0 || n_sp < 0 || n_layers < 3 || n_layers > 8)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "seed_workspace_size: bad argument");
+  *bytes = ckf::seed_workspace_bytes((long long)n_events * n_surfaces, n_sp, n_events, n_layers);
+  return CKF_OK;
+}
+
+ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas_offsets, int64_t n_sp,
+                    const float* spacepoints, const float* loc, const int32_t* layers, int32_t n_layers, double bz,
+                    void* workspace, size_t workspace_bytes, int64_t cap_seeds, int32_t* n_seeds,
+                    int32_t* seed_event, int32_t* seed_surface, double* seed_params, double* seed_cov,
+                    int32_t* seed_spacepoints, void* stream) {
+  if (!g || !layers || !n_seeds || n_events < 0 || n_sp < 0 || cap_seeds < 0)
+    return fail(CKF_ERR_INVALID_ARGUMENT, "seed: bad argument");
+  if (n_layers < 3 || n_layers > 8) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: 3 to 8 seeding layers");
+  if (!(std::isfinite(bz) && bz != 0.0)) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: bz must be finite and non-zero");
+  if (n_sp > INT32_MAX || (long long)n_events * g->dev.n_surfaces >= INT32_MAX ||
+      (long long)n_events * n_layers * 48 >= INT32_MAX)
+    return fail(CKF_ERR_NOT_SUPPORTED, "seed: too many spacepoints or rows");
+  if (n_events > 0 && !meas_offsets) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: NULL offsets");
+  if (n_sp > 0 && (!spacepoints || !loc)) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: NULL spacepoints");
+  if (cap_seeds > 0 && (!seed_event || !seed_surface || !seed_params || !seed_cov))
+    return fail(CKF_ERR_INVALID_ARGUMENT, "seed: NULL output");
+  for (int q = 0; q < n_layers; ++q)
+    if (layers[q] < 0 || layers[q] >= g->dev.n_layers) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: bad layer id");
+  if (!workspace || workspace_bytes < ckf::seed_workspace_bytes((long long)n_events * g->dev.n_surfaces, n_sp,
+                                                                n_events, n_layers))
+    return fail(CKF_ERR_CAPACITY, "seed: workspace too small");
+  HIP_TRY(ckf::launch_seed(g->dev, n_events, g->dev.n_surfaces, meas_offsets, n_sp, spacepoints, loc, layers,
+                           n_layers, bz, workspace, cap_seeds, n_seeds, seed_event, seed_surface, seed_params,
+                           seed_cov, seed_spacepoints, static_cast<hipStream_t>(stream)),
+          "launch the seeding");
+  return CKF_OK;
+}
+
 ckf_status ckf_resolve_workspace_size(int32_t cap_tracks, int64_t n_meas, size_t* bytes) {
   if (cap_tracks < 0 || n_meas < 0 || !bytes) return fail(CKF_ERR_INVALID_ARGUMENT, "resolve_workspace_size: bad argument");
   *bytes = ckf::resolve_workspace_bytes(cap_tracks, n_meas);

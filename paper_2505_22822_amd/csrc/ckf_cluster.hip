@@ -28,22 +28,14 @@
 //             variances, the spacepoint.
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
+#include "ckf_scan.hpp"
 
 namespace ckf {
 
 namespace {
 
 constexpr int kClBlock = 256;
-constexpr int kScanBlock = 1024;
-
-struct OpSum {
-  __device__ static long long id() { return 0; }
-  __device__ static long long f(long long a, long long b) { return a + b; }
-};
-struct OpMax {
-  __device__ static long long id() { return -1; }
-  __device__ static long long f(long long a, long long b) { return a > b ? a : b; }
-};
+constexpr int kScanBlock = scan_detail::kScanBlock;
 
 __device__ __forceinline__ int grid_i() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
@@ -68,58 +60,6 @@ __global__ void k_cl_heads(CellsIn c, int* __restrict__ head, int* __restrict__ 
   }
   if (r == 0 && a != 0) atomicOr(status, CKF_CLUSTER_BAD_OFFSETS);
   if (a < b) head[a] = (int)r;
-}
-
-// scan of n values in blocks of kScanBlock (inclusive or exclusive): per-block
-// scans and block totals; then the totals scanned by one block; then applied
-template <class Op, bool kIncl>
-__global__ void __launch_bounds__(kScanBlock) k_scan_blocks(const int* __restrict__ in, long long n,
-                                                              int* __restrict__ out, long long* __restrict__ sums) {
-  __shared__ long long sh[kScanBlock];
-  const long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x;
-  const long long v = i < n ? in[i] : Op::id();
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 1; o < kScanBlock; o <<= 1) {
-    const long long t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : Op::id();
-    __syncthreads();
-    sh[threadIdx.x] = Op::f(sh[threadIdx.x], t);
-    __syncthreads();
-  }
-  if (i < n) out[i] = (int)(kIncl ? sh[threadIdx.x] : (threadIdx.x ? sh[threadIdx.x - 1] : Op::id()));
-  if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = sh[threadIdx.x];
-}
-
-// one block: block totals -> exclusive block prefixes (serial over chunks); the grand total
-template <class Op>
-__global__ void __launch_bounds__(kScanBlock) k_scan_sums(long long nb, long long* __restrict__ sums,
-                                                            int* __restrict__ total) {
-  __shared__ long long sh[kScanBlock];
-  long long base = Op::id();
-  for (long long b0 = 0; b0 < nb; b0 += kScanBlock) {
-    const long long b = b0 + threadIdx.x;
-    const long long v = b < nb ? sums[b] : Op::id();
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < kScanBlock; o <<= 1) {
-      const long long t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : Op::id();
-      __syncthreads();
-      sh[threadIdx.x] = Op::f(sh[threadIdx.x], t);
-      __syncthreads();
-    }
-    const long long prev = threadIdx.x ? sh[threadIdx.x - 1] : Op::id();
-    if (b < nb) sums[b] = Op::f(base, prev);
-    const long long chunk = sh[kScanBlock - 1];
-    __syncthreads();
-    base = Op::f(base, chunk);
-  }
-  if (threadIdx.x == 0 && total) *total = (int)base;
-}
-
-template <class Op>
-__global__ void k_scan_apply(long long n, int* __restrict__ out, const long long* __restrict__ sums) {
-  const long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x;
-  if (i < n) out[i] = (int)Op::f(sums[blockIdx.x], out[i]);
 }
 
 __device__ __forceinline__ int cl_find(int* p, int x) {
@@ -265,15 +205,6 @@ ClWs cl_view(void* ws, long long n) {
   return w;
 }
 
-template <class Op, bool kIncl>
-void scan(const int* in, long long n, int* out, long long* sums, int* total, hipStream_t st) {
-  const long long nb = (n + kScanBlock - 1) / kScanBlock;
-  if (nb > 0)
-    hipLaunchKernelGGL((k_scan_blocks<Op, kIncl>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, out, sums);
-  hipLaunchKernelGGL((k_scan_sums<Op>), dim3(1), dim3(kScanBlock), 0, st, nb, sums, total);
-  if (nb > 0) hipLaunchKernelGGL((k_scan_apply<Op>), dim3((unsigned)nb), dim3(kScanBlock), 0, st, n, out, sums);
-}
-
 }  // namespace
 
 size_t cluster_workspace_bytes(long long rows, long long n_cells) {
@@ -292,13 +223,13 @@ hipError_t launch_cluster(const CellsIn& c, const GeomDev& g, const float* pitch
   const auto blocks = [](long long m) { return dim3((unsigned)((m + kClBlock - 1) / kClBlock)); };
   if (n > 0) hipLaunchKernelGGL(k_cl_init, blocks(n), dim3(kClBlock), 0, st, n, w.head, w.parent);
   if (rows > 0) hipLaunchKernelGGL(k_cl_heads, blocks(rows), dim3(kClBlock), 0, st, c, w.head, status);
-  scan<OpMax, true>(w.head, n, w.row, w.sums, nullptr, st);
+  device_scan<OpMax, true>(w.head, n, w.row, w.sums, nullptr, st);
   if (n > 0) {
     hipLaunchKernelGGL(k_cl_link, blocks(n), dim3(kClBlock), 0, st, c, w.row, w.parent, status);
     // the row heads are scanned already: their array takes the roots
     hipLaunchKernelGGL(k_cl_flatten, blocks(n), dim3(kClBlock), 0, st, n, w.parent, w.head, w.is_root);
   }
-  scan<OpSum, false>(w.is_root, n, w.cid, w.sums, w.n_cl, st);
+  device_scan<OpSum, false>(w.is_root, n, w.cid, w.sums, w.n_cl, st);
   if (n > 0) {
     hipLaunchKernelGGL(k_cl_roots, blocks(n), dim3(kClBlock), 0, st, n, w.head, w.cid, w.first, w.acc);
     hipLaunchKernelGGL(k_cl_sums, blocks(n), dim3(kClBlock), 0, st, c, w.row, w.head, w.cid, w.acc, cell_cluster);

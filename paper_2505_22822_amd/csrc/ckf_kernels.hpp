@@ -64,6 +64,11 @@ hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* 
                                 const int* msurf, const double* mpar, long long cap_pairs, float* x, int* label,
                                 int* track, long long* counts, void* ws, hipStream_t st);
 size_t fit_workspace_bytes(long long cap_meas);
+size_t seed_workspace_bytes(long long rows, long long n_sp, int n_events, int n_layers);
+hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int* moff, long long n_sp,
+                       const float* xyz, const float* loc, const int* layers, int n_layers, double bz, void* ws,
+                       long long cap, int* n_seeds, int* event, int* surface, double* params, double* cov,
+                       int* sp_ids, hipStream_t st);
 size_t cluster_workspace_bytes(long long rows, long long n_cells);
 hipError_t launch_cluster(const CellsIn& c, const GeomDev& g, const float* pitch, void* ws, int* moff, float* loc,
                           float* var, float* sp, int* cell_cluster, int* status, hipStream_t st);

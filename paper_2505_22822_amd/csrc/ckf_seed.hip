@@ -1,0 +1,322 @@
+// Triplet seeding and helix parameter estimation (paper section 2: triplets
+// of spacepoints that can approximately form a helix, and the track's
+// position and momentum estimated at the first spacepoint with the helix
+// model).
+//
+// Spacepoints are the measurements' global positions, in the measurement
+// layout (rows of (event, module)).  The seeding layers are a list ordered
+// outwards.  The kernels:
+//   rows    - every spacepoint's row by a max-scan of row heads;
+//   bin     - spacepoints of seeding layers keyed by (event, layer, phi bin)
+//             and counted; a sum-scan gives the bins' starts; a placement
+//             pass fills them (order inside a bin does not matter: a middle's
+//             candidates are all tested and ranked by value and index);
+//   triplet - one thread per spacepoint of an inner seeding layer: bottoms on
+//             lower and tops on higher layers, in the same and the two
+//             neighbouring phi bins (a bin is wider than the azimuth cut),
+//             go through the doublet and triplet cuts; the KEEP best by
+//             (d0, bottom, top) are kept;
+//   write   - a sum-scan of the per-middle counts places the seeds in middle
+//             order; each gets its helix estimate at the bottom spacepoint.
+// Every cut is computed in FP64 with the same operations in the same order
+// as its definition, and the file is compiled without contraction into
+// fused multiply-adds, so the decisions are the definition's to the bit.
+#include "ckf_device.hpp"
+#include "ckf_kernels.hpp"
+#include "ckf_scan.hpp"
+
+#pragma clang fp contract(off)
+
+namespace ckf {
+
+namespace {
+
+constexpr int kSdBlock = 256;
+constexpr int kNphi = 48;  // 0.1309 rad per bin, more than the azimuth cut
+constexpr int kKeep = 2;
+constexpr int kMaxSeedLayers = 8;
+constexpr double kKappa64 = 2.99792458e-4;
+constexpr double kCotMax = 3.0, kZ0Max = 200.0, kPtMin = 0.5, kD0Max = 1.0, kDcotBase = 0.01, kDcotMs = 0.007;
+constexpr double kSigma[5] = {0.2, 0.6, 0.01, 0.01, 0.15};
+
+struct SeedLayers {
+  int n;
+  int layer[kMaxSeedLayers];  // geometry layer id of seeding layer index i
+};
+
+__global__ void k_sd_heads(long long rows, const int* __restrict__ moff, long long n_sp, int* __restrict__ head) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int a = moff[r], b = moff[r + 1];
+  if (a >= 0 && a < b && (long long)b <= n_sp) head[a] = (int)r;
+}
+
+__global__ void k_sd_fill(long long n, int* __restrict__ head, int* __restrict__ cnt, int nbins) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) head[i] = -1;
+  if (i < nbins) cnt[i] = 0;
+}
+
+__device__ __forceinline__ int phi_bin(double x, double y) {
+  const double pi = 3.14159265358979323846;
+  int b = (int)floor((atan2(y, x) + pi) * (kNphi / (2.0 * pi)));
+  return b < 0 ? 0 : (b >= kNphi ? kNphi - 1 : b);
+}
+
+// key of every spacepoint (-1: not on a seeding layer) and the bin counts
+__global__ void k_sd_key(long long n, int n_surfaces, GeomDev g, SeedLayers sl, const int* __restrict__ row,
+                         const float* __restrict__ xyz, int* __restrict__ key, int* __restrict__ cnt) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = row[i];
+  int k = -1;
+  if (r >= 0) {
+    const int s = r % n_surfaces, e = r / n_surfaces;
+    Module M;
+    load_module(g, s, M);
+    int li = -1;
+    for (int q = 0; q < sl.n; ++q)
+      if (sl.layer[q] == M.layer) li = q;
+    if (li >= 0) {
+      k = (e * sl.n + li) * kNphi + phi_bin(xyz[3 * i], xyz[3 * i + 1]);
+      atomicAdd(&cnt[k], 1);
+    }
+  }
+  key[i] = k;
+}
+
+__global__ void k_sd_place(long long n, const int* __restrict__ key, const int* __restrict__ start,
+                           int* __restrict__ fill, int* __restrict__ sorted) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || key[i] < 0) return;
+  sorted[start[key[i]] + atomicAdd(&fill[key[i]], 1)] = (int)i;
+}
+
+struct P3 {
+  double x, y, z;
+};
+
+__device__ __forceinline__ P3 sp_at(const float* xyz, int i) {
+  return P3{(double)xyz[3 * i], (double)xyz[3 * i + 1], (double)xyz[3 * i + 2]};
+}
+
+// doublet cuts for an inner point p and an outer point q (see the oracle's
+// definition: the same operations, in the same order)
+__device__ __forceinline__ bool doublet(const P3& p, const P3& q, bool bottom, double tan_dphi, double& cot) {
+  const double rp = sqrt(p.x * p.x + p.y * p.y);
+  const double rq = sqrt(q.x * q.x + q.y * q.y);
+  const double dr = rq - rp;
+  if (!(dr > 0.0)) return false;
+  cot = (q.z - p.z) / dr;
+  if (!(fabs(cot) <= kCotMax)) return false;
+  if (bottom && !(fabs(p.z - rp * cot) <= kZ0Max)) return false;
+  const double dot = p.x * q.x + p.y * q.y;
+  const double cross = p.x * q.y - p.y * q.x;
+  return dot > 0.0 && fabs(cross) <= tan_dphi * dot;
+}
+
+__device__ __forceinline__ bool circle(const P3& a, const P3& b, const P3& c, double& ux, double& uy, double& R) {
+  const double d = 2.0 * (a.x * (b.y - c.y) + b.x * (c.y - a.y) + c.x * (a.y - b.y));
+  if (d == 0.0) return false;
+  const double a2 = a.x * a.x + a.y * a.y, b2 = b.x * b.x + b.y * b.y, c2 = c.x * c.x + c.y * c.y;
+  ux = (a2 * (b.y - c.y) + b2 * (c.y - a.y) + c2 * (a.y - b.y)) / d;
+  uy = (a2 * (c.x - b.x) + b2 * (a.x - c.x) + c2 * (b.x - a.x)) / d;
+  const double rx = a.x - ux, ry = a.y - uy;
+  R = sqrt(rx * rx + ry * ry);
+  return true;
+}
+
+struct Cand {
+  double d0;
+  int b, t;
+};
+
+__device__ __forceinline__ bool cand_less(const Cand& x, const Cand& y) {
+  return x.d0 < y.d0 || (x.d0 == y.d0 && (x.b < y.b || (x.b == y.b && x.t < y.t)));
+}
+
+__global__ void k_sd_triplets(long long n, int n_events, SeedLayers sl, const int* __restrict__ key,
+                              const int* __restrict__ start, const int* __restrict__ cnt,
+                              const int* __restrict__ sorted, const float* __restrict__ xyz, double rmin,
+                              double tan_dphi, int* __restrict__ count, int2* __restrict__ best_out) {
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  count[m] = 0;
+  const int km = key[m];
+  if (km < 0) return;
+  const int bin_m = km % kNphi, li_m = (km / kNphi) % sl.n, e = km / (kNphi * sl.n);
+  if (li_m == 0 || li_m == sl.n - 1) return;
+  const P3 M = sp_at(xyz, (int)m);
+  Cand best[kKeep];
+#pragma unroll
+  for (int k = 0; k < kKeep; ++k) best[k] = Cand{INFINITY, -1, -1};
+  for (int lb = 0; lb < li_m; ++lb)
+    for (int db = -1; db <= 1; ++db) {
+      const int kb = (e * sl.n + lb) * kNphi + (bin_m + db + kNphi) % kNphi;
+      for (int ib = start[kb]; ib < start[kb] + cnt[kb]; ++ib) {
+        const int b = sorted[ib];
+        const P3 B = sp_at(xyz, b);
+        double cb;
+        if (!doublet(B, M, true, tan_dphi, cb)) continue;
+        const double tol = kDcotBase + kDcotMs * (1.0 + cb * cb);
+        for (int lt = li_m + 1; lt < sl.n; ++lt)
+          for (int dt = -1; dt <= 1; ++dt) {
+            const int kt = (e * sl.n + lt) * kNphi + (bin_m + dt + kNphi) % kNphi;
+            for (int it = start[kt]; it < start[kt] + cnt[kt]; ++it) {
+              const int t = sorted[it];
+              const P3 T = sp_at(xyz, t);
+              double ct;
+              if (!doublet(M, T, false, tan_dphi, ct)) continue;
+              if (!(fabs(cb - ct) <= tol)) continue;
+              double ux, uy, R;
+              if (!circle(B, M, T, ux, uy, R)) continue;  // collinear: no finite circle, the triplet fails
+              if (!(R >= rmin)) continue;
+              const double d0 = fabs(sqrt(ux * ux + uy * uy) - R);
+              if (!(d0 <= kD0Max)) continue;
+              Cand c{d0, b, t};
+              if (!cand_less(c, best[kKeep - 1])) continue;
+              best[kKeep - 1] = c;
+#pragma unroll
+              for (int k = kKeep - 1; k > 0; --k)
+                if (cand_less(best[k], best[k - 1])) {
+                  const Cand tmp = best[k];
+                  best[k] = best[k - 1];
+                  best[k - 1] = tmp;
+                }
+            }
+          }
+      }
+    }
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kKeep; ++k) {
+    best_out[kKeep * m + k] = make_int2(best[k].b, best[k].t);
+    c += best[k].b >= 0 ? 1 : 0;
+  }
+  count[m] = c;
+}
+
+__global__ void k_sd_write(long long n, int n_surfaces, double bz, const int* __restrict__ row,
+                           const float* __restrict__ xyz, const float* __restrict__ loc,
+                           const int* __restrict__ count, const int* __restrict__ off,
+                           const int2* __restrict__ best, long long cap, int* __restrict__ event,
+                           int* __restrict__ surface, double* __restrict__ params, double* __restrict__ cov,
+                           int* __restrict__ sp_ids) {
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n || count[m] == 0) return;
+  const P3 M = sp_at(xyz, (int)m);
+  for (int k = 0; k < count[m]; ++k) {
+    const long long o = (long long)off[m] + k;
+    if (o >= cap) return;
+    const int b = best[kKeep * m + k].x, t = best[kKeep * m + k].y;
+    const P3 B = sp_at(xyz, b), T = sp_at(xyz, t);
+    double ux, uy, R;
+    circle(B, M, T, ux, uy, R);
+    const double rx = B.x - ux, ry = B.y - uy;
+    double tx = -ry / R, ty = rx / R;
+    if (tx * (M.x - B.x) + ty * (M.y - B.y) < 0.0) {
+      tx = -tx;
+      ty = -ty;
+    }
+    const double phi = atan2(ty, tx);
+    const double cr = (M.x - B.x) * (T.y - M.y) - (M.y - B.y) * (T.x - M.x);
+    const double q = ((cr < 0.0) == (bz > 0.0)) ? 1.0 : -1.0;
+    const double cx = T.x - B.x, cy = T.y - B.y;
+    const double chord = sqrt(cx * cx + cy * cy);
+    const double s = 2.0 * R * asin(fmin(1.0, chord / (2.0 * R)));
+    const double theta = atan2(s, T.z - B.z);
+    const double qop = q * sin(theta) / (kKappa64 * fabs(bz) * R);
+    const int rb = row[b];
+    event[o] = rb / n_surfaces;
+    surface[o] = rb % n_surfaces;
+    double* p = params + 5 * o;
+    p[0] = loc[2 * b];
+    p[1] = loc[2 * b + 1];
+    p[2] = phi;
+    p[3] = theta;
+    p[4] = qop;
+    double* C = cov + 15 * o;
+    for (int j = 0; j < 15; ++j) C[j] = 0.0;
+    C[0] = kSigma[0] * kSigma[0];
+    C[5] = kSigma[1] * kSigma[1];
+    C[9] = kSigma[2] * kSigma[2];
+    C[12] = kSigma[3] * kSigma[3];
+    C[14] = (kSigma[4] * qop) * (kSigma[4] * qop);
+    if (sp_ids) {
+      sp_ids[3 * o] = b;
+      sp_ids[3 * o + 1] = (int)m;
+      sp_ids[3 * o + 2] = t;
+    }
+  }
+}
+
+size_t al256s(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t seed_workspace_bytes(long long rows, long long n_sp, int n_events, int n_layers) {
+  (void)rows;
+  const long long n = n_sp > 0 ? n_sp : 1;
+  const long long nbins = (long long)n_events * n_layers * kNphi + 1;
+  const long long nb = (n > nbins ? n : nbins) / scan_detail::kScanBlock + 2;
+  return 5 * al256s((size_t)n * 4) + al256s((size_t)n * 8 * kKeep) + 3 * al256s((size_t)nbins * 4) +
+         al256s((size_t)nb * 8) + 512;
+}
+
+hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int* moff, long long n_sp,
+                       const float* xyz, const float* loc, const int* layers, int n_layers, double bz, void* ws,
+                       long long cap, int* n_seeds, int* event, int* surface, double* params, double* cov,
+                       int* sp_ids, hipStream_t st) {
+  SeedLayers sl;
+  sl.n = n_layers;
+  for (int q = 0; q < kMaxSeedLayers; ++q) sl.layer[q] = q < n_layers ? layers[q] : -1;
+  const long long rows = (long long)n_events * n_surfaces;
+  const long long n = n_sp;
+  const long long nbins = (long long)n_events * n_layers * kNphi;
+  char* p = static_cast<char*>(ws);
+  const long long na = n > 0 ? n : 1;
+  int* head = reinterpret_cast<int*>(p);
+  p += al256s((size_t)na * 4);
+  int* row = reinterpret_cast<int*>(p);
+  p += al256s((size_t)na * 4);
+  int* key = reinterpret_cast<int*>(p);
+  p += al256s((size_t)na * 4);
+  int* sorted = reinterpret_cast<int*>(p);
+  p += al256s((size_t)na * 4);
+  int* count = reinterpret_cast<int*>(p);
+  p += al256s((size_t)na * 4);
+  int2* best = reinterpret_cast<int2*>(p);
+  p += al256s((size_t)na * 8 * kKeep);
+  int* cnt = reinterpret_cast<int*>(p);
+  p += al256s((size_t)(nbins + 1) * 4);
+  int* start = reinterpret_cast<int*>(p);
+  p += al256s((size_t)(nbins + 1) * 4);
+  int* fill = reinterpret_cast<int*>(p);
+  p += al256s((size_t)(nbins + 1) * 4);
+  long long* sums = reinterpret_cast<long long*>(p);
+  const auto blocks = [](long long m) { return dim3((unsigned)((m + kSdBlock - 1) / kSdBlock)); };
+  const long long nfill = n > nbins ? n : nbins;
+  if (nfill > 0) {
+    hipLaunchKernelGGL(k_sd_fill, blocks(nfill), dim3(kSdBlock), 0, st, n, head, cnt, (int)nbins);
+    hipLaunchKernelGGL(k_sd_fill, blocks(nbins > 0 ? nbins : 1), dim3(kSdBlock), 0, st, 0ll, head, fill, (int)nbins);
+  }
+  if (rows > 0) hipLaunchKernelGGL(k_sd_heads, blocks(rows), dim3(kSdBlock), 0, st, rows, moff, n, head);
+  device_scan<OpMax, true>(head, n, row, sums, nullptr, st);
+  if (n > 0)
+    hipLaunchKernelGGL(k_sd_key, blocks(n), dim3(kSdBlock), 0, st, n, n_surfaces, g, sl, row, xyz, key, cnt);
+  device_scan<OpSum, false>(cnt, nbins, start, sums, nullptr, st);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_sd_place, blocks(n), dim3(kSdBlock), 0, st, n, key, start, fill, sorted);
+    const double rmin = kPtMin / (kKappa64 * fabs(bz));
+    const double tan_dphi = tan(0.12);
+    hipLaunchKernelGGL(k_sd_triplets, blocks(n), dim3(kSdBlock), 0, st, n, n_events, sl, key, start, cnt, sorted,
+                       xyz, rmin, tan_dphi, count, best);
+  }
+  device_scan<OpSum, false>(count, n, head, sums, n_seeds, st);  // head now holds the seed offsets
+  if (n > 0)
+    hipLaunchKernelGGL(k_sd_write, blocks(n), dim3(kSdBlock), 0, st, n, n_surfaces, bz, row, xyz, loc, count, head,
+                       best, cap, event, surface, params, cov, sp_ids);
+  return hipGetLastError();
+}
+
+}  // namespace ckf

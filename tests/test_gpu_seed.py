@@ -1,0 +1,155 @@
+"""Triplet seeding on the GPU (ckf_seed) against the oracle on the same
+spacepoints: the same triplets in the same order and the same parameters on
+a mu = 20 event; sampled middle spacepoints of an 8 x mu = 200 batch; the
+chain cells -> clusters -> seeds -> tracks on the GPU; edge cases."""
+import sys
+
+import numpy as np
+import pytest
+
+from synth import make_event
+from synth.cells import cell_grid, concat_cells, make_cells
+
+pytestmark = pytest.mark.gpu
+LAYERS = [0, 1, 2, 3]   # the pixel barrel layers of the dense detector, outwards
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ckf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_22822_amd as ckf
+    return ckf
+
+
+def _clusters_on_device(det, cells, ckf):
+    import torch
+    geo = ckf.Geometry(det.as_arrays())
+    _, pitch = cell_grid(det)
+    cl = ckf.Clusterer(geo, ckf.CellBatch.from_cells(cells), torch.as_tensor(pitch, device="cuda"))
+    cl.enqueue()
+    r = cl.result()
+    m = r["n_meas"]
+    return geo, cl, r, m
+
+
+def _layer_index(det, offsets, n_events):
+    S = det.n_surfaces
+    rows = np.repeat(np.arange(n_events * S), np.diff(offsets))
+    layer = det.as_arrays()["layer"][rows % S]
+    li = np.full(len(rows), -1)
+    for k, L in enumerate(LAYERS):
+        li[layer == L] = k
+    return li, rows
+
+
+def test_seed_matches_oracle(ckf, det_dense):
+    """A mu = 20 event's clusters: the GPU's seeds are the oracle's, triplet
+    by triplet in the same order, on the same modules, with parameters to
+    1e-12 relative (FP64 on both sides)."""
+    from oracle import seeding as OS
+    ev = make_event(det_dense, 6000, mu=20)
+    cells = make_cells(det_dense, ev, 1)
+    geo, cl, r, m = _clusters_on_device(det_dense, cells, ckf)
+    sd, n = ckf.seed(geo, 1, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+    li, rows = _layer_index(det_dense, r["offsets"], 1)
+    ref = OS.seeds(r["spacepoints"].astype(np.float64), li, rows, r["loc"].astype(np.float64), 2.0)
+    _say(f"# seeding: {m} spacepoints, {n} seeds (oracle {len(ref['middle'])})")
+    sp = sd["spacepoints"].cpu().numpy()
+    assert n == len(ref["middle"])
+    np.testing.assert_array_equal(sp[:, 0], ref["bottom"])
+    np.testing.assert_array_equal(sp[:, 1], ref["middle"])
+    np.testing.assert_array_equal(sp[:, 2], ref["top"])
+    np.testing.assert_array_equal(sd["surface"].cpu().numpy(), ref["surface"])
+    assert np.all(sd["event"].cpu().numpy() == 0)
+    p = sd["params"].cpu().numpy()
+    np.testing.assert_allclose(p, ref["params"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(sd["cov"].cpu().numpy(), ref["cov"], rtol=1e-12, atol=0)
+
+
+def test_seed_batch_sampled_middles(ckf, det_dense):
+    """8 x mu = 200 events in one call: for 400 sampled middle spacepoints
+    the oracle, on that middle's event alone, keeps the same triplets."""
+    from oracle import seeding as OS
+    evs = [make_event(det_dense, 7100 + i, mu=200) for i in range(8)]
+    cells = concat_cells([make_cells(det_dense, e, 200 + i) for i, e in enumerate(evs)])
+    geo, cl, r, m = _clusters_on_device(det_dense, cells, ckf)
+    sd, n = ckf.seed(geo, 8, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+    sp = sd["spacepoints"].cpu().numpy()
+    _say(f"# seeding batch: {m} spacepoints, {n} seeds")
+    li, rows = _layer_index(det_dense, r["offsets"], 8)
+    S = det_dense.n_surfaces
+    ev_of = rows // S
+    xyz = r["spacepoints"].astype(np.float64)
+    rng = np.random.default_rng(9)
+    middles = rng.choice(np.nonzero((li == 1) | (li == 2))[0], 400, replace=False)
+    for mid in middles:
+        e = ev_of[mid]
+        idx = np.nonzero(ev_of == e)[0]
+        local = np.searchsorted(idx, mid)
+        ref = OS.triplets(xyz[idx], li[idx], 2.0, middles=[local])
+        got = sp[sp[:, 1] == mid]
+        assert [(idx[b], idx[t]) for _, b, t, _ in ref] == [(int(a), int(c)) for a, _, c in got], mid
+
+
+def test_chain_cells_to_tracks(ckf, det_dense):
+    """cells -> clusters -> seeds -> tracks, all on the GPU, for a mu = 50
+    event: most central particles (|eta| < 1.2, pT > 0.6 GeV, |z_vertex|
+    < 150 mm) end with a track made mostly of their own clusters."""
+    import torch
+    ev = make_event(det_dense, 6200, mu=50)
+    cells = make_cells(det_dense, ev, 4)
+    geo, cl, r, m = _clusters_on_device(det_dense, cells, ckf)
+    sd, n = ckf.seed(geo, 1, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+    cc = r["cell_cluster"]
+    o = np.lexsort((-cells.q, cc))
+    first = o[np.r_[True, cc[o][1:] != cc[o][:-1]]]
+    cl_part = np.full(m, -1, np.int64)
+    cl_part[cc[first]] = cells.particle[first]
+    b = ckf.Batch(1, ev.n_surfaces, cl.offsets, cl.loc[:m].contiguous(), cl.var[:m].contiguous(),
+                  sd["event"].contiguous(), sd["surface"].contiguous(), sd["params"].contiguous(),
+                  sd["cov"].contiguous())
+    res = ckf.find(geo, ckf.UniformField(0, 0, 2.0), b)
+    found = set()
+    for k in range(res["n_tracks"]):
+        ids = res["meas"][res["offsets"][k]:res["offsets"][k + 1]]
+        parts, cnt = np.unique(cl_part[ids], return_counts=True)
+        j = int(np.argmax(cnt))
+        if parts[j] >= 0 and cnt[j] > len(ids) / 2:
+            found.add(int(parts[j]))
+    cen = [p for p in range(len(ev.particle_pt))
+           if abs(ev.particle_eta[p]) < 1.2 and ev.particle_pt[p] > 0.6 and abs(ev.particle_vtx[p, 2]) < 150]
+    eff = np.mean([p in found for p in cen])
+    _say(f"# chain: {m} clusters, {n} seeds, {res['n_tracks']} tracks, central particles found {eff:.4f}")
+    assert len(cen) > 500 and eff > 0.95
+
+
+def test_seed_edge_cases(ckf, det_dense):
+    """No spacepoints; fewer than three or unknown seeding layers are
+    rejected; a short capacity counts all seeds and writes the first."""
+    import torch
+    from paper_2505_22822_amd import CkfError
+    geo = ckf.Geometry(det_dense.as_arrays())
+    S = det_dense.n_surfaces
+    off = torch.zeros(S + 1, dtype=torch.int32, device="cuda")
+    z3 = torch.zeros((1, 3), dtype=torch.float32, device="cuda")
+    z2 = torch.zeros((1, 2), dtype=torch.float32, device="cuda")
+    sd, n = ckf.seed(geo, 1, off, z3[:0], z2[:0], LAYERS, 2.0)
+    assert n == 0
+    with pytest.raises(CkfError):
+        ckf.seed(geo, 1, off, z3[:0], z2[:0], [0, 1], 2.0)
+    with pytest.raises(CkfError):
+        ckf.seed(geo, 1, off, z3[:0], z2[:0], [0, 1, 999], 2.0)
+    ev = make_event(det_dense, 6000, mu=20)
+    cells = make_cells(det_dense, ev, 1)
+    geo, cl, r, m = _clusters_on_device(det_dense, cells, ckf)
+    full, n_full = ckf.seed(geo, 1, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+    part, n_part = ckf.seed(geo, 1, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0, cap_seeds=100)
+    assert n_part == n_full > 100 and part["params"].shape[0] == 100
+    np.testing.assert_array_equal(part["spacepoints"].cpu().numpy(), full["spacepoints"][:100].cpu().numpy())
