@@ -325,11 +325,75 @@ def measure_cluster(ckf, geo, det, cells, stream, reps):
     r = cl.result()
     rows = cells.n_events * cells.n_surfaces
     algo = 16 * cells.n_cells + 28 * r["n_meas"] + 8 * rows
+    measure_cluster.last = cl
     return dict(cells=cells.n_cells, clusters=r["n_meas"], status=r["status"], ms=round(ms, 4),
                 cells_per_s=round(cells.n_cells / (ms * 1e-3), 1),
                 roofline=dict(bound="hbm", achieved=round(algo / (ms * 1e-3) / 1e9, 1), peak=8000.0, unit="GB/s",
                               frac=round(algo / (ms * 1e-3) / 8e12, 5), traffic=None, kernel="k_cl_*",
                               algorithmic_bytes=int(algo)))
+
+
+SEED_LAYERS = [0, 1, 2, 3]  # the pixel barrel layers, outwards
+
+
+def measure_chain(ckf, geo, fld, det, cells, evs, cl, cl_ms, stream, reps):
+    """Seeding on the batch's clusters (device time of one ckf_seed, mean of
+    reps), then the track finder on the clusters with those seeds (one
+    call): the chain cells -> clusters -> seeds -> tracks, and the share of
+    central particles (|eta| < 1.2, pT > 0.6 GeV, |z_vertex| < 150 mm) whose
+    clusters make the majority of a track."""
+    import torch
+    r = cl.result()
+    m = r["n_meas"]
+    args = (geo, cells.n_events, cl.offsets, cl.spacepoints[:m], cl.loc[:m], SEED_LAYERS, 2.0)
+    sd, n = ckf.seed(*args, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ckf.seed(*args, cap_seeds=int(sd["params"].shape[0]), stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seed_ms = e0.elapsed_time(e1) / reps
+    b = ckf.Batch(cells.n_events, cells.n_surfaces, cl.offsets, cl.loc[:m].contiguous(), cl.var[:m].contiguous(),
+                  sd["event"].contiguous(), sd["surface"].contiguous(), sd["params"].contiguous(),
+                  sd["cov"].contiguous())
+    timer = ckf.KernelTimer()
+    f = ckf.Finder(geo, fld, b, ckf.config(), ckf.launch(timer=timer), counters=False)
+    f.enqueue(stream)
+    res = f.result(check=False)
+    f.enqueue(stream)
+    torch.cuda.synchronize()
+    find_ms = timer.elapsed_ms()
+    flags = int(res["status"][0])
+    # truth of a cluster: its largest-charge cell's particle (global particle ids per event)
+    cc = r["cell_cluster"]
+    o = np.lexsort((-cells.q, cc))
+    first = o[np.r_[True, cc[o][1:] != cc[o][:-1]]]
+    cell_event = np.repeat(np.arange(cells.n_events), np.diff(cells.offsets[::cells.n_surfaces]))
+    part = np.full(m, -1, np.int64)
+    base = np.cumsum([0] + [len(e.particle_pt) for e in evs])
+    pid = cells.particle[first]
+    part[cc[first]] = np.where(pid >= 0, pid + base[cell_event[first]], -1)
+    tid = np.repeat(np.arange(res["n_tracks"]), np.diff(res["offsets"]))
+    tp = part[res["meas"]]
+    found = set()
+    if res["n_tracks"]:
+        key = tid.astype(np.int64) * (base[-1] + 1) + (tp + 1)
+        uk, cnt = np.unique(key, return_counts=True)
+        t_of, p_of = uk // (base[-1] + 1), uk % (base[-1] + 1) - 1
+        n_of = np.diff(res["offsets"])[t_of]
+        ok = (p_of >= 0) & (cnt > n_of / 2)
+        found = set(p_of[ok].tolist())
+    cen = np.concatenate([base[i] + np.nonzero((np.abs(e.particle_eta) < 1.2) & (e.particle_pt > 0.6) &
+                                               (np.abs(e.particle_vtx[:, 2]) < 150))[0] for i, e in enumerate(evs)])
+    eff = float(np.mean([p in found for p in cen.tolist()])) if len(cen) else 0.0
+    chain_ms = cl_ms + seed_ms + find_ms
+    return dict(seeds=n, seed_ms=round(seed_ms, 4), seeds_per_s=round(n / (seed_ms * 1e-3), 1),
+                tracks=res["n_tracks"], find_ms=round(find_ms, 4), chain_ms=round(chain_ms, 4),
+                chain_tracks_per_s=round(res["n_tracks"] / (chain_ms * 1e-3), 1), central_particles=int(len(cen)),
+                central_found=round(eff, 5), find_status_flags=flags,
+                note="device times of one ckf_cluster, one ckf_seed and one ckf_find (kernel timer) on the batch")
 
 
 def roofline_of(m, form, shape):
@@ -445,6 +509,11 @@ def main():
     say(f"# clustering of the batch's {clu['cells']} cells: {clu['clusters']} clusters in {clu['ms']:.3f} ms "
         f"({clu['cells_per_s'] / 1e9:.2f} G cells/s, {clu['roofline']['achieved']:.0f} GB/s algorithmic), "
         f"status {clu['status']}")
+    chain = measure_chain(ckf, geo, fld, det, cells, evs, measure_cluster.last, clu["ms"], stream,
+                          max(3, args.steps // 4))
+    say(f"# seeding on the clusters: {chain['seeds']} seeds in {chain['seed_ms']:.3f} ms; track finding with them: "
+        f"{chain['tracks']} tracks in {chain['find_ms']:.3f} ms; chain cells -> tracks {chain['chain_ms']:.2f} ms "
+        f"({chain['chain_tracks_per_s'] / 1e6:.2f} M tracks/s), central particles found {chain['central_found']:.4f}")
     say(f"# ambiguity resolution of the plain search's tracks: {amb['ms']:.2f} ms, {amb['rounds']} rounds, "
         f"{amb['removed']} of {amb['tracks_in']} removed; fake rate {amb['before']['fake_rate']:.5f} -> "
         f"{amb['after']['fake_rate']:.5f}, duplicate rate {amb['before']['duplicate_rate']:.5f} -> "
@@ -516,7 +585,7 @@ def main():
                 roofline=roofline_of(head, "learned" if learned_info else "plain",
                                      learned_info["launch"] if learned_info else shape_plain),
                 plain_roofline=roofline_of(plain, "plain", shape_plain),
-                fit=fit, ambiguity=amb, clustering=clu, cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
+                fit=fit, ambiguity=amb, clustering=clu, chain=chain, cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
     print(json.dumps(line))
 
 

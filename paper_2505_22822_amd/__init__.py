@@ -558,6 +558,7 @@ def seed(geometry: Geometry, n_events: int, meas_offsets, spacepoints, loc, laye
                         lay.ctypes.data_as(C.c_void_p), nl, float(bz), _ptr(ws), ws.numel(), cap, _ptr(n),
                         _ptr(out["event"]), _ptr(out["surface"]), _ptr(out["params"]), _ptr(out["cov"]),
                         _ptr(out["spacepoints"]), _stream_handle(stream)), "ckf_seed")
+    torch.cuda.synchronize()  # the count is read on the host: wait for the call's stream, whichever it is
     k = int(n.cpu()[0])
     m = min(k, cap)
     return {key: v[:m] for key, v in out.items()}, k

@@ -7,15 +7,20 @@
 // layout (rows of (event, module)).  The seeding layers are a list ordered
 // outwards.  The kernels:
 //   rows    - every spacepoint's row by a max-scan of row heads;
-//   bin     - spacepoints of seeding layers keyed by (event, layer, phi bin)
-//             and counted; a sum-scan gives the bins' starts; a placement
-//             pass fills them (order inside a bin does not matter: a middle's
-//             candidates are all tested and ranked by value and index);
-//   triplet - one thread per spacepoint of an inner seeding layer: bottoms on
-//             lower and tops on higher layers, in the same and the two
-//             neighbouring phi bins (a bin is wider than the azimuth cut),
-//             go through the doublet and triplet cuts; the KEEP best by
-//             (d0, bottom, top) are kept;
+//   bin     - spacepoints of seeding layers keyed by (event, layer, phi bin,
+//             z bin) and counted, each layer's radius range taken; a
+//             sum-scan gives the bins' starts; a placement pass fills them
+//             (order inside a bin does not matter: a middle's candidates are
+//             all tested and ranked by value and index);
+//   triplet - one thread per spacepoint of an inner seeding layer.  Bottoms
+//             come from lower layers in the same and the two neighbouring
+//             phi bins (a bin is wider than the azimuth cut) and in the z
+//             bins the beam-line cut allows at that layer's radii; for each
+//             bottom that passes, tops come from higher layers in the z bins
+//             its cot window allows.  The windows are bilinear in the radius
+//             and the cut variable, so their corners bound them; they get a
+//             1 mm margin and only select candidates: every cut is then
+//             applied as defined.  The KEEP best by (d0, bottom, top) stay;
 //   write   - a sum-scan of the per-middle counts places the seeds in middle
 //             order; each gets its helix estimate at the bottom spacepoint.
 // Every cut is computed in FP64 with the same operations in the same order
@@ -33,6 +38,8 @@ namespace {
 
 constexpr int kSdBlock = 256;
 constexpr int kNphi = 48;  // 0.1309 rad per bin, more than the azimuth cut
+constexpr int kNz = 40;    // 30 mm bins over |z| < 600 mm (the edge bins take the rest)
+constexpr double kZLo = -600.0, kZBin = 30.0, kZMargin = 1.0;
 constexpr int kKeep = 2;
 constexpr int kMaxSeedLayers = 8;
 constexpr double kKappa64 = 2.99792458e-4;
@@ -51,10 +58,20 @@ __global__ void k_sd_heads(long long rows, const int* __restrict__ moff, long lo
   if (a >= 0 && a < b && (long long)b <= n_sp) head[a] = (int)r;
 }
 
-__global__ void k_sd_fill(long long n, int* __restrict__ head, int* __restrict__ cnt, int nbins) {
+__global__ void k_sd_fill(long long n, int* __restrict__ head, int* __restrict__ cnt, int nbins,
+                          unsigned* __restrict__ rlim) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) head[i] = -1;
   if (i < nbins) cnt[i] = 0;
+  if (rlim && i < kMaxSeedLayers) {
+    rlim[2 * i] = 0x7f800000u;  // +inf: minimum radius of the layer's spacepoints
+    rlim[2 * i + 1] = 0u;       // maximum
+  }
+}
+
+__device__ __forceinline__ int z_bin(double z) {
+  const double b = floor((z - kZLo) / kZBin);  // clamped before the conversion: NaN and inf map to bin 0
+  return !(b >= 0.0) ? 0 : (b >= (double)kNz ? kNz - 1 : (int)b);
 }
 
 __device__ __forceinline__ int phi_bin(double x, double y) {
@@ -65,7 +82,8 @@ __device__ __forceinline__ int phi_bin(double x, double y) {
 
 // key of every spacepoint (-1: not on a seeding layer) and the bin counts
 __global__ void k_sd_key(long long n, int n_surfaces, GeomDev g, SeedLayers sl, const int* __restrict__ row,
-                         const float* __restrict__ xyz, int* __restrict__ key, int* __restrict__ cnt) {
+                         const float* __restrict__ xyz, int* __restrict__ key, int* __restrict__ cnt,
+                         unsigned* __restrict__ rlim) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int r = row[i];
@@ -78,8 +96,12 @@ __global__ void k_sd_key(long long n, int n_surfaces, GeomDev g, SeedLayers sl, 
     for (int q = 0; q < sl.n; ++q)
       if (sl.layer[q] == M.layer) li = q;
     if (li >= 0) {
-      k = (e * sl.n + li) * kNphi + phi_bin(xyz[3 * i], xyz[3 * i + 1]);
+      const double x = xyz[3 * i], y = xyz[3 * i + 1];
+      k = ((e * sl.n + li) * kNphi + phi_bin(x, y)) * kNz + z_bin(xyz[3 * i + 2]);
       atomicAdd(&cnt[k], 1);
+      const float r = (float)sqrt(x * x + y * y);  // radius bounds (positive floats order as their bits)
+      atomicMin(&rlim[2 * li], __float_as_uint(r));
+      atomicMax(&rlim[2 * li + 1], __float_as_uint(r));
     }
   }
   key[i] = k;
@@ -135,58 +157,83 @@ __device__ __forceinline__ bool cand_less(const Cand& x, const Cand& y) {
   return x.d0 < y.d0 || (x.d0 == y.d0 && (x.b < y.b || (x.b == y.b && x.t < y.t)));
 }
 
+__device__ __forceinline__ void z_window(double a00, double a01, double a10, double a11, int& b0, int& b1) {
+  const double lo = fmin(fmin(a00, a01), fmin(a10, a11)) - kZMargin;
+  const double hi = fmax(fmax(a00, a01), fmax(a10, a11)) + kZMargin;
+  b0 = z_bin(lo);
+  b1 = z_bin(hi);
+}
+
 __global__ void k_sd_triplets(long long n, int n_events, SeedLayers sl, const int* __restrict__ key,
                               const int* __restrict__ start, const int* __restrict__ cnt,
-                              const int* __restrict__ sorted, const float* __restrict__ xyz, double rmin,
-                              double tan_dphi, int* __restrict__ count, int2* __restrict__ best_out) {
+                              const int* __restrict__ sorted, const float* __restrict__ xyz,
+                              const unsigned* __restrict__ rlim, double rmin, double tan_dphi,
+                              int* __restrict__ count, int2* __restrict__ best_out) {
   const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   count[m] = 0;
   const int km = key[m];
   if (km < 0) return;
-  const int bin_m = km % kNphi, li_m = (km / kNphi) % sl.n, e = km / (kNphi * sl.n);
+  const int bin_m = (km / kNz) % kNphi, li_m = (km / (kNz * kNphi)) % sl.n, e = km / (kNz * kNphi * sl.n);
   if (li_m == 0 || li_m == sl.n - 1) return;
   const P3 M = sp_at(xyz, (int)m);
+  const double rM = sqrt(M.x * M.x + M.y * M.y);
   Cand best[kKeep];
 #pragma unroll
   for (int k = 0; k < kKeep; ++k) best[k] = Cand{INFINITY, -1, -1};
-  for (int lb = 0; lb < li_m; ++lb)
-    for (int db = -1; db <= 1; ++db) {
-      const int kb = (e * sl.n + lb) * kNphi + (bin_m + db + kNphi) % kNphi;
-      for (int ib = start[kb]; ib < start[kb] + cnt[kb]; ++ib) {
-        const int b = sorted[ib];
-        const P3 B = sp_at(xyz, b);
-        double cb;
-        if (!doublet(B, M, true, tan_dphi, cb)) continue;
-        const double tol = kDcotBase + kDcotMs * (1.0 + cb * cb);
-        for (int lt = li_m + 1; lt < sl.n; ++lt)
-          for (int dt = -1; dt <= 1; ++dt) {
-            const int kt = (e * sl.n + lt) * kNphi + (bin_m + dt + kNphi) % kNphi;
-            for (int it = start[kt]; it < start[kt] + cnt[kt]; ++it) {
-              const int t = sorted[it];
-              const P3 T = sp_at(xyz, t);
-              double ct;
-              if (!doublet(M, T, false, tan_dphi, ct)) continue;
-              if (!(fabs(cb - ct) <= tol)) continue;
-              double ux, uy, R;
-              if (!circle(B, M, T, ux, uy, R)) continue;  // collinear: no finite circle, the triplet fails
-              if (!(R >= rmin)) continue;
-              const double d0 = fabs(sqrt(ux * ux + uy * uy) - R);
-              if (!(d0 <= kD0Max)) continue;
-              Cand c{d0, b, t};
-              if (!cand_less(c, best[kKeep - 1])) continue;
-              best[kKeep - 1] = c;
+  for (int lb = 0; lb < li_m; ++lb) {
+    // bottoms: z_B = z0 + r_B (z_M - z0) / r_M for |z0| <= Z0_MAX, r_B in the layer's range
+    const double r0 = __uint_as_float(rlim[2 * lb]), r1 = __uint_as_float(rlim[2 * lb + 1]);
+    if (!(r0 <= r1)) continue;  // no spacepoints on that layer
+    int zb0, zb1;
+    z_window(-kZ0Max + r0 * (M.z + kZ0Max) / rM, kZ0Max + r0 * (M.z - kZ0Max) / rM,
+             -kZ0Max + r1 * (M.z + kZ0Max) / rM, kZ0Max + r1 * (M.z - kZ0Max) / rM, zb0, zb1);
+    for (int db = -1; db <= 1; ++db)
+      for (int zb = zb0; zb <= zb1; ++zb) {
+        const int kb = ((e * sl.n + lb) * kNphi + (bin_m + db + kNphi) % kNphi) * kNz + zb;
+        for (int ib = start[kb]; ib < start[kb] + cnt[kb]; ++ib) {
+          const int b = sorted[ib];
+          const P3 B = sp_at(xyz, b);
+          double cb;
+          if (!doublet(B, M, true, tan_dphi, cb)) continue;
+          const double tol = kDcotBase + kDcotMs * (1.0 + cb * cb);
+          for (int lt = li_m + 1; lt < sl.n; ++lt) {
+            // tops: z_T = z_M + (r_T - r_M) cot_T for cot_T within tol of cot_BM
+            const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
+            if (!(s0 <= s1)) continue;
+            int zt0, zt1;
+            z_window(M.z + s0 * (cb - tol), M.z + s0 * (cb + tol), M.z + s1 * (cb - tol), M.z + s1 * (cb + tol),
+                     zt0, zt1);
+            for (int dt = -1; dt <= 1; ++dt)
+              for (int zt = zt0; zt <= zt1; ++zt) {
+                const int kt = ((e * sl.n + lt) * kNphi + (bin_m + dt + kNphi) % kNphi) * kNz + zt;
+                for (int it = start[kt]; it < start[kt] + cnt[kt]; ++it) {
+                  const int t = sorted[it];
+                  const P3 T = sp_at(xyz, t);
+                  double ct;
+                  if (!doublet(M, T, false, tan_dphi, ct)) continue;
+                  if (!(fabs(cb - ct) <= tol)) continue;
+                  double ux, uy, R;
+                  if (!circle(B, M, T, ux, uy, R)) continue;  // collinear: no finite circle, the triplet fails
+                  if (!(R >= rmin)) continue;
+                  const double d0 = fabs(sqrt(ux * ux + uy * uy) - R);
+                  if (!(d0 <= kD0Max)) continue;
+                  Cand c{d0, b, t};
+                  if (!cand_less(c, best[kKeep - 1])) continue;
+                  best[kKeep - 1] = c;
 #pragma unroll
-              for (int k = kKeep - 1; k > 0; --k)
-                if (cand_less(best[k], best[k - 1])) {
-                  const Cand tmp = best[k];
-                  best[k] = best[k - 1];
-                  best[k - 1] = tmp;
+                  for (int k = kKeep - 1; k > 0; --k)
+                    if (cand_less(best[k], best[k - 1])) {
+                      const Cand tmp = best[k];
+                      best[k] = best[k - 1];
+                      best[k - 1] = tmp;
+                    }
                 }
-            }
+              }
           }
+        }
       }
-    }
+  }
   int c = 0;
 #pragma unroll
   for (int k = 0; k < kKeep; ++k) {
@@ -257,10 +304,10 @@ size_t al256s(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t seed_workspace_bytes(long long rows, long long n_sp, int n_events, int n_layers) {
   (void)rows;
   const long long n = n_sp > 0 ? n_sp : 1;
-  const long long nbins = (long long)n_events * n_layers * kNphi + 1;
+  const long long nbins = (long long)n_events * n_layers * kNphi * kNz + 1;
   const long long nb = (n > nbins ? n : nbins) / scan_detail::kScanBlock + 2;
   return 5 * al256s((size_t)n * 4) + al256s((size_t)n * 8 * kKeep) + 3 * al256s((size_t)nbins * 4) +
-         al256s((size_t)nb * 8) + 512;
+         al256s((size_t)nb * 8) + 256 + 512;
 }
 
 hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int* moff, long long n_sp,
@@ -272,7 +319,7 @@ hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int
   for (int q = 0; q < kMaxSeedLayers; ++q) sl.layer[q] = q < n_layers ? layers[q] : -1;
   const long long rows = (long long)n_events * n_surfaces;
   const long long n = n_sp;
-  const long long nbins = (long long)n_events * n_layers * kNphi;
+  const long long nbins = (long long)n_events * n_layers * kNphi * kNz;
   char* p = static_cast<char*>(ws);
   const long long na = n > 0 ? n : 1;
   int* head = reinterpret_cast<int*>(p);
@@ -293,24 +340,27 @@ hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int
   p += al256s((size_t)(nbins + 1) * 4);
   int* fill = reinterpret_cast<int*>(p);
   p += al256s((size_t)(nbins + 1) * 4);
+  unsigned* rlim = reinterpret_cast<unsigned*>(p);
+  p += 256;
   long long* sums = reinterpret_cast<long long*>(p);
   const auto blocks = [](long long m) { return dim3((unsigned)((m + kSdBlock - 1) / kSdBlock)); };
   const long long nfill = n > nbins ? n : nbins;
   if (nfill > 0) {
-    hipLaunchKernelGGL(k_sd_fill, blocks(nfill), dim3(kSdBlock), 0, st, n, head, cnt, (int)nbins);
-    hipLaunchKernelGGL(k_sd_fill, blocks(nbins > 0 ? nbins : 1), dim3(kSdBlock), 0, st, 0ll, head, fill, (int)nbins);
+    hipLaunchKernelGGL(k_sd_fill, blocks(nfill), dim3(kSdBlock), 0, st, n, head, cnt, (int)nbins, rlim);
+    hipLaunchKernelGGL(k_sd_fill, blocks(nbins > 0 ? nbins : 1), dim3(kSdBlock), 0, st, 0ll, head, fill, (int)nbins,
+                       (unsigned*)nullptr);
   }
   if (rows > 0) hipLaunchKernelGGL(k_sd_heads, blocks(rows), dim3(kSdBlock), 0, st, rows, moff, n, head);
   device_scan<OpMax, true>(head, n, row, sums, nullptr, st);
   if (n > 0)
-    hipLaunchKernelGGL(k_sd_key, blocks(n), dim3(kSdBlock), 0, st, n, n_surfaces, g, sl, row, xyz, key, cnt);
+    hipLaunchKernelGGL(k_sd_key, blocks(n), dim3(kSdBlock), 0, st, n, n_surfaces, g, sl, row, xyz, key, cnt, rlim);
   device_scan<OpSum, false>(cnt, nbins, start, sums, nullptr, st);
   if (n > 0) {
     hipLaunchKernelGGL(k_sd_place, blocks(n), dim3(kSdBlock), 0, st, n, key, start, fill, sorted);
     const double rmin = kPtMin / (kKappa64 * fabs(bz));
     const double tan_dphi = tan(0.12);
     hipLaunchKernelGGL(k_sd_triplets, blocks(n), dim3(kSdBlock), 0, st, n, n_events, sl, key, start, cnt, sorted,
-                       xyz, rmin, tan_dphi, count, best);
+                       xyz, rlim, rmin, tan_dphi, count, best);
   }
   device_scan<OpSum, false>(count, n, head, sums, n_seeds, st);  // head now holds the seed offsets
   if (n > 0)
