@@ -449,6 +449,15 @@ ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas
                     int32_t* seed_event, int32_t* seed_surface, double* seed_params, double* seed_cov,
                     int32_t* seed_spacepoints, void* stream);
 
+/* Tuning of ckf_seed's triplet search (process-wide, for later calls).  The
+ * search holds a middle spacepoint's tops that pass the doublet cuts in
+ * on-chip memory, ordered by cot, and falls back to scanning each bottom's
+ * window of tops directly when a middle has more than `cap` of them; both
+ * ways give the same seeds.  cap in [0, *cap_max] (0: always scan); the
+ * default is the maximum.  cap_max (host, out) or NULL.  Not synchronised
+ * with calls in flight on other threads. */
+ckf_status ckf_seed_set_top_cap(int32_t cap, int32_t* cap_max);
+
 /* Greedy ambiguity resolution of found tracks by shared measurements (paper
  * section 4: the stage after track finding that removes duplicate and fake
  * tracks).  A measurement is shared when more than one surviving track holds

@@ -564,6 +564,17 @@ def seed(geometry: Geometry, n_events: int, meas_offsets, spacepoints, loc, laye
     return {key: v[:m] for key, v in out.items()}, k
 
 
+def seed_top_cap(cap=None):
+    """ckf_seed_set_top_cap: sets the triplet search's capacity of tops held
+    on chip per middle spacepoint (0: always scan each bottom's window; None:
+    the maximum, the default).  Returns the maximum."""
+    lib = _abi.load()
+    mx = C.c_int32(0)
+    _check(lib.ckf_seed_set_top_cap(0, C.byref(mx)), "ckf_seed_set_top_cap")  # query the maximum
+    _check(lib.ckf_seed_set_top_cap(int(mx.value if cap is None else cap), C.byref(mx)), "ckf_seed_set_top_cap")
+    return int(mx.value)
+
+
 def resolve(tracks: dict, n_meas: int, max_shared=1, stream=None, workspace=None):
     """Greedy ambiguity resolution (ckf_resolve) of found tracks held as
     device tensors in ckf_find's layout (n_tracks, offsets, meas, chi2, ndf;

@@ -964,6 +964,14 @@ ckf_status ckf_seed_workspace_size(int32_t n_events, int32_t n_surfaces, int64_t
   return CKF_OK;
 }
 
+ckf_status ckf_seed_set_top_cap(int32_t cap, int32_t* cap_max) {
+  const int mx = ckf::seed_top_cap_max();
+  if (cap_max) *cap_max = mx;
+  if (cap < 0 || cap > mx) return fail(CKF_ERR_INVALID_ARGUMENT, "seed_set_top_cap: cap outside [0, max]");
+  ckf::seed_set_top_cap(cap);
+  return CKF_OK;
+}
+
 ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas_offsets, int64_t n_sp,
                     const float* spacepoints, const float* loc, const int32_t* layers, int32_t n_layers, double bz,
                     void* workspace, size_t workspace_bytes, int64_t cap_seeds, int32_t* n_seeds,
@@ -974,7 +982,7 @@ ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas
   if (n_layers < 3 || n_layers > 8) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: 3 to 8 seeding layers");
   if (!(std::isfinite(bz) && bz != 0.0)) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: bz must be finite and non-zero");
   if (n_sp > INT32_MAX || (long long)n_events * g->dev.n_surfaces >= INT32_MAX ||
-      (long long)n_events * n_layers * 48 * 40 >= INT32_MAX)
+      (long long)n_events * n_layers * 48 * 240 >= INT32_MAX)
     return fail(CKF_ERR_NOT_SUPPORTED, "seed: too many spacepoints or rows");
   if (n_events > 0 && !meas_offsets) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: NULL offsets");
   if (n_sp > 0 && (!spacepoints || !loc)) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: NULL spacepoints");

@@ -27,6 +27,8 @@
 // as its definition, and the file is compiled without contraction into
 // fused multiply-adds, so the decisions are the definition's to the bit.
 #include "ckf_device.hpp"
+#include <atomic>
+
 #include "ckf_kernels.hpp"
 #include "ckf_scan.hpp"
 
@@ -38,13 +40,14 @@ namespace {
 
 constexpr int kSdBlock = 256;
 constexpr int kNphi = 48;  // 0.1309 rad per bin, more than the azimuth cut
-constexpr int kNz = 40;    // 30 mm bins over |z| < 600 mm (the edge bins take the rest)
-constexpr double kZLo = -600.0, kZBin = 30.0, kZMargin = 1.0;
+constexpr int kNz = 240;   // 5 mm bins over |z| < 600 mm (the edge bins take the rest)
+constexpr double kZLo = -600.0, kZBin = 5.0, kZMargin = 1.0;
 constexpr int kKeep = 2;
 constexpr int kMaxSeedLayers = 8;
 constexpr double kKappa64 = 2.99792458e-4;
 constexpr double kCotMax = 3.0, kZ0Max = 200.0, kPtMin = 0.5, kD0Max = 1.0, kDcotBase = 0.01, kDcotMs = 0.007;
 constexpr double kSigma[5] = {0.2, 0.6, 0.01, 0.01, 0.15};
+constexpr int kTriGrid = 1024;  // persistent workgroups of the triplet search: 4 per CU, a multiple of the 8 XCDs
 
 struct SeedLayers {
   int n;
@@ -81,12 +84,17 @@ __device__ __forceinline__ int phi_bin(double x, double y) {
 }
 
 // key of every spacepoint (-1: not on a seeding layer) and the bin counts
-__global__ void k_sd_key(long long n, int n_surfaces, GeomDev g, SeedLayers sl, const int* __restrict__ row,
-                         const float* __restrict__ xyz, int* __restrict__ key, int* __restrict__ cnt,
-                         unsigned* __restrict__ rlim) {
+__global__ void __launch_bounds__(kSdBlock) k_sd_key(long long n, int n_surfaces, GeomDev g, SeedLayers sl,
+                                                     const int* __restrict__ row, const float* __restrict__ xyz,
+                                                     int* __restrict__ key, int* __restrict__ cnt,
+                                                     unsigned* __restrict__ rlim) {
+  // the layers' radius limits are reduced in the workgroup first: one global
+  // atomic per layer and workgroup instead of one per spacepoint
+  __shared__ unsigned s_lim[2 * kMaxSeedLayers];
+  if (threadIdx.x < 2 * kMaxSeedLayers) s_lim[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0x7f800000u;
+  __syncthreads();
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int r = row[i];
+  const int r = i < n ? row[i] : -1;
   int k = -1;
   if (r >= 0) {
     const int s = r % n_surfaces, e = r / n_surfaces;
@@ -100,18 +108,35 @@ __global__ void k_sd_key(long long n, int n_surfaces, GeomDev g, SeedLayers sl, 
       k = ((e * sl.n + li) * kNphi + phi_bin(x, y)) * kNz + z_bin(xyz[3 * i + 2]);
       atomicAdd(&cnt[k], 1);
       const float r = (float)sqrt(x * x + y * y);  // radius bounds (positive floats order as their bits)
-      atomicMin(&rlim[2 * li], __float_as_uint(r));
-      atomicMax(&rlim[2 * li + 1], __float_as_uint(r));
+      atomicMin(&s_lim[2 * li], __float_as_uint(r));
+      atomicMax(&s_lim[2 * li + 1], __float_as_uint(r));
     }
   }
-  key[i] = k;
+  if (i < n) key[i] = k;
+  __syncthreads();
+  if (threadIdx.x < 2 * kMaxSeedLayers) {
+    const unsigned v = s_lim[threadIdx.x];
+    if (threadIdx.x & 1) {
+      if (v != 0u) atomicMax(&rlim[threadIdx.x], v);
+    } else if (v != 0x7f800000u) {
+      atomicMin(&rlim[threadIdx.x], v);
+    }
+  }
 }
 
+// sorted copy of the binned spacepoints: (x, y, z, r) in float64, r as the
+// doublet cuts compute it
 __global__ void k_sd_place(long long n, const int* __restrict__ key, const int* __restrict__ start,
-                           int* __restrict__ fill, int* __restrict__ sorted) {
+                           int* __restrict__ fill, const float* __restrict__ xyz, int* __restrict__ sorted,
+                           double4* __restrict__ spt, int* __restrict__ count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || key[i] < 0) return;
-  sorted[start[key[i]] + atomicAdd(&fill[key[i]], 1)] = (int)i;
+  if (i >= n) return;
+  count[i] = 0;  // seeds per middle: set by the triplet search for middles only
+  if (key[i] < 0) return;
+  const int j = start[key[i]] + atomicAdd(&fill[key[i]], 1);
+  sorted[j] = (int)i;
+  const double x = xyz[3 * i], y = xyz[3 * i + 1];
+  spt[j] = make_double4(x, y, (double)xyz[3 * i + 2], sqrt(x * x + y * y));
 }
 
 struct P3 {
@@ -122,11 +147,10 @@ __device__ __forceinline__ P3 sp_at(const float* xyz, int i) {
   return P3{(double)xyz[3 * i], (double)xyz[3 * i + 1], (double)xyz[3 * i + 2]};
 }
 
-// doublet cuts for an inner point p and an outer point q (see the oracle's
-// definition: the same operations, in the same order)
-__device__ __forceinline__ bool doublet(const P3& p, const P3& q, bool bottom, double tan_dphi, double& cot) {
-  const double rp = sqrt(p.x * p.x + p.y * p.y);
-  const double rq = sqrt(q.x * q.x + q.y * q.y);
+// doublet cuts for an inner point p and an outer point q with their radii
+// rp, rq (see the oracle's definition: the same operations, in the same order)
+__device__ __forceinline__ bool doublet(const P3& p, double rp, const P3& q, double rq, bool bottom, double tan_dphi,
+                                        double& cot) {
   const double dr = rq - rp;
   if (!(dr > 0.0)) return false;
   cot = (q.z - p.z) / dr;
@@ -164,83 +188,231 @@ __device__ __forceinline__ void z_window(double a00, double a01, double a10, dou
   b1 = z_bin(hi);
 }
 
-__global__ void k_sd_triplets(long long n, int n_events, SeedLayers sl, const int* __restrict__ key,
-                              const int* __restrict__ start, const int* __restrict__ cnt,
-                              const int* __restrict__ sorted, const float* __restrict__ xyz,
-                              const unsigned* __restrict__ rlim, double rmin, double tan_dphi,
-                              int* __restrict__ count, int2* __restrict__ best_out) {
-  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
-  count[m] = 0;
-  const int km = key[m];
-  if (km < 0) return;
-  const int bin_m = (km / kNz) % kNphi, li_m = (km / (kNz * kNphi)) % sl.n, e = km / (kNz * kNphi * sl.n);
-  if (li_m == 0 || li_m == sl.n - 1) return;
-  const P3 M = sp_at(xyz, (int)m);
-  const double rM = sqrt(M.x * M.x + M.y * M.y);
-  Cand best[kKeep];
+// One wave per middle spacepoint M (a persistent grid walks the binned
+// spacepoints in sorted order, so the waves of one XCD work on neighbouring
+// middles at the same time).  For M:
+//   1. its tops: spacepoints of higher layers in M's and the two neighbouring
+//      phi bins and in the z window of |cot| <= COT_MAX; the lanes split them,
+//      and the ones passing the (M, T) doublet cuts go to LDS with their cot;
+//   2. the tops are ordered into cot buckets (counting sort in LDS);
+//   3. its bottoms, split over the lanes like the tops: a bottom passing the
+//      (B, M) cuts visits the tops of the buckets around cot_BM +- tol and
+//      applies the triplet cuts to each;
+//   4. each lane keeps its best KEEP by (d0, B, T); a wave reduction takes the
+//      best KEEP of the middle.
+// More passing tops than the LDS holds: each bottom then scans the tops of
+// its z window directly (the same cuts, no buckets).
+constexpr int kTriWaves = 4;          // waves per workgroup
+constexpr int kTopCap = 640;          // passing tops of one middle held in LDS (at most)
+constexpr double kCotBucket = 0.025;  // cot bucket width
+constexpr int kNcot = 241;            // buckets over [-COT_MAX, COT_MAX] (cot = COT_MAX lands in the last)
+constexpr int kNcotPad = 256;         // 4 per lane for the scan
+constexpr double kCotMargin = 1e-9;   // widens a bucket window beyond rounding
+
+__device__ __forceinline__ int cot_bucket(double c) {
+  const double b = floor((c + kCotMax) / kCotBucket);
+  return !(b >= 0.0) ? 0 : (b >= (double)kNcot ? kNcot - 1 : (int)b);
+}
+
+// LDS traffic of one wave ordered against its own later LDS accesses
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lanes_below(unsigned long long mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ __forceinline__ void keep_best(Cand (&best)[kKeep], const Cand& c) {
+  if (!cand_less(c, best[kKeep - 1])) return;
+  best[kKeep - 1] = c;
 #pragma unroll
-  for (int k = 0; k < kKeep; ++k) best[k] = Cand{INFINITY, -1, -1};
-  for (int lb = 0; lb < li_m; ++lb) {
-    // bottoms: z_B = z0 + r_B (z_M - z0) / r_M for |z0| <= Z0_MAX, r_B in the layer's range
-    const double r0 = __uint_as_float(rlim[2 * lb]), r1 = __uint_as_float(rlim[2 * lb + 1]);
-    if (!(r0 <= r1)) continue;  // no spacepoints on that layer
-    int zb0, zb1;
-    z_window(-kZ0Max + r0 * (M.z + kZ0Max) / rM, kZ0Max + r0 * (M.z - kZ0Max) / rM,
-             -kZ0Max + r1 * (M.z + kZ0Max) / rM, kZ0Max + r1 * (M.z - kZ0Max) / rM, zb0, zb1);
-    for (int db = -1; db <= 1; ++db)
-      for (int zb = zb0; zb <= zb1; ++zb) {
-        const int kb = ((e * sl.n + lb) * kNphi + (bin_m + db + kNphi) % kNphi) * kNz + zb;
-        for (int ib = start[kb]; ib < start[kb] + cnt[kb]; ++ib) {
-          const int b = sorted[ib];
-          const P3 B = sp_at(xyz, b);
+  for (int k = kKeep - 1; k > 0; --k)
+    if (cand_less(best[k], best[k - 1])) {
+      const Cand tmp = best[k];
+      best[k] = best[k - 1];
+      best[k - 1] = tmp;
+    }
+}
+
+// triplet cuts of (B, M, T) past both doublets and the cot difference
+__device__ __forceinline__ void try_triplet(const P3& B, int b, const P3& M, const double4& pt, int t, double rmin,
+                                            Cand (&best)[kKeep]) {
+  const P3 T{pt.x, pt.y, pt.z};
+  double ux, uy, R;
+  if (!circle(B, M, T, ux, uy, R)) return;  // collinear: no finite circle, the triplet fails
+  if (!(R >= rmin)) return;
+  const double d0 = fabs(sqrt(ux * ux + uy * uy) - R);
+  if (!(d0 <= kD0Max)) return;
+  keep_best(best, Cand{d0, b, t});
+}
+
+__global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
+    long long nbins, SeedLayers sl, const int* __restrict__ key, const int* __restrict__ start,
+    const int* __restrict__ cnt, const int* __restrict__ sorted, const double4* __restrict__ spt,
+    const unsigned* __restrict__ rlim, double rmin, double tan_dphi, int top_cap, int* __restrict__ count,
+    int2* __restrict__ best_out) {
+  __shared__ double s_ct[kTriWaves][kTopCap];
+  __shared__ int s_j[kTriWaves][kTopCap];
+  __shared__ short s_perm[kTriWaves][kTopCap];
+  __shared__ int s_bs[kTriWaves][kNcotPad];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* ct_l = s_ct[w];
+  int* j_l = s_j[w];
+  short* perm = s_perm[w];
+  int* bs = s_bs[w];
+  // XCD-aware numbering: workgroups are dealt round-robin to the 8 XCDs, so
+  // consecutive logical waves are put on one XCD
+  const int G = gridDim.x, xcd = blockIdx.x % 8, per = G / 8;
+  const int lblock = (G % 8 == 0) ? xcd * per + blockIdx.x / 8 : blockIdx.x;
+  const long long W = (long long)G * kTriWaves;
+  const long long total = nbins > 0 ? (long long)start[nbins - 1] + cnt[nbins - 1] : 0;
+  for (long long j = (long long)lblock * kTriWaves + w; j < total; j += W) {
+    const int m = sorted[j];
+    const int km = key[m];
+    const int bin_m = (km / kNz) % kNphi, li_m = (km / (kNz * kNphi)) % sl.n, e = km / (kNz * kNphi * sl.n);
+    if (li_m == 0 || li_m == sl.n - 1) continue;
+    const double4 pm = spt[j];
+    const P3 M{pm.x, pm.y, pm.z};
+    const double rM = pm.w;
+    const auto range = [&](int layer, int dphi, int z0, int z1, int& j0, int& j1) {
+      // consecutive z bins of one (event, layer, phi bin) are adjacent in the
+      // sorted order: a z window is one range
+      const int k0 = ((e * sl.n + layer) * kNphi + (bin_m + dphi + kNphi) % kNphi) * kNz;
+      j0 = start[k0 + z0];
+      j1 = start[k0 + z1] + cnt[k0 + z1];
+    };
+    wave_sync();  // the previous middle's LDS reads are done
+    // 1. tops passing the (M, T) doublet cuts
+    int n_top = 0;
+    for (int lt = li_m + 1; lt < sl.n; ++lt) {
+      const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
+      if (!(s0 <= s1)) continue;
+      int zt0, zt1;
+      z_window(M.z - kCotMax * s0, M.z + kCotMax * s0, M.z - kCotMax * s1, M.z + kCotMax * s1, zt0, zt1);
+      for (int dt = -1; dt <= 1; ++dt) {
+        int j0, j1;
+        range(lt, dt, zt0, zt1, j0, j1);
+        for (int base = j0; base < j1; base += 64) {
+          const int jt = base + lane;
+          bool pass = false;
+          double ct = 0.0;
+          if (jt < j1) {
+            const double4 pt = spt[jt];
+            pass = doublet(M, rM, P3{pt.x, pt.y, pt.z}, pt.w, false, tan_dphi, ct);
+          }
+          const unsigned long long mask = __ballot(pass);
+          const int pos = n_top + lanes_below(mask);
+          if (pass && pos < top_cap) {
+            ct_l[pos] = ct;
+            j_l[pos] = jt;
+          }
+          n_top += __popcll(mask);
+        }
+      }
+    }
+    const bool in_lds = n_top <= top_cap;
+    // 2. counting sort of the tops by cot bucket: afterwards bs[k] is the end
+    //    of bucket k in perm
+    if (in_lds) {
+      for (int q = lane; q < kNcotPad; q += 64) bs[q] = 0;
+      wave_sync();
+      for (int i = lane; i < n_top; i += 64) atomicAdd(&bs[cot_bucket(ct_l[i])], 1);
+      wave_sync();
+      const int v0 = bs[4 * lane], v1 = bs[4 * lane + 1], v2 = bs[4 * lane + 2], v3 = bs[4 * lane + 3];
+      const int sum = v0 + v1 + v2 + v3;
+      int incl = sum;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+      }
+      const int ex = incl - sum;
+      bs[4 * lane] = ex;
+      bs[4 * lane + 1] = ex + v0;
+      bs[4 * lane + 2] = ex + v0 + v1;
+      bs[4 * lane + 3] = ex + v0 + v1 + v2;
+      wave_sync();
+      for (int i = lane; i < n_top; i += 64) perm[atomicAdd(&bs[cot_bucket(ct_l[i])], 1)] = (short)i;
+      wave_sync();
+    }
+    // 3. bottoms
+    Cand best[kKeep];
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) best[k] = Cand{INFINITY, -1, -1};
+    for (int lb = 0; lb < li_m; ++lb) {
+      // z_B = z0 + r_B (z_M - z0) / r_M for |z0| <= Z0_MAX, r_B in the layer's range
+      const double r0 = __uint_as_float(rlim[2 * lb]), r1 = __uint_as_float(rlim[2 * lb + 1]);
+      if (!(r0 <= r1)) continue;  // no spacepoints on that layer
+      int zb0, zb1;
+      z_window(-kZ0Max + r0 * (M.z + kZ0Max) / rM, kZ0Max + r0 * (M.z - kZ0Max) / rM,
+               -kZ0Max + r1 * (M.z + kZ0Max) / rM, kZ0Max + r1 * (M.z - kZ0Max) / rM, zb0, zb1);
+      for (int db = -1; db <= 1; ++db) {
+        int j0, j1;
+        range(lb, db, zb0, zb1, j0, j1);
+        for (int jb = j0 + lane; jb < j1; jb += 64) {
+          const double4 pb = spt[jb];
+          const P3 B{pb.x, pb.y, pb.z};
           double cb;
-          if (!doublet(B, M, true, tan_dphi, cb)) continue;
+          if (!doublet(B, pb.w, M, rM, true, tan_dphi, cb)) continue;
+          const int b = sorted[jb];
           const double tol = kDcotBase + kDcotMs * (1.0 + cb * cb);
-          for (int lt = li_m + 1; lt < sl.n; ++lt) {
-            // tops: z_T = z_M + (r_T - r_M) cot_T for cot_T within tol of cot_BM
-            const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
-            if (!(s0 <= s1)) continue;
-            int zt0, zt1;
-            z_window(M.z + s0 * (cb - tol), M.z + s0 * (cb + tol), M.z + s1 * (cb - tol), M.z + s1 * (cb + tol),
-                     zt0, zt1);
-            for (int dt = -1; dt <= 1; ++dt)
-              for (int zt = zt0; zt <= zt1; ++zt) {
-                const int kt = ((e * sl.n + lt) * kNphi + (bin_m + dt + kNphi) % kNphi) * kNz + zt;
-                for (int it = start[kt]; it < start[kt] + cnt[kt]; ++it) {
-                  const int t = sorted[it];
-                  const P3 T = sp_at(xyz, t);
+          if (in_lds) {
+            const int k0 = cot_bucket(cb - tol - kCotMargin), k1 = cot_bucket(cb + tol + kCotMargin);
+            for (int p = k0 > 0 ? bs[k0 - 1] : 0; p < bs[k1]; ++p) {
+              const int i = perm[p];
+              if (!(fabs(cb - ct_l[i]) <= tol)) continue;
+              const int jt = j_l[i];
+              try_triplet(B, b, M, spt[jt], sorted[jt], rmin, best);
+            }
+          } else {
+            for (int lt = li_m + 1; lt < sl.n; ++lt) {
+              // z_T = z_M + (r_T - r_M) cot_T for cot_T within tol of cot_BM
+              const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
+              if (!(s0 <= s1)) continue;
+              int zt0, zt1;
+              z_window(M.z + s0 * (cb - tol), M.z + s0 * (cb + tol), M.z + s1 * (cb - tol), M.z + s1 * (cb + tol),
+                       zt0, zt1);
+              for (int dt = -1; dt <= 1; ++dt) {
+                int t0, t1;
+                range(lt, dt, zt0, zt1, t0, t1);
+                for (int jt = t0; jt < t1; ++jt) {
+                  const double4 pt = spt[jt];
                   double ct;
-                  if (!doublet(M, T, false, tan_dphi, ct)) continue;
+                  if (!doublet(M, rM, P3{pt.x, pt.y, pt.z}, pt.w, false, tan_dphi, ct)) continue;
                   if (!(fabs(cb - ct) <= tol)) continue;
-                  double ux, uy, R;
-                  if (!circle(B, M, T, ux, uy, R)) continue;  // collinear: no finite circle, the triplet fails
-                  if (!(R >= rmin)) continue;
-                  const double d0 = fabs(sqrt(ux * ux + uy * uy) - R);
-                  if (!(d0 <= kD0Max)) continue;
-                  Cand c{d0, b, t};
-                  if (!cand_less(c, best[kKeep - 1])) continue;
-                  best[kKeep - 1] = c;
-#pragma unroll
-                  for (int k = kKeep - 1; k > 0; --k)
-                    if (cand_less(best[k], best[k - 1])) {
-                      const Cand tmp = best[k];
-                      best[k] = best[k - 1];
-                      best[k - 1] = tmp;
-                    }
+                  try_triplet(B, b, M, pt, sorted[jt], rmin, best);
                 }
               }
+            }
           }
         }
       }
-  }
-  int c = 0;
+    }
+    // 4. the middle's best KEEP over the lanes: KEEP rounds of a butterfly
+    //    minimum over the lanes' next unused candidate ((B, T) pairs are
+    //    distinct across lanes, each bottom being one lane's)
+    int used = 0, c = 0;
 #pragma unroll
-  for (int k = 0; k < kKeep; ++k) {
-    best_out[kKeep * m + k] = make_int2(best[k].b, best[k].t);
-    c += best[k].b >= 0 ? 1 : 0;
+    for (int k = 0; k < kKeep; ++k) {
+      Cand head = Cand{INFINITY, -1, -1};
+#pragma unroll
+      for (int q = 0; q < kKeep; ++q)
+        if (q == used) head = best[q];
+      Cand x = head;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const Cand y{__shfl_xor(x.d0, off), __shfl_xor(x.b, off), __shfl_xor(x.t, off)};
+        if (cand_less(y, x)) x = y;
+      }
+      if (x.b >= 0 && head.b == x.b && head.t == x.t) ++used;
+      if (lane == 0) best_out[kKeep * (long long)m + k] = make_int2(x.b, x.t);
+      c += x.b >= 0 ? 1 : 0;
+    }
+    if (lane == 0) count[m] = c;
   }
-  count[m] = c;
 }
 
 __global__ void k_sd_write(long long n, int n_surfaces, double bz, const int* __restrict__ row,
@@ -301,13 +473,20 @@ size_t al256s(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
+namespace {
+std::atomic<int> g_top_cap{kTopCap};
+}  // namespace
+
+int seed_top_cap_max() { return kTopCap; }
+void seed_set_top_cap(int cap) { g_top_cap.store(cap); }
+
 size_t seed_workspace_bytes(long long rows, long long n_sp, int n_events, int n_layers) {
   (void)rows;
   const long long n = n_sp > 0 ? n_sp : 1;
   const long long nbins = (long long)n_events * n_layers * kNphi * kNz + 1;
   const long long nb = (n > nbins ? n : nbins) / scan_detail::kScanBlock + 2;
-  return 5 * al256s((size_t)n * 4) + al256s((size_t)n * 8 * kKeep) + 3 * al256s((size_t)nbins * 4) +
-         al256s((size_t)nb * 8) + 256 + 512;
+  return 5 * al256s((size_t)n * 4) + al256s((size_t)n * 8 * kKeep) + al256s((size_t)n * 32) +
+         3 * al256s((size_t)nbins * 4) + al256s((size_t)nb * 8) + 256 + 512;
 }
 
 hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int* moff, long long n_sp,
@@ -334,6 +513,8 @@ hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int
   p += al256s((size_t)na * 4);
   int2* best = reinterpret_cast<int2*>(p);
   p += al256s((size_t)na * 8 * kKeep);
+  double4* spt = reinterpret_cast<double4*>(p);
+  p += al256s((size_t)na * 32);
   int* cnt = reinterpret_cast<int*>(p);
   p += al256s((size_t)(nbins + 1) * 4);
   int* start = reinterpret_cast<int*>(p);
@@ -356,11 +537,11 @@ hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int
     hipLaunchKernelGGL(k_sd_key, blocks(n), dim3(kSdBlock), 0, st, n, n_surfaces, g, sl, row, xyz, key, cnt, rlim);
   device_scan<OpSum, false>(cnt, nbins, start, sums, nullptr, st);
   if (n > 0) {
-    hipLaunchKernelGGL(k_sd_place, blocks(n), dim3(kSdBlock), 0, st, n, key, start, fill, sorted);
+    hipLaunchKernelGGL(k_sd_place, blocks(n), dim3(kSdBlock), 0, st, n, key, start, fill, xyz, sorted, spt, count);
     const double rmin = kPtMin / (kKappa64 * fabs(bz));
     const double tan_dphi = tan(0.12);
-    hipLaunchKernelGGL(k_sd_triplets, blocks(n), dim3(kSdBlock), 0, st, n, n_events, sl, key, start, cnt, sorted,
-                       xyz, rlim, rmin, tan_dphi, count, best);
+    hipLaunchKernelGGL(k_sd_triplets, dim3(kTriGrid), dim3(64 * kTriWaves), 0, st, nbins, sl, key, start, cnt,
+                       sorted, spt, rlim, rmin, tan_dphi, g_top_cap.load(), count, best);
   }
   device_scan<OpSum, false>(count, n, head, sums, n_seeds, st);  // head now holds the seed offsets
   if (n > 0)

@@ -52,34 +52,47 @@ def _layer_index(det, offsets, n_events):
 def test_seed_matches_oracle(ckf, det_dense):
     """A mu = 20 event's clusters: the GPU's seeds are the oracle's, triplet
     by triplet in the same order, on the same modules, with parameters to
-    1e-12 relative (FP64 on both sides)."""
+    1e-12 relative (FP64 on both sides); with the tops of every middle held
+    on chip (default), with none (every bottom scans its window) and with a
+    capacity that some middles exceed."""
     from oracle import seeding as OS
     ev = make_event(det_dense, 6000, mu=20)
     cells = make_cells(det_dense, ev, 1)
     geo, cl, r, m = _clusters_on_device(det_dense, cells, ckf)
-    sd, n = ckf.seed(geo, 1, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
     li, rows = _layer_index(det_dense, r["offsets"], 1)
     ref = OS.seeds(r["spacepoints"].astype(np.float64), li, rows, r["loc"].astype(np.float64), 2.0)
-    _say(f"# seeding: {m} spacepoints, {n} seeds (oracle {len(ref['middle'])})")
-    sp = sd["spacepoints"].cpu().numpy()
-    assert n == len(ref["middle"])
-    np.testing.assert_array_equal(sp[:, 0], ref["bottom"])
-    np.testing.assert_array_equal(sp[:, 1], ref["middle"])
-    np.testing.assert_array_equal(sp[:, 2], ref["top"])
-    np.testing.assert_array_equal(sd["surface"].cpu().numpy(), ref["surface"])
-    assert np.all(sd["event"].cpu().numpy() == 0)
-    p = sd["params"].cpu().numpy()
-    np.testing.assert_allclose(p, ref["params"], rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(sd["cov"].cpu().numpy(), ref["cov"], rtol=1e-12, atol=0)
+    try:
+        for cap in (None, 0, 12):
+            ckf.seed_top_cap(cap)
+            sd, n = ckf.seed(geo, 1, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+            _say(f"# seeding (top capacity {cap}): {m} spacepoints, {n} seeds (oracle {len(ref['middle'])})")
+            sp = sd["spacepoints"].cpu().numpy()
+            assert n == len(ref["middle"])
+            np.testing.assert_array_equal(sp[:, 0], ref["bottom"])
+            np.testing.assert_array_equal(sp[:, 1], ref["middle"])
+            np.testing.assert_array_equal(sp[:, 2], ref["top"])
+            np.testing.assert_array_equal(sd["surface"].cpu().numpy(), ref["surface"])
+            assert np.all(sd["event"].cpu().numpy() == 0)
+            p = sd["params"].cpu().numpy()
+            np.testing.assert_allclose(p, ref["params"], rtol=1e-12, atol=1e-12)
+            np.testing.assert_allclose(sd["cov"].cpu().numpy(), ref["cov"], rtol=1e-12, atol=0)
+    finally:
+        ckf.seed_top_cap(None)
 
 
-def test_seed_batch_sampled_middles(ckf, det_dense):
+@pytest.fixture(scope="module")
+def batch200(ckf, det_dense):
+    """Clusters of 8 x mu = 200 events on the GPU."""
+    evs = [make_event(det_dense, 7100 + i, mu=200) for i in range(8)]
+    cells = concat_cells([make_cells(det_dense, e, 200 + i) for i, e in enumerate(evs)])
+    return _clusters_on_device(det_dense, cells, ckf)
+
+
+def test_seed_batch_sampled_middles(ckf, det_dense, batch200):
     """8 x mu = 200 events in one call: for 400 sampled middle spacepoints
     the oracle, on that middle's event alone, keeps the same triplets."""
     from oracle import seeding as OS
-    evs = [make_event(det_dense, 7100 + i, mu=200) for i in range(8)]
-    cells = concat_cells([make_cells(det_dense, e, 200 + i) for i, e in enumerate(evs)])
-    geo, cl, r, m = _clusters_on_device(det_dense, cells, ckf)
+    geo, cl, r, m = batch200
     sd, n = ckf.seed(geo, 8, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
     sp = sd["spacepoints"].cpu().numpy()
     _say(f"# seeding batch: {m} spacepoints, {n} seeds")
@@ -96,6 +109,28 @@ def test_seed_batch_sampled_middles(ckf, det_dense):
         ref = OS.triplets(xyz[idx], li[idx], 2.0, middles=[local])
         got = sp[sp[:, 1] == mid]
         assert [(idx[b], idx[t]) for _, b, t, _ in ref] == [(int(a), int(c)) for a, _, c in got], mid
+
+
+def test_seed_top_capacity_batch(ckf, batch200):
+    """8 x mu = 200 events: the seeds are the same, bit for bit, whether the
+    middles' tops are held on chip, never (every bottom scans its window),
+    or up to a capacity that part of the middles exceed."""
+    geo, cl, r, m = batch200
+    out = []
+    try:
+        for cap in (None, 0, 160):
+            ckf.seed_top_cap(cap)
+            sd, n = ckf.seed(geo, 8, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+            out.append((n, {k: v.cpu().numpy() for k, v in sd.items()}))
+            _say(f"# seeding batch (top capacity {cap}): {n} seeds")
+    finally:
+        ckf.seed_top_cap(None)
+    n0, ref = out[0]
+    assert n0 > 100000
+    for n, got in out[1:]:
+        assert n == n0
+        for k in ref:
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
 
 
 def test_chain_cells_to_tracks(ckf, det_dense):
