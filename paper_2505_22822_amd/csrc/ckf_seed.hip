@@ -10,17 +10,20 @@
 //   bin     - spacepoints of seeding layers keyed by (event, layer, phi bin,
 //             z bin) and counted, each layer's radius range taken; a
 //             sum-scan gives the bins' starts; a placement pass fills them
-//             (order inside a bin does not matter: a middle's candidates are
-//             all tested and ranked by value and index);
-//   triplet - one thread per spacepoint of an inner seeding layer.  Bottoms
-//             come from lower layers in the same and the two neighbouring
-//             phi bins (a bin is wider than the azimuth cut) and in the z
-//             bins the beam-line cut allows at that layer's radii; for each
-//             bottom that passes, tops come from higher layers in the z bins
-//             its cot window allows.  The windows are bilinear in the radius
-//             and the cut variable, so their corners bound them; they get a
-//             1 mm margin and only select candidates: every cut is then
-//             applied as defined.  The KEEP best by (d0, bottom, top) stay;
+//             and copies the points in that order with their radius (order
+//             inside a bin does not matter: a middle's candidates are all
+//             tested and ranked by value and index);
+//   triplet - one wave per spacepoint of an inner seeding layer (the
+//             middle).  Candidates come from the same and the two
+//             neighbouring phi bins (a bin is wider than the azimuth cut) and
+//             from z windows: tops on higher layers within |cot| <= COT_MAX,
+//             bottoms on lower layers within the beam-line cut at that
+//             layer's radii.  The windows are bilinear in the radius and the
+//             cut variable, so their corners bound them; they get a 1 mm
+//             margin and only select candidates: every cut is then applied
+//             as defined.  The middle's passing tops are bucketed by cot in
+//             LDS, so a passing bottom visits only the buckets of its cot
+//             window; the KEEP best by (d0, bottom, top) stay;
 //   write   - a sum-scan of the per-middle counts places the seeds in middle
 //             order; each gets its helix estimate at the bottom spacepoint.
 // Every cut is computed in FP64 with the same operations in the same order
