@@ -195,18 +195,23 @@ __device__ __forceinline__ void z_window(double a00, double a01, double a10, dou
 // spacepoints in sorted order, so the waves of one XCD work on neighbouring
 // middles at the same time).  For M:
 //   1. its tops: spacepoints of higher layers in M's and the two neighbouring
-//      phi bins and in the z window of |cot| <= COT_MAX; the lanes split them,
-//      and the ones passing the (M, T) doublet cuts go to LDS with their cot;
-//   2. the tops are ordered into cot buckets (counting sort in LDS);
-//   3. its bottoms, split over the lanes like the tops: a bottom passing the
-//      (B, M) cuts visits the tops of the buckets around cot_BM +- tol and
-//      applies the triplet cuts to each;
-//   4. each lane keeps its best KEEP by (d0, B, T); a wave reduction takes the
+//      phi bins and in the z window of |cot| <= COT_MAX.  The lanes split
+//      them; a first pass counts the ones passing the (M, T) doublet cuts per
+//      cot bucket, a second pass (the same arithmetic, so the same results)
+//      writes their (cot, index) into LDS in bucket order;
+//   2. its bottoms, split over the lanes like the tops.  Bottoms passing the
+//      (B, M) cuts enter a wave queue; each batch of 64 gives every lane one
+//      bottom, which walks the tops of the buckets around cot_BM +- tol and
+//      puts the (B, T) pairs within the cot cut into a second wave queue;
+//      each batch of 64 pairs gets the circle and d0 cuts, one pair per lane.
+//      So the expensive tests run on full waves;
+//   3. each lane keeps its best KEEP by (d0, B, T); a wave reduction takes the
 //      best KEEP of the middle.
 // More passing tops than the LDS holds: each bottom then scans the tops of
-// its z window directly (the same cuts, no buckets).
+// its z window directly (the same cuts, no buckets, no queues).
 constexpr int kTriWaves = 4;          // waves per workgroup
-constexpr int kTopCap = 640;          // passing tops of one middle held in LDS (at most)
+constexpr int kTopCap = 608;          // passing tops of one middle held in LDS (at most)
+constexpr int kRing = 128;            // capacity of each wave queue (a power of two >= 127)
 constexpr double kCotBucket = 0.025;  // cot bucket width
 constexpr int kNcot = 241;            // buckets over [-COT_MAX, COT_MAX] (cot = COT_MAX lands in the last)
 constexpr int kNcotPad = 256;         // 4 per lane for the scan
@@ -259,13 +264,15 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
     int2* __restrict__ best_out) {
   __shared__ double s_ct[kTriWaves][kTopCap];
   __shared__ int s_j[kTriWaves][kTopCap];
-  __shared__ short s_perm[kTriWaves][kTopCap];
   __shared__ int s_bs[kTriWaves][kNcotPad];
+  __shared__ int s_bq[kTriWaves][kRing];
+  __shared__ int2 s_pq[kTriWaves][kRing];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* ct_l = s_ct[w];
-  int* j_l = s_j[w];
-  short* perm = s_perm[w];
+  double* ct_s = s_ct[w];
+  int* j_s = s_j[w];
   int* bs = s_bs[w];
+  int* bq = s_bq[w];
+  int2* pq = s_pq[w];
   // XCD-aware numbering: workgroups are dealt round-robin to the 8 XCDs, so
   // consecutive logical waves are put on one XCD
   const int G = gridDim.x, xcd = blockIdx.x % 8, per = G / 8;
@@ -287,42 +294,49 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
       j0 = start[k0 + z0];
       j1 = start[k0 + z1] + cnt[k0 + z1];
     };
-    wave_sync();  // the previous middle's LDS reads are done
-    // 1. tops passing the (M, T) doublet cuts
-    int n_top = 0;
-    for (int lt = li_m + 1; lt < sl.n; ++lt) {
-      const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
-      if (!(s0 <= s1)) continue;
-      int zt0, zt1;
-      z_window(M.z - kCotMax * s0, M.z + kCotMax * s0, M.z - kCotMax * s1, M.z + kCotMax * s1, zt0, zt1);
-      for (int dt = -1; dt <= 1; ++dt) {
-        int j0, j1;
-        range(lt, dt, zt0, zt1, j0, j1);
-        for (int base = j0; base < j1; base += 64) {
-          const int jt = base + lane;
-          bool pass = false;
-          double ct = 0.0;
-          if (jt < j1) {
-            const double4 pt = spt[jt];
-            pass = doublet(M, rM, P3{pt.x, pt.y, pt.z}, pt.w, false, tan_dphi, ct);
+    // every top candidate of M through the (M, T) doublet cuts; place = false
+    // counts the passing ones per bucket, place = true writes them in bucket
+    // order (bs holds the buckets' starts then, and their ends afterwards)
+    const auto tops = [&](bool place) {
+      int n = 0;
+      for (int lt = li_m + 1; lt < sl.n; ++lt) {
+        const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
+        if (!(s0 <= s1)) continue;
+        int zt0, zt1;
+        z_window(M.z - kCotMax * s0, M.z + kCotMax * s0, M.z - kCotMax * s1, M.z + kCotMax * s1, zt0, zt1);
+        for (int dt = -1; dt <= 1; ++dt) {
+          int j0, j1;
+          range(lt, dt, zt0, zt1, j0, j1);
+          for (int base = j0; base < j1; base += 64) {
+            const int jt = base + lane;
+            bool pass = false;
+            double ct = 0.0;
+            if (jt < j1) {
+              const double4 pt = spt[jt];
+              pass = doublet(M, rM, P3{pt.x, pt.y, pt.z}, pt.w, false, tan_dphi, ct);
+            }
+            if (pass) {
+              if (!place) {
+                atomicAdd(&bs[cot_bucket(ct)], 1);
+              } else {
+                const int pos = atomicAdd(&bs[cot_bucket(ct)], 1);
+                ct_s[pos] = ct;
+                j_s[pos] = jt;
+              }
+            }
+            n += __popcll(__ballot(pass));
           }
-          const unsigned long long mask = __ballot(pass);
-          const int pos = n_top + lanes_below(mask);
-          if (pass && pos < top_cap) {
-            ct_l[pos] = ct;
-            j_l[pos] = jt;
-          }
-          n_top += __popcll(mask);
         }
       }
-    }
+      return n;
+    };
+    wave_sync();  // the previous middle's LDS reads are done
+    // 1. tops: count per bucket, scan, place
+    for (int q = lane; q < kNcotPad; q += 64) bs[q] = 0;
+    wave_sync();
+    const int n_top = tops(false);
     const bool in_lds = n_top <= top_cap;
-    // 2. counting sort of the tops by cot bucket: afterwards bs[k] is the end
-    //    of bucket k in perm
     if (in_lds) {
-      for (int q = lane; q < kNcotPad; q += 64) bs[q] = 0;
-      wave_sync();
-      for (int i = lane; i < n_top; i += 64) atomicAdd(&bs[cot_bucket(ct_l[i])], 1);
       wave_sync();
       const int v0 = bs[4 * lane], v1 = bs[4 * lane + 1], v2 = bs[4 * lane + 2], v3 = bs[4 * lane + 3];
       const int sum = v0 + v1 + v2 + v3;
@@ -338,13 +352,56 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
       bs[4 * lane + 2] = ex + v0 + v1;
       bs[4 * lane + 3] = ex + v0 + v1 + v2;
       wave_sync();
-      for (int i = lane; i < n_top; i += 64) perm[atomicAdd(&bs[cot_bucket(ct_l[i])], 1)] = (short)i;
+      tops(true);
       wave_sync();
     }
-    // 3. bottoms
     Cand best[kKeep];
 #pragma unroll
     for (int k = 0; k < kKeep; ++k) best[k] = Cand{INFINITY, -1, -1};
+    // 2. bottoms
+    int btail = 0, bhead = 0, ptail = 0, phead = 0;  // queue positions (the same in every lane)
+    // up to 64 queued pairs, one per lane, through the circle and d0 cuts
+    const auto run_pairs = [&]() {
+      wave_sync();
+      const int np = min(64, ptail - phead);
+      if (lane < np) {
+        const int2 q = pq[(phead + lane) & (kRing - 1)];
+        const double4 pb = spt[q.x];
+        try_triplet(P3{pb.x, pb.y, pb.z}, sorted[q.x], M, spt[q.y], sorted[q.y], rmin, best);
+      }
+      phead += np;
+      wave_sync();
+    };
+    // up to 64 queued bottoms, one per lane, walk their cot window
+    const auto run_bottoms = [&]() {
+      wave_sync();
+      const int nb = min(64, btail - bhead);
+      int p = 0, p1 = 0, jb = 0;
+      double cb = 0.0, tol = 0.0;
+      if (lane < nb) {
+        jb = bq[(bhead + lane) & (kRing - 1)];
+        const double4 pb = spt[jb];
+        cb = (M.z - pb.z) / (rM - pb.w);  // cot of the (B, M) doublet, as its cut computed it
+        tol = kDcotBase + kDcotMs * (1.0 + cb * cb);
+        const int k0 = cot_bucket(cb - tol - kCotMargin), k1 = cot_bucket(cb + tol + kCotMargin);
+        p = k0 > 0 ? bs[k0 - 1] : 0;
+        p1 = bs[k1];
+      }
+      bhead += nb;
+      while (__any(p < p1)) {
+        bool hit = false;
+        int jt = 0;
+        if (p < p1) {
+          hit = fabs(cb - ct_s[p]) <= tol;
+          jt = j_s[p];
+          ++p;
+        }
+        const unsigned long long mask = __ballot(hit);
+        if (hit) pq[(ptail + lanes_below(mask)) & (kRing - 1)] = make_int2(jb, jt);
+        ptail += __popcll(mask);
+        if (ptail - phead >= 64) run_pairs();
+      }
+    };
     for (int lb = 0; lb < li_m; ++lb) {
       // z_B = z0 + r_B (z_M - z0) / r_M for |z0| <= Z0_MAX, r_B in the layer's range
       const double r0 = __uint_as_float(rlim[2 * lb]), r1 = __uint_as_float(rlim[2 * lb + 1]);
@@ -355,6 +412,22 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
       for (int db = -1; db <= 1; ++db) {
         int j0, j1;
         range(lb, db, zb0, zb1, j0, j1);
+        if (in_lds) {
+          for (int base = j0; base < j1; base += 64) {
+            const int jb = base + lane;
+            bool pass = false;
+            if (jb < j1) {
+              const double4 pb = spt[jb];
+              double cb;
+              pass = doublet(P3{pb.x, pb.y, pb.z}, pb.w, M, rM, true, tan_dphi, cb);
+            }
+            const unsigned long long mask = __ballot(pass);
+            if (pass) bq[(btail + lanes_below(mask)) & (kRing - 1)] = jb;
+            btail += __popcll(mask);
+            if (btail - bhead >= 64) run_bottoms();
+          }
+          continue;
+        }
         for (int jb = j0 + lane; jb < j1; jb += 64) {
           const double4 pb = spt[jb];
           const P3 B{pb.x, pb.y, pb.z};
@@ -362,41 +435,36 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
           if (!doublet(B, pb.w, M, rM, true, tan_dphi, cb)) continue;
           const int b = sorted[jb];
           const double tol = kDcotBase + kDcotMs * (1.0 + cb * cb);
-          if (in_lds) {
-            const int k0 = cot_bucket(cb - tol - kCotMargin), k1 = cot_bucket(cb + tol + kCotMargin);
-            for (int p = k0 > 0 ? bs[k0 - 1] : 0; p < bs[k1]; ++p) {
-              const int i = perm[p];
-              if (!(fabs(cb - ct_l[i]) <= tol)) continue;
-              const int jt = j_l[i];
-              try_triplet(B, b, M, spt[jt], sorted[jt], rmin, best);
-            }
-          } else {
-            for (int lt = li_m + 1; lt < sl.n; ++lt) {
-              // z_T = z_M + (r_T - r_M) cot_T for cot_T within tol of cot_BM
-              const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
-              if (!(s0 <= s1)) continue;
-              int zt0, zt1;
-              z_window(M.z + s0 * (cb - tol), M.z + s0 * (cb + tol), M.z + s1 * (cb - tol), M.z + s1 * (cb + tol),
-                       zt0, zt1);
-              for (int dt = -1; dt <= 1; ++dt) {
-                int t0, t1;
-                range(lt, dt, zt0, zt1, t0, t1);
-                for (int jt = t0; jt < t1; ++jt) {
-                  const double4 pt = spt[jt];
-                  double ct;
-                  if (!doublet(M, rM, P3{pt.x, pt.y, pt.z}, pt.w, false, tan_dphi, ct)) continue;
-                  if (!(fabs(cb - ct) <= tol)) continue;
-                  try_triplet(B, b, M, pt, sorted[jt], rmin, best);
-                }
+          for (int lt = li_m + 1; lt < sl.n; ++lt) {
+            // z_T = z_M + (r_T - r_M) cot_T for cot_T within tol of cot_BM
+            const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
+            if (!(s0 <= s1)) continue;
+            int zt0, zt1;
+            z_window(M.z + s0 * (cb - tol), M.z + s0 * (cb + tol), M.z + s1 * (cb - tol), M.z + s1 * (cb + tol),
+                     zt0, zt1);
+            for (int dt = -1; dt <= 1; ++dt) {
+              int t0, t1;
+              range(lt, dt, zt0, zt1, t0, t1);
+              for (int jt = t0; jt < t1; ++jt) {
+                const double4 pt = spt[jt];
+                double ct;
+                if (!doublet(M, rM, P3{pt.x, pt.y, pt.z}, pt.w, false, tan_dphi, ct)) continue;
+                if (!(fabs(cb - ct) <= tol)) continue;
+                try_triplet(B, b, M, pt, sorted[jt], rmin, best);
               }
             }
           }
         }
       }
     }
-    // 4. the middle's best KEEP over the lanes: KEEP rounds of a butterfly
+    if (in_lds) {
+      if (btail > bhead) run_bottoms();  // the last, partial batch
+      if (ptail > phead) run_pairs();    // fewer than 64 left after run_bottoms
+    }
+    // 3. the middle's best KEEP over the lanes: KEEP rounds of a butterfly
     //    minimum over the lanes' next unused candidate ((B, T) pairs are
-    //    distinct across lanes, each bottom being one lane's)
+    //    distinct across lanes: each bottom is visited once, and each of its
+    //    tops once)
     int used = 0, c = 0;
 #pragma unroll
     for (int k = 0; k < kKeep; ++k) {
