@@ -430,7 +430,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--events", type=int, default=64)
     ap.add_argument("--mu", type=float, default=200.0)
-    ap.add_argument("--cpu-events", type=int, default=8)
+    ap.add_argument("--cpu-events", type=int, default=64,
+                    help="events of the batch the oracle's CPU baseline runs on (default: all 64, a few seconds on "
+                         "16 host cores)")
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--seeds-per-group", type=int, default=0)
