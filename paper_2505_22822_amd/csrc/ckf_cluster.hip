@@ -20,12 +20,16 @@
 //             readout order of their first cells: clusters come out grouped
 //             by row, in the order the measurement layout needs, and a row's
 //             measurement offset is the scan at its first cell;
-//   sums    - each cell adds q, q (c0 + 1/2), q (c1 + 1/2) to its cluster in
-//             FP64 atomics: every term has at most 35 significant bits and
-//             the sums stay far below 2^53 of their quantum, so they are exact
-//             and the result does not depend on the order of the additions;
-//   measure - per cluster: loc = pitch X / W - half length, pitch^2 / 12
-//             variances, the spacepoint.
+//   label   - every cell's cluster number; each root notes its cluster's
+//             first cell;
+//   measure - per cluster: W = sum q, X = sum q (c + 1/2) over its cells in
+//             FP64 and index order, then loc = pitch X / W - half length,
+//             pitch^2 / 12 variances, the spacepoint.  The cluster's cells
+//             follow its first cell in the module's row, and their c1 values
+//             form an interval starting at the first cell's (a connected
+//             set, first in readout order): the scan stops at the first cell
+//             whose c1 is past the last member's c1 + 1.  No atomics, and the
+//             additions happen in the same order as in a sequential pass.
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
 #include "ckf_scan.hpp"
@@ -115,39 +119,24 @@ __global__ void k_cl_flatten(long long n, const int* __restrict__ parent, int* _
   is_root[i] = x == i ? 1 : 0;
 }
 
-// roots: clear their cluster's sums and note the cluster's first cell
-__global__ void k_cl_roots(long long n, const int* __restrict__ root, const int* __restrict__ cid,
-                           int* __restrict__ first, double* __restrict__ acc) {
+// every cell's cluster number; the roots note their cluster's first cell
+__global__ void k_cl_label(long long n, const int* __restrict__ row, const int* __restrict__ root,
+                           const int* __restrict__ cid, int* __restrict__ first, int* __restrict__ cell_cluster) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || root[i] != i) return;
-  const int k = cid[i];
-  first[k] = (int)i;
-  acc[3ll * k] = acc[3ll * k + 1] = acc[3ll * k + 2] = 0.0;
-}
-
-__global__ void k_cl_sums(CellsIn c, const int* __restrict__ row, const int* __restrict__ root,
-                          const int* __restrict__ cid, double* __restrict__ acc, int* __restrict__ cell_cluster) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c.n_cells) return;
-  if (row[i] < 0) {
-    if (cell_cluster) cell_cluster[i] = -1;
-    return;
-  }
+  if (i >= n) return;
   const int k = cid[root[i]];
-  const double q = c.q[i];
-  atomicAdd(&acc[3ll * k], q);
-  atomicAdd(&acc[3ll * k + 1], q * ((double)c.c0[i] + 0.5));
-  atomicAdd(&acc[3ll * k + 2], q * ((double)c.c1[i] + 0.5));
-  if (cell_cluster) cell_cluster[i] = k;
+  if (root[i] == i) first[k] = (int)i;
+  if (cell_cluster) cell_cluster[i] = row[i] < 0 ? -1 : k;
 }
 
 __global__ void k_cl_measure(CellsIn c, GeomDev g, const float* __restrict__ pitch, const int* __restrict__ n_cl,
                              const int* __restrict__ first, const int* __restrict__ row,
-                             const double* __restrict__ acc, float* __restrict__ loc, float* __restrict__ var,
+                             const int* __restrict__ root, float* __restrict__ loc, float* __restrict__ var,
                              float* __restrict__ sp) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= *n_cl) return;
-  const int rr = row[first[k]];
+  const int f = first[k];
+  const int rr = row[f];
   if (rr < 0) {  // a cell before the first row (bad offsets, flagged): no module
     loc[2 * k] = loc[2 * k + 1] = var[2 * k] = var[2 * k + 1] = NAN;
     if (sp) sp[3 * k] = sp[3 * k + 1] = sp[3 * k + 2] = NAN;
@@ -157,8 +146,22 @@ __global__ void k_cl_measure(CellsIn c, GeomDev g, const float* __restrict__ pit
   Module M;
   load_module(g, s, M);
   const double p0 = pitch[2 * s], p1 = pitch[2 * s + 1];
-  const double w = acc[3 * k];
-  const double l0 = p0 * (acc[3 * k + 1] / w) - (double)M.hw0, l1 = p1 * (acc[3 * k + 2] / w) - (double)M.hw1;
+  // the cluster's cells: from its first cell to the end of its c1 interval
+  // (the first cell at least, should flagged offsets have put it past its row's end)
+  const long long end = max((long long)c.offsets[rr + 1], (long long)f + 1);
+  double w = 0.0, x0 = 0.0, x1 = 0.0;
+  int last = c.c1[f];
+  for (long long j = f; j < end; ++j) {
+    const int y = c.c1[j];
+    if (y > last + 1) break;
+    if (root[j] != f) continue;
+    const double q = c.q[j];
+    w += q;
+    x0 += q * ((double)c.c0[j] + 0.5);
+    x1 += q * ((double)y + 0.5);
+    last = y;
+  }
+  const double l0 = p0 * (x0 / w) - (double)M.hw0, l1 = p1 * (x1 / w) - (double)M.hw1;
   loc[2 * k] = (float)l0;
   loc[2 * k + 1] = (float)l1;
   var[2 * k] = (float)(p0 * p0 / 12.0);
@@ -185,7 +188,6 @@ size_t al256c(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct ClWs {
   int *head, *row, *parent, *is_root, *cid, *first, *n_cl;
-  double* acc;
   long long* sums;
 };
 
@@ -197,8 +199,6 @@ ClWs cl_view(void* ws, long long n) {
     *q = reinterpret_cast<int*>(p);
     p += al256c((size_t)n * 4);
   }
-  w.acc = reinterpret_cast<double*>(p);
-  p += al256c((size_t)n * 24);
   w.n_cl = reinterpret_cast<int*>(p);
   p += 256;
   w.sums = reinterpret_cast<long long*>(p);
@@ -211,7 +211,7 @@ size_t cluster_workspace_bytes(long long rows, long long n_cells) {
   (void)rows;
   const long long n = n_cells > 0 ? n_cells : 1;
   const long long nb = (n + kScanBlock - 1) / kScanBlock;
-  return 6 * al256c((size_t)n * 4) + al256c((size_t)n * 24) + 256 + al256c((size_t)(nb + 1) * 8) + 256;
+  return 6 * al256c((size_t)n * 4) + 256 + al256c((size_t)(nb + 1) * 8) + 256;
 }
 
 hipError_t launch_cluster(const CellsIn& c, const GeomDev& g, const float* pitch, void* ws, int* moff, float* loc,
@@ -231,9 +231,8 @@ hipError_t launch_cluster(const CellsIn& c, const GeomDev& g, const float* pitch
   }
   device_scan<OpSum, false>(w.is_root, n, w.cid, w.sums, w.n_cl, st);
   if (n > 0) {
-    hipLaunchKernelGGL(k_cl_roots, blocks(n), dim3(kClBlock), 0, st, n, w.head, w.cid, w.first, w.acc);
-    hipLaunchKernelGGL(k_cl_sums, blocks(n), dim3(kClBlock), 0, st, c, w.row, w.head, w.cid, w.acc, cell_cluster);
-    hipLaunchKernelGGL(k_cl_measure, blocks(n), dim3(kClBlock), 0, st, c, g, pitch, w.n_cl, w.first, w.row, w.acc,
+    hipLaunchKernelGGL(k_cl_label, blocks(n), dim3(kClBlock), 0, st, n, w.row, w.head, w.cid, w.first, cell_cluster);
+    hipLaunchKernelGGL(k_cl_measure, blocks(n), dim3(kClBlock), 0, st, c, g, pitch, w.n_cl, w.first, w.row, w.head,
                        loc, var, sp);
   }
   hipLaunchKernelGGL(k_cl_offsets, blocks(rows + 1), dim3(kClBlock), 0, st, c, w.cid, w.n_cl, moff);
