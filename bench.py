@@ -55,6 +55,13 @@ MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.56e9, ("plain", 3072, 48, 3): 29.
 # (560,806 tracks, 4,620,871 measurements), same counters and factors.
 # Source: profiles/k_fit_mu200x64.md.
 FIT_TRAFFIC = {(560806, 4620871): {"rts": 7.571e9, "two_filter": 7.019e9}}
+# HBM bytes per call of ckf_cluster (cells, clusters), ckf_seed (spacepoints,
+# seeds) and ckf_resolve (tracks, measurements) on the same batch, summed over
+# the call's kernels, same counters and factors.
+# Source: profiles/k_cl_k_sd_k_res_mu200x64_hbm_traffic.md.
+CLUSTER_TRAFFIC = {(9783486, 5260424): 1.252e9}
+SEED_TRAFFIC = {(5260424, 2312126): 4.462e9}
+RESOLVE_TRAFFIC = {(560806, 4620871): 1.494e9}
 PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
 PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
 PEAK_BF16 = 2.5e15    # MI355X dense bf16 MFMA, FLOP/s
@@ -299,7 +306,9 @@ def measure_resolve(ckf, finder, ev, stream, reps=3):
     return dict(ms=round(float(np.mean(times[1:])), 4), rounds=rounds, tracks_in=int(r["n_tracks"]),
                 removed=int(np.sum(keep[:r["n_tracks"]] == 0)), before=before, after=after,
                 efficiency_before=round(efficiency(ev, r), 5), efficiency_after=round(efficiency(ev, kept_tracks(r, keep)), 5),
-                note="wall time of the synchronous call (one stream synchronisation per round)")
+                traffic=RESOLVE_TRAFFIC.get((int(r["n_tracks"]), int(r["offsets"][r["n_tracks"]]))),
+                note="wall time of the synchronous call (one stream synchronisation per round); traffic: HBM bytes "
+                     "of its kernels (counters)")
 
 
 def measure_cluster(ckf, geo, det, cells, stream, reps):
@@ -329,7 +338,8 @@ def measure_cluster(ckf, geo, det, cells, stream, reps):
     return dict(cells=cells.n_cells, clusters=r["n_meas"], status=r["status"], ms=round(ms, 4),
                 cells_per_s=round(cells.n_cells / (ms * 1e-3), 1),
                 roofline=dict(bound="hbm", achieved=round(algo / (ms * 1e-3) / 1e9, 1), peak=8000.0, unit="GB/s",
-                              frac=round(algo / (ms * 1e-3) / 8e12, 5), traffic=None, kernel="k_cl_*",
+                              frac=round(algo / (ms * 1e-3) / 8e12, 5),
+                              traffic=CLUSTER_TRAFFIC.get((int(cells.n_cells), int(r["n_meas"]))), kernel="k_cl_*",
                               algorithmic_bytes=int(algo)))
 
 
@@ -393,7 +403,9 @@ def measure_chain(ckf, geo, fld, det, cells, evs, cl, cl_ms, stream, reps):
                 tracks=res["n_tracks"], find_ms=round(find_ms, 4), chain_ms=round(chain_ms, 4),
                 chain_tracks_per_s=round(res["n_tracks"] / (chain_ms * 1e-3), 1), central_particles=int(len(cen)),
                 central_found=round(eff, 5), find_status_flags=flags,
-                note="device times of one ckf_cluster, one ckf_seed and one ckf_find (kernel timer) on the batch")
+                seed_traffic=SEED_TRAFFIC.get((int(m), int(n))),
+                note="device times of one ckf_cluster, one ckf_seed and one ckf_find (kernel timer) on the batch; "
+                     "seed_traffic: HBM bytes of one ckf_seed call (counters)")
 
 
 def roofline_of(m, form, shape):
