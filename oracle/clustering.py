@@ -26,6 +26,17 @@ from __future__ import annotations
 import numpy as np
 
 
+def spacepoints(geom, surface, loc):
+    """Global positions centre + loc0 u + loc1 v (float64) of points with
+    local positions loc [n, 2] on modules surface [n] of the geometry
+    (as_arrays()): the spacepoint definition above."""
+    rot = geom["rot"].astype(np.float64).reshape(-1, 3, 3)
+    centre = geom["center"].astype(np.float64)
+    s = np.asarray(surface)
+    loc = np.asarray(loc, np.float64)
+    return centre[s] + loc[:, 0:1] * rot[s, 0] + loc[:, 1:2] * rot[s, 1]
+
+
 def components(c0, c1):
     """Labels (index of the component's first cell) of one module's cells by
     breadth-first search over touching cells."""

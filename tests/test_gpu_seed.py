@@ -1,14 +1,17 @@
 """Triplet seeding on the GPU (ckf_seed) against the oracle on the same
 spacepoints: the same triplets in the same order and the same parameters on
-a mu = 20 event; sampled middle spacepoints of an 8 x mu = 200 batch; the
-chain cells -> clusters -> seeds -> tracks on the GPU; edge cases."""
+the oracle's clusters of a mu = 20 event; sampled middle spacepoints of an
+8 x mu = 200 batch of measurements; the chain cells -> clusters -> seeds ->
+tracks on the GPU; edge cases.  The spacepoints both sides take are the
+oracle's (its clusters, or its spacepoint definition applied to the
+measurements), rounded to FP32 once."""
 import sys
 
 import numpy as np
 import pytest
 
 from synth import make_event
-from synth.cells import cell_grid, concat_cells, make_cells
+from synth.cells import cell_grid, make_cells
 
 pytestmark = pytest.mark.gpu
 LAYERS = [0, 1, 2, 3]   # the pixel barrel layers of the dense detector, outwards
@@ -39,6 +42,22 @@ def _clusters_on_device(det, cells, ckf):
     return geo, cl, r, m
 
 
+def _upload(offsets, xyz, loc):
+    import torch
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    return t(offsets, torch.int32), t(xyz, torch.float32), t(loc, torch.float32)
+
+
+def _measurement_spacepoints(det, ev):
+    """Spacepoints of an event's (or batch's) measurements by the oracle's
+    definition, rounded to FP32: (offsets, xyz, loc)."""
+    from oracle import clustering as OC
+    S = det.n_surfaces
+    rows = np.repeat(np.arange(ev.n_events * S), np.diff(ev.offsets))
+    xyz = OC.spacepoints(det.as_arrays(), rows % S, ev.loc).astype(np.float32)
+    return np.asarray(ev.offsets, np.int32), xyz, np.asarray(ev.loc, np.float32)
+
+
 def _layer_index(det, offsets, n_events):
     S = det.n_surfaces
     rows = np.repeat(np.arange(n_events * S), np.diff(offsets))
@@ -55,16 +74,21 @@ def test_seed_matches_oracle(ckf, det_dense):
     1e-12 relative (FP64 on both sides); with the tops of every middle held
     on chip (default), with none (every bottom scans its window) and with a
     capacity that some middles exceed."""
-    from oracle import seeding as OS
+    from oracle import clustering as OC, seeding as OS
     ev = make_event(det_dense, 6000, mu=20)
     cells = make_cells(det_dense, ev, 1)
-    geo, cl, r, m = _clusters_on_device(det_dense, cells, ckf)
-    li, rows = _layer_index(det_dense, r["offsets"], 1)
-    ref = OS.seeds(r["spacepoints"].astype(np.float64), li, rows, r["loc"].astype(np.float64), 2.0)
+    _, pitch = cell_grid(det_dense)
+    oc = OC.cluster(cells, det_dense.as_arrays(), pitch)
+    xyz, loc = oc["spacepoint"].astype(np.float32), oc["loc"].astype(np.float32)
+    m = len(xyz)
+    geo = ckf.Geometry(det_dense.as_arrays())
+    d_off, d_xyz, d_loc = _upload(oc["offsets"], xyz, loc)
+    li, rows = _layer_index(det_dense, oc["offsets"], 1)
+    ref = OS.seeds(xyz.astype(np.float64), li, rows, loc.astype(np.float64), 2.0)
     try:
         for cap in (None, 0, 12):
             ckf.seed_top_cap(cap)
-            sd, n = ckf.seed(geo, 1, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+            sd, n = ckf.seed(geo, 1, d_off, d_xyz, d_loc, LAYERS, 2.0)
             _say(f"# seeding (top capacity {cap}): {m} spacepoints, {n} seeds (oracle {len(ref['middle'])})")
             sp = sd["spacepoints"].cpu().numpy()
             assert n == len(ref["middle"])
@@ -82,24 +106,27 @@ def test_seed_matches_oracle(ckf, det_dense):
 
 @pytest.fixture(scope="module")
 def batch200(ckf, det_dense):
-    """Clusters of 8 x mu = 200 events on the GPU."""
-    evs = [make_event(det_dense, 7100 + i, mu=200) for i in range(8)]
-    cells = concat_cells([make_cells(det_dense, e, 200 + i) for i, e in enumerate(evs)])
-    return _clusters_on_device(det_dense, cells, ckf)
+    """Spacepoints of the measurements of 8 x mu = 200 events (the oracle's
+    definition, FP32), on the host and on the device."""
+    from synth import concat_events
+    ev = concat_events([make_event(det_dense, 7100 + i, mu=200) for i in range(8)])
+    off, xyz, loc = _measurement_spacepoints(det_dense, ev)
+    return ckf.Geometry(det_dense.as_arrays()), (off, xyz, loc), _upload(off, xyz, loc)
 
 
 def test_seed_batch_sampled_middles(ckf, det_dense, batch200):
     """8 x mu = 200 events in one call: for 400 sampled middle spacepoints
     the oracle, on that middle's event alone, keeps the same triplets."""
     from oracle import seeding as OS
-    geo, cl, r, m = batch200
-    sd, n = ckf.seed(geo, 8, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+    geo, (off, xyz32, _), dev = batch200
+    m = len(xyz32)
+    sd, n = ckf.seed(geo, 8, *dev, LAYERS, 2.0)
     sp = sd["spacepoints"].cpu().numpy()
     _say(f"# seeding batch: {m} spacepoints, {n} seeds")
-    li, rows = _layer_index(det_dense, r["offsets"], 8)
+    li, rows = _layer_index(det_dense, off, 8)
     S = det_dense.n_surfaces
     ev_of = rows // S
-    xyz = r["spacepoints"].astype(np.float64)
+    xyz = xyz32.astype(np.float64)
     rng = np.random.default_rng(9)
     middles = rng.choice(np.nonzero((li == 1) | (li == 2))[0], 400, replace=False)
     for mid in middles:
@@ -115,12 +142,12 @@ def test_seed_top_capacity_batch(ckf, batch200):
     """8 x mu = 200 events: the seeds are the same, bit for bit, whether the
     middles' tops are held on chip, never (every bottom scans its window),
     or up to a capacity that part of the middles exceed."""
-    geo, cl, r, m = batch200
+    geo, _, dev = batch200
     out = []
     try:
         for cap in (None, 0, 160):
             ckf.seed_top_cap(cap)
-            sd, n = ckf.seed(geo, 8, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0)
+            sd, n = ckf.seed(geo, 8, *dev, LAYERS, 2.0)
             out.append((n, {k: v.cpu().numpy() for k, v in sd.items()}))
             _say(f"# seeding batch (top capacity {cap}): {n} seeds")
     finally:

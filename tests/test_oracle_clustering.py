@@ -111,3 +111,17 @@ def test_measurements_against_truth(det_dense):
     assert np.all(np.abs(res.mean(0)) < 0.05)
     assert np.all(np.abs(res).mean(0) < 0.25) and np.abs(res).max() < 1.5
     assert np.median(dist) < 0.1
+
+
+def test_spacepoints_of_truth_crossings(det_dense):
+    """The spacepoint definition on the simulator's truth: the local position
+    of every crossing, taken to global coordinates, is the crossing point
+    the simulator computed on the helix (planes of flat modules), to the
+    rounding of the FP32 module geometry (centres up to ~1.5 m: a float32
+    ulp there is 1.2e-4 mm)."""
+    from oracle import clustering as OC
+    ev = make_event(det_dense, 6002, mu=5)
+    tr = ev.truth
+    sp = OC.spacepoints(det_dense.as_arrays(), tr.surface, tr.loc)
+    d = np.linalg.norm(sp - tr.pos, axis=1)
+    assert len(d) > 1000 and d.max() < 1.2e-4
