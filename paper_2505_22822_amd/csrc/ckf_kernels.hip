@@ -994,41 +994,59 @@ __global__ __launch_bounds__(kScanBlock) void k_out_scan_blocks(int nb, int* bs_
   }
 }
 
+// One thread per seed walks its best candidate's history backwards for the
+// measurement list.  The tracks' parameter and covariance rows go through
+// LDS and leave as one contiguous range per workgroup (coalesced stores).
 __global__ __launch_bounds__(kScanBlock) void k_out_write(int n, const int* res_node, const int* res_nm,
                                                           const int* res_holes, const double* res_chi2,
                                                           const int* seed_event, const Node* nodes,
                                                           long long node_cap, const int* bs_a, const int* bs_b,
                                                           ckf_tracks out) {
+  __shared__ double s_pc[kScanBlock * 20];  // per track of the workgroup: parameters (5), covariance (15)
+  __shared__ int s_ok[kScanBlock];
   const int s = blockIdx.x * kScanBlock + threadIdx.x;
   const int has = s < n && res_node[s] >= 0 ? 1 : 0;
   const int nm = has ? res_nm[s] : 0;
   int ea, eb, ta, tb;
   block_scan2(has, nm, ea, eb, ta, tb);
-  if (!has) return;
-  if (out.status[CKF_STATUS_FLAGS] & CKF_FLAG_NODE_CAPACITY) return;
-  const int t = bs_a[blockIdx.x] + ea;
+  if (out.status[CKF_STATUS_FLAGS] & CKF_FLAG_NODE_CAPACITY) return;  // the same for the whole workgroup
+  const int t0 = bs_a[blockIdx.x];
+  const int t = t0 + ea;
   const long long mo = (long long)bs_b[blockIdx.x] + eb;
-  if (t >= out.cap_tracks || mo + nm > out.cap_meas) return;
-  out.offsets[t] = (int)mo;
-  int nd = res_node[s];
-  if (nd >= node_cap) return;
-  const Node& last = nodes[nd];
-  for (int k = 0; k < 5; ++k) out.params[5 * t + k] = last.p[k];
-  for (int k = 0; k < 15; ++k) out.cov[15 * t + k] = last.cov[k];
-  out.last_surface[t] = last.surface;
-  for (int k = nm - 1; k >= 0 && nd >= 0 && nd < node_cap; --k) {
-    const Node& q = nodes[nd];
-    out.meas[mo + k] = q.meas;
-    if (out.meas_surface) out.meas_surface[mo + k] = q.surface;
-    if (out.meas_params)
-      for (int c = 0; c < 5; ++c) out.meas_params[5 * (mo + k) + c] = q.p[c];
-    nd = q.parent;
+  int nd = has ? res_node[s] : -1;
+  const bool ok = has && t < out.cap_tracks && mo + nm <= out.cap_meas && nd < node_cap;
+  if (has) s_ok[ea] = ok ? 1 : 0;
+  if (ok) {
+    out.offsets[t] = (int)mo;
+    const Node& last = nodes[nd];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) s_pc[20 * ea + k] = last.p[k];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) s_pc[20 * ea + 5 + k] = last.cov[k];
+    out.last_surface[t] = last.surface;
+    for (int k = nm - 1; k >= 0 && nd >= 0 && nd < node_cap; --k) {
+      const Node& q = nodes[nd];
+      out.meas[mo + k] = q.meas;
+      if (out.meas_surface) out.meas_surface[mo + k] = q.surface;
+      if (out.meas_params)
+        for (int c = 0; c < 5; ++c) out.meas_params[5 * (mo + k) + c] = q.p[c];
+      nd = q.parent;
+    }
+    out.chi2[t] = res_chi2[s];
+    out.ndf[t] = 2 * nm - 5;
+    out.holes[t] = res_holes[s];
+    out.seed[t] = s;
+    out.event[t] = seed_event[s];
   }
-  out.chi2[t] = res_chi2[s];
-  out.ndf[t] = 2 * nm - 5;
-  out.holes[t] = res_holes[s];
-  out.seed[t] = s;
-  out.event[t] = seed_event[s];
+  __syncthreads();
+  for (int i = threadIdx.x; i < 5 * ta; i += kScanBlock) {
+    const int e = i / 5;
+    if (s_ok[e]) out.params[5ll * t0 + i] = s_pc[20 * e + i % 5];
+  }
+  for (int i = threadIdx.x; i < 15 * ta; i += kScanBlock) {
+    const int e = i / 15;
+    if (s_ok[e]) out.cov[15ll * t0 + i] = s_pc[20 * e + 5 + i % 15];
+  }
 }
 
 // ---------------------------------------------------------------------------

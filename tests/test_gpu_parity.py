@@ -264,6 +264,29 @@ def test_ckf_edge_cases(ckf, det_dense):
         ckf.find(geo, fld, badoff)
 
 
+def test_ckf_history_capacity_short(ckf, det_dense):
+    """A history capacity of one node per seed: the device flags the
+    shortage, writes no node past the capacity and ends the launch (every
+    wave leaves its loop on the flag); the binding's retries double the
+    capacity until it fits, and the tracks are then bitwise the default
+    run's."""
+    from paper_2505_22822_amd import _abi
+    ev = make_event(det_dense, 9, mu=40)
+    geo = ckf.Geometry(det_dense.as_arrays())
+    fld = ckf.UniformField(0, 0, 2.0)
+    b = ckf.Batch.from_event(ev)
+    _say(f"[ckf/capacity] {ev.n_seeds} seeds, 1 history node per seed")
+    f = ckf.Finder(geo, fld, b, launch_cfg=ckf.launch(nodes_per_seed=1), counters=False)
+    f.enqueue()
+    short = f.result(check=False)
+    assert int(short["status"][_abi.ST_FLAGS]) & _abi.FLAG_NODE_CAPACITY
+    ref = ckf.find(geo, fld, b)
+    got = ckf.find(geo, fld, b, launch_cfg=ckf.launch(nodes_per_seed=1), retries=7)
+    assert got["n_tracks"] == ref["n_tracks"]
+    for k in ("offsets", "meas", "params", "cov", "chi2", "seed"):
+        assert np.array_equal(got[k], ref[k]), k
+
+
 def test_graph_replay_equals_eager(ckf, det_dense):
     """The hipGraph-captured ckf_find, replayed several times with eager
     calls and synchronisations in between, reproduces the eager result
