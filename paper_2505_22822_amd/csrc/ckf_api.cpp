@@ -982,7 +982,7 @@ ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas
   if (n_layers < 3 || n_layers > 8) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: 3 to 8 seeding layers");
   if (!(std::isfinite(bz) && bz != 0.0)) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: bz must be finite and non-zero");
   if (n_sp > INT32_MAX || (long long)n_events * g->dev.n_surfaces >= INT32_MAX ||
-      (long long)n_events * n_layers * 48 * 240 >= INT32_MAX)
+      ckf::seed_bin_count(n_events, n_layers) >= INT32_MAX)
     return fail(CKF_ERR_NOT_SUPPORTED, "seed: too many spacepoints or rows");
   if (n_events > 0 && !meas_offsets) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: NULL offsets");
   if (n_sp > 0 && (!spacepoints || !loc)) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: NULL spacepoints");

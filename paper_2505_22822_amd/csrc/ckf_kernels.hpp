@@ -66,6 +66,7 @@ hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* 
 size_t fit_workspace_bytes(long long cap_meas);
 size_t seed_workspace_bytes(long long rows, long long n_sp, int n_events, int n_layers);
 int seed_top_cap_max();
+long long seed_bin_count(int n_events, int n_layers);  // (event, layer, phi bin, z bin) bins
 void seed_set_top_cap(int cap);
 hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int* moff, long long n_sp,
                        const float* xyz, const float* loc, const int* layers, int n_layers, double bz, void* ws,

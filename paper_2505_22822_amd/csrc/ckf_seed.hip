@@ -549,12 +549,13 @@ std::atomic<int> g_top_cap{kTopCap};
 }  // namespace
 
 int seed_top_cap_max() { return kTopCap; }
+long long seed_bin_count(int n_events, int n_layers) { return (long long)n_events * n_layers * kNphi * kNz; }
 void seed_set_top_cap(int cap) { g_top_cap.store(cap); }
 
 size_t seed_workspace_bytes(long long rows, long long n_sp, int n_events, int n_layers) {
   (void)rows;
   const long long n = n_sp > 0 ? n_sp : 1;
-  const long long nbins = (long long)n_events * n_layers * kNphi * kNz + 1;
+  const long long nbins = seed_bin_count(n_events, n_layers) + 1;
   const long long nb = (n > nbins ? n : nbins) / scan_detail::kScanBlock + 2;
   return 5 * al256s((size_t)n * 4) + al256s((size_t)n * 8 * kKeep) + al256s((size_t)n * 32) +
          3 * al256s((size_t)nbins * 4) + al256s((size_t)nb * 8) + 256 + 512;
@@ -569,7 +570,7 @@ hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int
   for (int q = 0; q < kMaxSeedLayers; ++q) sl.layer[q] = q < n_layers ? layers[q] : -1;
   const long long rows = (long long)n_events * n_surfaces;
   const long long n = n_sp;
-  const long long nbins = (long long)n_events * n_layers * kNphi * kNz;
+  const long long nbins = seed_bin_count(n_events, n_layers);
   char* p = static_cast<char*>(ws);
   const long long na = n > 0 ? n : 1;
   int* head = reinterpret_cast<int*>(p);

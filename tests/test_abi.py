@@ -89,3 +89,52 @@ def test_host_side_validation(lib):
     assert lib.ckf_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == 1
     assert lib.ckf_kf_update_batch(-1, None, None, None, None, None, None, None, None) == 1
     assert lib.ckf_status_string(5) == b"not supported"
+
+
+def test_host_side_validation_of_the_next_rows(lib):
+    """Argument checks of the fit, resolve, clustering and seeding entry
+    points, taken on the host before any device work: NULL or negative
+    arguments are rejected, sizes beyond the 32-bit index range are not
+    supported, the workspace sizes grow with the problem, and the seeding
+    top capacity accepts only [0, max]."""
+    from paper_2505_22822_amd import _abi
+    nb = C.c_size_t(0)
+    # fit
+    assert lib.ckf_fit_workspace_size(-1, C.byref(nb)) == 1
+    assert lib.ckf_fit_workspace_size(0, C.byref(nb)) == 0
+    small = nb.value
+    assert lib.ckf_fit_workspace_size(10 ** 6, C.byref(nb)) == 0 and nb.value > small
+    assert lib.ckf_fit(None, None, None, None, None, None, 0, 0, None, None, None, None, 0, None, 0, None, None, None,
+                       None, None) == 1
+    # ambiguity resolution
+    assert lib.ckf_resolve_workspace_size(-1, 0, C.byref(nb)) == 1
+    assert lib.ckf_resolve_workspace_size(10, 100, C.byref(nb)) == 0 and nb.value > 0
+    assert lib.ckf_resolve(None, 5, 0, None, None, 0, None, None, 1, None, 0, None, None, None) == 1  # NULL arrays
+    assert lib.ckf_resolve(None, 0, 0, None, None, 0, None, None, -1, None, 0, None, None, None) == 1  # max_shared < 0
+    assert lib.ckf_resolve(None, 0, 0, None, None, 1 << 31, None, None, 1, None, 0, None, None, None) == 5
+    # clustering
+    cells = _abi.CellsDesc()
+    assert lib.ckf_cluster_workspace_size(None, C.byref(nb)) == 1
+    cells.n_events, cells.n_surfaces, cells.n_cells = -1, 10, 0
+    assert lib.ckf_cluster_workspace_size(C.byref(cells), C.byref(nb)) == 1
+    cells.n_events = 1
+    assert lib.ckf_cluster_workspace_size(C.byref(cells), C.byref(nb)) == 0
+    small = nb.value
+    cells.n_cells = 10 ** 6
+    assert lib.ckf_cluster_workspace_size(C.byref(cells), C.byref(nb)) == 0 and nb.value > small
+    assert lib.ckf_cluster(None, C.byref(cells), None, None, 0, None, None, None, None, None, None, None) == 1
+    # seeding
+    assert lib.ckf_seed_workspace_size(1, 10, 0, 2, C.byref(nb)) == 1   # fewer than 3 layers
+    assert lib.ckf_seed_workspace_size(1, 10, 0, 9, C.byref(nb)) == 1   # more than 8
+    assert lib.ckf_seed_workspace_size(1, 10, 100, 4, C.byref(nb)) == 0
+    small = nb.value
+    assert lib.ckf_seed_workspace_size(2, 10, 100, 4, C.byref(nb)) == 0 and nb.value > small  # bins per event
+    layers = (C.c_int32 * 4)(0, 1, 2, 3)
+    n = C.c_int32(0)
+    assert lib.ckf_seed(None, 1, None, 0, None, None, layers, 4, 2.0, None, 0, 0, C.byref(n), None, None, None, None,
+                        None, None) == 1
+    mx = C.c_int32(0)
+    assert lib.ckf_seed_set_top_cap(-1, C.byref(mx)) == 1 and mx.value > 0
+    assert lib.ckf_seed_set_top_cap(mx.value + 1, None) == 1
+    assert lib.ckf_seed_set_top_cap(0, None) == 0
+    assert lib.ckf_seed_set_top_cap(mx.value, None) == 0  # back to the default
