@@ -38,6 +38,17 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _settle(dev):
+    """Wait for the work torch's current stream holds on `dev` (the fills and
+    copies that just initialised a call's buffers).  The library's calls run
+    on the stream the caller names, which need not be torch's current one
+    and is not ordered after it; a buffer is therefore complete before it is
+    handed to a call."""
+    import torch
+    if not torch.cuda.is_current_stream_capturing():
+        torch.cuda.current_stream(dev).synchronize()
+
+
 def _stream_handle(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -332,6 +343,7 @@ class Finder:
                                        _ptr(b.var))
         self._seeds = _abi.Seeds(b.n_seeds, _ptr(b.seed_event), _ptr(b.seed_surface), _ptr(b.seed_params),
                                  _ptr(b.seed_cov))
+        _settle(dev)
 
     def enqueue(self, stream=None):
         """One ckf_find on the stream (asynchronous, allocation-free)."""
@@ -427,6 +439,7 @@ class Fitter:
                                        _ptr(b.var))
         self._seeds = _abi.Seeds(b.n_seeds, _ptr(b.seed_event), _ptr(b.seed_surface), _ptr(b.seed_params),
                                  _ptr(b.seed_cov))
+        _settle(dev)
 
     @staticmethod
     def from_finder(finder: "Finder", smoother="rts"):
@@ -498,6 +511,7 @@ class Clusterer:
         self.spacepoints = z((n, 3), torch.float32) if spacepoints else None
         self.cell_cluster = z(n, torch.int32) if cell_cluster else None
         self.status = z(1, torch.int32)
+        _settle(dev)
 
     def enqueue(self, stream=None):
         _check(_abi.load().ckf_cluster(self.geometry.handle, C.byref(self._desc), _ptr(self.pitch),
@@ -554,6 +568,7 @@ def seed(geometry: Geometry, n_events: int, meas_offsets, spacepoints, loc, laye
     out = dict(event=z(cap, torch.int32), surface=z(cap, torch.int32), params=z((cap, 5), torch.float64),
                cov=z((cap, 15), torch.float64), spacepoints=z((cap, 3), torch.int32))
     n = z(1, torch.int32)
+    _settle(dev)
     _check(lib.ckf_seed(geometry.handle, int(n_events), _ptr(meas_offsets), n_sp, _ptr(spacepoints), _ptr(loc),
                         lay.ctypes.data_as(C.c_void_p), nl, float(bz), _ptr(ws), ws.numel(), cap, _ptr(n),
                         _ptr(out["event"]), _ptr(out["surface"]), _ptr(out["params"]), _ptr(out["cov"]),
@@ -591,6 +606,7 @@ def resolve(tracks: dict, n_meas: int, max_shared=1, stream=None, workspace=None
         workspace = torch.empty(max(1, int(nb.value)), dtype=torch.uint8, device=dev)
     keep = torch.zeros(max(1, cap_tracks), dtype=torch.int32, device=dev)
     rounds = C.c_int32(0)
+    _settle(dev)
     _check(lib.ckf_resolve(_ptr(tracks["n_tracks"]), cap_tracks, cap_meas, _ptr(tracks["offsets"]),
                            _ptr(tracks["meas"]), int(n_meas), _ptr(tracks["chi2"]), _ptr(tracks["ndf"]),
                            int(max_shared), _ptr(workspace), workspace.numel(), _ptr(keep), C.byref(rounds),
@@ -631,6 +647,7 @@ def propagate_batch(geometry, field, src, params, cov, dst, cfg=None, stream=Non
     jac = torch.zeros((n, 25), dtype=torch.float64, device=dev)
     path = torch.zeros(n, dtype=torch.float64, device=dev)
     ok = torch.zeros(n, dtype=torch.int32, device=dev)
+    _settle(dev)
     _check(_abi.load().ckf_propagate_batch(geometry.handle, field.handle, C.byref(cfg), n, _ptr(src), _ptr(params),
                                            _ptr(cov), _ptr(dst), _ptr(p_out), _ptr(c_out), _ptr(jac), _ptr(path),
                                            _ptr(ok), _stream_handle(stream)), "ckf_propagate_batch")
@@ -644,6 +661,7 @@ def kf_update_batch(params, cov, meas, var, stream=None):
     p_out = torch.zeros((n, 5), dtype=torch.float64, device=dev)
     c_out = torch.zeros((n, 15), dtype=torch.float64, device=dev)
     chi2 = torch.zeros(n, dtype=torch.float64, device=dev)
+    _settle(dev)
     _check(_abi.load().ckf_kf_update_batch(n, _ptr(params), _ptr(cov), _ptr(meas), _ptr(var), _ptr(p_out),
                                            _ptr(c_out), _ptr(chi2), _stream_handle(stream)), "ckf_kf_update_batch")
     return p_out, c_out, chi2
