@@ -41,8 +41,6 @@ namespace {
 constexpr int kClBlock = 256;
 constexpr int kScanBlock = scan_detail::kScanBlock;
 
-__device__ __forceinline__ int grid_i() { return blockIdx.x * blockDim.x + threadIdx.x; }
-
 __global__ void k_cl_clear(int* status) { *status = 0; }
 
 __global__ void k_cl_init(long long n, int* __restrict__ head, int* __restrict__ parent) {

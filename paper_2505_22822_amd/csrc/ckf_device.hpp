@@ -457,33 +457,6 @@ __device__ __forceinline__ void transport_cov(const float J[5][5], double* C) {
   for (int q = 0; q < 15; ++q) C[q] = R[q];
 }
 
-// C <- J C J^T with J (FP32, row-major) read element by element from
-// per-lane LDS with stride kWave, so the Jacobian does not occupy registers
-// through the transport.
-__device__ __forceinline__ void transport_cov_lds(const float* J, double* C) {
-  double R[15];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    double row[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int l = 0; l < 5; ++l) s = fma((double)J[(5 * i + l) * kWave], C[pk(l, k)], s);
-      row[k] = s;
-    }
-#pragma unroll
-    for (int j = i; j < 5; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) s = fma(row[k], (double)J[(5 * j + k) * kWave], s);
-      R[pk(i, j)] = s;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 15; ++q) C[q] = R[q];
-}
-
 __device__ __forceinline__ double chi2_of(const double* p, const double* C, double m0, double m1, double v0,
                                           double v1) {
   const double r0 = m0 - p[0], r1 = m1 - p[1];

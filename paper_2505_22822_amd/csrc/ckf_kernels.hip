@@ -119,26 +119,6 @@ struct Light {
   float h, path;
 };
 
-__device__ __forceinline__ void load_light(const Pool& P, int r, Light& c) {
-#pragma unroll
-  for (int k = 0; k < 5; ++k) c.p[k] = PDr(P, r, (PD_P + k));
-  c.chi2 = PDr(P, r, PD_CHI2);
-  c.surf = PIr(P, r, PI_SURF);
-  c.node = PIr(P, r, PI_NODE);
-  const int nmh = PIr(P, r, PI_NMH);
-  c.nm = nmh & 0xffff;
-  c.holes = nmh >> 16;
-  c.mask = (unsigned long long)(unsigned)PIr(P, r, PI_MASK_LO) |
-           ((unsigned long long)(unsigned)PIr(P, r, PI_MASK_HI) << 32);
-#pragma unroll
-  for (int k = 0; k < kMaxList; ++k) c.list[k] = PIr(P, r, (PI_LIST + k));
-  const int nl = PIr(P, r, PI_NLIST);
-  c.nlist = nl & 0xff;
-  c.root = nl >> 8;
-  c.h = PFr(P, r, PF_H);
-  c.path = PFr(P, r, PF_PATH);
-}
-
 __device__ __forceinline__ void load_cov(const Pool& P, int r, double* C) {
 #pragma unroll
   for (int k = 0; k < 15; ++k) C[k] = PDr(P, r, PD_C + k);

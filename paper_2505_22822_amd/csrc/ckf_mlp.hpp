@@ -22,7 +22,6 @@ __device__ __forceinline__ unsigned short bf16_bits(float f) {
   return (unsigned short)(u >> 16);
 }
 
-__device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
 __device__ __forceinline__ bf16x4 pack_bf16(f32x4 v) {
   bf16x4 r;
