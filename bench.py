@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.56e9, ("plain", 3072, 48, 3): 29.
 # HBM bytes per k_fit launch on the 64 x mu=200 batch's plain-search tracks
 # (560,806 tracks, 4,620,871 measurements), same counters and factors.
 # Source: profiles/k_fit_mu200x64.md.
-FIT_TRAFFIC = {(560806, 4620871): {"rts": 7.571e9, "two_filter": 7.019e9}}
+FIT_TRAFFIC = {(560806, 4620871): {"rts": 8.749e9, "two_filter": 6.271e9}}
 # HBM bytes per call of ckf_cluster (cells, clusters), ckf_seed (spacepoints,
 # seeds) and ckf_resolve (tracks, measurements) on the same batch, summed over
 # the call's kernels, same counters and factors.

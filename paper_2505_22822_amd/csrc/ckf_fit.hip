@@ -7,9 +7,12 @@
 // visits the surfaces of its measurements in order: an FP32 RKN4 leg with
 // its tangent-column Jacobian (the search's stepper), FP64 covariance
 // transport, FP64 gain-form update with the Joseph covariance, then the
-// module's Highland scattering added at the updated state.  Predicted and
-// filtered states and the leg Jacobians go to the workspace (one 432-byte
-// record per measurement); the smoother then runs backwards over them:
+// module's Highland scattering added at the updated state.  The smoother
+// runs backwards over one workspace record per measurement, which holds only
+// what it reads: the filtered state and covariance, and for RTS also the
+// predicted state and the leg's Jacobian (the predicted covariance is
+// rebuilt from the record before it with the forward pass's own scattering
+// and transport functions):
 //   RTS:        A_k = C_k|k F^T C_k+1|k^-1 (a Cholesky solve, no inverse),
 //               x_k|n = x_k|k + A_k (x_k+1|n - x_k+1|k),
 //               C_k|n = C_k|k + A_k (C_k+1|n - C_k+1|k) A_k^T;
@@ -20,6 +23,8 @@
 //               surface to its prediction there, and is combined with the
 //               forward filtered state as x = x_f + C_f (C_f + C_b)^-1
 //               (x_b - x_f), C = C_f - C_f (C_f + C_b)^-1 C_f.
+#include <type_traits>
+
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
 
@@ -28,15 +33,19 @@ namespace ckf {
 constexpr double kBackwardInflation = 100.0;
 constexpr double kPi = 3.14159265358979323846;
 
-struct alignas(16) FitRec {
-  double pp[5], pC[15];  // predicted at the measurement
+struct alignas(16) RecRts {
+  double pp[5];          // predicted state at the measurement
   double fp[5], fC[15];  // filtered
   float F[25];           // the leg into the measurement (row-major)
-  float pad[3];
+  float pad[1];
 };
-static_assert(sizeof(FitRec) == 432, "fit record layout");
+static_assert(sizeof(RecRts) == 304, "RTS record layout");
+struct alignas(16) RecTwo {
+  double fp[5], fC[15];  // filtered
+};
+static_assert(sizeof(RecTwo) == 160, "two-filter record layout");
 
-size_t fit_workspace_bytes(long long cap_meas) { return (size_t)cap_meas * sizeof(FitRec); }
+size_t fit_workspace_bytes(long long cap_meas) { return (size_t)cap_meas * sizeof(RecRts); }
 
 namespace {
 
@@ -147,9 +156,11 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
                                             const int* __restrict__ n_tracks_p, int cap_tracks, long long cap_meas,
                                             const int* __restrict__ off, const int* __restrict__ meas,
                                             const int* __restrict__ msurf, const int* __restrict__ seed,
-                                            FitRec* __restrict__ ws, double* __restrict__ out_p,
+                                            void* __restrict__ ws_raw, double* __restrict__ out_p,
                                             double* __restrict__ out_C, double* __restrict__ chi2_out,
                                             int* __restrict__ ok) {
+  using Rec = typename std::conditional<kTwo, RecTwo, RecRts>::type;
+  Rec* __restrict__ ws = static_cast<Rec*>(ws_raw);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n_t = min(*n_tracks_p, cap_tracks);
   if (t >= n_t) return;
@@ -181,7 +192,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
   int cur = s.surface[si];
   double chi2 = 0.0;
   for (long long k = a; k < b; ++k) {
-    FitRec& R = ws[k];
+    Rec& R = ws[k];
     const int dst = msurf[k];
     float J[5][5];
     if (dst != cur) {
@@ -195,14 +206,14 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
         for (int j = 0; j < 5; ++j) J[i][j] = i == j ? 1.f : 0.f;
     }
+    if constexpr (!kTwo) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) R.pp[i] = p[i];
+      for (int i = 0; i < 5; ++i) R.pp[i] = p[i];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) R.pC[i] = C[i];
+      for (int i = 0; i < 5; ++i)
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
-#pragma unroll
-      for (int j = 0; j < 5; ++j) R.F[5 * i + j] = J[i][j];
+        for (int j = 0; j < 5; ++j) R.F[5 * i + j] = J[i][j];
+    }
     const int id = meas[k];
     const double m0 = m.loc[2ll * id], m1 = m.loc[2ll * id + 1], v0 = m.var[2ll * id], v1 = m.var[2ll * id + 1];
     chi2 += chi2_of(p, C, m0, m1, v0, v1);
@@ -223,17 +234,38 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
   // ---- the last measurement: smoothed = filtered
   double xs[5], Cs[15];
   {
-    const FitRec& R = ws[b - 1];
+    const Rec& R = ws[b - 1];
 #pragma unroll
     for (int i = 0; i < 5; ++i) xs[i] = out_p[5 * (b - 1) + i] = R.fp[i];
 #pragma unroll
     for (int i = 0; i < 15; ++i) Cs[i] = out_C[15 * (b - 1) + i] = R.fC[i];
   }
-  if (!kTwo) {
+  if constexpr (!kTwo) {
     // ---- RTS
     for (long long k = b - 2; k >= a; --k) {
-      const FitRec& Rk = ws[k];
-      const FitRec& Rn = ws[k + 1];
+      const Rec& Rk = ws[k];
+      const Rec& Rn = ws[k + 1];
+      // the prediction's covariance at k+1, as the forward pass made it:
+      // the scattering of module k at the filtered state, then the leg
+      // (none between two measurements of one module)
+      double pC[15], kp[5];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) pC[i] = Rk.fC[i];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) kp[i] = Rk.fp[i];
+      if (cfg.material) {
+        Module M;
+        load_module(g, msurf[k], M);
+        apply_ms(M, cfg.mass, kp, pC);
+      }
+      if (msurf[k + 1] != msurf[k]) {
+        float Fn[5][5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+#pragma unroll
+          for (int j = 0; j < 5; ++j) Fn[i][j] = Rn.F[5 * i + j];
+        transport_cov(Fn, pC);
+      }
       double fC[5][5], G[5][5], L[5][5];
       unpack5(Rk.fC, fC);
       // G = F fC  (so A^T = pC^-1 G)
@@ -246,7 +278,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
           for (int l = 0; l < 5; ++l) acc = fma((double)Rn.F[5 * i + l], fC[l][j], acc);
           G[i][j] = acc;
         }
-      unpack5(Rn.pC, L);
+      unpack5(pC, L);
       if (!chol5(L)) {
         fail_track(a, b, out_p, out_C, ok, t, 0);
         return;
@@ -270,7 +302,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
       for (int i = 0; i < 5; ++i)
 #pragma unroll
-        for (int j = i; j < 5; ++j) D[i][j] = D[j][i] = Cs[pk(i, j)] - Rn.pC[pk(i, j)];
+        for (int j = i; j < 5; ++j) D[i][j] = D[j][i] = Cs[pk(i, j)] - pC[pk(i, j)];
 #pragma unroll
       for (int i = 0; i < 5; ++i)
 #pragma unroll
@@ -300,7 +332,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
     // ---- two-filter: backward filter, combined with the forward one
     double bp[5], bC[15];
     {
-      const FitRec& R = ws[b - 1];
+      const Rec& R = ws[b - 1];
       double q[5], Q[15];
 #pragma unroll
       for (int i = 0; i < 5; ++i) q[i] = R.fp[i];
@@ -310,7 +342,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
       kf_update(q, Q, m.loc[2ll * id], m.loc[2ll * id + 1], m.var[2ll * id], m.var[2ll * id + 1], bp, bC);
     }
     for (long long k = b - 2; k >= a; --k) {
-      const FitRec& Rk = ws[k];
+      const Rec& Rk = ws[k];
       flip(bp, bC);
       if (msurf[k + 1] != msurf[k]) {
         float J[5][5];
@@ -389,7 +421,7 @@ hipError_t launch_fit(const GeomDev& g, const FieldDev& f, const CfgDev& cfg, co
                       double* chi2, int* ok, hipStream_t st) {
   if (cap_tracks <= 0) return hipSuccess;
   const dim3 grid((cap_tracks + 63) / 64), block(64);
-  FitRec* w = static_cast<FitRec*>(ws);
+  void* w = ws;
   if (f.map) {
     if (two_filter)
       hipLaunchKernelGGL((k_fit<true, true>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks, cap_meas,
