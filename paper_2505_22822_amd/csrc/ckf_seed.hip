@@ -50,6 +50,7 @@ constexpr int kMaxSeedLayers = 8;
 constexpr double kKappa64 = 2.99792458e-4;
 constexpr double kCotMax = 3.0, kZ0Max = 200.0, kPtMin = 0.5, kD0Max = 1.0, kDcotBase = 0.01, kDcotMs = 0.007;
 constexpr double kSigma[5] = {0.2, 0.6, 0.01, 0.01, 0.15};
+constexpr double kTolMax = kDcotBase + kDcotMs * (1.0 + kCotMax * kCotMax);  // the largest cot tolerance
 constexpr int kTriGrid = 1024;  // persistent workgroups of the triplet search: 4 per CU, a multiple of the 8 XCDs
 
 struct SeedLayers {
@@ -297,13 +298,19 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
     // every top candidate of M through the (M, T) doublet cuts; place = false
     // counts the passing ones per bucket, place = true writes them in bucket
     // order (bs holds the buckets' starts then, and their ends afterwards)
+    // A top of a triplet has |cot_MT| <= COT_MAX and, since the bottom's
+    // doublet line meets z0 = z_M - r_M cot_BM within Z0_MAX and cot_MT is
+    // within tol <= kTolMax of cot_BM, |z_M - r_M cot_MT| <= Z0_MAX + r_M
+    // kTolMax: the cot window of the tops (1 mm of margin)
+    const double zb = kZ0Max + kTolMax * rM + kZMargin;
+    const double clo = fmax(-kCotMax, (M.z - zb) / rM), chi = fmin(kCotMax, (M.z + zb) / rM);
     const auto tops = [&](bool place) {
       int n = 0;
       for (int lt = li_m + 1; lt < sl.n; ++lt) {
         const double s0 = __uint_as_float(rlim[2 * lt]) - rM, s1 = __uint_as_float(rlim[2 * lt + 1]) - rM;
-        if (!(s0 <= s1)) continue;
+        if (!(s0 <= s1) || !(clo <= chi)) continue;
         int zt0, zt1;
-        z_window(M.z - kCotMax * s0, M.z + kCotMax * s0, M.z - kCotMax * s1, M.z + kCotMax * s1, zt0, zt1);
+        z_window(M.z + s0 * clo, M.z + s0 * chi, M.z + s1 * clo, M.z + s1 * chi, zt0, zt1);
         for (int dt = -1; dt <= 1; ++dt) {
           int j0, j1;
           range(lt, dt, zt0, zt1, j0, j1);
