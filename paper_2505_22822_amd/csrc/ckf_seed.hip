@@ -413,9 +413,15 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
       // z_B = z0 + r_B (z_M - z0) / r_M for |z0| <= Z0_MAX, r_B in the layer's range
       const double r0 = __uint_as_float(rlim[2 * lb]), r1 = __uint_as_float(rlim[2 * lb + 1]);
       if (!(r0 <= r1)) continue;  // no spacepoints on that layer
-      int zb0, zb1;
+      int zb0, zb1, zc0, zc1;
       z_window(-kZ0Max + r0 * (M.z + kZ0Max) / rM, kZ0Max + r0 * (M.z - kZ0Max) / rM,
                -kZ0Max + r1 * (M.z + kZ0Max) / rM, kZ0Max + r1 * (M.z - kZ0Max) / rM, zb0, zb1);
+      // and |cot_BM| <= COT_MAX: z_B = z_M - (r_M - r_B) cot_BM
+      z_window(M.z - kCotMax * (rM - r0), M.z + kCotMax * (rM - r0), M.z - kCotMax * (rM - r1),
+               M.z + kCotMax * (rM - r1), zc0, zc1);
+      zb0 = max(zb0, zc0);
+      zb1 = min(zb1, zc1);
+      if (zb0 > zb1) continue;
       for (int db = -1; db <= 1; ++db) {
         int j0, j1;
         range(lb, db, zb0, zb1, j0, j1);
