@@ -33,6 +33,7 @@ __global__ void k_meas_rows(int n_rows, long long n_meas, const int* __restrict_
     return;
   }
   float mv = 0.f;
+#pragma unroll 8  // eight independent loads in flight instead of one round trip per measurement
   for (int i = a; i < b; ++i) {
     row_of[i] = row;
     mv = fmaxf(mv, var[2 * i]);
@@ -52,6 +53,7 @@ __global__ void k_meas_scatter(long long n_meas, const int* __restrict__ offsets
   const int a = offsets[row], b = offsets[row + 1];
   const float x = loc[2 * i];
   int rank = 0;
+#pragma unroll 8
   for (int j = a; j < b; ++j) {
     const float y = loc[2 * j];
     rank += (y < x || (y == x && j < i)) ? 1 : 0;
