@@ -625,29 +625,35 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
               const int mid = (l + u) >> 1;
               if (A.w.m_sorted[mid].x < lo) l = mid + 1; else u = mid;
             }
+            // measurements in loc0 order until past the window; the next
+            // record is loaded before the current one is gated, so two loads
+            // are in flight (the order of the visits is unchanged)
+            float4 ms = l < b ? A.w.m_sorted[l] : make_float4(INFINITY, 0.f, 0.f, 0.f);
             for (int i = l; i < b; ++i) {
-              const float4 ms = A.w.m_sorted[i];
+              const float4 nx = i + 1 < b ? A.w.m_sorted[i + 1] : make_float4(INFINITY, 0.f, 0.f, 0.f);
               if (ms.x > hi) break;
               CNT_ADD(CKF_CNT_CHI2, 1);
               const double x2 = chi2_of(p, C, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w);
-              if (!(x2 < cfg.chi2_max)) continue;
-              double cx = x2;
-              int cid = A.w.m_id[i], cpos = i;
+              if (x2 < cfg.chi2_max) {
+                double cx = x2;
+                int cid = A.w.m_id[i], cpos = i;
 #pragma unroll
-              for (int k = 0; k < kMaxBranch; ++k) {
-                const bool lt = cx < acc_x2[k] || (cx == acc_x2[k] && cid < acc_id[k]);
-                if (lt) {
-                  const double tx = acc_x2[k];
-                  const int ti = acc_id[k], tp = acc_pos[k];
-                  acc_x2[k] = cx;
-                  acc_id[k] = cid;
-                  acc_pos[k] = cpos;
-                  cx = tx;
-                  cid = ti;
-                  cpos = tp;
+                for (int k = 0; k < kMaxBranch; ++k) {
+                  const bool lt = cx < acc_x2[k] || (cx == acc_x2[k] && cid < acc_id[k]);
+                  if (lt) {
+                    const double tx = acc_x2[k];
+                    const int ti = acc_id[k], tp = acc_pos[k];
+                    acc_x2[k] = cx;
+                    acc_id[k] = cid;
+                    acc_pos[k] = cpos;
+                    cx = tx;
+                    cid = ti;
+                    cpos = tp;
+                  }
                 }
+                n_acc = min(n_acc + 1, cfg.branches);
               }
-              n_acc = min(n_acc + 1, cfg.branches);
+              ms = nx;
             }
           }
           if (n_acc == 0) {  // a hole
