@@ -671,27 +671,27 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
   ListAcc acc;
   list_init(acc);
   int visited = 0;
-  for (int ipr = ip0; ipr <= ip1; ++ipr) {
+  for (int ipr = ip0; ipr <= ip1 && iw0 <= iw1; ++ipr) {
     int ip = ipr % Lr.nphi;
     if (ip < 0) ip += Lr.nphi;
-    for (int iw = iw0; iw <= iw1; ++iw) {
-      const int cell = Lr.cell_base + ip * Lr.nw + iw;
-      const int a = g.cell_off[cell], b = g.cell_off[cell + 1];
-      // two candidates per round: their id and record loads are in flight together
-      for (int q = a; q < b; q += 2) {
-        if (visited >= kMaxCand) {
-          overflow = 1;
-          break;
-        }
-        visited += 2;
-        const int m0 = g.cell_mod[q];
-        const int m1 = q + 1 < b ? g.cell_mod[q + 1] : -1;
-        Module M0, M1;
-        load_module(g, m0, M0);
-        if (m1 >= 0) load_module(g, m1, M1);
-        if (m0 != exclude) list_test(acc, m0, M0, P, T, k, s_base, margin, n_tested);
-        if (m1 >= 0 && m1 != exclude) list_test(acc, m1, M1, P, T, k, s_base, margin, n_tested);
+    // the cells iw0..iw1 of one phi row are adjacent in the grid's CSR, so
+    // their entries are one range (two bound loads per row, not per cell)
+    const int row = Lr.cell_base + ip * Lr.nw;
+    const int a = g.cell_off[row + iw0], b = g.cell_off[row + iw1 + 1];
+    // two candidates per round: their id and record loads are in flight together
+    for (int q = a; q < b; q += 2) {
+      if (visited >= kMaxCand) {
+        overflow = 1;
+        break;
       }
+      visited += q + 1 < b ? 2 : 1;
+      const int m0 = g.cell_mod[q];
+      const int m1 = q + 1 < b ? g.cell_mod[q + 1] : -1;
+      Module M0, M1;
+      load_module(g, m0, M0);
+      if (m1 >= 0) load_module(g, m1, M1);
+      if (m0 != exclude) list_test(acc, m0, M0, P, T, k, s_base, margin, n_tested);
+      if (m1 >= 0 && m1 != exclude) list_test(acc, m1, M1, P, T, k, s_base, margin, n_tested);
     }
   }
   return list_out(acc, list);
