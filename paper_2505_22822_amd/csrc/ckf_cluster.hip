@@ -30,6 +30,8 @@
 //             set, first in readout order): the scan stops at the first cell
 //             whose c1 is past the last member's c1 + 1.  No atomics, and the
 //             additions happen in the same order as in a sequential pass.
+#include <climits>
+
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
 #include "ckf_scan.hpp"
@@ -75,6 +77,23 @@ __device__ __forceinline__ int cl_find(int* p, int x) {
   return x;
 }
 
+// joins the components of touching cells i and j: the larger root is hooked
+// under the smaller one with compare-and-swap, retried on a lost race
+__device__ __forceinline__ void link_pair(int* parent, int i, int j) {
+  int ri = cl_find(parent, i), rj = cl_find(parent, j);
+  while (ri != rj) {
+    if (ri < rj) {
+      const int t = ri;
+      ri = rj;
+      rj = t;
+    }
+    const int old = atomicCAS(&parent[ri], ri, rj);
+    if (old == ri) break;
+    ri = cl_find(parent, old);
+    rj = cl_find(parent, rj);
+  }
+}
+
 __global__ void k_cl_link(CellsIn c, const int* __restrict__ row, int* __restrict__ parent,
                           int* __restrict__ status) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -84,19 +103,25 @@ __global__ void k_cl_link(CellsIn c, const int* __restrict__ row, int* __restric
   const int x = c.c0[i], y = c.c1[i];
   const long long a = c.offsets[r];
   if (i > a && (c.c1[i - 1] > y || (c.c1[i - 1] == y && c.c0[i - 1] >= x))) atomicOr(status, CKF_CLUSTER_UNSORTED);
-  for (long long j = i - 1; j >= a && c.c1[j] >= y - 1; --j) {
-    if (abs(c.c0[j] - x) > 1) continue;
-    int ri = cl_find(parent, (int)i), rj = cl_find(parent, (int)j);
-    while (ri != rj) {  // hook the larger root under the smaller one
-      if (ri < rj) {
-        const int t = ri;
-        ri = rj;
-        rj = t;
+  // earlier cells of the module, newest first, while their row is c1 - 1 or
+  // c1; their positions are loaded four at a time (loads in flight together)
+  bool more = true;
+  for (long long j0 = i - 1; more && j0 >= a; j0 -= 4) {
+    int cy[4], cx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long j = j0 - u;
+      cy[u] = j >= a ? c.c1[j] : INT_MIN;
+      cx[u] = j >= a ? c.c0[j] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!more) break;
+      if (cy[u] < y - 1) {  // also past the module's first cell (INT_MIN)
+        more = false;
+        break;
       }
-      const int old = atomicCAS(&parent[ri], ri, rj);
-      if (old == ri) break;
-      ri = cl_find(parent, old);
-      rj = cl_find(parent, rj);
+      if (abs(cx[u] - x) <= 1) link_pair(parent, (int)i, (int)(j0 - u));
     }
   }
 }
@@ -149,15 +174,33 @@ __global__ void k_cl_measure(CellsIn c, GeomDev g, const float* __restrict__ pit
   const long long end = max((long long)c.offsets[rr + 1], (long long)f + 1);
   double w = 0.0, x0 = 0.0, x1 = 0.0;
   int last = c.c1[f];
-  for (long long j = f; j < end; ++j) {
-    const int y = c.c1[j];
-    if (y > last + 1) break;
-    if (root[j] != f) continue;
-    const double q = c.q[j];
-    w += q;
-    x0 += q * ((double)c.c0[j] + 0.5);
-    x1 += q * ((double)y + 0.5);
-    last = y;
+  bool more = true;
+  for (long long j0 = f; more && j0 < end; j0 += 4) {  // four cells' loads in flight together
+    int cy[4], cx[4], rt[4];
+    float cq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long j = j0 + u;
+      const bool in = j < end;
+      cy[u] = in ? c.c1[j] : INT_MAX;
+      rt[u] = in ? root[j] : -1;
+      cx[u] = in ? c.c0[j] : 0;
+      cq[u] = in ? c.q[j] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!more) break;
+      if (cy[u] > last + 1) {  // also past the row's end (INT_MAX)
+        more = false;
+        break;
+      }
+      if (rt[u] != f) continue;
+      const double q = cq[u];
+      w += q;
+      x0 += q * ((double)cx[u] + 0.5);
+      x1 += q * ((double)cy[u] + 0.5);
+      last = cy[u];
+    }
   }
   const double l0 = p0 * (x0 / w) - (double)M.hw0, l1 = p1 * (x1 / w) - (double)M.hw1;
   loc[2 * k] = (float)l0;
