@@ -49,8 +49,8 @@ MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 
 # by (form, grid, seeds per group, waves per SIMD): the pools make the
 # traffic depend on the launch shape.  Source: profiles/k_ckf_mu200x64_hbm_traffic.md;
 # an entry is dropped when its kernel changes.
-MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.56e9, ("plain", 3072, 48, 3): 29.56e9,
-                    ("learned", 2048, 48, 2): 24.57e9, ("learned", 4096, 48, 2): 24.57e9}
+MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.67e9, ("plain", 3072, 48, 3): 29.67e9,
+                    ("learned", 2048, 48, 2): 24.94e9, ("learned", 4096, 48, 2): 24.94e9}
 # HBM bytes per k_fit launch on the 64 x mu=200 batch's plain-search tracks
 # (560,806 tracks, 4,620,871 measurements), same counters and factors.
 # Source: profiles/k_fit_mu200x64.md.
