@@ -194,6 +194,10 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
   for (long long k = a; k < b; ++k) {
     Rec& R = ws[k];
     const int dst = msurf[k];
+    // the measurement is loaded before the leg, so its loads are in flight
+    // while the leg is propagated
+    const int id = meas[k];
+    const float lm0 = m.loc[2ll * id], lm1 = m.loc[2ll * id + 1], lv0 = m.var[2ll * id], lv1 = m.var[2ll * id + 1];
     float J[5][5];
     if (dst != cur) {
       if (!fit_leg<kMap>(g, F, cfg, cur, dst, p, C, J)) {
@@ -214,8 +218,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
         for (int j = 0; j < 5; ++j) R.F[5 * i + j] = J[i][j];
     }
-    const int id = meas[k];
-    const double m0 = m.loc[2ll * id], m1 = m.loc[2ll * id + 1], v0 = m.var[2ll * id], v1 = m.var[2ll * id + 1];
+    const double m0 = lm0, m1 = lm1, v0 = lv0, v1 = lv1;
     chi2 += chi2_of(p, C, m0, m1, v0, v1);
     double po[5], Co[15];
     kf_update(p, C, m0, m1, v0, v1, po, Co);
