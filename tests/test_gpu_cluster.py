@@ -137,3 +137,46 @@ def test_cluster_edge_cases(ckf, det_dense):
                  np.zeros(2, np.int64))
     _, got = _run(ckf, det_dense, bad2)
     assert got["status"] & 1
+
+
+def test_cluster_dense_modules(ckf, det_dense):
+    """Extremes of cell density on two pixel modules of one event: a fully
+    filled 150 x 150 block (one cluster of 22,500 cells: the longest
+    union-find chains and member scan) and a 120 x 120 region filled at 30 %
+    (thousands of clusters of every shape).  Same clusters and centroids as
+    the oracle."""
+    from oracle import clustering as OC
+    from synth.cells import Cells
+    S = det_dense.n_surfaces
+    g = det_dense.as_arrays()
+    n_cells, pitch = cell_grid(det_dense)
+    pix = [s for s in range(S) if n_cells[s, 0] >= 300 and n_cells[s, 1] >= 300][:2]
+    assert len(pix) == 2
+    rng = np.random.default_rng(41)
+    yy, xx = np.mgrid[0:150, 0:150]
+    block = (xx.ravel() + 10, yy.ravel() + 20)
+    yy, xx = np.mgrid[0:120, 0:120]
+    keep = rng.random(xx.size) < 0.3
+    sparse = (xx.ravel()[keep], yy.ravel()[keep])
+    parts = {pix[0]: block, pix[1]: sparse}
+    c0, c1, counts = [], [], np.zeros(S, np.int64)
+    for s in range(S):
+        if s in parts:
+            a0, a1 = parts[s]
+            o = np.lexsort((a0, a1))  # readout order: row c1, then column c0
+            c0.append(a0[o])
+            c1.append(a1[o])
+            counts[s] = len(o)
+    c0 = np.concatenate(c0).astype(np.int32)
+    c1 = np.concatenate(c1).astype(np.int32)
+    q = rng.uniform(0.2, 2.0, len(c0)).astype(np.float32)
+    off = np.r_[0, np.cumsum(counts)].astype(np.int32)
+    cells = Cells(1, S, off, c0, c1, q, np.full(len(c0), -1, np.int64))
+    ref = OC.cluster(cells, g, pitch)
+    _, got = _run(ckf, det_dense, cells)
+    _say(f"# dense modules: {cells.n_cells} cells, {got['n_meas']} clusters (oracle {len(ref['size'])}), "
+         f"largest {ref['size'].max()}")
+    assert got["status"] == 0
+    np.testing.assert_array_equal(got["offsets"], ref["offsets"])
+    np.testing.assert_array_equal(got["cell_cluster"], ref["label"])
+    assert np.all(np.abs(got["loc"] - ref["loc"]) <= 4e-6)
