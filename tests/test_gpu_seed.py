@@ -215,3 +215,52 @@ def test_seed_edge_cases(ckf, det_dense):
     part, n_part = ckf.seed(geo, 1, cl.offsets, cl.spacepoints[:m], cl.loc[:m], LAYERS, 2.0, cap_seeds=100)
     assert n_part == n_full > 100 and part["params"].shape[0] == 100
     np.testing.assert_array_equal(part["spacepoints"].cpu().numpy(), full["spacepoints"][:100].cpu().numpy())
+
+
+def test_seed_hand_placed_degenerate_cases(ckf, det_dense):
+    """Hand-placed spacepoints on modules of the first three seeding layers,
+    against the oracle case by case: points exactly on the x axis (zero
+    circle determinant: no finite circle, no seed); a radial line at phi =
+    0.3 (collinear up to rounding: a huge radius and d0 ~ 0, a seed); a
+    curved helix of 2 GeV (a seed with the right charge sign); the middle
+    moved 3 mm sideways (d0 cut fails); an azimuth step of 0.15 rad (no
+    seed)."""
+    import math
+    import torch
+    from oracle import seeding as OS
+    g = det_dense.as_arrays()
+    S = det_dense.n_surfaces
+    mods = np.array([int(np.nonzero(g["layer"] == L)[0][0]) for L in LAYERS[:3]])  # one module per layer
+    order = np.argsort(mods)  # spacepoints come in row (module id) order
+    geo = ckf.Geometry(g)
+
+    def run(xyz):
+        off = np.zeros(S + 1, np.int32)
+        for s in mods:
+            off[s + 1:] += 1
+        xyz32 = np.asarray(xyz, np.float32)[order]
+        li = np.array([0, 1, 2])[order]
+        loc = np.zeros((3, 2), np.float32)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+        sd, n = ckf.seed(geo, 1, t(off, torch.int32), t(xyz32, torch.float32), t(loc, torch.float32), LAYERS, 2.0)
+        ref = OS.triplets(xyz32.astype(np.float64), li, 2.0)
+        got = [tuple(int(v) for v in r) for r in sd["spacepoints"].cpu().numpy()]
+        assert [(b, m, t_) for m, b, t_, _ in ref] == got
+        return n, sd
+
+    pt = lambda r, z, phi: [r * math.cos(phi), r * math.sin(phi), z]
+    n, _ = run([[30.0, 0.0, 3.0], [70.0, 0.0, 7.0], [120.0, 0.0, 12.0]])
+    assert n == 0  # exactly collinear
+    n, _ = run([pt(30, 3, 0.3), pt(70, 7, 0.3), pt(120, 12, 0.3)])
+    assert n == 1
+    R = 2.0 / (OS.KAPPA * 2.0)  # a 2 GeV helix from the origin, turning clockwise (positive charge)
+    arc = lambda r: [R * math.sin(2 * math.asin(r / (2 * R))) * 1.0, -R * (1 - math.cos(2 * math.asin(r / (2 * R)))), 0.1 * r]
+    n, sd = run([arc(30), arc(70), arc(120)])
+    assert n == 1 and sd["params"][0, 4].item() > 0
+    side = [pt(30, 3, 0.3), pt(70, 7, 0.3), pt(120, 12, 0.3)]
+    side[1][0] += -3.0 * math.sin(0.3)
+    side[1][1] += 3.0 * math.cos(0.3)
+    n, _ = run(side)
+    assert n == 0
+    n, _ = run([pt(30, 3, 0.3), pt(70, 7, 0.45), pt(120, 12, 0.6)])
+    assert n == 0
