@@ -173,3 +173,47 @@ def test_fit_edge_cases(ckf, det_dense):
                        f.tracks["meas"].data_ptr(), f.tracks["meas_surface"].data_ptr(),
                        f.tracks["seed"].data_ptr(), 2, f.workspace.data_ptr(), f.workspace.numel(),
                        f.params.data_ptr(), f.cov.data_ptr(), f.chi2.data_ptr(), f.ok.data_ptr(), None) == 1
+
+
+@pytest.mark.parametrize("smoother", ["rts", "two_filter"])
+def test_fit_tracks_on_the_seed_module(ckf, det_dense, oracle_event, smoother):
+    """Tracks the search does not make, fitted against the oracle: one
+    measurement on the seed's own module (no leg; smoothed = filtered), and
+    two measurements of the seed's module in a row (a second update with no
+    leg between; the RTS step then rebuilds the prediction without a
+    transport).  Same tolerances as the fit of the oracle's tracks."""
+    import torch
+    from oracle import fit as OF
+    ev, inp, _ = oracle_event
+    seeds = [s for s in range(ev.n_seeds)
+             if ev.offsets[ev.seed_surface[s] + 1] - ev.offsets[ev.seed_surface[s]] >= 2][:40]
+    assert len(seeds) >= 10
+    off, meas, msurf, seed = [0], [], [], []
+    for k, s in enumerate(seeds):
+        sf = int(ev.seed_surface[s])
+        a = int(ev.offsets[sf])
+        ids = [a] if k % 2 == 0 else [a, a + 1]
+        meas += ids
+        msurf += [sf] * len(ids)
+        seed.append(s)
+        off.append(len(meas))
+    off, meas, msurf, seed = (np.array(x, np.int32) for x in (off, meas, msurf, seed))
+    dev = lambda x: torch.as_tensor(x, device="cuda")
+    tr = dict(n_tracks=dev(np.array([len(seed)], np.int32)), offsets=dev(off), meas=dev(meas),
+              meas_surface=dev(msurf), seed=dev(seed))
+    geo = ckf.Geometry(det_dense.as_arrays())
+    fld = ckf.UniformField(0, 0, 2.0)
+    f = ckf.Fitter(geo, fld, ckf.Batch.from_event(ev), tr, ckf.config(), smoother)
+    f.enqueue()
+    g = f.result()
+    op, oc, ochi2, ook = OF.fit_tracks(inp, ev, off, meas, msurf, seed, "rts" if smoother == "rts" else "two")
+    assert np.all(ook == 1) and np.all(g["ok"] == 1)
+    d = g["params"] - op
+    d[:, 2] = (d[:, 2] + math.pi) % (2 * math.pi) - math.pi
+    m = len(meas)
+    scale = np.concatenate([np.broadcast_to(SCALE, (m, 4)), np.abs(op[:, 4:5])], 1)
+    rel = np.abs(d) / np.maximum(np.abs(op), scale)
+    crel = np.abs(g["cov"][:, DIAG] - oc[:, DIAG]) / oc[:, DIAG]
+    _say(f"#   {smoother} on the seed module: {len(seed)} tracks, params worst {rel.max(0)}, cov worst {crel.max():.2e}")
+    assert np.all(rel < 1e-4) and np.all(crel < 1e-4)
+    np.testing.assert_allclose(g["chi2"], ochi2, rtol=0, atol=2e-2)
