@@ -51,6 +51,10 @@ MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 
 # an entry is dropped when its kernel changes.
 MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.67e9, ("plain", 3072, 48, 3): 29.67e9,
                     ("learned", 2048, 48, 2): 24.94e9, ("learned", 4096, 48, 2): 24.94e9}
+# SIMT efficiency of the same launches, SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU): the share of
+# lanes a VALU instruction finds active.  Source: profiles/k_ckf_mu200x64_sq_counters.md.
+MEASURED_SIMT = {("plain", 6144, 48, 3): 0.243, ("plain", 3072, 48, 3): 0.243,
+                 ("learned", 2048, 48, 2): 0.312, ("learned", 4096, 48, 2): 0.312}
 # HBM bytes per k_fit launch on the 64 x mu=200 batch's plain-search tracks
 # (560,806 tracks, 4,620,871 measurements), same counters and factors.
 # Source: profiles/k_fit_mu200x64.md.
@@ -415,10 +419,10 @@ def roofline_of(m, form, shape):
     mf = c.get("mlp_blocks", 0) * MFMA_FLOP_PER_BLOCK
     t = m["kernel_ms"] * 1e-3
     frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64 + mf / PEAK_BF16) / t
-    traffic = MEASURED_TRAFFIC.get((form, shape["grid"], shape["seeds_per_group"], shape["waves_per_simd"]))
+    key = (form, shape["grid"], shape["seeds_per_group"], shape["waves_per_simd"])
     return dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                frac=round(frac, 5), traffic=traffic, kernel="k_ckf", kernel_ms=round(m["kernel_ms"], 4), fp32_flop=f32,
-                fp64_flop=f64, bf16_mfma_flop=mf,
+                frac=round(frac, 5), traffic=MEASURED_TRAFFIC.get(key), simt_efficiency=MEASURED_SIMT.get(key),
+                kernel="k_ckf", kernel_ms=round(m["kernel_ms"], 4), fp32_flop=f32, fp64_flop=f64, bf16_mfma_flop=mf,
                 note="achieved = FP32-equivalent rate (F32 + 2*F64 + F_bf16/15.9)/t against the FP32 vector peak")
 
 
