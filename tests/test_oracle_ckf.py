@@ -90,6 +90,47 @@ def test_pulls_unit_width_with_scattering(oracle_lib, det_dense):
     assert X.mean() == pytest.approx(1.0, abs=0.04)
 
 
+def test_true_hit_chi2_is_chi2_two_dof(oracle_lib, det_barrel):
+    """The gate's chi2 (paper section 2: from the predicted covariance and
+    the residual) of a particle's own hit, predicted by propagating the
+    filtered state along the particle's true crossings: without material the
+    residual is Gaussian with covariance S = H C H^T + V, so the values follow
+    the chi-square law with 2 degrees of freedom, CDF 1 - exp(-x/2).  The
+    Kolmogorov-Smirnov distance stays below its 1 % critical value 1.63/sqrt(n)
+    (a variance 20 % off moves it to about four times that), the mean is 2."""
+    x2 = []
+    inp = oracle_lib.Inputs(det_barrel.as_arrays(), (0, 0, 2.0))
+    for i in range(6):
+        ev = make_event(det_barrel, 700 + i, kind="tiny")
+        inp.set_event(ev)
+        tr = ev.truth
+        for k in range(ev.n_seeds):
+            p = ev.seed_particle[k]
+            path = tr.surface[tr.particle == p]
+            s, x, C = int(ev.seed_surface[k]), ev.seed_params[k].copy(), ev.seed_cov[k].copy()
+            assert path[0] == s
+            for j, m in enumerate(path):
+                if j > 0:
+                    res = oracle_lib.propagate(inp, s, x, C, int(m), material_on=0)
+                    assert res is not None
+                    x, C, _, _ = res
+                    s = int(m)
+                mine = [q for q in range(ev.offsets[s], ev.offsets[s + 1]) if ev.meas_particle[q] == p]
+                if len(mine) != 1:
+                    continue
+                q = mine[0]
+                x, C, c2 = oracle_lib.kf_update(x, C, ev.loc[q].astype(float), ev.var[q].astype(float))
+                if j > 0:
+                    x2.append(c2)
+    v = np.sort(np.array(x2))
+    n = len(v)
+    assert n > 5000
+    F = 1.0 - np.exp(-v / 2.0)
+    D = max(np.max(np.arange(1, n + 1) / n - F), np.max(F - np.arange(n) / n))
+    assert D < 1.63 / math.sqrt(n), D
+    assert v.mean() == pytest.approx(2.0, abs=6 * 2.0 / math.sqrt(n))
+
+
 def test_efficiency_tiny_event(oracle_lib, det_barrel):
     """Isolated 1-10 GeV muons, 99 % hit efficiency: at least 98 % of seeds
     give a double-matched track (paper section 3.1 definition)."""
