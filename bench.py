@@ -452,7 +452,7 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--seeds-per-group", type=int, default=0)
-    ap.add_argument("--waves", type=int, default=0, help="kernel register variant: waves per SIMD (1 or 2)")
+    ap.add_argument("--waves", type=int, default=0, help="kernel register variant: waves per SIMD (1, 2 or 3; 0: the autotuner picks)")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--no-learned", action="store_true", help="plain form only")
     ap.add_argument("--train-events", type=int, default=26)
