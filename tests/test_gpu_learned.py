@@ -291,3 +291,28 @@ def test_learned_search_equals_plain_where_listing_agrees(ckf, det_dense, traine
         r = f.result()
         for k in ("offsets", "meas", "params"):
             assert np.array_equal(r[k], learned[k]), (waves, k)
+
+
+def test_trained_network_saves_listing_work(ckf, det_dense, trained):
+    """What training gains over the search without it, on one mu = 200 event
+    (instrumented runs): the untrained network (its initial weights) is never
+    confident, so every navigation falls back to the geometric listing and
+    the module tests equal the plain search's; the trained network is
+    confident on a share of the rows and its proposals replace the grid
+    listing there, so fewer modules are tested."""
+    import torch
+    from paper_2505_22822_amd import learned
+    geo, fld, params, log, info = trained
+    b = ckf.Batch.from_event(make_event(det_dense, 6001, mu=200))
+    plain = ckf.find(geo, fld, b)
+    fresh = ckf.find(geo, fld, b, model=ckf.Model(torch.as_tensor(learned.init_params(1), device="cuda")))
+    tuned = ckf.find(geo, fld, b, model=ckf.Model(params))
+    cp, cf, ct = plain["counters"], fresh["counters"], tuned["counters"]
+    _say(f"# listing module tests: plain {cp['nav_modules']}, untrained {cf['nav_modules']} "
+         f"({cf['proposals']} proposals of {cf['mlp_rows']} rows), trained {ct['nav_modules']} "
+         f"({ct['proposals']} proposals of {ct['mlp_rows']} rows)")
+    # (the initial weights' summed top-3 probability stays below 0.8 over the inputs' whole range)
+    assert cf["proposals"] == 0 and cf["nav_modules"] == cp["nav_modules"]
+    assert ct["proposals"] >= 0.1 * ct["mlp_rows"]
+    # (seen: 13 % fewer, 806,568 against 927,099, with 27 % of the rows confident)
+    assert ct["nav_modules"] < 0.95 * cp["nav_modules"]
