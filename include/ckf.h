@@ -454,8 +454,10 @@ ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas
  * on-chip memory, ordered by cot, and falls back to scanning each bottom's
  * window of tops directly when a middle has more than `cap` of them; both
  * ways give the same seeds.  cap in [0, *cap_max] (0: always scan); the
- * default is the maximum.  cap_max (host, out) or NULL.  Not synchronised
- * with calls in flight on other threads. */
+ * default is the maximum.  cap_max (host, out) or NULL: written in every
+ * case.  A cap outside the range returns CKF_ERR_INVALID_ARGUMENT and keeps
+ * the current setting.  Not synchronised with calls in flight on other
+ * threads. */
 ckf_status ckf_seed_set_top_cap(int32_t cap, int32_t* cap_max);
 
 /* Greedy ambiguity resolution of found tracks by shared measurements (paper
