@@ -503,8 +503,11 @@ ckf_status ckf_geometry_create(const ckf_geometry_desc* d, ckf_geometry** out) {
   if (st != CKF_OK) return st;
   NbTable nb;
   build_neighbours(d, nb);
+  int device = 0;
+  const hipError_t ed = hipGetDevice(&device);
+  if (ed != hipSuccess) return hip_fail(ed, "hipGetDevice");
   ckf_geometry* g = new ckf_geometry();
-  hipGetDevice(&g->device);
+  g->device = device;
   auto cleanup = [&](ckf_status s) {
     for (void* p : g->allocations) (void)hipFree(p);
     delete g;
@@ -824,8 +827,11 @@ ckf_status ckf_model_create(const float* params, void* stream, ckf_model** out) 
   *out = nullptr;
   if (reinterpret_cast<uintptr_t>(params) % 16 != 0)
     return fail(CKF_ERR_INVALID_ARGUMENT, "model_create: params must be 16-byte aligned");
+  int device = 0;
+  const hipError_t ed = hipGetDevice(&device);
+  if (ed != hipSuccess) return hip_fail(ed, "hipGetDevice");
   ckf_model* md = new ckf_model();
-  hipGetDevice(&md->device);
+  md->device = device;
   const hipError_t e = hipMalloc(&md->buf, ckf::kModelBytes);
   if (e != hipSuccess) {
     delete md;
