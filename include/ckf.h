@@ -63,7 +63,8 @@ enum {
 };
 #define CKF_FLAG_NODE_CAPACITY 1  /* workspace history too small: retry larger */
 #define CKF_FLAG_OUT_CAPACITY 2   /* output arrays too small: retry larger */
-#define CKF_FLAG_BAD_OFFSETS 4    /* measurement offsets not non-decreasing */
+#define CKF_FLAG_BAD_OFFSETS 4    /* measurement offsets that do not tile [0, n_meas): offsets[0] != 0,
+                                     a decreasing pair, or offsets[last] != n_meas (nothing is searched) */
 
 typedef struct ckf_geometry ckf_geometry; /* opaque, device-resident */
 typedef struct ckf_field ckf_field;       /* opaque, device-resident */
@@ -148,12 +149,16 @@ typedef struct ckf_config {
 
 /* Measurements of one or more events, grouped by (event, surface): those of
  * event e on surface s are rows offsets[e*n_surfaces+s] .. offsets[..+1]-1.
- * A measurement's id is its row; found tracks report ids.  Device memory. */
+ * A measurement's id is its row; found tracks report ids.  Device memory.
+ * Offsets that do not tile [0, n_meas) set CKF_FLAG_BAD_OFFSETS and nothing
+ * is searched.  A measurement whose loc0 is NaN sorts after every finite one
+ * of its module and is never accepted (its chi2 is not finite), as is one
+ * with a NaN loc1 or variance. */
 typedef struct ckf_measurements {
   int32_t n_events;
   int32_t n_surfaces;        /* must equal the geometry's */
   int64_t n_meas;
-  const int32_t* offsets;    /* [n_events*n_surfaces+1], non-decreasing, offsets[0] = 0 */
+  const int32_t* offsets;    /* [n_events*n_surfaces+1], non-decreasing, offsets[0] = 0, last = n_meas */
   const float* loc;          /* [n_meas][2] */
   const float* var;          /* [n_meas][2] variances of loc0, loc1 */
 } ckf_measurements;

@@ -20,14 +20,16 @@ namespace ckf {
 // ---------------------------------------------------------------------------
 // measurement preparation
 
-// Pass 1, one thread per (event, module) row: validate the offsets, tag
+// Pass 1, one thread per (event, module) row: validate the offsets (the
+// rows must tile [0, n_meas) exactly, so every measurement gets a row), tag
 // every measurement with its row, largest var0 of the row.
 __global__ void k_meas_rows(int n_rows, long long n_meas, const int* __restrict__ offsets,
                             const float* __restrict__ var, int* row_of, float* maxv0, int* status) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n_rows) return;
   const int a = offsets[row], b = offsets[row + 1];
-  if ((row == 0 && a != 0) || a > b || a < 0 || (long long)b > n_meas) {
+  if ((row == 0 && a != 0) || a > b || a < 0 || (long long)b > n_meas ||
+      (row == n_rows - 1 && (long long)b != n_meas)) {
     atomicOr(status + CKF_STATUS_FLAGS, CKF_FLAG_BAD_OFFSETS);
     maxv0[row] = 0.f;
     return;
@@ -41,21 +43,28 @@ __global__ void k_meas_rows(int n_rows, long long n_meas, const int* __restrict_
   maxv0[row] = mv;
 }
 
-// Pass 2, one thread per measurement: its rank by (loc0, id) inside its row
-// is its sorted position (a stable segmented sort by loc0).
-__global__ void k_meas_scatter(long long n_meas, const int* __restrict__ offsets, const int* __restrict__ row_of,
-                               const float* __restrict__ loc, const float* __restrict__ var, float4* sorted, int* id,
-                               const int* status) {
+// Sort key of a loc0: NaN sorts as +infinity (after every finite value), so
+// that (key, index) is a strict total order and the ranks of a row are a
+// permutation of it whatever the values.  Such a measurement never lies
+// inside a chi2 window and its chi2 is never accepted.
+__device__ __forceinline__ float loc0_key(float x) { return x != x ? INFINITY : x; }
+
+// Pass 2, one thread per measurement: its rank by (loc0 key, id) inside its
+// row is its sorted position (a stable segmented sort by loc0).
+__global__ void k_meas_scatter(long long n_meas, int n_rows, const int* __restrict__ offsets,
+                               const int* __restrict__ row_of, const float* __restrict__ loc,
+                               const float* __restrict__ var, float4* sorted, int* id, const int* status) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_meas) return;
   if (status[CKF_STATUS_FLAGS] & CKF_FLAG_BAD_OFFSETS) return;
   const int row = row_of[i];
+  if (row < 0 || row >= n_rows) return;  // (cannot happen once the offsets passed pass 1)
   const int a = offsets[row], b = offsets[row + 1];
-  const float x = loc[2 * i];
+  const float x = loc0_key(loc[2 * i]);
   int rank = 0;
 #pragma unroll 8
   for (int j = a; j < b; ++j) {
-    const float y = loc[2 * j];
+    const float y = loc0_key(loc[2 * j]);
     rank += (y < x || (y == x && j < i)) ? 1 : 0;
   }
   const int d = a + rank;
@@ -1112,7 +1121,7 @@ hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status,
                      m.var, w.row_of, w.row_maxvar0, status);
   if (m.n_meas > 0)
     hipLaunchKernelGGL(k_meas_scatter, dim3((unsigned)((m.n_meas + 255) / 256)), dim3(256), 0, st,
-                       (long long)m.n_meas, m.offsets, w.row_of, m.loc, m.var, w.m_sorted, w.m_id, status);
+                       (long long)m.n_meas, rows, m.offsets, w.row_of, m.loc, m.var, w.m_sorted, w.m_id, status);
   return hipGetLastError();
 }
 

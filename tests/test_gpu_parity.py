@@ -264,6 +264,45 @@ def test_ckf_edge_cases(ckf, det_dense):
         ckf.find(geo, fld, badoff)
 
 
+def test_ckf_measurement_input_rules(ckf, det_dense):
+    """Measurement offsets must tile [0, n_meas): a final offset short of
+    n_meas is flagged (those measurements would have no module) and nothing
+    is searched.  NaN positions sort after every finite value of their
+    module and are never accepted: a batch with NaN loc0 and loc1 values on
+    busy modules gives exactly the oracle's tracks on the same input."""
+    from paper_2505_22822_amd import _abi
+    geo = ckf.Geometry(det_dense.as_arrays())
+    fld = ckf.UniformField(0, 0, 2.0)
+    ev = make_event(det_dense, 12, mu=20)
+    _say(f"[ckf/meas-rules] {ev.n_seeds} seeds, short final offset and NaN positions")
+    b = ckf.Batch.from_event(ev)
+    offs = b.offsets.clone()
+    offs[-1] = offs[-1] - 3
+    short = ckf.Batch(b.n_events, b.n_surfaces, offs, b.loc, b.var, b.seed_event, b.seed_surface,
+                      b.seed_params, b.seed_cov)
+    f = ckf.Finder(geo, fld, short, counters=False)
+    f.enqueue()
+    r = f.result(check=False)
+    assert int(r["status"][_abi.ST_FLAGS]) & _abi.FLAG_BAD_OFFSETS
+    assert r["n_tracks"] == 0
+    # NaN positions: every 7th measurement of the ten busiest modules
+    rows = np.diff(ev.offsets)
+    busy = np.argsort(-rows, kind="stable")[:10]
+    loc = ev.loc.copy()
+    nan_ids = []
+    for k, row in enumerate(busy):
+        ids = np.arange(ev.offsets[row], ev.offsets[row + 1])[::7]
+        loc[ids, k % 2] = np.nan
+        nan_ids.extend(ids.tolist())
+    ev.loc = loc
+    ref = _oracle_run(det_dense, ev)
+    got = _gpu_run(ckf, det_dense, ev)
+    assert got["status"][_abi.ST_FLAGS] == 0
+    assert not np.isin(got["meas"], nan_ids).any()
+    same, extra, worst, cw, mism = _compare_tracks(ref, got, "ckf/meas-rules")
+    assert same == ref["n_tracks"] and not extra and not mism
+
+
 def test_ckf_history_capacity_short(ckf, det_dense):
     """A history capacity of one node per seed: the device flags the
     shortage, writes no node past the capacity and ends the launch (every
