@@ -85,12 +85,22 @@ class _Tracks(C.Structure):
 
 
 _STAT_NAMES = ("steps", "navigations", "nav_modules", "legs", "legs_failed", "rk_trials", "rk_rejects",
-               "chi2_evals", "kf_updates", "ms_updates", "crossed", "holes", "pruned", "finished")
+               "chi2_evals", "kf_updates", "ms_updates", "crossed", "holes", "pruned", "finished",
+               "mlp_rows", "proposals", "proposal_misses")
 
 
 class _Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in _STAT_NAMES]
 
+
+class _Learned(C.Structure):
+    _fields_ = [("next", C.c_void_p), ("region", C.c_void_p), ("anchor", C.c_void_p), ("params", C.c_void_p),
+                ("min_prob", C.c_double), ("topk", C.c_int32), ("bf16", C.c_int32)]
+
+
+# causes (bits of the per-seed `near` output) by which an FP32 evaluation of
+# the learned proposal can decide otherwise than the oracle's FP64 one
+NEAR_CONF, NEAR_BF16, NEAR_EDGE, NEAR_RANK = 1, 2, 4, 8
 
 _lib = None
 
@@ -110,6 +120,13 @@ def lib():
         _lib.orc_navigate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                       C.c_uint64, C.c_double, C.c_void_p, C.c_void_p]
         _lib.orc_scatter.restype = C.c_int
+        _lib.orc_ckf_find_learned.restype = C.c_int
+        _lib.orc_mlp_forward.restype = C.c_int
+        _lib.orc_mlp_forward.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p]
+        _lib.orc_learned_propose.restype = C.c_int
+        _lib.orc_learned_propose.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                             C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p]
     return _lib
 
 
@@ -154,8 +171,27 @@ def make_config(**over):
     return _Config(**d), d
 
 
-def ckf_find(inp: Inputs, n_threads=0, cap_tracks=None, cap_meas=None, **cfg):
-    """Run the oracle; returns a dict of numpy arrays (tracks in seed order)."""
+class LearnedInputs:
+    """The learned proposal's inputs for the oracle: the neighbour table of
+    the whole detector (``oracle.learned.neighbour_table``), the network
+    parameters and the use rule; keeps the arrays alive."""
+
+    def __init__(self, table, params, min_prob=0.95, topk=3, bf16=True):
+        nxt, reg, anc = table
+        self.next = np.ascontiguousarray(nxt, np.int32)
+        self.region = np.ascontiguousarray(reg, np.int32)
+        self.anchor = np.ascontiguousarray(anc, np.float64)
+        self.params = np.ascontiguousarray(params, np.float32)
+        assert self.params.shape == (6752,)
+        self.struct = _Learned(_p(self.next), _p(self.region), _p(self.anchor), _p(self.params),
+                               float(min_prob), int(topk), int(bool(bf16)))
+
+
+def ckf_find(inp: Inputs, n_threads=0, cap_tracks=None, cap_meas=None, learned: LearnedInputs = None, **cfg):
+    """Run the oracle; returns a dict of numpy arrays (tracks in seed order).
+    With `learned`, the search uses the learned proposal and the result also
+    holds per seed ``near`` (the NEAR_* causes met) and ``differs`` (a used
+    proposal listed differently from the geometric lookup)."""
     conf, _ = make_config(**cfg)
     n = inp.n_seeds
     mult = 1 if conf.tracks_per_seed == 1 else 64
@@ -171,8 +207,15 @@ def ckf_find(inp: Inputs, n_threads=0, cap_tracks=None, cap_meas=None, **cfg):
                                         ("offsets", "meas", "params", "cov", "chi2", "ndf", "holes",
                                          "seed", "event", "last_surface", "meas_surface", "meas_params")))
     st = _Stats()
-    rc = lib().orc_ckf_find(C.byref(inp.geom), C.byref(inp.field), C.byref(inp.meas), C.byref(inp.seeds),
-                            C.byref(conf), int(n_threads), C.byref(tr), C.byref(st))
+    if learned is None:
+        rc = lib().orc_ckf_find(C.byref(inp.geom), C.byref(inp.field), C.byref(inp.meas), C.byref(inp.seeds),
+                                C.byref(conf), int(n_threads), C.byref(tr), C.byref(st))
+    else:
+        near = np.zeros(max(1, n), np.int32)
+        differs = np.zeros(max(1, n), np.int32)
+        rc = lib().orc_ckf_find_learned(C.byref(inp.geom), C.byref(inp.field), C.byref(inp.meas),
+                                        C.byref(inp.seeds), C.byref(conf), C.byref(learned.struct),
+                                        int(n_threads), C.byref(tr), C.byref(st), _p(near), _p(differs))
     if rc != 0:
         raise RuntimeError(f"orc_ckf_find failed with status {rc} (tracks {tr.n_tracks}, meas {tr.n_meas_total})")
     nt, nm = tr.n_tracks, tr.n_meas_total
@@ -183,7 +226,42 @@ def ckf_find(inp: Inputs, n_threads=0, cap_tracks=None, cap_meas=None, **cfg):
         res[k] = out[k][:nm]
     res["n_tracks"] = nt
     res["stats"] = {k: int(getattr(st, k)) for k in _STAT_NAMES}
+    if learned is not None:
+        res["near"] = near[:n]
+        res["differs"] = differs[:n]
     return res
+
+
+def mlp_forward(params, x, bf16=True):
+    """Network logits [n, 32] of inputs x [n, 7] (the oracle's C++ pass)."""
+    pr = np.ascontiguousarray(params, np.float32)
+    xx = np.ascontiguousarray(x, np.float64).reshape(-1, 7)
+    out = np.zeros((xx.shape[0], 32))
+    rc = lib().orc_mlp_forward(_p(pr), int(bool(bf16)), xx.shape[0], _p(xx), _p(out))
+    if rc != 0:
+        raise RuntimeError("orc_mlp_forward failed")
+    return out
+
+
+def learned_propose(inp: Inputs, learned: LearnedInputs, surface, layer, X, T, qop):
+    """One proposal: None when the network does not run, else a dict with the
+    window cell, the unrounded input, the summed top-k probability, the three
+    most probable outputs, the proposed modules, `used` and the NEAR_* causes."""
+    Xa = np.ascontiguousarray(X, np.float64)
+    Ta = np.ascontiguousarray(T, np.float64)
+    cell = np.zeros(2, np.int32)
+    feat = np.zeros(7)
+    conf = C.c_double(0)
+    cls = np.zeros(3, np.int32)
+    mods = np.zeros(3, np.int32)
+    near = C.c_int32(0)
+    rc = lib().orc_learned_propose(C.byref(inp.geom), C.byref(learned.struct), int(surface), int(layer), _p(Xa),
+                                   _p(Ta), float(qop), _p(cell), _p(feat), C.byref(conf), _p(cls), _p(mods),
+                                   C.byref(near))
+    if rc < 0:
+        return None
+    return dict(cell=cell, features=feat, conf=conf.value, classes=cls, modules=mods, used=bool(rc),
+                near=near.value)
 
 
 def propagate(inp: Inputs, src, params, cov, dst, **cfg):

@@ -238,12 +238,13 @@ Cfg load_cfg(const orc_config* c) {
 struct Stats {
   int64_t steps = 0, navigations = 0, nav_modules = 0, legs = 0, legs_failed = 0, rk_trials = 0,
           rk_rejects = 0, chi2_evals = 0, kf_updates = 0, ms_updates = 0, crossed = 0, holes = 0,
-          pruned = 0, finished = 0;
+          pruned = 0, finished = 0, mlp_rows = 0, proposals = 0, proposal_misses = 0;
   void add(const Stats& o) {
     steps += o.steps; navigations += o.navigations; nav_modules += o.nav_modules; legs += o.legs;
     legs_failed += o.legs_failed; rk_trials += o.rk_trials; rk_rejects += o.rk_rejects;
     chi2_evals += o.chi2_evals; kf_updates += o.kf_updates; ms_updates += o.ms_updates;
     crossed += o.crossed; holes += o.holes; pruned += o.pruned; finished += o.finished;
+    mlp_rows += o.mlp_rows; proposals += o.proposals; proposal_misses += o.proposal_misses;
   }
 };
 
@@ -642,34 +643,34 @@ struct Listed {
   int id;
 };
 
-// Modules of `layer` listed from the trajectory point P (path s_base from
-// the current state, direction T, curvature k): those whose plane the
-// second-order expansion P + d T + d^2 k / 2 meets within the half lengths
-// plus nav_margin at a positive total path, in path order (at most 4).
-void list_layer(const Geometry& G, const Cfg& cfg, int layer, V3 P, V3 T, V3 k, double s_base, int exclude,
-                std::vector<int>& list, Stats& st) {
-  std::vector<Listed> cand;
-  for (int m : G.members[layer]) {
-    if (m == exclude) continue;
-    const Surface& S = G.s[m];
-    const double half_diag = std::sqrt((S.hw0 + cfg.nav_margin) * (S.hw0 + cfg.nav_margin) +
-                                       (S.hw1 + cfg.nav_margin) * (S.hw1 + cfg.nav_margin));
-    if (norm(S.c - P) > half_diag + kReach) continue;
-    ++st.nav_modules;
-    const double a = 0.5 * dot(S.n, k), b = dot(S.n, T), c0 = dot(S.n, P - S.c);
-    if (std::fabs(b) < 1e-3) continue;
-    double d = -c0 / b;
-    const double disc = b * b - 4.0 * a * c0;
-    if (disc >= 0) {
-      const double q = -0.5 * (b + std::copysign(std::sqrt(disc), b));
-      if (q != 0) d = c0 / q;
-    }
-    const V3 Q = P + d * T + (0.5 * d * d) * k;
-    const double l0 = dot(S.u, Q - S.c), l1 = dot(S.v, Q - S.c);
-    if (std::fabs(l0) > S.hw0 + cfg.nav_margin || std::fabs(l1) > S.hw1 + cfg.nav_margin) continue;
-    if (!(s_base + d > 0)) continue;
-    cand.push_back({s_base + d, m});
+// The listing test of one module m from the trajectory point P (path
+// s_base from the current state, direction T, curvature k): the second-order
+// expansion P + d T + d^2 k / 2 meets its plane within the half lengths plus
+// nav_margin at a positive total path.
+void list_test(const Geometry& G, const Cfg& cfg, int m, V3 P, V3 T, V3 k, double s_base,
+               std::vector<Listed>& cand, Stats& st) {
+  const Surface& S = G.s[m];
+  const double half_diag = std::sqrt((S.hw0 + cfg.nav_margin) * (S.hw0 + cfg.nav_margin) +
+                                     (S.hw1 + cfg.nav_margin) * (S.hw1 + cfg.nav_margin));
+  if (norm(S.c - P) > half_diag + kReach) return;
+  ++st.nav_modules;
+  const double a = 0.5 * dot(S.n, k), b = dot(S.n, T), c0 = dot(S.n, P - S.c);
+  if (std::fabs(b) < 1e-3) return;
+  double d = -c0 / b;
+  const double disc = b * b - 4.0 * a * c0;
+  if (disc >= 0) {
+    const double q = -0.5 * (b + std::copysign(std::sqrt(disc), b));
+    if (q != 0) d = c0 / q;
   }
+  const V3 Q = P + d * T + (0.5 * d * d) * k;
+  const double l0 = dot(S.u, Q - S.c), l1 = dot(S.v, Q - S.c);
+  if (std::fabs(l0) > S.hw0 + cfg.nav_margin || std::fabs(l1) > S.hw1 + cfg.nav_margin) return;
+  if (!(s_base + d > 0)) return;
+  cand.push_back({s_base + d, m});
+}
+
+// The listed modules in path order (ties by id), at most 4.
+void list_sorted(std::vector<Listed>& cand, std::vector<int>& list) {
   std::sort(cand.begin(), cand.end(), [](const Listed& x, const Listed& y) {
     return x.s < y.s || (x.s == y.s && x.id < y.id);
   });
@@ -677,9 +678,361 @@ void list_layer(const Geometry& G, const Cfg& cfg, int layer, V3 P, V3 T, V3 k, 
   for (size_t i = 0; i < cand.size() && (int)i < kMaxList; ++i) list.push_back(cand[i].id);
 }
 
+// Modules of `layer` that pass the listing test, in path order (at most 4).
+void list_layer(const Geometry& G, const Cfg& cfg, int layer, V3 P, V3 T, V3 k, double s_base, int exclude,
+                std::vector<int>& list, Stats& st) {
+  std::vector<Listed> cand;
+  for (int m : G.members[layer]) {
+    if (m == exclude) continue;
+    list_test(G, cfg, m, P, T, k, s_base, cand, st);
+  }
+  list_sorted(cand, list);
+}
+
+// ---------------------------------------------------------------------------
+// The learned next-module proposal.  It is not in the paper: it replaces only
+// the module lookup of the navigation (section 2, intersected modules) and
+// keeps that lookup as its fallback.  Readings:
+//   table    per module m, up to three next layers L', each with an anchor A
+//            on L''s envelope, the module pitches (pu, pv) of L' there and a
+//            region of 24 x 8 cells iu in [-12, 11], iv in [-4, 3] around A
+//            holding module ids (an input here, built from the geometry by
+//            the Python side of the oracle);
+//   window   the navigation's own crossing X of L''s envelope, in the layer's
+//            curvilinear coordinates around A - (R dphi, dz) on a barrel of
+//            radius R, (r dphi, dr) on a disk with r the radius of X - divided
+//            by the pitches; the rounded cell (floor(q + 1/2)) is the centre
+//            of an 8 x 4 window iu in [-4, 3], iv in [-2, 1], outputs in
+//            order (iv, iu); no window when |q| >= 1000;
+//   input    X's fractional position in its cell (2), the direction at X in
+//            the layer frame (phi-hat, then z-hat and r-hat on barrels, r-hat
+//            and z-hat on disks), q/p, L' / number of layers;
+//   network  7 -> 64 -> 64 -> 32 with ReLU; in the bfloat16 reading the
+//            weights, the input and both hidden activations are rounded to
+//            bfloat16 (through FP32, nearest, ties to even), sums and biases
+//            stay wide;
+//   use      softmax over the 32 outputs; the top k (probability descending,
+//            index ascending) are summed; at or above min_prob their modules
+//            (empty cells skipped) go through the listing test; when none
+//            passes, or the sum is lower, the geometric lookup runs.
+constexpr int kNIn = 7, kNH = 64, kNOut = 32;
+constexpr int kMaxNext = 3;
+constexpr int kWinU = 8, kWinV = 4, kWU0 = -4, kWV0 = -2;
+constexpr int kRegU = 24, kRegV = 8, kRU0 = -12, kRV0 = -4, kRegCells = kRegU * kRegV;
+
+// Causes by which a decision of the oracle can legitimately differ from one
+// taken in FP32 with FP32 matrix-core sums (reported per seed, never used to
+// decide anything):
+constexpr int kNearConf = 1;  // summed probability within kConfEps of min_prob
+constexpr int kNearBf16 = 2;  // one value near a bfloat16 rounding boundary decides the outcome
+constexpr int kNearEdge = 4;  // crossing near a cell edge, and the neighbouring window decides otherwise
+constexpr int kNearRank = 8;  // k-th and (k+1)-th probabilities within kConfEps (proposed set ambiguous)
+constexpr double kConfEps = 1e-4;
+constexpr double kEdgeEps = 5e-5;  // cell units
+// how far an FP32 evaluation's network input can sit from the FP64 one:
+// cell fractions, direction components, and q/p (relative)
+constexpr double kInEps[kNIn] = {5e-5, 5e-5, 5e-6, 5e-6, 5e-6, 0.0, 1e-7};
+constexpr double kQopRel = 1e-6;
+constexpr double kSumRel = 1e-6;   // hidden pre-activations: relative to the sum of |terms|
+
+double bf16_round(double v) {
+  float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  u &= 0xffff0000u;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+struct Net {
+  double W1[kNH][kNIn], b1[kNH], W2[kNH][kNH], b2[kNH], W3[kNOut][kNH], b3[kNOut];
+};
+
+Net load_net(const float* p, bool round) {
+  Net n;
+  auto w = [&](double v) { return round ? bf16_round(v) : v; };
+  int o = 0;
+  for (int i = 0; i < kNH; ++i)
+    for (int j = 0; j < kNIn; ++j) n.W1[i][j] = w(p[o++]);
+  for (int i = 0; i < kNH; ++i) n.b1[i] = p[o++];
+  for (int i = 0; i < kNH; ++i)
+    for (int j = 0; j < kNH; ++j) n.W2[i][j] = w(p[o++]);
+  for (int i = 0; i < kNH; ++i) n.b2[i] = p[o++];
+  for (int i = 0; i < kNOut; ++i)
+    for (int j = 0; j < kNH; ++j) n.W3[i][j] = w(p[o++]);
+  for (int i = 0; i < kNOut; ++i) n.b3[i] = p[o++];
+  return n;
+}
+
+struct Learned {
+  const int32_t* next;
+  const int32_t* region;
+  const double* anchor;
+  Net net;
+  double min_prob;
+  int topk;
+  bool bf16;
+};
+
+// Activations of one evaluation: pre-activations z, the sums of |terms|, and
+// the (rounded) outputs h of the hidden layers.
+struct Pass {
+  double x[kNIn];
+  double z1[kNH], a1[kNH], h1[kNH];
+  double z2[kNH], a2[kNH], h2[kNH];
+  double z3[kNOut];
+};
+
+double act(const Learned& L, double z) {
+  const double r = z > 0 ? z : 0.0;
+  return L.bf16 ? bf16_round(r) : r;
+}
+
+void layer2(const Learned& L, Pass& e) {
+  for (int i = 0; i < kNH; ++i) {
+    double z = 0, a = 0;
+    for (int j = 0; j < kNH; ++j) {
+      z += L.net.W2[i][j] * e.h1[j];
+      a += std::fabs(L.net.W2[i][j] * e.h1[j]);
+    }
+    e.z2[i] = z + L.net.b2[i];
+    e.a2[i] = a + std::fabs(L.net.b2[i]);
+    e.h2[i] = act(L, e.z2[i]);
+  }
+}
+
+void layer3(const Learned& L, Pass& e) {
+  for (int i = 0; i < kNOut; ++i) {
+    double z = 0;
+    for (int j = 0; j < kNH; ++j) z += L.net.W3[i][j] * e.h2[j];
+    e.z3[i] = z + L.net.b3[i];
+  }
+}
+
+// Forward pass from the (already rounded) input e.x.
+void forward(const Learned& L, Pass& e) {
+  for (int i = 0; i < kNH; ++i) {
+    double z = 0, a = 0;
+    for (int j = 0; j < kNIn; ++j) {
+      z += L.net.W1[i][j] * e.x[j];
+      a += std::fabs(L.net.W1[i][j] * e.x[j]);
+    }
+    e.z1[i] = z + L.net.b1[i];
+    e.a1[i] = a + std::fabs(L.net.b1[i]);
+    e.h1[i] = act(L, e.z1[i]);
+  }
+  layer2(L, e);
+  layer3(L, e);
+}
+
+// Softmax and the top k (probability descending, index ascending).
+struct Ranked {
+  int cls[kNOut];
+  double p[kNOut];  // probabilities in ranked order
+  double conf;
+};
+
+Ranked rank_outputs(const Learned& L, const double* z) {
+  Ranked r;
+  double mx = z[0];
+  for (int i = 1; i < kNOut; ++i) mx = std::max(mx, z[i]);
+  double e[kNOut], sum = 0;
+  for (int i = 0; i < kNOut; ++i) {
+    e[i] = std::exp(z[i] - mx);
+    sum += e[i];
+  }
+  for (int i = 0; i < kNOut; ++i) r.cls[i] = i;
+  std::stable_sort(r.cls, r.cls + kNOut, [&](int a, int b) { return e[a] > e[b]; });
+  for (int i = 0; i < kNOut; ++i) r.p[i] = e[r.cls[i]] / sum;
+  r.conf = 0;
+  for (int i = 0; i < L.topk; ++i) r.conf += r.p[i];
+  return r;
+}
+
+struct Window {
+  int iu, iv;
+  double fu, fv;
+};
+
+double wrap_pm_pi(double a) {  // into [-pi, pi)
+  double w = std::fmod(a + kPi, 2 * kPi);
+  if (w < 0) w += 2 * kPi;
+  return w - kPi;
+}
+
+// The window cell of a crossing X of layer Lr for the anchor row anc
+// (A x, y, z, pitch u, pitch v); false for a non-finite or far crossing.
+bool window_of(const Layer& Lr, const double* anc, V3 X, Window& w, double& qu, double& qv) {
+  const double dphi = wrap_pm_pi(std::atan2(X.y, X.x) - std::atan2(anc[1], anc[0]));
+  const double rX = std::hypot(X.x, X.y);
+  double du, dv;
+  if (Lr.type == 0) {
+    du = dphi * Lr.pos;
+    dv = X.z - anc[2];
+  } else {
+    du = dphi * rX;
+    dv = rX - std::hypot(anc[0], anc[1]);
+  }
+  qu = du / anc[3];
+  qv = dv / anc[4];
+  if (!(std::fabs(qu) < 1000.0 && std::fabs(qv) < 1000.0)) return false;
+  const double cu = std::floor(qu + 0.5), cv = std::floor(qv + 0.5);
+  w.iu = (int)cu;
+  w.iv = (int)cv;
+  w.fu = qu - cu;
+  w.fv = qv - cv;
+  return true;
+}
+
+// The network input at the crossing (unrounded).
+void features(const Layer& Lr, int layer, int n_layers, const Window& w, V3 X, V3 T, double qop, double* x) {
+  const double r = std::hypot(X.x, X.y);
+  const V3 ph{-X.y / r, X.x / r, 0.0}, rh{X.x / r, X.y / r, 0.0};
+  x[0] = w.fu;
+  x[1] = w.fv;
+  x[2] = dot(T, ph);
+  x[3] = Lr.type == 0 ? T.z : dot(T, rh);
+  x[4] = Lr.type == 0 ? dot(T, rh) : T.z;
+  x[5] = qop;
+  x[6] = (double)layer / (double)n_layers;
+}
+
+// Module id of window output c (empty cell or outside the region: -1).
+int window_module(const int32_t* region, const Window& w, int c) {
+  const int cu = w.iu + kWU0 + c % kWinU, cv = w.iv + kWV0 + c / kWinU;
+  if (cu < kRU0 || cu >= kRU0 + kRegU || cv < kRV0 || cv >= kRV0 + kRegV) return -1;
+  return region[(cv - kRV0) * kRegU + (cu - kRU0)];
+}
+
+// The outcome of a proposal: not confident, or the modules of the top k.
+struct Decision {
+  bool confident = false;
+  std::vector<int> mods;  // in rank order, empty cells skipped
+  bool operator==(const Decision& o) const {
+    if (confident != o.confident) return false;
+    if (!confident) return true;
+    std::vector<int> a = mods, b = o.mods;
+    std::sort(a.begin(), a.end());
+    std::sort(b.begin(), b.end());
+    return a == b;
+  }
+};
+
+Decision decide(const Learned& L, const Pass& e, const int32_t* region, const Window& w, Ranked* out = nullptr) {
+  const Ranked r = rank_outputs(L, e.z3);
+  Decision d;
+  d.confident = r.conf >= L.min_prob;
+  if (d.confident)
+    for (int i = 0; i < L.topk; ++i) {
+      const int m = window_module(region, w, r.cls[i]);
+      if (m >= 0) d.mods.push_back(m);
+    }
+  if (out) *out = r;
+  return d;
+}
+
+// Network evaluation at a crossing: the decision, and (near != nullptr) the
+// causes that could make an FP32 evaluation decide otherwise.
+Decision evaluate(const Geometry& G, const Learned& L, int layer, const int32_t* region, const Window& w, V3 X,
+                  V3 T, double qop, int* near, Ranked* ranked) {
+  const Layer& Lr = G.layers[layer];
+  double xr[kNIn];
+  features(Lr, layer, (int)G.layers.size(), w, X, T, qop, xr);
+  Pass e;
+  for (int i = 0; i < kNIn; ++i) e.x[i] = L.bf16 ? bf16_round(xr[i]) : xr[i];
+  forward(L, e);
+  Ranked r;
+  const Decision d = decide(L, e, region, w, &r);
+  if (ranked) *ranked = r;
+  if (!near) return d;
+  if (std::fabs(r.conf - L.min_prob) < kConfEps) *near |= kNearConf;
+  if (d.confident && r.p[L.topk - 1] - r.p[L.topk] < kConfEps) *near |= kNearRank;
+  if (!L.bf16) return d;
+  // one rounding at a time the other way: inputs, then hidden activations
+  for (int i = 0; i < kNIn; ++i) {
+    const double m = i == 5 ? kQopRel * std::fabs(xr[i]) : kInEps[i] * (i == 6 ? std::fabs(xr[i]) : 1.0);
+    for (double v : {xr[i] - m, xr[i] + m}) {
+      const double alt = bf16_round(v);
+      if (alt == e.x[i]) continue;
+      Pass f = e;
+      f.x[i] = alt;
+      forward(L, f);
+      if (!(decide(L, f, region, w) == d)) *near |= kNearBf16;
+    }
+  }
+  for (int j = 0; j < kNH; ++j) {
+    const double m = kSumRel * e.a1[j];
+    for (double v : {e.z1[j] - m, e.z1[j] + m}) {
+      const double alt = act(L, v);
+      if (alt == e.h1[j]) continue;
+      Pass f = e;
+      f.h1[j] = alt;
+      layer2(L, f);
+      layer3(L, f);
+      if (!(decide(L, f, region, w) == d)) *near |= kNearBf16;
+    }
+  }
+  for (int j = 0; j < kNH; ++j) {
+    const double m = kSumRel * e.a2[j];
+    for (double v : {e.z2[j] - m, e.z2[j] + m}) {
+      const double alt = act(L, v);
+      if (alt == e.h2[j]) continue;
+      Pass f = e;
+      f.h2[j] = alt;
+      layer3(L, f);
+      if (!(decide(L, f, region, w) == d)) *near |= kNearBf16;
+    }
+  }
+  return d;
+}
+
+// The proposal for a navigation from module m to layer `layer`, crossing its
+// envelope at X with direction T.  Returns false when the layer has no row
+// in m's table or the crossing has no window (the network does not run).
+bool propose(const Geometry& G, const Learned& L, int m, int layer, V3 X, V3 T, double qop, Decision& d,
+             int* near, Stats& st) {
+  int slot = -1;
+  for (int q = 0; q < kMaxNext; ++q)
+    if (slot < 0 && L.next[m * kMaxNext + q] == layer) slot = q;
+  if (slot < 0) return false;
+  const double* anc = L.anchor + ((size_t)m * kMaxNext + slot) * 5;
+  const int32_t* region = L.region + ((size_t)m * kMaxNext + slot) * kRegCells;
+  Window w;
+  double qu, qv;
+  if (!window_of(G.layers[layer], anc, X, w, qu, qv)) return false;
+  ++st.mlp_rows;
+  d = evaluate(G, L, layer, region, w, X, T, qop, near, nullptr);
+  if (near && (0.5 - std::fabs(w.fu) < kEdgeEps || 0.5 - std::fabs(w.fv) < kEdgeEps)) {
+    // the neighbouring centre cell an FP32 crossing could round to
+    Window w2 = w;
+    if (0.5 - std::fabs(w.fu) < kEdgeEps) {
+      const int s = w.fu > 0 ? 1 : -1;
+      w2.iu += s;
+      w2.fu -= s;
+    }
+    if (0.5 - std::fabs(w.fv) < kEdgeEps) {
+      const int s = w.fv > 0 ? 1 : -1;
+      w2.iv += s;
+      w2.fv -= s;
+    }
+    if (!(evaluate(G, L, layer, region, w2, X, T, qop, nullptr, nullptr) == d)) *near |= kNearEdge;
+  }
+  return true;
+}
+
+// Per-seed record of the learned navigation: causes of possible FP32
+// disagreement, and whether a used proposal listed differently from the
+// geometric lookup (then the seed may differ from the plain search).
+struct LearnedTrace {
+  int near = 0;
+  bool differs = false;
+};
+
 // The next layer and its listed modules.  Returns the layer or -1.
 int navigate(const Geometry& G, const Field& F, const Cfg& cfg, const Free& f, uint64_t mask,
-             double path, std::vector<int>& list, Stats& st) {
+             double path, std::vector<int>& list, Stats& st, const Learned* lrn = nullptr, int surface = -1,
+             LearnedTrace* trace = nullptr) {
   ++st.navigations;
   const Helix H(f, F.at(f.r));
   const double rperp = std::sqrt(f.r.x * f.r.x + f.r.y * f.r.y);
@@ -711,7 +1064,29 @@ int navigate(const Geometry& G, const Field& F, const Cfg& cfg, const Free& f, u
   if (best < 0) return -1;
   V3 P, T;
   H.at(sbest, P, T);
-  list_layer(G, cfg, best, P, T, (kKappa * f.qop) * cross(T, H.B), sbest, -1, list, st);
+  const V3 kk = (kKappa * f.qop) * cross(T, H.B);
+  if (lrn && surface >= 0) {
+    Decision d;
+    if (propose(G, *lrn, surface, best, P, T, f.qop, d, trace ? &trace->near : nullptr, st) && d.confident) {
+      std::vector<Listed> cand;
+      for (int m : d.mods) list_test(G, cfg, m, P, T, kk, sbest, cand, st);
+      list_sorted(cand, list);
+      if (!list.empty()) {
+        ++st.proposals;
+        if (trace) {  // audit against the geometric lookup
+          Stats scratch;
+          std::vector<int> full;
+          list_layer(G, cfg, best, P, T, kk, sbest, -1, full, scratch);
+          if (full != list) {
+            ++st.proposal_misses;
+            trace->differs = true;
+          }
+        }
+        return best;
+      }
+    }
+  }
+  list_layer(G, cfg, best, P, T, kk, sbest, -1, list, st);
   return best;
 }
 
@@ -759,14 +1134,15 @@ struct Accepted {
 // navigate if its list is empty and visit the next listed module.  Surviving
 // candidates go to `outs`, terminated ones to `fin`.
 void step_candidate(const Geometry& G, const Field& F, const Cfg& cfg, const orc_measurements* M,
-                    int event, Cand c, std::vector<Cand>& outs, std::vector<Cand>& fin, Stats& st) {
+                    int event, Cand c, std::vector<Cand>& outs, std::vector<Cand>& fin, Stats& st,
+                    const Learned* lrn, LearnedTrace* trace) {
   ++st.steps;
   if (c.root) {
     c.root = false;
   } else {
     if (c.list.empty()) {
       const Free f = bound_to_free(G.s[c.surface], c.p);
-      const int L = navigate(G, F, cfg, f, c.mask, c.path, c.list, st);
+      const int L = navigate(G, F, cfg, f, c.mask, c.path, c.list, st, lrn, c.surface, trace);
       if (L < 0) {
         fin.push_back(std::move(c));
         return;
@@ -847,7 +1223,8 @@ struct SeedResult {
 };
 
 void find_seed(const Geometry& G, const Field& F, const Cfg& cfg, const orc_measurements* M,
-               const orc_seeds* S, int k, SeedResult& res, Stats& st) {
+               const orc_seeds* S, int k, SeedResult& res, Stats& st, const Learned* lrn = nullptr,
+               LearnedTrace* trace = nullptr) {
   Cand root;
   root.surface = S->surface[k];
   std::memcpy(root.p, S->params + 5 * k, sizeof root.p);
@@ -867,7 +1244,7 @@ void find_seed(const Geometry& G, const Field& F, const Cfg& cfg, const orc_meas
   };
   for (int step = 0; step < cfg.max_steps && !live.empty(); ++step) {
     std::vector<Cand> outs, fin;
-    for (Cand& c : live) step_candidate(G, F, cfg, M, event, std::move(c), outs, fin, st);
+    for (Cand& c : live) step_candidate(G, F, cfg, M, event, std::move(c), outs, fin, st, lrn, trace);
     for (Cand& c : fin) consider(c);
     if (cfg.max_live > 0 && (int)outs.size() > cfg.max_live) {
       std::sort(outs.begin(), outs.end(), better);
@@ -890,30 +1267,14 @@ void to_stats(const Stats& s, orc_stats* o) {
   o->rk_rejects = s.rk_rejects; o->chi2_evals = s.chi2_evals; o->kf_updates = s.kf_updates;
   o->ms_updates = s.ms_updates; o->crossed = s.crossed; o->holes = s.holes;
   o->pruned = s.pruned; o->finished = s.finished;
+  o->mlp_rows = s.mlp_rows; o->proposals = s.proposals; o->proposal_misses = s.proposal_misses;
 }
 
-}  // namespace
-
-extern "C" int orc_field_eval(const orc_field* f, int32_t n, const double* p, double* B, double* G) {
-  if (!f || !p || !B || n < 0) return ORC_ERR_ARG;
-  const Field F = load_field(f);
-  for (int i = 0; i < n; ++i) {
-    V3 b;
-    double g[3][3];
-    F.eval({p[3 * i], p[3 * i + 1], p[3 * i + 2]}, b, g, G != nullptr);
-    B[3 * i] = b.x;
-    B[3 * i + 1] = b.y;
-    B[3 * i + 2] = b.z;
-    if (G)
-      for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) G[9 * i + 3 * a + c] = g[a][c];
-  }
-  return ORC_OK;
-}
-
-extern "C" int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc_measurements* m,
-                            const orc_seeds* s, const orc_config* c, int n_threads, orc_tracks* out,
-                            orc_stats* stats) {
+// Track finding for every seed, plain (lrn == nullptr) or with the learned
+// proposal; traces (learned form only) are per seed.
+int find_all(const orc_geometry* g, const orc_field* f, const orc_measurements* m, const orc_seeds* s,
+             const orc_config* c, const Learned* lrn, int n_threads, orc_tracks* out, orc_stats* stats,
+             int32_t* seed_near, int32_t* seed_differs) {
   if (!g || !f || !m || !s || !c || !out) return ORC_ERR_ARG;
   if (g->n_layers > 64 || m->n_surfaces != g->n_surfaces) return ORC_ERR_ARG;
   const Geometry G = load_geometry(g);
@@ -921,6 +1282,7 @@ extern "C" int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc
   const Cfg cfg = load_cfg(c);
   const int n = s->n_seeds;
   std::vector<SeedResult> res(n);
+  std::vector<LearnedTrace> traces(lrn ? n : 0);
   if (n_threads <= 0) n_threads = (int)std::max(1u, std::thread::hardware_concurrency());
   n_threads = std::max(1, std::min(n_threads, std::max(1, n)));
   std::vector<Stats> tstats(n_threads);
@@ -929,7 +1291,7 @@ extern "C" int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc
     for (;;) {
       const int k = next.fetch_add(1);
       if (k >= n) break;
-      find_seed(G, F, cfg, m, s, k, res[k], tstats[t]);
+      find_seed(G, F, cfg, m, s, k, res[k], tstats[t], lrn, lrn ? &traces[k] : nullptr);
     }
   };
   std::vector<std::thread> pool;
@@ -939,6 +1301,10 @@ extern "C" int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc
   Stats total;
   for (auto& ts : tstats) total.add(ts);
   to_stats(total, stats);
+  for (int k = 0; k < (lrn ? n : 0); ++k) {
+    if (seed_near) seed_near[k] = traces[k].near;
+    if (seed_differs) seed_differs[k] = traces[k].differs ? 1 : 0;
+  }
   // Assemble the output in seed order.
   int nt = 0, nm = 0;
   for (int k = 0; k < n; ++k)
@@ -970,6 +1336,102 @@ extern "C" int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc
       ++it;
     }
   return ORC_OK;
+}
+
+bool load_learned(const orc_geometry* g, const orc_learned* l, Learned& L) {
+  if (!l || !l->next || !l->region || !l->anchor || !l->params) return false;
+  if (l->topk < 1 || l->topk > 3) return false;
+  L.next = l->next;
+  L.region = l->region;
+  L.anchor = l->anchor;
+  L.bf16 = l->bf16 != 0;
+  L.net = load_net(l->params, L.bf16);
+  L.min_prob = l->min_prob;
+  L.topk = l->topk;
+  (void)g;
+  return true;
+}
+
+}  // namespace
+
+extern "C" int orc_field_eval(const orc_field* f, int32_t n, const double* p, double* B, double* G) {
+  if (!f || !p || !B || n < 0) return ORC_ERR_ARG;
+  const Field F = load_field(f);
+  for (int i = 0; i < n; ++i) {
+    V3 b;
+    double g[3][3];
+    F.eval({p[3 * i], p[3 * i + 1], p[3 * i + 2]}, b, g, G != nullptr);
+    B[3 * i] = b.x;
+    B[3 * i + 1] = b.y;
+    B[3 * i + 2] = b.z;
+    if (G)
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) G[9 * i + 3 * a + c] = g[a][c];
+  }
+  return ORC_OK;
+}
+
+extern "C" int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc_measurements* m,
+                            const orc_seeds* s, const orc_config* c, int n_threads, orc_tracks* out,
+                            orc_stats* stats) {
+  return find_all(g, f, m, s, c, nullptr, n_threads, out, stats, nullptr, nullptr);
+}
+
+extern "C" int orc_ckf_find_learned(const orc_geometry* g, const orc_field* f, const orc_measurements* m,
+                                    const orc_seeds* s, const orc_config* c, const orc_learned* l,
+                                    int n_threads, orc_tracks* out, orc_stats* stats, int32_t* seed_near,
+                                    int32_t* seed_differs) {
+  Learned L;
+  if (!load_learned(g, l, L)) return ORC_ERR_ARG;
+  if (f && f->map) return ORC_ERR_ARG;  // the proposal is defined in the uniform field
+  return find_all(g, f, m, s, c, &L, n_threads, out, stats, seed_near, seed_differs);
+}
+
+extern "C" int orc_mlp_forward(const float* params, int32_t bf16, int64_t n, const double* x, double* logits) {
+  if (!params || n < 0 || (n > 0 && (!x || !logits))) return ORC_ERR_ARG;
+  Learned L;
+  L.bf16 = bf16 != 0;
+  L.net = load_net(params, L.bf16);
+  for (int64_t r = 0; r < n; ++r) {
+    Pass e;
+    for (int i = 0; i < kNIn; ++i) e.x[i] = L.bf16 ? bf16_round(x[r * kNIn + i]) : x[r * kNIn + i];
+    forward(L, e);
+    for (int i = 0; i < kNOut; ++i) logits[r * kNOut + i] = e.z3[i];
+  }
+  return ORC_OK;
+}
+
+extern "C" int orc_learned_propose(const orc_geometry* g, const orc_learned* l, int32_t surface, int32_t layer,
+                                   const double* X, const double* T, double qop, int32_t* cell, double* feat,
+                                   double* conf, int32_t* classes, int32_t* modules, int32_t* near) {
+  Learned L;
+  if (!g || !X || !T || !cell || !feat || !conf || !classes || !modules || !near) return ORC_ERR_ARG;
+  if (!load_learned(g, l, L)) return ORC_ERR_ARG;
+  if (surface < 0 || surface >= g->n_surfaces || layer < 0 || layer >= g->n_layers) return ORC_ERR_ARG;
+  const Geometry G = load_geometry(g);
+  int slot = -1;
+  for (int q = 0; q < kMaxNext; ++q)
+    if (slot < 0 && L.next[surface * kMaxNext + q] == layer) slot = q;
+  if (slot < 0) return -1;
+  const double* anc = L.anchor + ((size_t)surface * kMaxNext + slot) * 5;
+  const int32_t* region = L.region + ((size_t)surface * kMaxNext + slot) * kRegCells;
+  Window w;
+  double qu, qv;
+  const V3 Xv{X[0], X[1], X[2]}, Tv{T[0], T[1], T[2]};
+  if (!window_of(G.layers[layer], anc, Xv, w, qu, qv)) return -1;
+  cell[0] = w.iu;
+  cell[1] = w.iv;
+  features(G.layers[layer], layer, (int)G.layers.size(), w, Xv, Tv, qop, feat);
+  Ranked r;
+  int nr = 0;
+  const Decision d = evaluate(G, L, layer, region, w, Xv, Tv, qop, &nr, &r);
+  *near = nr;
+  *conf = r.conf;
+  for (int i = 0; i < 3; ++i) {
+    classes[i] = r.cls[i];
+    modules[i] = i < L.topk ? window_module(region, w, r.cls[i]) : -1;
+  }
+  return d.confident ? 1 : 0;
 }
 
 extern "C" int orc_propagate(const orc_geometry* g, const orc_field* f, const orc_config* c, int32_t src,

@@ -121,7 +121,36 @@ typedef struct orc_stats {
   int64_t holes;
   int64_t pruned;
   int64_t finished;
+  int64_t mlp_rows;         /* learned form: navigations that evaluated the network */
+  int64_t proposals;        /* ... whose proposal was used (confident, non-empty listing) */
+  int64_t proposal_misses;  /* ... used proposals listing differently from the geometric lookup */
 } orc_stats;
+
+/* The learned next-module proposal (not in the paper: it replaces only the
+ * module lookup of the navigation and keeps that lookup as its fallback).
+ * The neighbour table is an input: for module m, next[m][q] (q < 3, -1 pads)
+ * is a next layer, anchor[m][q] = (A x, y, z, pitch u, pitch v) its anchor
+ * point on that layer's envelope and pitches, region[m][q][iv*24 + iu] the
+ * module id in cell (iu - 12, iv - 4) around the anchor (-1 empty).  The
+ * network parameters are W1 [64][7], b1, W2 [64][64], b2, W3 [32][64], b3
+ * (6752 FP32 values).  bf16 != 0 rounds weights, inputs and hidden
+ * activations to bfloat16 where a bf16 matrix-core evaluation does. */
+typedef struct orc_learned {
+  const int32_t* next;      /* [n_surfaces][3] */
+  const int32_t* region;    /* [n_surfaces][3][192] */
+  const double* anchor;     /* [n_surfaces][3][5] */
+  const float* params;      /* [6752] */
+  double min_prob;          /* proposal used when its top-k probabilities sum to at least this */
+  int32_t topk;             /* 1..3 modules proposed */
+  int32_t bf16;
+} orc_learned;
+
+/* Causes (bits of seed_near) by which an FP32 evaluation of the proposal can
+ * decide otherwise than this FP64 one. */
+#define ORC_NEAR_CONF 1     /* summed probability within 1e-4 of the threshold */
+#define ORC_NEAR_BF16 2     /* one value near a bfloat16 rounding boundary decides the outcome */
+#define ORC_NEAR_EDGE 4     /* crossing within 5e-5 of a cell edge, the neighbouring window decides otherwise */
+#define ORC_NEAR_RANK 8     /* k-th and (k+1)-th probabilities within 1e-4 */
 
 /* Status codes. */
 #define ORC_OK 0
@@ -138,6 +167,29 @@ int orc_field_eval(const orc_field* f, int32_t n, const double* p, double* B, do
 int orc_ckf_find(const orc_geometry* g, const orc_field* f, const orc_measurements* m,
                  const orc_seeds* s, const orc_config* cfg, int n_threads,
                  orc_tracks* out, orc_stats* stats);
+
+/* Track finding with the learned proposal (uniform field only).  seed_near
+ * (nullable, [n_seeds]) receives the OR of the ORC_NEAR_* causes met by any
+ * network evaluation of the seed's candidates; seed_differs (nullable) 1 for
+ * a seed one of whose used proposals listed differently from the geometric
+ * lookup (every other seed finds exactly the plain search's tracks). */
+int orc_ckf_find_learned(const orc_geometry* g, const orc_field* f, const orc_measurements* m,
+                         const orc_seeds* s, const orc_config* cfg, const orc_learned* l, int n_threads,
+                         orc_tracks* out, orc_stats* stats, int32_t* seed_near, int32_t* seed_differs);
+
+/* Network logits [n][32] of inputs x [n][7]. */
+int orc_mlp_forward(const float* params, int32_t bf16, int64_t n, const double* x, double* logits);
+
+/* The proposal of one navigation from `surface` to `layer`, whose local
+ * helix crosses the layer's envelope at X with direction T: returns -1 when
+ * the network does not run (no table row, or no window), else 1 when the
+ * proposal is used (confident) and 0 when not.  cell [2] the window's centre
+ * cell, feat [7] the unrounded input, conf the summed top-k probability,
+ * classes [3] the three most probable outputs, modules [3] the modules of
+ * the top k (-1 for an empty cell or beyond k), near the ORC_NEAR_* causes. */
+int orc_learned_propose(const orc_geometry* g, const orc_learned* l, int32_t surface, int32_t layer,
+                        const double* X, const double* T, double qop, int32_t* cell, double* feat,
+                        double* conf, int32_t* classes, int32_t* modules, int32_t* near);
 
 /* Propagate bound parameters and covariance from module src to the plane of
  * module dst (no material, no bounds test).  jac (5x5 row-major, may be

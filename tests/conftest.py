@@ -50,3 +50,17 @@ def double_matched(ev, meas_ids, seed_particle):
     maj = vals[np.argmax(cnt)]
     N = cnt.max()
     return bool(N > len(meas_ids) / 2 and N > ev.particle_nhits[maj] / 2 and maj == seed_particle)
+
+
+@pytest.fixture(scope="session")
+def dense_table(det_dense):
+    """The oracle's neighbour table of the whole barrel + endcap detector."""
+    from oracle import learned as OL
+    return OL.neighbour_table(det_dense.as_arrays())
+
+
+@pytest.fixture(scope="session")
+def golden_model():
+    """Network parameters trained by the oracle alone on its own tracks
+    (tests/golden/make_learned_model.py)."""
+    return np.loadtxt(os.path.join(ROOT, "tests", "golden", "learned_model.txt"), dtype=np.float32)
