@@ -12,7 +12,7 @@ them with the multiplicities and distributions of the named configurations:
 
 Truth trajectories are exact helices in a uniform axial field (closed-form
 crossings with the barrel planes, the disk planes and the layer envelopes),
-kinked at every crossed module by a Gaussian multiple-scattering kick of the
+or integrated numerically through a given field (synth.fieldsim), kinked at every crossed module by a Gaussian multiple-scattering kick of the
 Highland width when the module has material.  Each crossing yields a hit with
 probability ``eff``, smeared by the module's resolution; each module also
 carries one uniform noise hit with probability ``noise``.  Seeds are the true
@@ -375,7 +375,11 @@ def _pack_diag(sig):
 
 
 def make_event(det: Detector, rng_seed: int, kind="pileup", mu=200.0, bz=2.0,
-               eff=0.99, noise=0.01, material=None, smear_seeds=True) -> Event:
+               eff=0.99, noise=0.01, material=None, smear_seeds=True, field=None) -> Event:
+    """One event.  The truth follows closed-form helices in the uniform axial
+    field bz, or, with ``field`` (a function of points [M, 3] in mm giving
+    the field [M, 3] in tesla, e.g. synth.field.solenoid_field), is
+    integrated numerically through that field (synth.fieldsim)."""
     rng = np.random.Generator(np.random.PCG64(rng_seed))
     if kind == "tiny":
         vtx, pt, eta, phi, q = tiny_particles(rng)
@@ -385,7 +389,13 @@ def make_event(det: Detector, rng_seed: int, kind="pileup", mu=200.0, bz=2.0,
         material = bool(np.any(det.thick > 0))
     theta = 2.0 * np.arctan(np.exp(-eta))
     mom = np.stack([pt * np.cos(phi), pt * np.sin(phi), pt / np.tan(theta)], -1)
-    tr = simulate(det, vtx, mom, q, bz, rng, material=material)
+    if field is None:
+        tr = simulate(det, vtx, mom, q, bz, rng, material=material)
+    else:
+        from .fieldsim import simulate_field
+        cat = simulate_field(det, vtx, mom, q, field, rng, material=material)
+        o = np.lexsort((cat["order"], cat["particle"]))
+        tr = Truth(**{k: v[o] for k, v in cat.items()})
     S = det.n_surfaces
     sig = det.sigma().astype(np.float64)
     # signal hits
