@@ -47,50 +47,91 @@ MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 
 # HBM bytes per launch of the track-finding kernel from the FETCH_SIZE and
 # WRITE_SIZE counters (scaled by a plain copy's factors 2.0 and 1.0), keyed
 # by (form, grid, seeds per group, waves per SIMD): the pools make the
-# traffic depend on the launch shape.  Source: profiles/k_ckf_mu200x64_hbm_traffic.md;
-# an entry is dropped when its kernel changes.
-MEASURED_TRAFFIC = {("plain", 6144, 48, 3): 29.67e9, ("plain", 3072, 48, 3): 29.67e9,
-                    ("learned", 2048, 48, 2): 24.94e9, ("learned", 4096, 48, 2): 24.94e9}
+# traffic depend on the launch shape.  Each value carries the hash of the
+# library sources it was measured on (code_hash()); roofline_of reports it
+# only while the sources hash the same, so a changed kernel prints null
+# until it is profiled again.  Source: profiles/k_ckf_mu200x64_hbm_traffic.md.
+MEASURED_TRAFFIC = {}
 # SIMT efficiency of the same launches, SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU): the share of
-# lanes a VALU instruction finds active.  Source: profiles/k_ckf_mu200x64_sq_counters.md.
-MEASURED_SIMT = {("plain", 6144, 48, 3): 0.243, ("plain", 3072, 48, 3): 0.243,
-                 ("learned", 2048, 48, 2): 0.312, ("learned", 4096, 48, 2): 0.312}
+# lanes a VALU instruction finds active, same keys and hashes.  Source: profiles/k_ckf_mu200x64_sq_counters.md.
+MEASURED_SIMT = {}
 # HBM bytes per k_fit launch on the 64 x mu=200 batch's plain-search tracks
-# (560,806 tracks, 4,620,871 measurements), same counters and factors.
-# Source: profiles/k_fit_mu200x64.md.
-FIT_TRAFFIC = {(560806, 4620871): {"rts": 8.749e9, "two_filter": 6.271e9}}
-# HBM bytes per call of ckf_cluster (cells, clusters), ckf_seed (spacepoints,
-# seeds) and ckf_resolve (tracks, measurements) on the same batch, summed over
-# the call's kernels, same counters and factors.
-# Source: profiles/k_cl_k_sd_k_res_mu200x64_hbm_traffic.md.
-CLUSTER_TRAFFIC = {(9783486, 5260424): 1.252e9}
-SEED_TRAFFIC = {(5260424, 2312126): 4.462e9}
-RESOLVE_TRAFFIC = {(560806, 4620871): 1.494e9}
+# (per smoother), and per call of ckf_cluster, ckf_seed and ckf_resolve on
+# the same batch, summed over the call's kernels, same counters and
+# factors, keyed by the sizes of the call and carrying the source hash like
+# the values above.  Sources: profiles/k_fit_mu200x64.md,
+# profiles/k_cl_k_sd_k_res_mu200x64_hbm_traffic.md.
+FIT_TRAFFIC = {}      # (tracks, measurements, smoother) -> (bytes, hash)
+CLUSTER_TRAFFIC = {}  # (cells, clusters) -> (bytes, hash)
+SEED_TRAFFIC = {}     # (spacepoints, seeds) -> (bytes, hash)
+RESOLVE_TRAFFIC = {}  # (tracks, measurements) -> (bytes, hash)
+# Learned proposal: the configured threshold, the candidates the bench
+# chooses from on held-out events, and the equal-efficiency allowance
+# (absolute finding efficiency) with the margin the choice keeps below it.
+CFG_MIN_PROB = 0.95
+THRESHOLDS = (0.95, 0.97, 0.98, 0.99, 0.995)
+EFF_ALLOWANCE = 0.005
+EFF_MARGIN = 0.001
 PEAK_FP32 = 157.3e12  # MI355X vector FP32, FLOP/s
 PEAK_FP64 = 78.6e12   # MI355X vector FP64, FLOP/s
 PEAK_BF16 = 2.5e15    # MI355X dense bf16 MFMA, FLOP/s
 
 
+def code_hash():
+    """First 16 hex digits of the SHA-256 over the library's HIP and C++
+    sources (file names and contents, in name order)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2505_22822_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _measured(table, key):
+    """A measured counter value of `table` for `key`, or None when none was
+    measured for it or the sources changed since."""
+    v = table.get(key)
+    if v is None or v[1] != code_hash():
+        return None
+    return v[0]
+
+
 def _gen(args):
     from synth import barrel_endcap, make_event
-    seed, mu, cells = args
+    seed, mu, cells = args[:3]
+    field_map = len(args) > 3 and args[3]
     det = barrel_endcap()
-    ev = make_event(det, seed, mu=mu)
+    if field_map:
+        from synth.field import solenoid_field
+        ev = make_event(det, seed, mu=mu, field=solenoid_field)
+    else:
+        ev = make_event(det, seed, mu=mu)
     if not cells:
         return ev
     from synth.cells import make_cells
     return ev, make_cells(det, ev, seed + 100000)
 
 
-def make_events(seeds, mu, workers, cells=False):
+def make_events(seeds, mu, workers, cells=False, field_map=False):
     """Events (and, with cells=True, their detector cells) generated in
-    parallel; returns (events, concatenated batch[, concatenated cells])."""
+    parallel; mu is one pileup for all events or one per event; field_map:
+    truth integrated through the solenoid field instead of helices in 2 T.
+    Returns (events, concatenated batch[, concatenated cells])."""
     from synth import concat_events
-    jobs = [(s, mu, cells) for s in seeds]
+    mus = np.broadcast_to(np.asarray(mu, dtype=float), (len(seeds),))
+    jobs = [(s, float(m), cells, field_map) for s, m in zip(seeds, mus)]
     if workers > 1:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers) as pool:
+        # closed and joined, not terminated: the workers end on their own
+        pool = mp.get_context("fork").Pool(workers)
+        try:
             out = pool.map(_gen, jobs)
+        finally:
+            pool.close()
+            pool.join()
     else:
         out = [_gen(j) for j in jobs]
     if not cells:
@@ -98,6 +139,16 @@ def make_events(seeds, mu, workers, cells=False):
     from synth.cells import concat_cells
     evs = [e for e, _ in out]
     return evs, concat_events(evs), concat_cells([c for _, c in out])
+
+
+# The uneven batch: 64 events whose pileup is drawn uniformly in [20, 200]
+# (about 1k to 10k seeds each), found in one persistent launch.
+UNEVEN_SEEDS = [6100 + i for i in range(64)]
+
+
+def uneven_mus(n, seed=6100):
+    """Pileup of each event of the uneven batch: U[20, 200] from PCG64(seed)."""
+    return np.random.Generator(np.random.PCG64(seed)).uniform(20.0, 200.0, n)
 
 
 def efficiency(ev, r):
@@ -132,6 +183,21 @@ def efficiency(ev, r):
     found = np.zeros(P - 1, bool)
     found[maj[matched]] = True
     return float((found & den).sum() / max(1, den.sum()))
+
+
+def cpu_single_thread(batch, n_seeds):
+    """The oracle on one thread: the first n_seeds seeds of the batch."""
+    import oracle
+    from synth import barrel_endcap
+    det = barrel_endcap()
+    inp = oracle.Inputs(det.as_arrays(), (0, 0, 2.0))
+    sel = np.arange(min(n_seeds, batch.n_seeds))
+    inp.set_event(batch, seeds=sel)
+    t0 = time.perf_counter()
+    r = oracle.ckf_find(inp, n_threads=1)
+    dt = time.perf_counter() - t0
+    return dict(value=r["n_tracks"] / dt, unit="tracks/s", cores=1,
+                sample=f"first {len(sel)} seeds of the batch ({r['n_tracks']} tracks) in {dt:.2f} s")
 
 
 def cpu_baseline(batch, n_events):
@@ -192,6 +258,56 @@ def measure(ckf, geo, fld, b, shape, steps, warmup, stream, model=None, audit=Fa
                 ms_per_step=ms_per_step, tracks_per_s=r["n_tracks"] / (ms_per_step * 1e-3))
 
 
+def _find_once(ckf, geo, fld, b, shape, model=None, cfg=None):
+    """One uninstrumented ckf_find; the result arrays."""
+    f = ckf.Finder(geo, fld, b, cfg or ckf.config(),
+                   ckf.launch(shape["grid"], shape["seeds_per_group"], 0, None, shape["waves_per_simd"]),
+                   counters=False, model=model)
+    f.enqueue()
+    return f.result()
+
+
+def measure_end_to_end(ckf, geo, fld, batch, shape, stream, reps):
+    """The whole batch from host memory: the inputs (measurement offsets,
+    loc, var; seed events, surfaces, parameters, covariances) copied from
+    pinned host buffers to the device, the captured ckf_find, the outputs
+    (track CSR and per-track arrays) copied back to pinned host buffers;
+    wall time of the sequence on one stream, mean over reps."""
+    import torch
+    host = ckf.Batch.from_event(batch, device="cpu")
+    names = ("offsets", "loc", "var", "seed_event", "seed_surface", "seed_params", "seed_cov")
+    pinned = {k: getattr(host, k).pin_memory() for k in names}
+    dev = ckf.Batch.from_event(batch)
+    finder = ckf.Finder(geo, fld, dev, ckf.config(),
+                        ckf.launch(shape["grid"], shape["seeds_per_group"], 0, None, shape["waves_per_simd"]),
+                        counters=False)
+    finder.capture(stream)
+    outs = ("n_tracks", "offsets", "meas", "params", "cov", "chi2", "ndf", "holes", "seed", "event", "last_surface",
+            "status")
+    back = {k: torch.empty_like(finder.out[k], device="cpu").pin_memory() for k in outs}
+    bytes_in = sum(t.numel() * t.element_size() for t in pinned.values())
+    bytes_out = sum(t.numel() * t.element_size() for t in back.values())
+    times = []
+    for i in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for k in names:
+                getattr(dev, k).copy_(pinned[k], non_blocking=True)
+            finder.launch_graph(stream)
+            for k in outs:
+                back[k].copy_(finder.out[k], non_blocking=True)
+        stream.synchronize()
+        if i > 0:
+            times.append((time.perf_counter() - t0) * 1e3)
+    nt = int(back["n_tracks"][0])
+    ms = float(np.mean(times))
+    return dict(ms=round(ms, 4), tracks=nt, tracks_per_s=round(nt / (ms * 1e-3), 1), bytes_in=int(bytes_in),
+                bytes_out=int(bytes_out), reps=reps,
+                note="wall time: pinned host inputs -> device, the captured ckf_find, outputs -> pinned host "
+                     "(output arrays at their full capacity)")
+
+
 # Kalman-filter fit, per measurement (FP32 flop, FP64 flop): the forward
 # filter's leg (bound->free, free->bound Jacobian; J C J^T), chi2, update and
 # scattering; the RTS step (F C_k|k, Cholesky of C_k+1|k and its solve for
@@ -235,7 +351,7 @@ def measure_fit(ckf, geo, fld, b, shape, stream, reps, trials_per_leg):
             f32 = n_m * (FIT_FORWARD[0] + FIT_TWO[0] + 2 * rk)
             f64 = n_m * (FIT_FORWARD[1] + FIT_TWO[1])
         frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64) / (ms * 1e-3)
-        traffic = FIT_TRAFFIC.get((n_t, n_m), {}).get(name)
+        traffic = _measured(FIT_TRAFFIC, (n_t, n_m, name))
         out[name] = dict(tracks_per_s=round(n_t / (ms * 1e-3), 1), kernel_ms=round(ms, 4),
                          fitted=round(float(np.mean(g["ok"] == 1)), 6),
                          roofline=dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3),
@@ -310,7 +426,7 @@ def measure_resolve(ckf, finder, ev, stream, reps=3):
     return dict(ms=round(float(np.mean(times[1:])), 4), rounds=rounds, tracks_in=int(r["n_tracks"]),
                 removed=int(np.sum(keep[:r["n_tracks"]] == 0)), before=before, after=after,
                 efficiency_before=round(efficiency(ev, r), 5), efficiency_after=round(efficiency(ev, kept_tracks(r, keep)), 5),
-                traffic=RESOLVE_TRAFFIC.get((int(r["n_tracks"]), int(r["offsets"][r["n_tracks"]]))),
+                traffic=_measured(RESOLVE_TRAFFIC, (int(r["n_tracks"]), int(r["offsets"][r["n_tracks"]]))),
                 note="wall time of the synchronous call (one stream synchronisation per round); traffic: HBM bytes "
                      "of its kernels (counters)")
 
@@ -343,7 +459,7 @@ def measure_cluster(ckf, geo, det, cells, stream, reps):
                 cells_per_s=round(cells.n_cells / (ms * 1e-3), 1),
                 roofline=dict(bound="hbm", achieved=round(algo / (ms * 1e-3) / 1e9, 1), peak=8000.0, unit="GB/s",
                               frac=round(algo / (ms * 1e-3) / 8e12, 5),
-                              traffic=CLUSTER_TRAFFIC.get((int(cells.n_cells), int(r["n_meas"]))), kernel="k_cl_*",
+                              traffic=_measured(CLUSTER_TRAFFIC, (int(cells.n_cells), int(r["n_meas"]))), kernel="k_cl_*",
                               algorithmic_bytes=int(algo)))
 
 
@@ -407,7 +523,7 @@ def measure_chain(ckf, geo, fld, det, cells, evs, cl, cl_ms, stream, reps):
                 tracks=res["n_tracks"], find_ms=round(find_ms, 4), chain_ms=round(chain_ms, 4),
                 chain_tracks_per_s=round(res["n_tracks"] / (chain_ms * 1e-3), 1), central_particles=int(len(cen)),
                 central_found=round(eff, 5), find_status_flags=flags,
-                seed_traffic=SEED_TRAFFIC.get((int(m), int(n))),
+                seed_traffic=_measured(SEED_TRAFFIC, (int(m), int(n))),
                 note="device times of one ckf_cluster, one ckf_seed and one ckf_find (kernel timer) on the batch; "
                      "seed_traffic: HBM bytes of one ckf_seed call (counters)")
 
@@ -421,7 +537,8 @@ def roofline_of(m, form, shape):
     frac = (f32 / PEAK_FP32 + f64 / PEAK_FP64 + mf / PEAK_BF16) / t
     key = (form, shape["grid"], shape["seeds_per_group"], shape["waves_per_simd"])
     return dict(bound="alu", achieved=round(frac * PEAK_FP32 / 1e12, 3), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                frac=round(frac, 5), traffic=MEASURED_TRAFFIC.get(key), simt_efficiency=MEASURED_SIMT.get(key),
+                frac=round(frac, 5), traffic=_measured(MEASURED_TRAFFIC, key),
+                simt_efficiency=_measured(MEASURED_SIMT, key), code=code_hash(),
                 kernel="k_ckf", kernel_ms=round(m["kernel_ms"], 4), fp32_flop=f32, fp64_flop=f64, bf16_mfma_flop=mf,
                 note="achieved = FP32-equivalent rate (F32 + 2*F64 + F_bf16/15.9)/t against the FP32 vector peak")
 
@@ -455,11 +572,20 @@ def main():
     ap.add_argument("--waves", type=int, default=0, help="kernel register variant: waves per SIMD (1, 2 or 3; 0: the autotuner picks)")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--no-learned", action="store_true", help="plain form only")
-    ap.add_argument("--train-events", type=int, default=26)
+    ap.add_argument("--train-events", type=int, default=34,
+                    help="mu=200 training events (seeds 5000 + i) whose plain-search tracks give the pairs "
+                         "(34: about 2M pairs)")
+    ap.add_argument("--heldout-events", type=int, default=8,
+                    help="held-out mu=200 events (seeds 5500 + i) on which the threshold is chosen")
     ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--min-prob", type=float, default=0.98,
-                    help="learned form: summed top-3 probability above which the proposal is used (0.98: the "
-                         "threshold at which its efficiency stays within 0.5 %% of the plain form's)")
+    ap.add_argument("--min-prob", type=float, default=0.0,
+                    help="learned form: summed top-3 probability above which the proposal is used (0: the "
+                         "smallest of the candidates whose held-out efficiency stays within the allowance)")
+    ap.add_argument("--map-events", type=int, default=16,
+                    help="mu=200 events with truth integrated through the solenoid map, found in the map "
+                         "(0: skip)")
+    ap.add_argument("--single-thread-seeds", type=int, default=4000,
+                    help="seeds of the oracle's single-thread run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -480,10 +606,29 @@ def main():
     say = lambda msg: print(msg, file=sys.stderr, flush=True)
 
     t0 = time.time()
+    # every event set is generated before the GPU is touched (forked workers)
     evs, batch, cells = make_events([6000 + i for i in range(args.events)], args.mu, args.workers, cells=True)
     say(f"# generated {batch.n_events} events, {batch.n_seeds} seeds, {batch.n_meas} measurements, "
-        f"{cells.n_cells} cells "
-        f"in {time.time() - t0:.1f} s")
+        f"{cells.n_cells} cells in {time.time() - t0:.1f} s")
+    t0 = time.time()
+    umus = uneven_mus(len(UNEVEN_SEEDS))
+    uevs, ubatch = make_events(UNEVEN_SEEDS, umus, args.workers)
+    useeds = np.bincount(ubatch.seed_event, minlength=ubatch.n_events)
+    say(f"# uneven batch: {ubatch.n_events} events, mu {umus.min():.0f}..{umus.max():.0f}, seeds per event "
+        f"{useeds.min()}..{useeds.max()} ({ubatch.n_seeds} in all), generated in {time.time() - t0:.1f} s")
+    mevs = mbatch = None
+    if args.map_events > 0:
+        t0 = time.time()
+        mevs, mbatch = make_events([6200 + i for i in range(args.map_events)], args.mu, args.workers, field_map=True)
+        say(f"# field-map batch: {mbatch.n_events} events with truth integrated through the solenoid map, "
+            f"{mbatch.n_seeds} seeds, generated in {time.time() - t0:.1f} s")
+    tevs = hevs = None
+    if not args.no_learned:
+        t0 = time.time()
+        _, tbatch = make_events([5000 + i for i in range(args.train_events)], args.mu, args.workers)
+        hevs, hbatch = make_events([5500 + i for i in range(args.heldout_events)], args.mu, args.workers)
+        say(f"# training events: {tbatch.n_events} ({tbatch.n_seeds} seeds); held-out events for the threshold: "
+            f"{hbatch.n_events}; generated in {time.time() - t0:.1f} s")
 
     import torch
     import paper_2505_22822_amd as ckf
@@ -515,6 +660,38 @@ def main():
         f"efficiency {eff_plain:.4f}")
     cyc_plain = {k: plain["counters"].pop(k) for k in CYCLE_KEYS}
     say(phase_line({**plain["counters"], **cyc_plain}, "plain"))
+    e2e = measure_end_to_end(ckf, geo, fld, batch, shape_plain, stream, max(3, args.steps // 4))
+    say(f"# end to end (host -> device inputs, ckf_find, device -> host outputs): {e2e['ms']:.2f} ms per batch, "
+        f"{e2e['tracks_per_s'] / 1e6:.2f} M tracks/s (inputs {e2e['bytes_in'] / 1e6:.0f} MB, outputs "
+        f"{e2e['bytes_out'] / 1e6:.0f} MB)")
+
+    ub = ckf.Batch.from_event(ubatch)
+    um = measure(ckf, geo, fld, ub, shape_plain, args.steps, args.warmup, stream)
+    uneven = dict(events=ubatch.n_events, mu_min=round(float(umus.min()), 2), mu_max=round(float(umus.max()), 2),
+                  seeds=ubatch.n_seeds, seeds_per_event_min=int(useeds.min()), seeds_per_event_max=int(useeds.max()),
+                  measurements=ubatch.n_meas, tracks=um["result"]["n_tracks"],
+                  plain=dict(tracks_per_s=round(um["tracks_per_s"], 1), ms_per_step=round(um["ms_per_step"], 4),
+                             kernel_ms=round(um["kernel_ms"], 4), efficiency=round(efficiency(ubatch, um["result"]), 5),
+                             launch=shape_plain))
+    del um["counters"]
+    say(f"# uneven batch, plain: {uneven['plain']['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel "
+        f"{uneven['plain']['kernel_ms']:.3f} ms, efficiency {uneven['plain']['efficiency']:.4f}")
+
+    field_map = None
+    if mbatch is not None:
+        from synth.field import solenoid_map
+        fmap = ckf.FieldMap(solenoid_map())
+        mb = ckf.Batch.from_event(mbatch)
+        mshape = dict(grid=n_cu * 4 * 2, seeds_per_group=48, waves_per_simd=2)
+        mm = measure(ckf, geo, fmap, mb, mshape, max(3, args.steps // 4), args.warmup, stream)
+        field_map = dict(events=mbatch.n_events, seeds=mbatch.n_seeds, measurements=mbatch.n_meas,
+                         tracks=mm["result"]["n_tracks"], truth="integrated through the solenoid map (FP64 RK4)",
+                         tracks_per_s=round(mm["tracks_per_s"], 1), ms_per_step=round(mm["ms_per_step"], 4),
+                         kernel_ms=round(mm["kernel_ms"], 4), efficiency=round(efficiency(mbatch, mm["result"]), 5),
+                         launch=mshape, roofline=roofline_of(mm, "map", mshape))
+        say(f"# field map, plain: {field_map['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel "
+            f"{field_map['kernel_ms']:.3f} ms, efficiency {field_map['efficiency']:.4f} on {mbatch.n_events} events")
+        del mb, mm, fmap
 
     c0 = plain["counters"]
     fit = measure_fit(ckf, geo, fld, b, shape_plain, stream, max(3, args.steps // 4),
@@ -542,38 +719,77 @@ def main():
     head = plain
     if not args.no_learned:
         from paper_2505_22822_amd import learned
-        t0 = time.time()
-        tevs, tbatch = make_events([5000 + i for i in range(args.train_events)], args.mu, args.workers)
         tb = ckf.Batch.from_event(tbatch)
-        del tevs
         t1 = time.time()
         params, log, info = learned.train_from_batches(geo, fld, [tb], epochs=args.epochs, batch=4096, lr=1e-3,
                                                        seed=0, stream=stream)
         torch.cuda.synchronize()
         t2 = time.time()
-        say(f"# training: {info['pairs']} pairs ({info['dropped']} dropped) from {tbatch.n_events} events "
-            f"(generated in {t1 - t0:.1f} s); {log.steps} Adam steps in {t2 - t1:.1f} s; loss {log.loss[0]:.3f} -> "
+        say(f"# training: {info['pairs']} pairs ({info['dropped']} dropped) from {tbatch.n_events} events; "
+            f"{log.steps} Adam steps in {t2 - t1:.1f} s; loss {log.loss[0]:.3f} -> "
             f"{log.loss[-1]:.3f}; validation top-1 {log.val_top1:.3f}, top-3 {log.val_top3:.3f}, "
             f"confident {log.val_confident:.3f} (of which right {log.val_confident_right:.4f})")
         del tb, tbatch
         model = ckf.Model(params)
         shape_learned = pick(model)
         say(f"# learned launch shape {shape_learned}")
-        lm = measure(ckf, geo, fld, b, shape_learned, args.steps, args.warmup, stream, model=model, audit=True,
-                     cfg=ckf.config(learned_min_prob=args.min_prob))
-        eff_learned = efficiency(batch, lm["result"])
+        # the threshold: the smallest candidate whose efficiency on the held-out events stays within the
+        # allowance of the plain form's there (chosen before the evaluation batch is looked at)
+        hb = ckf.Batch.from_event(hbatch)
+        h_plain = efficiency(hbatch, _find_once(ckf, geo, fld, hb, shape_plain))
+        choice = []
+        chosen = None
+        for th in THRESHOLDS:
+            e = efficiency(hbatch, _find_once(ckf, geo, fld, hb, shape_learned, model,
+                                              ckf.config(learned_min_prob=th)))
+            choice.append(dict(min_prob=th, efficiency=round(e, 5)))
+            if chosen is None and e >= h_plain - EFF_ALLOWANCE + EFF_MARGIN:
+                chosen = th
+        if chosen is None:
+            chosen = THRESHOLDS[-1]
+        if args.min_prob > 0:
+            chosen = args.min_prob
+        say(f"# threshold on {hbatch.n_events} held-out events: plain efficiency {h_plain:.4f}; "
+            + ", ".join(f"{c['min_prob']}: {c['efficiency']:.4f}" for c in choice) + f"; chosen {chosen}")
+        del hb, hbatch
+
+        def learned_run(th, audit):
+            lm = measure(ckf, geo, fld, b, shape_learned, args.steps, args.warmup, stream, model=model,
+                         audit=audit, cfg=ckf.config(learned_min_prob=th))
+            eff = efficiency(batch, lm["result"])
+            c = lm["counters"]
+            say(f"# learned at {th}: {lm['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel {lm['kernel_ms']:.3f} ms, "
+                f"efficiency {eff:.4f}; network rows {c['mlp_rows']} of {c['navigations']} navigations, "
+                f"proposals used {c['proposals']}, listings differing from the geometric one {c['proposal_misses']}, "
+                f"seeds affected {int(lm['seed_flags'].sum()) if audit else -1}")
+            return lm, eff
+
+        lm, eff_learned = learned_run(chosen, True)
         c = lm["counters"]
-        say(f"# learned: {lm['tracks_per_s'] / 1e6:.2f} M tracks/s, kernel {lm['kernel_ms']:.3f} ms, "
-            f"efficiency {eff_learned:.4f}; network rows {c['mlp_rows']} of {c['navigations']} navigations, "
-            f"proposals used {c['proposals']}, listings differing from the geometric one {c['proposal_misses']}, "
-            f"seeds affected {int(lm['seed_flags'].sum())}")
         cyc_learned = {k: lm["counters"].pop(k) for k in CYCLE_KEYS}
         say(phase_line({**lm["counters"], **cyc_learned}, "learned"))
+        at_cfg = None
+        if abs(chosen - CFG_MIN_PROB) > 1e-12:
+            l95, e95 = learned_run(CFG_MIN_PROB, False)
+            at_cfg = dict(min_prob=CFG_MIN_PROB, tracks_per_s=round(l95["tracks_per_s"], 1),
+                          ms_per_step=round(l95["ms_per_step"], 4), kernel_ms=round(l95["kernel_ms"], 4),
+                          efficiency=round(e95, 5), equal_efficiency=bool(e95 >= eff_plain - EFF_ALLOWANCE),
+                          proposals=l95["counters"]["proposals"])
+            del l95
+        lu = measure(ckf, geo, fld, ub, shape_learned, args.steps, args.warmup, stream, model=model,
+                     cfg=ckf.config(learned_min_prob=chosen))
+        uneven["learned"] = dict(min_prob=chosen, tracks_per_s=round(lu["tracks_per_s"], 1),
+                                 ms_per_step=round(lu["ms_per_step"], 4), kernel_ms=round(lu["kernel_ms"], 4),
+                                 efficiency=round(efficiency(ubatch, lu["result"]), 5), launch=shape_learned)
+        del lu
         learned_info = dict(tracks_per_s=round(lm["tracks_per_s"], 1), ms_per_step=round(lm["ms_per_step"], 4),
-                            min_prob=args.min_prob,
+                            kernel_ms=round(lm["kernel_ms"], 4), min_prob=chosen,
+                            threshold_choice=dict(events=args.heldout_events, plain_efficiency=round(h_plain, 5),
+                                                  allowance=EFF_ALLOWANCE, margin=EFF_MARGIN, candidates=choice),
                             efficiency=round(eff_learned, 5), launch=shape_learned,
                             proposals=c["proposals"], network_rows=c["mlp_rows"], navigations=c["navigations"],
                             listing_misses=c["proposal_misses"], seeds_affected=int(lm["seed_flags"].sum()),
+                            at_configured_threshold=at_cfg,
                             training=dict(events=args.train_events, pairs=info["pairs"], dropped=info["dropped"],
                                           epochs=log.epochs, adam_steps=log.steps, seconds=round(t2 - t1, 2),
                                           loss_first=round(log.loss[0], 4), loss_last=round(log.loss[-1], 4),
@@ -585,6 +801,7 @@ def main():
     cpu = None
     if args.cpu_events > 0:
         cpu = cpu_baseline(batch, min(args.cpu_events, batch.n_events))
+        cpu["single_thread"] = cpu_single_thread(batch, args.single_thread_seeds)
     form = "learned proposal" if learned_info else "plain"
     line = dict(metric="CKF tracks/s at mu=200 on 1 GPU; learned-proposal vs plain at equal efficiency",
                 value=round(head["tracks_per_s"], 1), unit="tracks/s", n_gpus=1, steps=args.steps,
@@ -597,13 +814,16 @@ def main():
                             tracks=head["result"]["n_tracks"],
                             launch=learned_info["launch"] if learned_info else shape_plain),
                 plain=dict(tracks_per_s=round(plain["tracks_per_s"], 1), ms_per_step=round(plain["ms_per_step"], 4),
-                           efficiency=round(eff_plain, 5), launch=shape_plain),
+                           kernel_ms=round(plain["kernel_ms"], 4), efficiency=round(eff_plain, 5), launch=shape_plain),
                 learned=learned_info,
-                equal_efficiency=(learned_info["efficiency"] >= eff_plain - 0.005) if learned_info else None,
+                equal_efficiency=(learned_info["efficiency"] >= eff_plain - EFF_ALLOWANCE) if learned_info else None,
+                learned_faster=(learned_info["tracks_per_s"] > plain["tracks_per_s"]) if learned_info else None,
                 roofline=roofline_of(head, "learned" if learned_info else "plain",
                                      learned_info["launch"] if learned_info else shape_plain),
                 plain_roofline=roofline_of(plain, "plain", shape_plain),
-                fit=fit, ambiguity=amb, clustering=clu, chain=chain, cpu_baseline=cpu, counters=plain["counters"], clocks=cyc_plain)
+                end_to_end=e2e, uneven=uneven, field_map=field_map,
+                fit=fit, ambiguity=amb, clustering=clu, chain=chain, cpu_baseline=cpu, counters=plain["counters"],
+                clocks=cyc_plain)
     print(json.dumps(line))
 
 

@@ -1,7 +1,8 @@
 """The benchmark's host-side contract (no GPU needed): it refuses more than
 one GPU with a message, and its roofline object is self-consistent (frac =
 achieved / peak, inversely proportional to the kernel time, measured traffic
-reported only for the launch shapes it was measured on)."""
+reported only for the launch shapes and the library sources it was
+measured on)."""
 import os
 import subprocess
 import sys
@@ -28,7 +29,23 @@ def test_roofline_object_is_self_consistent():
     assert abs(a["frac"] - a["achieved"] / a["peak"]) <= 1e-5 * max(1.0, a["frac"])
     assert abs(a["frac"] - 2.0 * b["frac"]) <= 2e-5 * max(1.0, a["frac"])
     assert a["fp32_flop"] > 0 and a["fp64_flop"] > 0 and a["bf16_mfma_flop"] == 77 * bench.MFMA_FLOP_PER_BLOCK
-    assert a["traffic"] == bench.MEASURED_TRAFFIC[("plain", 3072, 48, 3)]
-    other = bench.roofline_of(dict(counters=counters, kernel_ms=2.0), "plain",
-                              dict(grid=1234, seeds_per_group=16, waves_per_simd=1))
-    assert other["traffic"] is None and other["simt_efficiency"] is None
+    key = ("plain", 3072, 48, 3)
+    saved = dict(bench.MEASURED_TRAFFIC), dict(bench.MEASURED_SIMT)
+    try:
+        bench.MEASURED_TRAFFIC[key] = (1.5e9, bench.code_hash())
+        bench.MEASURED_SIMT[key] = (0.5, bench.code_hash())
+        a = bench.roofline_of(dict(counters=counters, kernel_ms=2.0), "plain", shape)
+        assert a["traffic"] == 1.5e9 and a["simt_efficiency"] == 0.5 and a["code"] == bench.code_hash()
+        other = bench.roofline_of(dict(counters=counters, kernel_ms=2.0), "plain",
+                                  dict(grid=1234, seeds_per_group=16, waves_per_simd=1))
+        assert other["traffic"] is None and other["simt_efficiency"] is None
+        # values measured on other sources are not reported
+        bench.MEASURED_TRAFFIC[key] = (1.5e9, "0" * 16)
+        bench.MEASURED_SIMT[key] = (0.5, "0" * 16)
+        stale = bench.roofline_of(dict(counters=counters, kernel_ms=2.0), "plain", shape)
+        assert stale["traffic"] is None and stale["simt_efficiency"] is None
+    finally:
+        bench.MEASURED_TRAFFIC.clear()
+        bench.MEASURED_TRAFFIC.update(saved[0])
+        bench.MEASURED_SIMT.clear()
+        bench.MEASURED_SIMT.update(saved[1])
