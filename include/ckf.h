@@ -359,10 +359,12 @@ ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, in
  * the updated state).  The smoother gives every measurement the state
  * estimated from all of the track's measurements:
  *   CKF_SMOOTHER_RTS:        Rauch-Tung-Striebel gains over the forward pass;
- *   CKF_SMOOTHER_TWO_FILTER: a backward filter over reversed legs, started
- *                            at the last measurement from the forward state
- *                            with 100 times its covariance, combined with
- *                            the forward filtered state by weight.
+ *   CKF_SMOOTHER_TWO_FILTER: Fraser and Potter's optimal smoother: an
+ *                            independent backward information filter (no
+ *                            prior, no forward information) over the model
+ *                            the forward pass linearised, combined with the
+ *                            forward filtered state by weight; equal to RTS
+ *                            up to rounding.
  * Tracks (device memory, the layout ckf_find writes): n_tracks (device
  * int32, at most cap_tracks used), offsets [cap_tracks+1] into meas,
  * meas_surface [cap_meas] and seed [cap_tracks]; measurement ids index the

@@ -26,22 +26,22 @@ Readings (the paper gives no formulas for the fit):
 * RTS: A_k = C_k|k F^T C_k+1|k^-1, x_k|n = x_k|k + A_k (x_k+1|n - x_k+1|k),
   C_k|n = C_k|k + A_k (C_k+1|n - C_k+1|k) A_k^T; the phi difference is
   taken modulo 2 pi;
-* two-filter: a backward filter starts at the last measurement from the
-  forward estimate there, with the forward covariance there multiplied by
-  BACKWARD_INFLATION (100), and runs towards the first measurement.  (An
-  uninformative start leaves the angles and q/p free for the first
-  backward updates, and their linearisation then goes far off the track:
-  with a diagonal prior of 1e4 mm^2 and 1e2 rad^2 the two smoothers
-  differed by up to thousands of sigma on central tracks; with the factor
-  100 by at most 0.3 sigma.  The start still holds 1 % of the forward
-  information at the last measurement, a 1 % double count there.)
-  Its legs reverse the track (a particle with opposite direction and
-  charge follows the same curve: phi + pi, pi - theta, -q/p), and the
-  scattering of surface k is added to its prediction at k.  The smoothed
-  state at k is the inverse-covariance weighted mean of the forward
-  filtered state at k and the backward predicted state at k (which holds
-  measurements k+1..n only); at the last measurement it is the forward
-  filtered state;
+* two-filter (Fraser and Potter's optimal smoother): a backward filter
+  that holds only the measurements after k, with no information from the
+  forward filter, is combined with the forward filtered state at k as the
+  inverse-covariance weighted mean.  The backward filter runs in
+  information form (matrix Y, vector y) on the model the forward pass
+  linearised: deviations from the forward filtered states,
+  d_k+1 = a_k+1 + F_k+1 (d_k + w_k) with a_k+1 = x_k+1|k - x_k+1|k+1 and
+  w_k the scattering of module k (covariance Q_k, evaluated at the
+  forward filtered state, as the forward prediction uses it).  It starts
+  from the last measurement's information alone (Y = H^T V^-1 H), so it
+  needs no prior and no reversed legs; a step back is Y <- F^T Y F,
+  y <- F^T (y - Y a), then the scattering (I + Y Q)^-1 applied to both;
+  each measurement adds H^T V^-1 H and H^T V^-1 (m - H x_k|k).  On one
+  linearised model the two smoothers are the same estimator, so RTS and
+  two-filter agree to rounding; at the last measurement both are the
+  forward filtered state;
 * chi2 of the fit: the sum of the forward filter's chi2 increments.
 """
 from __future__ import annotations
@@ -52,21 +52,12 @@ import numpy as np
 
 from . import kf_update, pack_cov, propagate, scatter, unpack_cov
 
-# the backward filter starts from the forward filtered covariance at the last
-# measurement times this factor
-BACKWARD_INFLATION = 100.0
-_FLIP = np.diag([1.0, 1.0, 1.0, -1.0, -1.0])
+_H = np.zeros((2, 5))
+_H[0, 0] = _H[1, 1] = 1.0
 
 
 def _wrap(a):
     return (a + math.pi) % (2.0 * math.pi) - math.pi
-
-
-def _flip(p, C):
-    """The same curve traversed backwards: (l0, l1, phi + pi, pi - theta,
-    -q/p); the covariance transforms with diag(1, 1, 1, -1, -1)."""
-    q = np.array([p[0], p[1], _wrap(p[2] + math.pi), math.pi - p[3], -p[4]])
-    return q, _FLIP @ C @ _FLIP
 
 
 def _leg(inp, src, p, C, dst, **cfg):
@@ -124,41 +115,41 @@ def rts(fw):
     return xs, Cs
 
 
-def two_filter(inp, fw, surfaces, loc, var, material=True, inflation=BACKWARD_INFLATION, **cfg):
-    """Optimal (two-filter) smoothing: weighted mean of the forward filtered
-    and the backward predicted state at each measurement.  None when a
-    backward leg fails."""
-    xf, Cf = fw["filt_p"], fw["filt_C"]
+def two_filter(inp, fw, surfaces, loc, var, material=True, **cfg):
+    """Optimal (two-filter) smoothing: the inverse-covariance weighted mean of
+    the forward filtered state at k and an independent backward filter's
+    information from the measurements after k, in the deviations from the
+    forward filtered states of the model the forward pass linearised."""
+    xp, F, xf, Cf = fw["pred_p"], fw["F"], fw["filt_p"], fw["filt_C"]
     n = xf.shape[0]
     xs, Cs = xf.copy(), Cf.copy()
-    # backward filter: prior at the last measurement, then its update there
-    bp = xf[n - 1].copy()
-    bC = Cf[n - 1] * inflation
-    pu, cu, _ = kf_update(bp, pack_cov(bC), loc[n - 1], var[n - 1])
-    bp, bC = pu, unpack_cov(cu)
+
+    def info(k):  # the information of measurement k about d_k
+        Vi = np.diag(1.0 / np.asarray(var[k], np.float64))
+        r = np.asarray(loc[k], np.float64) - _H @ xf[k]
+        return _H.T @ Vi @ _H, _H.T @ Vi @ r
+
+    Y, y = info(n - 1)
     for k in range(n - 2, -1, -1):
-        # reverse leg from measurement k+1 to k, then the scattering of k
-        q, Q = _flip(bp, bC)
-        r = _leg(inp, int(surfaces[k + 1]), q, Q, int(surfaces[k]), **cfg)
-        if r is None:
-            return None
-        q, Q, _ = r
-        bp, bC = _flip(q, Q)
-        bC = _scatter(inp, int(surfaces[k]), bp, bC, material, **cfg)
-        # weighted mean with the forward filtered state (phi taken near it)
-        b = bp.copy()
-        b[2] = xf[k, 2] + _wrap(b[2] - xf[k, 2])
-        Wf, Wb = np.linalg.inv(Cf[k]), np.linalg.inv(bC)
-        Cs[k] = np.linalg.inv(Wf + Wb)
-        xs[k] = Cs[k] @ (Wf @ xf[k] + Wb @ b)
+        # step back from k+1 to k through d_k+1 = a + F (d_k + w_k)
+        a = xp[k + 1] - xf[k + 1]
+        a[2] = _wrap(a[2])
+        Fk = F[k + 1]
+        Yu, yu = Fk.T @ Y @ Fk, Fk.T @ (y - Y @ a)
+        Q = _scatter(inp, int(surfaces[k]), xf[k], np.zeros((5, 5)), material, **cfg)
+        M = np.linalg.inv(np.eye(5) + Yu @ Q)
+        Y, y = M @ Yu, M @ yu
+        Y = 0.5 * (Y + Y.T)
+        # the weighted mean with the forward filtered state (deviation 0)
+        Cs[k] = np.linalg.inv(np.linalg.inv(Cf[k]) + Y)
+        xs[k] = xf[k] + Cs[k] @ y
         xs[k, 2] = _wrap(xs[k, 2])
-        pu, cu, _ = kf_update(bp, pack_cov(bC), loc[k], var[k])
-        bp, bC = pu, unpack_cov(cu)
+        Ym, ym = info(k)
+        Y, y = Y + Ym, y + ym
     return xs, Cs
 
 
-def fit_track(inp, seed_surface, seed_p, seed_cov, surfaces, loc, var, smoother="rts", material=True,
-              inflation=BACKWARD_INFLATION, **cfg):
+def fit_track(inp, seed_surface, seed_p, seed_cov, surfaces, loc, var, smoother="rts", material=True, **cfg):
     """Fit one track: dict(params [n,5], cov [n,5,5] smoothed at each
     measurement, filt_p, filt_C, chi2) or None."""
     fw = forward(inp, seed_surface, seed_p, seed_cov, surfaces, loc, var, material, **cfg)
@@ -167,7 +158,7 @@ def fit_track(inp, seed_surface, seed_p, seed_cov, surfaces, loc, var, smoother=
     if smoother == "rts":
         sm = rts(fw)
     else:
-        sm = two_filter(inp, fw, surfaces, loc, var, material, inflation, **cfg)
+        sm = two_filter(inp, fw, surfaces, loc, var, material, **cfg)
         if sm is None:
             return None
     return dict(params=sm[0], cov=sm[1], filt_p=fw["filt_p"], filt_C=fw["filt_C"], chi2=float(fw["chi2"].sum()))

@@ -8,44 +8,39 @@
 // its tangent-column Jacobian (the search's stepper), FP64 covariance
 // transport, FP64 gain-form update with the Joseph covariance, then the
 // module's Highland scattering added at the updated state.  The smoother
-// runs backwards over one workspace record per measurement, which holds only
-// what it reads: the filtered state and covariance, and for RTS also the
-// predicted state and the leg's Jacobian (the predicted covariance is
-// rebuilt from the record before it with the forward pass's own scattering
-// and transport functions):
+// runs backwards over one workspace record per measurement, which holds what
+// it reads: the predicted and filtered states, the filtered covariance and
+// the leg's Jacobian (the predicted covariance is rebuilt from the record
+// before it with the forward pass's own scattering and transport functions):
 //   RTS:        A_k = C_k|k F^T C_k+1|k^-1 (a Cholesky solve, no inverse),
 //               x_k|n = x_k|k + A_k (x_k+1|n - x_k+1|k),
 //               C_k|n = C_k|k + A_k (C_k+1|n - C_k+1|k) A_k^T;
-//   two-filter: a backward filter from the last measurement (its start is
-//               the forward state there with the forward covariance times
-//               kBackwardInflation) runs reversed legs (the same curve with
-//               opposite direction and charge), adds the scattering of each
-//               surface to its prediction there, and is combined with the
-//               forward filtered state as x = x_f + C_f (C_f + C_b)^-1
-//               (x_b - x_f), C = C_f - C_f (C_f + C_b)^-1 C_f.
-#include <type_traits>
-
+//   two-filter: Fraser and Potter's optimal smoother.  An independent
+//               backward filter in information form (Y, y), started from
+//               the last measurement's information alone, runs over the
+//               model the forward pass linearised, in deviations from the
+//               forward filtered states: d_k+1 = a + F (d_k + w_k), with
+//               a = x_k+1|k - x_k+1|k+1 and w_k the scattering of module k.
+//               A step back is Y <- F^T Y F, y <- F^T (y - Y a), then
+//               (I + Y Q_k)^-1 on both (Q_k touches phi and theta only, so
+//               a 2x2 solve); the smoothed state is the weighted mean
+//               C = (C_f^-1 + Y)^-1, x = x_f + C y (two Cholesky
+//               factorisations); each measurement then adds H^T V^-1 H
+//               and H^T V^-1 (m - H x_f).
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
 
 namespace ckf {
 
-constexpr double kBackwardInflation = 100.0;
-constexpr double kPi = 3.14159265358979323846;
-
-struct alignas(16) RecRts {
+struct alignas(16) Rec {
   double pp[5];          // predicted state at the measurement
   double fp[5], fC[15];  // filtered
   float F[25];           // the leg into the measurement (row-major)
   float pad[1];
 };
-static_assert(sizeof(RecRts) == 304, "RTS record layout");
-struct alignas(16) RecTwo {
-  double fp[5], fC[15];  // filtered
-};
-static_assert(sizeof(RecTwo) == 160, "two-filter record layout");
+static_assert(sizeof(Rec) == 304, "fit record layout");
 
-size_t fit_workspace_bytes(long long cap_meas) { return (size_t)cap_meas * sizeof(RecRts); }
+size_t fit_workspace_bytes(long long cap_meas) { return (size_t)cap_meas * sizeof(Rec); }
 
 namespace {
 
@@ -99,19 +94,6 @@ __device__ __forceinline__ void chol5_solve(const double L[5][5], double B[5][5]
   }
 }
 
-// Reverse the direction of travel on the same surface: (l0, l1, phi + pi,
-// pi - theta, -q/p); the covariance picks up the signs (1, 1, 1, -1, -1).
-__device__ __forceinline__ void flip(double* p, double* C) {
-  p[2] = wrap_phi(p[2] + kPi);
-  p[3] = kPi - p[3];
-  p[4] = -p[4];
-#pragma unroll
-  for (int i = 0; i < 5; ++i)
-#pragma unroll
-    for (int j = i; j < 5; ++j)
-      if ((i >= 3) != (j >= 3)) C[pk(i, j)] = -C[pk(i, j)];
-}
-
 // One leg from module src to module dst: state and covariance replaced by
 // the transported ones, J the bound-to-bound Jacobian.  False if it fails.
 template <bool kMap>
@@ -159,7 +141,6 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
                                             void* __restrict__ ws_raw, double* __restrict__ out_p,
                                             double* __restrict__ out_C, double* __restrict__ chi2_out,
                                             int* __restrict__ ok) {
-  using Rec = typename std::conditional<kTwo, RecTwo, RecRts>::type;
   Rec* __restrict__ ws = static_cast<Rec*>(ws_raw);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n_t = min(*n_tracks_p, cap_tracks);
@@ -210,14 +191,12 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
         for (int j = 0; j < 5; ++j) J[i][j] = i == j ? 1.f : 0.f;
     }
-    if constexpr (!kTwo) {
 #pragma unroll
-      for (int i = 0; i < 5; ++i) R.pp[i] = p[i];
+    for (int i = 0; i < 5; ++i) R.pp[i] = p[i];
 #pragma unroll
-      for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 5; ++i)
 #pragma unroll
-        for (int j = 0; j < 5; ++j) R.F[5 * i + j] = J[i][j];
-    }
+      for (int j = 0; j < 5; ++j) R.F[5 * i + j] = J[i][j];
     const double m0 = lm0, m1 = lm1, v0 = lv0, v1 = lv1;
     chi2 += chi2_of(p, C, m0, m1, v0, v1);
     double po[5], Co[15];
@@ -332,85 +311,152 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
       for (int i = 0; i < 15; ++i) out_C[15 * k + i] = Cs[i];
     }
   } else {
-    // ---- two-filter: backward filter, combined with the forward one
-    double bp[5], bC[15];
-    {
-      const Rec& R = ws[b - 1];
-      double q[5], Q[15];
+    // ---- two-filter: the backward information filter, combined with the
+    // forward filtered state at each measurement
+    double Y[5][5], y[5];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) q[i] = R.fp[i];
+    for (int i = 0; i < 5; ++i) {
+      y[i] = 0.0;
 #pragma unroll
-      for (int i = 0; i < 15; ++i) Q[i] = R.fC[i] * kBackwardInflation;
-      const int id = meas[b - 1];
-      kf_update(q, Q, m.loc[2ll * id], m.loc[2ll * id + 1], m.var[2ll * id], m.var[2ll * id + 1], bp, bC);
+      for (int j = 0; j < 5; ++j) Y[i][j] = 0.0;
     }
+    auto add_meas = [&](long long k, const double* xf) {
+      const int id = meas[k];
+      const double v0 = m.var[2ll * id], v1 = m.var[2ll * id + 1];
+      Y[0][0] += 1.0 / v0;
+      Y[1][1] += 1.0 / v1;
+      y[0] += ((double)m.loc[2ll * id] - xf[0]) / v0;
+      y[1] += ((double)m.loc[2ll * id + 1] - xf[1]) / v1;
+    };
+    add_meas(b - 1, ws[b - 1].fp);
     for (long long k = b - 2; k >= a; --k) {
       const Rec& Rk = ws[k];
-      flip(bp, bC);
-      if (msurf[k + 1] != msurf[k]) {
-        float J[5][5];
-        if (!fit_leg<kMap>(g, F, cfg, msurf[k + 1], msurf[k], bp, bC, J)) {
-          fail_track(a, b, out_p, out_C, ok, t, 0);
-          return;
-        }
+      const Rec& Rn = ws[k + 1];
+      // step back through d_k+1 = a + F (d_k + w_k): Yu = F^T Y F,
+      // yu = F^T (y - Y a)
+      double av[5], tv[5], YF[5][5], Yu[5][5], yu[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) av[i] = Rn.pp[i] - Rn.fp[i];
+      av[2] = wrap_phi(av[2]);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        double acc = y[i];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) acc = fma(-Y[i][l], av[l], acc);
+        tv[i] = acc;
       }
-      flip(bp, bC);
-      if (cfg.material) {
-        Module M;
-        load_module(g, msurf[k], M);
-        apply_ms(M, cfg.mass, bp, bC);
-      }
-      // K^T = (fC + bC)^-1 fC
-      double S[5][5], Z[5][5];
 #pragma unroll
       for (int i = 0; i < 5; ++i)
 #pragma unroll
-        for (int j = i; j < 5; ++j) {
-          S[i][j] = S[j][i] = Rk.fC[pk(i, j)] + bC[pk(i, j)];
-          Z[i][j] = Z[j][i] = Rk.fC[pk(i, j)];
+        for (int j = 0; j < 5; ++j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int l = 0; l < 5; ++l) acc = fma(Y[i][l], (double)Rn.F[5 * l + j], acc);
+          YF[i][j] = acc;
         }
-      if (!chol5(S)) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < 5; ++l) acc = fma((double)Rn.F[5 * l + i], tv[l], acc);
+        yu[i] = acc;
+#pragma unroll
+        for (int j = i; j < 5; ++j) {
+          double s = 0.0;
+#pragma unroll
+          for (int l = 0; l < 5; ++l) s = fma((double)Rn.F[5 * l + i], YF[l][j], s);
+          Yu[i][j] = s;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) Yu[i][j] = Yu[j][i];
+      // the scattering of module k at its filtered state: Q = diag(0, 0,
+      // q2, q3, 0); (I + Yu Q)^-1 = I - Yu[:, S] G Q-rows with
+      // G = (I2 + q Yu[S, S])^-1 q, S = {phi, theta}
+      if (cfg.material) {
+        double qc[15], qp[5];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) qc[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) qp[i] = Rk.fp[i];
+        Module M;
+        load_module(g, msurf[k], M);
+        apply_ms(M, cfg.mass, qp, qc);
+        const double q2 = qc[pk(2, 2)], q3 = qc[pk(3, 3)];
+        const double a00 = 1.0 + q2 * Yu[2][2], a01 = q2 * Yu[2][3], a10 = q3 * Yu[3][2], a11 = 1.0 + q3 * Yu[3][3];
+        const double idet = 1.0 / (a00 * a11 - a01 * a10);
+        // G = A^-1 diag(q2, q3)
+        const double g00 = a11 * idet * q2, g01 = -a01 * idet * q3, g10 = -a10 * idet * q2, g11 = a00 * idet * q3;
+        const double gs = 0.5 * (g01 + g10);
+        double yn[5], Yn[5][5];
+        const double ys2 = g00 * yu[2] + gs * yu[3], ys3 = gs * yu[2] + g11 * yu[3];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          yn[i] = yu[i] - (Yu[i][2] * ys2 + Yu[i][3] * ys3);
+          const double r2 = g00 * Yu[2][i] + gs * Yu[3][i], r3 = gs * Yu[2][i] + g11 * Yu[3][i];
+#pragma unroll
+          for (int j = 0; j < 5; ++j) Yn[j][i] = Yu[j][i] - (Yu[j][2] * r2 + Yu[j][3] * r3);
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          y[i] = yn[i];
+#pragma unroll
+          for (int j = 0; j < 5; ++j) Y[i][j] = 0.5 * (Yn[i][j] + Yn[j][i]);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          y[i] = yu[i];
+#pragma unroll
+          for (int j = 0; j < 5; ++j) Y[i][j] = Yu[i][j];
+        }
+      }
+      // weighted mean: W = C_f^-1 + Y, C = W^-1, x = x_f + C y
+      double Lf[5][5], W[5][5];
+      unpack5(Rk.fC, Lf);
+      if (!chol5(Lf)) {
         fail_track(a, b, out_p, out_C, ok, t, 0);
         return;
       }
-      chol5_solve(S, Z);
-      double d[5];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) d[i] = bp[i] - Rk.fp[i];
-      d[2] = wrap_phi(d[2]);
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) W[i][j] = i == j ? 1.0 : 0.0;
+      chol5_solve(Lf, W);  // C_f^-1
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) W[i][j] = 0.5 * (W[i][j] + W[j][i]) + Y[i][j];
+      double Cm[5][5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) Cm[i][j] = i == j ? 1.0 : 0.0;
+      if (!chol5(W)) {
+        fail_track(a, b, out_p, out_C, ok, t, 0);
+        return;
+      }
+      chol5_solve(W, Cm);  // W^-1
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = i; j < 5; ++j) Cs[pk(i, j)] = 0.5 * (Cm[i][j] + Cm[j][i]);
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
         double acc = Rk.fp[i];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) acc = fma(Z[j][i], d[j], acc);
+        for (int j = 0; j < 5; ++j) acc = fma(Cs[pk(min(i, j), max(i, j))], y[j], acc);
         xs[i] = acc;
       }
       xs[2] = wrap_phi(xs[2]);
-      // C = fC - K fC, symmetrised
-#pragma unroll
-      for (int i = 0; i < 5; ++i)
-#pragma unroll
-        for (int j = i; j < 5; ++j) {
-          double kij = 0.0, kji = 0.0;
-#pragma unroll
-          for (int l = 0; l < 5; ++l) {
-            kij = fma(Z[l][i], Rk.fC[pk(l, j)], kij);
-            kji = fma(Z[l][j], Rk.fC[pk(l, i)], kji);
-          }
-          Cs[pk(i, j)] = Rk.fC[pk(i, j)] - 0.5 * (kij + kji);
-        }
 #pragma unroll
       for (int i = 0; i < 5; ++i) out_p[5 * k + i] = xs[i];
 #pragma unroll
       for (int i = 0; i < 15; ++i) out_C[15 * k + i] = Cs[i];
       // the backward filter takes measurement k
-      const int id = meas[k];
-      double q[5], Q[15];
-      kf_update(bp, bC, m.loc[2ll * id], m.loc[2ll * id + 1], m.var[2ll * id], m.var[2ll * id + 1], q, Q);
-#pragma unroll
-      for (int i = 0; i < 5; ++i) bp[i] = q[i];
-#pragma unroll
-      for (int i = 0; i < 15; ++i) bC[i] = Q[i];
+      add_meas(k, Rk.fp);
     }
   }
   ok[t] = 1;
