@@ -543,17 +543,32 @@ def roofline_of(m, form, shape):
                 note="achieved = FP32-equivalent rate (F32 + 2*F64 + F_bf16/15.9)/t against the FP32 vector peak")
 
 
+def loop_use(c):
+    """Lane use of the search's data-dependent loops: iterations summed over
+    the lanes that ran the loop, over 64 times the longest lane's iterations
+    summed over the wave's passes (1.0: every lane busy for every pass)."""
+    out = {}
+    for k in ("list", "next", "land", "win"):
+        w = c.get(k + "_wave", 0)
+        out[k] = round(c.get(k + "_lane", 0) / (64.0 * w), 4) if w else None
+    return out
+
+
 def phase_line(c, label):
     tot = max(1, c["cycles_step"])
+    lu = loop_use(c)
     return ("# {} instrumented run, share of step time: phase1 (nav+leg) {:.2f}, search {:.2f}, out {:.2f}; "
             "lane-average navigation / phase1 {:.2f}, next-layer search / navigation {:.2f}; "
-            "lane occupancy {:.2f}; clocks per 64-lane pass {:.0f}").format(
+            "lane occupancy {:.2f}; clocks per 64-lane pass {:.0f}; loop lane use: listing {}, next layer {}, "
+            "landing {}, window {}").format(
         label, c["cycles_leg"] / tot, c["cycles_search"] / tot, c["cycles_out"] / tot,
         c["cycles_nav"] / 64.0 / max(1, c["cycles_leg"]), c["cycles_next"] / max(1, c["cycles_nav"]),
-        c["steps"] / 64.0 / max(1, c["chunks"]), tot / max(1, c["chunks"]))
+        c["steps"] / 64.0 / max(1, c["chunks"]), tot / max(1, c["chunks"]), lu["list"], lu["next"], lu["land"],
+        lu["win"])
 
 
-CYCLE_KEYS = ("cycles_leg", "cycles_search", "cycles_out", "cycles_nav", "cycles_step", "cycles_next", "chunks")
+CYCLE_KEYS = ("cycles_leg", "cycles_search", "cycles_out", "cycles_nav", "cycles_step", "cycles_next", "chunks",
+              "list_lane", "list_wave", "next_lane", "next_wave", "land_lane", "land_wave", "win_lane", "win_wave")
 
 
 def main():
@@ -823,7 +838,7 @@ def main():
                 plain_roofline=roofline_of(plain, "plain", shape_plain),
                 end_to_end=e2e, uneven=uneven, field_map=field_map,
                 fit=fit, ambiguity=amb, clustering=clu, chain=chain, cpu_baseline=cpu, counters=plain["counters"],
-                clocks=cyc_plain)
+                clocks=cyc_plain, loop_lane_use=loop_use(cyc_plain))
     print(json.dumps(line))
 
 

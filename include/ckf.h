@@ -189,7 +189,7 @@ typedef struct ckf_tracks {
   int32_t* event;            /* [cap_tracks] */
   int32_t* last_surface;     /* [cap_tracks] module of the last measurement */
   int32_t* status;           /* [8] CKF_STATUS_* words */
-  int64_t* counters;         /* [24] or NULL: work-unit counters (CKF_CNT_*) */
+  int64_t* counters;         /* [32] or NULL: work-unit counters (CKF_CNT_*) */
   int32_t* meas_surface;     /* [cap_meas] or NULL: module of each measurement */
   double* meas_params;       /* [cap_meas][5] or NULL: filtered parameters after each measurement */
   int32_t* seed_flags;       /* [n_seeds] or NULL: with counters and a model, 1 for a seed one of whose
@@ -225,7 +225,18 @@ enum {
   CKF_CNT_PROPOSALS = 21,  /* ... whose proposal was used (confident, non-empty listing) */
   CKF_CNT_PROPOSAL_MISS = 22, /* used proposals whose listing differs from the geometric one (audit) */
   CKF_CNT_MLP_BLOCKS = 23, /* 16-row network evaluations on the matrix cores */
-  CKF_CNT_N = 24
+  /* loop divergence (instrumented run): iterations summed over the lanes
+   * that ran a loop, and the longest lane's iterations summed over the
+   * wave's passes through it (their ratio / 64 is the loop's lane use) */
+  CKF_CNT_LIST_LANE = 24,  /* grid entries visited by a module listing */
+  CKF_CNT_LIST_WAVE = 25,
+  CKF_CNT_NEXT_LANE = 26,  /* layer envelopes tried by a next-layer search */
+  CKF_CNT_NEXT_WAVE = 27,
+  CKF_CNT_LAND_LANE = 28,  /* landing iterations (RKN4 trials plus the final plane distance) of a leg */
+  CKF_CNT_LAND_WAVE = 29,
+  CKF_CNT_WIN_LANE = 30,   /* measurements read by a window scan */
+  CKF_CNT_WIN_WAVE = 31,
+  CKF_CNT_N = 32
 };
 
 /* Launch shape of ckf_find (chosen by the autotuner or the caller). */

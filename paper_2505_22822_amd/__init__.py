@@ -329,7 +329,7 @@ class Finder:
                         params=z((n, 5), torch.float64), cov=z((n, 15), torch.float64), chi2=z(n, torch.float64),
                         ndf=z(n, torch.int32), holes=z(n, torch.int32), seed=z(n, torch.int32),
                         event=z(n, torch.int32), last_surface=z(n, torch.int32), status=z(8, torch.int32),
-                        counters=z(24, torch.int64) if counters else None,
+                        counters=z(len(COUNTER_NAMES), torch.int64) if counters else None,
                         meas_surface=z(cap_m, torch.int32) if meas_states else None,
                         meas_params=z((cap_m, 5), torch.float64) if meas_states else None,
                         seed_flags=z(n, torch.int32) if seed_flags else None)

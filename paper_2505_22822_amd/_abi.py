@@ -16,7 +16,8 @@ ST_FLAGS, ST_NODES, ST_TRACKS, ST_MEAS, ST_BAD_SEEDS, ST_FAILED_LEGS, ST_NAV_OVF
 COUNTER_NAMES = ("steps", "navigations", "nav_modules", "legs", "rk_trials", "chi2_evals", "kf_updates",
                  "ms_updates", "crossed", "holes", "pruned", "finished", "rk_rejects", "cycles_leg",
                  "cycles_search", "cycles_out", "cycles_nav", "cycles_step", "chunks", "cycles_next",
-                 "mlp_rows", "proposals", "proposal_misses", "mlp_blocks")
+                 "mlp_rows", "proposals", "proposal_misses", "mlp_blocks", "list_lane", "list_wave",
+                 "next_lane", "next_wave", "land_lane", "land_wave", "win_lane", "win_wave")
 MAX_NEXT_LAYERS, NEIGHBOURS, MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS = 3, 32, 7, 32, 6752
 REGION_U, REGION_V = 24, 8
 

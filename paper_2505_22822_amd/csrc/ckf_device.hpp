@@ -636,7 +636,7 @@ __device__ __forceinline__ int list_out(const ListAcc& a, int* list) {
 // (navigation grid lookup), each put through the listing test.  Returns the
 // number listed (<= kMaxList, sorted by path then id).
 __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_base, int exclude, float margin,
-                          int* list, int& n_tested, int& overflow) {
+                          int* list, int& n_tested, int& overflow, int& n_visited) {
   const LayerRec Lr = g.layers[l];
   // segment of the trajectory that can reach the layer's modules
   float span;
@@ -685,6 +685,7 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
         break;
       }
       visited += q + 1 < b ? 2 : 1;
+      n_visited += q + 1 < b ? 2 : 1;
       const int m0 = g.cell_mod[q];
       const int m1 = q + 1 < b ? g.cell_mod[q + 1] : -1;
       Module M0, M1;
@@ -700,7 +701,8 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
 // The next navigation layer from free state (p, T, lam) in global
 // coordinates: the unvisited layer whose envelope the local helix meets
 // first within its extent and the path budget.  Returns -1 if none.
-__device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long mask, float budget, float& s_best) {
+__device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long mask, float budget, float& s_best,
+                          int& n_tried) {
   const float rperp = sqrtf(H.p0.x * H.p0.x + H.p0.y * H.p0.y);
   int best = -1;
   s_best = INFINITY;
@@ -710,6 +712,7 @@ __device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long m
     if (mask & (1ull << l)) continue;
     const LayerRec Lr = g.layers[l];
     if (!(Lr.pos > rperp)) continue;
+    ++n_tried;
     float s;
     if (!cross_cylinder(H, Lr.pos, s)) continue;
     V3 p, T;
@@ -727,6 +730,7 @@ __device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long m
     const int l = order[q];
     if (mask & (1ull << l)) continue;
     const LayerRec Lr = g.layers[l];
+    ++n_tried;
     float s;
     if (!cross_zplane(H, Lr.pos, s)) continue;
     if (s > s_best || s > budget) break;

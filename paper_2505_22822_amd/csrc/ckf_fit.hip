@@ -425,20 +425,19 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
         for (int j = 0; j < 5; ++j) W[i][j] = i == j ? 1.0 : 0.0;
       chol5_solve(Lf, W);  // C_f^-1
+      double Ws[5][5], Cm[5][5];
 #pragma unroll
       for (int i = 0; i < 5; ++i)
 #pragma unroll
-        for (int j = 0; j < 5; ++j) W[i][j] = 0.5 * (W[i][j] + W[j][i]) + Y[i][j];
-      double Cm[5][5];
-#pragma unroll
-      for (int i = 0; i < 5; ++i)
-#pragma unroll
-        for (int j = 0; j < 5; ++j) Cm[i][j] = i == j ? 1.0 : 0.0;
-      if (!chol5(W)) {
+        for (int j = 0; j < 5; ++j) {
+          Ws[i][j] = 0.5 * (W[i][j] + W[j][i]) + Y[i][j];
+          Cm[i][j] = i == j ? 1.0 : 0.0;
+        }
+      if (!chol5(Ws)) {
         fail_track(a, b, out_p, out_C, ok, t, 0);
         return;
       }
-      chol5_solve(W, Cm);  // W^-1
+      chol5_solve(Ws, Cm);  // W^-1
 #pragma unroll
       for (int i = 0; i < 5; ++i)
 #pragma unroll

@@ -174,6 +174,12 @@ __device__ __forceinline__ int wave_excl_scan(int v, int& total) {
   return x - v;
 }
 
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+
 __device__ __forceinline__ long long wave_sum64(long long v) {
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
@@ -350,6 +356,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       int outcome = 0;
       bool moved = false;
       float J[5][5];
+      int c_list = 0, c_next = 0, c_land = 0, c_win = 0;  // loop iterations of this lane (instrumented run)
       long long t_phase = kCount ? clock64() : 0;
       if (kCount && lane == 0) CNT_ADD(CKF_CNT_CHUNKS, 1);
 
@@ -408,7 +415,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           float sL;
           CNT_ADD(CKF_CNT_NAV, 1);
           const long long t_next = kCount ? clock64() : 0;
-          const int nl = next_layer(g, H, mask, cfg.path_max - path, sL);
+          const int nl = next_layer(g, H, mask, cfg.path_max - path, sL, c_next);
           if (kCount) CNT_ADD(CKF_CNT_CYC_NEXT, (int)(clock64() - t_next));
           if (nl < 0) {
             outcome = 3;
@@ -520,7 +527,8 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
               if (kCount) {  // audit against the geometric listing
                 int full[kMaxList];
                 int nt2 = 0, ovf2 = 0;
-                const int nf = list_layer(g, lay, Pl, Tl, kl, sb, excl, margin, full, nt2, ovf2);
+                int nv2 = 0;
+                const int nf = list_layer(g, lay, Pl, Tl, kl, sb, excl, margin, full, nt2, ovf2, nv2);
                 bool same = nf == np;
 #pragma unroll
                 for (int k = 0; k < kMaxList; ++k) same = same && full[k] == list[k];
@@ -531,7 +539,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
               }
             }
           }
-          if (!listed) nlist = list_layer(g, lay, Pl, Tl, kl, sb, excl, margin, list, nt, ovf);
+          if (!listed) nlist = list_layer(g, lay, Pl, Tl, kl, sb, excl, margin, list, nt, ovf, c_list);
           CNT_ADD(CKF_CNT_NAV_MODULES, nt);
           CNT_ADD(kNavOvf, ovf);
           if (!root && nlist == 0) {
@@ -558,6 +566,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             CNT_ADD(CKF_CNT_LEGS, 1);
             bool good = land<kMap>(L, origin, dB, ld3(Bm.n), A.f, cfg, h, path, ls);
             CNT_ADD(CKF_CNT_RK_TRIALS, ls.trials);
+            c_land = ls.trials + 1;
             CNT_ADD(CKF_CNT_RK_REJECTS, ls.rejects);
             if (good) {
               double pn[5];
@@ -640,6 +649,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             float4 ms = l < b ? A.w.m_sorted[l] : make_float4(INFINITY, 0.f, 0.f, 0.f);
             for (int i = l; i < b; ++i) {
               const float4 nx = i + 1 < b ? A.w.m_sorted[i + 1] : make_float4(INFINITY, 0.f, 0.f, 0.f);
+              ++c_win;
               if (ms.x > hi) break;
               CNT_ADD(CKF_CNT_CHI2, 1);
               const double x2 = chi2_of(p, C, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w);
@@ -688,6 +698,19 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         const long long t = clock64();
         CNT_ADD(CKF_CNT_CYC_SEARCH, (int)(t - t_phase));
         t_phase = t;
+      }
+      if (kCount) {  // loop divergence: lane iterations and the wave's longest lane
+        CNT_ADD(CKF_CNT_LIST_LANE, c_list);
+        CNT_ADD(CKF_CNT_NEXT_LANE, c_next);
+        CNT_ADD(CKF_CNT_LAND_LANE, c_land);
+        CNT_ADD(CKF_CNT_WIN_LANE, c_win);
+        const int m0 = wave_max(c_list), m1 = wave_max(c_next), m2 = wave_max(c_land), m3 = wave_max(c_win);
+        if (lane == 0) {
+          CNT_ADD(CKF_CNT_LIST_WAVE, m0);
+          CNT_ADD(CKF_CNT_NEXT_WAVE, m1);
+          CNT_ADD(CKF_CNT_LAND_WAVE, m2);
+          CNT_ADD(CKF_CNT_WIN_WAVE, m3);
+        }
       }
       // ---- phase 3: slots for the outputs (wave scan) and history nodes
       const int n_out = outcome == 1 ? 1 : (outcome == 2 ? n_acc : 0);
