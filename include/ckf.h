@@ -229,7 +229,7 @@ enum {
    * that ran a loop, and the longest lane's iterations summed over the
    * wave's passes through it (their ratio / 64 is the loop's lane use) */
   CKF_CNT_LIST_LANE = 24,  /* grid entries visited by a module listing */
-  CKF_CNT_LIST_WAVE = 25,
+  CKF_CNT_LIST_WAVE = 25,  /* (the listing is wave-cooperative: its 64-entry passes) */
   CKF_CNT_NEXT_LANE = 26,  /* layer envelopes tried by a next-layer search */
   CKF_CNT_NEXT_WAVE = 27,
   CKF_CNT_LAND_LANE = 28,  /* landing iterations (RKN4 trials plus the final plane distance) of a leg */

@@ -585,16 +585,21 @@ __device__ __forceinline__ void list_init(ListAcc& a) {
   }
 }
 
-__device__ __forceinline__ void list_test(ListAcc& a, int m, const Module& M, V3 P, V3 T, V3 k, float s_base,
-                                          float margin, int& n_tested) {
+// The listing test of module m (record M) from the base point: true when the
+// expansion meets its plane within the half lengths plus the margin at
+// positive total path cs; `tested` is raised when the module passes the
+// reach pre-filter.
+__device__ __forceinline__ bool list_probe(const Module& M, V3 P, V3 T, V3 k, float s_base, float margin,
+                                           float& cs, bool& tested) {
   const V3 c = ld3(M.c), nn = ld3(M.n);
   const float hd = sqrtf((M.hw0 + margin) * (M.hw0 + margin) + (M.hw1 + margin) * (M.hw1 + margin));
   const V3 dc = c - P;
   const float reach = hd + kReach;
-  if (dot(dc, dc) > reach * reach) return;
-  ++n_tested;
+  tested = false;
+  if (dot(dc, dc) > reach * reach) return false;
+  tested = true;
   const float qa = 0.5f * dot(nn, k), qb = dot(nn, T), c0 = dot(nn, P - c);
-  if (fabsf(qb) < 1e-3f) return;
+  if (fabsf(qb) < 1e-3f) return false;
   float d = fdiv_fast(-c0, qb);
   const float disc = qb * qb - 4.0f * qa * c0;
   if (disc >= 0.f) {
@@ -603,9 +608,15 @@ __device__ __forceinline__ void list_test(ListAcc& a, int m, const Module& M, V3
   }
   const V3 X = P + d * T + (0.5f * d * d) * k - c;
   const float l0 = dot(ld3(M.u), X), l1 = dot(ld3(M.v), X);
-  if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) return;
-  float cs = s_base + d;
-  if (!(cs > 0.f)) return;
+  if (fabsf(l0) > M.hw0 + margin || fabsf(l1) > M.hw1 + margin) return false;
+  cs = s_base + d;
+  return cs > 0.f;
+}
+
+// Insert a listed (path, module) into the accumulator: the kMaxList smallest
+// (path, id) in order, each module once.  (A module met twice has the same
+// path both times, so the result does not depend on the order of insertion.)
+__device__ __forceinline__ void list_insert(ListAcc& a, int m, float cs) {
   if (a.lm[0] == m || a.lm[1] == m || a.lm[2] == m || a.lm[3] == m) return;
   int cm = m;
 #pragma unroll
@@ -622,6 +633,15 @@ __device__ __forceinline__ void list_test(ListAcc& a, int m, const Module& M, V3
   }
 }
 
+__device__ __forceinline__ void list_test(ListAcc& a, int m, const Module& M, V3 P, V3 T, V3 k, float s_base,
+                                          float margin, int& n_tested) {
+  float cs;
+  bool tested;
+  const bool pass = list_probe(M, P, T, k, s_base, margin, cs, tested);
+  n_tested += tested ? 1 : 0;
+  if (pass) list_insert(a, m, cs);
+}
+
 __device__ __forceinline__ int list_out(const ListAcc& a, int* list) {
   int n = 0;
 #pragma unroll
@@ -632,12 +652,15 @@ __device__ __forceinline__ int list_out(const ListAcc& a, int* list) {
   return n;
 }
 
-// Candidate modules of layer `l` near the trajectory segment from P along T
-// (navigation grid lookup), each put through the listing test.  Returns the
-// number listed (<= kMaxList, sorted by path then id).
-__device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_base, int exclude, float margin,
-                          int* list, int& n_tested, int& overflow, int& n_visited) {
-  const LayerRec Lr = g.layers[l];
+// The navigation grid's cells near the trajectory segment from P along T on
+// layer Lr: phi rows ip0..ip1 (taken modulo nphi) and w cells iw0..iw1 of
+// each row.  False when the segment's bounds are not finite (nothing is
+// listed then); iw0 > iw1 means no cells.
+struct GridRange {
+  int ip0, ip1, iw0, iw1;
+};
+
+__device__ __forceinline__ bool grid_range(const LayerRec& Lr, V3 P, V3 T, GridRange& gr) {
   // segment of the trajectory that can reach the layer's modules
   float span;
   if (Lr.type == 0) {
@@ -658,26 +681,49 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
   if (dph < -3.14159265f) dph += twopi;
   const float phlo = fminf(ph0, ph0 + dph), phhi = fmaxf(ph0, ph0 + dph);
   const float wlo = fminf(w0, w1), whi = fmaxf(w0, w1);
-  if (!(isfinite(phlo) && isfinite(phhi) && isfinite(wlo) && isfinite(whi))) return 0;
+  if (!(isfinite(phlo) && isfinite(phhi) && isfinite(wlo) && isfinite(whi))) return false;
   // bins per radian and per unit of w (the grid extents are padded, so
   // rounding of the bin edges cannot lose a module)
   const float iph = (float)Lr.nphi * (1.0f / twopi), iw = fdiv_fast((float)Lr.nw, Lr.whi - Lr.wlo);
-  int ip0 = (int)floorf((phlo + 3.14159265f) * iph);
-  int ip1 = (int)floorf((phhi + 3.14159265f) * iph);
-  int iw0 = (int)floorf((wlo - Lr.wlo) * iw), iw1 = (int)floorf((whi - Lr.wlo) * iw);
-  iw0 = max(iw0, 0);
-  iw1 = min(iw1, Lr.nw - 1);
-  if (ip1 - ip0 >= Lr.nphi) { ip0 = 0; ip1 = Lr.nphi - 1; }
+  gr.ip0 = (int)floorf((phlo + 3.14159265f) * iph);
+  gr.ip1 = (int)floorf((phhi + 3.14159265f) * iph);
+  gr.iw0 = max((int)floorf((wlo - Lr.wlo) * iw), 0);
+  gr.iw1 = min((int)floorf((whi - Lr.wlo) * iw), Lr.nw - 1);
+  if (gr.ip1 - gr.ip0 >= Lr.nphi) {
+    gr.ip0 = 0;
+    gr.ip1 = Lr.nphi - 1;
+  }
+  return true;
+}
+
+// The CSR range of phi row ipr (modulo nphi) over the cells iw0..iw1: the
+// cells of one row are adjacent in the grid's CSR.
+__device__ __forceinline__ void grid_row(const GeomDev& g, const LayerRec& Lr, const GridRange& gr, int ipr, int& a,
+                                         int& b) {
+  int ip = ipr % Lr.nphi;
+  if (ip < 0) ip += Lr.nphi;
+  const int row = Lr.cell_base + ip * Lr.nw;
+  a = g.cell_off[row + gr.iw0];
+  b = g.cell_off[row + gr.iw1 + 1];
+}
+
+// Candidate modules of layer `l` near the trajectory segment from P along T
+// (navigation grid lookup), each put through the listing test, at most
+// kMaxCand grid entries in visiting order (rows by phi, entries in pairs).
+// Returns the number listed (<= kMaxList, sorted by path then id).  One lane
+// on its own; the search kernel lists a wave's lanes together (list_wave)
+// and comes here only for the rare lane that does not fit that scheme.
+__device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_base, int exclude, float margin,
+                          int* list, int& n_tested, int& overflow, int& n_visited) {
+  const LayerRec Lr = g.layers[l];
+  GridRange gr;
+  if (!grid_range(Lr, P, T, gr)) return 0;
   ListAcc acc;
   list_init(acc);
   int visited = 0;
-  for (int ipr = ip0; ipr <= ip1 && iw0 <= iw1; ++ipr) {
-    int ip = ipr % Lr.nphi;
-    if (ip < 0) ip += Lr.nphi;
-    // the cells iw0..iw1 of one phi row are adjacent in the grid's CSR, so
-    // their entries are one range (two bound loads per row, not per cell)
-    const int row = Lr.cell_base + ip * Lr.nw;
-    const int a = g.cell_off[row + iw0], b = g.cell_off[row + iw1 + 1];
+  for (int ipr = gr.ip0; ipr <= gr.ip1 && gr.iw0 <= gr.iw1; ++ipr) {
+    int a, b;
+    grid_row(g, Lr, gr, ipr, a, b);
     // two candidates per round: their id and record loads are in flight together
     for (int q = a; q < b; q += 2) {
       if (visited >= kMaxCand) {

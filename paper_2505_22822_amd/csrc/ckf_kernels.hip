@@ -211,6 +211,237 @@ __device__ bool better(int nmA, double chiA, int hoA, int nodeA, int nmB, double
 }
 
 
+// ---------------------------------------------------------------------------
+// wave-cooperative module listing
+//
+// The lanes of a wave that need a listing have grid rows of very different
+// lengths; listed one lane at a time, the wave walks its longest lane's rows
+// (a quarter of the lanes busy on average).  Here the wave flattens all its
+// lanes' rows into one sequence of grid entries and tests 64 entries per
+// pass, each for the lane that owns it; passing modules go to the owner's
+// slots in LDS and the owner keeps the kMaxList smallest (path, id).  The
+// entries a lane tests are exactly those its own walk would test (the first
+// kMaxCand in visiting order, counted in pairs), so the listing is the same.
+constexpr int kListRows = 128;  // grid rows of one wave-wide listing
+constexpr int kListRes = 6;     // passing modules kept per lane (more: the lane lists alone)
+
+struct ListShared {
+  int row_a[kListRows];        // first CSR entry of the row
+  int row_pre[kListRows + 1];  // entries of the rows before it (exclusive scan)
+  int row_own[kListRows];      // owning lane
+  int res_n[kWave];            // passing modules per lane
+  float res_s[kListRes][kWave];
+  int res_m[kListRes][kWave];
+};
+
+// Called by all lanes of the wave together; lanes with want == false take
+// part in the passes only.  Returns the number listed for this lane.
+// `passes` (uniform) is the number of 64-entry passes the wave made.
+template <bool kCount>
+__device__ int list_wave(const GeomDev& g, ListShared& S, bool want, int l, V3 P, V3 T, V3 k, float s_base,
+                         int exclude, float margin, int* list, int& n_tested, int& overflow, int& n_visited,
+                         int& passes, int* tested_cnt) {
+  const int lane = threadIdx.x;
+  GridRange gr{0, -1, 0, -1};
+  LayerRec Lr{};
+  bool ok = false;
+  if (want) {
+    Lr = g.layers[l];
+    ok = grid_range(Lr, P, T, gr);
+  }
+  int nr = (ok && gr.iw0 <= gr.iw1) ? gr.ip1 - gr.ip0 + 1 : 0;
+  // lanes whose rows do not fit list alone afterwards
+  int rtot;
+  int rbase = wave_excl_scan(nr, rtot);
+  bool alone = want && ok && rbase + nr > kListRows;
+  if (alone) nr = 0;
+  rbase = wave_excl_scan(nr, rtot);
+  // this lane's rows: the entries its own walk visits (pairs started
+  // before kMaxCand entries)
+  int ovf = 0, vis = 0, before = 0;
+  for (int j = 0; j < nr; ++j) {
+    int a, b;
+    grid_row(g, Lr, gr, gr.ip0 + j, a, b);
+    const int n = b - a;
+    const int take = before >= kMaxCand ? 0 : min(n, 2 * ((kMaxCand - before + 1) / 2));
+    if (take < n) ovf = 1;
+    vis += take;
+    before += n;
+    S.row_a[rbase + j] = a;
+    S.row_pre[rbase + j] = take;  // counts for now, prefixes below
+    S.row_own[rbase + j] = lane;
+  }
+  S.res_n[lane] = 0;
+  __syncthreads();
+  // exclusive prefix over the wave's rows (two rows per lane)
+  {
+    const int r0 = 2 * lane, r1 = 2 * lane + 1;
+    const int c0 = r0 < rtot ? S.row_pre[r0] : 0, c1 = r1 < rtot ? S.row_pre[r1] : 0;
+    int tot;
+    const int e = wave_excl_scan(c0 + c1, tot);
+    __syncthreads();
+    if (r0 < rtot) S.row_pre[r0] = e;
+    if (r1 < rtot) S.row_pre[r1] = e + c0;
+    if (lane == 0) S.row_pre[rtot] = tot;
+    __syncthreads();
+  }
+  const int total = S.row_pre[rtot];
+  passes = (total + kWave - 1) / kWave;
+  for (int c0 = 0; c0 < total; c0 += kWave) {
+    const int c = c0 + lane;
+    const bool act = c < total;
+    int own = 0, q = 0;
+    if (act) {  // the row holding entry c: the last row whose prefix is <= c
+      int lo = 0, hi = rtot - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S.row_pre[mid] <= c) lo = mid; else hi = mid - 1;
+      }
+      own = S.row_own[lo];
+      q = S.row_a[lo] + (c - S.row_pre[lo]);
+    }
+    // the owner's trajectory (all lanes take part in the exchange)
+    const V3 Po{__shfl(P.x, own), __shfl(P.y, own), __shfl(P.z, own)};
+    const V3 To{__shfl(T.x, own), __shfl(T.y, own), __shfl(T.z, own)};
+    const V3 ko{__shfl(k.x, own), __shfl(k.y, own), __shfl(k.z, own)};
+    const float sbo = __shfl(s_base, own);
+    const int exo = __shfl(exclude, own);
+    if (act) {
+      const int m = g.cell_mod[q];
+      if (m != exo) {
+        Module M;
+        load_module(g, m, M);
+        float cs;
+        bool tested;
+        if (list_probe(M, Po, To, ko, sbo, margin, cs, tested)) {
+          const int slot = atomicAdd(&S.res_n[own], 1);
+          if (slot < kListRes) {
+            S.res_s[slot][own] = cs;
+            S.res_m[slot][own] = m;
+          }
+        }
+        if (kCount && tested) atomicAdd(&tested_cnt[own], 1);
+      }
+    }
+  }
+  __syncthreads();
+  int nlist = 0;
+  if (want && ok) {
+    const int nres = S.res_n[lane];
+    if (!alone && nres <= kListRes) {
+      ListAcc acc;
+      list_init(acc);
+      for (int i = 0; i < nres; ++i) list_insert(acc, S.res_m[i][lane], S.res_s[i][lane]);
+      nlist = list_out(acc, list);
+      overflow |= ovf;
+      n_visited += vis;
+    } else {  // too many rows or passing modules for the shared slots
+      int nt_seen = 0;  // (entries already tested in the passes were counted there)
+      nlist = list_layer(g, l, P, T, k, s_base, exclude, margin, list, alone ? n_tested : nt_seen, overflow,
+                         n_visited);
+    }
+  }
+  if (want && !ok) {
+#pragma unroll
+    for (int q = 0; q < kMaxList; ++q) list[q] = -1;
+  }
+  __syncthreads();
+  return nlist;
+}
+
+// ---------------------------------------------------------------------------
+// wave-cooperative window scan
+//
+// Each crossing lane gates the measurements of its module inside its exact
+// loc0 window [l, e) (found by two binary searches on the sorted row).  The
+// windows differ in length from lane to lane, so the wave flattens them and
+// gates 64 measurements per pass, each against its owning lane's predicted
+// position and covariance; accepted ones go to the owner's slots in LDS and
+// the owner keeps the smallest (chi2, id).  Every measurement of a window is
+// gated exactly once, as in the lane's own scan, so the result is the same.
+constexpr int kWinRes = 4;  // accepted measurements kept per lane (more: the lane scans alone)
+
+struct WinShared {
+  int pre[kWave + 1];  // measurements of the lanes before (exclusive scan)
+  int start[kWave];    // first sorted position of the lane's window
+  int res_n[kWave];
+  double res_x2[kWinRes][kWave];
+  int res_id[kWinRes][kWave];
+  int res_pos[kWinRes][kWave];
+};
+
+// Insert an accepted measurement into a lane's kMaxBranch smallest (chi2, id).
+__device__ __forceinline__ void acc_insert(double* acc_x2, int* acc_id, int* acc_pos, double cx, int cid, int cpos) {
+#pragma unroll
+  for (int k = 0; k < kMaxBranch; ++k) {
+    const bool lt = cx < acc_x2[k] || (cx == acc_x2[k] && cid < acc_id[k]);
+    if (lt) {
+      const double tx = acc_x2[k];
+      const int ti = acc_id[k], tp = acc_pos[k];
+      acc_x2[k] = cx;
+      acc_id[k] = cid;
+      acc_pos[k] = cpos;
+      cx = tx;
+      cid = ti;
+      cpos = tp;
+    }
+  }
+}
+
+// Called by all lanes together.  A lane with n > 0 owns the window of n
+// sorted measurements from `start`, gated with (p0, p1) and the covariance
+// entries (c00, c01, c11).  Returns the number accepted (all of them, not
+// capped), or -1 when more than kWinRes were accepted (the lane then scans
+// alone); acc_* receive the smallest.  `passes` (uniform): 64-entry passes.
+__device__ int window_wave(WinShared& S, const Workspace& w, double chi2_max, int start, int n, double p0, double p1,
+                           double c00, double c01, double c11, double* acc_x2, int* acc_id, int* acc_pos,
+                           int& passes) {
+  const int lane = threadIdx.x;
+  int tot;
+  const int e = wave_excl_scan(n, tot);
+  S.pre[lane] = e;
+  S.start[lane] = start;
+  S.res_n[lane] = 0;
+  if (lane == 0) S.pre[kWave] = tot;
+  __syncthreads();
+  passes = (tot + kWave - 1) / kWave;
+  for (int c0 = 0; c0 < tot; c0 += kWave) {
+    const int c = c0 + lane;
+    const bool act = c < tot;
+    int own = 0;
+    if (act) {  // the last lane whose prefix is <= c
+      int lo = 0, hi = kWave - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S.pre[mid] <= c) lo = mid; else hi = mid - 1;
+      }
+      own = lo;
+    }
+    const double q0 = __shfl(p0, own), q1 = __shfl(p1, own);
+    const double d00 = __shfl(c00, own), d01 = __shfl(c01, own), d11 = __shfl(c11, own);
+    if (act) {
+      const int i = S.start[own] + (c - S.pre[own]);
+      const float4 ms = w.m_sorted[i];
+      const double pq[2] = {q0, q1}, cq[6] = {d00, d01, 0.0, 0.0, 0.0, d11};
+      const double x2 = chi2_of(pq, cq, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w);
+      if (x2 < chi2_max) {
+        const int slot = atomicAdd(&S.res_n[own], 1);
+        if (slot < kWinRes) {
+          S.res_x2[slot][own] = x2;
+          S.res_id[slot][own] = w.m_id[i];
+          S.res_pos[slot][own] = i;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int nres = S.res_n[lane];
+  if (n > 0 && nres <= kWinRes)
+    for (int k = 0; k < nres; ++k) acc_insert(acc_x2, acc_id, acc_pos, S.res_x2[k][lane], S.res_id[k][lane], S.res_pos[k][lane]);
+  __syncthreads();
+  return nres <= kWinRes ? nres : -1;
+}
+
 constexpr int kMaxSlots = 64;
 
 // kCount: the instrumented variant that accumulates the work-unit counters
@@ -231,10 +462,23 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   __shared__ unsigned short sh_x[kLearned ? kWave * 8 : 1];  // network inputs (bf16), one row per lane
   // phase 4 work list: per output slot of a pass its parent lane and branch;
   // per parent lane its child count, node offset and accepted measurements
-  __shared__ int sh_item[kWave * kMaxBranch];
-  __shared__ int sh_kind[kWave], sh_noff[kWave];
-  __shared__ int sh_acc_pos[kMaxBranch][kWave], sh_acc_id[kMaxBranch][kWave];
-  __shared__ double sh_acc_x2[kMaxBranch][kWave];
+  // (the listing's LDS is only used during navigation: the two share space)
+  __shared__ union {
+    struct {
+      int item[kWave * kMaxBranch];
+      int kind[kWave], noff[kWave];
+      int acc_pos[kMaxBranch][kWave], acc_id[kMaxBranch][kWave];
+      double acc_x2[kMaxBranch][kWave];
+    } o;
+    ListShared l;
+    WinShared w;
+  } sh_u;
+  auto& sh_item = sh_u.o.item;
+  auto& sh_kind = sh_u.o.kind;
+  auto& sh_noff = sh_u.o.noff;
+  auto& sh_acc_pos = sh_u.o.acc_pos;
+  auto& sh_acc_id = sh_u.o.acc_id;
+  auto& sh_acc_x2 = sh_u.o.acc_x2;
 
   const CfgDev& cfg = A.cfg;
   const int lane = lane_id();
@@ -357,6 +601,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       bool moved = false;
       float J[5][5];
       int c_list = 0, c_next = 0, c_land = 0, c_win = 0;  // loop iterations of this lane (instrumented run)
+      int c_list_passes = 0, c_win_passes = 0;             // the wave's listing and window passes
       long long t_phase = kCount ? clock64() : 0;
       if (kCount && lane == 0) CNT_ADD(CKF_CNT_CHUNKS, 1);
 
@@ -379,6 +624,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       long long t_nav = 0;
       int prop[3] = {-1, -1, -1};
       bool confident = false;
+      V3 kl{0.f, 0.f, 0.f};
       auto stage_a = [&]() {
         CNT_ADD(CKF_CNT_STEPS, 1);
 #pragma unroll
@@ -445,6 +691,8 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             }
           }
         }
+        // the listing's curvature term at its base point
+        if (need_list) kl = (kKappa * L.lam) * cross(Tl, field_at<kMap>(A.f, Pl));
       };
       // learned proposal: the network for every lane that found a next layer
       // listed in its module's neighbour table, 16 rows per MFMA pass
@@ -497,16 +745,12 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           }
         }
       };
-      auto stage_b = [&]() {
-        if (kLearned) {
-          // recomputed rather than kept in registers across the network
-          load_module(g, surf, Am);
-          leg_start(Am, p, L, uA, vA);
-          origin = ld3(Am.c);
-        }
+      // stage B1: the learned proposal's listing (confident lanes); which
+      // lanes still need the geometric listing
+      bool want_geo = false;
+      int nt = 0, ovf = 0;
+      auto stage_b1 = [&]() {
         if (need_list) {
-          const V3 kl = (kKappa * L.lam) * cross(Tl, field_at<kMap>(A.f, Pl));
-          int nt = 0, ovf = 0;
           bool listed = false;
           if (kLearned && confident) {
             // the proposed modules through the same listing test
@@ -539,7 +783,28 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
               }
             }
           }
-          if (!listed) nlist = list_layer(g, lay, Pl, Tl, kl, sb, excl, margin, list, nt, ovf, c_list);
+          want_geo = !listed;
+        }
+      };
+      // the geometric listing, all lanes of the wave together
+      auto listing = [&]() {
+        int passes = 0;
+        const int nl_geo = list_wave<kCount>(g, sh_u.l, act && want_geo, lay, Pl, Tl, kl, sb, excl, margin, list,
+                                             nt, ovf, c_list, passes,
+                                             kCount ? &sh_cnt[CNT_IDX(CKF_CNT_NAV_MODULES)][0] : nullptr);
+        if (act && want_geo) nlist = nl_geo;
+        if (kCount && lane == 0) c_list_passes += passes;
+      };
+      // stage B2: the leg to the next listed module.  The start state is
+      // rebuilt from the record rather than kept in registers across the
+      // network and the listing.
+      auto stage_b2 = [&]() {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
+        load_module(g, surf, Am);
+        leg_start(Am, p, L, uA, vA);
+        origin = ld3(Am.c);
+        if (need_list) {
           CNT_ADD(CKF_CNT_NAV_MODULES, nt);
           CNT_ADD(kNavOvf, ovf);
           if (!root && nlist == 0) {
@@ -596,15 +861,12 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         PFr(Pin, r, PF_H) = h;
         PFr(Pin, r, PF_PATH) = path;
       };
-      if (kLearned) {
-        // the network runs with all lanes together between the two stages
-        if (act) stage_a();
-        proposal();
-        if (act) stage_b();
-      } else if (act) {
-        stage_a();
-        stage_b();
-      }
+      if (act) stage_a();
+      // the network runs with all lanes together between the stages
+      if (kLearned) proposal();
+      if (act) stage_b1();
+      listing();
+      if (act) stage_b2();
 
       if (kCount && lane == 0) {
         const long long t = clock64();
@@ -622,76 +884,99 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         acc_pos[k] = 0;
       }
       int n_acc = 0;
+      // phase 2a (per lane): the covariance transport, stored back into the
+      // record, and the crossing lanes' exact loc0 windows
+      int w_start = 0, w_n = 0, surf2 = -1;
+      double g0 = 0.0, g1 = 0.0, k00 = 0.0, k01 = 0.0, k11 = 0.0;
       if (outcome == 1 || outcome == 2) {
         double C[15];
         load_cov(Pin, r, C);
-        if (moved) transport_cov(J, C);
-        bool changed = moved;
+        if (moved) {
+          transport_cov(J, C);
+#pragma unroll
+          for (int k = 0; k < 15; ++k) PDr(Pin, r, (PD_C + k)) = C[k];
+        }
         if (outcome == 2) {
           CNT_ADD(CKF_CNT_CROSSED, 1);
-          double p[5];
-#pragma unroll
-          for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
-          const int surf = PIr(Pin, r, PI_SURF);
-          const int row = sh_event[slot] * g.n_surfaces + surf;
+          g0 = PDr(Pin, r, PD_P + 0);
+          g1 = PDr(Pin, r, PD_P + 1);
+          k00 = C[0];
+          k01 = C[1];
+          k11 = C[5];
+          surf2 = PIr(Pin, r, PI_SURF);
+          const int row = sh_event[slot] * g.n_surfaces + surf2;
           const int a = A.m.offsets[row], b = A.m.offsets[row + 1];
           if (b > a) {
             const double wd = sqrt(cfg.chi2_max * (C[0] + (double)A.w.row_maxvar0[row]));
-            const float lo = (float)(p[0] - wd) - 1e-3f, hi = (float)(p[0] + wd) + 1e-3f;
+            const float lo = (float)(g0 - wd) - 1e-3f, hi = (float)(g0 + wd) + 1e-3f;
             int l = a, u = b;
             while (l < u) {  // first position with loc0 >= lo
               const int mid = (l + u) >> 1;
               if (A.w.m_sorted[mid].x < lo) l = mid + 1; else u = mid;
             }
-            // measurements in loc0 order until past the window; the next
-            // record is loaded before the current one is gated, so two loads
-            // are in flight (the order of the visits is unchanged)
-            float4 ms = l < b ? A.w.m_sorted[l] : make_float4(INFINITY, 0.f, 0.f, 0.f);
-            for (int i = l; i < b; ++i) {
-              const float4 nx = i + 1 < b ? A.w.m_sorted[i + 1] : make_float4(INFINITY, 0.f, 0.f, 0.f);
-              ++c_win;
-              if (ms.x > hi) break;
-              CNT_ADD(CKF_CNT_CHI2, 1);
-              const double x2 = chi2_of(p, C, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w);
-              if (x2 < cfg.chi2_max) {
-                double cx = x2;
-                int cid = A.w.m_id[i], cpos = i;
-#pragma unroll
-                for (int k = 0; k < kMaxBranch; ++k) {
-                  const bool lt = cx < acc_x2[k] || (cx == acc_x2[k] && cid < acc_id[k]);
-                  if (lt) {
-                    const double tx = acc_x2[k];
-                    const int ti = acc_id[k], tp = acc_pos[k];
-                    acc_x2[k] = cx;
-                    acc_id[k] = cid;
-                    acc_pos[k] = cpos;
-                    cx = tx;
-                    cid = ti;
-                    cpos = tp;
-                  }
-                }
-                n_acc = min(n_acc + 1, cfg.branches);
-              }
-              ms = nx;
+            int l2 = l, u2 = b;
+            while (l2 < u2) {  // first position with loc0 > hi
+              const int mid = (l2 + u2) >> 1;
+              if (A.w.m_sorted[mid].x <= hi) l2 = mid + 1; else u2 = mid;
             }
-          }
-          if (n_acc == 0) {  // a hole
-            CNT_ADD(CKF_CNT_HOLES, 1);
-            const int nmh = PIr(Pin, r, PI_NMH) + (1 << 16);
-            PIr(Pin, r, PI_NMH) = nmh;
-            if (cfg.material) {
-              Module M;
-              load_module(g, surf, M);
-              apply_ms(M, cfg.mass, p, C);
-              CNT_ADD(CKF_CNT_MS, 1);
-              changed = true;
-            }
-            outcome = (nmh >> 16) > cfg.max_holes ? 3 : 1;
+            w_start = l;
+            w_n = l2 - l;
+            CNT_ADD(CKF_CNT_CHI2, w_n);
           }
         }
-        if (changed)
+      }
+      // phase 2b (the wave together): the windows' gates
+      {
+        int passes = 0;
+        n_acc = window_wave(sh_u.w, A.w, cfg.chi2_max, w_start, w_n, g0, g1, k00, k01, k11, acc_x2, acc_id,
+                            acc_pos, passes);
+        if (kCount) {
+          c_win = w_n;
+          if (lane == 0) c_win_passes += passes;
+        }
+      }
+      // phase 2c (per lane): a lane with more accepted measurements than the
+      // shared slots scans its window alone; holes
+      if (outcome == 2) {
+        if (n_acc < 0) {
+          n_acc = 0;
 #pragma unroll
-          for (int k = 0; k < 15; ++k) PDr(Pin, r, (PD_C + k)) = C[k];
+          for (int k = 0; k < kMaxBranch; ++k) {
+            acc_x2[k] = INFINITY;
+            acc_id[k] = 0x7fffffff;
+            acc_pos[k] = 0;
+          }
+          for (int i = w_start; i < w_start + w_n; ++i) {
+            const float4 ms = A.w.m_sorted[i];
+            const double pq[2] = {g0, g1}, cq[6] = {k00, k01, 0.0, 0.0, 0.0, k11};
+            const double x2 = chi2_of(pq, cq, (double)ms.x, (double)ms.y, (double)ms.z, (double)ms.w);
+            if (x2 < cfg.chi2_max) {
+              acc_insert(acc_x2, acc_id, acc_pos, x2, A.w.m_id[i], i);
+              ++n_acc;
+            }
+          }
+        }
+        n_acc = min(n_acc, cfg.branches);
+        if (n_acc == 0) {  // a hole
+          CNT_ADD(CKF_CNT_HOLES, 1);
+          const int nmh = PIr(Pin, r, PI_NMH) + (1 << 16);
+          PIr(Pin, r, PI_NMH) = nmh;
+          if (cfg.material) {
+            double p[5], C[15];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
+            load_cov(Pin, r, C);
+            Module M;
+            load_module(g, surf2, M);
+            apply_ms(M, cfg.mass, p, C);
+            CNT_ADD(CKF_CNT_MS, 1);
+#pragma unroll
+            for (int k = 0; k < 15; ++k) PDr(Pin, r, (PD_C + k)) = C[k];
+          }
+          outcome = (nmh >> 16) > cfg.max_holes ? 3 : 1;
+        }
+      } else {
+        n_acc = 0;
       }
 
       if (kCount && lane == 0) {
@@ -704,12 +989,12 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         CNT_ADD(CKF_CNT_NEXT_LANE, c_next);
         CNT_ADD(CKF_CNT_LAND_LANE, c_land);
         CNT_ADD(CKF_CNT_WIN_LANE, c_win);
-        const int m0 = wave_max(c_list), m1 = wave_max(c_next), m2 = wave_max(c_land), m3 = wave_max(c_win);
+        const int m1 = wave_max(c_next), m2 = wave_max(c_land);
         if (lane == 0) {
-          CNT_ADD(CKF_CNT_LIST_WAVE, m0);
+          CNT_ADD(CKF_CNT_LIST_WAVE, c_list_passes);
           CNT_ADD(CKF_CNT_NEXT_WAVE, m1);
           CNT_ADD(CKF_CNT_LAND_WAVE, m2);
-          CNT_ADD(CKF_CNT_WIN_WAVE, m3);
+          CNT_ADD(CKF_CNT_WIN_WAVE, c_win_passes);
         }
       }
       // ---- phase 3: slots for the outputs (wave scan) and history nodes
