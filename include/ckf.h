@@ -397,6 +397,25 @@ ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurem
                    int32_t smoother, void* workspace, size_t workspace_bytes, double* params, double* cov,
                    double* chi2, int32_t* ok, void* stream);
 
+/* ckf_fit without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, outputs and errors as ckf_fit
+ * minus the workspace: the fit's per-measurement records live in a fixed
+ * device array of the library, ckf_fit_noalloc_max_bytes() = 64 MiB per GPU
+ * (allocated when the library's code is loaded on a GPU and held until the
+ * process ends), enough for ckf_fit_noalloc_max_meas() = 220,752
+ * measurements; a larger cap_meas fails with CKF_ERR_CAPACITY and launches
+ * nothing.  The call itself allocates nothing.  All calls on one GPU share
+ * that array: calls that can overlap on one GPU (different streams, or
+ * different host threads) race and must be ordered by the caller. */
+ckf_status ckf_fit_noalloc(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m,
+                           const ckf_seeds* s, const ckf_config* cfg, const int32_t* n_tracks, int32_t cap_tracks,
+                           int64_t cap_meas, const int32_t* offsets, const int32_t* meas,
+                           const int32_t* meas_surface, const int32_t* seed, int32_t smoother, double* params,
+                           double* cov, double* chi2, int32_t* ok, void* stream);
+size_t ckf_fit_noalloc_max_bytes(void);
+int64_t ckf_fit_noalloc_max_meas(void);
+
 /* Activated detector cells (device memory) in readout order: grouped by
  * (event, module) row like the measurements, then by row c1 and column c0
  * inside a module (strictly increasing (c1, c0) within a module). */

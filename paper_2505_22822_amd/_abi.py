@@ -92,6 +92,10 @@ SIGNATURES = {
     "ckf_fit_workspace_size": (I32, [I64, C.POINTER(C.c_size_t)]),
     "ckf_fit": (I32, [VP, VP, C.POINTER(Measurements), C.POINTER(Seeds), C.POINTER(Config), VP, I32, I64, VP, VP,
                       VP, VP, I32, VP, C.c_size_t, VP, VP, VP, VP, VP]),
+    "ckf_fit_noalloc": (I32, [VP, VP, C.POINTER(Measurements), C.POINTER(Seeds), C.POINTER(Config), VP, I32, I64,
+                              VP, VP, VP, VP, I32, VP, VP, VP, VP, VP]),
+    "ckf_fit_noalloc_max_bytes": (C.c_size_t, []),
+    "ckf_fit_noalloc_max_meas": (I64, []),
     "ckf_cluster_workspace_size": (I32, [C.POINTER(CellsDesc), C.POINTER(C.c_size_t)]),
     "ckf_cluster": (I32, [VP, C.POINTER(CellsDesc), VP, VP, C.c_size_t, VP, VP, VP, VP, VP, VP, VP]),
     "ckf_seed_workspace_size": (I32, [I32, I32, I64, I32, C.POINTER(C.c_size_t)]),

@@ -934,6 +934,28 @@ ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurem
   return CKF_OK;
 }
 
+ckf_status ckf_fit_noalloc(const ckf_geometry* g, const ckf_field* f, const ckf_measurements* m,
+                           const ckf_seeds* s, const ckf_config* cfg, const int32_t* n_tracks, int32_t cap_tracks,
+                           int64_t cap_meas, const int32_t* offsets, const int32_t* meas,
+                           const int32_t* meas_surface, const int32_t* seed, int32_t smoother, double* params,
+                           double* cov, double* chi2, int32_t* ok, void* stream) {
+  if (cap_meas < 0) return fail(CKF_ERR_INVALID_ARGUMENT, "fit_noalloc: negative capacity");
+  if (ckf::fit_workspace_bytes(cap_meas) > ckf_fit_noalloc_max_bytes())
+    return fail(CKF_ERR_CAPACITY, "fit_noalloc: cap_meas " + std::to_string(cap_meas) + " exceeds the scratch limit of " +
+                                      std::to_string(ckf_fit_noalloc_max_meas()) + " measurements");
+  void* scratch = nullptr;
+  size_t bytes = 0;
+  HIP_TRY(ckf::fit_scratch(&scratch, &bytes), "hipGetSymbolAddress(fit scratch)");
+  return ckf_fit(g, f, m, s, cfg, n_tracks, cap_tracks, cap_meas, offsets, meas, meas_surface, seed, smoother,
+                 scratch, bytes, params, cov, chi2, ok, stream);
+}
+
+size_t ckf_fit_noalloc_max_bytes(void) { return size_t(64) << 20; }
+
+int64_t ckf_fit_noalloc_max_meas(void) {
+  return (int64_t)(ckf_fit_noalloc_max_bytes() / ckf::fit_workspace_bytes(1));
+}
+
 ckf_status ckf_cluster_workspace_size(const ckf_cells* c, size_t* bytes) {
   if (!c || !bytes || c->n_events < 0 || c->n_surfaces < 0 || c->n_cells < 0)
     return fail(CKF_ERR_INVALID_ARGUMENT, "cluster_workspace_size: bad argument");

@@ -27,6 +27,8 @@
 //               C = (C_f^-1 + Y)^-1, x = x_f + C y (two Cholesky
 //               factorisations); each measurement then adds H^T V^-1 H
 //               and H^T V^-1 (m - H x_f).
+#include <mutex>
+
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
 
@@ -41,6 +43,35 @@ struct alignas(16) Rec {
 static_assert(sizeof(Rec) == 304, "fit record layout");
 
 size_t fit_workspace_bytes(long long cap_meas) { return (size_t)cap_meas * sizeof(Rec); }
+
+// The fit's records for callers that cannot allocate: one file-scope device
+// array per GPU, held until the process ends.  Every call on a GPU shares it
+// (calls that overlap on one GPU race); the forward pass writes each record
+// before the smoother reads it, so nothing needs clearing between calls.
+constexpr size_t kFitScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kFitScratchBytes];
+
+hipError_t fit_scratch(void** ptr, size_t* bytes) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    // the device address of this GPU's copy (the array's name is a host
+    // stand-in, not a device address)
+    e = hipGetSymbolAddress(&addr[dev], HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      addr[dev] = nullptr;
+      return e;
+    }
+  }
+  *ptr = addr[dev];
+  *bytes = kFitScratchBytes;
+  return hipSuccess;
+}
 
 namespace {
 

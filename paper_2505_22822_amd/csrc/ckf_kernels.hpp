@@ -64,6 +64,10 @@ hipError_t launch_capture_pairs(const GeomDev& g, const FieldDev& f, const int* 
                                 const int* msurf, const double* mpar, long long cap_pairs, float* x, int* label,
                                 int* track, long long* counts, void* ws, hipStream_t st);
 size_t fit_workspace_bytes(long long cap_meas);
+constexpr int kMaxDevices = 64;
+// Device address and size of this GPU's fit scratch array (looked up once per
+// device, on the first call with that device current).
+hipError_t fit_scratch(void** ptr, size_t* bytes);
 size_t seed_workspace_bytes(long long rows, long long n_sp, int n_events, int n_layers);
 int seed_top_cap_max();
 long long seed_bin_count(int n_events, int n_layers);  // (event, layer, phi bin, z bin) bins
