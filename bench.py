@@ -403,9 +403,10 @@ def kept_tracks(r, keep):
     return dict(n_tracks=len(k), offsets=off, meas=r["meas"][idx], seed=r["seed"][k])
 
 
-def measure_resolve(ckf, finder, ev, stream, reps=3):
-    """Ambiguity resolution of a finder's tracks: wall time of the
-    (synchronous) call, rounds, removed tracks, fake and duplicate rates and
+def measure_resolve(ckf, finder, ev, stream, reps=3, max_rounds=8):
+    """Ambiguity resolution of a finder's tracks: wall time of the call (its
+    rounds run on the device, bounded by max_rounds, with no host
+    synchronisation), rounds, removed tracks, fake and duplicate rates and
     efficiency before and after."""
     import torch
     r = finder.result()
@@ -418,7 +419,7 @@ def measure_resolve(ckf, finder, ev, stream, reps=3):
     for _ in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        keep, rounds = ckf.resolve(finder.out, ev.n_meas, stream=stream, workspace=ws)
+        keep, rounds = ckf.resolve(finder.out, ev.n_meas, stream=stream, workspace=ws, max_rounds=max_rounds)
         torch.cuda.synchronize()
         times.append((time.perf_counter() - t0) * 1e3)
     keep = keep.cpu().numpy()
@@ -427,8 +428,9 @@ def measure_resolve(ckf, finder, ev, stream, reps=3):
                 removed=int(np.sum(keep[:r["n_tracks"]] == 0)), before=before, after=after,
                 efficiency_before=round(efficiency(ev, r), 5), efficiency_after=round(efficiency(ev, kept_tracks(r, keep)), 5),
                 traffic=_measured(RESOLVE_TRAFFIC, (int(r["n_tracks"]), int(r["offsets"][r["n_tracks"]]))),
-                note="wall time of the synchronous call (one stream synchronisation per round); traffic: HBM bytes "
-                     "of its kernels (counters)")
+                max_rounds=max_rounds,
+                note="wall time of one call and its synchronisation (the rounds run on the device, unused ones "
+                     "return at once); traffic: HBM bytes of its kernels (counters)")
 
 
 def measure_cluster(ckf, geo, det, cells, stream, reps):

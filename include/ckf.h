@@ -63,6 +63,8 @@ enum {
 };
 #define CKF_FLAG_NODE_CAPACITY 1  /* workspace history too small: retry larger */
 #define CKF_FLAG_OUT_CAPACITY 2   /* output arrays too small: retry larger */
+#define CKF_FLAG_FIN_CAPACITY 8   /* tracks_per_seed = 0: more than 64 finished candidates per seed on
+                                     average (the excess is lost; the output is incomplete) */
 #define CKF_FLAG_BAD_OFFSETS 4    /* measurement offsets that do not tile [0, n_meas): offsets[0] != 0,
                                      a decreasing pair, or offsets[last] != n_meas (nothing is searched) */
 
@@ -142,7 +144,9 @@ typedef struct ckf_config {
   double nav_margin;            /* mm, margin of the module-listing test (<= 2) */
   double mass;                  /* GeV, particle hypothesis for scattering */
   int32_t material_on;          /* apply multiple scattering */
-  int32_t tracks_per_seed;      /* must be 1: the best finished candidate per seed */
+  int32_t tracks_per_seed;      /* 1: the best finished candidate per seed; 0: every finished candidate
+                                   with at least min_meas measurements (ordered within a seed by the rank
+                                   key), for tests; the workspace then holds up to 64 per seed */
   double learned_min_prob;      /* learned proposal: used when its top-k probabilities sum to at least this */
   int32_t learned_topk;         /* learned proposal: modules tested (1..3) */
 } ckf_config;
@@ -173,7 +177,8 @@ typedef struct ckf_seeds {
 } ckf_seeds;
 
 /* Output (device memory, caller-allocated).  Tracks are ordered by seed
- * index, at most one per seed. */
+ * index: at most one per seed, or with tracks_per_seed = 0 every finished
+ * candidate of the seed in rank-key order (best first). */
 typedef struct ckf_tracks {
   int32_t cap_tracks;        /* capacity of the per-track arrays (n_seeds suffices) */
   int64_t cap_meas;          /* capacity of meas */
@@ -511,17 +516,21 @@ ckf_status ckf_seed_set_top_cap(int32_t cap, int32_t* cap_max);
  * most cap_tracks used), offsets [cap_tracks+1] into meas [cap_meas],
  * chi2 and ndf [cap_tracks]; measurement ids must lie in [0, n_meas).
  * keep [cap_tracks] (device) receives 1 kept, 0 removed, -1 for a track
- * whose offsets or ids are out of range (it takes no part).  rounds (host,
- * may be NULL) receives the number of parallel rounds.  workspace: at least
+ * whose offsets or ids are out of range (it takes no part).  The rounds run
+ * on the device: max_rounds (1..1024) of them are launched, and once no bad
+ * track is left the remaining ones return at once.  info (device int32[2],
+ * or NULL) receives the rounds that removed tracks and 1 if no bad track is
+ * left (0: max_rounds did not suffice and the result is a prefix of the
+ * greedy; call again with a larger bound).  workspace: at least
  * ckf_resolve_workspace_size(cap_tracks, n_meas) bytes (CKF_ERR_CAPACITY if
- * smaller).  SYNCHRONOUS: the call waits on `stream` once per round (it
- * reads the number of bad tracks); it allocates nothing.  n_meas above
- * 2^31 - 1 gives CKF_ERR_NOT_SUPPORTED. */
+ * smaller).  Asynchronous on `stream` with no host synchronisation, so it can
+ * be captured in a graph; it allocates nothing.  n_meas above 2^31 - 1 gives
+ * CKF_ERR_NOT_SUPPORTED. */
 ckf_status ckf_resolve_workspace_size(int32_t cap_tracks, int64_t n_meas, size_t* bytes);
 ckf_status ckf_resolve(const int32_t* n_tracks, int32_t cap_tracks, int64_t cap_meas, const int32_t* offsets,
                        const int32_t* meas, int64_t n_meas, const double* chi2, const int32_t* ndf,
-                       int32_t max_shared, void* workspace, size_t workspace_bytes, int32_t* keep, int32_t* rounds,
-                       void* stream);
+                       int32_t max_shared, int32_t max_rounds, void* workspace, size_t workspace_bytes, int32_t* keep,
+                       int32_t* info, void* stream);
 
 /* Device workspace of ckf_capture_pairs for cap_tracks tracks: bytes it needs. */
 ckf_status ckf_capture_workspace_size(int32_t cap_tracks, size_t* bytes);

@@ -311,7 +311,7 @@ class Finder:
     one batch shape, so the timed call allocates nothing."""
 
     def __init__(self, geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, counters=True,
-                 model: "Model" = None, meas_states=False, seed_flags=False):
+                 model: "Model" = None, meas_states=False, seed_flags=False, tracks_per_seed_cap=None):
         import torch
         self.geometry, self.field, self.batch, self.model = geometry, field, batch, model
         self.cfg = cfg if cfg is not None else config()
@@ -322,7 +322,10 @@ class Finder:
         _check(lib.ckf_workspace_size(geometry.handle, C.byref(self.cfg), C.byref(self.launch), batch.n_events,
                                       batch.n_seeds, batch.n_meas, C.byref(nb)), "ckf_workspace_size")
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
-        n = max(1, batch.n_seeds)
+        # output capacity: one track per seed, or (tracks_per_seed = 0, every
+        # finished candidate) tracks_per_seed_cap per seed
+        per_seed = 1 if self.cfg.tracks_per_seed == 1 else int(tracks_per_seed_cap or 64)
+        n = max(1, batch.n_seeds) * per_seed
         cap_m = n * int(self.cfg.max_steps)
         z = lambda shape, dt: torch.zeros(shape, dtype=dt, device=dev)
         self.out = dict(n_tracks=z(1, torch.int32), offsets=z(n + 1, torch.int32), meas=z(cap_m, torch.int32),
@@ -332,7 +335,7 @@ class Finder:
                         counters=z(len(COUNTER_NAMES), torch.int64) if counters else None,
                         meas_surface=z(cap_m, torch.int32) if meas_states else None,
                         meas_params=z((cap_m, 5), torch.float64) if meas_states else None,
-                        seed_flags=z(n, torch.int32) if seed_flags else None)
+                        seed_flags=z(max(1, batch.n_seeds), torch.int32) if seed_flags else None)
         o = self.out
         self._tracks = _abi.Tracks(n, cap_m, *(_ptr(o[k]) for k in
                                               ("n_tracks", "offsets", "meas", "params", "cov", "chi2", "ndf",
@@ -590,11 +593,15 @@ def seed_top_cap(cap=None):
     return int(mx.value)
 
 
-def resolve(tracks: dict, n_meas: int, max_shared=1, stream=None, workspace=None):
+def resolve(tracks: dict, n_meas: int, max_shared=1, stream=None, workspace=None, max_rounds=128, info=None,
+            sync=True):
     """Greedy ambiguity resolution (ckf_resolve) of found tracks held as
     device tensors in ckf_find's layout (n_tracks, offsets, meas, chi2, ndf;
-    a Finder's .out).  Returns (keep device tensor [cap_tracks] int32:
-    1 kept, 0 removed, -1 invalid; number of parallel rounds).  Synchronous."""
+    a Finder's .out).  The call itself is asynchronous (its rounds run on the
+    device); with sync=True this waits and returns (keep device tensor
+    [cap_tracks] int32: 1 kept, 0 removed, -1 invalid; rounds that removed
+    tracks), raising if max_rounds did not suffice.  With sync=False it
+    returns (keep, info device tensor [2]: rounds, converged)."""
     import torch
     lib = _abi.load()
     dev = tracks["offsets"].device
@@ -605,13 +612,20 @@ def resolve(tracks: dict, n_meas: int, max_shared=1, stream=None, workspace=None
         _check(lib.ckf_resolve_workspace_size(cap_tracks, int(n_meas), C.byref(nb)), "ckf_resolve_workspace_size")
         workspace = torch.empty(max(1, int(nb.value)), dtype=torch.uint8, device=dev)
     keep = torch.zeros(max(1, cap_tracks), dtype=torch.int32, device=dev)
-    rounds = C.c_int32(0)
+    if info is None:
+        info = torch.zeros(2, dtype=torch.int32, device=dev)
     _settle(dev)
     _check(lib.ckf_resolve(_ptr(tracks["n_tracks"]), cap_tracks, cap_meas, _ptr(tracks["offsets"]),
                            _ptr(tracks["meas"]), int(n_meas), _ptr(tracks["chi2"]), _ptr(tracks["ndf"]),
-                           int(max_shared), _ptr(workspace), workspace.numel(), _ptr(keep), C.byref(rounds),
-                           _stream_handle(stream)), "ckf_resolve")
-    return keep[:cap_tracks], int(rounds.value)
+                           int(max_shared), int(max_rounds), _ptr(workspace), workspace.numel(), _ptr(keep),
+                           _ptr(info), _stream_handle(stream)), "ckf_resolve")
+    if not sync:
+        return keep[:cap_tracks], info
+    torch.cuda.synchronize()
+    r, conv = (int(x) for x in info.cpu())
+    if not conv:
+        raise CkfError(3, f"ckf_resolve: {max_rounds} rounds did not remove every bad track")
+    return keep[:cap_tracks], r
 
 
 def find(geometry: Geometry, field, batch: Batch, cfg=None, launch_cfg=None, stream=None, retries=3, model=None,

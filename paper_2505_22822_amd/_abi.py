@@ -102,7 +102,7 @@ SIGNATURES = {
     "ckf_seed": (I32, [VP, I32, VP, I64, VP, VP, VP, I32, F64, VP, C.c_size_t, I64, VP, VP, VP, VP, VP, VP, VP]),
     "ckf_seed_set_top_cap": (I32, [I32, C.POINTER(I32)]),
     "ckf_resolve_workspace_size": (I32, [I32, I64, C.POINTER(C.c_size_t)]),
-    "ckf_resolve": (I32, [VP, I32, I64, VP, VP, I64, VP, VP, I32, VP, C.c_size_t, VP, C.POINTER(I32), VP]),
+    "ckf_resolve": (I32, [VP, I32, I64, VP, VP, I64, VP, VP, I32, I32, VP, C.c_size_t, VP, VP, VP]),
     "ckf_capture_workspace_size": (I32, [I32, C.POINTER(C.c_size_t)]),
     "ckf_capture_pairs": (I32, [VP, VP, VP, I32, VP, VP, VP, I64, VP, VP, VP, VP, VP, C.c_size_t, VP]),
     "ckf_status_string": (C.c_char_p, [I32]),

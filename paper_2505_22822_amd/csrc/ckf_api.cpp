@@ -337,7 +337,8 @@ ckf_status check_config(const ckf_config* c) {
   if (c->max_live_per_seed < 1 || c->max_live_per_seed * c->branches_per_surface > 64)
     return fail(CKF_ERR_NOT_SUPPORTED, "max_live_per_seed * branches_per_surface must be 1..64 on the GPU");
   if (c->max_steps > ckf::kMaxSteps) return fail(CKF_ERR_NOT_SUPPORTED, "max_steps must be <= 64");
-  if (c->tracks_per_seed != 1) return fail(CKF_ERR_NOT_SUPPORTED, "tracks_per_seed must be 1 on the GPU");
+  if (c->tracks_per_seed != 0 && c->tracks_per_seed != 1)
+    return fail(CKF_ERR_NOT_SUPPORTED, "tracks_per_seed must be 1 (best) or 0 (all finished) on the GPU");
   if (c->nav_margin > ckf::kMaxNavMargin) return fail(CKF_ERR_NOT_SUPPORTED, "nav_margin must be <= 2 mm");
   if (!(c->learned_min_prob >= 0) || c->learned_topk < 1 || c->learned_topk > 3)
     return fail(CKF_ERR_INVALID_ARGUMENT, "learned_min_prob must be >= 0 and learned_topk 1..3");
@@ -362,6 +363,7 @@ ckf::CfgDev to_dev(const ckf_config* c) {
   d.material = c->material_on != 0;
   d.min_prob = (float)c->learned_min_prob;
   d.topk = c->learned_topk;
+  d.all_tracks = c->tracks_per_seed == 0;
   return d;
 }
 
@@ -374,6 +376,7 @@ int device_cus() {
 
 constexpr int kDefaultSeedsPerGroup = 48;
 constexpr int kNodesPerSeed = 32;
+constexpr int kFinPerSeed = 64;  // finished candidates kept per seed on average (tracks_per_seed = 0)
 
 ckf::Launch resolve_launch(const ckf_config* c, const ckf_launch* l, int n_seeds) {
   ckf::Launch r;
@@ -389,12 +392,13 @@ ckf::Launch resolve_launch(const ckf_config* c, const ckf_launch* l, int n_seeds
 }
 
 struct Layout {
-  size_t off_sorted, off_id, off_rowof, off_maxv, off_nodes, off_nodecnt, off_queue, off_res_node,
-      off_res_nm, off_res_holes, off_res_chi2, off_scan_a, off_scan_b, off_pools, total;
-  long long node_cap;
+  size_t off_sorted, off_key, off_id, off_rowof, off_maxv, off_nodes, off_nodecnt, off_queue, off_res_node,
+      off_res_nm, off_res_holes, off_res_chi2, off_scan_a, off_scan_b, off_pools, off_fin_seed, off_fin_node,
+      off_fin_nmh, off_fin_chi2, off_fin_count, off_seed_cnt, off_seed_meas, off_seed_fill, off_fin_order, total;
+  long long node_cap, fin_cap;
 };
 
-Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, long long n_meas) {
+Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, long long n_meas, bool all_tracks) {
   Layout o;
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -407,6 +411,7 @@ Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, l
   const size_t ns = (size_t)std::max(1, n_seeds);
   o.node_cap = (long long)ns * L.nodes_per_seed + 1024;
   o.off_sorted = take(nm * 16);
+  o.off_key = take(nm * 4);
   o.off_id = take(nm * 4);
   o.off_rowof = take(nm * 4);
   o.off_maxv = take(rows * 4);
@@ -421,6 +426,18 @@ Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, l
   o.off_scan_a = take(nb * 4);
   o.off_scan_b = take(nb * 4);
   o.off_pools = take((size_t)L.grid * 2 * L.pool_cap * ckf::kRecStride);
+  // every finished candidate (tracks_per_seed = 0 only)
+  o.fin_cap = all_tracks ? (long long)ns * kFinPerSeed + 1024 : 0;
+  const size_t fc = (size_t)std::max<long long>(o.fin_cap, 1), sn = all_tracks ? ns : 1;
+  o.off_fin_seed = take(fc * 4);
+  o.off_fin_node = take(fc * 4);
+  o.off_fin_nmh = take(fc * 4);
+  o.off_fin_chi2 = take(fc * 8);
+  o.off_fin_count = take(8);
+  o.off_seed_cnt = take(sn * 4);
+  o.off_seed_meas = take(sn * 4);
+  o.off_seed_fill = take(sn * 4);
+  o.off_fin_order = take(fc * 4);
   o.total = at;
   return o;
 }
@@ -615,7 +632,7 @@ ckf_status ckf_workspace_size(const ckf_geometry* g, const ckf_config* cfg, cons
   if (n_events < 0 || n_seeds < 0 || n_meas < 0) return fail(CKF_ERR_INVALID_ARGUMENT, "workspace_size: negative size");
   if (n_meas > INT32_MAX) return fail(CKF_ERR_NOT_SUPPORTED, "more than 2^31 measurements");
   const ckf::Launch L = resolve_launch(cfg, launch, n_seeds);
-  *bytes = layout(L, n_events, g->dev.n_surfaces, n_seeds, n_meas).total;
+  *bytes = layout(L, n_events, g->dev.n_surfaces, n_seeds, n_meas, cfg->tracks_per_seed == 0).total;
   return CKF_OK;
 }
 
@@ -642,12 +659,13 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
   if (!workspace) return fail(CKF_ERR_INVALID_ARGUMENT, "workspace is NULL");
   if (model && f->dev.map) return fail(CKF_ERR_NOT_SUPPORTED, "the learned proposal runs in a uniform field");
   const ckf::Launch L = resolve_launch(cfg, launch, s->n_seeds);
-  const Layout o = layout(L, m->n_events, m->n_surfaces, s->n_seeds, m->n_meas);
+  const Layout o = layout(L, m->n_events, m->n_surfaces, s->n_seeds, m->n_meas, cfg->tracks_per_seed == 0);
   if (workspace_bytes < o.total)
     return fail(CKF_ERR_CAPACITY, "workspace too small: need " + std::to_string(o.total) + " bytes");
   char* ws = static_cast<char*>(workspace);
   ckf::Workspace w;
   w.m_sorted = reinterpret_cast<float4*>(ws + o.off_sorted);
+  w.m_key = reinterpret_cast<float*>(ws + o.off_key);
   w.m_id = reinterpret_cast<int*>(ws + o.off_id);
   w.row_of = reinterpret_cast<int*>(ws + o.off_rowof);
   w.row_maxvar0 = reinterpret_cast<float*>(ws + o.off_maxv);
@@ -662,6 +680,16 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
   w.scan_a = reinterpret_cast<int*>(ws + o.off_scan_a);
   w.scan_b = reinterpret_cast<int*>(ws + o.off_scan_b);
   w.pools = ws + o.off_pools;
+  w.fin_seed = reinterpret_cast<int*>(ws + o.off_fin_seed);
+  w.fin_node = reinterpret_cast<int*>(ws + o.off_fin_node);
+  w.fin_nmh = reinterpret_cast<int*>(ws + o.off_fin_nmh);
+  w.fin_chi2 = reinterpret_cast<double*>(ws + o.off_fin_chi2);
+  w.fin_count = reinterpret_cast<unsigned long long*>(ws + o.off_fin_count);
+  w.fin_cap = o.fin_cap;
+  w.seed_cnt = reinterpret_cast<int*>(ws + o.off_seed_cnt);
+  w.seed_meas = reinterpret_cast<int*>(ws + o.off_seed_meas);
+  w.seed_fill = reinterpret_cast<int*>(ws + o.off_seed_fill);
+  w.fin_order = reinterpret_cast<int*>(ws + o.off_fin_order);
   w.pool_cap = L.pool_cap;
   w.seeds_per_group = L.seeds_per_group;
   w.grid = L.grid;
@@ -686,7 +714,10 @@ ckf_status ckf_find(const ckf_geometry* g, const ckf_field* f, const ckf_measure
     HIP_TRY(ckf::launch_ckf(a, L.waves_per_simd, hs), "launch k_ckf");
     if (launch && launch->timer) HIP_TRY(hipEventRecord(launch->timer->stop, hs), "hipEventRecord");
   }
-  HIP_TRY(ckf::launch_output(s->n_seeds, w, s->event, *out, hs), "launch output");
+  if (cfg->tracks_per_seed == 0)
+    HIP_TRY(ckf::launch_output_all(s->n_seeds, w, s->event, *out, hs), "launch output (all finished)");
+  else
+    HIP_TRY(ckf::launch_output(s->n_seeds, w, s->event, *out, hs), "launch output");
   return CKF_OK;
 }
 
@@ -1036,22 +1067,19 @@ ckf_status ckf_resolve_workspace_size(int32_t cap_tracks, int64_t n_meas, size_t
 
 ckf_status ckf_resolve(const int32_t* n_tracks, int32_t cap_tracks, int64_t cap_meas, const int32_t* offsets,
                        const int32_t* meas, int64_t n_meas, const double* chi2, const int32_t* ndf,
-                       int32_t max_shared, void* workspace, size_t workspace_bytes, int32_t* keep, int32_t* rounds,
-                       void* stream) {
+                       int32_t max_shared, int32_t max_rounds, void* workspace, size_t workspace_bytes, int32_t* keep,
+                       int32_t* info, void* stream) {
   if (cap_tracks < 0 || cap_meas < 0 || n_meas < 0 || max_shared < 0)
     return fail(CKF_ERR_INVALID_ARGUMENT, "resolve: negative size or max_shared");
+  if (max_rounds < 1 || max_rounds > 1024) return fail(CKF_ERR_INVALID_ARGUMENT, "resolve: max_rounds must be 1..1024");
   if (n_meas > INT32_MAX) return fail(CKF_ERR_NOT_SUPPORTED, "resolve: more than 2^31 - 1 measurements");
   if (cap_tracks > 0 && (!n_tracks || !offsets || !chi2 || !ndf || !keep || (cap_meas > 0 && !meas)))
     return fail(CKF_ERR_INVALID_ARGUMENT, "resolve: NULL array");
   if (!workspace || workspace_bytes < ckf::resolve_workspace_bytes(cap_tracks, n_meas))
     return fail(CKF_ERR_CAPACITY, "resolve: workspace too small");
-  int r = 0;
-  bool conv = true;
-  HIP_TRY(ckf::run_resolve(n_tracks, cap_tracks, cap_meas, offsets, meas, n_meas, chi2, ndf, max_shared, workspace,
-                           keep, 100000, &r, &conv, static_cast<hipStream_t>(stream)),
+  HIP_TRY(ckf::run_resolve(n_tracks, cap_tracks, cap_meas, offsets, meas, n_meas, chi2, ndf, max_shared, max_rounds,
+                           workspace, keep, info, static_cast<hipStream_t>(stream)),
           "ambiguity resolution");
-  if (rounds) *rounds = r;
-  if (!conv) return fail(CKF_ERR_CAPACITY, "resolve: round limit reached");
   return CKF_OK;
 }
 

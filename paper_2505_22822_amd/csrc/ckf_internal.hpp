@@ -87,6 +87,7 @@ struct CfgDev {
   int material;
   float min_prob;  // learned proposal: smallest summed probability of the top-k to use it
   int topk;        // learned proposal: modules tested per proposal
+  int all_tracks;  // every finished candidate goes to the output (tracks_per_seed = 0)
 };
 
 // The next-module network packed for the bf16 matrix cores: weight tiles in
@@ -126,6 +127,7 @@ constexpr size_t kRecStride = (kRecBytes + 15) / 16 * 16;  // array-of-structs r
 struct Workspace {
   // carved from the caller's workspace
   float4* m_sorted;  // (loc0, loc1, var0, var1) sorted by loc0 within each row
+  float* m_key;      // the sorted loc0 keys alone (the window search reads 16 per cache line)
   int* m_id;         // caller's id of each sorted measurement
   int* row_of;
   float* row_maxvar0;
@@ -139,6 +141,18 @@ struct Workspace {
   double* res_chi2;
   int* scan_a;      // per-block sums for the output scan
   int* scan_b;
+  // every finished candidate (tracks_per_seed = 0): seed, last node, counts
+  // (n_meas | holes << 16), chi2; per-seed counts and the records by seed
+  int* fin_seed;
+  int* fin_node;
+  int* fin_nmh;
+  double* fin_chi2;
+  unsigned long long* fin_count;
+  long long fin_cap;
+  int* seed_cnt;
+  int* seed_meas;
+  int* seed_fill;
+  int* fin_order;
   char* pools;      // per-workgroup candidate pools
   int pool_cap;     // records per pool
   int seeds_per_group;

@@ -53,7 +53,8 @@ __device__ __forceinline__ float loc0_key(float x) { return x != x ? INFINITY : 
 // row is its sorted position (a stable segmented sort by loc0).
 __global__ void k_meas_scatter(long long n_meas, int n_rows, const int* __restrict__ offsets,
                                const int* __restrict__ row_of, const float* __restrict__ loc,
-                               const float* __restrict__ var, float4* sorted, int* id, const int* status) {
+                               const float* __restrict__ var, float4* sorted, float* key, int* id,
+                               const int* status) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_meas) return;
   if (status[CKF_STATUS_FLAGS] & CKF_FLAG_BAD_OFFSETS) return;
@@ -69,6 +70,7 @@ __global__ void k_meas_scatter(long long n_meas, int n_rows, const int* __restri
   }
   const int d = a + rank;
   sorted[d] = make_float4(x, loc[2 * i + 1], var[2 * i], var[2 * i + 1]);
+  key[d] = x;
   id[d] = (int)i;
 }
 
@@ -76,16 +78,23 @@ __global__ void k_meas_scatter(long long n_meas, int n_rows, const int* __restri
 // per-call initialisation (a fill kernel, so the sequence can be captured)
 
 __global__ void k_init(int n_seeds, int* res_node, int* res_nm, int* queue_head, unsigned long long* node_count,
-                       int* status, long long* counters, int* n_tracks, int* offsets, int* seed_flags) {
+                       int* status, long long* counters, int* n_tracks, int* offsets, int* seed_flags,
+                       int* seed_cnt, int* seed_meas, int* seed_fill, unsigned long long* fin_count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_seeds) {
     res_node[i] = -1;
     res_nm[i] = 0;
     if (seed_flags) seed_flags[i] = 0;
+    if (seed_cnt) {
+      seed_cnt[i] = 0;
+      seed_meas[i] = 0;
+      seed_fill[i] = 0;
+    }
   }
   if (i == 0) {
     *queue_head = 0;
     *node_count = 0ull;
+    *fin_count = 0ull;
     *n_tracks = 0;
     offsets[0] = 0;
   }
@@ -440,6 +449,20 @@ __device__ int window_wave(WinShared& S, const Workspace& w, double chi2_max, in
     for (int k = 0; k < nres; ++k) acc_insert(acc_x2, acc_id, acc_pos, S.res_x2[k][lane], S.res_id[k][lane], S.res_pos[k][lane]);
   __syncthreads();
   return nres <= kWinRes ? nres : -1;
+}
+
+// tracks_per_seed = 0: append a finished candidate (seed, last node, counts,
+// chi2) to the batch's list; beyond its capacity the flag is raised.
+__device__ __forceinline__ void fin_append(const Workspace& w, int* status, int seed, int node, int nmh, double chi2) {
+  const unsigned long long i = atomicAdd(w.fin_count, 1ull);
+  if ((long long)i >= w.fin_cap) {
+    atomicOr(status + CKF_STATUS_FLAGS, CKF_FLAG_FIN_CAPACITY);
+    return;
+  }
+  w.fin_seed[i] = seed;
+  w.fin_node[i] = node;
+  w.fin_nmh[i] = nmh;
+  w.fin_chi2[i] = chi2;
 }
 
 constexpr int kMaxSlots = 64;
@@ -912,12 +935,12 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             int l = a, u = b;
             while (l < u) {  // first position with loc0 >= lo
               const int mid = (l + u) >> 1;
-              if (A.w.m_sorted[mid].x < lo) l = mid + 1; else u = mid;
+              if (A.w.m_key[mid] < lo) l = mid + 1; else u = mid;
             }
             int l2 = l, u2 = b;
             while (l2 < u2) {  // first position with loc0 > hi
               const int mid = (l2 + u2) >> 1;
-              if (A.w.m_sorted[mid].x <= hi) l2 = mid + 1; else u2 = mid;
+              if (A.w.m_key[mid] <= hi) l2 = mid + 1; else u2 = mid;
             }
             w_start = l;
             w_n = l2 - l;
@@ -1086,7 +1109,15 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         atomicAdd(&sh_live[pslot], 1);
       }
       // ---- finished candidates update their seed's best (one lane at a time)
-      unsigned long long fm = __ballot(outcome == 3);
+      if (cfg.all_tracks) {  // every finished candidate is kept (no per-seed best)
+        if (outcome == 3) {
+          CNT_ADD(CKF_CNT_FINISHED, 1);
+          const int nmh = PIr(Pin, r, PI_NMH);
+          if ((nmh & 0xffff) >= cfg.min_meas)
+            fin_append(A.w, A.status, sh_seed[slot], PIr(Pin, r, PI_NODE), nmh, PDr(Pin, r, PD_CHI2));
+        }
+      }
+      unsigned long long fm = cfg.all_tracks ? 0ull : __ballot(outcome == 3);
       while (fm) {
         const int l = __ffsll((long long)fm) - 1;
         fm &= fm - 1;
@@ -1174,7 +1205,11 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
               PIr(Pout, r, PI_SLOT) = -1;
             }
           }
-          unsigned long long fm = __ballot(f);
+          if (cfg.all_tracks && f) {
+            CNT_ADD(CKF_CNT_FINISHED, 1);
+            if (nm >= cfg.min_meas) fin_append(A.w, A.status, sh_seed[sl], nd, nm | (ho << 16), ch);
+          }
+          unsigned long long fm = cfg.all_tracks ? 0ull : __ballot(f);
           while (fm) {
             const int l = __ffsll((long long)fm) - 1;
             fm &= fm - 1;
@@ -1355,6 +1390,111 @@ __global__ __launch_bounds__(kScanBlock) void k_out_write(int n, const int* res_
 }
 
 // ---------------------------------------------------------------------------
+// output of every finished candidate (tracks_per_seed = 0): per-seed counts,
+// the same block scans as above over (tracks, measurements) per seed, the
+// records bucketed by seed, then one thread per seed orders its bucket by the
+// rank key and writes its tracks.
+
+__global__ void k_all_count(const Workspace w) {
+  const long long n = min((long long)*w.fin_count, w.fin_cap);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    atomicAdd(&w.seed_cnt[w.fin_seed[i]], 1);
+    atomicAdd(&w.seed_meas[w.fin_seed[i]], w.fin_nmh[i] & 0xffff);
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_all_block_sums(int n, const int* cnt, const int* meas, int* bs_a,
+                                                               int* bs_b) {
+  const int s = blockIdx.x * kScanBlock + threadIdx.x;
+  int ea, eb, ta, tb;
+  block_scan2(s < n ? cnt[s] : 0, s < n ? meas[s] : 0, ea, eb, ta, tb);
+  if (threadIdx.x == 0) {
+    bs_a[blockIdx.x] = ta;
+    bs_b[blockIdx.x] = tb;
+  }
+}
+
+// The seed's first track (block scan plus the scanned block sums) becomes
+// its bucket cursor; each record then takes a slot in its seed's bucket.
+__global__ __launch_bounds__(kScanBlock) void k_all_offsets(int n, const Workspace w, const int* bs_a) {
+  const int s = blockIdx.x * kScanBlock + threadIdx.x;
+  int ea, eb, ta, tb;
+  block_scan2(s < n ? w.seed_cnt[s] : 0, 0, ea, eb, ta, tb);
+  if (s < n) w.seed_fill[s] = bs_a[blockIdx.x] + ea;
+}
+
+__global__ void k_all_bucket(const Workspace w) {
+  const long long n = min((long long)*w.fin_count, w.fin_cap);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    w.fin_order[atomicAdd(&w.seed_fill[w.fin_seed[i]], 1)] = (int)i;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_all_write(int n, const Workspace w, const int* seed_event,
+                                                          const int* bs_a, const int* bs_b, ckf_tracks out) {
+  const int s = blockIdx.x * kScanBlock + threadIdx.x;
+  const int cnt = s < n ? w.seed_cnt[s] : 0, nms = s < n ? w.seed_meas[s] : 0;
+  int ea, eb, ta, tb;
+  block_scan2(cnt, nms, ea, eb, ta, tb);
+  if (out.status[CKF_STATUS_FLAGS] & (CKF_FLAG_NODE_CAPACITY | CKF_FLAG_FIN_CAPACITY)) return;
+  if (s >= n || cnt == 0) return;
+  const int t0 = bs_a[blockIdx.x] + ea;
+  long long mo = (long long)bs_b[blockIdx.x] + eb;
+  if (t0 + cnt > out.cap_tracks || mo + nms > out.cap_meas) return;
+  // the seed's bucket, ordered by the rank key (insertion sort: buckets are
+  // small, and this is a mode for tests)
+  int* b = w.fin_order + t0;
+  for (int a = 1; a < cnt; ++a) {
+    const int i = b[a];
+    const int nm = w.fin_nmh[i] & 0xffff, ho = w.fin_nmh[i] >> 16, nd = w.fin_node[i];
+    const double ch = w.fin_chi2[i];
+    int j = a;
+    while (j > 0) {
+      const int o = b[j - 1];
+      if (!better(nm, ch, ho, nd, w.fin_nmh[o] & 0xffff, w.fin_chi2[o], w.fin_nmh[o] >> 16, w.fin_node[o], w.nodes))
+        break;
+      b[j] = o;
+      --j;
+    }
+    b[j] = i;
+  }
+  for (int k = 0; k < cnt; ++k) {
+    const int t = t0 + k;
+    const int i = b[k];
+    const int nm = w.fin_nmh[i] & 0xffff;
+    int nd = w.fin_node[i];
+    out.offsets[t] = (int)mo;
+    if (nd >= 0 && nd < w.node_cap) {
+      const Node& last = w.nodes[nd];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) out.params[5ll * t + c] = last.p[c];
+#pragma unroll
+      for (int c = 0; c < 15; ++c) out.cov[15ll * t + c] = last.cov[c];
+      out.last_surface[t] = last.surface;
+    } else {  // no measurement: nothing filtered
+#pragma unroll
+      for (int c = 0; c < 5; ++c) out.params[5ll * t + c] = NAN;
+#pragma unroll
+      for (int c = 0; c < 15; ++c) out.cov[15ll * t + c] = NAN;
+      out.last_surface[t] = -1;
+    }
+    for (int q = nm - 1; q >= 0 && nd >= 0 && nd < w.node_cap; --q) {
+      const Node& nn = w.nodes[nd];
+      out.meas[mo + q] = nn.meas;
+      if (out.meas_surface) out.meas_surface[mo + q] = nn.surface;
+      if (out.meas_params)
+        for (int c = 0; c < 5; ++c) out.meas_params[5 * (mo + q) + c] = nn.p[c];
+      nd = nn.parent;
+    }
+    out.chi2[t] = w.fin_chi2[i];
+    out.ndf[t] = 2 * nm - 5;
+    out.holes[t] = w.fin_nmh[i] >> 16;
+    out.seed[t] = s;
+    out.event[t] = seed_event[s];
+    mo += nm;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // component kernels
 
 template <bool kMap>
@@ -1416,9 +1556,10 @@ __global__ void k_kf_update_batch(int n, const double* p_in, const double* cov_i
 
 hipError_t launch_init(int n_seeds, const Workspace& w, const ckf_tracks& out, hipStream_t st) {
   const int n = n_seeds > 64 ? n_seeds : 64;
+  const bool all = w.fin_cap > 0;
   hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, st, n_seeds, w.res_node, w.res_nm, w.queue_head,
                      w.node_count, out.status, reinterpret_cast<long long*>(out.counters), out.n_tracks, out.offsets,
-                     out.seed_flags);
+                     out.seed_flags, all ? w.seed_cnt : nullptr, w.seed_meas, w.seed_fill, w.fin_count);
   return hipGetLastError();
 }
 
@@ -1429,7 +1570,7 @@ hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status,
                      m.var, w.row_of, w.row_maxvar0, status);
   if (m.n_meas > 0)
     hipLaunchKernelGGL(k_meas_scatter, dim3((unsigned)((m.n_meas + 255) / 256)), dim3(256), 0, st,
-                       (long long)m.n_meas, rows, m.offsets, w.row_of, m.loc, m.var, w.m_sorted, w.m_id, status);
+                       (long long)m.n_meas, rows, m.offsets, w.row_of, m.loc, m.var, w.m_sorted, w.m_key, w.m_id, status);
   return hipGetLastError();
 }
 
@@ -1478,6 +1619,22 @@ hipError_t launch_output(int n_seeds, const Workspace& w, const int* seed_event,
                      out.n_tracks, out.cap_tracks, (long long)out.cap_meas, out.offsets, w.node_count);
   hipLaunchKernelGGL(k_out_write, dim3(nb), dim3(kScanBlock), 0, st, n_seeds, w.res_node, w.res_nm, w.res_holes,
                      w.res_chi2, seed_event, w.nodes, w.node_cap, w.scan_a, w.scan_b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_output_all(int n_seeds, const Workspace& w, const int* seed_event, const ckf_tracks& out,
+                             hipStream_t st) {
+  const int nb = (n_seeds + kScanBlock - 1) / kScanBlock;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_all_count, dim3(1024), dim3(256), 0, st, w);
+  hipLaunchKernelGGL(k_all_block_sums, dim3(nb), dim3(kScanBlock), 0, st, n_seeds, w.seed_cnt, w.seed_meas,
+                     w.scan_a, w.scan_b);
+  hipLaunchKernelGGL(k_out_scan_blocks, dim3(1), dim3(kScanBlock), 0, st, nb, w.scan_a, w.scan_b, out.status,
+                     out.n_tracks, out.cap_tracks, (long long)out.cap_meas, out.offsets, w.node_count);
+  hipLaunchKernelGGL(k_all_offsets, dim3(nb), dim3(kScanBlock), 0, st, n_seeds, w, w.scan_a);
+  hipLaunchKernelGGL(k_all_bucket, dim3(1024), dim3(256), 0, st, w);
+  hipLaunchKernelGGL(k_all_write, dim3(nb), dim3(kScanBlock), 0, st, n_seeds, w, seed_event, w.scan_a, w.scan_b,
+                     out);
   return hipGetLastError();
 }
 

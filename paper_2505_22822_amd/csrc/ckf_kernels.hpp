@@ -48,6 +48,9 @@ hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status,
 hipError_t launch_ckf(const CkfArgs& a, int waves_per_simd, hipStream_t st);
 hipError_t launch_output(int n_seeds, const Workspace& w, const int* seed_event, const ckf_tracks& out,
                          hipStream_t st);
+// tracks_per_seed = 0: every finished candidate, by seed, in rank-key order
+hipError_t launch_output_all(int n_seeds, const Workspace& w, const int* seed_event, const ckf_tracks& out,
+                             hipStream_t st);
 hipError_t launch_propagate(const GeomDev& g, const FieldDev& f, const CfgDev& c, int n, const int* src,
                             const double* p_in, const double* cov_in, const int* dst, double* p_out,
                             double* cov_out, double* jac, double* path, int* ok, hipStream_t st);
@@ -81,8 +84,8 @@ hipError_t launch_cluster(const CellsIn& c, const GeomDev& g, const float* pitch
                           float* var, float* sp, int* cell_cluster, int* status, hipStream_t st);
 size_t resolve_workspace_bytes(int cap_tracks, long long n_meas);
 hipError_t run_resolve(const int* n_tracks, int cap_tracks, long long cap_meas, const int* off, const int* meas,
-                       long long n_meas, const double* chi2, const int* ndf, int max_shared, void* ws, int* keep,
-                       int max_rounds, int* rounds, bool* converged, hipStream_t st);
+                       long long n_meas, const double* chi2, const int* ndf, int max_shared, int max_rounds, void* ws,
+                       int* keep, int* info, hipStream_t st);
 hipError_t launch_fit(const GeomDev& g, const FieldDev& f, const CfgDev& cfg, const MeasIn& m, const SeedsIn& s,
                       const int* n_tracks, int cap_tracks, long long cap_meas, const int* off, const int* meas,
                       const int* msurf, const int* seed, bool two_filter, void* ws, double* out_p, double* out_C,

@@ -18,8 +18,13 @@
 //   decide  - a bad track that holds both slots of all its shared
 //             measurements is marked for removal;
 //   apply   - marked tracks die and release their measurements.
-// The host reads the number of bad tracks after each "shared" pass and
-// stops when it is zero.
+// The rounds run on the device with no host synchronisation (the call can be
+// captured in a graph): a fixed number of rounds is launched, and once a
+// "shared" pass finds no bad track every later kernel returns at once.  The
+// bad-track count alternates between two words by round parity, so that a
+// round reads the previous round's count while its own is being formed.  A
+// last "shared" pass after the final round tells whether any bad track is
+// left.
 #include "ckf_device.hpp"
 #include "ckf_kernels.hpp"
 
@@ -36,7 +41,8 @@ struct ResWs {
   unsigned long long* key;   // [cap_tracks]
   int* state;                // [cap_tracks] 1 live, 0 removed, -1 invalid; 2 marked this round (transient)
   int* bad;                  // [cap_tracks] 1 if bad this round
-  int* n_bad;                // [1]
+  int* n_bad;                // [2] bad tracks of the rounds of even / odd index
+  int* rounds;               // [1] rounds that removed tracks
 };
 
 __device__ __forceinline__ bool track_range(const int* off, int t, long long cap_meas, long long& a, long long& b) {
@@ -52,7 +58,10 @@ __global__ void k_res_init(long long n_meas, int cap_tracks, ResWs w) {
     w.state[i] = 0;
     w.bad[i] = 0;
   }
-  if (i == 0) *w.n_bad = 0;
+  if (i == 0) {
+    w.n_bad[0] = w.n_bad[1] = 0;
+    *w.rounds = 0;
+  }
 }
 
 // every live track's measurements counted; tracks with ids out of range
@@ -81,7 +90,8 @@ __device__ __forceinline__ unsigned long long share_key(int s, int n, double chi
 
 __global__ void k_res_shared(const int* __restrict__ n_tracks_p, int cap_tracks, const int* __restrict__ off,
                              const int* __restrict__ meas, const double* __restrict__ chi2,
-                             const int* __restrict__ ndf, int max_shared, ResWs w) {
+                             const int* __restrict__ ndf, int max_shared, ResWs w, int r) {
+  if (r > 0 && w.n_bad[(r - 1) & 1] == 0) return;  // converged in an earlier round
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n_t = min(*n_tracks_p, cap_tracks);
   if (t >= n_t) return;
@@ -93,7 +103,7 @@ __global__ void k_res_shared(const int* __restrict__ n_tracks_p, int cap_tracks,
   if (s <= max_shared) return;
   w.bad[t] = 1;
   w.key[t] = share_key(s, (int)(b - a), chi2[t], ndf[t]);
-  atomicAdd(w.n_bad, 1);
+  atomicAdd(&w.n_bad[r & 1], 1);
   for (long long k = a; k < b; ++k) {
     const int m = meas[k];
     if (w.use[m] > 1) {
@@ -104,7 +114,8 @@ __global__ void k_res_shared(const int* __restrict__ n_tracks_p, int cap_tracks,
 }
 
 __global__ void k_res_claim_a(const int* __restrict__ n_tracks_p, int cap_tracks, const int* __restrict__ off,
-                              const int* __restrict__ meas, ResWs w) {
+                              const int* __restrict__ meas, ResWs w, int r) {
+  if (w.n_bad[r & 1] == 0) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n_t = min(*n_tracks_p, cap_tracks);
   if (t >= n_t || !w.bad[t]) return;
@@ -116,7 +127,8 @@ __global__ void k_res_claim_a(const int* __restrict__ n_tracks_p, int cap_tracks
 }
 
 __global__ void k_res_claim_b(const int* __restrict__ n_tracks_p, int cap_tracks, const int* __restrict__ off,
-                              const int* __restrict__ meas, ResWs w) {
+                              const int* __restrict__ meas, ResWs w, int r) {
+  if (w.n_bad[r & 1] == 0) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n_t = min(*n_tracks_p, cap_tracks);
   if (t >= n_t || !w.bad[t]) return;
@@ -128,8 +140,10 @@ __global__ void k_res_claim_b(const int* __restrict__ n_tracks_p, int cap_tracks
 }
 
 __global__ void k_res_decide(const int* __restrict__ n_tracks_p, int cap_tracks, const int* __restrict__ off,
-                             const int* __restrict__ meas, ResWs w) {
+                             const int* __restrict__ meas, ResWs w, int r) {
+  if (w.n_bad[r & 1] == 0) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) ++*w.rounds;
   const int n_t = min(*n_tracks_p, cap_tracks);
   if (t >= n_t || !w.bad[t]) return;
   const unsigned long long key = w.key[t];
@@ -142,18 +156,24 @@ __global__ void k_res_decide(const int* __restrict__ n_tracks_p, int cap_tracks,
 }
 
 __global__ void k_res_apply(const int* __restrict__ n_tracks_p, int cap_tracks, const int* __restrict__ off,
-                            const int* __restrict__ meas, ResWs w) {
+                            const int* __restrict__ meas, ResWs w, int r) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) w.n_bad[(r + 1) & 1] = 0;  // the next round's count (the previous round's is no longer read)
+  if (w.n_bad[r & 1] == 0) return;
   const int n_t = min(*n_tracks_p, cap_tracks);
   if (t >= n_t) return;
-  if (t == 0) *w.n_bad = 0;
   if (w.state[t] != 2) return;
   w.state[t] = 0;
   for (long long k = off[t]; k < off[t + 1]; ++k) atomicSub(&w.use[meas[k]], 1);
 }
 
-__global__ void k_res_out(const int* __restrict__ n_tracks_p, int cap_tracks, ResWs w, int* __restrict__ keep) {
+__global__ void k_res_out(const int* __restrict__ n_tracks_p, int cap_tracks, ResWs w, int* __restrict__ keep,
+                          int* __restrict__ info, int r_last) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && info) {
+    info[0] = *w.rounds;
+    info[1] = w.n_bad[r_last & 1] == 0 ? 1 : 0;
+  }
   if (t >= cap_tracks) return;
   const int n_t = min(*n_tracks_p, cap_tracks);
   keep[t] = t < n_t ? w.state[t] : 0;
@@ -177,6 +197,7 @@ ResWs res_view(void* ws, int cap_tracks, long long n_meas) {
   w.bad = reinterpret_cast<int*>(p);
   p += al256((size_t)cap_tracks * 4);
   w.n_bad = reinterpret_cast<int*>(p);
+  w.rounds = w.n_bad + 2;
   return w;
 }
 
@@ -184,39 +205,33 @@ ResWs res_view(void* ws, int cap_tracks, long long n_meas) {
 
 size_t resolve_workspace_bytes(int cap_tracks, long long n_meas) {
   return al256((size_t)n_meas * 4) + al256((size_t)n_meas * 8) + al256((size_t)n_meas * 4) +
-         al256((size_t)cap_tracks * 8) + 2 * al256((size_t)cap_tracks * 4) + 256;
+         al256((size_t)cap_tracks * 8) + 2 * al256((size_t)cap_tracks * 4) + 256;  // last: n_bad[2], rounds
 }
 
 hipError_t run_resolve(const int* n_tracks, int cap_tracks, long long cap_meas, const int* off, const int* meas,
-                       long long n_meas, const double* chi2, const int* ndf, int max_shared, void* ws, int* keep,
-                       int max_rounds, int* rounds, bool* converged, hipStream_t st) {
-  *rounds = 0;
-  *converged = true;
+                       long long n_meas, const double* chi2, const int* ndf, int max_shared, int max_rounds, void* ws,
+                       int* keep, int* info, hipStream_t st) {
   const ResWs w = res_view(ws, cap_tracks, n_meas);
   const long long n_init = n_meas > cap_tracks ? n_meas : (long long)cap_tracks;
   hipLaunchKernelGGL(k_res_init, dim3((unsigned)((n_init + kResBlock) / kResBlock)), dim3(kResBlock), 0, st, n_meas,
                      cap_tracks, w);
-  if (cap_tracks <= 0) return hipGetLastError();
+  if (cap_tracks <= 0) {  // nothing to resolve (the track arrays may be NULL): report 0 rounds, converged
+    hipLaunchKernelGGL(k_res_out, dim3(1), dim3(kResBlock), 0, st, n_tracks, 0, w, keep, info, 0);
+    return hipGetLastError();
+  }
   const dim3 grid((cap_tracks + kResBlock - 1) / kResBlock), block(kResBlock);
   hipLaunchKernelGGL(k_res_count, grid, block, 0, st, n_tracks, cap_tracks, cap_meas, off, meas, n_meas, w);
   for (int r = 0; r < max_rounds; ++r) {
-    hipLaunchKernelGGL(k_res_shared, grid, block, 0, st, n_tracks, cap_tracks, off, meas, chi2, ndf, max_shared, w);
-    int nb = 0;
-    hipError_t e = hipMemcpyAsync(&nb, w.n_bad, sizeof(int), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
-    if (nb == 0) break;
-    if (r == max_rounds - 1) {  // every round removes at least the bad track with the largest key
-      *converged = false;
-      break;
-    }
-    *rounds = r + 1;
-    hipLaunchKernelGGL(k_res_claim_a, grid, block, 0, st, n_tracks, cap_tracks, off, meas, w);
-    hipLaunchKernelGGL(k_res_claim_b, grid, block, 0, st, n_tracks, cap_tracks, off, meas, w);
-    hipLaunchKernelGGL(k_res_decide, grid, block, 0, st, n_tracks, cap_tracks, off, meas, w);
-    hipLaunchKernelGGL(k_res_apply, grid, block, 0, st, n_tracks, cap_tracks, off, meas, w);
+    hipLaunchKernelGGL(k_res_shared, grid, block, 0, st, n_tracks, cap_tracks, off, meas, chi2, ndf, max_shared, w, r);
+    hipLaunchKernelGGL(k_res_claim_a, grid, block, 0, st, n_tracks, cap_tracks, off, meas, w, r);
+    hipLaunchKernelGGL(k_res_claim_b, grid, block, 0, st, n_tracks, cap_tracks, off, meas, w, r);
+    hipLaunchKernelGGL(k_res_decide, grid, block, 0, st, n_tracks, cap_tracks, off, meas, w, r);
+    hipLaunchKernelGGL(k_res_apply, grid, block, 0, st, n_tracks, cap_tracks, off, meas, w, r);
   }
-  hipLaunchKernelGGL(k_res_out, grid, block, 0, st, n_tracks, cap_tracks, w, keep);
+  // is any bad track left after the last round?
+  hipLaunchKernelGGL(k_res_shared, grid, block, 0, st, n_tracks, cap_tracks, off, meas, chi2, ndf, max_shared, w,
+                     max_rounds);
+  hipLaunchKernelGGL(k_res_out, grid, block, 0, st, n_tracks, cap_tracks, w, keep, info, max_rounds);
   return hipGetLastError();
 }
 

@@ -54,3 +54,31 @@ def compare(ref, got):
         cov_worst = max(cov_worst, np.max(np.abs(Mg / np.outer(dg, dg) - Mr / np.outer(dr, dr))))
     extra = [s for s in got_by_seed if s not in ref_by_seed]
     return same, mism, extra, worst, cov_worst
+
+
+def decoy_event():
+    """The enumeration input: four pixel barrel layers, a tiny event whose
+    every hit has up to two decoy hits on the same module (Gaussian, 3 sigma
+    of the resolution), and every 17th seed.  Returns (detector, event,
+    seed indices kept)."""
+    from synth import make_event
+    from synth.detector import _Builder, PIXEL
+    b = _Builder("four")
+    for R in (30.0, 70.0, 120.0, 180.0):
+        b.barrel(R, 300.0, 11, 0.0, PIXEL)
+    det = b.build()
+    ev = make_event(det, 7, kind="tiny")
+    rng = np.random.default_rng(1)
+    keep = np.arange(0, ev.n_seeds, 17)
+    loc, var, surf, part = [], [], [], []
+    for s in range(det.n_surfaces):
+        for i in range(ev.offsets[s], ev.offsets[s + 1]):
+            loc.append(ev.loc[i]); var.append(ev.var[i]); surf.append(s); part.append(ev.meas_particle[i])
+            for _ in range(rng.integers(0, 3)):
+                loc.append(ev.loc[i] + rng.normal(0, 3.0, 2) * np.sqrt(ev.var[i]))
+                var.append(ev.var[i]); surf.append(s); part.append(-1)
+    surf = np.asarray(surf)
+    ev.loc, ev.var = np.asarray(loc, np.float32), np.asarray(var, np.float32)
+    ev.meas_particle = np.asarray(part)
+    ev.offsets = np.r_[0, np.cumsum(np.bincount(surf, minlength=det.n_surfaces))].astype(np.int32)
+    return det, ev, keep

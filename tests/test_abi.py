@@ -109,9 +109,10 @@ def test_host_side_validation_of_the_next_rows(lib):
     # ambiguity resolution
     assert lib.ckf_resolve_workspace_size(-1, 0, C.byref(nb)) == 1
     assert lib.ckf_resolve_workspace_size(10, 100, C.byref(nb)) == 0 and nb.value > 0
-    assert lib.ckf_resolve(None, 5, 0, None, None, 0, None, None, 1, None, 0, None, None, None) == 1  # NULL arrays
-    assert lib.ckf_resolve(None, 0, 0, None, None, 0, None, None, -1, None, 0, None, None, None) == 1  # max_shared < 0
-    assert lib.ckf_resolve(None, 0, 0, None, None, 1 << 31, None, None, 1, None, 0, None, None, None) == 5
+    assert lib.ckf_resolve(None, 5, 0, None, None, 0, None, None, 1, 8, None, 0, None, None, None) == 1  # NULL arrays
+    assert lib.ckf_resolve(None, 0, 0, None, None, 0, None, None, -1, 8, None, 0, None, None, None) == 1  # max_shared < 0
+    assert lib.ckf_resolve(None, 0, 0, None, None, 0, None, None, 1, 0, None, 0, None, None, None) == 1  # max_rounds 0
+    assert lib.ckf_resolve(None, 0, 0, None, None, 1 << 31, None, None, 1, 8, None, 0, None, None, None) == 5
     # clustering
     cells = _abi.CellsDesc()
     assert lib.ckf_cluster_workspace_size(None, C.byref(nb)) == 1

@@ -35,6 +35,23 @@ def _dev_tracks(off, meas, chi2, ndf):
                 ndf=t(ndf, torch.int32))
 
 
+def _random_set(rng, n_t, n_m, span):
+    """n_t tracks of 6-12 measurements drawn from n_m ids in local
+    neighbourhoods of `span` ids (heavy sharing, long chains); chi2 with few
+    distinct values, so many keys tie."""
+    tracks = []
+    for t in range(n_t):
+        n = int(rng.integers(6, 13))
+        c = int(rng.integers(0, n_m - span))
+        tracks.append(np.sort(rng.choice(np.arange(c, c + span), n, replace=False)))
+    off = np.zeros(n_t + 1, np.int32)
+    off[1:] = np.cumsum([len(t) for t in tracks])
+    meas = np.concatenate(tracks).astype(np.int32)
+    chi2 = rng.integers(1, 6, n_t).astype(np.float64) * 2.5   # few distinct values: many ties
+    ndf = np.array([2 * len(t) - 5 for t in tracks], np.int32)
+    return off, meas, chi2, ndf, n_m
+
+
 def test_resolve_matches_oracle_on_oracle_tracks(ckf, det_dense):
     import oracle
     from oracle import ambiguity as OA
@@ -56,17 +73,7 @@ def test_resolve_matches_oracle_on_random_sets(ckf, seed):
     sequential greedy's set, for max_shared 0, 1 and 2."""
     from oracle import ambiguity as OA
     rng = np.random.default_rng(seed)
-    n_t, n_m = 2000, 3000
-    tracks = []
-    for t in range(n_t):
-        n = int(rng.integers(6, 13))
-        c = int(rng.integers(0, n_m - 40))
-        tracks.append(np.sort(rng.choice(np.arange(c, c + 40), n, replace=False)))
-    off = np.zeros(n_t + 1, np.int32)
-    off[1:] = np.cumsum([len(t) for t in tracks])
-    meas = np.concatenate(tracks).astype(np.int32)
-    chi2 = rng.integers(1, 6, n_t).astype(np.float64) * 2.5   # few distinct values: many ties
-    ndf = np.array([2 * len(t) - 5 for t in tracks], np.int32)
+    off, meas, chi2, ndf, n_m = _random_set(rng, 2000, 3000, 40)
     for ms in (0, 1, 2):
         keep_o, order = OA.resolve(off, meas, chi2, ndf, max_shared=ms)
         keep, rounds = ckf.resolve(_dev_tracks(off, meas, chi2, ndf), n_m, max_shared=ms)
@@ -111,8 +118,52 @@ def test_resolve_edge_cases(ckf):
     lib = _abi.load()
     ws = torch.empty(64, dtype=torch.uint8, device="cuda")
     k = torch.zeros(3, dtype=torch.int32, device="cuda")
-    r = C.c_int32(0)
     args = [t1["n_tracks"].data_ptr(), 3, 12, t1["offsets"].data_ptr(), t1["meas"].data_ptr(), 50,
             t1["chi2"].data_ptr(), t1["ndf"].data_ptr()]
-    assert lib.ckf_resolve(*args, 1, ws.data_ptr(), 64, k.data_ptr(), C.byref(r), None) == 3
-    assert lib.ckf_resolve(*args, -1, ws.data_ptr(), 64, k.data_ptr(), C.byref(r), None) == 1
+    assert lib.ckf_resolve(*args, 1, 8, ws.data_ptr(), 64, k.data_ptr(), None, None) == 3
+    assert lib.ckf_resolve(*args, -1, 8, ws.data_ptr(), 64, k.data_ptr(), None, None) == 1
+    assert lib.ckf_resolve(*args, 1, 0, ws.data_ptr(), 64, k.data_ptr(), None, None) == 1
+
+
+def test_resolve_round_bound_and_graph_capture(ckf):
+    """The rounds run on the device: a bound too small for a heavily shared
+    set reports converged = 0 and a prefix of the greedy (its removals are
+    among the greedy's); and the call, captured in a graph, replayed three
+    times with eager work between, gives the eager result every time."""
+    import torch
+    import oracle.ambiguity as OA
+    rng = np.random.default_rng(11)
+    off, meas, chi2, ndf, n_m = _random_set(rng, 400, 900, 20)
+    t = _dev_tracks(off, meas, chi2, ndf)
+    keep_o, _ = OA.resolve(off, meas, chi2, ndf)
+    keep, rounds = ckf.resolve(t, n_m)
+    assert np.array_equal(keep.cpu().numpy(), keep_o)
+    _say(f"[resolve] heavily shared set: {rounds} rounds")
+    assert rounds >= 2
+    k1, info = ckf.resolve(t, n_m, max_rounds=1, sync=False)
+    torch.cuda.synchronize()
+    assert list(info.cpu().numpy()) == [1, 0]
+    k1 = k1.cpu().numpy()
+    assert np.all(keep_o[k1 == 0] == 0) and np.sum(k1 == 0) < np.sum(keep_o == 0)
+    # graph capture of the whole call (the rounds are on the device)
+    s = torch.cuda.Stream()
+    nb = C.c_size_t(0)
+    from paper_2505_22822_amd import _abi
+    assert _abi.load().ckf_resolve_workspace_size(len(off) - 1, n_m, C.byref(nb)) == 0
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    info = torch.zeros(2, dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(s):
+        ckf.resolve(t, n_m, stream=s, workspace=ws, info=info, sync=False)  # warm-up outside the graph
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        kg, _ = ckf.resolve(t, n_m, stream=s, workspace=ws, info=info, sync=False)
+    for rep in range(3):
+        kg.fill_(7)
+        info.zero_()
+        _ = torch.ones(1000, device="cuda").sum()  # eager work between the replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(kg.cpu().numpy(), keep_o), rep
+        assert list(info.cpu().numpy()) == [rounds, 1], rep

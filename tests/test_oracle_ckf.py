@@ -218,26 +218,8 @@ def test_ckf_equals_exhaustive_enumeration(oracle_lib):
     """Four pixel layers crowded with decoy hits near every true hit, all
     branches kept, no pruning: the oracle's finished candidates equal the
     depth-first enumeration of all gated sequences."""
-    from synth.detector import _Builder, PIXEL
-    b = _Builder("four")
-    for R in (30.0, 70.0, 120.0, 180.0):
-        b.barrel(R, 300.0, 11, 0.0, PIXEL)
-    det = b.build()
-    ev = make_event(det, 7, kind="tiny")
-    rng = np.random.default_rng(1)
-    # add up to two decoys around each hit on the same module
-    keep = np.arange(0, ev.n_seeds, 17)
-    loc, var, surf, part = [], [], [], []
-    for s in range(det.n_surfaces):
-        for i in range(ev.offsets[s], ev.offsets[s + 1]):
-            loc.append(ev.loc[i]); var.append(ev.var[i]); surf.append(s); part.append(ev.meas_particle[i])
-            for _ in range(rng.integers(0, 3)):
-                loc.append(ev.loc[i] + rng.normal(0, 3.0, 2) * np.sqrt(ev.var[i]))
-                var.append(ev.var[i]); surf.append(s); part.append(-1)
-    surf = np.asarray(surf)
-    ev.loc, ev.var = np.asarray(loc, np.float32), np.asarray(var, np.float32)
-    ev.meas_particle = np.asarray(part)
-    ev.offsets = np.r_[0, np.cumsum(np.bincount(surf, minlength=det.n_surfaces))].astype(np.int32)
+    from parity_util import decoy_event
+    det, ev, keep = decoy_event()
     cfg = dict(oracle_lib.DEFAULT_CONFIG, branches_per_surface=0, max_live_per_seed=0, tracks_per_seed=0,
                min_meas=0, material_on=0, max_steps=12, step_tol=1e-6)
     inp = oracle_lib.Inputs(det.as_arrays(), (0, 0, 2.0))
