@@ -465,6 +465,36 @@ __device__ __forceinline__ void fin_append(const Workspace& w, int* status, int 
   w.fin_chi2[i] = chi2;
 }
 
+// C <- J C J^T on a pool record's covariance (J promoted to FP64), each new
+// element stored as soon as it is formed; the three the gate needs are
+// returned.
+__device__ __forceinline__ void transport_cov_rec(const float J[5][5], const Pool& P, int r, double& c00, double& c01,
+                                                  double& c11) {
+  double C[15];
+  load_cov(P, r, C);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double row[5];  // (J C)[i][:]
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < 5; ++l) s = fma((double)J[i][l], C[pk(l, k)], s);
+      row[k] = s;
+    }
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s = fma(row[k], (double)J[j][k], s);
+      if (i == 0 && j == 0) c00 = s;
+      if (i == 0 && j == 1) c01 = s;
+      if (i == 1 && j == 1) c11 = s;
+      PDr(P, r, PD_C + pk(i, j)) = s;
+    }
+  }
+}
+
 constexpr int kMaxSlots = 64;
 
 // kCount: the instrumented variant that accumulates the work-unit counters
@@ -647,6 +677,8 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       long long t_nav = 0;
       int prop[3] = {-1, -1, -1};
       bool confident = false;
+      int pf_a = 0, pf_b = 0;  // the searched row's measurement range and largest var0 (loaded early)
+      float pf_mv = 0.f;
       V3 kl{0.f, 0.f, 0.f};
       auto stage_a = [&]() {
         CNT_ADD(CKF_CNT_STEPS, 1);
@@ -822,6 +854,12 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       // rebuilt from the record rather than kept in registers across the
       // network and the listing.
       auto stage_b2 = [&]() {
+        if (root) {  // the searched row (the seed's own module), loaded ahead of the search
+          const int row = sh_event[slot] * g.n_surfaces + surf;
+          pf_a = A.m.offsets[row];
+          pf_b = A.m.offsets[row + 1];
+          pf_mv = A.w.row_maxvar0[row];
+        }
 #pragma unroll
         for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
         load_module(g, surf, Am);
@@ -849,6 +887,12 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             --nlist;
             Module Bm;
             load_module(g, m, Bm);
+            {  // the row searched if the leg crosses m, loaded while the leg is propagated
+              const int row = sh_event[slot] * g.n_surfaces + m;
+              pf_a = A.m.offsets[row];
+              pf_b = A.m.offsets[row + 1];
+              pf_mv = A.w.row_maxvar0[row];
+            }
             const V3 dB = ld3(Bm.c) - origin;
             LegStats ls{0, 0};
             CNT_ADD(CKF_CNT_LEGS, 1);
@@ -912,25 +956,21 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       int w_start = 0, w_n = 0, surf2 = -1;
       double g0 = 0.0, g1 = 0.0, k00 = 0.0, k01 = 0.0, k11 = 0.0;
       if (outcome == 1 || outcome == 2) {
-        double C[15];
-        load_cov(Pin, r, C);
         if (moved) {
-          transport_cov(J, C);
-#pragma unroll
-          for (int k = 0; k < 15; ++k) PDr(Pin, r, (PD_C + k)) = C[k];
+          transport_cov_rec(J, Pin, r, k00, k01, k11);
+        } else {
+          k00 = PDr(Pin, r, PD_C + 0);
+          k01 = PDr(Pin, r, PD_C + 1);
+          k11 = PDr(Pin, r, PD_C + 5);
         }
         if (outcome == 2) {
           CNT_ADD(CKF_CNT_CROSSED, 1);
           g0 = PDr(Pin, r, PD_P + 0);
           g1 = PDr(Pin, r, PD_P + 1);
-          k00 = C[0];
-          k01 = C[1];
-          k11 = C[5];
           surf2 = PIr(Pin, r, PI_SURF);
-          const int row = sh_event[slot] * g.n_surfaces + surf2;
-          const int a = A.m.offsets[row], b = A.m.offsets[row + 1];
+          const int a = pf_a, b = pf_b;  // the row of surf2 (the seed's module, or the leg's target)
           if (b > a) {
-            const double wd = sqrt(cfg.chi2_max * (C[0] + (double)A.w.row_maxvar0[row]));
+            const double wd = sqrt(cfg.chi2_max * (k00 + (double)pf_mv));
             const float lo = (float)(g0 - wd) - 1e-3f, hi = (float)(g0 + wd) + 1e-3f;
             int l = a, u = b;
             while (l < u) {  // first position with loc0 >= lo
@@ -1055,13 +1095,11 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         const int rs = b0 + src, q = out_base + c;
         const int nkf = sh_kind[src];
         const int pslot = PIr(Pin, rs, PI_SLOT);
-        if (nkf == 0) {  // the record moves on unchanged
+        if (nkf == 0) {  // the record moves on unchanged: 14 16-byte words (records are 16-byte aligned)
+          const float4* from = reinterpret_cast<const float4*>(Pin.base + (size_t)rs * kRecStride);
+          float4* to = reinterpret_cast<float4*>(Pout.base + (size_t)q * kRecStride);
 #pragma unroll
-          for (int k = 0; k < PD_N; ++k) PDr(Pout, q, k) = PDr(Pin, rs, k);
-#pragma unroll
-          for (int k = 0; k < PI_N; ++k) PIr(Pout, q, k) = PIr(Pin, rs, k);
-#pragma unroll
-          for (int k = 0; k < PF_N; ++k) PFr(Pout, q, k) = PFr(Pin, rs, k);
+          for (int k = 0; k < (int)(kRecStride / 16); ++k) to[k] = from[k];
         } else {  // the Kalman-updated child for the parent's j-th accepted measurement
           const long long nd = (long long)sh_node_base + sh_noff[src];
           const bool room = nd + nkf <= A.w.node_cap;
