@@ -138,6 +138,14 @@ __device__ __forceinline__ void load_module(const GeomDev& g, int m, Module& M) 
   M.hw0 = d.x; M.hw1 = d.y; M.thick = d.z; M.layer = __float_as_int(d.w);
 }
 
+// Only what the scattering reads (normal, thickness): two of the four loads.
+__device__ __forceinline__ void load_module_ms(const GeomDev& g, int m, Module& M) {
+  const float4* s = reinterpret_cast<const float4*>(g.mod + m);
+  const float4 c = s[2], d = s[3];
+  M.n[0] = c.y; M.n[1] = c.z; M.n[2] = c.w;
+  M.thick = d.z;
+}
+
 // ---------------------------------------------------------------------------
 // Propagation leg: free state relative to `origin` (the start module centre)
 // plus tangent columns d(state)/d(bound start parameters).  In a uniform

@@ -519,7 +519,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   __shared__ union {
     struct {
       int item[kWave * kMaxBranch];
-      int kind[kWave], noff[kWave];
+      int kind[kWave], noff[kWave], surf[kWave];
       int acc_pos[kMaxBranch][kWave], acc_id[kMaxBranch][kWave];
       double acc_x2[kMaxBranch][kWave];
     } o;
@@ -529,6 +529,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   auto& sh_item = sh_u.o.item;
   auto& sh_kind = sh_u.o.kind;
   auto& sh_noff = sh_u.o.noff;
+  auto& sh_surf = sh_u.o.surf;
   auto& sh_acc_pos = sh_u.o.acc_pos;
   auto& sh_acc_id = sh_u.o.acc_id;
   auto& sh_acc_x2 = sh_u.o.acc_x2;
@@ -972,15 +973,19 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           if (b > a) {
             const double wd = sqrt(cfg.chi2_max * (k00 + (double)pf_mv));
             const float lo = (float)(g0 - wd) - 1e-3f, hi = (float)(g0 + wd) + 1e-3f;
-            int l = a, u = b;
-            while (l < u) {  // first position with loc0 >= lo
-              const int mid = (l + u) >> 1;
-              if (A.w.m_key[mid] < lo) l = mid + 1; else u = mid;
-            }
-            int l2 = l, u2 = b;
-            while (l2 < u2) {  // first position with loc0 > hi
-              const int mid = (l2 + u2) >> 1;
-              if (A.w.m_key[mid] <= hi) l2 = mid + 1; else u2 = mid;
+            // the first position with loc0 >= lo and the first with loc0 >
+            // hi: two binary searches side by side, so that their loads are
+            // in flight together
+            int l = a, u = b, l2 = a, u2 = b;
+            while (l < u || l2 < u2) {
+              const int m1 = (l + u) >> 1, m2 = (l2 + u2) >> 1;
+              const float k1 = l < u ? A.w.m_key[m1] : 0.f, k2 = l2 < u2 ? A.w.m_key[m2] : 0.f;
+              if (l < u) {
+                if (k1 < lo) l = m1 + 1; else u = m1;
+              }
+              if (l2 < u2) {
+                if (k2 <= hi) l2 = m2 + 1; else u2 = m2;
+              }
             }
             w_start = l;
             w_n = l2 - l;
@@ -1030,7 +1035,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, r, (PD_P + k));
             load_cov(Pin, r, C);
             Module M;
-            load_module(g, surf2, M);
+            load_module_ms(g, surf2, M);
             apply_ms(M, cfg.mass, p, C);
             CNT_ADD(CKF_CNT_MS, 1);
 #pragma unroll
@@ -1080,6 +1085,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       // three children costs three lanes instead of three rounds of the wave
       sh_kind[lane] = act ? n_kf : 0;
       sh_noff[lane] = noff;
+      sh_surf[lane] = surf2;
 #pragma unroll
       for (int j = 0; j < kMaxBranch; ++j) {
         sh_acc_pos[j][lane] = acc_pos[j];
@@ -1104,11 +1110,15 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           const long long nd = (long long)sh_node_base + sh_noff[src];
           const bool room = nd + nkf <= A.w.node_cap;
           if (!room && j == 0) atomicOr(A.status + CKF_STATUS_FLAGS, CKF_FLAG_NODE_CAPACITY);
+          // the parent's module (from its search) and its normal and
+          // thickness for the scattering, requested with the parent's state
+          const int surf = sh_surf[src];
+          Module M;
+          if (cfg.material) load_module_ms(g, surf, M);
           double p[5], C[15];
 #pragma unroll
           for (int k = 0; k < 5; ++k) p[k] = PDr(Pin, rs, (PD_P + k));
           load_cov(Pin, rs, C);
-          const int surf = PIr(Pin, rs, PI_SURF);
           const int i = sh_acc_pos[j][src];
           double pc[5], Cc[15];
           const float4 ms = A.w.m_sorted[i];
@@ -1126,8 +1136,6 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             for (int k = 0; k < 15; ++k) np->cov[k] = Cc[k];
           }
           if (cfg.material) {
-            Module M;
-            load_module(g, surf, M);
             apply_ms(M, cfg.mass, pc, Cc);
             CNT_ADD(CKF_CNT_MS, 1);
           }
