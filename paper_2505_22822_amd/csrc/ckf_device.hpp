@@ -760,12 +760,25 @@ __device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long m
   const float rperp = sqrtf(H.p0.x * H.p0.x + H.p0.y * H.p0.y);
   int best = -1;
   s_best = INFINITY;
+  // With the field along z, z grows linearly along the path and the distance
+  // from the axis by at most sin(theta) per unit path, so the crossing of
+  // radius R lies at z beyond p0.z + cot(theta) (R - r): a barrel whose
+  // extent that bound already overshoots (by more than kZSkip) is crossed
+  // outside it, and its Newton solve can be skipped with the same outcome.
+  constexpr float kZSkip = 1.0f;  // mm, far above the FP32 error of the bound
+  const bool axial = H.bhat.x == 0.f && H.bhat.y == 0.f;
+  const float sth = sqrtf(H.T0.x * H.T0.x + H.T0.y * H.T0.y);
+  const float cot = sth > 0.f ? fdiv_fast(H.T0.z, sth) : 0.f;
   // barrels by radius: the first crossed within its extent is the nearest
   for (int q = 0; q < g.n_barrel; ++q) {
     const int l = g.barrel_order[q];
     if (mask & (1ull << l)) continue;
     const LayerRec Lr = g.layers[l];
     if (!(Lr.pos > rperp)) continue;
+    if (axial && sth > 0.f) {
+      const float zb = H.p0.z + cot * (Lr.pos - rperp);
+      if (H.T0.z > 0.f ? zb > Lr.hi + kZSkip : zb < Lr.lo - kZSkip) continue;
+    }
     ++n_tried;
     float s;
     if (!cross_cylinder(H, Lr.pos, s)) continue;
