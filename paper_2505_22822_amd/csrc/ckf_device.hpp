@@ -276,17 +276,19 @@ __device__ __forceinline__ Helix make_helix(V3 p, V3 T, float lam, V3 B) {
   return H;
 }
 
+// (One accurate sine and cosine, of the half angle: sin a = 2 sh ch and
+// cos a = 1 - 2 sh^2, and 1 - cos a = 2 sh^2 without cancellation.)
 __device__ __forceinline__ void helix_at(const Helix& H, float s, V3& p, V3& T) {
   const float a = H.om * s;
-  float S, Cc, sa, ca;
-  sincosf(a, &sa, &ca);
+  float S, Cc, sh, ch;
+  sincosf(0.5f * a, &sh, &ch);
+  const float sa = 2.0f * sh * ch, ca = 1.0f - 2.0f * sh * sh;
   if (fabsf(a) < 1e-3f) {
     S = s * (1.0f - a * a * (1.0f / 6.0f));
     Cc = s * (0.5f * a) * (1.0f - a * a * (1.0f / 12.0f));
   } else {
-    const float hs = sinf(0.5f * a);
     S = sa * H.inv_om;
-    Cc = 2.0f * hs * hs * H.inv_om;
+    Cc = 2.0f * sh * sh * H.inv_om;
   }
   p = H.p0 + (H.tpar * s) * H.bhat + S * H.tperp + Cc * H.w;
   T = H.tpar * H.bhat + ca * H.tperp + sa * H.w;
