@@ -512,7 +512,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
 
   __shared__ LayerRec sh_layers[kMaxLayers];
   __shared__ int sh_order[3][kMaxLayers];
-  __shared__ unsigned short sh_x[kLearned ? kWave * 8 : 1];  // network inputs (bf16), one row per lane
+  __shared__ __align__(16) unsigned short sh_x[kLearned ? kWave * 8 : 1];  // network inputs (bf16), one row per lane
   // phase 4 work list: per output slot of a pass its parent lane and branch;
   // per parent lane its child count, node offset and accepted measurements
   // (the listing's LDS is only used during navigation: the two share space)
@@ -525,6 +525,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
     } o;
     ListShared l;
     WinShared w;
+    float lg[kLearned ? kWave * kLogitStride : 1];  // the network's logits (learned proposal)
   } sh_u;
   auto& sh_item = sh_u.o.item;
   auto& sh_kind = sh_u.o.kind;
@@ -712,6 +713,16 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         if (root) {
           outcome = 2;
         } else if (nlist == 0) {
+          // learned: the module's neighbour-table entries, requested before
+          // the next-layer search so that they arrive during it
+          int nb_l[kMaxNext], nb_r[kMaxNext];
+          if (kLearned) {
+#pragma unroll
+            for (int q = 0; q < kMaxNext; ++q) {
+              nb_l[q] = g.nb_next[surf * kMaxNext + q];
+              nb_r[q] = g.nb_row[surf * kMaxNext + q];
+            }
+          }
           const V3 Bf = field_at<kMap>(A.f, Pl);
           const Helix H = make_helix(Pl, L.T, L.lam, Bf);
           float sL;
@@ -731,18 +742,18 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             sb = sL;
             if (kLearned) {
 #pragma unroll
-              for (int q = 0; q < kMaxNext; ++q)
-                if (nb_slot < 0 && g.nb_next[surf * kMaxNext + q] == nl) nb_slot = q;
-              if (nb_slot >= 0) {
-                nb_row = g.nb_row[surf * kMaxNext + nb_slot];
-                if (!crossing_window(g.layers[nl], g.nb_anc[nb_row], Pl, win)) nb_slot = -1;
-              }
+              for (int q = kMaxNext - 1; q >= 0; --q)  // the first slot holding layer nl
+                if (nb_l[q] == nl) {
+                  nb_slot = q;
+                  nb_row = nb_r[q];
+                }
+              if (nb_slot >= 0 && !crossing_window(g.layers[nl], g.nb_anc[nb_row], Pl, win)) nb_slot = -1;
               if (nb_slot >= 0) {  // the network input goes to LDS now
                 float f[7];
                 mlp_features(g.layers[nl], nl, g.n_layers, win, Pl, Tl, L.lam, f);
-#pragma unroll
-                for (int c = 0; c < 7; ++c) sh_x[lane * 8 + c] = bf16_bits(f[c]);
-                sh_x[lane * 8 + 7] = 0;
+                *reinterpret_cast<uint4*>(&sh_x[lane * 8]) =
+                    make_uint4(cvt_pk_bf16(f[0], f[1]), cvt_pk_bf16(f[2], f[3]), cvt_pk_bf16(f[4], f[5]),
+                               cvt_pk_bf16(f[6], 0.f));
               }
             }
           }
@@ -756,49 +767,42 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         const unsigned long long wm = __ballot(nb_slot >= 0);
         if (wm) {
           if (nb_slot < 0) {
-#pragma unroll
-            for (int c = 0; c < 8; ++c) sh_x[lane * 8 + c] = 0;
+            *reinterpret_cast<uint4*>(&sh_x[lane * 8]) = make_uint4(0u, 0u, 0u, 0u);
           }
           __syncthreads();
           const int q4 = 4 * (lane >> 4);
-          // two 16-row blocks at a time: each weight tile is read once per pair
-          Top3 mine;
-          float conf = 0.f;
-#pragma unroll 1
-          for (int rb0 = 0; rb0 < 4; rb0 += 2) {
-            if (((wm >> (16 * rb0)) & 0xffffffffull) == 0) continue;
-            bf16x4 xb[2];
+          // the four 16-row blocks together: each weight tile is read once
+          // per pass; the logits go to LDS, one row per lane
+          {
+            bf16x4 xb[4];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int src = (16 * (rb0 + h) + (lane & 15)) * 8 + q4;
-              xb[h].x = q4 < 8 ? (short)sh_x[src + 0] : (short)0;
-              xb[h].y = q4 < 8 ? (short)sh_x[src + 1] : (short)0;
-              xb[h].z = q4 < 8 ? (short)sh_x[src + 2] : (short)0;
-              xb[h].w = q4 < 8 ? (short)sh_x[src + 3] : (short)0;
+            for (int h = 0; h < 4; ++h) {
+              // features q4..q4+3 of the row (8-byte aligned; zero beyond the 8 stored)
+              const int src = (16 * h + (lane & 15)) * 8 + q4;
+              xb[h] = as_bf16x4(q4 < 8 ? *reinterpret_cast<const uint2*>(&sh_x[src]) : make_uint2(0u, 0u));
             }
-            f32x4 out[2][2];
-            mlp_blocks<2>(A.model, xb, lane, out);
-            if (kCount && lane == 0) CNT_ADD(CKF_CNT_MLP_BLOCKS, 2);
+            f32x4 out[4][2];
+            mlp_blocks<4>(A.model, xb, lane, out);
+            if (kCount && lane == 0) CNT_ADD(CKF_CNT_MLP_BLOCKS, 4);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              Top3 t;
-              float c;
-              mlp_top3(out[h], lane, cfg.topk, t, c);
-              if ((lane >> 4) == rb0 + h) {
-                mine = t;
-                conf = c;
-              }
-            }
+            for (int h = 0; h < 4; ++h) logits_to_lds(out[h], h, lane, sh_u.lg);
           }
           __syncthreads();
           if (nb_slot >= 0) {
             CNT_ADD(CKF_CNT_MLP_ROWS, 1);
+            RowTop rt;
+            const float conf = row_top3_values(&sh_u.lg[lane * kLogitStride], cfg.topk, rt);
             confident = conf >= cfg.min_prob;
+            if (confident) {
+              int cls[3];
+              row_top3_classes(rt, cls);
 #pragma unroll
-            for (int k = 0; k < 3; ++k)  // (a class outside 0..31 only if the logits were not finite)
-              if (k < cfg.topk && mine.c[k] >= 0 && mine.c[k] < kNeighbours)
-                prop[k] = window_module(g, nb_row, win, mine.c[k]);
+              for (int k = 0; k < 3; ++k)  // (a class outside 0..31 only if the logits were not finite)
+                if (k < cfg.topk && cls[k] >= 0 && cls[k] < kNeighbours)
+                  prop[k] = window_module(g, nb_row, win, cls[k]);
+            }
           }
+          __syncthreads();
         }
       };
       // stage B1: the learned proposal's listing (confident lanes); which

@@ -22,31 +22,30 @@ __device__ __forceinline__ unsigned short bf16_bits(float f) {
   return (unsigned short)(u >> 16);
 }
 
+// four bfloat16 values from two words (element 0 in the low half of u.x)
+__device__ __forceinline__ bf16x4 as_bf16x4(uint2 u) { return __builtin_bit_cast(bf16x4, u); }
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// two floats -> a packed bfloat16 pair (a in the low half), round to nearest
+// even: one v_cvt_pk_bf16_f32 on gfx950; the same bits as bf16_bits for
+// finite inputs
+__device__ __forceinline__ unsigned cvt_pk_bf16(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
+}
+
+// max(x, 0) on the bit pattern: a float with the sign bit set is a negative
+// int, so one integer max gives 0 for it (-0 included) and x otherwise
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
 __device__ __forceinline__ bf16x4 pack_bf16(f32x4 v) {
-  bf16x4 r;
-  r.x = (short)bf16_bits(v.x);
-  r.y = (short)bf16_bits(v.y);
-  r.z = (short)bf16_bits(v.z);
-  r.w = (short)bf16_bits(v.w);
-  return r;
+  return as_bf16x4(make_uint2(cvt_pk_bf16(v.x, v.y), cvt_pk_bf16(v.z, v.w)));
 }
 
 __device__ __forceinline__ bf16x4 relu_bf16(f32x4 v) {
-  v.x = fmaxf(v.x, 0.f);
-  v.y = fmaxf(v.y, 0.f);
-  v.z = fmaxf(v.z, 0.f);
-  v.w = fmaxf(v.w, 0.f);
-  return pack_bf16(v);
-}
-
-__device__ __forceinline__ bf16x4 as_bf16x4(uint2 u) {
-  bf16x4 r;
-  r.x = (short)(u.x & 0xffffu);
-  r.y = (short)(u.x >> 16);
-  r.z = (short)(u.y & 0xffffu);
-  r.w = (short)(u.y >> 16);
-  return r;
+  return as_bf16x4(make_uint2(cvt_pk_bf16(relu_bits(v.x), relu_bits(v.y)), cvt_pk_bf16(relu_bits(v.z), relu_bits(v.w))));
 }
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
@@ -191,80 +190,82 @@ __device__ __forceinline__ int window_module(const GeomDev& g, int row, const Wi
   return g.nb_reg[(long long)row * kRegCells + (cv - kRegV0) * kRegU + (cu - kRegU0)];
 }
 
-// Sorted top-3 (value descending, class ascending) of (v, c) pairs.
-struct Top3 {
-  float v[3];
-  int c[3];
+
+// Logits of one pass (up to 64 rows, row r = the lane that asked for it) in
+// LDS, one row of 32 per lane: the result tiles of block rb land at rows
+// 16 rb + l%16, classes 16 ob + 4 (l/16) .. +3.  The row stride keeps every
+// 16-byte access aligned.
+constexpr int kLogitStride = 36;
+
+__device__ __forceinline__ void logits_to_lds(const f32x4 out[2], int rb, int lane, float* lg) {
+  float* row = lg + (16 * rb + (lane & 15)) * kLogitStride + 4 * (lane >> 4);
+#pragma unroll
+  for (int ob = 0; ob < 2; ++ob) *reinterpret_cast<f32x4*>(row + 16 * ob) = out[ob];
+}
+
+// Softmax statistics of one row of 32 logits and its three largest values
+// (with multiplicity, descending): each logit is inserted into the sorted
+// three by a maximum and two medians (v_med3_f32), no branches.  conf =
+// summed probability of the first k (1..3) of the three.  NaN logits (only
+// from non-finite parameters) are not supported.
+struct RowTop {
+  float v[32];
+  float t[3];
 };
 
-__device__ __forceinline__ bool top_before(float va, int ca, float vb, int cb) {
-  return va > vb || (va == vb && ca < cb);
-}
-
-__device__ __forceinline__ void top_insert(Top3& t, float v, int c) {
-  if (!top_before(v, c, t.v[2], t.c[2])) return;
-  if (top_before(v, c, t.v[1], t.c[1])) {
-    t.v[2] = t.v[1];
-    t.c[2] = t.c[1];
-    if (top_before(v, c, t.v[0], t.c[0])) {
-      t.v[1] = t.v[0];
-      t.c[1] = t.c[0];
-      t.v[0] = v;
-      t.c[0] = c;
-    } else {
-      t.v[1] = v;
-      t.c[1] = c;
-    }
-  } else {
-    t.v[2] = v;
-    t.c[2] = c;
-  }
-}
-
-// Softmax statistics and the top-3 classes of each row of a block: the four
-// lanes holding one row (l, l^16, l^32, l^48) all end with the same result.
-// conf = summed probability of the first k (1..3) of the top three.
-__device__ __forceinline__ void mlp_top3(const f32x4 out[2], int lane, int k, Top3& t, float& conf) {
-  const int q4 = 4 * (lane >> 4);
-  float vals[8];
+__device__ __forceinline__ float row_top3_values(const float* row, int k, RowTop& r) {
 #pragma unroll
-  for (int ob = 0; ob < 2; ++ob) {
-    vals[4 * ob + 0] = out[ob].x;
-    vals[4 * ob + 1] = out[ob].y;
-    vals[4 * ob + 2] = out[ob].z;
-    vals[4 * ob + 3] = out[ob].w;
+  for (int q = 0; q < 8; ++q) {
+    const f32x4 x = *reinterpret_cast<const f32x4*>(row + 4 * q);
+    r.v[4 * q + 0] = x.x;
+    r.v[4 * q + 1] = x.y;
+    r.v[4 * q + 2] = x.z;
+    r.v[4 * q + 3] = x.w;
   }
-  float mx = vals[0];
+  float v0 = -INFINITY, v1 = -INFINITY, v2 = -INFINITY;
 #pragma unroll
-  for (int i = 1; i < 8; ++i) mx = fmaxf(mx, vals[i]);
-  mx = fmaxf(mx, __shfl_xor(mx, 16));
-  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  for (int i = 0; i < 32; ++i) {
+    const float x = r.v[i];
+    v2 = __builtin_amdgcn_fmed3f(v1, v2, x);
+    v1 = __builtin_amdgcn_fmed3f(v0, v1, x);
+    v0 = __builtin_amdgcn_fmed3f(v0, x, INFINITY);
+  }
+  r.t[0] = v0;
+  r.t[1] = v1;
+  r.t[2] = v2;
+  // the row's maximum is v0
+  const float l2e = 1.44269504f, m2 = v0 * l2e;
   float s = 0.f;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) s += __expf(vals[i] - mx);
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
-  t.v[0] = t.v[1] = t.v[2] = -INFINITY;
-  t.c[0] = t.c[1] = t.c[2] = 1 << 20;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) top_insert(t, vals[i], 16 * (i >> 2) + q4 + (i & 3));
-#pragma unroll
-  for (int x = 16; x <= 32; x <<= 1) {
-    float ov[3];
-    int oc[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      ov[j] = __shfl_xor(t.v[j], x);
-      oc[j] = __shfl_xor(t.c[j], x);
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) top_insert(t, ov[j], oc[j]);
-  }
+  for (int i = 0; i < 32; ++i) s += __builtin_amdgcn_exp2f(fmaf(r.v[i], l2e, -m2));
   float num = 0.f;
 #pragma unroll
   for (int j = 0; j < 3; ++j)
-    if (j < k) num += __expf(t.v[j] - mx);
-  conf = num / s;
+    if (j < k) num += __builtin_amdgcn_exp2f(fmaf(r.t[j], l2e, -m2));
+  return num / s;
+}
+
+// The classes of the three values in (value descending, class ascending)
+// order: each is the smallest index holding its value that an earlier one
+// has not taken.
+__device__ __forceinline__ void row_top3_classes(const RowTop& r, int c[3]) {
+  int c0 = 1 << 20, c1 = 1 << 20, c2 = 1 << 20;
+#pragma unroll
+  for (int i = 31; i >= 0; --i) {
+    c0 = r.v[i] == r.t[0] ? i : c0;
+    c1 = r.v[i] == r.t[1] ? i : c1;
+    c2 = r.v[i] == r.t[2] ? i : c2;
+  }
+  if (r.t[1] == r.t[0] || r.t[2] == r.t[1]) {  // equal values: take the next free index
+    c1 = c2 = 1 << 20;
+#pragma unroll
+    for (int i = 31; i >= 0; --i) c1 = (r.v[i] == r.t[1] && i != c0) ? i : c1;
+#pragma unroll
+    for (int i = 31; i >= 0; --i) c2 = (r.v[i] == r.t[2] && i != c0 && i != c1) ? i : c2;
+  }
+  c[0] = c0;
+  c[1] = c1;
+  c[2] = c2;
 }
 
 }  // namespace ckf
