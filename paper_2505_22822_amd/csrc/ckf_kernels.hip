@@ -1167,18 +1167,27 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
             fin_append(A.w, A.status, sh_seed[slot], PIr(Pin, r, PI_NODE), nmh, PDr(Pin, r, PD_CHI2));
         }
       }
-      unsigned long long fm = cfg.all_tracks ? 0ull : __ballot(outcome == 3);
+      // the finished records' counts are read by all their lanes at once;
+      // the comparisons with the seed's best then go one lane at a time
+      int f_nm = 0, f_ho = 0, f_nd = -1;
+      double f_ch = 0.0;
+      if (!cfg.all_tracks && outcome == 3) {
+        CNT_ADD(CKF_CNT_FINISHED, 1);
+        const int nmh = PIr(Pin, r, PI_NMH);
+        f_nm = nmh & 0xffff;
+        f_ho = nmh >> 16;
+        f_nd = PIr(Pin, r, PI_NODE);
+        f_ch = PDr(Pin, r, PD_CHI2);
+      }
+      unsigned long long fm = cfg.all_tracks ? 0ull : __ballot(outcome == 3 && f_nm >= cfg.min_meas);
       while (fm) {
         const int l = __ffsll((long long)fm) - 1;
         fm &= fm - 1;
         if (lane == l) {
-          CNT_ADD(CKF_CNT_FINISHED, 1);
-          const int nmh = PIr(Pin, r, PI_NMH);
-          const int nm = nmh & 0xffff, ho = nmh >> 16, nd = PIr(Pin, r, PI_NODE);
-          const double ch = PDr(Pin, r, PD_CHI2);
-          if (nm >= cfg.min_meas && (sh_best_node[slot] < 0 || better(nm, ch, ho, nd, sh_best_nm[slot],
-                                                                      sh_best_chi2[slot], sh_best_holes[slot],
-                                                                      sh_best_node[slot], A.w.nodes))) {
+          const int nm = f_nm, ho = f_ho, nd = f_nd;
+          const double ch = f_ch;
+          if (sh_best_node[slot] < 0 || better(nm, ch, ho, nd, sh_best_nm[slot], sh_best_chi2[slot],
+                                               sh_best_holes[slot], sh_best_node[slot], A.w.nodes)) {
             sh_best_node[slot] = nd;
             sh_best_nm[slot] = nm;
             sh_best_chi2[slot] = ch;
