@@ -44,6 +44,46 @@ static_assert(sizeof(Rec) == 304, "fit record layout");
 
 size_t fit_workspace_bytes(long long cap_meas) { return (size_t)cap_meas * sizeof(Rec); }
 
+// Where a record lives.  The tracks of one full wave (64 consecutive
+// tracks t0 .. t0+63) own the workspace records [off[t0], off[t0+64]).  For
+// the first `common` measurements (the wave's shortest track) the records
+// are kept by field across the lanes: step j is a block of 64 records in
+// which word k of lane l sits at word 64 k + l (the Jacobian's floats
+// likewise after the 25 doubles), so the lanes' stores of one field are
+// contiguous.  The records after that come one after another per lane, as
+// whole 304-byte records, in lane order behind the blocks.  A partial wave
+// (or one whose CSR cannot be trusted) keeps every record whole at its CSR
+// position.  S is the stride between consecutive fields (compile time, so
+// that the field offsets are immediates).
+constexpr int kFitBlock = 64;
+
+template <int S>
+struct RecAt {
+  char* d;  // double field 0 of this record
+  char* f;  // Jacobian element 0
+  __device__ double& D(int k) const { return *reinterpret_cast<double*>(d + 8 * k * S); }
+  __device__ float& F(int i) const { return *reinterpret_cast<float*>(f + 4 * i * S); }
+};
+
+struct WaveLayout {
+  char* ws;
+  long long off0;  // the wave's first record
+  int lane, common;
+  long long a;     // this lane's first measurement (CSR)
+  __device__ bool in_block(long long j) const { return j < common; }
+  // the record of this lane's j-th measurement: in a block (j < common) ...
+  __device__ RecAt<kFitBlock> blk(long long j) const {
+    char* b = ws + (off0 + j * kFitBlock) * (long long)sizeof(Rec);
+    return RecAt<kFitBlock>{b + 8 * lane, b + 200 * kFitBlock + 4 * lane};
+  }
+  // ... or whole, behind the blocks
+  __device__ RecAt<1> whole(long long j) const {
+    const long long r = off0 + (long long)kFitBlock * common + (a - off0) - (long long)lane * common + (j - common);
+    char* rp = ws + r * (long long)sizeof(Rec);
+    return RecAt<1>{rp, rp + 200};
+  }
+};
+
 // The fit's records for callers that cannot allocate: one file-scope device
 // array per GPU, held until the process ends.  Every call on a GPU shares it
 // (calls that overlap on one GPU race); the forward pass writes each record
@@ -172,12 +212,31 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
                                             void* __restrict__ ws_raw, double* __restrict__ out_p,
                                             double* __restrict__ out_C, double* __restrict__ chi2_out,
                                             int* __restrict__ ok) {
-  Rec* __restrict__ ws = static_cast<Rec*>(ws_raw);
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x;
+  const int t0 = blockIdx.x * blockDim.x, t = t0 + lane;
   const int n_t = min(*n_tracks_p, cap_tracks);
-  if (t >= n_t) return;
-  const long long a = off[t], b = off[t + 1];
-  if (a < 0 || b > cap_meas || b < a) {  // the CSR itself cannot be trusted: touch nothing of it
+  if (t0 >= n_t) return;  // (the whole wave)
+  const bool live = t < n_t;
+  long long a = 0, b = 0;
+  bool bad = false;
+  if (live) {
+    a = off[t];
+    b = off[t + 1];
+    bad = a < 0 || b > cap_meas || b < a;
+  }
+  // the wave's record layout: its shortest track's length of steps kept by
+  // field, none when any lane's CSR cannot be trusted
+  const int len = live && !bad ? (int)min(b - a, (long long)INT_MAX) : 0;
+  int common = live && !bad ? len : INT_MAX, longest = len;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    common = min(common, __shfl_xor(common, o));
+    longest = max(longest, __shfl_xor(longest, o));
+  }
+  if (__any(live && bad) || n_t - t0 < kFitBlock) common = 0;
+  const WaveLayout lay{static_cast<char*>(ws_raw), (long long)off[t0], lane, common, a};
+  if (!live) return;
+  if (bad) {  // the CSR itself cannot be trusted: touch nothing of it
     ok[t] = -1;
     chi2_out[t] = 0.0;
     return;
@@ -204,7 +263,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
   int cur = s.surface[si];
   double chi2 = 0.0;
   for (long long k = a; k < b; ++k) {
-    Rec& R = ws[k];
+    const bool in_blk = lay.in_block(k - a);
     const int dst = msurf[k];
     // the measurement is loaded before the leg, so its loads are in flight
     // while the leg is propagated
@@ -222,20 +281,30 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
         for (int j = 0; j < 5; ++j) J[i][j] = i == j ? 1.f : 0.f;
     }
+    const auto put_pred = [&](auto R) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) R.pp[i] = p[i];
+      for (int i = 0; i < 5; ++i) R.D(i) = p[i];
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
+      for (int i = 0; i < 5; ++i)
 #pragma unroll
-      for (int j = 0; j < 5; ++j) R.F[5 * i + j] = J[i][j];
+        for (int j = 0; j < 5; ++j) R.F(5 * i + j) = J[i][j];
+    };
+    if (in_blk) put_pred(lay.blk(k - a)); else put_pred(lay.whole(k - a));
     const double m0 = lm0, m1 = lm1, v0 = lv0, v1 = lv1;
     chi2 += chi2_of(p, C, m0, m1, v0, v1);
     double po[5], Co[15];
     kf_update(p, C, m0, m1, v0, v1, po, Co);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) R.fp[i] = p[i] = po[i];
+    for (int i = 0; i < 5; ++i) p[i] = po[i];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) R.fC[i] = C[i] = Co[i];
+    for (int i = 0; i < 15; ++i) C[i] = Co[i];
+    const auto put_filt = [&](auto R) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) R.D(5 + i) = po[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) R.D(10 + i) = Co[i];
+    };
+    if (in_blk) put_filt(lay.blk(k - a)); else put_filt(lay.whole(k - a));
     if (cfg.material) {
       Module M;
       load_module(g, dst, M);
@@ -247,25 +316,30 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
   // ---- the last measurement: smoothed = filtered
   double xs[5], Cs[15];
   {
-    const Rec& R = ws[b - 1];
+    const auto get = [&](auto R) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) xs[i] = out_p[5 * (b - 1) + i] = R.fp[i];
+      for (int i = 0; i < 5; ++i) xs[i] = R.D(5 + i);
 #pragma unroll
-    for (int i = 0; i < 15; ++i) Cs[i] = out_C[15 * (b - 1) + i] = R.fC[i];
+      for (int i = 0; i < 15; ++i) Cs[i] = R.D(10 + i);
+    };
+    if (lay.in_block(b - 1 - a)) get(lay.blk(b - 1 - a)); else get(lay.whole(b - 1 - a));
+#pragma unroll
+    for (int i = 0; i < 5; ++i) out_p[5 * (b - 1) + i] = xs[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) out_C[15 * (b - 1) + i] = Cs[i];
   }
   if constexpr (!kTwo) {
     // ---- RTS
-    for (long long k = b - 2; k >= a; --k) {
-      const Rec& Rk = ws[k];
-      const Rec& Rn = ws[k + 1];
+    // one step back from k+1 to k (records Rk, Rn); false if it fails
+    const auto rts_step = [&](long long k, auto Rk, auto Rn) -> bool {
       // the prediction's covariance at k+1, as the forward pass made it:
       // the scattering of module k at the filtered state, then the leg
       // (none between two measurements of one module)
       double pC[15], kp[5];
 #pragma unroll
-      for (int i = 0; i < 15; ++i) pC[i] = Rk.fC[i];
+      for (int i = 0; i < 15; ++i) pC[i] = Rk.D(10 + i);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) kp[i] = Rk.fp[i];
+      for (int i = 0; i < 5; ++i) kp[i] = Rk.D(5 + i);
       if (cfg.material) {
         Module M;
         load_module(g, msurf[k], M);
@@ -276,11 +350,16 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
         for (int i = 0; i < 5; ++i)
 #pragma unroll
-          for (int j = 0; j < 5; ++j) Fn[i][j] = Rn.F[5 * i + j];
+          for (int j = 0; j < 5; ++j) Fn[i][j] = Rn.F(5 * i + j);
         transport_cov(Fn, pC);
       }
       double fC[5][5], G[5][5], L[5][5];
-      unpack5(Rk.fC, fC);
+      {
+        double kfC[15];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) kfC[i] = Rk.D(10 + i);
+        unpack5(kfC, fC);
+      }
       // G = F fC  (so A^T = pC^-1 G)
 #pragma unroll
       for (int i = 0; i < 5; ++i)
@@ -288,23 +367,22 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
         for (int j = 0; j < 5; ++j) {
           double acc = 0.0;
 #pragma unroll
-          for (int l = 0; l < 5; ++l) acc = fma((double)Rn.F[5 * i + l], fC[l][j], acc);
+          for (int l = 0; l < 5; ++l) acc = fma((double)Rn.F(5 * i + l), fC[l][j], acc);
           G[i][j] = acc;
         }
       unpack5(pC, L);
       if (!chol5(L)) {
-        fail_track(a, b, out_p, out_C, ok, t, 0);
-        return;
+        return false;
       }
       chol5_solve(L, G);  // G now holds X = A^T
       double d[5];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) d[i] = xs[i] - Rn.pp[i];
+      for (int i = 0; i < 5; ++i) d[i] = xs[i] - Rn.D(i);
       d[2] = wrap_phi(d[2]);
       double xn[5];
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
-        double acc = Rk.fp[i];
+        double acc = Rk.D(5 + i);
 #pragma unroll
         for (int j = 0; j < 5; ++j) acc = fma(G[j][i], d[j], acc);
         xn[i] = acc;
@@ -340,6 +418,20 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
       for (int i = 0; i < 5; ++i) out_p[5 * k + i] = xs[i];
 #pragma unroll
       for (int i = 0; i < 15; ++i) out_C[15 * k + i] = Cs[i];
+      return true;
+    };
+    // the lanes step back in one index j (a lane starts at its own last
+    // measurement), so that a block's fields are read together
+    for (long long j = longest - 2; j >= 0; --j) {
+      if (j > b - a - 2) continue;
+      const long long k = a + j;
+      const bool good = lay.in_block(j + 1) ? rts_step(k, lay.blk(j), lay.blk(j + 1))
+                        : lay.in_block(j)   ? rts_step(k, lay.blk(j), lay.whole(j + 1))
+                                            : rts_step(k, lay.whole(j), lay.whole(j + 1));
+      if (!good) {
+        fail_track(a, b, out_p, out_C, ok, t, 0);
+        return;
+      }
     }
   } else {
     // ---- two-filter: the backward information filter, combined with the
@@ -359,15 +451,19 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
       y[0] += ((double)m.loc[2ll * id] - xf[0]) / v0;
       y[1] += ((double)m.loc[2ll * id + 1] - xf[1]) / v1;
     };
-    add_meas(b - 1, ws[b - 1].fp);
-    for (long long k = b - 2; k >= a; --k) {
-      const Rec& Rk = ws[k];
-      const Rec& Rn = ws[k + 1];
+    add_meas(b - 1, xs);  // (xs: the filtered state there)
+    // one step back from k+1 to k (records Rk, Rn); false if it fails
+    const auto tf_step = [&](long long k, auto Rk, auto Rn) -> bool {
+      double kfp[5], kfC[15];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) kfp[i] = Rk.D(5 + i);
+#pragma unroll
+      for (int i = 0; i < 15; ++i) kfC[i] = Rk.D(10 + i);
       // step back through d_k+1 = a + F (d_k + w_k): Yu = F^T Y F,
       // yu = F^T (y - Y a)
       double av[5], tv[5], YF[5][5], Yu[5][5], yu[5];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) av[i] = Rn.pp[i] - Rn.fp[i];
+      for (int i = 0; i < 5; ++i) av[i] = Rn.D(i) - Rn.D(5 + i);
       av[2] = wrap_phi(av[2]);
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
@@ -382,20 +478,20 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
         for (int j = 0; j < 5; ++j) {
           double acc = 0.0;
 #pragma unroll
-          for (int l = 0; l < 5; ++l) acc = fma(Y[i][l], (double)Rn.F[5 * l + j], acc);
+          for (int l = 0; l < 5; ++l) acc = fma(Y[i][l], (double)Rn.F(5 * l + j), acc);
           YF[i][j] = acc;
         }
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
         double acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < 5; ++l) acc = fma((double)Rn.F[5 * l + i], tv[l], acc);
+        for (int l = 0; l < 5; ++l) acc = fma((double)Rn.F(5 * l + i), tv[l], acc);
         yu[i] = acc;
 #pragma unroll
         for (int j = i; j < 5; ++j) {
           double s = 0.0;
 #pragma unroll
-          for (int l = 0; l < 5; ++l) s = fma((double)Rn.F[5 * l + i], YF[l][j], s);
+          for (int l = 0; l < 5; ++l) s = fma((double)Rn.F(5 * l + i), YF[l][j], s);
           Yu[i][j] = s;
         }
       }
@@ -411,7 +507,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
         for (int i = 0; i < 15; ++i) qc[i] = 0.0;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) qp[i] = Rk.fp[i];
+        for (int i = 0; i < 5; ++i) qp[i] = kfp[i];
         Module M;
         load_module(g, msurf[k], M);
         apply_ms(M, cfg.mass, qp, qc);
@@ -446,10 +542,9 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
       }
       // weighted mean: W = C_f^-1 + Y, C = W^-1, x = x_f + C y
       double Lf[5][5], W[5][5];
-      unpack5(Rk.fC, Lf);
+      unpack5(kfC, Lf);
       if (!chol5(Lf)) {
-        fail_track(a, b, out_p, out_C, ok, t, 0);
-        return;
+        return false;
       }
 #pragma unroll
       for (int i = 0; i < 5; ++i)
@@ -465,8 +560,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
           Cm[i][j] = i == j ? 1.0 : 0.0;
         }
       if (!chol5(Ws)) {
-        fail_track(a, b, out_p, out_C, ok, t, 0);
-        return;
+        return false;
       }
       chol5_solve(Ws, Cm);  // W^-1
 #pragma unroll
@@ -475,7 +569,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
         for (int j = i; j < 5; ++j) Cs[pk(i, j)] = 0.5 * (Cm[i][j] + Cm[j][i]);
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
-        double acc = Rk.fp[i];
+        double acc = kfp[i];
 #pragma unroll
         for (int j = 0; j < 5; ++j) acc = fma(Cs[pk(min(i, j), max(i, j))], y[j], acc);
         xs[i] = acc;
@@ -486,7 +580,19 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
       for (int i = 0; i < 15; ++i) out_C[15 * k + i] = Cs[i];
       // the backward filter takes measurement k
-      add_meas(k, Rk.fp);
+      add_meas(k, kfp);
+      return true;
+    };
+    for (long long j = longest - 2; j >= 0; --j) {  // (one index j for all lanes, as for RTS)
+      if (j > b - a - 2) continue;
+      const long long k = a + j;
+      const bool good = lay.in_block(j + 1) ? tf_step(k, lay.blk(j), lay.blk(j + 1))
+                        : lay.in_block(j)   ? tf_step(k, lay.blk(j), lay.whole(j + 1))
+                                            : tf_step(k, lay.whole(j), lay.whole(j + 1));
+      if (!good) {
+        fail_track(a, b, out_p, out_C, ok, t, 0);
+        return;
+      }
     }
   }
   ok[t] = 1;
