@@ -315,6 +315,13 @@ def measure_end_to_end(ckf, geo, fld, batch, shape, stream, reps):
 # backward leg, its update and scattering, the Cholesky solve of the
 # combination and its products).  The legs' RKN4 trials are priced at the
 # search's measured trials per leg.
+# FP64 flop per work unit of ckf_seed's triplet search (CKF_SEED_CNT_*),
+# counted from the arithmetic of its cuts: an (M, T) doublet (radius
+# difference, cot, the two azimuth products and their bound) 10, a (B, M)
+# doublet 12 (its line's z at r = 0 too), a (B, T) cot comparison 1, a
+# triplet 44 (the circle through the three points, its radius and the
+# distance of closest approach).
+SEED_FLOPS = (10, 12, 1, 44)
 FIT_FORWARD = (300 + 40, 400 + 15 + 450 + 4)
 FIT_RTS = (0, 1100)
 FIT_TWO = (300 + 40, 400 + 450 + 4 + 780)
@@ -487,6 +494,12 @@ def measure_chain(ckf, geo, fld, det, cells, evs, cl, cl_ms, stream, reps):
     e1.record(stream)
     torch.cuda.synchronize()
     seed_ms = e0.elapsed_time(e1) / reps
+    work = torch.zeros(4, dtype=torch.int64, device=cl.offsets.device)
+    ckf.seed(*args, cap_seeds=int(sd["params"].shape[0]), stream=stream, counters=work)
+    torch.cuda.synchronize()
+    units = [int(x) for x in work.cpu()]
+    seed_f64 = sum(u * f for u, f in zip(units, SEED_FLOPS))
+    seed_frac = seed_f64 / PEAK_FP64 / (seed_ms * 1e-3)
     b = ckf.Batch(cells.n_events, cells.n_surfaces, cl.offsets, cl.loc[:m].contiguous(), cl.var[:m].contiguous(),
                   sd["event"].contiguous(), sd["surface"].contiguous(), sd["params"].contiguous(),
                   sd["cov"].contiguous())
@@ -526,8 +539,14 @@ def measure_chain(ckf, geo, fld, det, cells, evs, cl, cl_ms, stream, reps):
                 chain_tracks_per_s=round(res["n_tracks"] / (chain_ms * 1e-3), 1), central_particles=int(len(cen)),
                 central_found=round(eff, 5), find_status_flags=flags,
                 seed_traffic=_measured(SEED_TRAFFIC, (int(m), int(n))),
+                seed_work=dict(mt_doublets=units[0], bm_doublets=units[1], cot_comparisons=units[2],
+                               triplets=units[3]),
+                seed_roofline=dict(bound="alu", achieved=round(seed_frac * PEAK_FP64 / 1e12, 3),
+                                   peak=PEAK_FP64 / 1e12, unit="TFLOP/s", frac=round(seed_frac, 5),
+                                   fp64_flop=int(seed_f64), kernel="ckf_seed (all its kernels)"),
                 note="device times of one ckf_cluster, one ckf_seed and one ckf_find (kernel timer) on the batch; "
-                     "seed_traffic: HBM bytes of one ckf_seed call (counters)")
+                     "seed_traffic: HBM bytes of one ckf_seed call (counters); seed_roofline: the triplet search's "
+                     "counted FP64 work (SEED_FLOPS per unit) over the call's time, against the FP64 vector peak")
 
 
 def roofline_of(m, form, shape):
@@ -725,7 +744,9 @@ def main():
                           max(3, args.steps // 4))
     say(f"# seeding on the clusters: {chain['seeds']} seeds in {chain['seed_ms']:.3f} ms; track finding with them: "
         f"{chain['tracks']} tracks in {chain['find_ms']:.3f} ms; chain cells -> tracks {chain['chain_ms']:.2f} ms "
-        f"({chain['chain_tracks_per_s'] / 1e6:.2f} M tracks/s), central particles found {chain['central_found']:.4f}")
+        f"({chain['chain_tracks_per_s'] / 1e6:.2f} M tracks/s), central particles found {chain['central_found']:.4f}; "
+        f"seeding work {chain['seed_work']}, FP64 rate {chain['seed_roofline']['achieved']} TFLOP/s "
+        f"({chain['seed_roofline']['frac']:.3f} of peak)")
     say(f"# ambiguity resolution of the plain search's tracks: {amb['ms']:.2f} ms, {amb['rounds']} rounds, "
         f"{amb['removed']} of {amb['tracks_in']} removed; fake rate {amb['before']['fake_rate']:.5f} -> "
         f"{amb['after']['fake_rate']:.5f}, duplicate rate {amb['before']['duplicate_rate']:.5f} -> "

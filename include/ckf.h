@@ -481,15 +481,28 @@ ckf_status ckf_cluster(const ckf_geometry* g, const ckf_cells* cells, const floa
  * rows; seeds beyond the capacity are counted but not written): n_seeds
  * [1], seed_event, seed_surface, seed_params [cap][5], seed_cov [cap][15]
  * (the layout of ckf_seeds), seed_spacepoints [cap][3] (bottom, middle,
- * top) or NULL.  workspace: at least ckf_seed_workspace_size bytes
- * (CKF_ERR_CAPACITY).  Asynchronous on `stream`; allocates nothing. */
+ * top) or NULL.  counters [4] (device) or NULL: set by the call to the work
+ * units of the triplet search, CKF_SEED_CNT_* (for the algorithmic rate).
+ * workspace: at least ckf_seed_workspace_size bytes (CKF_ERR_CAPACITY).
+ * Asynchronous on `stream`; allocates nothing. */
 ckf_status ckf_seed_workspace_size(int32_t n_events, int32_t n_surfaces, int64_t n_sp, int32_t n_layers,
                                    size_t* bytes);
 ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas_offsets, int64_t n_sp,
                     const float* spacepoints, const float* loc, const int32_t* layers, int32_t n_layers, double bz,
                     void* workspace, size_t workspace_bytes, int64_t cap_seeds, int32_t* n_seeds,
                     int32_t* seed_event, int32_t* seed_surface, double* seed_params, double* seed_cov,
-                    int32_t* seed_spacepoints, void* stream);
+                    int32_t* seed_spacepoints, int64_t* counters, void* stream);
+
+/* Work units of ckf_seed's triplet search (counters[k]).  A middle's tops
+ * are counted once, though the on-chip path runs their test twice (to count
+ * and then to place them). */
+enum {
+  CKF_SEED_CNT_MT = 0,  /* (middle, top) doublet tests */
+  CKF_SEED_CNT_BM = 1,  /* (bottom, middle) doublet tests */
+  CKF_SEED_CNT_COT = 2, /* (bottom, top) cot comparisons */
+  CKF_SEED_CNT_TRI = 3, /* triplet tests (circle, radius, d0) */
+  CKF_SEED_CNT_N = 4
+};
 
 /* Tuning of ckf_seed's triplet search (process-wide, for later calls).  The
  * search holds a middle spacepoint's tops that pass the doublet cuts in

@@ -550,12 +550,14 @@ def cluster(geometry: Geometry, cells: CellBatch, pitch, stream=None):
 
 
 def seed(geometry: Geometry, n_events: int, meas_offsets, spacepoints, loc, layers, bz=2.0, cap_seeds=None,
-         stream=None):
+         stream=None, counters=None):
     """Triplet seeding (ckf_seed) on spacepoints in the measurement layout
     (a Clusterer's offsets, spacepoints and loc, device tensors).  layers:
-    the seeding layers' geometry ids ordered outwards.  Returns a dict of
-    device tensors (event, surface, params, cov, spacepoints) sized to the
-    number of seeds, and that number."""
+    the seeding layers' geometry ids ordered outwards.  counters: None or a
+    device int64 tensor [4] that receives the search's work units
+    (CKF_SEED_CNT_*).  Returns a dict of device tensors (event, surface,
+    params, cov, spacepoints) sized to the number of seeds, and that
+    number."""
     import torch
     lib = _abi.load()
     dev = meas_offsets.device
@@ -575,7 +577,8 @@ def seed(geometry: Geometry, n_events: int, meas_offsets, spacepoints, loc, laye
     _check(lib.ckf_seed(geometry.handle, int(n_events), _ptr(meas_offsets), n_sp, _ptr(spacepoints), _ptr(loc),
                         lay.ctypes.data_as(C.c_void_p), nl, float(bz), _ptr(ws), ws.numel(), cap, _ptr(n),
                         _ptr(out["event"]), _ptr(out["surface"]), _ptr(out["params"]), _ptr(out["cov"]),
-                        _ptr(out["spacepoints"]), _stream_handle(stream)), "ckf_seed")
+                        _ptr(out["spacepoints"]), _ptr(counters) if counters is not None else None,
+                        _stream_handle(stream)), "ckf_seed")
     torch.cuda.synchronize()  # the count is read on the host: wait for the call's stream, whichever it is
     k = int(n.cpu()[0])
     m = min(k, cap)

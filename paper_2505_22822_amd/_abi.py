@@ -99,7 +99,7 @@ SIGNATURES = {
     "ckf_cluster_workspace_size": (I32, [C.POINTER(CellsDesc), C.POINTER(C.c_size_t)]),
     "ckf_cluster": (I32, [VP, C.POINTER(CellsDesc), VP, VP, C.c_size_t, VP, VP, VP, VP, VP, VP, VP]),
     "ckf_seed_workspace_size": (I32, [I32, I32, I64, I32, C.POINTER(C.c_size_t)]),
-    "ckf_seed": (I32, [VP, I32, VP, I64, VP, VP, VP, I32, F64, VP, C.c_size_t, I64, VP, VP, VP, VP, VP, VP, VP]),
+    "ckf_seed": (I32, [VP, I32, VP, I64, VP, VP, VP, I32, F64, VP, C.c_size_t, I64, VP, VP, VP, VP, VP, VP, VP, VP]),
     "ckf_seed_set_top_cap": (I32, [I32, C.POINTER(I32)]),
     "ckf_resolve_workspace_size": (I32, [I32, I64, C.POINTER(C.c_size_t)]),
     "ckf_resolve": (I32, [VP, I32, I64, VP, VP, I64, VP, VP, I32, I32, VP, C.c_size_t, VP, VP, VP]),

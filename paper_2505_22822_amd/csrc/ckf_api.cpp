@@ -1035,7 +1035,7 @@ ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas
                     const float* spacepoints, const float* loc, const int32_t* layers, int32_t n_layers, double bz,
                     void* workspace, size_t workspace_bytes, int64_t cap_seeds, int32_t* n_seeds,
                     int32_t* seed_event, int32_t* seed_surface, double* seed_params, double* seed_cov,
-                    int32_t* seed_spacepoints, void* stream) {
+                    int32_t* seed_spacepoints, int64_t* counters, void* stream) {
   if (!g || !layers || !n_seeds || n_events < 0 || n_sp < 0 || cap_seeds < 0)
     return fail(CKF_ERR_INVALID_ARGUMENT, "seed: bad argument");
   if (n_layers < 3 || n_layers > 8) return fail(CKF_ERR_INVALID_ARGUMENT, "seed: 3 to 8 seeding layers");
@@ -1054,7 +1054,8 @@ ckf_status ckf_seed(const ckf_geometry* g, int32_t n_events, const int32_t* meas
     return fail(CKF_ERR_CAPACITY, "seed: workspace too small");
   HIP_TRY(ckf::launch_seed(g->dev, n_events, g->dev.n_surfaces, meas_offsets, n_sp, spacepoints, loc, layers,
                            n_layers, bz, workspace, cap_seeds, n_seeds, seed_event, seed_surface, seed_params,
-                           seed_cov, seed_spacepoints, static_cast<hipStream_t>(stream)),
+                           seed_cov, seed_spacepoints, reinterpret_cast<long long*>(counters),
+                           static_cast<hipStream_t>(stream)),
           "launch the seeding");
   return CKF_OK;
 }

@@ -78,7 +78,7 @@ void seed_set_top_cap(int cap);
 hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int* moff, long long n_sp,
                        const float* xyz, const float* loc, const int* layers, int n_layers, double bz, void* ws,
                        long long cap, int* n_seeds, int* event, int* surface, double* params, double* cov,
-                       int* sp_ids, hipStream_t st);
+                       int* sp_ids, long long* counters, hipStream_t st);
 size_t cluster_workspace_bytes(long long rows, long long n_cells);
 hipError_t launch_cluster(const CellsIn& c, const GeomDev& g, const float* pitch, void* ws, int* moff, float* loc,
                           float* var, float* sp, int* cell_cluster, int* status, hipStream_t st);

@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
     long long nbins, SeedLayers sl, const int* __restrict__ key, const int* __restrict__ start,
     const int* __restrict__ cnt, const int* __restrict__ sorted, const double4* __restrict__ spt,
     const unsigned* __restrict__ rlim, double rmin, double tan_dphi, int top_cap, int* __restrict__ count,
-    int2* __restrict__ best_out) {
+    int2* __restrict__ best_out, unsigned long long* __restrict__ work) {
   __shared__ double s_ct[kTriWaves][kTopCap];
   __shared__ int s_j[kTriWaves][kTopCap];
   __shared__ int s_bs[kTriWaves][kNcotPad];
@@ -280,6 +280,9 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
   const int lblock = (G % 8 == 0) ? xcd * per + blockIdx.x / 8 : blockIdx.x;
   const long long W = (long long)G * kTriWaves;
   const long long total = nbins > 0 ? (long long)start[nbins - 1] + cnt[nbins - 1] : 0;
+  // this lane's work units: (M, T) and (B, M) doublet tests, (B, T) cot
+  // comparisons, triplet (circle) tests
+  unsigned n_mt = 0, n_bm = 0, n_cot = 0, n_tri = 0;
   for (long long j = (long long)lblock * kTriWaves + w; j < total; j += W) {
     const int m = sorted[j];
     const int km = key[m];
@@ -321,6 +324,7 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
             if (jt < j1) {
               const double4 pt = spt[jt];
               pass = doublet(M, rM, P3{pt.x, pt.y, pt.z}, pt.w, false, tan_dphi, ct);
+              if (!place) ++n_mt;  // (the placing pass repeats the same tests)
             }
             if (pass) {
               if (!place) {
@@ -372,6 +376,7 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
       wave_sync();
       const int np = min(64, ptail - phead);
       if (lane < np) {
+        ++n_tri;
         const int2 q = pq[(phead + lane) & (kRing - 1)];
         const double4 pb = spt[q.x];
         try_triplet(P3{pb.x, pb.y, pb.z}, sorted[q.x], M, spt[q.y], sorted[q.y], rmin, best);
@@ -399,6 +404,7 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
         bool hit = false;
         int jt = 0;
         if (p < p1) {
+          ++n_cot;
           hit = fabs(cb - ct_s[p]) <= tol;
           jt = j_s[p];
           ++p;
@@ -433,6 +439,7 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
               const double4 pb = spt[jb];
               double cb;
               pass = doublet(P3{pb.x, pb.y, pb.z}, pb.w, M, rM, true, tan_dphi, cb);
+              ++n_bm;
             }
             const unsigned long long mask = __ballot(pass);
             if (pass) bq[(btail + lanes_below(mask)) & (kRing - 1)] = jb;
@@ -445,6 +452,7 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
           const double4 pb = spt[jb];
           const P3 B{pb.x, pb.y, pb.z};
           double cb;
+          ++n_bm;
           if (!doublet(B, pb.w, M, rM, true, tan_dphi, cb)) continue;
           const int b = sorted[jb];
           const double tol = kDcotBase + kDcotMs * (1.0 + cb * cb);
@@ -461,8 +469,11 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
               for (int jt = t0; jt < t1; ++jt) {
                 const double4 pt = spt[jt];
                 double ct;
+                ++n_mt;
                 if (!doublet(M, rM, P3{pt.x, pt.y, pt.z}, pt.w, false, tan_dphi, ct)) continue;
+                ++n_cot;
                 if (!(fabs(cb - ct) <= tol)) continue;
+                ++n_tri;
                 try_triplet(B, b, M, pt, sorted[jt], rmin, best);
               }
             }
@@ -497,6 +508,19 @@ __global__ void __launch_bounds__(64 * kTriWaves) k_sd_triplets(
     }
     if (lane == 0) count[m] = c;
   }
+  if (work) {  // summed over the wave, then one atomic per unit
+    unsigned long long u[4] = {n_mt, n_bm, n_cot, n_tri};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) u[q] += __shfl_xor(u[q], off);
+      if (lane == 0 && u[q]) atomicAdd(work + q, u[q]);
+    }
+  }
+}
+
+__global__ void k_sd_clear(unsigned long long* work) {
+  if (threadIdx.x < 4) work[threadIdx.x] = 0;
 }
 
 __global__ void k_sd_write(long long n, int n_surfaces, double bz, const int* __restrict__ row,
@@ -577,7 +601,7 @@ size_t seed_workspace_bytes(long long rows, long long n_sp, int n_events, int n_
 hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int* moff, long long n_sp,
                        const float* xyz, const float* loc, const int* layers, int n_layers, double bz, void* ws,
                        long long cap, int* n_seeds, int* event, int* surface, double* params, double* cov,
-                       int* sp_ids, hipStream_t st) {
+                       int* sp_ids, long long* counters, hipStream_t st) {
   SeedLayers sl;
   sl.n = n_layers;
   for (int q = 0; q < kMaxSeedLayers; ++q) sl.layer[q] = q < n_layers ? layers[q] : -1;
@@ -610,6 +634,8 @@ hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int
   p += 256;
   long long* sums = reinterpret_cast<long long*>(p);
   const auto blocks = [](long long m) { return dim3((unsigned)((m + kSdBlock - 1) / kSdBlock)); };
+  unsigned long long* work = reinterpret_cast<unsigned long long*>(counters);
+  if (work) hipLaunchKernelGGL(k_sd_clear, dim3(1), dim3(64), 0, st, work);
   const long long nfill = n > nbins ? n : nbins;
   if (nfill > 0) {
     hipLaunchKernelGGL(k_sd_fill, blocks(nfill), dim3(kSdBlock), 0, st, n, head, cnt, (int)nbins, rlim);
@@ -626,7 +652,7 @@ hipError_t launch_seed(const GeomDev& g, int n_events, int n_surfaces, const int
     const double rmin = kPtMin / (kKappa64 * fabs(bz));
     const double tan_dphi = tan(0.12);
     hipLaunchKernelGGL(k_sd_triplets, dim3(kTriGrid), dim3(64 * kTriWaves), 0, st, nbins, sl, key, start, cnt,
-                       sorted, spt, rlim, rmin, tan_dphi, g_top_cap.load(), count, best);
+                       sorted, spt, rlim, rmin, tan_dphi, g_top_cap.load(), count, best, work);
   }
   device_scan<OpSum, false>(count, n, head, sums, n_seeds, st);  // head now holds the seed offsets
   if (n > 0)

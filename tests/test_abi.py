@@ -133,7 +133,7 @@ def test_host_side_validation_of_the_next_rows(lib):
     layers = (C.c_int32 * 4)(0, 1, 2, 3)
     n = C.c_int32(0)
     assert lib.ckf_seed(None, 1, None, 0, None, None, layers, 4, 2.0, None, 0, 0, C.byref(n), None, None, None, None,
-                        None, None) == 1
+                        None, None, None) == 1
     mx = C.c_int32(0)
     assert lib.ckf_seed_set_top_cap(-1, C.byref(mx)) == 1 and mx.value > 0
     assert lib.ckf_seed_set_top_cap(mx.value + 1, None) == 1

@@ -141,15 +141,23 @@ def test_seed_batch_sampled_middles(ckf, det_dense, batch200):
 def test_seed_top_capacity_batch(ckf, batch200):
     """8 x mu = 200 events: the seeds are the same, bit for bit, whether the
     middles' tops are held on chip, never (every bottom scans its window),
-    or up to a capacity that part of the middles exceed."""
+    or up to a capacity that part of the middles exceed, and with or without
+    the work counters.  The counters agree where the paths do the same work:
+    every bottom is tested once per middle, and the same (B, M, T) triples
+    reach the triplet test, on every path."""
+    import torch
     geo, _, dev = batch200
-    out = []
+    out, work = [], []
     try:
         for cap in (None, 0, 160):
             ckf.seed_top_cap(cap)
-            sd, n = ckf.seed(geo, 8, *dev, LAYERS, 2.0)
+            w = torch.zeros(4, dtype=torch.int64, device="cuda")
+            sd, n = ckf.seed(geo, 8, *dev, LAYERS, 2.0, counters=w)
             out.append((n, {k: v.cpu().numpy() for k, v in sd.items()}))
-            _say(f"# seeding batch (top capacity {cap}): {n} seeds")
+            work.append([int(x) for x in w.cpu()])
+            _say(f"# seeding batch (top capacity {cap}): {n} seeds; work (MT, BM, cot, triplets) {work[-1]}")
+        sd, n = ckf.seed(geo, 8, *dev, LAYERS, 2.0)  # (the last capacity, no counters)
+        out.append((n, {k: v.cpu().numpy() for k, v in sd.items()}))
     finally:
         ckf.seed_top_cap(None)
     n0, ref = out[0]
@@ -158,6 +166,9 @@ def test_seed_top_capacity_batch(ckf, batch200):
         assert n == n0
         for k in ref:
             np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+    for w in work:
+        assert min(w) > 0 and w[2] >= w[3]
+    assert all(w[1] == work[0][1] and w[3] == work[0][3] for w in work)
 
 
 def test_chain_cells_to_tracks(ckf, det_dense):
