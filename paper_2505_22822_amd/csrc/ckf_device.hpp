@@ -442,7 +442,9 @@ __device__ __forceinline__ int pk(int i, int j) {
   return i <= j ? i * 5 - (i * (i - 1)) / 2 + (j - i) : j * 5 - (j * (j - 1)) / 2 + (i - j);
 }
 
-// C <- J C J^T (J promoted to FP64), symmetric by construction.
+// C <- J C J^T (J promoted to FP64), symmetric by construction.  J's q/p
+// row is the unit row (a leg loses no energy), so its products are the
+// covariance's own q/p row and column.
 __device__ __forceinline__ void transport_cov(const float J[5][5], double* C) {
   double R[15];
 #pragma unroll
@@ -453,13 +455,14 @@ __device__ __forceinline__ void transport_cov(const float J[5][5], double* C) {
       double s = 0.0;
 #pragma unroll
       for (int l = 0; l < 5; ++l) s = fma((double)J[i][l], C[pk(l, k)], s);
-      row[k] = s;
+      row[k] = i == 4 ? C[pk(4, k)] : s;  // (q/p row of J: the unit row)
     }
 #pragma unroll
     for (int j = i; j < 5; ++j) {
       double s = 0.0;
 #pragma unroll
       for (int k = 0; k < 5; ++k) s = fma(row[k], (double)J[j][k], s);
+      if (j == 4) s = row[4];
       R[pk(i, j)] = s;
     }
   }
@@ -534,7 +537,7 @@ __device__ __forceinline__ void apply_ms(const Module& M, double mass, const dou
   C[pk(3, 3)] += t2;
 }
 
-__device__ bool cross_cylinder(const Helix& H, float R, float& s_out) {
+__device__ bool cross_cylinder(const Helix& H, float R, float& s_out, V3& p_out, V3& T_out) {
   const float a = H.T0.x * H.T0.x + H.T0.y * H.T0.y;
   const float b = H.p0.x * H.T0.x + H.p0.y * H.T0.y;
   const float c = H.p0.x * H.p0.x + H.p0.y * H.p0.y - R * R;
@@ -558,7 +561,14 @@ __device__ bool cross_cylinder(const Helix& H, float R, float& s_out) {
   helix_at_nav(H, s, p, T);
   if (fabsf(sqrtf(p.x * p.x + p.y * p.y) - R) > 1e-3f) return false;
   s_out = s;
+  p_out = p;
+  T_out = T;
   return true;
+}
+
+__device__ __forceinline__ bool cross_cylinder(const Helix& H, float R, float& s_out) {
+  V3 p, T;
+  return cross_cylinder(H, R, s_out, p, T);
 }
 
 __device__ bool cross_zplane(const Helix& H, float Z, float& s_out) {
@@ -756,9 +766,10 @@ __device__ int list_layer(const GeomDev& g, int l, V3 P, V3 T, V3 k, float s_bas
 
 // The next navigation layer from free state (p, T, lam) in global
 // coordinates: the unvisited layer whose envelope the local helix meets
-// first within its extent and the path budget.  Returns -1 if none.
+// first within its extent and the path budget, with the crossing's path,
+// point and direction.  Returns -1 if none.
 __device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long mask, float budget, float& s_best,
-                          int& n_tried) {
+                          V3& p_best, V3& T_best, int& n_tried) {
   const float rperp = sqrtf(H.p0.x * H.p0.x + H.p0.y * H.p0.y);
   int best = -1;
   s_best = INFINITY;
@@ -783,13 +794,14 @@ __device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long m
     }
     ++n_tried;
     float s;
-    if (!cross_cylinder(H, Lr.pos, s)) continue;
     V3 p, T;
-    helix_at_nav(H, s, p, T);
+    if (!cross_cylinder(H, Lr.pos, s, p, T)) continue;
     if (p.z < Lr.lo || p.z > Lr.hi) continue;
     if (s > budget) break;
     best = l;
     s_best = s;
+    p_best = p;
+    T_best = T;
     break;
   }
   // disks on the side the track moves to, by |z|
@@ -810,6 +822,8 @@ __device__ int next_layer(const GeomDev& g, const Helix& H, unsigned long long m
     if (s < s_best || (s == s_best && l < best)) {
       best = l;
       s_best = s;
+      p_best = p;
+      T_best = T;
     }
     break;
   }

@@ -467,7 +467,8 @@ __device__ __forceinline__ void fin_append(const Workspace& w, int* status, int 
 
 // C <- J C J^T on a pool record's covariance (J promoted to FP64), each new
 // element stored as soon as it is formed; the three the gate needs are
-// returned.
+// returned.  J's q/p row is the unit row (no energy loss along a leg), so
+// its products are the covariance's own q/p row and column.
 __device__ __forceinline__ void transport_cov_rec(const float J[5][5], const Pool& P, int r, double& c00, double& c01,
                                                   double& c11) {
   double C[15];
@@ -480,13 +481,14 @@ __device__ __forceinline__ void transport_cov_rec(const float J[5][5], const Poo
       double s = 0.0;
 #pragma unroll
       for (int l = 0; l < 5; ++l) s = fma((double)J[i][l], C[pk(l, k)], s);
-      row[k] = s;
+      row[k] = i == 4 ? C[pk(4, k)] : s;  // (q/p row of J: the unit row)
     }
 #pragma unroll
     for (int j = i; j < 5; ++j) {
       double s = 0.0;
 #pragma unroll
       for (int k = 0; k < 5; ++k) s = fma(row[k], (double)J[j][k], s);
+      if (j == 4) s = row[4];
       if (i == 0 && j == 0) c00 = s;
       if (i == 0 && j == 1) c01 = s;
       if (i == 1 && j == 1) c11 = s;
@@ -622,7 +624,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
 #pragma unroll
           for (int k = 0; k < 15; ++k) C[k] = A.s.cov[15 * seed + k];
           c.surf = A.s.surface[seed];
-          c.mask = 1ull << g.mod[c.surf].layer;
+          c.mask = 0;  // the seed's own layer is marked at its first step (its module is loaded there)
 #pragma unroll
           for (int k = 0; k < kMaxList; ++k) c.list[k] = -1;
           c.nlist = 0;
@@ -702,6 +704,7 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
         load_module(g, surf, Am);
         leg_start(Am, p, L, uA, vA);
         origin = ld3(Am.c);
+        if (root) mask |= 1ull << Am.layer;
         go = !root;
         // one listing call for both the seed's own layer and a newly found
         // layer, so that a wave holding both kinds of lanes lists once
@@ -728,14 +731,16 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
           float sL;
           CNT_ADD(CKF_CNT_NAV, 1);
           const long long t_next = kCount ? clock64() : 0;
-          const int nl = next_layer(g, H, mask, cfg.path_max - path, sL, c_next);
+          V3 Pn, Tn;  // the crossing of the layer found (its point and direction)
+          const int nl = next_layer(g, H, mask, cfg.path_max - path, sL, Pn, Tn, c_next);
           if (kCount) CNT_ADD(CKF_CNT_CYC_NEXT, (int)(clock64() - t_next));
           if (nl < 0) {
             outcome = 3;
             go = false;
           } else {
             mask |= 1ull << nl;
-            helix_at_nav(H, sL, Pl, Tl);
+            Pl = Pn;
+            Tl = Tn;
             need_list = true;
             lay = nl;
             excl = -1;
