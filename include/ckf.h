@@ -388,11 +388,15 @@ ckf_status ckf_mlp_adam(float* params, float* m, float* v, const float* grad, in
  * caller-owned): params [cap_meas][5] and cov [cap_meas][15] smoothed at
  * each measurement (NaN for a track that failed), chi2 [cap_tracks] (sum of
  * the forward filter's chi2), ok [cap_tracks]: 1 fitted, 0 a leg failed or
- * a covariance lost positive definiteness, -1 ids out of range (offsets
- * outside [0, cap_meas] leave the track's outputs untouched).  workspace:
- * at least ckf_fit_workspace_size(cap_meas) bytes of device memory
- * (CKF_ERR_CAPACITY if smaller).  Asynchronous on `stream`; allocates
- * nothing. */
+ * a covariance lost positive definiteness, -1 ids out of range or a track
+ * of more than 64 measurements (ckf_find's step bound; NaN outputs), -1
+ * with the outputs untouched for offsets outside [0, cap_meas] or tracks
+ * whose ranges overlap (more measurements in all than cap_meas: then no
+ * track of the call is fitted).  The tracks are dealt to 64-lane waves
+ * longest first, so a wave's lanes take about the same number of steps.
+ * workspace: at least ckf_fit_workspace_size(cap_meas) bytes of device
+ * memory (CKF_ERR_CAPACITY if smaller).  Asynchronous on `stream`;
+ * allocates nothing. */
 #define CKF_SMOOTHER_RTS 0
 #define CKF_SMOOTHER_TWO_FILTER 1
 ckf_status ckf_fit_workspace_size(int64_t cap_meas, size_t* bytes);
@@ -408,7 +412,7 @@ ckf_status ckf_fit(const ckf_geometry* g, const ckf_field* f, const ckf_measurem
  * minus the workspace: the fit's per-measurement records live in a fixed
  * device array of the library, ckf_fit_noalloc_max_bytes() = 64 MiB per GPU
  * (allocated when the library's code is loaded on a GPU and held until the
- * process ends), enough for ckf_fit_noalloc_max_meas() = 220,752
+ * process ends), enough for ckf_fit_noalloc_max_meas() = 213,823
  * measurements; a larger cap_meas fails with CKF_ERR_CAPACITY and launches
  * nothing.  The call itself allocates nothing.  All calls on one GPU share
  * that array: calls that can overlap on one GPU (different streams, or

@@ -984,7 +984,13 @@ ckf_status ckf_fit_noalloc(const ckf_geometry* g, const ckf_field* f, const ckf_
 size_t ckf_fit_noalloc_max_bytes(void) { return size_t(64) << 20; }
 
 int64_t ckf_fit_noalloc_max_meas(void) {
-  return (int64_t)(ckf_fit_noalloc_max_bytes() / ckf::fit_workspace_bytes(1));
+  // the largest capacity whose workspace fits (the size grows with it)
+  int64_t lo = 0, hi = (int64_t)(ckf_fit_noalloc_max_bytes() / 4);
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (ckf::fit_workspace_bytes(mid) <= ckf_fit_noalloc_max_bytes()) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 ckf_status ckf_cluster_workspace_size(const ckf_cells* c, size_t* bytes) {

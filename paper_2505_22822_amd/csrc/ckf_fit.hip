@@ -42,21 +42,41 @@ struct alignas(16) Rec {
 };
 static_assert(sizeof(Rec) == 304, "fit record layout");
 
-size_t fit_workspace_bytes(long long cap_meas) { return (size_t)cap_meas * sizeof(Rec); }
-
-// Where a record lives.  The tracks of one full wave (64 consecutive
-// tracks t0 .. t0+63) own the workspace records [off[t0], off[t0+64]).  For
-// the first `common` measurements (the wave's shortest track) the records
-// are kept by field across the lanes: step j is a block of 64 records in
-// which word k of lane l sits at word 64 k + l (the Jacobian's floats
-// likewise after the 25 doubles), so the lanes' stores of one field are
-// contiguous.  The records after that come one after another per lane, as
-// whole 304-byte records, in lane order behind the blocks.  A partial wave
-// (or one whose CSR cannot be trusted) keeps every record whole at its CSR
-// position.  S is the stride between consecutive fields (compile time, so
-// that the field offsets are immediates).
+// Tracks are fitted in waves of 64 lanes, longest tracks first: a counting
+// sort by measurement count (1 .. kFitMaxLen) deals them to waves, so that
+// the lanes of a wave have (nearly) the same number of steps.  Wave w's
+// records are maxlen_w blocks of 64 records: step j of lane l is record l of
+// the wave's block j, kept by field (word k of lane l at word 64 k + l, the
+// Jacobian's floats likewise after the 25 doubles), so the lanes' stores and
+// loads of one field are contiguous.  With the tracks in descending order,
+// 64 maxlen_w <= the measurements of wave w-1, so all waves need at most
+// cap_meas / 64 + kFitMaxLen blocks.  Empty tracks are settled in the sort
+// pass; a track of more than kFitMaxLen measurements is not fitted.
 constexpr int kFitBlock = 64;
+constexpr int kFitMaxLen = 64;  // the finder's step bound (kMaxSteps)
+static_assert(kFitMaxLen == kMaxSteps, "fit length bound");
 
+long long fit_blocks(long long cap_meas) { return cap_meas / kFitBlock + kFitMaxLen + 1; }
+static size_t fit_al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// the workspace: record blocks, the sorted track order, the sort's counters
+struct FitSort {
+  int cnt[kFitMaxLen + 1];    // tracks per length
+  int start[kFitMaxLen + 1];  // first sorted position of each length (longest first)
+  int fill[kFitMaxLen + 1];
+  unsigned long long total;   // measurements of the sorted tracks
+  int n_sorted;               // tracks in the sorted order
+  int bad;                    // the tracks' ranges overlap: nothing is fitted
+};
+
+size_t fit_workspace_bytes(long long cap_meas) {
+  const long long cm = cap_meas > 0 ? cap_meas : 1;
+  return fit_al256((size_t)fit_blocks(cap_meas) * kFitBlock * sizeof(Rec)) + fit_al256((size_t)cm * 4) +
+         fit_al256(sizeof(FitSort));
+}
+
+// S is the stride between consecutive fields of a record (compile time, so
+// that the field offsets are immediates).
 template <int S>
 struct RecAt {
   char* d;  // double field 0 of this record
@@ -67,27 +87,20 @@ struct RecAt {
 
 struct WaveLayout {
   char* ws;
-  long long off0;  // the wave's first record
-  int lane, common;
-  long long a;     // this lane's first measurement (CSR)
-  __device__ bool in_block(long long j) const { return j < common; }
-  // the record of this lane's j-th measurement: in a block (j < common) ...
+  long long base;  // the wave's first block
+  int lane;
+  // the record of this lane's j-th measurement
   __device__ RecAt<kFitBlock> blk(long long j) const {
-    char* b = ws + (off0 + j * kFitBlock) * (long long)sizeof(Rec);
+    char* b = ws + (base + j) * (long long)(kFitBlock * sizeof(Rec));
     return RecAt<kFitBlock>{b + 8 * lane, b + 200 * kFitBlock + 4 * lane};
-  }
-  // ... or whole, behind the blocks
-  __device__ RecAt<1> whole(long long j) const {
-    const long long r = off0 + (long long)kFitBlock * common + (a - off0) - (long long)lane * common + (j - common);
-    char* rp = ws + r * (long long)sizeof(Rec);
-    return RecAt<1>{rp, rp + 200};
   }
 };
 
-// The fit's records for callers that cannot allocate: one file-scope device
-// array per GPU, held until the process ends.  Every call on a GPU shares it
-// (calls that overlap on one GPU race); the forward pass writes each record
-// before the smoother reads it, so nothing needs clearing between calls.
+// The fit's workspace for callers that cannot allocate: one file-scope
+// device array per GPU, held until the process ends.  Every call on a GPU
+// shares it (calls that overlap on one GPU race).  The length sort's
+// counters are cleared by a fill kernel at the start of every call, and the
+// forward pass writes each record before the smoother reads it.
 constexpr size_t kFitScratchBytes = size_t(64) << 20;
 static __device__ __align__(256) char scratch[kFitScratchBytes];
 
@@ -204,41 +217,135 @@ __device__ __forceinline__ void fail_track(long long a, long long b, double* out
   ok[t] = code;
 }
 
+__global__ void k_fit_sort_clear(FitSort* fs) {
+  const int i = threadIdx.x;
+  if (i <= kFitMaxLen) fs->cnt[i] = fs->fill[i] = 0;
+  if (i == 0) {
+    fs->total = 0ull;
+    fs->n_sorted = 0;
+    fs->bad = 0;
+  }
+}
+
+constexpr int kSortBlock = 256;
+
+// One thread per track: a CSR the fit cannot trust (ok -1, outputs
+// untouched), an empty track (ok 1, or -1 for a seed out of range) and a
+// track longer than kFitMaxLen (ok -1, NaN outputs) are settled here; the
+// others are counted per length (a workgroup's histogram in LDS, then one
+// global atomic per length it holds).
+__global__ void __launch_bounds__(kSortBlock) k_fit_sort_count(
+    const int* __restrict__ n_tracks_p, int cap_tracks, long long cap_meas, const int* __restrict__ off,
+    const int* __restrict__ seed, SeedsIn s, int n_surfaces, FitSort* fs, double* __restrict__ out_p,
+    double* __restrict__ out_C, double* __restrict__ chi2_out, int* __restrict__ ok) {
+  __shared__ int h[kFitMaxLen + 1];
+  __shared__ unsigned long long tot;
+  const int i = threadIdx.x;
+  if (i <= kFitMaxLen) h[i] = 0;
+  if (i == 0) tot = 0ull;
+  __syncthreads();
+  const int t = blockIdx.x * kSortBlock + i;
+  if (t < min(*n_tracks_p, cap_tracks)) {
+    const long long a = off[t], b = off[t + 1];
+    if (a < 0 || b > cap_meas || b < a) {  // the CSR itself cannot be trusted: touch nothing of it
+      ok[t] = -1;
+      chi2_out[t] = 0.0;
+    } else if (b == a) {
+      const int si = seed[t];
+      ok[t] = si >= 0 && si < s.n && s.surface[si] >= 0 && s.surface[si] < n_surfaces ? 1 : -1;
+      chi2_out[t] = 0.0;
+    } else if (b - a > kFitMaxLen) {
+      chi2_out[t] = 0.0;
+      fail_track(a, b, out_p, out_C, ok, t, -1);
+    } else {
+      atomicAdd(&h[b - a], 1);
+      atomicAdd(&tot, (unsigned long long)(b - a));
+    }
+  }
+  __syncthreads();
+  if (i <= kFitMaxLen && h[i] > 0) atomicAdd(&fs->cnt[i], h[i]);
+  if (i == 0 && tot > 0) atomicAdd(&fs->total, tot);
+}
+
+// One thread: each length's first position in the order (longest first).
+// Tracks whose ranges overlap (more measurements than the capacity) make
+// the whole call unfittable.
+__global__ void k_fit_sort_offsets(long long cap_meas, FitSort* fs) {
+  if (threadIdx.x != 0) return;
+  int pos = 0;
+  for (int l = kFitMaxLen; l >= 1; --l) {
+    fs->start[l] = pos;
+    pos += fs->cnt[l];
+  }
+  fs->bad = fs->total > (unsigned long long)cap_meas ? 1 : 0;
+  fs->n_sorted = fs->bad ? 0 : pos;
+}
+
+// Each sorted track's position: its length's start, the range its
+// workgroup reserved for that length (one global atomic per length), its
+// rank among the workgroup's tracks of that length (LDS atomics).
+__global__ void __launch_bounds__(kSortBlock) k_fit_sort_place(const int* __restrict__ n_tracks_p, int cap_tracks,
+                                                             long long cap_meas, const int* __restrict__ off,
+                                                             FitSort* fs, int* __restrict__ order,
+                                                             double* __restrict__ chi2_out, int* __restrict__ ok) {
+  __shared__ int h[kFitMaxLen + 1], base[kFitMaxLen + 1];
+  const int i = threadIdx.x;
+  if (i <= kFitMaxLen) h[i] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * kSortBlock + i;
+  int l = 0, r = 0;
+  if (t < min(*n_tracks_p, cap_tracks)) {
+    const long long a = off[t], b = off[t + 1];
+    if (a >= 0 && b <= cap_meas && b > a && b - a <= kFitMaxLen) {  // (the others were settled by the count pass)
+      l = (int)(b - a);
+      if (fs->bad) {
+        ok[t] = -1;
+        chi2_out[t] = 0.0;
+        l = 0;
+      } else {
+        r = atomicAdd(&h[l], 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (i >= 1 && i <= kFitMaxLen && h[i] > 0) base[i] = atomicAdd(&fs->fill[i], h[i]);
+  __syncthreads();
+  if (l > 0) order[fs->start[l] + base[l] + r] = t;
+}
+
+// The first block of wave w: the blocks of the waves before it, each as many
+// as its first (longest) track has measurements.
+__device__ __forceinline__ long long wave_base(const FitSort* fs, int w) {
+  long long base = 0;
+  const long long end = (long long)w * kFitBlock;  // positions before the wave
+  for (int l = kFitMaxLen; l >= 1; --l) {
+    const long long p0 = fs->start[l], p1 = min(p0 + fs->cnt[l], end);
+    if (p1 > p0)  // waves whose first position lies in [p0, p1)
+      base += (long long)l * ((p1 + kFitBlock - 1) / kFitBlock - (p0 + kFitBlock - 1) / kFitBlock);
+  }
+  return base;
+}
+
 template <bool kMap, bool kTwo>
 __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, MeasIn m, SeedsIn s,
-                                            const int* __restrict__ n_tracks_p, int cap_tracks, long long cap_meas,
                                             const int* __restrict__ off, const int* __restrict__ meas,
                                             const int* __restrict__ msurf, const int* __restrict__ seed,
-                                            void* __restrict__ ws_raw, double* __restrict__ out_p,
-                                            double* __restrict__ out_C, double* __restrict__ chi2_out,
-                                            int* __restrict__ ok) {
+                                            void* __restrict__ ws_raw, const FitSort* __restrict__ fs,
+                                            const int* __restrict__ order, long long n_blocks,
+                                            double* __restrict__ out_p, double* __restrict__ out_C,
+                                            double* __restrict__ chi2_out, int* __restrict__ ok) {
   const int lane = threadIdx.x;
-  const int t0 = blockIdx.x * blockDim.x, t = t0 + lane;
-  const int n_t = min(*n_tracks_p, cap_tracks);
-  if (t0 >= n_t) return;  // (the whole wave)
-  const bool live = t < n_t;
-  long long a = 0, b = 0;
-  bool bad = false;
-  if (live) {
-    a = off[t];
-    b = off[t + 1];
-    bad = a < 0 || b > cap_meas || b < a;
-  }
-  // the wave's record layout: its shortest track's length of steps kept by
-  // field, none when any lane's CSR cannot be trusted
-  const int len = live && !bad ? (int)min(b - a, (long long)INT_MAX) : 0;
-  int common = live && !bad ? len : INT_MAX, longest = len;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    common = min(common, __shfl_xor(common, o));
-    longest = max(longest, __shfl_xor(longest, o));
-  }
-  if (__any(live && bad) || n_t - t0 < kFitBlock) common = 0;
-  const WaveLayout lay{static_cast<char*>(ws_raw), (long long)off[t0], lane, common, a};
-  if (!live) return;
-  if (bad) {  // the CSR itself cannot be trusted: touch nothing of it
-    ok[t] = -1;
-    chi2_out[t] = 0.0;
+  const int w = blockIdx.x, q = w * kFitBlock + lane;  // this lane's position in the sorted order
+  const int n_sorted = fs->n_sorted;
+  if (w * kFitBlock >= n_sorted) return;  // (the whole wave)
+  // the wave's tracks, longest first: its first track's length is its blocks
+  const int t = q < n_sorted ? order[q] : -1;
+  const int longest = (int)(off[order[w * kFitBlock] + 1] - off[order[w * kFitBlock]]);
+  const WaveLayout lay{static_cast<char*>(ws_raw), wave_base(fs, w), lane};
+  if (t < 0) return;
+  const long long a = off[t], b = off[t + 1];
+  if (lay.base + longest > n_blocks) {  // (cannot happen: the sort's bound)
+    fail_track(a, b, out_p, out_C, ok, t, -1);
     return;
   }
   const int si = seed[t];
@@ -250,10 +357,6 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
     fail_track(a, b, out_p, out_C, ok, t, -1);
     return;
   }
-  if (b == a) {
-    ok[t] = 1;
-    return;
-  }
   // ---- forward filter
   double p[5], C[15];
 #pragma unroll
@@ -263,7 +366,6 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
   int cur = s.surface[si];
   double chi2 = 0.0;
   for (long long k = a; k < b; ++k) {
-    const bool in_blk = lay.in_block(k - a);
     const int dst = msurf[k];
     // the measurement is loaded before the leg, so its loads are in flight
     // while the leg is propagated
@@ -289,7 +391,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
         for (int j = 0; j < 5; ++j) R.F(5 * i + j) = J[i][j];
     };
-    if (in_blk) put_pred(lay.blk(k - a)); else put_pred(lay.whole(k - a));
+    put_pred(lay.blk(k - a));
     const double m0 = lm0, m1 = lm1, v0 = lv0, v1 = lv1;
     chi2 += chi2_of(p, C, m0, m1, v0, v1);
     double po[5], Co[15];
@@ -304,7 +406,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
       for (int i = 0; i < 15; ++i) R.D(10 + i) = Co[i];
     };
-    if (in_blk) put_filt(lay.blk(k - a)); else put_filt(lay.whole(k - a));
+    put_filt(lay.blk(k - a));
     if (cfg.material) {
       Module M;
       load_module(g, dst, M);
@@ -322,7 +424,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
 #pragma unroll
       for (int i = 0; i < 15; ++i) Cs[i] = R.D(10 + i);
     };
-    if (lay.in_block(b - 1 - a)) get(lay.blk(b - 1 - a)); else get(lay.whole(b - 1 - a));
+    get(lay.blk(b - 1 - a));
 #pragma unroll
     for (int i = 0; i < 5; ++i) out_p[5 * (b - 1) + i] = xs[i];
 #pragma unroll
@@ -425,10 +527,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
     for (long long j = longest - 2; j >= 0; --j) {
       if (j > b - a - 2) continue;
       const long long k = a + j;
-      const bool good = lay.in_block(j + 1) ? rts_step(k, lay.blk(j), lay.blk(j + 1))
-                        : lay.in_block(j)   ? rts_step(k, lay.blk(j), lay.whole(j + 1))
-                                            : rts_step(k, lay.whole(j), lay.whole(j + 1));
-      if (!good) {
+      if (!rts_step(k, lay.blk(j), lay.blk(j + 1))) {
         fail_track(a, b, out_p, out_C, ok, t, 0);
         return;
       }
@@ -586,10 +685,7 @@ __global__ void __launch_bounds__(64) k_fit(GeomDev g, FieldDev F, CfgDev cfg, M
     for (long long j = longest - 2; j >= 0; --j) {  // (one index j for all lanes, as for RTS)
       if (j > b - a - 2) continue;
       const long long k = a + j;
-      const bool good = lay.in_block(j + 1) ? tf_step(k, lay.blk(j), lay.blk(j + 1))
-                        : lay.in_block(j)   ? tf_step(k, lay.blk(j), lay.whole(j + 1))
-                                            : tf_step(k, lay.whole(j), lay.whole(j + 1));
-      if (!good) {
+      if (!tf_step(k, lay.blk(j), lay.blk(j + 1))) {
         fail_track(a, b, out_p, out_C, ok, t, 0);
         return;
       }
@@ -605,22 +701,34 @@ hipError_t launch_fit(const GeomDev& g, const FieldDev& f, const CfgDev& cfg, co
                       const int* msurf, const int* seed, bool two_filter, void* ws, double* out_p, double* out_C,
                       double* chi2, int* ok, hipStream_t st) {
   if (cap_tracks <= 0) return hipSuccess;
+  const long long n_blocks = fit_blocks(cap_meas);
+  char* p = static_cast<char*>(ws);
+  char* rec = p;
+  p += fit_al256((size_t)n_blocks * kFitBlock * sizeof(Rec));
+  int* order = reinterpret_cast<int*>(p);
+  p += fit_al256((size_t)(cap_meas > 0 ? cap_meas : 1) * 4);
+  FitSort* fs = reinterpret_cast<FitSort*>(p);
+  const dim3 tg((cap_tracks + kSortBlock - 1) / kSortBlock), tb(kSortBlock);
+  hipLaunchKernelGGL(k_fit_sort_clear, dim3(1), dim3(128), 0, st, fs);
+  hipLaunchKernelGGL(k_fit_sort_count, tg, tb, 0, st, n_tracks, cap_tracks, cap_meas, off, seed, s, g.n_surfaces, fs,
+                     out_p, out_C, chi2, ok);
+  hipLaunchKernelGGL(k_fit_sort_offsets, dim3(1), dim3(64), 0, st, cap_meas, fs);
+  hipLaunchKernelGGL(k_fit_sort_place, tg, tb, 0, st, n_tracks, cap_tracks, cap_meas, off, fs, order, chi2, ok);
   const dim3 grid((cap_tracks + 63) / 64), block(64);
-  void* w = ws;
   if (f.map) {
     if (two_filter)
-      hipLaunchKernelGGL((k_fit<true, true>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks, cap_meas,
-                         off, meas, msurf, seed, w, out_p, out_C, chi2, ok);
+      hipLaunchKernelGGL((k_fit<true, true>), grid, block, 0, st, g, f, cfg, m, s, off, meas, msurf, seed, rec, fs,
+                         order, n_blocks, out_p, out_C, chi2, ok);
     else
-      hipLaunchKernelGGL((k_fit<true, false>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks, cap_meas,
-                         off, meas, msurf, seed, w, out_p, out_C, chi2, ok);
+      hipLaunchKernelGGL((k_fit<true, false>), grid, block, 0, st, g, f, cfg, m, s, off, meas, msurf, seed, rec, fs,
+                         order, n_blocks, out_p, out_C, chi2, ok);
   } else {
     if (two_filter)
-      hipLaunchKernelGGL((k_fit<false, true>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks, cap_meas,
-                         off, meas, msurf, seed, w, out_p, out_C, chi2, ok);
+      hipLaunchKernelGGL((k_fit<false, true>), grid, block, 0, st, g, f, cfg, m, s, off, meas, msurf, seed, rec, fs,
+                         order, n_blocks, out_p, out_C, chi2, ok);
     else
-      hipLaunchKernelGGL((k_fit<false, false>), grid, block, 0, st, g, f, cfg, m, s, n_tracks, cap_tracks,
-                         cap_meas, off, meas, msurf, seed, w, out_p, out_C, chi2, ok);
+      hipLaunchKernelGGL((k_fit<false, false>), grid, block, 0, st, g, f, cfg, m, s, off, meas, msurf, seed, rec, fs,
+                         order, n_blocks, out_p, out_C, chi2, ok);
   }
   return hipGetLastError();
 }

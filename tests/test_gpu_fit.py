@@ -134,7 +134,10 @@ def test_fit_of_gpu_tracks_properties(ckf, det_dense):
 def test_fit_edge_cases(ckf, det_dense):
     """No tracks; a track with a measurement id out of range (ok -1, NaN
     outputs); offsets beyond the capacity (ok -1, outputs untouched); a
-    short workspace (CKF_ERR_CAPACITY); an unknown smoother."""
+    track longer than the finder's 64 steps (ok -1, NaN outputs) beside an
+    empty one (ok 1) and a normal one (fitted); tracks whose ranges overlap
+    (ok -1, outputs untouched); a short workspace (CKF_ERR_CAPACITY); an
+    unknown smoother."""
     import torch
     import ctypes as C
     from paper_2505_22822_amd import _abi
@@ -161,6 +164,26 @@ def test_fit_edge_cases(ckf, det_dense):
     assert list(g["ok"]) == [-1, -1]
     p = f.params.cpu().numpy()
     assert np.all(np.isnan(p[:2])) and np.all(p[2:] == 7.0)
+    # 65 measurements on the seed's module; an empty track; one measurement
+    t2 = dict(n_tracks=dev(np.array([3], np.int32)), offsets=dev(np.array([0, 65, 65, 66], np.int32)),
+              meas=dev(np.zeros(66, np.int32)), meas_surface=dev(np.full(66, s, np.int32)),
+              seed=dev(np.zeros(3, np.int32)))
+    f = ckf.Fitter(geo, fld, b, t2)
+    f.enqueue()
+    g = f.result()
+    assert list(g["ok"]) == [-1, 1, 1]
+    p = f.params.cpu().numpy()
+    assert np.all(np.isnan(p[:65])) and np.all(np.isfinite(p[65]))
+    # offsets going back: the first and the third track share measurements,
+    # 5 in all against a capacity of 3 (the second track's range is reversed)
+    t3 = dict(n_tracks=dev(np.array([3], np.int32)), offsets=dev(np.array([0, 3, 1, 3], np.int32)),
+              meas=dev(np.zeros(3, np.int32)), meas_surface=dev(np.full(3, s, np.int32)),
+              seed=dev(np.zeros(3, np.int32)))
+    f = ckf.Fitter(geo, fld, b, t3)
+    f.params.fill_(7.0)
+    f.enqueue()
+    g = f.result()
+    assert list(g["ok"]) == [-1, -1, -1] and np.all(f.params.cpu().numpy() == 7.0)
     lib = _abi.load()
     cfg = ckf.config()
     assert lib.ckf_fit(geo.handle, fld.handle, C.byref(f._meas), C.byref(f._seeds), C.byref(cfg),

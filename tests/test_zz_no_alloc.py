@@ -31,7 +31,9 @@ def test_fit_noalloc_equals_fit(det_dense):
     fld = ckf.UniformField(0, 0, 2.0)
     p = lambda t: C.c_void_p(t.data_ptr())
     limit = int(lib.ckf_fit_noalloc_max_meas())
-    assert limit * 304 <= int(lib.ckf_fit_noalloc_max_bytes())
+    nb = C.c_size_t(0)
+    assert lib.ckf_fit_workspace_size(limit, C.byref(nb)) == 0 and nb.value <= int(lib.ckf_fit_noalloc_max_bytes())
+    assert lib.ckf_fit_workspace_size(limit + 1, C.byref(nb)) == 0 and nb.value > int(lib.ckf_fit_noalloc_max_bytes())
     sizes = []
     for seed, mu in ((41, 60), (42, 20)):  # the second call has the smaller input
         ev = make_event(det_dense, seed, mu=mu)
