@@ -20,23 +20,11 @@ namespace ckf {
 // ---------------------------------------------------------------------------
 // measurement preparation
 
-// Sort key of a loc0: NaN sorts as +infinity (after every finite value), so
-// that (key, index) is a strict total order and the ranks of a row are a
-// permutation of it whatever the values.  Such a measurement never lies
-// inside a chi2 window and its chi2 is never accepted.
-__device__ __forceinline__ float loc0_key(float x) { return x != x ? INFINITY : x; }
-
-constexpr int kShortRow = 8;  // rows up to this many measurements are sorted in registers
-
 // Pass 1, one thread per (event, module) row: validate the offsets (the
-// rows must tile [0, n_meas) exactly, so every measurement gets a row) and
-// the row's largest var0.  A row of at most kShortRow measurements is put in
-// (loc0 key, index) order here, in registers (each measurement's rank by
-// comparisons within the row), and its measurements tagged -1; a longer
-// row's measurements are tagged with the row for pass 2.
+// rows must tile [0, n_meas) exactly, so every measurement gets a row), tag
+// every measurement with its row, largest var0 of the row.
 __global__ void k_meas_rows(int n_rows, long long n_meas, const int* __restrict__ offsets,
-                            const float* __restrict__ loc, const float* __restrict__ var, int* row_of, float* maxv0,
-                            float4* sorted, float* key, int* id, int* status) {
+                            const float* __restrict__ var, int* row_of, float* maxv0, int* status) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n_rows) return;
   const int a = offsets[row], b = offsets[row + 1];
@@ -46,51 +34,23 @@ __global__ void k_meas_rows(int n_rows, long long n_meas, const int* __restrict_
     maxv0[row] = 0.f;
     return;
   }
-  const int n = b - a;
   float mv = 0.f;
-  if (n <= kShortRow) {
-    float2 l[kShortRow], v[kShortRow];
-    float x[kShortRow];
-#pragma unroll
-    for (int k = 0; k < kShortRow; ++k) {  // the row's loads in flight together
-      if (k < n) {
-        l[k] = reinterpret_cast<const float2*>(loc)[a + k];
-        v[k] = reinterpret_cast<const float2*>(var)[a + k];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kShortRow; ++k) {
-      if (k < n) {
-        x[k] = loc0_key(l[k].x);
-        mv = fmaxf(mv, v[k].x);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kShortRow; ++i) {
-      if (i >= n) break;
-      int rank = 0;
-#pragma unroll
-      for (int j = 0; j < kShortRow; ++j)
-        if (j < n) rank += (x[j] < x[i] || (x[j] == x[i] && j < i)) ? 1 : 0;
-      const int d = a + rank;
-      sorted[d] = make_float4(x[i], l[i].y, v[i].x, v[i].y);
-      key[d] = x[i];
-      id[d] = a + i;
-      row_of[a + i] = -1;
-    }
-  } else {
 #pragma unroll 8  // eight independent loads in flight instead of one round trip per measurement
-    for (int i = a; i < b; ++i) {
-      row_of[i] = row;
-      mv = fmaxf(mv, var[2 * i]);
-    }
+  for (int i = a; i < b; ++i) {
+    row_of[i] = row;
+    mv = fmaxf(mv, var[2 * i]);
   }
   maxv0[row] = mv;
 }
 
-// Pass 2, one thread per measurement of a long row: its rank by (loc0 key,
-// id) inside its row is its sorted position (a stable segmented sort by
-// loc0).  Measurements of short rows (tag -1) were placed by pass 1.
+// Sort key of a loc0: NaN sorts as +infinity (after every finite value), so
+// that (key, index) is a strict total order and the ranks of a row are a
+// permutation of it whatever the values.  Such a measurement never lies
+// inside a chi2 window and its chi2 is never accepted.
+__device__ __forceinline__ float loc0_key(float x) { return x != x ? INFINITY : x; }
+
+// Pass 2, one thread per measurement: its rank by (loc0 key, id) inside its
+// row is its sorted position (a stable segmented sort by loc0).
 __global__ void k_meas_scatter(long long n_meas, int n_rows, const int* __restrict__ offsets,
                                const int* __restrict__ row_of, const float* __restrict__ loc,
                                const float* __restrict__ var, float4* sorted, float* key, int* id,
@@ -99,7 +59,7 @@ __global__ void k_meas_scatter(long long n_meas, int n_rows, const int* __restri
   if (i >= n_meas) return;
   if (status[CKF_STATUS_FLAGS] & CKF_FLAG_BAD_OFFSETS) return;
   const int row = row_of[i];
-  if (row < 0 || row >= n_rows) return;  // (a short row's measurement, placed by pass 1)
+  if (row < 0 || row >= n_rows) return;  // (cannot happen once the offsets passed pass 1)
   const int a = offsets[row], b = offsets[row + 1];
   const float x = loc0_key(loc[2 * i]);
   int rank = 0;
@@ -1671,7 +1631,7 @@ hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status,
   const int rows = m.n_events * m.n_surfaces;
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_meas_rows, dim3((rows + 255) / 256), dim3(256), 0, st, rows, (long long)m.n_meas, m.offsets,
-                     m.loc, m.var, w.row_of, w.row_maxvar0, w.m_sorted, w.m_key, w.m_id, status);
+                     m.var, w.row_of, w.row_maxvar0, status);
   if (m.n_meas > 0)
     hipLaunchKernelGGL(k_meas_scatter, dim3((unsigned)((m.n_meas + 255) / 256)), dim3(256), 0, st,
                        (long long)m.n_meas, rows, m.offsets, w.row_of, m.loc, m.var, w.m_sorted, w.m_key, w.m_id, status);

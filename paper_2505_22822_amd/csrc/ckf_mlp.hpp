@@ -207,7 +207,8 @@ __device__ __forceinline__ void logits_to_lds(const f32x4 out[2], int rb, int la
 // (with multiplicity, descending): each logit is inserted into the sorted
 // three by a maximum and two medians (v_med3_f32), no branches.  conf =
 // summed probability of the first k (1..3) of the three.  NaN logits (only
-// from non-finite parameters) are not supported.
+// from non-finite parameters) give a NaN confidence, which is never taken
+// as confident.
 struct RowTop {
   float v[32];
   float t[3];
