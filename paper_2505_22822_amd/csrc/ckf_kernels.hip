@@ -50,23 +50,48 @@ __global__ void k_meas_rows(int n_rows, long long n_meas, const int* __restrict_
 __device__ __forceinline__ float loc0_key(float x) { return x != x ? INFINITY : x; }
 
 // Pass 2, one thread per measurement: its rank by (loc0 key, id) inside its
-// row is its sorted position (a stable segmented sort by loc0).
-__global__ void k_meas_scatter(long long n_meas, int n_rows, const int* __restrict__ offsets,
-                               const int* __restrict__ row_of, const float* __restrict__ loc,
-                               const float* __restrict__ var, float4* sorted, float* key, int* id,
-                               const int* status) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// row is its sorted position (a stable segmented sort by loc0).  A
+// workgroup's measurements lie in a few consecutive rows; their keys are
+// read once into LDS and each thread ranks its measurement there (a row
+// longer than the LDS span is ranked from memory).
+constexpr int kScatterBlock = 256;
+constexpr int kScatterSpan = 2304;  // keys of a workgroup's rows held in LDS
+
+__global__ void __launch_bounds__(kScatterBlock) k_meas_scatter(long long n_meas, int n_rows,
+                                                                const int* __restrict__ offsets,
+                                                                const int* __restrict__ row_of,
+                                                                const float* __restrict__ loc,
+                                                                const float* __restrict__ var, float4* sorted,
+                                                                float* key, int* id, const int* status) {
+  __shared__ float s_key[kScatterSpan];
+  if (status[CKF_STATUS_FLAGS] & CKF_FLAG_BAD_OFFSETS) return;  // (the same for the whole workgroup)
+  const long long i0 = (long long)blockIdx.x * kScatterBlock;
+  const long long i1 = min(i0 + kScatterBlock, n_meas);
+  // the rows of the workgroup's measurements: [offsets[r0], offsets[r1 + 1])
+  const int r0 = row_of[i0], r1 = row_of[i1 - 1];
+  const long long s0 = offsets[r0], s1 = offsets[r1 + 1];
+  const bool in_lds = s1 - s0 <= kScatterSpan;
+  if (in_lds)
+    for (long long j = s0 + threadIdx.x; j < s1; j += kScatterBlock) s_key[j - s0] = loc0_key(loc[2 * j]);
+  __syncthreads();
+  const long long i = i0 + threadIdx.x;
   if (i >= n_meas) return;
-  if (status[CKF_STATUS_FLAGS] & CKF_FLAG_BAD_OFFSETS) return;
   const int row = row_of[i];
   if (row < 0 || row >= n_rows) return;  // (cannot happen once the offsets passed pass 1)
   const int a = offsets[row], b = offsets[row + 1];
   const float x = loc0_key(loc[2 * i]);
   int rank = 0;
+  if (in_lds) {
+    for (int j = a; j < b; ++j) {
+      const float y = s_key[j - s0];
+      rank += (y < x || (y == x && j < i)) ? 1 : 0;
+    }
+  } else {
 #pragma unroll 8
-  for (int j = a; j < b; ++j) {
-    const float y = loc0_key(loc[2 * j]);
-    rank += (y < x || (y == x && j < i)) ? 1 : 0;
+    for (int j = a; j < b; ++j) {
+      const float y = loc0_key(loc[2 * j]);
+      rank += (y < x || (y == x && j < i)) ? 1 : 0;
+    }
   }
   const int d = a + rank;
   sorted[d] = make_float4(x, loc[2 * i + 1], var[2 * i], var[2 * i + 1]);
@@ -1633,7 +1658,8 @@ hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status,
   hipLaunchKernelGGL(k_meas_rows, dim3((rows + 255) / 256), dim3(256), 0, st, rows, (long long)m.n_meas, m.offsets,
                      m.var, w.row_of, w.row_maxvar0, status);
   if (m.n_meas > 0)
-    hipLaunchKernelGGL(k_meas_scatter, dim3((unsigned)((m.n_meas + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_meas_scatter, dim3((unsigned)((m.n_meas + kScatterBlock - 1) / kScatterBlock)),
+                       dim3(kScatterBlock), 0, st,
                        (long long)m.n_meas, rows, m.offsets, w.row_of, m.loc, m.var, w.m_sorted, w.m_key, w.m_id, status);
   return hipGetLastError();
 }
