@@ -164,16 +164,17 @@ def test_fit_edge_cases(ckf, det_dense):
     assert list(g["ok"]) == [-1, -1]
     p = f.params.cpu().numpy()
     assert np.all(np.isnan(p[:2])) and np.all(p[2:] == 7.0)
-    # 65 measurements on the seed's module; an empty track; one measurement
-    t2 = dict(n_tracks=dev(np.array([3], np.int32)), offsets=dev(np.array([0, 65, 65, 66], np.int32)),
-              meas=dev(np.zeros(66, np.int32)), meas_surface=dev(np.full(66, s, np.int32)),
-              seed=dev(np.zeros(3, np.int32)))
+    # 65 measurements on the seed's module; an empty track; one measurement;
+    # 64 measurements (the longest fitted)
+    t2 = dict(n_tracks=dev(np.array([4], np.int32)), offsets=dev(np.array([0, 65, 65, 66, 130], np.int32)),
+              meas=dev(np.zeros(130, np.int32)), meas_surface=dev(np.full(130, s, np.int32)),
+              seed=dev(np.zeros(4, np.int32)))
     f = ckf.Fitter(geo, fld, b, t2)
     f.enqueue()
     g = f.result()
-    assert list(g["ok"]) == [-1, 1, 1]
+    assert list(g["ok"]) == [-1, 1, 1, 1]
     p = f.params.cpu().numpy()
-    assert np.all(np.isnan(p[:65])) and np.all(np.isfinite(p[65]))
+    assert np.all(np.isnan(p[:65])) and np.all(np.isfinite(p[65:130]))
     # offsets going back: the first and the third track share measurements,
     # 5 in all against a capacity of 3 (the second track's range is reversed)
     t3 = dict(n_tracks=dev(np.array([3], np.int32)), offsets=dev(np.array([0, 3, 1, 3], np.int32)),
