@@ -417,7 +417,7 @@ Layout layout(const ckf::Launch& L, int n_events, int n_surfaces, int n_seeds, l
   o.off_maxv = take(rows * 4);
   o.off_nodes = take((size_t)o.node_cap * sizeof(ckf::Node));
   o.off_nodecnt = take(8);
-  o.off_queue = take(8);
+  o.off_queue = take(ckf::kSeedQueues * 4);
   o.off_res_node = take(ns * 4);
   o.off_res_nm = take(ns * 4);
   o.off_res_holes = take(ns * 4);

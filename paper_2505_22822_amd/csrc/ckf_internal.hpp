@@ -124,6 +124,14 @@ enum PoolF { PF_H = 0, PF_PATH, PF_N };
 constexpr size_t kRecBytes = PD_N * 8 + PI_N * 4 + PF_N * 4;
 constexpr size_t kRecStride = (kRecBytes + 15) / 16 * 16;  // array-of-structs record stride
 
+// The seed list is split into kSeedQueues equal parts, one per XCD: a
+// workgroup takes seeds from the part of its own XCD (workgroups are dealt to
+// the 8 XCDs round-robin by index) and, when that part is used up, from the
+// next ones.  Seeds of one part are neighbours in the caller's order (for
+// seeds listed by event, a few events), so each XCD's L2 holds the
+// measurements of its own events.
+constexpr int kSeedQueues = 8;
+
 struct Workspace {
   // carved from the caller's workspace
   float4* m_sorted;  // (loc0, loc1, var0, var1) sorted by loc0 within each row
@@ -134,7 +142,7 @@ struct Workspace {
   Node* nodes;
   long long node_cap;
   unsigned long long* node_count;
-  int* queue_head;
+  int* queue_head;  // kSeedQueues heads, one per part of the seed list
   int* res_node;
   int* res_nm;
   int* res_holes;

@@ -117,7 +117,7 @@ __global__ void k_init(int n_seeds, int* res_node, int* res_nm, int* queue_head,
     }
   }
   if (i == 0) {
-    *queue_head = 0;
+    for (int k = 0; k < kSeedQueues; ++k) queue_head[k] = 0;
     *node_count = 0ull;
     *fin_count = 0ull;
     *n_tracks = 0;
@@ -601,6 +601,9 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
   int cur = 0, n_in = 0;
   // invalid measurement offsets: search ranges cannot be trusted, do nothing
   bool queue_done = (((volatile int*)A.status)[CKF_STATUS_FLAGS] & CKF_FLAG_BAD_OFFSETS) != 0;
+  // the part of the seed list taken from (this XCD's first), and how many
+  // parts were found used up
+  int part = blockIdx.x % kSeedQueues, parts_done = 0;
   for (;;) {
     if (((volatile int*)A.status)[CKF_STATUS_FLAGS] & CKF_FLAG_NODE_CAPACITY) break;
     const Pool Pin = pool_at(base, cap, cur), Pout = pool_at(base, cap, 1 - cur);
@@ -611,13 +614,18 @@ __global__ __launch_bounds__(kWave, kMinWaves) void k_ckf(CkfArgs A) {
       const unsigned long long fm = __ballot(free_slot);
       const int nfree = __popcll(fm);
       if (nfree > 0) {
-        if (lane == 0) sh_bcast = atomicAdd(A.w.queue_head, nfree);
+        if (lane == 0) sh_bcast = atomicAdd(A.w.queue_head + part, nfree);
         __syncthreads();
         const int start = sh_bcast;
         __syncthreads();
-        if (start + nfree >= A.s.n) queue_done = true;
-        const int seed = start + __popcll(fm & lt_mask);
-        bool ok = free_slot && seed < A.s.n;
+        const long long p0 = (long long)part * A.s.n / kSeedQueues, p1 = (long long)(part + 1) * A.s.n / kSeedQueues;
+        const long long pos = p0 + start + __popcll(fm & lt_mask);
+        if (p0 + start + nfree >= p1) {  // this part is used up: the next one
+          part = (part + 1) % kSeedQueues;
+          if (++parts_done == kSeedQueues) queue_done = true;
+        }
+        bool ok = free_slot && pos < p1;
+        const int seed = ok ? (int)pos : 0;
         if (ok) {
           const int sf = A.s.surface[seed], ev = A.s.event[seed];
           bool good = sf >= 0 && sf < g.n_surfaces && ev >= 0 && ev < A.m.n_events;
