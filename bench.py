@@ -52,18 +52,16 @@ MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 
 # only while the sources hash the same, so a changed kernel prints null
 # until it is profiled again.  Source: profiles/k_ckf_mu200x64_hbm_traffic.md.
 MEASURED_TRAFFIC = {
-    ("plain", 2048, 48, 2): (24.30e9, "872bc96a56b1b725"),
-    ("plain", 4096, 48, 2): (24.28e9, "872bc96a56b1b725"),
-    ("learned", 2048, 48, 2): (24.76e9, "872bc96a56b1b725"),
-    ("learned", 4096, 48, 2): (25.10e9, "872bc96a56b1b725"),
+    ("plain", 2048, 48, 2): (22.94e9, "b96f9223978b4870"),
+    ("learned", 2048, 48, 2): (23.85e9, "b96f9223978b4870"),
+    ("learned", 4096, 48, 2): (23.55e9, "b96f9223978b4870"),
 }
 # SIMT efficiency of the same launches, SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU): the share of
 # lanes a VALU instruction finds active, same keys and hashes.  Source: profiles/k_ckf_mu200x64_sq_counters.md.
 MEASURED_SIMT = {
-    ("plain", 2048, 48, 2): (0.384, "872bc96a56b1b725"),
-    ("plain", 4096, 48, 2): (0.384, "872bc96a56b1b725"),
-    ("learned", 2048, 48, 2): (0.338, "872bc96a56b1b725"),
-    ("learned", 4096, 48, 2): (0.338, "872bc96a56b1b725"),
+    ("plain", 2048, 48, 2): (0.385, "b96f9223978b4870"),
+    ("learned", 2048, 48, 2): (0.339, "b96f9223978b4870"),
+    ("learned", 4096, 48, 2): (0.339, "b96f9223978b4870"),
 }
 # HBM bytes per ckf_fit call (k_fit and its sort kernels) on the 64 x mu=200
 # batch's plain-search tracks (per smoother), and per call of ckf_cluster, ckf_seed and ckf_resolve on
@@ -72,17 +70,17 @@ MEASURED_SIMT = {
 # the values above.  Sources: profiles/k_fit_mu200x64.md,
 # profiles/k_cl_k_sd_k_res_mu200x64_hbm_traffic.md.
 FIT_TRAFFIC = {      # (tracks, measurements, smoother) -> (bytes, hash)
-    (560805, 4620862, "rts"): (6.896e9, "872bc96a56b1b725"),
-    (560805, 4620862, "two_filter"): (8.628e9, "872bc96a56b1b725"),
+    (560805, 4620862, "rts"): (6.894e9, "b96f9223978b4870"),
+    (560805, 4620862, "two_filter"): (8.625e9, "b96f9223978b4870"),
 }
 CLUSTER_TRAFFIC = {  # (cells, clusters) -> (bytes, hash)
-    (9783486, 5260424): (1.252e9, "872bc96a56b1b725"),
+    (9783486, 5260424): (1.252e9, "b96f9223978b4870"),
 }
 SEED_TRAFFIC = {     # (spacepoints, seeds) -> (bytes, hash)
-    (5260424, 2312126): (3.941e9, "872bc96a56b1b725"),
+    (5260424, 2312126): (3.954e9, "b96f9223978b4870"),
 }
 RESOLVE_TRAFFIC = {  # (tracks, measurements) -> (bytes, hash)
-    (560805, 4620862): (1.495e9, "872bc96a56b1b725"),
+    (560805, 4620862): (1.495e9, "b96f9223978b4870"),
 }
 # Learned proposal: the configured threshold, the candidates the bench
 # chooses from on held-out events, and the equal-efficiency allowance
