@@ -42,7 +42,7 @@ def ckf():
     return ckf
 
 
-@pytest.mark.parametrize("min_prob", [0.95, 0.98])
+@pytest.mark.parametrize("min_prob", [0.95, 0.97, 0.98])
 def test_learned_search_matches_oracle(ckf, oracle_lib, det_dense, dense_table, golden_model, min_prob):
     import torch
     import oracle
