@@ -52,16 +52,16 @@ MFMA_FLOP_PER_BLOCK = 28 * 16 * 16 * 16 * 2  # one 16-row network pass: 28 bf16 
 # only while the sources hash the same, so a changed kernel prints null
 # until it is profiled again.  Source: profiles/k_ckf_mu200x64_hbm_traffic.md.
 MEASURED_TRAFFIC = {
-    ("plain", 2048, 48, 2): (22.94e9, "b96f9223978b4870"),
-    ("learned", 2048, 48, 2): (23.85e9, "b96f9223978b4870"),
-    ("learned", 4096, 48, 2): (23.55e9, "b96f9223978b4870"),
+    ("plain", 2048, 48, 2): (22.94e9, "2da49482bb6e3ae2"),
+    ("learned", 2048, 48, 2): (23.85e9, "2da49482bb6e3ae2"),
+    ("learned", 4096, 48, 2): (23.55e9, "2da49482bb6e3ae2"),
 }
 # SIMT efficiency of the same launches, SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU): the share of
 # lanes a VALU instruction finds active, same keys and hashes.  Source: profiles/k_ckf_mu200x64_sq_counters.md.
 MEASURED_SIMT = {
-    ("plain", 2048, 48, 2): (0.385, "b96f9223978b4870"),
-    ("learned", 2048, 48, 2): (0.339, "b96f9223978b4870"),
-    ("learned", 4096, 48, 2): (0.339, "b96f9223978b4870"),
+    ("plain", 2048, 48, 2): (0.385, "2da49482bb6e3ae2"),
+    ("learned", 2048, 48, 2): (0.339, "2da49482bb6e3ae2"),
+    ("learned", 4096, 48, 2): (0.339, "2da49482bb6e3ae2"),
 }
 # HBM bytes per ckf_fit call (k_fit and its sort kernels) on the 64 x mu=200
 # batch's plain-search tracks (per smoother), and per call of ckf_cluster, ckf_seed and ckf_resolve on
@@ -70,17 +70,17 @@ MEASURED_SIMT = {
 # the values above.  Sources: profiles/k_fit_mu200x64.md,
 # profiles/k_cl_k_sd_k_res_mu200x64_hbm_traffic.md.
 FIT_TRAFFIC = {      # (tracks, measurements, smoother) -> (bytes, hash)
-    (560805, 4620862, "rts"): (6.894e9, "b96f9223978b4870"),
-    (560805, 4620862, "two_filter"): (8.625e9, "b96f9223978b4870"),
+    (560805, 4620862, "rts"): (6.894e9, "2da49482bb6e3ae2"),
+    (560805, 4620862, "two_filter"): (8.625e9, "2da49482bb6e3ae2"),
 }
 CLUSTER_TRAFFIC = {  # (cells, clusters) -> (bytes, hash)
-    (9783486, 5260424): (1.252e9, "b96f9223978b4870"),
+    (9783486, 5260424): (1.252e9, "2da49482bb6e3ae2"),
 }
 SEED_TRAFFIC = {     # (spacepoints, seeds) -> (bytes, hash)
-    (5260424, 2312126): (3.954e9, "b96f9223978b4870"),
+    (5260424, 2312126): (3.954e9, "2da49482bb6e3ae2"),
 }
 RESOLVE_TRAFFIC = {  # (tracks, measurements) -> (bytes, hash)
-    (560805, 4620862): (1.495e9, "b96f9223978b4870"),
+    (560805, 4620862): (1.495e9, "2da49482bb6e3ae2"),
 }
 # Learned proposal: the configured threshold, the candidates the bench
 # chooses from on held-out events, and the equal-efficiency allowance

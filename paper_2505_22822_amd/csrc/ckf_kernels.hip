@@ -1674,8 +1674,8 @@ hipError_t launch_meas_prepare(const MeasIn& m, const Workspace& w, int* status,
 
 hipError_t launch_ckf(const CkfArgs& a, int waves_per_simd, hipStream_t st) {
   const dim3 grid(a.w.grid), block(kWave);
-  // Register budgets of 1, 2 and 3 waves per SIMD (the 3-wave build spills a
-  // little and is still the fastest on the dense batch; 4 would spill much
+  // Register budgets of 1, 2 and 3 waves per SIMD (the 3-wave builds spill;
+  // the 2-wave builds are the fastest on the dense batch; 4 would spill much
   // more).  The learned form runs in a uniform field (the host rejects a map).
   const int w = waves_per_simd;
   if (a.f.map) {
