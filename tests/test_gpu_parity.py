@@ -264,6 +264,30 @@ def test_ckf_edge_cases(ckf, det_dense):
         ckf.find(geo, fld, badoff)
 
 
+def test_ckf_fewer_seeds_than_queue_parts(ckf, det_dense):
+    """The seed list is taken in eight parts (one per XCD); with fewer seeds
+    than parts most parts are empty.  The first n seeds of an event, n = 1,
+    3, 7, 9, 17, give each seed exactly the track it gets in the whole
+    event's launch (every seed taken once, none lost)."""
+    geo = ckf.Geometry(det_dense.as_arrays())
+    fld = ckf.UniformField(0, 0, 2.0)
+    ev = make_event(det_dense, 7, mu=5)
+    b = ckf.Batch.from_event(ev)
+    _say(f"[ckf/few-seeds] {ev.n_seeds} seeds, prefixes of 1..17")
+    full = ckf.find(geo, fld, b)
+    ft = {int(s): t for t, s in enumerate(full["seed"])}
+    for n in (1, 3, 7, 9, 17):
+        bn = ckf.Batch(b.n_events, b.n_surfaces, b.offsets, b.loc, b.var, b.seed_event[:n], b.seed_surface[:n],
+                       b.seed_params[:n], b.seed_cov[:n])
+        r = ckf.find(geo, fld, bn)
+        assert sorted(int(s) for s in r["seed"]) == sorted(s for s in ft if s < n), n
+        for t, s in enumerate(r["seed"]):
+            u = ft[int(s)]
+            assert np.array_equal(r["meas"][r["offsets"][t]:r["offsets"][t + 1]],
+                                  full["meas"][full["offsets"][u]:full["offsets"][u + 1]]), (n, s)
+            assert np.array_equal(r["params"][t], full["params"][u]), (n, s)
+
+
 def test_ckf_measurement_input_rules(ckf, det_dense):
     """Measurement offsets must tile [0, n_meas): a final offset short of
     n_meas is flagged (those measurements would have no module) and nothing
